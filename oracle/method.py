@@ -1,0 +1,423 @@
+"""The discrete FFT-based method, computed plainly in FP64.  TEST INFRASTRUCTURE ONLY.
+
+This is the parity oracle: the same approximation as the library (Algorithms
+2.1, 3.1 and 4.1 with the frozen parameter set below) but computed directly,
+step by step in the paper's order:
+
+1. Fourier coefficients of the periodised function K (eq. 2.1 in 2D, eq. 3.3
+   in 3D), whose X'-integrals are evaluated by converged Gauss-Legendre
+   quadrature and a matrix product (the "matrix computation" of Section 2.1).
+2. Fourier coefficients of the removed singular part: F1, F2 in 2D
+   (eqs. 2.4, 2.5; Phi-hat by radial Hankel quadrature) and F in 3D (eq. 3.5,
+   the 3D integral reduced to a radial sine transform).
+3. L-hat = K-hat - F-hat (eqs. 2.3 and the line after 3.5); Maxwell fields
+   L-hat^{pq} = -c^p c^q L-hat (Section 4).
+4. Grid values of the truncated series L_N by *direct* separable DFT sums
+   (no FFT): L_N(x_p) = A sum_j L-hat_j exp(i pi j.p / N).
+5. Targets: reduction to the cell (Alg. 2.1 step 2c / Alg. 3.1 step 2c),
+   near/far branch on |x_t| <= c (step 2b), tensor-product 4-point Lagrange
+   interpolation (the 16- and 64-point stencils of Sections 2.3 and 3.3), exact
+   add-back of the singular part and the quasi-periodic phase.
+   The far branch (|x_t| > c), where the paper sums the eigenfunction series,
+   uses a far slab: the series' own per-slice coefficients
+   (i/4pi) beta^-1 e^{i beta z} (2D) or (i/8pi^2) beta^-1 e^{i beta z} (3D),
+   turned into grids over the periodic axes by direct DFT and interpolated the
+   same way.
+
+Readings of the paper taken here (its silent or garbled points):
+* cut-offs: C^8 smoothstep (see ``cutoffs``), c = 0.6, c~ = 1, eps = 0.2;
+* the 3D basis is exp[i(j1 x1 + j2 x2 + j3 pi x3 / c~)] / sqrt(8 pi^2 c~)
+  (Section 3.1 prints j1 x2 and drops the pi);
+* eq. 3.2 has e^{i(beta + j3 pi/c~) x3} as its second exponential and 3.4
+  has no stray i (they must agree with 3.3, which is consistent);
+* bicubic / tricubic interpolation is the 4-point cubic Lagrange rule per
+  axis (same stencil and O(h^4) order as the paper states);
+* the final phase uses the original coordinates, G = e^{i alpha.x'} K(t)
+  (Alg. 2.1 step 2e), so Alg. 3.1 step 2f returns G_d(x) and not G_d(t);
+* grid sizes are independent per axis: M_i = 2 N_i.
+
+Index conventions: coefficient arrays are indexed [j + N] (centred index j
+shifted to start at 0), grid arrays [p + N] with x = p h, so index 0 is
+x1 = -pi, x3 = -c~.
+"""
+
+import math
+
+import numpy as np
+from scipy.special import j0 as bessel_j0, j1 as bessel_j1
+
+from . import cutoffs as co
+from .truth import beta
+
+ORACLE_Q = 160          # Gauss-Legendre nodes for every 1D integral
+
+
+def gauss_legendre(a, b, q=ORACLE_Q):
+    t, w = np.polynomial.legendre.leggauss(q)
+    return 0.5 * (b - a) * t + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def lagrange4(f):
+    """Cubic Lagrange basis at nodes -1, 0, 1, 2 evaluated at fraction f (shape [...,4])."""
+    f = np.asarray(f, dtype=np.float64)
+    nodes = (-1.0, 0.0, 1.0, 2.0)
+    out = []
+    for a in range(4):
+        l = np.ones_like(f)
+        for b in range(4):
+            if b != a:
+                l = l * (f - nodes[b]) / (nodes[a] - nodes[b])
+        out.append(l)
+    return np.stack(out, axis=-1)
+
+
+def dft_matrix(N):
+    """E[p + N, j + N] = exp(i pi j p / N) for centred j, p in [-N, N)."""
+    j = np.arange(-N, N, dtype=np.float64)
+    return np.exp(1j * math.pi * np.outer(j, j) / N)
+
+
+# ----------------------------------------------------------------------------
+# the X'-integrals of (2.1) / (3.3)
+# ----------------------------------------------------------------------------
+
+def xprime_integrals(b, J, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
+    """I(b - J) and I(b + J) with I(g) = int_0^{c~} e^{i g x} X'(x) dx, as [len(b), len(J)].
+
+    X' vanishes outside [c, (c + c~)/2], so the integral runs over that interval.
+    The factorisation e^{i(b -+ J)x} = e^{ibx} e^{-+iJx} turns both families into
+    one matrix product (the "1D FFT and matrix computation" of Section 2.1).
+    """
+    x, w = gauss_legendre(c, 0.5 * (c + c_tilde), q)
+    a = np.exp(1j * np.outer(b, x)) * (w * co.dX(x, c, c_tilde))     # [P, q]
+    em = np.exp(-1j * np.outer(x, J))                                   # [q, M]
+    return a @ em, a @ np.conj(em)
+
+
+def _coef_K(A, k, b, J, lead_den, Im, Ip):
+    """A [ 1/(|xi|^2 - k^2) + I(b-J)/(2b(J-b)) - I(b+J)/(2b(J+b)) ]  (eqs. 2.1, 3.3)."""
+    return A * (1.0 / lead_den + Im / (2 * b * (J - b)) - Ip / (2 * b * (J + b)))
+
+
+# ----------------------------------------------------------------------------
+# 2D (Section 2)
+# ----------------------------------------------------------------------------
+
+def khat_2d(k, alpha, N1, N2, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
+    """K-hat_j of (2.1) for j in S_N, shape [2N1, 2N2]."""
+    A2 = 1.0 / (2.0 * math.sqrt(math.pi * c_tilde))
+    a = alpha + np.arange(-N1, N1, dtype=np.float64)
+    J = np.arange(-N2, N2, dtype=np.float64) * math.pi / c_tilde
+    b = beta(k, a)
+    Im, Ip = xprime_integrals(b, J, c, c_tilde, q)
+    B, JJ = b[:, None], J[None, :]
+    return _coef_K(A2, k, B, JJ, a[:, None] ** 2 + JJ ** 2 - k * k, Im, Ip)
+
+
+def phi1(r, eps=co.EPS):
+    """Phi_1 = (2 + ln r) Y'(r)/r + Y''(r) ln r, i.e. Delta(ln r Y) away from 0 (Section 2.2)."""
+    return (2.0 + np.log(r)) * co.dY(r, eps) / r + co.d2Y(r, eps) * np.log(r)
+
+
+def fhat_2d(N1, N2, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
+    """F-hat_1 and F-hat_2 of (2.4), (2.5) (and the j = 0 values), shape [2N1, 2N2].
+
+    Phi-hat_j = int Phi(x) phi_{-j}(x) dx with the same basis as K-hat.  For the
+    radial Phi_1: Phi-hat_1 = A2 2pi int Phi_1(r) J0(|eta| r) r dr, and for
+    Phi_2 = x1 Phi_1 (its x1-moment): Phi-hat_2 = -i A2 2pi (j1/|eta|) int Phi_1 J1(|eta| r) r^2 dr,
+    eta = (j1, j2 pi / c~).
+    """
+    A2 = 1.0 / (2.0 * math.sqrt(math.pi * c_tilde))
+    j1 = np.arange(-N1, N1, dtype=np.float64)[:, None]
+    J = (np.arange(-N2, N2, dtype=np.float64) * math.pi / c_tilde)[None, :]
+    eta2 = j1 ** 2 + J ** 2
+    eta = np.sqrt(eta2)
+    r, w = gauss_legendre(eps, 2 * eps, q)
+    wp = w * phi1(r, eps)
+    F1 = np.empty((2 * N1, 2 * N2), dtype=np.complex128)
+    F2 = np.empty_like(F1)
+    for i in range(2 * N1):                           # one j1 row at a time (memory)
+        e = eta[i][:, None] * r[None, :]
+        i0 = (bessel_j0(e) * r) @ wp
+        i1 = (bessel_j1(e) * r * r) @ wp
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ph1 = A2 * 2 * math.pi * i0
+            ph2 = -1j * A2 * 2 * math.pi * (j1[i, 0] / eta[i]) * i1
+            f1 = (A2 + ph1 / (2 * math.pi)) / eta2[i]
+            f2 = (-2j * j1[i, 0] * f1 + ph2 / (2 * math.pi)) / eta2[i]
+        F1[i], F2[i] = f1, f2
+    # j = 0 (Section 2.2): F1_0 = -A2 int_0^{2eps} t ln t Y(t) dt, F2_0 = 0.
+    tq, tw = gauss_legendre(eps, 2 * eps, q)
+    inner = eps * eps * (math.log(eps) / 2.0 - 0.25)      # int_0^eps t ln t dt (Y = 1 there)
+    F1[N1, N2] = -A2 * (inner + np.sum(tw * tq * np.log(tq) * co.Y(tq, eps)))
+    F2[N1, N2] = 0.0
+    return F1, F2
+
+
+def lhat_2d(k, alpha, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q, F=None):
+    """L-hat = K-hat - F-hat_1 + i alpha F-hat_2 (2.3)."""
+    F1, F2 = fhat_2d(N1, N2, c_tilde, eps, q) if F is None else F
+    return khat_2d(k, alpha, N1, N2, c, c_tilde, q) - F1 + 1j * alpha * F2
+
+
+def grid_2d(Lhat, c_tilde=co.C_TILDE):
+    """L_N at the grid, [2N1, 2N2] indexed [p1 + N1, p2 + N2], by direct DFT sums."""
+    M1, M2 = Lhat.shape
+    A2 = 1.0 / (2.0 * math.sqrt(math.pi * c_tilde))
+    return A2 * dft_matrix(M1 // 2) @ Lhat @ dft_matrix(M2 // 2).T
+
+
+def far_grid_2d(k, alpha, N1, z):
+    """Far-slab grid [S, 2N1]: (i/4pi) sum_n beta_n^-1 e^{i beta_n z_s} e^{i n x1_p} (series 1.2)."""
+    a = alpha + np.arange(-N1, N1, dtype=np.float64)
+    b = beta(k, a)
+    coef = 1j / (4 * math.pi) * np.exp(1j * np.outer(z, b)) / b      # [S, M1]
+    return coef @ dft_matrix(N1).T
+
+
+def _reduce(x):
+    """x = 2 pi n + t with t in [-pi, pi) (Alg. 2.1 step 2c)."""
+    n = np.floor((x + math.pi) / (2 * math.pi))
+    return x - 2 * math.pi * n, n
+
+
+def _stencil(u, M):
+    """Base node floor(u), fraction, and the 4 wrapped node indices -1..2."""
+    p0 = np.floor(u)
+    f = u - p0
+    idx = (p0.astype(np.int64)[:, None] + np.arange(-1, 3)[None, :]) % M
+    return idx, lagrange4(f)
+
+
+def _far_stencil(z, hf, S, c=co.C):
+    """Far-slab transverse stencil: slices z_s = c - hf + s hf, s in [0, S)."""
+    v = (z - (c - hf)) / hf
+    s0 = np.floor(v)
+    bad = s0 > S - 3
+    s0 = np.clip(s0, 1, S - 3)
+    idx = s0.astype(np.int64)[:, None] + np.arange(-1, 3)[None, :]
+    return idx, lagrange4(v - s0), bad
+
+
+def far_slices(hf, S, c=co.C):
+    return c - hf + hf * np.arange(S, dtype=np.float64)
+
+
+def eval_g2d(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
+             q=ORACLE_Q, F=None, return_parts=False):
+    """Algorithm 2.1 at targets x[T,2]; G_N(x) (NaN beyond the far slab)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    M1, M2 = 2 * N1, 2 * N2
+    h1, h2 = math.pi / N1, c_tilde / N2
+    grid = grid_2d(lhat_2d(k, alpha, N1, N2, c, c_tilde, eps, q, F), c_tilde)   # [p1, p2]
+    t, _ = _reduce(x[:, 0])
+    x2 = x[:, 1]
+    out = np.full(len(x), np.nan + 0j)
+    near = np.abs(x2) <= c
+    # near: bicubic on L_N, then K_N = L_N + f1 - i alpha f2, G = e^{i alpha x1} K_N
+    if near.any():
+        tn, zn = t[near], x2[near]
+        i1, w1 = _stencil((tn + math.pi) / h1, M1)
+        i2, w2 = _stencil((zn + c_tilde) / h2, M2)
+        vals = grid[i1[:, :, None], i2[:, None, :]]
+        L = np.einsum("ta,tb,tab->t", w1, w2, vals)
+        r = np.hypot(tn, zn)
+        sing = -np.log(r) * co.Y(r, eps) / (2 * math.pi) * (1.0 - 1j * alpha * tn)
+        out[near] = np.exp(1j * alpha * x[near, 0]) * (L + sing)
+    far = ~near
+    if far.any():
+        zf = far_slices(far_h, far_S, c)
+        fg = far_grid_2d(k, alpha, N1, zf)                    # [s, p1]
+        tf, z = t[far], np.abs(x2[far])
+        i1, w1 = _stencil((tf + math.pi) / h1, M1)
+        i2, w2, bad = _far_stencil(z, far_h, far_S, c)
+        vals = fg[i2[:, None, :], i1[:, :, None]]
+        L = np.einsum("ta,tb,tab->t", w1, w2, vals)
+        g = np.exp(1j * alpha * x[far, 0]) * L
+        g[bad] = np.nan
+        out[far] = g
+    return out
+
+
+# ----------------------------------------------------------------------------
+# 3D (Section 3) and the Maxwell fields (Section 4)
+# ----------------------------------------------------------------------------
+
+def radial_H(k, rho, eps=co.EPS, q=ORACLE_Q, chunk=1 << 16):
+    """H(rho) = rho^-1 int_eps^{2eps} e^{ikr} (2ik Y' + Y'') sin(rho r) dr;  H(0) = int (...) r dr.
+
+    With g = e^{ikr}/(4 pi r), the integral in (3.5) is the 3D Fourier transform of
+    the radial function g (2ik Y' + Y''), which reduces to this sine transform.
+    """
+    r, w = gauss_legendre(eps, 2 * eps, q)
+    wg = w * np.exp(1j * k * r) * (2j * k * co.dY(r, eps) + co.d2Y(r, eps))
+    rho = np.asarray(rho, dtype=np.float64)
+    flat = rho.ravel()
+    out = np.empty(flat.size, dtype=np.complex128)
+    for s in range(0, flat.size, chunk):
+        p = flat[s:s + chunk]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sn = np.where(p[:, None] > 0, np.sin(np.outer(p, r)) / p[:, None], r[None, :])
+        out[s:s + chunk] = sn @ wg
+    return out.reshape(rho.shape)
+
+
+def _xi_3d(a1, a2, N1, N2, N3, c_tilde):
+    xi1 = a1 + np.arange(-N1, N1, dtype=np.float64)
+    xi2 = a2 + np.arange(-N2, N2, dtype=np.float64)
+    J = np.arange(-N3, N3, dtype=np.float64) * math.pi / c_tilde
+    rp2 = (xi1[:, None] ** 2 + xi2[None, :] ** 2).ravel()           # one entry per pencil (j1, j2)
+    return rp2, J
+
+
+def khat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
+    """K-hat_dj of (3.3) (the corrected 3.2 integrated by parts), shape [2N1, 2N2, 2N3]."""
+    A3 = 1.0 / math.sqrt(8 * math.pi ** 2 * c_tilde)
+    rp2, J = _xi_3d(a1, a2, N1, N2, N3, c_tilde)
+    b = beta(k, np.sqrt(rp2))
+    Im, Ip = xprime_integrals(b, J, c, c_tilde, q)
+    den = rp2[:, None] + J[None, :] ** 2 - k * k
+    K = _coef_K(A3, k, b[:, None], J[None, :], den, Im, Ip)
+    return K.reshape(2 * N1, 2 * N2, 2 * N3)
+
+
+def fhat_3d(k, a1, a2, N1, N2, N3, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
+    """F-hat_j of (3.5): A3 (1 - H(|xi|)) / (|xi|^2 - k^2), shape [2N1, 2N2, 2N3]."""
+    A3 = 1.0 / math.sqrt(8 * math.pi ** 2 * c_tilde)
+    rp2, J = _xi_3d(a1, a2, N1, N2, N3, c_tilde)
+    xi2 = rp2[:, None] + J[None, :] ** 2
+    H = radial_H(k, np.sqrt(xi2), eps, q)
+    return (A3 * (1.0 - H) / (xi2 - k * k)).reshape(2 * N1, 2 * N2, 2 * N3)
+
+
+def lhat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
+    """L-hat_d = K-hat_d - F-hat (Algorithm 3.1 step 1b), shape [2N1, 2N2, 2N3]."""
+    return (khat_3d(k, a1, a2, N1, N2, N3, c, c_tilde, q)
+            - fhat_3d(k, a1, a2, N1, N2, N3, c_tilde, eps, q))
+
+
+def maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde=co.C_TILDE):
+    """-c^p c^q for the pairs 11,22,33,12,13,23 (Section 4), each [2N1,2N2,2N3]."""
+    c1 = (a1 + np.arange(-N1, N1, dtype=np.float64))[:, None, None]
+    c2 = (a2 + np.arange(-N2, N2, dtype=np.float64))[None, :, None]
+    c3 = (np.arange(-N3, N3, dtype=np.float64) * math.pi / c_tilde)[None, None, :]
+    cc = (c1, c2, c3)
+    from .truth import MAXWELL_PAIRS
+    return [-(cc[p] * cc[q]) for p, q in MAXWELL_PAIRS]
+
+
+def grid_3d(Lhat, c_tilde=co.C_TILDE):
+    """L_dN at the full grid [2N1,2N2,2N3] by direct separable DFT sums."""
+    A3 = 1.0 / math.sqrt(8 * math.pi ** 2 * c_tilde)
+    M1, M2, M3 = Lhat.shape
+    g = np.tensordot(Lhat, dft_matrix(M3 // 2), axes=([2], [1]))      # [j1, j2, p3]
+    g = np.tensordot(g, dft_matrix(M2 // 2), axes=([1], [1]))         # [j1, p3, p2]
+    g = np.tensordot(g, dft_matrix(M1 // 2), axes=([0], [1]))         # [p3, p2, p1]
+    return A3 * np.transpose(g, (2, 1, 0))
+
+
+def far_grid_3d(k, a1, a2, N1, N2, z, mult=None):
+    """Far-slab grids [S, 2N1, 2N2] of (i/8pi^2) beta^-1 e^{i beta z_s} (series 1.3).
+
+    ``mult(xi1, xi2, beta)`` optionally multiplies each coefficient (Maxwell).
+    """
+    xi1 = (a1 + np.arange(-N1, N1, dtype=np.float64))[:, None]
+    xi2 = (a2 + np.arange(-N2, N2, dtype=np.float64))[None, :]
+    b = beta(k, np.sqrt(xi1 ** 2 + xi2 ** 2))
+    m = 1.0 if mult is None else mult(xi1, xi2, b)
+    E1, E2 = dft_matrix(N1), dft_matrix(N2)
+    out = np.empty((len(z), 2 * N1, 2 * N2), dtype=np.complex128)
+    for s, zs in enumerate(z):
+        coef = 1j / (8 * math.pi ** 2) * m * np.exp(1j * b * zs) / b
+        out[s] = E1 @ coef @ E2.T
+    return out
+
+
+def _interp3(grids, i1, w1, i2, w2, i3, w3, slice_first=False):
+    """Tensor Lagrange over 64 nodes for each grid in ``grids``."""
+    res = []
+    for g in grids:
+        if slice_first:
+            v = g[i3[:, None, None, :], i1[:, :, None, None], i2[:, None, :, None]]
+        else:
+            v = g[i1[:, :, None, None], i2[:, None, :, None], i3[:, None, None, :]]
+        res.append(np.einsum("ta,tb,tc,tabc->t", w1, w2, w3, v))
+    return res
+
+
+def _psi_derivs(k, r, eps):
+    """psi = e^{ikr} Y(r)/(4 pi r) and its first two radial derivatives."""
+    g = np.exp(1j * k * r) / (4 * math.pi * r)
+    g1 = g * (1j * k - 1.0 / r)
+    g2 = g * ((1j * k - 1.0 / r) ** 2 + 1.0 / r ** 2)
+    y, y1, y2 = co.Y(r, eps), co.dY(r, eps), co.d2Y(r, eps)
+    return g * y, g1 * y + g * y1, g2 * y + 2 * g1 * y1 + g * y2
+
+
+def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
+            eps=co.EPS, q=ORACLE_Q):
+    """Algorithm 3.1 (G_d, returns [T]) or Algorithm 4.1 (Maxwell, returns [T,6]).
+
+    Maxwell components are ordered 11, 22, 33, 12, 13, 23.
+    """
+    from .truth import MAXWELL_PAIRS
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    M1, M2, M3 = 2 * N1, 2 * N2, 2 * N3
+    h1, h2, h3 = math.pi / N1, math.pi / N2, c_tilde / N3
+    L = lhat_3d(k, a1, a2, N1, N2, N3, c, c_tilde, eps, q)
+    fields = [L] + ([m * L for m in maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde)] if maxwell else [])
+    grids = [grid_3d(f, c_tilde) for f in fields]
+    t1, n1 = _reduce(x[:, 0])
+    t2, n2 = _reduce(x[:, 1])
+    x3 = x[:, 2]
+    T = len(x)
+    vals = np.full((T, len(fields)), np.nan + 0j)
+    phase = np.exp(1j * (a1 * x[:, 0] + a2 * x[:, 1]))
+    near = np.abs(x3) <= c
+    if near.any():
+        i1, w1 = _stencil((t1[near] + math.pi) / h1, M1)
+        i2, w2 = _stencil((t2[near] + math.pi) / h2, M2)
+        i3, w3 = _stencil((x3[near] + c_tilde) / h3, M3)
+        Ls = _interp3(grids, i1, w1, i2, w2, i3, w3)
+        tt = np.stack([t1[near], t2[near], x3[near]], axis=1)
+        r = np.linalg.norm(tt, axis=1)
+        psi, d1, d2 = _psi_derivs(k, r, eps)
+        lat = np.exp(2j * math.pi * (a1 * n1[near] + a2 * n2[near]))
+        vals[near, 0] = phase[near] * Ls[0] + lat * psi
+        for f, (p, qq) in enumerate(MAXWELL_PAIRS[: len(fields) - 1]):
+            tp, tq = tt[:, p], tt[:, qq]
+            hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
+            vals[near, f + 1] = phase[near] * Ls[f + 1] + lat * hess
+    far = ~near
+    if far.any():
+        z = far_slices(far_h, far_S, c)
+        mults = [None]
+        if maxwell:
+            def mk(p, qq):
+                return lambda xi1, xi2, b: -((xi1, xi2, b)[p] * (xi1, xi2, b)[qq])
+            mults += [mk(p, qq) for p, qq in MAXWELL_PAIRS]
+        fgrids = [far_grid_3d(k, a1, a2, N1, N2, z, m) for m in mults]
+        i1, w1 = _stencil((t1[far] + math.pi) / h1, M1)
+        i2, w2 = _stencil((t2[far] + math.pi) / h2, M2)
+        i3, w3, bad = _far_stencil(np.abs(x3[far]), far_h, far_S, c)
+        Ls = _interp3(fgrids, i1, w1, i2, w2, i3, w3, slice_first=True)
+        sg = np.sign(x3[far])
+        for f in range(len(fields)):
+            v = phase[far] * Ls[f]
+            if f >= 1 and 2 in MAXWELL_PAIRS[f - 1] and MAXWELL_PAIRS[f - 1] != (2, 2):
+                v = v * sg                     # d/dx3 of e^{i beta |x3|} brings sgn(x3)
+            v[bad] = np.nan
+            vals[far, f] = v
+    if not maxwell:
+        return vals[:, 0]
+    out = vals[:, 1:] / k ** 2
+    out[:, :3] += vals[:, :1]
+    return out
+
+
+def eval_gd3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, **kw):
+    return eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, **kw)
+
+
+def eval_maxwell3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, **kw):
+    return eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=True, **kw)
