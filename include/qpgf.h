@@ -1,0 +1,171 @@
+/*
+ * qpgf.h -- C ABI of libqpgf, the MI355X (gfx950) implementation of the
+ * FFT-based evaluator of quasi-periodic Green's functions of Zhang & Zhang,
+ * "An FFT-based algorithm for efficient computation of Green's functions for
+ * the Helmholtz and Maxwell's equations in periodic domains".
+ *
+ * Functions evaluated (Section 1 of the paper):
+ *   G(x; k, alpha)            2D, 2pi-periodic in x1, alpha-quasi-periodic, eq. (1.2)
+ *   G_d(x; k, alpha1, alpha2) 3D, 2pi-periodic in x1 and x2, eq. (1.3)
+ *   GG(x) = G_d I + k^-2 grad grad G_d, the Maxwell Green tensor, eq. (1.4)
+ * for k > 0, real alpha, away from Wood anomalies (beta_n != 0, Section 1).
+ *
+ * Method (Algorithms 2.1, 3.1, 4.1): preparation fills the Fourier
+ * coefficients L-hat = K-hat - F-hat of the periodised, desingularised
+ * function (eqs. 2.1-2.5, 3.3, 3.5, Section 4) in FP64 and transforms them to
+ * a uniform grid with inverse FFTs; evaluation reduces each target to the
+ * period cell, interpolates the grid with the 4-point cubic Lagrange rule per
+ * axis (16 / 64 points) and adds back the removed singular part exactly and the
+ * quasi-periodic phase.  Targets with |x_t| > c (x_t = x2 in 2D, x3 in 3D) take
+ * the far branch: a grid of the eigenfunction series itself on slices
+ * z_s = c - h_f + s h_f, s = 0 .. S_f-1, interpolated the same way.
+ *
+ * Conventions for every entry point:
+ *  - All bulk arrays (targets, outputs, flags) are DEVICE pointers owned by the
+ *    caller.  The plan owns its grids, coefficient tables and scratch, which it
+ *    allocates with hipMalloc at creation (grids) or on first use (target
+ *    scratch, grown as needed).
+ *  - Work is enqueued asynchronously on the plan's stream (default: the null
+ *    stream); the return value reports launch-time validation and HIP launch
+ *    errors only.  Calls on one plan must not overlap from several host threads.
+ *  - Targets are float64, row-major [T][dim].  Outputs are interleaved complex
+ *    (re, im) in the caller's target order: complex128 when the plan precision is
+ *    QPGF_C128, complex64 when QPGF_C64.  Maxwell outputs are [T][6] complex in
+ *    the order 11, 22, 33, 12, 13, 23.
+ *  - Per-target flags (optional, may be NULL), uint8 [T]:
+ *      bit 0  the target lies within params.lattice_rmin of a lattice point
+ *             (output NaN); with lattice_rmin = 0 only an exact hit is flagged,
+ *      bit 1  far branch (|x_t| > c),
+ *      bit 2  |x_t| beyond the far slab, i.e. > c + (S_f - 3) h_f (output NaN),
+ *      bit 3  non-finite target coordinate (output NaN).
+ *  - On error the call returns a nonzero qpgf_status and qpgf_last_error()
+ *    describes it; nothing is launched.
+ */
+#ifndef QPGF_H
+#define QPGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QPGF_OK = 0,
+  QPGF_E_ARG = 1,          /* invalid argument (null pointer, bad size, wrong plan kind) */
+  QPGF_E_WOOD = 2,         /* min_n |beta_n| < wood_tol: Wood anomaly (Section 1)        */
+  QPGF_E_SPECIAL = 3,      /* |beta -+ j pi / c~| < special_tol: the integration by parts
+                              behind eqs. 2.1 / 3.3 is singular (Sections 2.1, 3.1)      */
+  QPGF_E_SIZE = 4,         /* unsupported grid size                                      */
+  QPGF_E_HIP = 5,          /* a HIP runtime call failed                                  */
+  QPGF_E_NOMEM = 6,        /* device allocation failed                                   */
+  QPGF_E_UNSUPPORTED = 7
+} qpgf_status;
+
+typedef enum { QPGF_C128 = 0, QPGF_C64 = 1 } qpgf_prec;
+
+typedef enum {
+  QPGF_KIND_G2D = 0,       /* Algorithm 2.1 */
+  QPGF_KIND_GD3D = 1,      /* Algorithm 3.1 */
+  QPGF_KIND_MAXWELL3D = 2  /* Algorithm 4.1 */
+} qpgf_kind;
+
+/* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
+ * size per axis: m1 = 2 N1 modes in x1; 2D: m2 = 2 N2 transverse (x2) modes;
+ * 3D: m2 = 2 N2 modes in x2 and m3 = 2 N3 transverse (x3) modes.  Each must be
+ * a power of two in [16, 4096] (m3 unused in 2D).  Grid spacing: pi/N1, pi/N2
+ * (3D) and c_tilde/N_t in the transverse direction.
+ * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
+ * eps = 0.2, cut-offs: C^8 smoothstep I_u(9,9) transitions (Section 6 states C^8),
+ * quad_q = 64, far_h = c_tilde / N_t, far_zmax = c_tilde, wood_tol = 1e-3,
+ * special_tol = 1e-6, lattice_rmin = 0. */
+typedef struct {
+  int kind;                /* qpgf_kind */
+  int prec;                /* qpgf_prec: precision of grids, FFTs, gather and output */
+  int m1, m2, m3;
+  double c;                /* near/far threshold and start of the X cut-off transition */
+  double c_tilde;          /* periodisation half-length in the transverse axis, c_tilde > c */
+  double eps;              /* singular cut-off Y_eps: 1 on [0, eps], 0 beyond 2 eps; 2 eps <= c_tilde */
+  int quad_q;              /* Gauss-Legendre nodes for the X'- and radial integrals, 16..256 */
+  double far_h;            /* far-slab slice spacing h_f (> 0) */
+  double far_zmax;         /* largest |x_t| the far slab must cover */
+  double wood_tol;
+  double special_tol;
+  double lattice_rmin;
+} qpgf_params;
+
+typedef struct qpgf_plan qpgf_plan;
+
+/* Plan description returned by qpgf_plan_get_info. */
+typedef struct {
+  int kind, prec, m1, m2, m3;
+  int far_slices;          /* S_f */
+  double far_h;
+  double c, c_tilde, eps;
+  int n_fields;            /* 1, or 7 for Maxwell (L and the six L^{pq}) */
+  size_t grid_bytes;       /* bytes of one near-grid field */
+  size_t far_grid_bytes;   /* bytes of one far-slab field */
+} qpgf_plan_info;
+
+/* Fill *p with the defaults above for the given kind, precision and sizes. */
+void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int m3);
+
+/* Validate *p, allocate the plan's device buffers on the current HIP device and
+ * compute its parameter-only tables (quadrature nodes, FFT twiddles, and in 2D
+ * the k- and alpha-independent singular coefficients F-hat_1, F-hat_2 of
+ * eqs. 2.4 / 2.5, which Remark 2.1 lets one precompute once).  Synchronous.
+ * *out receives the plan; release it with qpgf_plan_destroy. */
+qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out);
+
+/* Free every device buffer of the plan (synchronises its stream first). */
+void qpgf_plan_destroy(qpgf_plan* plan);
+
+/* Set the HIP stream (hipStream_t passed as void*) all later work is enqueued on. */
+qpgf_status qpgf_plan_set_stream(qpgf_plan* plan, void* hip_stream);
+
+qpgf_status qpgf_plan_get_info(const qpgf_plan* plan, qpgf_plan_info* info);
+
+/* Preparation step of Algorithm 2.1 / 3.1 / 4.1 for one instance: fill the
+ * coefficients L-hat (and L-hat^{pq}) in FP64, inverse-FFT them to the near
+ * grid, and build the far-slab grid.  a2 is ignored in 2D.  The grids stay in
+ * the plan until the next prepare.  Returns QPGF_E_WOOD / QPGF_E_SPECIAL when
+ * the instance is excluded (checked on the host before any launch). */
+qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2);
+
+/* Calculation step (Algorithm 2.1 / 3.1 / 4.1 step 2) for T targets against the
+ * last prepared instance.  x: device float64 [T][dim]; out: device complex
+ * ([T] or [T][6]); flags: device uint8 [T] or NULL.  T = 0 is a no-op. */
+qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags);
+
+/* prepare + evaluate: G (kind G2D), G_d (GD3D) and GG (MAXWELL3D) at T targets. */
+qpgf_status qpgf_g2d(qpgf_plan* plan, double k, double alpha,
+                     const double* x, int64_t T, void* out, uint8_t* flags);
+qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
+                      const double* x, int64_t T, void* out, uint8_t* flags);
+qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
+                           const double* x, int64_t T, void* out, uint8_t* flags);
+
+/* Stage outputs for parity checks.  qpgf_prepare_stage runs the preparation only
+ * up to `stage`: 0 = coefficient fill (A L-hat_j with A the basis normalisation
+ * 1/(2 sqrt(pi c~)) in 2D, 1/sqrt(8 pi^2 c~) in 3D, in FFT order: index j mod m
+ * per axis), 1 = after the transverse inverse FFT, 2 = complete near grid
+ * L_N(x_p) (grid point p mod m per axis, x = p h).  qpgf_copy_field copies field `field`
+ * (0 = L, 1..6 = L^{pq} in the order 11,22,33,12,13,23) of the near grid buffer
+ * (which = 0) or the far-slab buffer (which = 1) to the device pointer dst,
+ * which must hold info.grid_bytes / info.far_grid_bytes.  Layout: [i3][i2][i1]
+ * (3D) or [i2][i1] (2D) with i1 fastest; far slab: [s][i2][i1] or [s][i1]. */
+qpgf_status qpgf_prepare_stage(qpgf_plan* plan, double k, double a1, double a2, int stage);
+qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* qpgf_last_error(void);
+
+/* Library version string. */
+const char* qpgf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPGF_H */

@@ -1,0 +1,131 @@
+// Batched inverse DFTs (unnormalised, e^{+2 pi i jp/n}) along one axis of a
+// strided array: the grid synthesis of Algorithms 2.1 / 3.1 / 4.1 (steps 1c-1d),
+// L_N(x_p) = sum_j L-hat_j e^{i pi j p / N}, with coefficients and grid points
+// both stored mod n.  Power-of-two lengths, radix-4 (plus one radix-2) Stockham
+// autosort passes staged in LDS.
+//
+// Batch b of a launch starts at element (b / b_in) * s_out + (b % b_in) * s_in
+// and its elements are elem_stride apart.  A block takes `tile` consecutive
+// batches: for rows (elem_stride 1) each batch is one contiguous run, for
+// columns (s_in 1) the tile's batches are adjacent, so both load coalesced.
+#include "qpgf_internal.h"
+
+namespace qpgf {
+
+namespace {
+
+template <typename V> __device__ __forceinline__ V c_add(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V c_sub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __device__ __forceinline__ V c_mul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// a + i b, a - i b
+template <typename V> __device__ __forceinline__ V c_addi(V a, V b) { V r; r.x = a.x - b.y; r.y = a.y + b.x; return r; }
+template <typename V> __device__ __forceinline__ V c_subi(V a, V b) { V r; r.x = a.x + b.y; r.y = a.y - b.x; return r; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch,
+                                             long b_in, long s_in, long s_out, int tile,
+                                             const cplx<T>* __restrict__ tw, int twlog2) {
+  using V = cplx<T>;
+  extern __shared__ char smem_raw[];
+  const int pitch = n + 1;   // pad rows so column-wise LDS writes do not share a bank
+  V* bufA = reinterpret_cast<V*>(smem_raw);
+  V* bufB = bufA + (size_t)tile * pitch;
+  const long b0 = (long)blockIdx.x * tile;
+  const int ntile = (int)min((long)tile, nbatch - b0);
+  const int total = tile * n;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, e;
+    if (es == 1) { t = idx / n; e = idx - t * n; }
+    else { e = idx / tile; t = idx - e * tile; }
+    if (t < ntile) {
+      const long b = b0 + t;
+      const long base = (b / b_in) * s_out + (b % b_in) * s_in;
+      bufA[t * pitch + e] = data[base + (long)e * es];
+    }
+  }
+  __syncthreads();
+  V* src = bufA;
+  V* dst = bufB;
+  int Ns = 1;
+  int rem = log2n;
+  while (rem > 0) {
+    const int R = (rem & 1) ? 2 : 4;
+    const int lr = (R == 4) ? 2 : 1;
+    const int nb = n >> lr;
+    const int step_log = twlog2 - (__builtin_ctz(Ns) + lr);   // NT / (Ns R)
+    for (int idx = threadIdx.x; idx < ntile * nb; idx += blockDim.x) {
+      const int t = idx / nb, j = idx - t * nb;
+      const V* s = src + t * pitch;
+      V* d = dst + t * pitch;
+      const int kk = j & (Ns - 1);
+      const int od = ((j - kk) << lr) + kk;
+      if (R == 4) {
+        V v0 = s[j], v1 = s[j + nb], v2 = s[j + 2 * nb], v3 = s[j + 3 * nb];
+        if (Ns > 1) {
+          v1 = c_mul(v1, tw[(kk) << step_log]);
+          v2 = c_mul(v2, tw[(2 * kk) << step_log]);
+          v3 = c_mul(v3, tw[(3 * kk) << step_log]);
+        }
+        const V a0 = c_add(v0, v2), a1 = c_sub(v0, v2), a2 = c_add(v1, v3), a3 = c_sub(v1, v3);
+        d[od] = c_add(a0, a2);
+        d[od + Ns] = c_addi(a1, a3);
+        d[od + 2 * Ns] = c_sub(a0, a2);
+        d[od + 3 * Ns] = c_subi(a1, a3);
+      } else {
+        V v0 = s[j], v1 = s[j + nb];
+        if (Ns > 1) v1 = c_mul(v1, tw[kk << step_log]);
+        d[od] = c_add(v0, v1);
+        d[od + Ns] = c_sub(v0, v1);
+      }
+    }
+    __syncthreads();
+    V* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= R;
+    rem -= lr;
+  }
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int t, e;
+    if (es == 1) { t = idx / n; e = idx - t * n; }
+    else { e = idx / tile; t = idx - e * tile; }
+    if (t < ntile) {
+      const long b = b0 + t;
+      const long base = (b / b_in) * s_out + (b % b_in) * s_in;
+      data[base + (long)e * es] = src[t * pitch + e];
+    }
+  }
+}
+
+template <typename T>
+hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
+  if (n <= 1 || nbatch <= 0) return hipSuccess;
+  const int log2n = __builtin_ctz((unsigned)n);
+  // about 32 KiB per LDS buffer
+  const int budget = (int)(32768 / sizeof(cplx<T>));
+  int tile = budget / (n + 1);
+  if (tile < 1) tile = 1;
+  if (tile > 64) tile = 64;
+  if (tile > nbatch) tile = (int)nbatch;
+  const size_t shm = (size_t)2 * tile * (n + 1) * sizeof(cplx<T>);
+  const long nblk = (nbatch + tile - 1) / tile;
+  const cplx<T>* tw = nullptr;
+  if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
+  hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(256), shm, P.stream, static_cast<cplx<T>*>(data), n, log2n,
+                     es, nbatch, b_in, s_in, s_out, tile, tw, P.twlog2);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
+  return P.p.prec == QPGF_C128 ? fft_impl<double>(P, data, n, es, nbatch, b_in, s_in, s_out)
+                               : fft_impl<float>(P, data, n, es, nbatch, b_in, s_in, s_out);
+}
+
+}  // namespace qpgf

@@ -1,0 +1,339 @@
+// FP64 coefficient fills: L-hat of the near grid (2D: eqs. 2.1, 2.3-2.5;
+// 3D: eqs. 3.3, 3.5; Maxwell: Section 4), the k-independent 2D singular tables
+// (eqs. 2.4, 2.5), the radial table of the 3D singular transform, and the
+// far-slab coefficients of the eigenfunction series (1.2), (1.3).
+//
+// Layout: coefficient j (centred, -M/2 <= j < M/2) of an axis of size M is
+// stored at index j mod M ("FFT order"), so the grid sums become plain
+// unnormalised inverse DFTs.  Near fields: [jt'][j2'][j1'] (3D) or [j2'][j1']
+// (2D), j1 fastest; far slab: [s][j2'][j1'] or [s][j1'].
+#include "qpgf_internal.h"
+
+namespace qpgf {
+
+namespace {
+
+constexpr int TP = 16;   // pencils (periodic-axis coefficients) per block
+constexpr int TL = 16;   // transverse lanes per pencil
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+__device__ __forceinline__ int centered(int jp, int M) { return jp < (M >> 1) ? jp : jp - M; }
+
+template <typename T> __device__ __forceinline__ void store_c(cplx<T>* p, size_t i, double2 v);
+template <> __device__ __forceinline__ void store_c<double>(double2* p, size_t i, double2 v) { p[i] = v; }
+template <> __device__ __forceinline__ void store_c<float>(float2* p, size_t i, double2 v) {
+  p[i] = make_float2((float)v.x, (float)v.y);
+}
+
+struct FillArgs {
+  double k, a1, a2;
+  double c, c_tilde, A;      // A = A2 = 1/(2 sqrt(pi c~)) or A3 = 1/sqrt(8 pi^2 c~)
+                             // (the basis normalisation: L-hat carries one factor A,
+                             // the grid sum L_N = sum L-hat_j phi_j another; both are
+                             // applied here so the FFTs are plain sums)
+  int M1, M2, Mt, Q;
+  double hd;                 // H table spacing (3D)
+  long fstride;              // elements per field
+};
+
+// a_q = w_q X'(x_q) e^{i beta x_q} for the TP pencils of this block, into LDS.
+// beta depends on the pencil only, so the X'-integrals of every transverse
+// coefficient of a pencil reduce to sums over these Q values.
+template <int DIM>
+__device__ __forceinline__ void pencil_weights(const FillArgs& A, int j1p0, int j2p, const double* __restrict__ xq,
+                                               const double* __restrict__ wxq, double2* sa) {
+  for (int idx = threadIdx.x; idx < TP * A.Q; idx += blockDim.x) {
+    int pp = idx / A.Q, q = idx - pp * A.Q;
+    int j1p = min(j1p0 + pp, A.M1 - 1);
+    double rho;
+    if (DIM == 2) {
+      rho = fabs(A.a1 + centered(j1p, A.M1));
+    } else {
+      double e1 = A.a1 + centered(j1p, A.M1), e2 = A.a2 + centered(j2p, A.M2);
+      rho = sqrt(e1 * e1 + e2 * e2);
+    }
+    double2 b = beta_of(A.k, rho);
+    sa[pp * A.Q + q] = cscale(cexpi(cscale(b, xq[q])), wxq[q]);
+  }
+}
+
+// I(b - J)/(2b(J - b)) - I(b + J)/(2b(J + b)), with I(g) = int e^{igx} X'(x) dx
+// = sum_q a_q e^{-+iJx_q}:  I(b-J) = C - iS, I(b+J) = C + iS,
+// C = sum_q a_q cos(J x_q), S = sum_q a_q sin(J x_q).
+__device__ __forceinline__ double2 xprime_term(const double2* __restrict__ ap, const double2* __restrict__ csr, int Q,
+                                               double sgn, double J, double2 b) {
+  double2 C = mk(0.0, 0.0), S = mk(0.0, 0.0);
+  for (int q = 0; q < Q; ++q) {
+    double2 a = ap[q], t = csr[q];
+    C.x = fma(a.x, t.x, C.x);
+    C.y = fma(a.y, t.x, C.y);
+    S.x = fma(a.x, t.y, S.x);
+    S.y = fma(a.y, t.y, S.y);
+  }
+  S = cscale(S, sgn);
+  double2 Im = mk(C.x + S.y, C.y - S.x);
+  double2 Ip = mk(C.x - S.y, C.y + S.x);
+  double2 b2 = cscale(b, 2.0);
+  double2 dm = cmul(b2, mk(J - b.x, -b.y));
+  double2 dp = cmul(b2, mk(J + b.x, b.y));
+  return csub(cdiv(Im, dm), cdiv(Ip, dp));
+}
+
+// H(rho) by 8-point Lagrange interpolation of the table H(m hd - 4 hd).
+__device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, double hd, double rho) {
+  double u = rho / hd;
+  double fl = floor(u);
+  double f = u - fl;
+  int m0 = (int)fl + 1;   // table index of the node at relative position -3
+  double pre[8], suf[8];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int a = 1; a < 8; ++a) pre[a] = pre[a - 1] * (f - (double)(a - 4));
+  suf[7] = 1.0;
+#pragma unroll
+  for (int a = 6; a >= 0; --a) suf[a] = suf[a + 1] * (f - (double)(a - 2));
+  const double den[8] = {-5040.0, 720.0, -240.0, 144.0, -144.0, 240.0, -720.0, 5040.0};
+  double2 acc = mk(0.0, 0.0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    double w = pre[a] * suf[a] / den[a];
+    double2 h = tab[m0 + a];
+    acc.x = fma(w, h.x, acc.x);
+    acc.y = fma(w, h.y, acc.y);
+  }
+  return acc;
+}
+
+// 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF == 7):
+// L-hat_dj = A3 [ I-terms + H(|xi|) / (|xi|^2 - k^2) ], i.e. K-hat_dj of (3.3)
+// minus F-hat_j of (3.5) with the common 1/(|xi|^2-k^2) cancelled exactly.
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __restrict__ xq,
+                                                const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                                const double2* __restrict__ htab, cplx<T>* __restrict__ out) {
+  extern __shared__ double2 sa[];
+  const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
+  const int j1p0 = blockIdx.x * TP, j2p = blockIdx.y;
+  const int j1p = j1p0 + ip;
+  pencil_weights<3>(A, j1p0, j2p, xq, wxq, sa);
+  __syncthreads();
+  if (j1p >= A.M1) return;
+  const double xi1 = A.a1 + centered(j1p, A.M1), xi2 = A.a2 + centered(j2p, A.M2);
+  const double rp2 = xi1 * xi1 + xi2 * xi2;
+  const double2 b = beta_of(A.k, sqrt(rp2));
+  const bool use_I = b.y * A.c < 41.5;   // else |I| < e^{-c Im beta} < 1e-18
+  const double2* ap = sa + ip * A.Q;
+  const double k2 = A.k * A.k;
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+    const double rho2 = rp2 + J * J;
+    const double2 H = h_interp(htab, A.hd, sqrt(rho2));
+    const double2 L = cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A);
+    const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
+    store_c<T>(out, o, L);
+    if (NF == 7) {
+      // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~)
+      const double cc[3] = {xi1, xi2, J};
+      const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int f = 0; f < 6; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+    }
+  }
+}
+
+// 2D near fill (Algorithm 2.1 steps 1a-1b): L-hat = K-hat (2.1) - F1 + i alpha F2 (2.3).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __restrict__ xq,
+                                                const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                                const double2* __restrict__ F1, const double2* __restrict__ F2,
+                                                cplx<T>* __restrict__ out) {
+  extern __shared__ double2 sa[];
+  const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
+  const int j1p0 = blockIdx.x * TP;
+  const int j1p = j1p0 + ip;
+  pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
+  __syncthreads();
+  if (j1p >= A.M1) return;
+  const double a = A.a1 + centered(j1p, A.M1);
+  const double2 b = beta_of(A.k, fabs(a));
+  const bool use_I = b.y * A.c < 41.5;
+  const double2* ap = sa + ip * A.Q;
+  const double lead0 = a * a - A.k * A.k;
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+    const double2 K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    const size_t o = (size_t)jtp * A.M1 + j1p;
+    const double2 f1 = F1[o], f2 = F2[o];
+    // L = K - F1 + i alpha F2, times the basis normalisation A2
+    const double2 L = cscale(mk(K.x - f1.x - A.a1 * f2.y, K.y - f1.y + A.a1 * f2.x), A.A);
+    store_c<T>(out, o, L);
+  }
+}
+
+// 2D singular tables (eqs. 2.4, 2.5), k- and alpha-independent (Remark 2.1):
+// Phi-hat_1 / 2pi = A2 int Phi1(r) J0(|eta| r) r dr,
+// Phi-hat_2 / 2pi = -i A2 (j1/|eta|) int Phi1(r) J1(|eta| r) r^2 dr, eta = (j1, j2 pi/c~).
+__global__ void k_sing2d(int M1, int M2, double c_tilde, double A2, int Q, const double* __restrict__ rq,
+                         const double* __restrict__ wphi, double f1zero, double2* __restrict__ F1,
+                         double2* __restrict__ F2) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M1 * M2) return;
+  const int j1p = (int)(idx % M1), j2p = (int)(idx / M1);
+  const double e1 = centered(j1p, M1), J = centered(j2p, M2) * kPi / c_tilde;
+  const double eta2 = e1 * e1 + J * J;
+  if (eta2 == 0.0) {
+    F1[idx] = mk(f1zero, 0.0);
+    F2[idx] = mk(0.0, 0.0);
+    return;
+  }
+  const double eta = sqrt(eta2);
+  double i0 = 0.0, i1 = 0.0;
+  for (int q = 0; q < Q; ++q) {
+    const double r = rq[q], er = eta * r;
+    i0 = fma(wphi[q] * r, j0(er), i0);
+    i1 = fma(wphi[q] * r * r, j1(er), i1);
+  }
+  const double f1 = (A2 + A2 * i0) / eta2;
+  F1[idx] = mk(f1, 0.0);
+  F2[idx] = mk(0.0, (-2.0 * e1 * f1 - A2 * (e1 / eta) * i1) / eta2);
+}
+
+// H(rho) = rho^-1 int_eps^{2eps} e^{ikr} (2ik Y' + Y'') sin(rho r) dr (the radial
+// form of the integral in eq. 3.5), tabulated on rho = (m - 4) hd, m in [0, hn).
+__global__ void k_htable(int hn, double hd, double k, int Q, const double* __restrict__ rq,
+                         const double* __restrict__ wrq, const double* __restrict__ y1q,
+                         const double* __restrict__ y2q, double2* __restrict__ htab) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= hn) return;
+  const double rho = fabs((m - 4) * hd);
+  double2 acc = mk(0.0, 0.0);
+  for (int q = 0; q < Q; ++q) {
+    const double r = rq[q];
+    double s, c;
+    sincos(k * r, &s, &c);
+    double2 g = cmul(mk(c, s), mk(y2q[q], 2.0 * k * y1q[q]));
+    const double sn = rho > 0.0 ? sin(rho * r) / rho : r;
+    acc = cadd(acc, cscale(g, wrq[q] * sn));
+  }
+  htab[m] = acc;
+}
+
+// Far slab, 3D: per-slice coefficients (i/8pi^2) beta^-1 e^{i beta z_s} of the
+// series (1.3) (times -xi_p xi_q, xi3 = beta, for the Maxwell fields).
+template <typename T, int NF>
+__global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, double z0, double hf, long fstride,
+                        cplx<T>* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)M1 * M2 * S;
+  if (idx >= n) return;
+  const int j1p = (int)(idx % M1);
+  const int j2p = (int)((idx / M1) % M2);
+  const int s = (int)(idx / ((long)M1 * M2));
+  const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
+  const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
+  const double z = z0 + s * hf;
+  const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
+  store_c<T>(out, idx, v);
+  if (NF == 7) {
+    const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
+    const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      double2 m = cmul(cc[P[f]], cc[Qp[f]]);
+      store_c<T>(out, (f + 1) * fstride + idx, cmul(v, mk(-m.x, -m.y)));
+    }
+  }
+}
+
+// Far slab, 2D: (i/4pi) beta_n^-1 e^{i beta_n z_s} of the series (1.2).
+template <typename T>
+__global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf, cplx<T>* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M1 * S) return;
+  const int j1p = (int)(idx % M1), s = (int)(idx / M1);
+  const double2 b = beta_of(k, fabs(a + centered(j1p, M1)));
+  const double z = z0 + s * hf;
+  store_c<T>(out, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
+}
+
+template <typename T>
+hipError_t fill_impl(Plan& P, double k, double a1, double a2) {
+  FillArgs A;
+  A.k = k;
+  A.a1 = a1;
+  A.a2 = a2;
+  A.c = P.p.c;
+  A.c_tilde = P.p.c_tilde;
+  A.M1 = P.M1;
+  A.M2 = P.M2;
+  A.Mt = P.Mt;
+  A.Q = P.p.quad_q;
+  A.hd = P.hd;
+  A.fstride = (long)P.ncell;
+  const size_t shm = (size_t)TP * A.Q * sizeof(double2);
+  auto* out = static_cast<cplx<T>*>(P.grid);
+  if (P.dim == 2) {
+    A.A = 1.0 / (2.0 * sqrt(kPi * A.c_tilde));
+    dim3 grid((P.M1 + TP - 1) / TP, 1);
+    hipLaunchKernelGGL(k_fill2d<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2, out);
+  } else {
+    A.A = 1.0 / sqrt(8.0 * kPi * kPi * A.c_tilde);
+    dim3 grid((P.M1 + TP - 1) / TP, P.M2);
+    if (P.nf == 7)
+      hipLaunchKernelGGL((k_fill3d<T, 7>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab, out);
+    else
+      hipLaunchKernelGGL((k_fill3d<T, 1>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab, out);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t far_impl(Plan& P, double k, double a1, double a2) {
+  auto* out = static_cast<cplx<T>*>(P.far);
+  const double hf = P.p.far_h, z0 = P.p.c - hf;
+  if (P.dim == 2) {
+    long n = (long)P.M1 * P.S;
+    hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
+  } else {
+    long n = (long)P.M1 * P.M2 * P.S;
+    if (P.nf == 7)
+      hipLaunchKernelGGL((k_far3d<T, 7>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
+                         z0, hf, (long)P.nfar, out);
+    else
+      hipLaunchKernelGGL((k_far3d<T, 1>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
+                         z0, hf, (long)P.nfar, out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sing2d(Plan& P, double f1zero) {
+  const long n = (long)P.M1 * P.M2;
+  const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
+  hipLaunchKernelGGL(k_sing2d, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
+                     P.p.quad_q, P.rq, P.wrq, f1zero, P.F1, P.F2);
+  return hipGetLastError();
+}
+
+hipError_t launch_htable(Plan& P, double k) {
+  hipLaunchKernelGGL(k_htable, dim3((P.hn + 255) / 256), dim3(256), 0, P.stream, P.hn, P.hd, k, P.p.quad_q, P.rq,
+                     P.wrq, P.y1q, P.y2q, P.htab);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(Plan& P, double k, double a1, double a2) {
+  return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2) : fill_impl<float>(P, k, a1, a2);
+}
+
+hipError_t launch_far(Plan& P, double k, double a1, double a2) {
+  return P.p.prec == QPGF_C128 ? far_impl<double>(P, k, a1, a2) : far_impl<float>(P, k, a1, a2);
+}
+
+}  // namespace qpgf

@@ -1,0 +1,135 @@
+// Internal declarations of libqpgf: plan layout, device helpers, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/qpgf.h"
+
+namespace qpgf {
+
+// ---------------------------------------------------------------------------
+// complex helpers (FP64 work is done in double2; bulk storage in T2)
+// ---------------------------------------------------------------------------
+template <typename T> struct C2;
+template <> struct C2<double> { using type = double2; };
+template <> struct C2<float> { using type = float2; };
+template <typename T> using cplx = typename C2<T>::type;
+
+__host__ __device__ inline double2 mk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return mk(a.x * s, a.y * s); }
+// Smith's algorithm: a / b without overflow for large |b|.
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return mk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  double r = b.x / b.y, d = b.x * r + b.y;
+  return mk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__host__ __device__ inline double2 crecip(double2 b) { return cdiv(mk(1.0, 0.0), b); }
+// e^{i z} for complex z.
+__device__ inline double2 cexpi(double2 z) {
+  double s, c;
+  sincos(z.x, &s, &c);
+  double m = exp(-z.y);
+  return mk(m * c, m * s);
+}
+// beta = sqrt(k^2 - rho^2) on the branch Im beta >= 0 (Section 1), evaluated as
+// sqrt((k - rho)(k + rho)) so it does not cancel near a Wood anomaly.
+__host__ __device__ inline double2 beta_of(double k, double rho) {
+  double d = (k - rho) * (k + rho);
+  return d >= 0.0 ? mk(sqrt(d), 0.0) : mk(0.0, sqrt(-d));
+}
+
+// ---------------------------------------------------------------------------
+// C^8 cut-off transition S(u) = I_u(9,9) (Bernstein form), S', S''
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double smooth_S(double u) {
+  if (u <= 0.0) return 0.0;
+  if (u >= 1.0) return 1.0;
+  // sum_{j=9}^{17} C(17,j) u^j (1-u)^{17-j}
+  const double binom[9] = {24310.0, 19448.0, 12376.0, 6188.0, 2380.0, 680.0, 136.0, 17.0, 1.0};
+  double v = 1.0 - u, s = 0.0;
+  double uj = 1.0;
+  for (int j = 0; j < 9; ++j) uj *= u;  // u^9
+  double vp[9];
+  vp[0] = 1.0;
+  for (int j = 1; j < 9; ++j) vp[j] = vp[j - 1] * v;  // v^0..v^8
+  for (int j = 9; j <= 17; ++j) {
+    s += binom[j - 9] * uj * vp[17 - j];
+    uj *= u;
+  }
+  return s;
+}
+__host__ __device__ inline double smooth_S1(double u) {
+  if (u <= 0.0 || u >= 1.0) return 0.0;
+  double w = u * (1.0 - u), w2 = w * w, w4 = w2 * w2;
+  return 218790.0 * w4 * w4;
+}
+__host__ __device__ inline double smooth_S2(double u) {
+  if (u <= 0.0 || u >= 1.0) return 0.0;
+  double w = u * (1.0 - u), w2 = w * w, w4 = w2 * w2;
+  return 218790.0 * 8.0 * w4 * w2 * w * (1.0 - 2.0 * u);
+}
+// Y_eps(r) = 1 - S((r - eps)/eps) and its radial derivatives.
+__host__ __device__ inline double cut_Y(double r, double eps) { return 1.0 - smooth_S((r - eps) / eps); }
+__host__ __device__ inline double cut_Y1(double r, double eps) { return -smooth_S1((r - eps) / eps) / eps; }
+__host__ __device__ inline double cut_Y2(double r, double eps) { return -smooth_S2((r - eps) / eps) / (eps * eps); }
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+constexpr int kMaxLog2 = 12;   // m <= 4096
+
+struct Plan {
+  qpgf_params p;
+  int dim = 2, nf = 1;         // nf: number of fields (7 for Maxwell)
+  int M1 = 0, M2 = 0, M3 = 1;  // 2D: M3 = 1, M2 = transverse
+  int Mt = 0;                  // transverse size (M2 in 2D, M3 in 3D)
+  int S = 0;                   // far-slab slices
+  size_t ncell = 0;            // points per near field
+  size_t nfar = 0;             // points per far field
+  size_t esize = 16;           // bytes per complex element
+  hipStream_t stream = nullptr;
+
+  // device buffers
+  void* grid = nullptr;        // nf * ncell complex
+  void* far = nullptr;         // nf * nfar complex
+  double* xq = nullptr;        // X' quadrature nodes on [c, (c+c~)/2]
+  double* wxq = nullptr;       // weights * X'(node)
+  double2* cs = nullptr;       // [Nt+1][Q]: (cos, sin)(j pi/c~ * xq)
+  double* rq = nullptr;        // radial quadrature nodes on [eps, 2 eps]
+  double* wrq = nullptr;       // weights
+  double* y1q = nullptr;       // Y'(rq)
+  double* y2q = nullptr;       // Y''(rq)
+  double2* tw = nullptr;       // twiddles e^{2 pi i j / NT}, double
+  float2* twf = nullptr;       // same, float
+  int twlog2 = 0;
+  double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
+  double2* F2 = nullptr;
+  double2* htab = nullptr;     // 3D: H(rho) on rho = (m - 4) dh
+  int hn = 0;
+  double hd = 0.05;
+  double last_k = 0, last_a1 = 0, last_a2 = 0;
+  bool prepared = false;
+};
+
+// kernel launchers (fill.hip, fft.hip, gather.hip)
+hipError_t launch_sing2d(Plan& P, double f1_zero);
+hipError_t launch_htable(Plan& P, double k);
+hipError_t launch_fill(Plan& P, double k, double a1, double a2);
+hipError_t launch_far(Plan& P, double k, double a1, double a2);
+hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
+                      long s_out);
+hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
+
+}  // namespace qpgf

@@ -1,0 +1,185 @@
+"""Thin ctypes binding of libqpgf (include/qpgf.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module only turns torch
+CUDA tensors into device pointers and the current torch stream into the
+plan's HIP stream.  Loading fails loudly if ``libqpgf.so`` is missing: there is
+no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpgf.so")
+
+C128, C64 = 0, 1
+KIND_G2D, KIND_GD3D, KIND_MAXWELL3D = 0, 1, 2
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_WOOD", 3: "E_SPECIAL", 4: "E_SIZE", 5: "E_HIP", 6: "E_NOMEM",
+          7: "E_UNSUPPORTED"}
+
+
+class QpgfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qpgf {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("prec", ctypes.c_int), ("m1", ctypes.c_int), ("m2", ctypes.c_int),
+                ("m3", ctypes.c_int), ("c", ctypes.c_double), ("c_tilde", ctypes.c_double),
+                ("eps", ctypes.c_double), ("quad_q", ctypes.c_int), ("far_h", ctypes.c_double),
+                ("far_zmax", ctypes.c_double), ("wood_tol", ctypes.c_double), ("special_tol", ctypes.c_double),
+                ("lattice_rmin", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("prec", ctypes.c_int), ("m1", ctypes.c_int), ("m2", ctypes.c_int),
+                ("m3", ctypes.c_int), ("far_slices", ctypes.c_int), ("far_h", ctypes.c_double),
+                ("c", ctypes.c_double), ("c_tilde", ctypes.c_double), ("eps", ctypes.c_double),
+                ("n_fields", ctypes.c_int), ("grid_bytes", ctypes.c_size_t), ("far_grid_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
+           "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
+           "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_last_error", "qpgf_version"]
+
+_lib = None
+
+
+def lib():
+    """Load libqpgf.so (once); raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_1801_05977_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, D, I64, VP, U8P = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+    L.qpgf_params_default.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int]
+    L.qpgf_params_default.restype = None
+    L.qpgf_plan_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(P)]
+    L.qpgf_plan_destroy.argtypes = [P]
+    L.qpgf_plan_destroy.restype = None
+    L.qpgf_plan_set_stream.argtypes = [P, VP]
+    L.qpgf_plan_get_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    L.qpgf_prepare.argtypes = [P, D, D, D]
+    L.qpgf_prepare_stage.argtypes = [P, D, D, D, ctypes.c_int]
+    L.qpgf_evaluate.argtypes = [P, VP, I64, VP, U8P]
+    L.qpgf_g2d.argtypes = [P, D, D, VP, I64, VP, U8P]
+    L.qpgf_gd3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
+    L.qpgf_maxwell3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
+    L.qpgf_copy_field.argtypes = [P, ctypes.c_int, ctypes.c_int, VP]
+    L.qpgf_last_error.restype = ctypes.c_char_p
+    L.qpgf_version.restype = ctypes.c_char_p
+    for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
+                 "qpgf_prepare_stage", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
+                 "qpgf_copy_field"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise QpgfError(status, lib().qpgf_last_error().decode())
+
+
+def default_params(kind, prec, m1, m2, m3=0, **overrides):
+    p = Params()
+    lib().qpgf_params_default(ctypes.byref(p), kind, prec, m1, m2, m3)
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t, dtype, name):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A qpgf plan bound to torch's current CUDA stream at each call."""
+
+    def __init__(self, kind, prec, m1, m2, m3=0, **overrides):
+        self.params = default_params(kind, prec, m1, m2, m3, **overrides)
+        self._h = ctypes.c_void_p()
+        torch.cuda.init()
+        _check(lib().qpgf_plan_create(ctypes.byref(self.params), ctypes.byref(self._h)))
+        info = PlanInfo()
+        _check(lib().qpgf_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.kind, self.prec = kind, prec
+        self.dim = 2 if kind == KIND_G2D else 3
+        self.cdtype = torch.complex128 if prec == C128 else torch.complex64
+
+    def close(self):
+        if self._h:
+            lib().qpgf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        _check(lib().qpgf_plan_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def out_tensor(self, T):
+        shape = (T, 6) if self.kind == KIND_MAXWELL3D else (T,)
+        return torch.empty(shape, dtype=self.cdtype, device="cuda")
+
+    def prepare(self, k, a1, a2=0.0, stage=2):
+        self._stream()
+        _check(lib().qpgf_prepare_stage(self._h, k, a1, a2, stage))
+
+    def evaluate(self, x, out=None, flags=None):
+        T = x.shape[0]
+        if out is None:
+            out = self.out_tensor(T)
+        self._stream()
+        _check(lib().qpgf_evaluate(self._h, _ptr(x, torch.float64, "x"), T, _ptr(out, self.cdtype, "out"),
+                                   _ptr(flags, torch.uint8, "flags")))
+        return out
+
+    def __call__(self, k, a1, a2=0.0, x=None, out=None, flags=None):
+        """prepare + evaluate through the kind's own entry point (qpgf_g2d / qpgf_gd3d / qpgf_maxwell3d)."""
+        T = x.shape[0]
+        if out is None:
+            out = self.out_tensor(T)
+        self._stream()
+        px, po, pf = _ptr(x, torch.float64, "x"), _ptr(out, self.cdtype, "out"), _ptr(flags, torch.uint8, "flags")
+        if self.kind == KIND_G2D:
+            _check(lib().qpgf_g2d(self._h, k, a1, px, T, po, pf))
+        elif self.kind == KIND_GD3D:
+            _check(lib().qpgf_gd3d(self._h, k, a1, a2, px, T, po, pf))
+        else:
+            _check(lib().qpgf_maxwell3d(self._h, k, a1, a2, px, T, po, pf))
+        return out
+
+    def field(self, which=0, field=0):
+        """Copy of a near-grid (which=0) or far-slab (which=1) field as a flat complex tensor."""
+        n = (self.info.grid_bytes if which == 0 else self.info.far_grid_bytes) // (16 if self.prec == C128 else 8)
+        dst = torch.empty(n, dtype=self.cdtype, device="cuda")
+        self._stream()
+        _check(lib().qpgf_copy_field(self._h, which, field, ctypes.c_void_p(dst.data_ptr())))
+        return dst
+
+
+def g2d(k, alpha, x, m1, m2, prec=C128, **kw):
+    return Plan(KIND_G2D, prec, m1, m2, **kw)(k, alpha, 0.0, x)
+
+
+def gd3d(k, a1, a2, x, m1, m2, m3, prec=C128, **kw):
+    return Plan(KIND_GD3D, prec, m1, m2, m3, **kw)(k, a1, a2, x)
+
+
+def maxwell3d(k, a1, a2, x, m1, m2, m3, prec=C128, **kw):
+    return Plan(KIND_MAXWELL3D, prec, m1, m2, m3, **kw)(k, a1, a2, x)

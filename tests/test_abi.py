@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, its structs match the ctypes layout, and argument validation
+(which runs before any HIP call) reports the documented status codes."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1801_05977_amd import qpgf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qpgf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qpgf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = qpgf.lib()
+    names = _declared()
+    assert "qpgf_plan_create" in names and "qpgf_gd3d" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(qpgf.EXPORTS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "qpgf.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(qpgf_params), offsetof(qpgf_params, lattice_rmin),"
+        " sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes), offsetof(qpgf_params, quad_q));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(qpgf.Params), qpgf.Params.lattice_rmin.offset, ctypes.sizeof(qpgf.PlanInfo),
+            qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset]
+    assert got == want
+
+
+def test_params_default_values():
+    p = qpgf.default_params(qpgf.KIND_GD3D, qpgf.C64, 256, 256, 64)
+    assert (p.kind, p.prec, p.m1, p.m2, p.m3) == (1, 1, 256, 256, 64)
+    assert (p.c, p.c_tilde, p.eps, p.quad_q) == (0.6, 1.0, 0.2, 64)
+    assert p.far_h == pytest.approx(1.0 / 32)
+    assert p.far_zmax == 1.0 and p.wood_tol == 1e-3
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("m1", 100, 4), ("m2", 8, 4), ("m3", 3, 4), ("c", 1.5, 1), ("eps", 0.6, 1), ("quad_q", 4, 1),
+    ("far_h", 0.0, 1), ("kind", 9, 1), ("prec", 5, 1),
+])
+def test_plan_create_rejects_bad_params(field, value, status):
+    L = qpgf.lib()
+    p = qpgf.default_params(qpgf.KIND_GD3D, qpgf.C128, 64, 64, 32)
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    st = L.qpgf_plan_create(ctypes.byref(p), ctypes.byref(h))
+    assert st == status
+    assert not h.value
+    assert L.qpgf_last_error().decode()
+
+
+def test_null_arguments():
+    L = qpgf.lib()
+    assert L.qpgf_plan_create(None, None) == 1
+    assert L.qpgf_prepare(None, 1.0, 0.1, 0.2) == 1
+    assert L.qpgf_evaluate(None, None, 0, None, None) == 1
+    assert L.qpgf_version().decode().startswith("qpgf")

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Stage checks compare coefficient fills, grids and far slabs element by element;
+end-to-end checks compare G, G_d and the Maxwell tensor at seeded targets.
+Bars (spec tolerances): complex128 path max parity error <= 1e-10,
+complex64 path <= 1e-5, where the parity error of a result set is
+max_i |g_i - o_i| / max(|o_i|, s), s = RMS |o| over the set (a pointwise
+relative error that does not blow up at isolated zeros of G).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import method
+from paper_1801_05977_amd import qpgf, workloads
+
+pytestmark = pytest.mark.gpu
+
+A2 = 1.0 / (2.0 * math.sqrt(math.pi))
+A3 = 1.0 / math.sqrt(8.0 * math.pi ** 2)
+TOL = {qpgf.C128: 1e-10, qpgf.C64: 1e-5}
+
+
+def parity(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    s = np.sqrt(np.mean(np.abs(o) ** 2))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), s)))
+
+
+def cen(a, axes):
+    """FFT order (index j mod M) -> centred order (index j + M/2) along the given axes."""
+    return np.fft.fftshift(a, axes=axes)
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+# ----------------------------------------------------------------------------- 2D stages
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_fill2d_and_grid2d_stages(prec):
+    M1, M2 = 64, 32
+    k, al = 2.1, 0.3
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
+    ref_L = A2 * method.lhat_2d(k, al, M1 // 2, M2 // 2)
+    P.prepare(k, al, 0.0, stage=0)
+    g = cen(P.field().cpu().numpy().reshape(M2, M1).T, (0, 1))
+    tol = 1e-13 if prec == qpgf.C128 else 1e-7
+    assert np.abs(g - ref_L).max() <= tol * np.abs(ref_L).max()
+    P.prepare(k, al, 0.0, stage=2)
+    g = cen(P.field().cpu().numpy().reshape(M2, M1).T, (0, 1))
+    ref_G = method.grid_2d(ref_L / A2)
+    tol = 1e-12 if prec == qpgf.C128 else 2e-6
+    assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
+    far = P.field(which=1).cpu().numpy().reshape(P.info.far_slices, M1)
+    z = method.far_slices(P.info.far_h, P.info.far_slices)
+    ref_F = method.far_grid_2d(k, al, M1 // 2, z)
+    assert np.abs(cen(far, (1,)) - ref_F).max() <= tol * np.abs(ref_F).max()
+
+
+# ----------------------------------------------------------------------------- 3D stages
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_fill3d_and_grid3d_stages(prec):
+    M1, M2, M3 = 32, 64, 32
+    k, a1, a2 = 3.7, 0.2, 0.35
+    P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
+    ref_L = A3 * method.lhat_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2)
+    P.prepare(k, a1, a2, stage=0)
+    g = cen(P.field().cpu().numpy().reshape(M3, M2, M1).transpose(2, 1, 0), (0, 1, 2))
+    tol = 1e-13 if prec == qpgf.C128 else 1e-7
+    assert np.abs(g - ref_L).max() <= tol * np.abs(ref_L).max()
+    P.prepare(k, a1, a2, stage=2)
+    g = cen(P.field().cpu().numpy().reshape(M3, M2, M1).transpose(2, 1, 0), (0, 1, 2))
+    ref_G = method.grid_3d(ref_L / A3)
+    tol = 1e-12 if prec == qpgf.C128 else 2e-6
+    assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
+    S = P.info.far_slices
+    far = P.field(which=1).cpu().numpy().reshape(S, M2, M1).transpose(0, 2, 1)
+    ref_F = method.far_grid_3d(k, a1, a2, M1 // 2, M2 // 2, method.far_slices(P.info.far_h, S))
+    assert np.abs(cen(far, (1, 2)) - ref_F).max() <= tol * np.abs(ref_F).max()
+
+
+# ----------------------------------------------------------------------------- end to end
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_g2d_small_workload(prec):
+    """2D, k = 2.1, alpha = 0.3, 256 x-modes, 64 slices, 1e4 uniform targets, seed 0."""
+    M1, M2, T = 256, 64, 10_000
+    k, al = 2.1, 0.3
+    x = workloads.targets(T, 2, seed=0)
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
+    flags = torch.empty(T, dtype=torch.uint8, device="cuda")
+    g = P(k, al, 0.0, dev(x), flags=flags).cpu().numpy()
+    o = method.eval_g2d(k, al, x, M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    assert parity(g, o) <= TOL[prec]
+    f = flags.cpu().numpy()
+    np.testing.assert_array_equal((f & 2) != 0, np.abs(x[:, 1]) > 0.6)
+    assert not np.any(f & 13)
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("shape", [(64, 64, 32), (32, 128, 64)])
+def test_gd3d_small(prec, shape):
+    M1, M2, M3 = shape
+    k, a1, a2 = 3.7, 0.2, 0.35
+    T = 3000
+    x = workloads.targets(T, 3, seed=2)
+    P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
+    g = P(k, a1, a2, dev(x)).cpu().numpy()
+    o = method.eval_gd3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    assert parity(g, o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_maxwell3d_small(prec):
+    M1, M2, M3 = 32, 32, 32
+    k, a1, a2 = 5.3, 0.1, 0.4
+    T = 2000
+    x = workloads.targets(T, 3, seed=3)
+    P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3)
+    g = P(k, a1, a2, dev(x)).cpu().numpy()
+    o = method.eval_maxwell3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    for comp in range(6):      # error per component, each with its own scale
+        assert parity(g[:, comp], o[:, comp]) <= TOL[prec], comp
+
+
+def test_prepare_then_evaluate_in_chunks_matches_single_call():
+    M1, M2, M3 = 64, 64, 32
+    k, a1, a2 = 3.7, 0.2, 0.35
+    x = dev(workloads.targets(5000, 3, seed=5))
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, M1, M2, M3)
+    whole = P(k, a1, a2, x)
+    P.prepare(k, a1, a2)
+    parts = torch.cat([P.evaluate(x[:1234].contiguous()), P.evaluate(x[1234:].contiguous())])
+    assert torch.equal(whole, parts)
+    again = P(k, a1, a2, x)
+    assert torch.equal(whole, again)            # deterministic
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_edge_targets_and_status_codes():
+    M1, M2 = 64, 32
+    k, al = 2.1, 0.3
+    P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C128, M1, M2)
+    x = np.array([[0.0, 0.0],                 # lattice point: NaN, flag 1
+                  [2 * math.pi, 0.0],         # lattice point one period over
+                  [math.pi, 0.1],             # x1 = pi reduces to t = -pi
+                  [-math.pi, 0.1],
+                  [1.0, 0.6],                 # |x2| = c exactly: near
+                  [1.0, 0.6000001],           # just far
+                  [1.0, 1.5],                 # beyond the far slab: NaN, flag 4
+                  [float("nan"), 0.2],        # non-finite: NaN, flag 8
+                  [0.3, -0.25]])
+    flags = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    g = P(k, al, 0.0, dev(x), flags=flags).cpu().numpy()
+    f = flags.cpu().numpy()
+    assert list(f) == [1, 1, 0, 0, 0, 2, 6, 8, 0]
+    assert np.isnan(g[[0, 1, 6, 7]]).all() and np.isfinite(g[[2, 3, 4, 5, 8]]).all()
+    o = method.eval_g2d(k, al, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    assert parity(g[[2, 3, 4, 5, 8]], o) <= 1e-10
+    # quasi-periodicity of the reduction: G(x1 + 2 pi) = e^{i 2 pi alpha} G(x1)
+    np.testing.assert_allclose(g[2], np.exp(2j * math.pi * al) * g[3], rtol=1e-12)
+    # T = 0 is a no-op
+    P(k, al, 0.0, dev(np.zeros((0, 2))))
+    # Wood anomaly: k = |alpha + 1| makes beta_1 = 0
+    with pytest.raises(qpgf.QpgfError) as e:
+        P(1.3, 0.3, 0.0, dev(x))
+    assert e.value.status == 2
+    # special coefficient: beta_0 = pi (j2 = 1, c~ = 1) for k^2 = alpha^2 + pi^2
+    with pytest.raises(qpgf.QpgfError) as e:
+        P(math.sqrt(0.3 ** 2 + math.pi ** 2), 0.3, 0.0, dev(x))
+    assert e.value.status == 3
+    # wrong entry point for the plan kind
+    P3 = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, 32, 32, 32)
+    with pytest.raises(qpgf.QpgfError) as e:
+        qpgf._check(qpgf.lib().qpgf_g2d(P3._h, k, al, None, 0, None, None))
+    assert e.value.status == 1
+
+
+# ----------------------------------------------------------------------------- full size, sampled
+
+@pytest.mark.timeout(900)
+def test_gd3d_full_size_sampled():
+    """3D G_d at the benchmark size: 256 x 256 modes, 64 slices, 1e7 targets.
+
+    The GPU evaluates all 1e7 targets in the launch configuration the benchmark
+    times; the oracle recomputes 400 of them (seeded sample, including the first
+    and last target) from its own full-size coefficients and direct-DFT grid.
+    """
+    M1, M2, M3, T = 256, 256, 64, 10_000_000
+    k, a1, a2 = 3.7, 0.2, 0.35
+    x = workloads.targets(T, 3, seed=2)
+    xd = dev(x)
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([[0, T - 1], rng.choice(T, 398, replace=False)]))
+    outs = {}
+    for prec in (qpgf.C128, qpgf.C64):
+        P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
+        outs[prec] = P(k, a1, a2, xd)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        info = P.info
+        P.close()
+    o = method.eval_gd3d(k, a1, a2, x[idx], M1 // 2, M2 // 2, M3 // 2, info.far_h, info.far_slices)
+    assert parity(outs[qpgf.C128], o) <= TOL[qpgf.C128]
+    assert parity(outs[qpgf.C64], o) <= TOL[qpgf.C64]
