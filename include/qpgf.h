@@ -158,6 +158,26 @@ qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alph
 qpgf_status qpgf_prepare_stage(qpgf_plan* plan, double k, double a1, double a2, int stage);
 qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst);
 
+/* Per-kernel timing, for profiling.  While enabled, every kernel the plan
+ * launches is bracketed by HIP events recorded on the plan's stream (the stream
+ * the kernel runs on).  qpgf_plan_get_timing waits for the recorded events and
+ * returns, for kernel class `id`, the summed duration in milliseconds and the
+ * number of launches since timing was last enabled.  Enabling resets the sums.
+ * Classes: */
+typedef enum {
+  QPGF_T_HTABLE = 0,   /* radial table H(rho) of the 3D singular transform       */
+  QPGF_T_FILL = 1,     /* FP64 coefficient fill of the near fields               */
+  QPGF_T_FFT_T = 2,    /* inverse FFT along the transverse axis                  */
+  QPGF_T_FFT_2 = 3,    /* inverse FFT along x2 (3D)                              */
+  QPGF_T_FFT_1 = 4,    /* inverse FFT along x1                                   */
+  QPGF_T_FAR = 5,      /* far-slab coefficient fill                              */
+  QPGF_T_FAR_FFT = 6,  /* inverse FFTs of the far slab                           */
+  QPGF_T_GATHER = 7,   /* interpolation gather, add-back and phase               */
+  QPGF_T_COUNT = 8
+} qpgf_timer_id;
+qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
+qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char* qpgf_last_error(void);
 

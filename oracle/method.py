@@ -354,24 +354,43 @@ def _psi_derivs(k, r, eps):
     return g * y, g1 * y + g * y1, g2 * y + 2 * g1 * y1 + g * y2
 
 
-def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
-            eps=co.EPS, q=ORACLE_Q):
-    """Algorithm 3.1 (G_d, returns [T]) or Algorithm 4.1 (Maxwell, returns [T,6]).
-
-    Maxwell components are ordered 11, 22, 33, 12, 13, 23.
-    """
+def prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
+               eps=co.EPS, q=ORACLE_Q):
+    """Algorithm 3.1 / 4.1 step 1: the near grids (1 or 7 fields) and the far-slab grids."""
     from .truth import MAXWELL_PAIRS
-    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
-    M1, M2, M3 = 2 * N1, 2 * N2, 2 * N3
-    h1, h2, h3 = math.pi / N1, math.pi / N2, c_tilde / N3
     L = lhat_3d(k, a1, a2, N1, N2, N3, c, c_tilde, eps, q)
     fields = [L] + ([m * L for m in maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde)] if maxwell else [])
     grids = [grid_3d(f, c_tilde) for f in fields]
+    z = far_slices(far_h, far_S, c)
+    mults = [None]
+    if maxwell:
+        def mk(p, qq):
+            return lambda xi1, xi2, b: -((xi1, xi2, b)[p] * (xi1, xi2, b)[qq])
+        mults += [mk(p, qq) for p, qq in MAXWELL_PAIRS]
+    fgrids = [far_grid_3d(k, a1, a2, N1, N2, z, m) for m in mults]
+    return dict(k=k, a1=a1, a2=a2, N=(N1, N2, N3), far_h=far_h, far_S=far_S, maxwell=maxwell, c=c,
+                c_tilde=c_tilde, eps=eps, grids=grids, fgrids=fgrids)
+
+
+def evaluate_3d(st, x):
+    """Algorithm 3.1 / 4.1 step 2 at targets x[T,3] against a prepared state.
+
+    Returns G_d [T] or the Maxwell components [T,6] (11, 22, 33, 12, 13, 23).
+    """
+    from .truth import MAXWELL_PAIRS
+    k, a1, a2, c, c_tilde, eps = st["k"], st["a1"], st["a2"], st["c"], st["c_tilde"], st["eps"]
+    N1, N2, N3 = st["N"]
+    far_h, far_S, maxwell = st["far_h"], st["far_S"], st["maxwell"]
+    grids, fgrids = st["grids"], st["fgrids"]
+    nfield = len(grids)
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    M1, M2, M3 = 2 * N1, 2 * N2, 2 * N3
+    h1, h2, h3 = math.pi / N1, math.pi / N2, c_tilde / N3
     t1, n1 = _reduce(x[:, 0])
     t2, n2 = _reduce(x[:, 1])
     x3 = x[:, 2]
     T = len(x)
-    vals = np.full((T, len(fields)), np.nan + 0j)
+    vals = np.full((T, nfield), np.nan + 0j)
     phase = np.exp(1j * (a1 * x[:, 0] + a2 * x[:, 1]))
     near = np.abs(x3) <= c
     if near.any():
@@ -384,25 +403,18 @@ def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_til
         psi, d1, d2 = _psi_derivs(k, r, eps)
         lat = np.exp(2j * math.pi * (a1 * n1[near] + a2 * n2[near]))
         vals[near, 0] = phase[near] * Ls[0] + lat * psi
-        for f, (p, qq) in enumerate(MAXWELL_PAIRS[: len(fields) - 1]):
+        for f, (p, qq) in enumerate(MAXWELL_PAIRS[: nfield - 1]):
             tp, tq = tt[:, p], tt[:, qq]
             hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
             vals[near, f + 1] = phase[near] * Ls[f + 1] + lat * hess
     far = ~near
     if far.any():
-        z = far_slices(far_h, far_S, c)
-        mults = [None]
-        if maxwell:
-            def mk(p, qq):
-                return lambda xi1, xi2, b: -((xi1, xi2, b)[p] * (xi1, xi2, b)[qq])
-            mults += [mk(p, qq) for p, qq in MAXWELL_PAIRS]
-        fgrids = [far_grid_3d(k, a1, a2, N1, N2, z, m) for m in mults]
         i1, w1 = _stencil((t1[far] + math.pi) / h1, M1)
         i2, w2 = _stencil((t2[far] + math.pi) / h2, M2)
         i3, w3, bad = _far_stencil(np.abs(x3[far]), far_h, far_S, c)
         Ls = _interp3(fgrids, i1, w1, i2, w2, i3, w3, slice_first=True)
         sg = np.sign(x3[far])
-        for f in range(len(fields)):
+        for f in range(nfield):
             v = phase[far] * Ls[f]
             if f >= 1 and 2 in MAXWELL_PAIRS[f - 1] and MAXWELL_PAIRS[f - 1] != (2, 2):
                 v = v * sg                     # d/dx3 of e^{i beta |x3|} brings sgn(x3)
@@ -413,6 +425,13 @@ def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_til
     out = vals[:, 1:] / k ** 2
     out[:, :3] += vals[:, :1]
     return out
+
+
+def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
+            eps=co.EPS, q=ORACLE_Q):
+    """Algorithm 3.1 (G_d, returns [T]) or Algorithm 4.1 (Maxwell, returns [T,6])."""
+    st = prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell, c, c_tilde, eps, q)
+    return evaluate_3d(st, x)
 
 
 def eval_gd3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, **kw):

@@ -161,11 +161,16 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage) {
       HIP_TRY(hipMalloc(reinterpret_cast<void**>(&P.htab), (size_t)need * sizeof(double2)));
       P.hn = need;
     }
+    KernelTimer t(P, QPGF_T_HTABLE);
     HIP_TRY(launch_htable(P, k));
   }
-  HIP_TRY(launch_fill(P, k, a1, a2));
+  {
+    KernelTimer t(P, QPGF_T_FILL);
+    HIP_TRY(launch_fill(P, k, a1, a2));
+  }
   if (stage >= 1) {
     const long nf = P.nf;
+    KernelTimer t(P, QPGF_T_FFT_T);
     if (P.dim == 2) {
       // transverse axis j2: stride M1, one batch per j1
       HIP_TRY(launch_fft(P, P.grid, P.M2, P.M1, (long)P.M1 * nf, P.M1, 1, (long)P.ncell));
@@ -176,17 +181,24 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage) {
   }
   if (stage >= 2) {
     const long nf = P.nf;
-    if (P.dim == 2) {
-      HIP_TRY(launch_fft(P, P.grid, P.M1, 1, (long)P.M2 * nf, 1, 0, P.M1));
-      HIP_TRY(launch_far(P, k, a1, a2));
-      HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)P.S * nf, 1, 0, P.M1));
-    } else {
-      // periodic axes x2 (columns) then x1 (rows), near grid and far slab
+    if (P.dim == 3) {
+      // periodic axis x2 (columns of each slice)
+      KernelTimer t(P, QPGF_T_FFT_2);
       HIP_TRY(launch_fft(P, P.grid, P.M2, P.M1, (long)P.M1 * P.M3 * nf, P.M1, 1, (long)P.M1 * P.M2));
+    }
+    {
+      KernelTimer t(P, QPGF_T_FFT_1);
       HIP_TRY(launch_fft(P, P.grid, P.M1, 1, (long)P.M2 * P.M3 * nf, 1, 0, P.M1));
+    }
+    {
+      KernelTimer t(P, QPGF_T_FAR);
       HIP_TRY(launch_far(P, k, a1, a2));
-      HIP_TRY(launch_fft(P, P.far, P.M2, P.M1, (long)P.M1 * P.S * nf, P.M1, 1, (long)P.M1 * P.M2));
-      HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)P.M2 * P.S * nf, 1, 0, P.M1));
+    }
+    {
+      KernelTimer t(P, QPGF_T_FAR_FFT);
+      if (P.dim == 3)
+        HIP_TRY(launch_fft(P, P.far, P.M2, P.M1, (long)P.M1 * P.S * nf, P.M1, 1, (long)P.M1 * P.M2));
+      HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)(P.dim == 3 ? P.M2 : 1) * P.S * nf, 1, 0, P.M1));
     }
     P.prepared = true;
   }
@@ -205,8 +217,22 @@ qpgf_status run_evaluate(Plan& P, const double* x, int64_t T, void* out, uint8_t
   if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
   if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
   if (T > (int64_t)1 << 40) return fail(QPGF_E_SIZE, "too many targets");
+  KernelTimer t(P, QPGF_T_GATHER);
   HIP_TRY(launch_gather(P, x, T, out, flags));
   return QPGF_OK;
+}
+
+void drain_timers(Plan& P) {
+  for (auto& e : P.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      P.t_ms[e.id] += ms;
+      P.t_n[e.id] += 1;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  P.pending.clear();
 }
 
 }  // namespace
@@ -363,6 +389,7 @@ void qpgf_plan_destroy(qpgf_plan* plan) {
   if (!plan) return;
   if (plan->P.stream) (void)hipStreamSynchronize(plan->P.stream);
   else (void)hipDeviceSynchronize();
+  drain_timers(plan->P);
   free_plan(plan->P);
   delete plan;
 }
@@ -452,6 +479,26 @@ qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst) {
   const size_t n = (which == 0 ? P.ncell : P.nfar) * P.esize;
   const char* src = static_cast<const char*>(which == 0 ? P.grid : P.far) + (size_t)field * n;
   HIP_TRY(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, P.stream));
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on) {
+  if (!plan) return fail(QPGF_E_ARG, "plan is NULL");
+  drain_timers(plan->P);
+  plan->P.timing = on != 0;
+  for (int i = 0; i < QPGF_T_COUNT; ++i) {
+    plan->P.t_ms[i] = 0.0;
+    plan->P.t_n[i] = 0;
+  }
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches) {
+  if (!plan || !total_ms || !launches) return fail(QPGF_E_ARG, "plan, total_ms and launches must be non-NULL");
+  if (id < 0 || id >= QPGF_T_COUNT) return fail(QPGF_E_ARG, "timer id out of range");
+  drain_timers(plan->P);
+  *total_ms = plan->P.t_ms[id];
+  *launches = plan->P.t_n[id];
   return QPGF_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/qpgf.h"
 
@@ -121,6 +122,32 @@ struct Plan {
   double hd = 0.05;
   double last_k = 0, last_a1 = 0, last_a2 = 0;
   bool prepared = false;
+
+  // per-kernel timing (qpgf_plan_enable_timing)
+  struct Pending { int id; hipEvent_t a, b; };
+  bool timing = false;
+  std::vector<Pending> pending;
+  double t_ms[QPGF_T_COUNT] = {};
+  int64_t t_n[QPGF_T_COUNT] = {};
+};
+
+// Brackets one launch with events on the plan's stream when timing is on.
+struct KernelTimer {
+  Plan& P;
+  int id;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(Plan& p, int i) : P(p), id(i) {
+    if (P.timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, P.stream);
+    else
+      a = b = nullptr;
+  }
+  ~KernelTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, P.stream);
+      P.pending.push_back({id, a, b});
+    }
+  }
 };
 
 // kernel launchers (fill.hip, fft.hip, gather.hip)

@@ -43,7 +43,9 @@ class PlanInfo(ctypes.Structure):
 
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
-           "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_last_error", "qpgf_version"]
+           "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
+           "qpgf_last_error", "qpgf_version"]
+TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather"]
 
 _lib = None
 
@@ -72,11 +74,14 @@ def lib():
     L.qpgf_gd3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
     L.qpgf_maxwell3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
     L.qpgf_copy_field.argtypes = [P, ctypes.c_int, ctypes.c_int, VP]
+    L.qpgf_plan_enable_timing.argtypes = [P, ctypes.c_int]
+    L.qpgf_plan_get_timing.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
     L.qpgf_last_error.restype = ctypes.c_char_p
     L.qpgf_version.restype = ctypes.c_char_p
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
                  "qpgf_prepare_stage", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
-                 "qpgf_copy_field"):
+                 "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -163,6 +168,18 @@ class Plan:
         else:
             _check(lib().qpgf_maxwell3d(self._h, k, a1, a2, px, T, po, pf))
         return out
+
+    def enable_timing(self, on=True):
+        _check(lib().qpgf_plan_enable_timing(self._h, int(on)))
+
+    def timing(self):
+        """{kernel class: (total ms, launches)} since timing was enabled."""
+        res = {}
+        for i, name in enumerate(TIMERS):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(lib().qpgf_plan_get_timing(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
+            res[name] = (ms.value, n.value)
+        return res
 
     def field(self, which=0, field=0):
         """Copy of a near-grid (which=0) or far-slab (which=1) field as a flat complex tensor."""
