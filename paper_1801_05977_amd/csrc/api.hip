@@ -81,7 +81,8 @@ qpgf_status upload(V** dst, const std::vector<V>& src) {
 }
 
 void free_plan(Plan& P) {
-  void* ptrs[] = {P.grid, P.far, P.xq, P.wxq, P.cs, P.rq, P.wrq, P.y1q, P.y2q, P.tw, P.twf, P.F1, P.F2, P.htab};
+  void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
+                  P.twf,  P.F1,  P.F2,   P.htab, P.bin_keyrank, P.bin_xs, P.bin_perm, P.bin_hist, P.bin_offs, P.bin_cnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -216,8 +217,7 @@ qpgf_status run_evaluate(Plan& P, const double* x, int64_t T, void* out, uint8_t
   if (T == 0) return QPGF_OK;
   if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
   if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
-  if (T > (int64_t)1 << 40) return fail(QPGF_E_SIZE, "too many targets");
-  KernelTimer t(P, QPGF_T_GATHER);
+  if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
   HIP_TRY(launch_gather(P, x, T, out, flags));
   return QPGF_OK;
 }

@@ -53,7 +53,8 @@ __device__ __forceinline__ void pencil_weights(const FillArgs& A, int j1p0, int 
       rho = sqrt(e1 * e1 + e2 * e2);
     }
     double2 b = beta_of(A.k, rho);
-    sa[pp * A.Q + q] = cscale(cexpi(cscale(b, xq[q])), wxq[q]);
+    // [q][pencil]: the 16 pencils of a wave read 16 consecutive entries
+    sa[q * TP + pp] = cscale(cexpi(cscale(b, xq[q])), wxq[q]);
   }
 }
 
@@ -64,7 +65,7 @@ __device__ __forceinline__ double2 xprime_term(const double2* __restrict__ ap, c
                                                double sgn, double J, double2 b) {
   double2 C = mk(0.0, 0.0), S = mk(0.0, 0.0);
   for (int q = 0; q < Q; ++q) {
-    double2 a = ap[q], t = csr[q];
+    double2 a = ap[q * TP], t = csr[q];
     C.x = fma(a.x, t.x, C.x);
     C.y = fma(a.y, t.x, C.y);
     S.x = fma(a.x, t.y, S.x);
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   const double rp2 = xi1 * xi1 + xi2 * xi2;
   const double2 b = beta_of(A.k, sqrt(rp2));
   const bool use_I = b.y * A.c < 41.5;   // else |I| < e^{-c Im beta} < 1e-18
-  const double2* ap = sa + ip * A.Q;
+  const double2* ap = sa + ip;
   const double k2 = A.k * A.k;
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __rest
   const double a = A.a1 + centered(j1p, A.M1);
   const double2 b = beta_of(A.k, fabs(a));
   const bool use_I = b.y * A.c < 41.5;
-  const double2* ap = sa + ip * A.Q;
+  const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);

@@ -4,6 +4,8 @@
 // (16 / 64 nodes, step 2d), add back the removed singular part in FP64 and apply
 // the quasi-periodic phase (steps 2e-2f; Algorithm 4.1 steps 2e-2i).  Far
 // targets interpolate the far-slab grid of the eigenfunction series.
+#include <algorithm>
+
 #include "qpgf_internal.h"
 
 namespace qpgf {
@@ -16,6 +18,7 @@ struct GArgs {
   double k, a1, a2, c, c_tilde, eps, rmin;
   int M1, M2, M3;          // 2D: M2 = transverse size, M3 = 1
   double h1, h2, h3;       // 2D: h2 = transverse spacing
+  double ih1, ih2, ih3;    // reciprocals of the spacings
   double hf;               // far-slab spacing
   int S;                   // far-slab slices
   long fs, ffs;            // field strides (near, far)
@@ -30,9 +33,10 @@ __device__ __forceinline__ void lag4(double f, double w[4]) {
   w[3] = fp1 * f * fm1 * (1.0 / 6.0);
 }
 
-// x = 2 pi n + t, t in [-pi, pi)
+// x = 2 pi n + t, t in [-pi, pi) (up to rounding at the cell edge, where the
+// grid is periodic and the singular part vanishes, so either cell gives G)
 __device__ __forceinline__ double reduce_cell(double x, double& n) {
-  n = floor((x + kPi) / (2.0 * kPi));
+  n = floor((x + kPi) * (0.5 / kPi));
   return x - 2.0 * kPi * n;
 }
 
@@ -56,158 +60,280 @@ template <> __device__ __forceinline__ void store_out<float>(float2* p, long i, 
   p[i] = make_float2((float)v.x, (float)v.y);
 }
 
-// sum over the 4 x 4 (x 4) stencil of field f: weights w1 (x1), w2 (x2), w3 (slices)
+__device__ __forceinline__ double2 nan2() { return mk(__builtin_nan(""), __builtin_nan("")); }
+
+// Stencil sum over global memory: field f, base nodes p1, p2 (periodic) and p3
+// (near: periodic slice index; far: far-slab slice s0 >= 1).
 template <typename T, int NF>
-__device__ __forceinline__ void stencil3(const cplx<T>* __restrict__ g, long fs, const int i1[4], const int i2[4],
-                                         const long i3[4], const double w1[4], const double w2[4], const double w3[4],
-                                         int M1, int M2, double2 out[NF]) {
-  Acc<T> acc[NF];
+struct GlobalFetch {
+  const cplx<T>* grid;
+  const cplx<T>* far;
+  long fs, ffs;
+  int M1, M2, M3;
+  __device__ void operator()(bool near, int p1, int p2, int p3, const double w1[4], const double w2[4],
+                             const double w3[4], double2 L[NF]) const {
+    const cplx<T>* g = near ? grid : far;
+    const long st = near ? fs : ffs;
+    Acc<T> acc[NF];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4; ++c) {
+      const long i3 = near ? (long)((p3 - 1 + c) & (M3 - 1)) : (long)(p3 - 1 + c);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long row = (i3[c] * M2 + i2[b]) * (long)M1;
-      const T wcb = (T)(w3[c] * w2[b]);
+      for (int b = 0; b < 4; ++b) {
+        const long row = (i3 * M2 + ((p2 - 1 + b) & (M2 - 1))) * (long)M1;
+        const T wcb = (T)(w3[c] * w2[b]);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const T w = wcb * (T)w1[a];
+        for (int a = 0; a < 4; ++a) {
+          const T w = wcb * (T)w1[a];
+          const long o = row + ((p1 - 1 + a) & (M1 - 1));
 #pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f].add(w, g[f * fs + row + i1[a]]);
+          for (int f = 0; f < NF; ++f) acc[f].add(w, g[f * st + o]);
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+  }
+};
+
+// One target of Algorithm 3.1 / 4.1 step 2 (G_d, or the six Maxwell entries).
+// `fetch` performs the 64-point stencil sum of the near grid or the far slab.
+template <typename T, int NF, typename Fetch>
+__device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double x2, double x3, const Fetch& fetch,
+                                              double2* res, uint8_t& fl) {
+  constexpr int NO = (NF == 1) ? 1 : 6;
+  fl = 0;
+  if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) {
+    fl = 8;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return;
+  }
+  double n1, n2;
+  const double t1 = reduce_cell(x1, n1), t2 = reduce_cell(x2, n2);
+  double w1[4], w2[4], w3[4];
+  const double u1 = t1 * A.ih1, q1 = floor(u1);
+  lag4(u1 - q1, w1);
+  const double u2 = t2 * A.ih2, q2 = floor(u2);
+  lag4(u2 - q2, w2);
+  double2 L[NF];
+  const bool is_near = fabs(x3) <= A.c;
+  if (is_near) {
+    const double u = x3 * A.ih3, q = floor(u);
+    lag4(u - q, w3);
+    fetch(true, (int)q1, (int)q2, (int)q, w1, w2, w3, L);
+  } else {
+    fl |= 2;
+    const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
+    double s0 = floor(v);
+    if (s0 > A.S - 3) {
+      fl |= 4;
+#pragma unroll
+      for (int o = 0; o < NO; ++o) res[o] = nan2();
+      return;
+    }
+    s0 = fmax(s0, 1.0);
+    lag4(v - s0, w3);
+    fetch(false, (int)q1, (int)q2, (int)s0, w1, w2, w3, L);
+  }
+  double ps, pc;
+  sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
+  const double2 phase = mk(pc, ps);
+  double2 G[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
+  if (!is_near && NF == 7) {
+    // d/dx3 of e^{i beta |x3|} carries sgn(x3): components 13 and 23
+    if (x3 < 0) {
+      G[5] = cscale(G[5], -1.0);
+      G[6] = cscale(G[6], -1.0);
+    }
+  }
+  if (is_near) {
+    const double r = sqrt(t1 * t1 + t2 * t2 + x3 * x3);
+    if (r <= A.rmin || r == 0.0) {
+      fl |= 1;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) G[f] = nan2();
+    } else if (r < 2.0 * A.eps) {
+      // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
+      double sn, cn;
+      sincos(A.k * r, &sn, &cn);
+      const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
+      double ls, lc;
+      sincospi(2.0 * (A.a1 * n1 + A.a2 * n2), &ls, &lc);
+      const double2 lat = mk(lc, ls);
+      const double Y = cut_Y(r, A.eps);
+      G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
+      if (NF == 7) {
+        // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
+        const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
+        const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
+        const double2 g1 = cmul(g, ikr);
+        const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
+        const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
+        const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
+        const double t[3] = {t1, t2, x3};
+        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const double tp = t[P[f]], tq = t[Qp[f]];
+          const double a = tp * tq / (r * r);
+          const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
+          G[f + 1] = cadd(G[f + 1], cmul(lat, cadd(cscale(d2, a), cscale(d1, bcoef))));
+        }
       }
     }
   }
+  if (NF == 1) {
+    res[0] = G[0];
+  } else {
+    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1)
+    const double ik2 = 1.0 / (A.k * A.k);
 #pragma unroll
-  for (int f = 0; f < NF; ++f) out[f] = acc[f].get();
+    for (int f = 0; f < 6; ++f) {
+      double2 v = cscale(G[f + 1], ik2);
+      if (f < 3) v = cadd(v, G[0]);
+      res[f] = v;
+    }
+  }
 }
 
-__device__ __forceinline__ double2 nan2() { return mk(__builtin_nan(""), __builtin_nan("")); }
+// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD runs a
+// contiguous range of logical blocks (neighbouring grid tiles) and its L2 holds
+// one region of the grid.
+__device__ __forceinline__ long xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x, x = b & 7u, per = nb >> 3, rem = nb & 7u;
+  return (long)x * per + min(x, rem) + (b >> 3);
+}
 
-// 3D: G_d (NF = 1) or the Maxwell tensor (NF = 7, output [T][6]).
+// 3D, unsorted targets: one thread per target, stencil read from global memory.
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_gather3d(GArgs A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
                                                   long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T_) return;
-  const double x1 = x[3 * i], x2 = x[3 * i + 1], x3 = x[3 * i + 2];
   constexpr int NO = (NF == 1) ? 1 : 6;
-  uint8_t fl = 0;
+  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
   double2 res[NO];
-  if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) {
-    fl = 8;
-#pragma unroll
-    for (int o = 0; o < NO; ++o) res[o] = nan2();
-  } else {
-    double n1, n2;
-    const double t1 = reduce_cell(x1, n1), t2 = reduce_cell(x2, n2);
-    double w1[4], w2[4], w3[4];
-    int i1[4], i2[4];
-    long i3[4];
-    {
-      const double u = t1 / A.h1, p = floor(u);
-      lag4(u - p, w1);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) i1[a] = ((int)p - 1 + a) & (A.M1 - 1);
-    }
-    {
-      const double u = t2 / A.h2, p = floor(u);
-      lag4(u - p, w2);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) i2[a] = ((int)p - 1 + a) & (A.M2 - 1);
-    }
-    double ps, pc;
-    sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
-    const double2 phase = mk(pc, ps);
-    double2 L[NF];
-    const bool is_near = fabs(x3) <= A.c;
-    bool bad = false;
-    if (is_near) {
-      const double u = x3 / A.h3, p = floor(u);
-      lag4(u - p, w3);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) i3[a] = ((int)p - 1 + a) & (A.M3 - 1);
-      stencil3<T, NF>(grid, A.fs, i1, i2, i3, w1, w2, w3, A.M1, A.M2, L);
-    } else {
-      fl |= 2;
-      const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
-      double s0 = floor(v);
-      if (s0 > A.S - 3) {
-        bad = true;
-        fl |= 4;
-      } else {
-        s0 = fmax(s0, 1.0);
-        lag4(v - s0, w3);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) i3[a] = (long)s0 - 1 + a;
-        stencil3<T, NF>(far, A.ffs, i1, i2, i3, w1, w2, w3, A.M1, A.M2, L);
-      }
-    }
-    if (bad) {
-#pragma unroll
-      for (int o = 0; o < NO; ++o) res[o] = nan2();
-    } else {
-      double2 G[NF];
-#pragma unroll
-      for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
-      if (!is_near && NF == 7) {
-        // d/dx3 of e^{i beta |x3|} carries sgn(x3): components 13 and 23
-        if (x3 < 0) { G[5] = cscale(G[5], -1.0); G[6] = cscale(G[6], -1.0); }
-      }
-      if (is_near) {
-        const double r = sqrt(t1 * t1 + t2 * t2 + x3 * x3);
-        if (r <= A.rmin || r == 0.0) {
-          fl |= 1;
-#pragma unroll
-          for (int f = 0; f < NF; ++f) G[f] = nan2();
-        } else if (r < 2.0 * A.eps) {
-          // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
-          double sn, cn;
-          sincos(A.k * r, &sn, &cn);
-          const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
-          const double2 lat = [&] {
-            double ls, lc;
-            sincospi(2.0 * (A.a1 * n1 + A.a2 * n2), &ls, &lc);
-            return mk(lc, ls);
-          }();
-          const double Y = cut_Y(r, A.eps);
-          G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
-          if (NF == 7) {
-            // psi' and psi'' (radial), then d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
-            const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
-            const double2 ikr = mk(-1.0 / r, A.k);                 // ik - 1/r
-            const double2 g1 = cmul(g, ikr);
-            const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
-            const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
-            const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
-            const double t[3] = {t1, t2, x3};
-            const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-              const double tp = t[P[f]], tq = t[Qp[f]];
-              const double a = tp * tq / (r * r);
-              const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
-              G[f + 1] = cadd(G[f + 1], cmul(lat, cadd(cscale(d2, a), cscale(d1, bcoef))));
-            }
-          }
-        }
-      }
-      if (NF == 1) {
-        res[0] = G[0];
-      } else {
-        // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1)
-        const double ik2 = 1.0 / (A.k * A.k);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-          double2 v = cscale(G[f + 1], ik2);
-          if (f < 3) v = cadd(v, G[0]);
-          res[f] = v;
-        }
-      }
-    }
-  }
+  uint8_t fl;
+  eval3d_target<T, NF>(A, x[3 * i], x[3 * i + 1], x[3 * i + 2], gf, res, fl);
 #pragma unroll
   for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
   if (flags) flags[i] = fl;
+}
+
+// ---------------------------------------------------------------------------
+// Tiled gather over targets sorted by grid tile.  Tile key (see tile_key):
+// near  (b3 nt2 + b2) nt1 + b1,  far  nnear + (b3 nt2 + b2) nt1 + b1,  last = invalid.
+// A tile covers 2^tb nodes per axis; the stencils of its targets lie in the
+// (2^tb + 3)^3 footprint starting one node before the tile.
+// ---------------------------------------------------------------------------
+struct TileArgs {
+  int tb1, tb2, tb3;       // tile edge = 1 << tb
+  int nt1, nt2, nt3n;      // tiles along x1, x2, near x3
+  int nnear, nkeys;
+};
+
+template <typename T, int NF>
+struct LdsFetch {
+  const cplx<T>* lds;      // [NF][F3][F2][F1]
+  int o1, o2, o3, F1, F2, F3;
+  bool near_tile;
+  int M1, M2;
+  GlobalFetch<T, NF> gf;
+  __device__ void operator()(bool near, int p1, int p2, int p3, const double w1[4], const double w2[4],
+                             const double w3[4], double2 L[NF]) const {
+    const int l1 = (p1 - 1 - o1) & (M1 - 1), l2 = (p2 - 1 - o2) & (M2 - 1);
+    const int l3 = near ? ((p3 - 1 - o3) & (gf.M3 - 1)) : (p3 - 1 - o3);
+    if (near != near_tile || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4) {
+      gf(near, p1, p2, p3, w1, w2, w3, L);   // outside the staged footprint
+      return;
+    }
+    const int fsz = F1 * F2 * F3;
+    Acc<T> acc[NF];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = ((l3 + c) * F2 + (l2 + b)) * F1 + l1;
+        const T wcb = (T)(w3[c] * w2[b]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const T w = wcb * (T)w1[a];
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f].add(w, lds[f * fsz + row + a]);
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+  }
+};
+
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_gather3d_tiled(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+                                                        const cplx<T>* __restrict__ far,
+                                                        const double* __restrict__ xs,
+                                                        const uint32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ hist,
+                                                        const uint32_t* __restrict__ offs,
+                                                        cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int NO = (NF == 1) ? 1 : 6;
+  const int key = (int)xcd_block();
+  const uint32_t cnt = hist[key];
+  if (cnt == 0) return;
+  const long start = offs[key];
+  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+  LdsFetch<T, NF> lf;
+  lf.lds = lds;
+  lf.F1 = (1 << B.tb1) + 3;
+  lf.F2 = (1 << B.tb2) + 3;
+  lf.F3 = (1 << B.tb3) + 3;
+  lf.M1 = A.M1;
+  lf.M2 = A.M2;
+  lf.gf = gf;
+  const bool valid = key < B.nkeys - 1;
+  if (valid) {
+    const bool near = key < B.nnear;
+    const int kk = near ? key : key - B.nnear;
+    const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
+    lf.near_tile = near;
+    lf.o1 = (b1 << B.tb1) - 1;
+    lf.o2 = (b2 << B.tb2) - 1;
+    lf.o3 = (b3 << B.tb3) - 1;
+    const int fsz = lf.F1 * lf.F2 * lf.F3;
+    for (int idx = threadIdx.x; idx < NF * fsz; idx += blockDim.x) {
+      const int f = idx / fsz, r = idx - f * fsz;
+      const int z = r / (lf.F1 * lf.F2), y = (r / lf.F1) % lf.F2, xx = r % lf.F1;
+      const int g1 = (lf.o1 + xx) & (A.M1 - 1), g2 = (lf.o2 + y) & (A.M2 - 1);
+      cplx<T> v;
+      if (near) {
+        const int g3 = (lf.o3 + z) & (A.M3 - 1);
+        v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+      } else {
+        const int g3 = min(max(lf.o3 + z, 0), A.S - 1);
+        v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+      }
+      lds[idx] = v;
+    }
+  }
+  __syncthreads();
+  for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
+    const long i = perm[j];
+    double2 res[NO];
+    uint8_t fl;
+    if (valid)
+      eval3d_target<T, NF>(A, xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], lf, res, fl);
+    else
+      eval3d_target<T, NF>(A, xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], gf, res, fl);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
+    if (flags) flags[i] = fl;
+  }
 }
 
 // 2D: G (Algorithm 2.1).
@@ -288,6 +414,152 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
   if (flags) flags[i] = fl;
 }
 
+// ---------------------------------------------------------------------------
+// Target binning (counting sort by grid tile): key pass with an atomic rank
+// inside each tile, one-block exclusive scan, scatter into tile order.
+// ---------------------------------------------------------------------------
+struct BinArgs {
+  double c, ih1, ih2, ih3, hf;
+  int M1, M2, M3, S;
+  TileArgs t;
+};
+
+__device__ __forceinline__ uint32_t tile_key(const BinArgs& B, double x1, double x2, double x3) {
+  if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) return B.t.nkeys - 1;
+  double n;
+  const double t1 = reduce_cell(x1, n), t2 = reduce_cell(x2, n);
+  const int b1 = (((int)floor(t1 * B.ih1)) & (B.M1 - 1)) >> B.t.tb1;
+  const int b2 = (((int)floor(t2 * B.ih2)) & (B.M2 - 1)) >> B.t.tb2;
+  if (fabs(x3) <= B.c) {
+    const int b3 = (((int)floor(x3 * B.ih3)) & (B.M3 - 1)) >> B.t.tb3;
+    return (uint32_t)((b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
+  }
+  const double s0 = floor((fabs(x3) - (B.c - B.hf)) / B.hf);
+  if (s0 > B.S - 3) return B.t.nkeys - 1;
+  const int b3 = ((int)fmax(s0, 1.0)) >> B.t.tb3;
+  return (uint32_t)(B.t.nnear + (b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_bin_key(BinArgs B, const double* __restrict__ x, long T_,
+                                                 uint32_t* __restrict__ hist, uint2* __restrict__ keyrank) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T_) return;
+  const uint32_t key = tile_key(B, x[3 * i], x[3 * i + 1], x[3 * i + 2]);
+  const uint32_t r = atomicAdd(&hist[key], 1u);
+  keyrank[i] = make_uint2(key, r);
+}
+
+// exclusive scan of hist[0..n) into offs[0..n) with one block of 1024 threads
+__global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
+                                                   int n) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x, per = (n + 1023) / 1024;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += hist[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    uint32_t v = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    offs[i] = run;
+    run += hist[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ x, const uint2* __restrict__ keyrank,
+                                                     const uint32_t* __restrict__ offs, long T_,
+                                                     double* __restrict__ xs, uint32_t* __restrict__ perm) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T_) return;
+  const uint2 kr = keyrank[i];
+  const long pos = (long)offs[kr.x] + kr.y;
+  xs[3 * pos] = x[3 * i];
+  xs[3 * pos + 1] = x[3 * i + 1];
+  xs[3 * pos + 2] = x[3 * i + 2];
+  perm[pos] = (uint32_t)i;
+}
+
+// Binning without per-target global atomics (used when the key count fits an
+// LDS histogram): each of kBinBlocks blocks takes a contiguous chunk of targets,
+//  (1) counts its tile keys in LDS and writes the counts to cnt[block][key],
+//  (2) k_bin_colscan turns cnt into per-(block, key) exclusive prefixes over the
+//      blocks and per-key totals,
+//  (3) k_bin_scan gives per-key offsets, and
+//  (4) each block re-derives its keys and scatters its targets to
+//      offs[key] + cnt[block][key] + (LDS-atomic rank within the block).
+constexpr int kBinBlocks = 256;
+constexpr int kBinLdsKeys = 16384;
+
+__global__ __launch_bounds__(1024) void k_bin_count(BinArgs B, const double* __restrict__ x, long T_, long chunk,
+                                                    uint32_t* __restrict__ cnt) {
+  extern __shared__ uint32_t h[];
+  const int nk = B.t.nkeys;
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
+  const long lo = (long)blockIdx.x * chunk, hi = min(T_, lo + chunk);
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x)
+    atomicAdd(&h[tile_key(B, x[3 * i], x[3 * i + 1], x[3 * i + 2])], 1u);
+  __syncthreads();
+  uint32_t* row = cnt + (long)blockIdx.x * nk;
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) row[k] = h[k];
+}
+
+// 64 keys per block; 4 groups of 64 threads each scan a quarter of the blocks.
+__global__ __launch_bounds__(256) void k_bin_colscan(uint32_t* __restrict__ cnt, int nk, int nblk,
+                                                     uint32_t* __restrict__ total) {
+  __shared__ uint32_t part[4][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
+  const int per = (nblk + 3) / 4, b0 = grp * per, b1 = min(nblk, b0 + per);
+  uint32_t s = 0;
+  if (k < nk)
+    for (int b = b0; b < b1; ++b) s += cnt[(long)b * nk + k];
+  part[grp][lane] = s;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int g = 0; g < grp; ++g) run += part[g][lane];
+  if (k < nk) {
+    for (int b = b0; b < b1; ++b) {
+      const long o = (long)b * nk + k;
+      const uint32_t c = cnt[o];
+      cnt[o] = run;
+      run += c;
+    }
+    if (grp == 3) total[k] = run;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __restrict__ x, long T_, long chunk,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ offs, double* __restrict__ xs,
+                                                    uint32_t* __restrict__ perm) {
+  extern __shared__ uint32_t cur[];
+  const int nk = B.t.nkeys;
+  const uint32_t* row = cnt + (long)blockIdx.x * nk;
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) cur[k] = offs[k] + row[k];
+  __syncthreads();
+  const long lo = (long)blockIdx.x * chunk, hi = min(T_, lo + chunk);
+  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double a = x[3 * i], b = x[3 * i + 1], c = x[3 * i + 2];
+    const long pos = atomicAdd(&cur[tile_key(B, a, b, c)], 1u);
+    xs[3 * pos] = a;
+    xs[3 * pos + 1] = b;
+    xs[3 * pos + 2] = c;
+    perm[pos] = (uint32_t)i;
+  }
+}
+
 template <typename T>
 hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {
   GArgs A;
@@ -309,6 +581,9 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     A.h2 = kPi / (P.M2 / 2);
     A.h3 = P.p.c_tilde / (P.M3 / 2);
   }
+  A.ih1 = 1.0 / A.h1;
+  A.ih2 = 1.0 / A.h2;
+  A.ih3 = A.h3 > 0.0 ? 1.0 / A.h3 : 0.0;
   A.hf = P.p.far_h;
   A.S = P.S;
   A.fs = (long)P.ncell;
@@ -317,16 +592,110 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   const auto* f = static_cast<const cplx<T>*>(P.far);
   auto* o = static_cast<cplx<T>*>(out);
   const dim3 grid((unsigned)((T_ + 255) / 256));
-  if (P.dim == 2)
+  if (P.dim == 2) {
+    KernelTimer t(P, QPGF_T_GATHER);
     hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
-  else if (P.nf == 7)
-    hipLaunchKernelGGL((k_gather3d<T, 7>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    return hipGetLastError();
+  }
+  if (P.bin_min_targets < 0 || T_ < P.bin_min_targets) {
+    KernelTimer t(P, QPGF_T_GATHER);
+    if (P.nf == 7)
+      hipLaunchKernelGGL((k_gather3d<T, 7>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    else
+      hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    return hipGetLastError();
+  }
+  BinArgs B;
+  B.c = A.c;
+  B.ih1 = A.ih1;
+  B.ih2 = A.ih2;
+  B.ih3 = A.ih3;
+  B.hf = A.hf;
+  B.M1 = P.M1;
+  B.M2 = P.M2;
+  B.M3 = P.M3;
+  B.S = P.S;
+  // tile edges: 8 nodes per axis, fewer where the staged footprint of the
+  // Maxwell fields would not fit in 64 KiB of LDS
+  TileArgs& Tl = B.t;
+  Tl.tb1 = 3;
+  Tl.tb2 = (P.nf == 7 && sizeof(T) == 8) ? 2 : 3;
+  Tl.tb3 = (P.nf == 7) ? 2 : 3;
+  Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
+  Tl.nt2 = std::max(1, P.M2 >> Tl.tb2);
+  Tl.nt3n = std::max(1, P.M3 >> Tl.tb3);
+  Tl.nnear = Tl.nt1 * Tl.nt2 * Tl.nt3n;
+  Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
+  hipError_t e = ensure_bin_scratch(P, T_, Tl.nkeys);
+  if (e != hipSuccess) return e;
+  {
+    KernelTimer t(P, QPGF_T_BIN);
+    if (Tl.nkeys <= kBinLdsKeys) {
+      const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
+      const size_t lds = (size_t)Tl.nkeys * sizeof(uint32_t);
+      hipLaunchKernelGGL(k_bin_count, dim3(kBinBlocks), dim3(1024), lds, P.stream, B, x, (long)T_, chunk, P.bin_cnt);
+      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(256), 0, P.stream, P.bin_cnt, Tl.nkeys,
+                         kBinBlocks, P.bin_hist);
+      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
+      hipLaunchKernelGGL(k_bin_place, dim3(kBinBlocks), dim3(1024), lds, P.stream, B, x, (long)T_, chunk, P.bin_cnt,
+                         P.bin_offs, P.bin_xs, P.bin_perm);
+    } else {
+      // large key spaces: one global atomic rank per target
+      hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, P.stream, P.bin_hist,
+                         (long)Tl.nkeys);
+      hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, P.stream, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
+      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
+      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_,
+                         P.bin_xs, P.bin_perm);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t fsz = (size_t)((1 << Tl.tb1) + 3) * ((1 << Tl.tb2) + 3) * ((1 << Tl.tb3) + 3);
+  const size_t shm = fsz * P.nf * sizeof(cplx<T>);
+  KernelTimer t(P, QPGF_T_GATHER);
+  if (P.nf == 7)
+    hipLaunchKernelGGL((k_gather3d_tiled<T, 7>), dim3(Tl.nkeys), dim3(256), shm, P.stream, A, Tl, g, f, P.bin_xs,
+                       P.bin_perm, P.bin_hist, P.bin_offs, o, flags);
   else
-    hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    hipLaunchKernelGGL((k_gather3d_tiled<T, 1>), dim3(Tl.nkeys), dim3(256), shm, P.stream, A, Tl, g, f, P.bin_xs,
+                       P.bin_perm, P.bin_hist, P.bin_offs, o, flags);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
+  if (T_ > P.bin_cap) {
+    for (void* q : {(void*)P.bin_keyrank, (void*)P.bin_xs, (void*)P.bin_perm})
+      if (q) (void)hipFree(q);
+    P.bin_keyrank = nullptr;
+    P.bin_xs = nullptr;
+    P.bin_perm = nullptr;
+    P.bin_cap = 0;
+    hipError_t e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_keyrank), (size_t)T_ * sizeof(uint2))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_xs), (size_t)T_ * 3 * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_perm), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
+    P.bin_cap = T_;
+  }
+  if (nkeys > P.bin_keycap) {
+    for (void* q : {(void*)P.bin_hist, (void*)P.bin_offs, (void*)P.bin_cnt})
+      if (q) (void)hipFree(q);
+    P.bin_hist = nullptr;
+    P.bin_offs = nullptr;
+    P.bin_cnt = nullptr;
+    P.bin_keycap = 0;
+    hipError_t e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_hist), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_offs), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_cnt), (size_t)nkeys * kBinBlocks * sizeof(uint32_t))) !=
+        hipSuccess)
+      return e;
+    P.bin_keycap = nkeys;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_gather(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {
   if (T_ <= 0) return hipSuccess;

@@ -123,6 +123,17 @@ struct Plan {
   double last_k = 0, last_a1 = 0, last_a2 = 0;
   bool prepared = false;
 
+  // target binning scratch (3D), grown on demand
+  int64_t bin_min_targets = 1 << 16;   // bin when T >= this; < 0 never
+  int64_t bin_cap = 0;
+  int bin_keycap = 0;
+  uint2* bin_keyrank = nullptr;
+  double* bin_xs = nullptr;
+  uint32_t* bin_perm = nullptr;
+  uint32_t* bin_hist = nullptr;
+  uint32_t* bin_offs = nullptr;
+  uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
+
   // per-kernel timing (qpgf_plan_enable_timing)
   struct Pending { int id; hipEvent_t a, b; };
   bool timing = false;
@@ -158,5 +169,6 @@ hipError_t launch_far(Plan& P, double k, double a1, double a2);
 hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
                       long s_out);
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
+hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
 
 }  // namespace qpgf

@@ -45,7 +45,7 @@ EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
            "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
            "qpgf_last_error", "qpgf_version"]
-TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather"]
+TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin"]
 
 _lib = None
 

@@ -129,6 +129,35 @@ def test_maxwell3d_small(prec):
         assert parity(g[:, comp], o[:, comp]) <= TOL[prec], comp
 
 
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("kind", [qpgf.KIND_GD3D, qpgf.KIND_MAXWELL3D])
+def test_binned_gather_large_target_count(prec, kind):
+    """T >= 65536 takes the binned path (targets sorted by grid tile); includes
+    targets beyond the far slab and on the lattice, whose flags must follow them."""
+    M1, M2, M3, T = 64, 32, 32, 120_001
+    k, a1, a2 = 5.3, 0.1, 0.4
+    x = workloads.targets(T, 3, seed=9, zmax=1.2)
+    x[17] = [0.0, 2 * math.pi, 0.0]
+    x[T - 1] = [4 * math.pi, 0.0, 0.0]
+    P = qpgf.Plan(kind, prec, M1, M2, M3)
+    flags = torch.empty(T, dtype=torch.uint8, device="cuda")
+    g = P(k, a1, a2, dev(x), flags=flags).cpu().numpy()
+    f = flags.cpu().numpy()
+    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices,
+                           maxwell=(kind == qpgf.KIND_MAXWELL3D))
+    o = method.evaluate_3d(st, x)
+    ok = np.isfinite(o) if o.ndim == 1 else np.isfinite(o).all(axis=1)
+    np.testing.assert_array_equal(ok, (f & 5) == 0)
+    assert f[17] == 1 and f[T - 1] == 1
+    assert np.all(np.isnan(g[~ok]))
+    gg, oo = g[ok], o[ok]
+    if gg.ndim == 1:
+        assert parity(gg, oo) <= TOL[prec]
+    else:
+        for comp in range(6):
+            assert parity(gg[:, comp], oo[:, comp]) <= TOL[prec], comp
+
+
 def test_prepare_then_evaluate_in_chunks_matches_single_call():
     M1, M2, M3 = 64, 64, 32
     k, a1, a2 = 3.7, 0.2, 0.35
