@@ -82,7 +82,7 @@ qpgf_status upload(V** dst, const std::vector<V>& src) {
 
 void free_plan(Plan& P) {
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
-                  P.twf,  P.F1,  P.F2,   P.htab, P.bin_keyrank, P.bin_xs, P.bin_perm, P.bin_hist, P.bin_offs, P.bin_cnt};
+                  P.twf,  P.F1,  P.F2,   P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -230,106 +230,165 @@ __global__ __launch_bounds__(256) void k_gather3d(GArgs A, const cplx<T>* __rest
 // A tile covers 2^tb nodes per axis; the stencils of its targets lie in the
 // (2^tb + 3)^3 footprint starting one node before the tile.
 // ---------------------------------------------------------------------------
+// A target in tile order: coordinates and caller index in one aligned 32-byte record.
+struct alignas(32) TRec {
+  double x, y, z;
+  uint32_t i, pad;
+};
+
 struct TileArgs {
   int tb1, tb2, tb3;       // tile edge = 1 << tb
   int nt1, nt2, nt3n;      // tiles along x1, x2, near x3
   int nnear, nkeys;
 };
 
-template <typename T, int NF>
+// Stencil sum from the LDS-staged footprint of one tile (compile-time footprint
+// F1 x F2 x F3 so every LDS address is a base plus an immediate offset).  A
+// target whose stencil does not lie in the footprint (a rounding disagreement
+// with the key pass) is not evaluated here but appended to the overflow list.
+template <typename T, int NF, int F1, int F2, int F3>
 struct LdsFetch {
   const cplx<T>* lds;      // [NF][F3][F2][F1]
-  int o1, o2, o3, F1, F2, F3;
+  int o1, o2, o3;
   bool near_tile;
-  int M1, M2;
-  GlobalFetch<T, NF> gf;
+  int M1, M2, M3;
+  mutable bool miss;
   __device__ void operator()(bool near, int p1, int p2, int p3, const double w1[4], const double w2[4],
                              const double w3[4], double2 L[NF]) const {
     const int l1 = (p1 - 1 - o1) & (M1 - 1), l2 = (p2 - 1 - o2) & (M2 - 1);
-    const int l3 = near ? ((p3 - 1 - o3) & (gf.M3 - 1)) : (p3 - 1 - o3);
+    const int l3 = near ? ((p3 - 1 - o3) & (M3 - 1)) : (p3 - 1 - o3);
     if (near != near_tile || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4) {
-      gf(near, p1, p2, p3, w1, w2, w3, L);   // outside the staged footprint
+      miss = true;
       return;
     }
-    const int fsz = F1 * F2 * F3;
-    Acc<T> acc[NF];
+    constexpr int FSZ = F1 * F2 * F3;
+    const cplx<T>* base = lds + (l3 * F2 + l2) * F1 + l1;
+    T a1[4], a2[4], a3[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int row = ((l3 + c) * F2 + (l2 + b)) * F1 + l1;
-        const T wcb = (T)(w3[c] * w2[b]);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const T w = wcb * (T)w1[a];
-#pragma unroll
-          for (int f = 0; f < NF; ++f) acc[f].add(w, lds[f * fsz + row + a]);
-        }
-      }
+    for (int a = 0; a < 4; ++a) {
+      a1[a] = (T)w1[a];
+      a2[a] = (T)w2[a];
+      a3[a] = (T)w3[a];
     }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+    for (int f = 0; f < NF; ++f) {
+      T accx = 0, accy = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T px = 0, py = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const cplx<T>* row = base + f * FSZ + (c * F2 + b) * F1;
+          T rx = 0, ry = 0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const cplx<T> v = row[a];
+            rx += a1[a] * v.x;
+            ry += a1[a] * v.y;
+          }
+          px += a2[b] * rx;
+          py += a2[b] * ry;
+        }
+        accx += a3[c] * px;
+        accy += a3[c] * py;
+      }
+      L[f] = mk((double)accx, (double)accy);
+    }
   }
 };
 
-template <typename T, int NF>
+template <typename T, int NF, int TB1, int TB2, int TB3>
 __global__ __launch_bounds__(256) void k_gather3d_tiled(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
                                                         const cplx<T>* __restrict__ far,
-                                                        const double* __restrict__ xs,
-                                                        const uint32_t* __restrict__ perm,
+                                                        const TRec* __restrict__ rec,
                                                         const uint32_t* __restrict__ hist,
                                                         const uint32_t* __restrict__ offs,
-                                                        cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
-  extern __shared__ char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+                                                        cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
+                                                        uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+  constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
+  __shared__ cplx<T> lds[NF * FSZ];
   constexpr int NO = (NF == 1) ? 1 : 6;
   const int key = (int)xcd_block();
   const uint32_t cnt = hist[key];
   if (cnt == 0) return;
   const long start = offs[key];
-  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
-  LdsFetch<T, NF> lf;
+  if (key >= B.nkeys - 1) {
+    // non-finite targets and targets beyond the far slab: NaN and their flags
+    const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
+      const TRec r = rec[j];
+      const long i = r.i;
+      double2 res[NO];
+      uint8_t fl;
+      eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
+      if (flags) flags[i] = fl;
+    }
+    return;
+  }
+  LdsFetch<T, NF, F1, F2, F3> lf;
   lf.lds = lds;
-  lf.F1 = (1 << B.tb1) + 3;
-  lf.F2 = (1 << B.tb2) + 3;
-  lf.F3 = (1 << B.tb3) + 3;
   lf.M1 = A.M1;
   lf.M2 = A.M2;
-  lf.gf = gf;
-  const bool valid = key < B.nkeys - 1;
-  if (valid) {
-    const bool near = key < B.nnear;
-    const int kk = near ? key : key - B.nnear;
-    const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
-    lf.near_tile = near;
-    lf.o1 = (b1 << B.tb1) - 1;
-    lf.o2 = (b2 << B.tb2) - 1;
-    lf.o3 = (b3 << B.tb3) - 1;
-    const int fsz = lf.F1 * lf.F2 * lf.F3;
-    for (int idx = threadIdx.x; idx < NF * fsz; idx += blockDim.x) {
-      const int f = idx / fsz, r = idx - f * fsz;
-      const int z = r / (lf.F1 * lf.F2), y = (r / lf.F1) % lf.F2, xx = r % lf.F1;
-      const int g1 = (lf.o1 + xx) & (A.M1 - 1), g2 = (lf.o2 + y) & (A.M2 - 1);
-      cplx<T> v;
-      if (near) {
-        const int g3 = (lf.o3 + z) & (A.M3 - 1);
-        v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-      } else {
-        const int g3 = min(max(lf.o3 + z, 0), A.S - 1);
-        v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-      }
-      lds[idx] = v;
+  lf.M3 = A.M3;
+  const bool near = key < B.nnear;
+  const int kk = near ? key : key - B.nnear;
+  const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
+  lf.near_tile = near;
+  lf.o1 = (b1 << TB1) - 1;
+  lf.o2 = (b2 << TB2) - 1;
+  lf.o3 = (b3 << TB3) - 1;
+  for (int idx = threadIdx.x; idx < NF * FSZ; idx += blockDim.x) {
+    const int f = idx / FSZ, r = idx - f * FSZ;
+    const int z = r / (F1 * F2), y = (r / F1) % F2, xx = r % F1;
+    const int g1 = (lf.o1 + xx) & (A.M1 - 1), g2 = (lf.o2 + y) & (A.M2 - 1);
+    cplx<T> v;
+    if (near) {
+      const int g3 = (lf.o3 + z) & (A.M3 - 1);
+      v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+    } else {
+      const int g3 = min(max(lf.o3 + z, 0), A.S - 1);
+      v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
     }
+    lds[idx] = v;
   }
   __syncthreads();
   for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
-    const long i = perm[j];
+    const TRec r = rec[j];
     double2 res[NO];
     uint8_t fl;
-    if (valid)
-      eval3d_target<T, NF>(A, xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], lf, res, fl);
-    else
-      eval3d_target<T, NF>(A, xs[3 * j], xs[3 * j + 1], xs[3 * j + 2], gf, res, fl);
+    lf.miss = false;
+    eval3d_target<T, NF>(A, r.x, r.y, r.z, lf, res, fl);
+    if (lf.miss) {
+      ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
+      continue;
+    }
+    const long i = r.i;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
+    if (flags) flags[i] = fl;
+  }
+}
+
+// Targets the tiled kernel handed over (stencil outside its tile footprint):
+// evaluated from global memory.  The count is read on the device.
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T>* __restrict__ grid,
+                                                           const cplx<T>* __restrict__ far,
+                                                           const TRec* __restrict__ rec,
+                                                           const uint32_t* __restrict__ ovf,
+                                                           const uint32_t* __restrict__ novf,
+                                                           cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
+  constexpr int NO = (NF == 1) ? 1 : 6;
+  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+  const long n = *novf;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+    const TRec r = rec[ovf[q]];
+    const long i = r.i;
+    double2 res[NO];
+    uint8_t fl;
+    eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
 #pragma unroll
     for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
     if (flags) flags[i] = fl;
@@ -479,15 +538,18 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ x, const uint2* __restrict__ keyrank,
                                                      const uint32_t* __restrict__ offs, long T_,
-                                                     double* __restrict__ xs, uint32_t* __restrict__ perm) {
+                                                     TRec* __restrict__ rec) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T_) return;
   const uint2 kr = keyrank[i];
   const long pos = (long)offs[kr.x] + kr.y;
-  xs[3 * pos] = x[3 * i];
-  xs[3 * pos + 1] = x[3 * i + 1];
-  xs[3 * pos + 2] = x[3 * i + 2];
-  perm[pos] = (uint32_t)i;
+  TRec r;
+  r.x = x[3 * i];
+  r.y = x[3 * i + 1];
+  r.z = x[3 * i + 2];
+  r.i = (uint32_t)i;
+  r.pad = 0u;
+  rec[pos] = r;
 }
 
 // Binning without per-target global atomics (used when the key count fits an
@@ -542,8 +604,7 @@ __global__ __launch_bounds__(256) void k_bin_colscan(uint32_t* __restrict__ cnt,
 
 __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __restrict__ x, long T_, long chunk,
                                                     const uint32_t* __restrict__ cnt,
-                                                    const uint32_t* __restrict__ offs, double* __restrict__ xs,
-                                                    uint32_t* __restrict__ perm) {
+                                                    const uint32_t* __restrict__ offs, TRec* __restrict__ rec) {
   extern __shared__ uint32_t cur[];
   const int nk = B.t.nkeys;
   const uint32_t* row = cnt + (long)blockIdx.x * nk;
@@ -553,10 +614,13 @@ __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __r
   for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const double a = x[3 * i], b = x[3 * i + 1], c = x[3 * i + 2];
     const long pos = atomicAdd(&cur[tile_key(B, a, b, c)], 1u);
-    xs[3 * pos] = a;
-    xs[3 * pos + 1] = b;
-    xs[3 * pos + 2] = c;
-    perm[pos] = (uint32_t)i;
+    TRec r;
+    r.x = a;
+    r.y = b;
+    r.z = c;
+    r.i = (uint32_t)i;
+    r.pad = 0u;
+    rec[pos] = r;
   }
 }
 
@@ -618,7 +682,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   // tile edges: 8 nodes per axis, fewer where the staged footprint of the
   // Maxwell fields would not fit in 64 KiB of LDS
   TileArgs& Tl = B.t;
-  Tl.tb1 = 3;
+  Tl.tb1 = 3;   // must match the instantiations of k_gather3d_tiled below
   Tl.tb2 = (P.nf == 7 && sizeof(T) == 8) ? 2 : 3;
   Tl.tb3 = (P.nf == 7) ? 2 : 3;
   Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
@@ -628,6 +692,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
   hipError_t e = ensure_bin_scratch(P, T_, Tl.nkeys);
   if (e != hipSuccess) return e;
+  TRec* rec = reinterpret_cast<TRec*>(P.bin_rec);
   {
     KernelTimer t(P, QPGF_T_BIN);
     if (Tl.nkeys <= kBinLdsKeys) {
@@ -638,28 +703,37 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
                          kBinBlocks, P.bin_hist);
       hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
       hipLaunchKernelGGL(k_bin_place, dim3(kBinBlocks), dim3(1024), lds, P.stream, B, x, (long)T_, chunk, P.bin_cnt,
-                         P.bin_offs, P.bin_xs, P.bin_perm);
+                         P.bin_offs, rec);
     } else {
       // large key spaces: one global atomic rank per target
       hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, P.stream, P.bin_hist,
                          (long)Tl.nkeys);
       hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, P.stream, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
       hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
-      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_,
-                         P.bin_xs, P.bin_perm);
+      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const size_t fsz = (size_t)((1 << Tl.tb1) + 3) * ((1 << Tl.tb2) + 3) * ((1 << Tl.tb3) + 3);
-  const size_t shm = fsz * P.nf * sizeof(cplx<T>);
   KernelTimer t(P, QPGF_T_GATHER);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.bin_novf, 1L);
+  const dim3 tg(Tl.nkeys);
+#define QPGF_TILED(NF_, A1_, A2_, A3_)                                                                           \
+  hipLaunchKernelGGL((k_gather3d_tiled<T, NF_, A1_, A2_, A3_>), tg, dim3(256), 0, P.stream, A, Tl, g, f, rec,      \
+                     P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
+  if (P.nf == 7) {
+    if (sizeof(T) == 8) QPGF_TILED(7, 3, 2, 2);
+    else QPGF_TILED(7, 3, 3, 2);
+  } else {
+    QPGF_TILED(1, 3, 3, 3);
+  }
+#undef QPGF_TILED
   if (P.nf == 7)
-    hipLaunchKernelGGL((k_gather3d_tiled<T, 7>), dim3(Tl.nkeys), dim3(256), shm, P.stream, A, Tl, g, f, P.bin_xs,
-                       P.bin_perm, P.bin_hist, P.bin_offs, o, flags);
+    hipLaunchKernelGGL((k_gather3d_overflow<T, 7>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
+                       P.bin_novf, o, flags);
   else
-    hipLaunchKernelGGL((k_gather3d_tiled<T, 1>), dim3(Tl.nkeys), dim3(256), shm, P.stream, A, Tl, g, f, P.bin_xs,
-                       P.bin_perm, P.bin_hist, P.bin_offs, o, flags);
+    hipLaunchKernelGGL((k_gather3d_overflow<T, 1>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
+                       P.bin_novf, o, flags);
   return hipGetLastError();
 }
 
@@ -667,16 +741,16 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 
 hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
   if (T_ > P.bin_cap) {
-    for (void* q : {(void*)P.bin_keyrank, (void*)P.bin_xs, (void*)P.bin_perm})
+    for (void* q : {(void*)P.bin_keyrank, (void*)P.bin_rec, (void*)P.bin_ovf})
       if (q) (void)hipFree(q);
     P.bin_keyrank = nullptr;
-    P.bin_xs = nullptr;
-    P.bin_perm = nullptr;
+    P.bin_rec = nullptr;
+    P.bin_ovf = nullptr;
     P.bin_cap = 0;
     hipError_t e;
     if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_keyrank), (size_t)T_ * sizeof(uint2))) != hipSuccess) return e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_xs), (size_t)T_ * 3 * sizeof(double))) != hipSuccess) return e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_perm), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(&P.bin_rec, (size_t)T_ * sizeof(TRec))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_ovf), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
     P.bin_cap = T_;
   }
   if (nkeys > P.bin_keycap) {
@@ -689,6 +763,7 @@ hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
     hipError_t e;
     if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_hist), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
     if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_offs), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
+    if (!P.bin_novf && (e = hipMalloc(reinterpret_cast<void**>(&P.bin_novf), sizeof(uint32_t))) != hipSuccess) return e;
     if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_cnt), (size_t)nkeys * kBinBlocks * sizeof(uint32_t))) !=
         hipSuccess)
       return e;

@@ -128,11 +128,12 @@ struct Plan {
   int64_t bin_cap = 0;
   int bin_keycap = 0;
   uint2* bin_keyrank = nullptr;
-  double* bin_xs = nullptr;
-  uint32_t* bin_perm = nullptr;
+  void* bin_rec = nullptr;             // targets in tile order (32-byte records)
   uint32_t* bin_hist = nullptr;
   uint32_t* bin_offs = nullptr;
   uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
+  uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
+  uint32_t* bin_novf = nullptr;        // their count
 
   // per-kernel timing (qpgf_plan_enable_timing)
   struct Pending { int id; hipEvent_t a, b; };
