@@ -207,22 +207,29 @@ __global__ void k_sing2d(int M1, int M2, double c_tilde, double A2, int Q, const
 
 // H(rho) = rho^-1 int_eps^{2eps} e^{ikr} (2ik Y' + Y'') sin(rho r) dr (the radial
 // form of the integral in eq. 3.5), tabulated on rho = (m - 4) hd, m in [0, hn).
-__global__ void k_htable(int hn, double hd, double k, int Q, const double* __restrict__ rq,
-                         const double* __restrict__ wrq, const double* __restrict__ y1q,
-                         const double* __restrict__ y2q, double2* __restrict__ htab) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int Q, const double* __restrict__ rq,
+                                                const double* __restrict__ wrq, const double* __restrict__ y1q,
+                                                const double* __restrict__ y2q, double2* __restrict__ htab) {
+  // one 64-lane wave per table entry, lanes over quadrature nodes
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (m >= hn) return;
   const double rho = fabs((m - 4) * hd);
   double2 acc = mk(0.0, 0.0);
-  for (int q = 0; q < Q; ++q) {
+  for (int q = lane; q < Q; q += 64) {
     const double r = rq[q];
     double s, c;
     sincos(k * r, &s, &c);
-    double2 g = cmul(mk(c, s), mk(y2q[q], 2.0 * k * y1q[q]));
+    const double2 g = cmul(mk(c, s), mk(y2q[q], 2.0 * k * y1q[q]));
     const double sn = rho > 0.0 ? sin(rho * r) / rho : r;
     acc = cadd(acc, cscale(g, wrq[q] * sn));
   }
-  htab[m] = acc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (lane == 0) htab[m] = acc;
 }
 
 // Far slab, 3D: per-slice coefficients (i/8pi^2) beta^-1 e^{i beta z_s} of the
@@ -324,7 +331,7 @@ hipError_t launch_sing2d(Plan& P, double f1zero) {
 }
 
 hipError_t launch_htable(Plan& P, double k) {
-  hipLaunchKernelGGL(k_htable, dim3((P.hn + 255) / 256), dim3(256), 0, P.stream, P.hn, P.hd, k, P.p.quad_q, P.rq,
+  hipLaunchKernelGGL(k_htable, dim3((P.hn + 3) / 4), dim3(256), 0, P.stream, P.hn, P.hd, k, P.p.quad_q, P.rq,
                      P.wrq, P.y1q, P.y2q, P.htab);
   return hipGetLastError();
 }
