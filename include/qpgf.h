@@ -74,7 +74,8 @@ typedef enum {
 /* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
  * size per axis: m1 = 2 N1 modes in x1; 2D: m2 = 2 N2 transverse (x2) modes;
  * 3D: m2 = 2 N2 modes in x2 and m3 = 2 N3 transverse (x3) modes.  Each must be
- * a power of two in [16, 4096] (m3 unused in 2D).  Grid spacing: pi/N1, pi/N2
+ * a power of two in [16, 4096] (m3 unused in 2D); with complex128 at most 2048,
+ * and axes transformed as columns (2D: m2; 3D: m2, m3) at most half the limit.  Grid spacing: pi/N1, pi/N2
  * (3D) and c_tilde/N_t in the transverse direction.
  * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
  * eps = 0.2, cut-offs: C^8 smoothstep I_u(9,9) transitions (Section 6 states C^8),
@@ -146,6 +147,30 @@ qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
 qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
                            const double* x, int64_t T, void* out, uint8_t* flags);
 
+/* Batched form of Algorithm 2.1: n_inst independent instances in one call.
+ * Instance i has wavenumber k[i], alpha[i] and x1 size m1[i] (a power of two,
+ * 16 <= m1[i] <= params.m1; every instance uses the plan's transverse size m2
+ * and method parameters) and owns targets t_off[i] .. t_off[i+1]-1 of the
+ * concatenated device array x [t_off[n_inst]][2]; its results go to the same
+ * positions of out (and flags).  k, alpha, m1 and t_off are HOST arrays, read
+ * during the call.  Each stage (coefficient fill, transverse FFT, x1 FFT, far
+ * slab, gather) is a single launch over all instances; the whole sequence is
+ * captured once in a HIP graph and replayed on later calls with the same n_inst,
+ * m1[], t_off[], x, out and flags (k and alpha may differ).  The 2D singular
+ * tables of the plan serve every instance (they depend on the coefficient index
+ * only, Remark 2.1).  Needs a plan of kind QPGF_KIND_G2D; every instance is
+ * checked for Wood anomalies and special coefficients before any launch. */
+qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const double* k, const double* alpha, const int* m1,
+                             const int64_t* t_off, const double* x, void* out, uint8_t* flags);
+
+/* FFT autotuner: for every transform shape the plan uses (and, for 2D plans,
+ * every power-of-two x1 length from 16 to params.m1), time the candidate numbers
+ * of transforms per block on scratch memory and keep the fastest.  Results are
+ * cached in the text file cache_path (NULL: no file), one line per shape:
+ * "<arch> <prec> <n> <rows|cols> <batch> <tile> <us>"; shapes found there are not
+ * re-timed.  Synchronous; call after plan creation. */
+qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_path);
+
 /* Stage outputs for parity checks.  qpgf_prepare_stage runs the preparation only
  * up to `stage`: 0 = coefficient fill (A L-hat_j with A the basis normalisation
  * 1/(2 sqrt(pi c~)) in 2D, 1/sqrt(8 pi^2 c~) in 3D, in FFT order: index j mod m
@@ -174,7 +199,8 @@ typedef enum {
   QPGF_T_FAR_FFT = 6,  /* inverse FFTs of the far slab                           */
   QPGF_T_GATHER = 7,   /* interpolation gather, add-back and phase               */
   QPGF_T_BIN = 8,      /* target binning by grid tile (key, scan, scatter)       */
-  QPGF_T_COUNT = 9
+  QPGF_T_BATCH = 9,    /* one replay of the batched 2D graph (all stages)        */
+  QPGF_T_COUNT = 10
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
 qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches);

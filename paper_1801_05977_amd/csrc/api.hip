@@ -80,7 +80,21 @@ qpgf_status upload(V** dst, const std::vector<V>& src) {
   return QPGF_OK;
 }
 
+void free_batch(Plan& P) {
+  if (P.b_exec) (void)hipGraphExecDestroy(P.b_exec);
+  if (P.b_graph) (void)hipGraphDestroy(P.b_graph);
+  P.b_exec = nullptr;
+  P.b_graph = nullptr;
+  P.b_sig.clear();
+}
+
 void free_plan(Plan& P) {
+  free_batch(P);
+  if (P.b_capture) (void)hipStreamDestroy(P.b_capture);
+  if (P.b_upload_done) (void)hipEventDestroy(P.b_upload_done);
+  if (P.b_host) (void)hipHostFree(P.b_host);
+  for (void* q : {P.b_grid, P.b_far, P.b_desc})
+    if (q) (void)hipFree(q);
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
                   P.twf,  P.F1,  P.F2,   P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
@@ -95,6 +109,14 @@ qpgf_status validate(const qpgf_params* p) {
     return fail(QPGF_E_SIZE, "m1 and m2 must be powers of two in [16, 4096]");
   if (p->kind != QPGF_KIND_G2D && !pow2_in(p->m3, 16, 4096))
     return fail(QPGF_E_SIZE, "m3 must be a power of two in [16, 4096]");
+  {
+    // one transform of the longest axis must fit the 64 KiB LDS of a block (two buffers)
+    // rows (x1) up to lim; column axes (x2, and x3 in 3D) have padded LDS rows: up to lim / 2
+    const int lim = p->prec == QPGF_C128 ? 2048 : 4096;
+    const bool bad = p->m1 > lim || p->m2 > lim / 2 || (p->kind != QPGF_KIND_G2D && p->m3 > lim / 2);
+    if (bad)
+      return fail(QPGF_E_SIZE, "m1 <= 2048 (complex128) / 4096 (complex64); m2, m3 at most half of that");
+  }
   if (!(p->c > 0.0) || !(p->c_tilde > p->c)) return fail(QPGF_E_ARG, "need 0 < c < c_tilde");
   if (!(p->eps > 0.0) || !(2.0 * p->eps <= p->c_tilde)) return fail(QPGF_E_ARG, "need 0 < 2 eps <= c_tilde");
   if (p->quad_q < 16 || p->quad_q > 256) return fail(QPGF_E_ARG, "quad_q must be in [16, 256]");
@@ -106,7 +128,12 @@ qpgf_status validate(const qpgf_params* p) {
 
 // Wood anomaly: beta_n = 0 for some mode n (Section 1).  Only lattice points with
 // |xi_perp| within 1 of k can come close.
+qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int M1);
 qpgf_status check_instance(const Plan& P, double k, double a1, double a2) {
+  return check_instance_m1(P, k, a1, a2, P.M1);
+}
+
+qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int M1) {
   if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(a1) || !std::isfinite(a2))
     return fail(QPGF_E_ARG, "need finite k > 0 and finite alpha");
   const double wt = P.p.wood_tol, st = P.p.special_tol;
@@ -124,7 +151,7 @@ qpgf_status check_instance(const Plan& P, double k, double a1, double a2) {
     for (long n = (long)floor(-k - a1) - 1; n <= (long)ceil(k - a1) + 1; ++n) {
       double rho = fabs(a1 + n);
       minb = std::min(minb, sqrt(fabs((k - rho) * (k + rho))));
-      if (n >= -P.M1 / 2 && n < P.M1 / 2 && special(rho))
+      if (n >= -M1 / 2 && n < M1 / 2 && special(rho))
         return fail(QPGF_E_SPECIAL, "beta_j1 = j2 pi / c_tilde within special_tol (perturb c_tilde)");
     }
   } else {
@@ -132,7 +159,7 @@ qpgf_status check_instance(const Plan& P, double k, double a1, double a2) {
       for (long n2 = (long)floor(-k - a2) - 1; n2 <= (long)ceil(k - a2) + 1; ++n2) {
         double rho = sqrt((a1 + n1) * (a1 + n1) + (a2 + n2) * (a2 + n2));
         minb = std::min(minb, sqrt(fabs((k - rho) * (k + rho))));
-        if (n1 >= -P.M1 / 2 && n1 < P.M1 / 2 && n2 >= -P.M2 / 2 && n2 < P.M2 / 2 && special(rho))
+        if (n1 >= -M1 / 2 && n1 < M1 / 2 && n2 >= -P.M2 / 2 && n2 < P.M2 / 2 && special(rho))
           return fail(QPGF_E_SPECIAL, "beta_j1j2 = j3 pi / c_tilde within special_tol (perturb c_tilde)");
       }
   }
@@ -467,6 +494,288 @@ qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double a1, double a2, cons
                            void* out, uint8_t* flags) {
   return both(plan, QPGF_KIND_MAXWELL3D, k, a1, a2, x, T, out, flags);
 }
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// batched 2D
+// ----------------------------------------------------------------------------
+namespace {
+
+template <typename V>
+hipError_t grow(V** p, size_t& cap, size_t bytes) {
+  if (bytes <= cap) return hipSuccess;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  cap = 0;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e == hipSuccess) cap = bytes;
+  return e;
+}
+
+struct BatchLayout {
+  size_t fill_off, far_off, gat_off, segT_off, segR_off, segF_off, bytes;
+  long fill_blocks, far_blocks, gat_blocks, segT_blocks, segR_blocks, segF_blocks;
+  long lds_T, lds_R, lds_F;   // largest tile * (n + 1) over the segments of each launch
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const double* k, const double* alpha,
+                                        const int* m1, const int64_t* t_off, const double* x, void* out,
+                                        uint8_t* flags) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, QPGF_KIND_G2D);
+  if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
+  if (n_inst <= 0 || !k || !alpha || !m1 || !t_off) return fail(QPGF_E_ARG, "need n_inst > 0 and host k, alpha, m1, t_off");
+  if (t_off[0] != 0) return fail(QPGF_E_ARG, "t_off[0] must be 0");
+  for (int i = 0; i < n_inst; ++i) {
+    if (!pow2_in(m1[i], 16, P.M1)) return fail(QPGF_E_SIZE, "m1[i] must be a power of two in [16, params.m1]");
+    if (t_off[i + 1] < t_off[i]) return fail(QPGF_E_ARG, "t_off must be non-decreasing");
+  }
+  const int64_t T = t_off[n_inst];
+  if (T > 0 && (!x || !out)) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
+  if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  for (int i = 0; i < n_inst; ++i) {
+    st = check_instance_m1(P, k[i], alpha[i], 0.0, m1[i]);
+    if (st != QPGF_OK) {
+      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      return st;
+    }
+  }
+  // layout of the instance grids and of the descriptors
+  const size_t fsz = fill_inst_size(), gsz = gather_inst_size();
+  BatchLayout Lo{};
+  Lo.fill_off = 0;
+  Lo.far_off = align_up(Lo.fill_off + n_inst * fsz);
+  Lo.gat_off = align_up(Lo.far_off + n_inst * fsz);
+  Lo.segT_off = align_up(Lo.gat_off + n_inst * gsz);
+  Lo.segR_off = align_up(Lo.segT_off + n_inst * sizeof(FftSeg));
+  Lo.segF_off = align_up(Lo.segR_off + n_inst * sizeof(FftSeg));
+  Lo.bytes = align_up(Lo.segF_off + n_inst * sizeof(FftSeg));
+  size_t grid_elems = 0, far_elems = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    grid_elems += (size_t)m1[i] * P.M2;
+    far_elems += (size_t)m1[i] * P.S;
+  }
+  HIP_TRY(grow(&P.b_grid, P.b_grid_cap, grid_elems * P.esize));
+  HIP_TRY(grow(&P.b_far, P.b_far_cap, far_elems * P.esize));
+  if (Lo.bytes > P.b_desc_cap) {
+    if (P.b_upload_done) HIP_TRY(hipEventSynchronize(P.b_upload_done));
+    if (P.b_host) (void)hipHostFree(P.b_host);
+    P.b_host = nullptr;
+    if (P.b_desc) (void)hipFree(P.b_desc);
+    P.b_desc = nullptr;
+    P.b_desc_cap = 0;
+    HIP_TRY(hipHostMalloc(&P.b_host, Lo.bytes));
+    HIP_TRY(hipMalloc(&P.b_desc, Lo.bytes));
+    P.b_desc_cap = Lo.bytes;
+    free_batch(P);     // the graph refers to the old descriptor buffer
+  }
+  if (!P.b_upload_done) HIP_TRY(hipEventCreateWithFlags(&P.b_upload_done, hipEventDisableTiming));
+  HIP_TRY(hipEventSynchronize(P.b_upload_done));   // previous upload finished with the staging buffer
+  char* h = static_cast<char*>(P.b_host);
+  long fb = 0, rb = 0, gb = 0, tb = 0, rrb = 0, frb = 0;
+  size_t goff = 0, foff = 0;
+  Lo.lds_T = Lo.lds_R = Lo.lds_F = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const int M = m1[i];
+    fill_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, fb, h + Lo.fill_off + i * fsz);
+    fb += (M + 15) / 16;
+    fill_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, rb, h + Lo.far_off + i * fsz);
+    rb += ((long)M * P.S + 255) / 256;
+    gather_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, (long)t_off[i], (long)t_off[i + 1], gb,
+                   h + Lo.gat_off + i * gsz);
+    gb += (long)((t_off[i + 1] - t_off[i] + 255) / 256);
+    FftSeg sT{(long)goff, P.M2, __builtin_ctz((unsigned)P.M2), (long)M, (long)M, (long)M, 1, 0,
+              fft_tile(P, P.M2, false, M), tb};
+    tb += (sT.nbatch + sT.tile - 1) / sT.tile;
+    Lo.lds_T = std::max(Lo.lds_T, (long)sT.tile * (sT.n + 1));   // column transforms: padded rows
+    FftSeg sR{(long)goff, M, __builtin_ctz((unsigned)M), 1, (long)P.M2, 1, 0, (long)M, fft_tile(P, M, true, P.M2), rrb};
+    rrb += (sR.nbatch + sR.tile - 1) / sR.tile;
+    Lo.lds_R = std::max(Lo.lds_R, (long)sR.tile * sR.n);
+    FftSeg sF{(long)foff, M, __builtin_ctz((unsigned)M), 1, (long)P.S, 1, 0, (long)M, fft_tile(P, M, true, P.S), frb};
+    frb += (sF.nbatch + sF.tile - 1) / sF.tile;
+    Lo.lds_F = std::max(Lo.lds_F, (long)sF.tile * sF.n);
+    std::memcpy(h + Lo.segT_off + i * sizeof(FftSeg), &sT, sizeof sT);
+    std::memcpy(h + Lo.segR_off + i * sizeof(FftSeg), &sR, sizeof sR);
+    std::memcpy(h + Lo.segF_off + i * sizeof(FftSeg), &sF, sizeof sF);
+    goff += (size_t)M * P.M2;
+    foff += (size_t)M * P.S;
+  }
+  Lo.fill_blocks = fb;
+  Lo.far_blocks = rb;
+  Lo.gat_blocks = gb;
+  Lo.segT_blocks = tb;
+  Lo.segR_blocks = rrb;
+  Lo.segF_blocks = frb;
+  // LDS of one k_fft_multi launch: two buffers for its largest tile * (n + 1)
+  if ((size_t)2 * std::max(Lo.lds_T, std::max(Lo.lds_R, Lo.lds_F)) * P.esize > 65536)
+    return fail(QPGF_E_SIZE, "FFT tile choice exceeds the LDS of one block");
+  const hipStream_t user = P.stream;
+  HIP_TRY(hipMemcpyAsync(P.b_desc, P.b_host, Lo.bytes, hipMemcpyHostToDevice, user));
+  HIP_TRY(hipEventRecord(P.b_upload_done, user));
+
+  std::vector<int64_t> sig;
+  sig.push_back(n_inst);
+  sig.push_back(P.p.prec);
+  for (int i = 0; i < n_inst; ++i) sig.push_back(m1[i]);
+  for (int i = 0; i <= n_inst; ++i) sig.push_back(t_off[i]);
+  for (const void* q : {(const void*)x, (const void*)out, (const void*)flags, (const void*)P.b_grid,
+                        (const void*)P.b_far, (const void*)P.b_desc})
+    sig.push_back((int64_t)(intptr_t)q);
+  if (!P.b_exec || sig != P.b_sig) {
+    free_batch(P);
+    if (!P.b_capture) HIP_TRY(hipStreamCreateWithFlags(&P.b_capture, hipStreamNonBlocking));
+    const bool timing = P.timing;
+    P.timing = false;
+    P.stream = P.b_capture;
+    char* d = static_cast<char*>(P.b_desc);
+    hipError_t e = hipStreamBeginCapture(P.b_capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_fill2d_multi(P, d + Lo.fill_off, n_inst, Lo.fill_blocks, P.b_grid);
+    if (e == hipSuccess)
+      e = launch_fft_multi(P, P.b_grid, reinterpret_cast<const FftSeg*>(d + Lo.segT_off), n_inst, Lo.segT_blocks,
+                           Lo.lds_T);
+    if (e == hipSuccess)
+      e = launch_fft_multi(P, P.b_grid, reinterpret_cast<const FftSeg*>(d + Lo.segR_off), n_inst, Lo.segR_blocks,
+                           Lo.lds_R);
+    if (e == hipSuccess) e = launch_far2d_multi(P, d + Lo.far_off, n_inst, Lo.far_blocks, P.b_far);
+    if (e == hipSuccess)
+      e = launch_fft_multi(P, P.b_far, reinterpret_cast<const FftSeg*>(d + Lo.segF_off), n_inst, Lo.segF_blocks,
+                           Lo.lds_F);
+    if (e == hipSuccess && Lo.gat_blocks > 0)
+      e = launch_gather2d_multi(P, d + Lo.gat_off, n_inst, Lo.gat_blocks, P.b_grid, P.b_far, x, out, flags);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(P.b_capture, &g);
+    P.stream = user;
+    P.timing = timing;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&P.b_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      P.b_exec = nullptr;
+      return hip_fail(e, "batched graph capture");
+    }
+    P.b_graph = g;
+    P.b_sig = sig;
+  }
+  KernelTimer t(P, QPGF_T_BATCH);
+  HIP_TRY(hipGraphLaunch(P.b_exec, user));
+  return QPGF_OK;
+}
+
+// ----------------------------------------------------------------------------
+// FFT autotuner
+// ----------------------------------------------------------------------------
+extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_path) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, -1);
+  if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
+  struct Shape { int n; bool rows; long batch; };
+  std::vector<Shape> shapes;
+  if (P.dim == 2) {
+    shapes.push_back({P.M2, false, (long)P.M1});
+    for (int n = 16; n <= P.M1; n <<= 1) {
+      shapes.push_back({n, true, (long)P.M2});
+      shapes.push_back({n, true, (long)P.S});
+    }
+  } else {
+    shapes.push_back({P.M3, false, (long)P.M1 * P.M2 * P.nf});
+    shapes.push_back({P.M2, false, (long)P.M1 * P.M3 * P.nf});
+    shapes.push_back({P.M1, true, (long)P.M2 * P.M3 * P.nf});
+    shapes.push_back({P.M2, false, (long)P.M1 * P.S * P.nf});
+    shapes.push_back({P.M1, true, (long)P.M2 * P.S * P.nf});
+  }
+  const char* arch = "gfx950";
+  const char* prec = P.p.prec == QPGF_C128 ? "c128" : "c64";
+  std::map<std::string, int> cache;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char a[32], pr[16], ax[8];
+      int n, tile;
+      long batch;
+      double us;
+      while (fscanf(f, "%31s %15s %d %7s %ld %d %lf", a, pr, &n, ax, &batch, &tile, &us) == 7)
+        cache[std::string(a) + " " + pr + " " + std::to_string(n) + " " + ax + " " + std::to_string(batch)] = tile;
+      fclose(f);
+    }
+  }
+  size_t need = 0;
+  for (const Shape& s : shapes) need = std::max(need, (size_t)s.n * s.batch * P.esize);
+  void* scratch = nullptr;
+  HIP_TRY(hipMalloc(&scratch, need));
+  HIP_TRY(hipMemset(scratch, 0, need));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  const bool timing = P.timing;
+  P.timing = false;
+  std::string lines;
+  for (const Shape& s : shapes) {
+    const std::string key = std::string(arch) + " " + prec + " " + std::to_string(s.n) + " " + (s.rows ? "rows" : "cols") +
+                            " " + std::to_string(s.batch);
+    const int mkey = (s.n << 2) | (s.rows ? 1 : 0) | (P.p.prec == QPGF_C64 ? 2 : 0);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      P.fft_tiles[mkey] = it->second;
+      continue;
+    }
+    int best = 0;
+    double best_us = 1e30;
+    for (int tile = 1; tile <= 64; tile <<= 1) {
+      if (tile > s.batch || (size_t)2 * tile * (s.n + (s.rows ? 0 : 1)) * P.esize > 65536) break;
+      P.fft_tiles[mkey] = tile;
+      // rows: batches contiguous; cols: element stride = batch count, adjacent batches
+      const long es = s.rows ? 1 : s.batch;
+      const long b_in = s.rows ? 1 : s.batch, s_in = s.rows ? 0 : 1, s_out = s.rows ? s.n : 0;
+      hipError_t e = hipSuccess;
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_fft(P, scratch, s.n, es, s.batch, b_in, s_in, s_out);
+      if (e == hipSuccess) e = hipEventRecord(a, P.stream);
+      for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_fft(P, scratch, s.n, es, s.batch, b_in, s_in, s_out);
+      if (e == hipSuccess) e = hipEventRecord(b, P.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) {
+        P.timing = timing;
+        (void)hipFree(scratch);
+        return hip_fail(e, "autotune");
+      }
+      const double us = 1000.0 * ms / 5;
+      if (us < best_us) {
+        best_us = us;
+        best = tile;
+      }
+    }
+    if (best > 0) {
+      P.fft_tiles[mkey] = best;
+      char buf[160];
+      snprintf(buf, sizeof buf, "%s %s %d %s %ld %d %.3f\n", arch, prec, s.n, s.rows ? "rows" : "cols", s.batch, best,
+               best_us);
+      lines += buf;
+    } else {
+      P.fft_tiles.erase(mkey);
+    }
+  }
+  P.timing = timing;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(scratch);
+  free_batch(P);   // a captured batched graph used the old tiles
+  if (cache_path && !lines.empty()) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fputs(lines.c_str(), f);
+      fclose(f);
+    }
+  }
+  return QPGF_OK;
+}
+
+extern "C" {
 
 qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst) {
   g_err.clear();

@@ -27,15 +27,14 @@ template <typename V> __device__ __forceinline__ V c_addi(V a, V b) { V r; r.x =
 template <typename V> __device__ __forceinline__ V c_subi(V a, V b) { V r; r.x = a.x + b.y; r.y = a.y - b.x; return r; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch,
-                                             long b_in, long s_in, long s_out, int tile,
-                                             const cplx<T>* __restrict__ tw, int twlog2) {
+__device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch, long b_in,
+                                         long s_in, long s_out, int tile, const cplx<T>* __restrict__ tw, int twlog2,
+                                         long blk, char* smem_raw) {
   using V = cplx<T>;
-  extern __shared__ char smem_raw[];
-  const int pitch = n + 1;   // pad rows so column-wise LDS writes do not share a bank
+  const int pitch = n + (es == 1 ? 0 : 1);   // pad column tiles so their LDS writes do not share a bank
   V* bufA = reinterpret_cast<V*>(smem_raw);
   V* bufB = bufA + (size_t)tile * pitch;
-  const long b0 = (long)blockIdx.x * tile;
+  const long b0 = blk * tile;
   const int ntile = (int)min((long)tile, nbatch - b0);
   const int total = tile * n;
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -103,16 +102,37 @@ __global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, 
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch,
+                                             long b_in, long s_in, long s_out, int tile,
+                                             const cplx<T>* __restrict__ tw, int twlog2) {
+  extern __shared__ char smem_raw[];
+  fft_body<T>(data, n, log2n, es, nbatch, b_in, s_in, s_out, tile, tw, twlog2, blockIdx.x, smem_raw);
+}
+
+// Several independent batched transforms (segments, e.g. one per instance, of
+// different lengths) in one launch; block b belongs to the last segment whose
+// first block is <= b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, const FftSeg* __restrict__ segs,
+                                                   int nseg, const cplx<T>* __restrict__ tw, int twlog2) {
+  extern __shared__ char smem_raw[];
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].blk0 <= (long)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const FftSeg g = segs[lo];
+  fft_body<T>(base + g.off, g.n, g.log2n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, twlog2,
+              (long)blockIdx.x - g.blk0, smem_raw);
+}
+
+template <typename T>
 hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   if (n <= 1 || nbatch <= 0) return hipSuccess;
   const int log2n = __builtin_ctz((unsigned)n);
-  // about 32 KiB per LDS buffer
-  const int budget = (int)(32768 / sizeof(cplx<T>));
-  int tile = budget / (n + 1);
-  if (tile < 1) tile = 1;
-  if (tile > 64) tile = 64;
-  if (tile > nbatch) tile = (int)nbatch;
-  const size_t shm = (size_t)2 * tile * (n + 1) * sizeof(cplx<T>);
+  int tile = fft_tile(P, n, es == 1, nbatch);
+  const size_t shm = (size_t)2 * tile * (n + (es == 1 ? 0 : 1)) * sizeof(cplx<T>);
   const long nblk = (nbatch + tile - 1) / tile;
   const cplx<T>* tw = nullptr;
   if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
@@ -121,7 +141,39 @@ hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t fft_multi_impl(Plan& P, void* base, const FftSeg* dsegs, int nseg, long nblocks, long lds_elems) {
+  const size_t shm = (size_t)2 * lds_elems * sizeof(cplx<T>);
+  const cplx<T>* tw = nullptr;
+  if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
+  hipLaunchKernelGGL(k_fft_multi<T>, dim3((unsigned)nblocks), dim3(256), shm, P.stream, static_cast<cplx<T>*>(base),
+                     dsegs, nseg, tw, P.twlog2);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+// Default tile (transforms per block): about 32 KiB per LDS buffer, at most 64,
+// unless the autotuner has recorded a faster choice for this length and axis.
+int fft_tile(const Plan& P, int n, bool rows, long nbatch) {
+  int tile = 0;
+  const int key = (n << 2) | (rows ? 1 : 0) | (P.p.prec == QPGF_C64 ? 2 : 0);
+  auto it = P.fft_tiles.find(key);
+  if (it != P.fft_tiles.end()) tile = it->second;
+  if (tile <= 0) {
+    const int budget = (int)(32768 / P.esize);
+    tile = budget / (n + (rows ? 0 : 1));
+    if (tile < 1) tile = 1;
+    if (tile > 64) tile = 64;
+  }
+  if (tile > nbatch) tile = (int)nbatch;
+  return tile;
+}
+
+hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, long nblocks, long lds_elems) {
+  return P.p.prec == QPGF_C128 ? fft_multi_impl<double>(P, base, dsegs, nseg, nblocks, lds_elems)
+                               : fft_multi_impl<float>(P, base, dsegs, nseg, nblocks, lds_elems);
+}
 
 hipError_t launch_fft(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   return P.p.prec == QPGF_C128 ? fft_impl<double>(P, data, n, es, nbatch, b_in, s_in, s_out)

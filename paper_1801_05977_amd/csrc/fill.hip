@@ -146,35 +146,77 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
 }
 
 // 2D near fill (Algorithm 2.1 steps 1a-1b): L-hat = K-hat (2.1) - F1 + i alpha F2 (2.3).
+// F1, F2: singular tables for x1 size M1t >= A.M1 (entry j at j mod M1t), shared by
+// every instance whose x1 size divides into the same table.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __restrict__ xq,
-                                                const double* __restrict__ wxq, const double2* __restrict__ cs,
-                                                const double2* __restrict__ F1, const double2* __restrict__ F2,
-                                                cplx<T>* __restrict__ out) {
-  extern __shared__ double2 sa[];
+__device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const double* __restrict__ xq,
+                                            const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                            const double2* __restrict__ F1, const double2* __restrict__ F2, int M1t,
+                                            cplx<T>* __restrict__ out, double2* sa) {
   const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
-  const int j1p0 = blockIdx.x * TP;
+  const int j1p0 = blk * TP;
   const int j1p = j1p0 + ip;
   pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
   __syncthreads();
   if (j1p >= A.M1) return;
-  const double a = A.a1 + centered(j1p, A.M1);
+  const int j1 = centered(j1p, A.M1);
+  const double a = A.a1 + j1;
   const double2 b = beta_of(A.k, fabs(a));
   const bool use_I = b.y * A.c < 41.5;
   const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
+  const int jt_tab = j1 & (M1t - 1);
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
     double2 term = mk(0.0, 0.0);
     if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
     const double2 K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
-    const size_t o = (size_t)jtp * A.M1 + j1p;
-    const double2 f1 = F1[o], f2 = F2[o];
+    const size_t ot = (size_t)jtp * M1t + jt_tab;
+    const double2 f1 = F1[ot], f2 = F2[ot];
     // L = K - F1 + i alpha F2, times the basis normalisation A2
     const double2 L = cscale(mk(K.x - f1.x - A.a1 * f2.y, K.y - f1.y + A.a1 * f2.x), A.A);
-    store_c<T>(out, o, L);
+    store_c<T>(out, (size_t)jtp * A.M1 + j1p, L);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __restrict__ xq,
+                                                const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                                const double2* __restrict__ F1, const double2* __restrict__ F2,
+                                                cplx<T>* __restrict__ out) {
+  extern __shared__ double2 sa[];
+  fill2d_body<T>(A, blockIdx.x, xq, wxq, cs, F1, F2, A.M1, out, sa);
+}
+
+// Many 2D instances in one launch: instance i owns blocks [inst[i].blk0, inst[i+1].blk0).
+struct FillInst {
+  FillArgs A;
+  long off;      // first element of the instance's near grid
+  long foff;     // first element of its far slab
+  long blk0;     // first block of the instance in this launch
+};
+
+__device__ __forceinline__ int find_inst(const FillInst* __restrict__ inst, int n, long blk) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].blk0 <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill2d_multi(const FillInst* __restrict__ inst, int n_inst,
+                                                      const double* __restrict__ xq, const double* __restrict__ wxq,
+                                                      const double2* __restrict__ cs, const double2* __restrict__ F1,
+                                                      const double2* __restrict__ F2, int M1t,
+                                                      cplx<T>* __restrict__ base) {
+  extern __shared__ double2 sa[];
+  const int i = find_inst(inst, n_inst, blockIdx.x);
+  const FillInst I = inst[i];
+  fill2d_body<T>(I.A, (int)(blockIdx.x - I.blk0), xq, wxq, cs, F1, F2, M1t, base + I.off, sa);
 }
 
 // 2D singular tables (eqs. 2.4, 2.5), k- and alpha-independent (Remark 2.1):
@@ -270,6 +312,20 @@ __global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf,
   store_c<T>(out, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
 }
 
+// Far slab of many 2D instances: instance i owns blocks [blk0_i, blk0_{i+1}) of 256 threads.
+template <typename T>
+__global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, int S, double z0, double hf,
+                              cplx<T>* __restrict__ base) {
+  const int i = find_inst(inst, n_inst, blockIdx.x);
+  const FillInst I = inst[i];
+  const long idx = (blockIdx.x - I.blk0) * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)I.A.M1 * S) return;
+  const int j1p = (int)(idx % I.A.M1), s = (int)(idx / I.A.M1);
+  const double2 b = beta_of(I.A.k, fabs(I.A.a1 + centered(j1p, I.A.M1)));
+  const double z = z0 + s * hf;
+  store_c<T>(base + I.foff, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
+}
+
 template <typename T>
 hipError_t fill_impl(Plan& P, double k, double a1, double a2) {
   FillArgs A;
@@ -333,6 +389,52 @@ hipError_t launch_sing2d(Plan& P, double f1zero) {
 hipError_t launch_htable(Plan& P, double k) {
   hipLaunchKernelGGL(k_htable, dim3((P.hn + 3) / 4), dim3(256), 0, P.stream, P.hn, P.hd, k, P.p.quad_q, P.rq,
                      P.wrq, P.y1q, P.y2q, P.htab);
+  return hipGetLastError();
+}
+
+// host-side descriptor of one 2D instance for the batched launches
+void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long blk0, void* dst) {
+  FillInst I;
+  I.A.k = k;
+  I.A.a1 = a;
+  I.A.a2 = 0.0;
+  I.A.c = P.p.c;
+  I.A.c_tilde = P.p.c_tilde;
+  I.A.A = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
+  I.A.M1 = M1;
+  I.A.M2 = P.M2;
+  I.A.Mt = P.M2;
+  I.A.Q = P.p.quad_q;
+  I.A.hd = P.hd;
+  I.A.fstride = (long)M1 * P.M2;
+  I.off = off;
+  I.foff = foff;
+  I.blk0 = blk0;
+  *static_cast<FillInst*>(dst) = I;
+}
+size_t fill_inst_size() { return sizeof(FillInst); }
+
+hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base) {
+  const size_t shm = (size_t)TP * P.p.quad_q * sizeof(double2);
+  const auto* in = static_cast<const FillInst*>(dinst);
+  if (P.p.prec == QPGF_C128)
+    hipLaunchKernelGGL(k_fill2d_multi<double>, dim3((unsigned)nblocks), dim3(TP * TL), shm, P.stream, in, n_inst,
+                       P.xq, P.wxq, P.cs, P.F1, P.F2, P.M1, static_cast<double2*>(base));
+  else
+    hipLaunchKernelGGL(k_fill2d_multi<float>, dim3((unsigned)nblocks), dim3(TP * TL), shm, P.stream, in, n_inst,
+                       P.xq, P.wxq, P.cs, P.F1, P.F2, P.M1, static_cast<float2*>(base));
+  return hipGetLastError();
+}
+
+hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base) {
+  const double hf = P.p.far_h, z0 = P.p.c - hf;
+  const auto* in = static_cast<const FillInst*>(dinst);
+  if (P.p.prec == QPGF_C128)
+    hipLaunchKernelGGL(k_far2d_multi<double>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst, P.S, z0,
+                       hf, static_cast<double2*>(base));
+  else
+    hipLaunchKernelGGL(k_far2d_multi<float>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst, P.S, z0,
+                       hf, static_cast<float2*>(base));
   return hipGetLastError();
 }
 

@@ -397,11 +397,9 @@ __global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T
 
 // 2D: G (Algorithm 2.1).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __restrict__ grid,
-                                                  const cplx<T>* __restrict__ far, const double* __restrict__ x,
-                                                  long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= T_) return;
+__device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+                                             const cplx<T>* __restrict__ far, const double* __restrict__ x, long i,
+                                             cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
   uint8_t fl = 0;
   double2 res;
@@ -471,6 +469,40 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
   }
   store_out<T>(out, i, res);
   if (flags) flags[i] = fl;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __restrict__ grid,
+                                                  const cplx<T>* __restrict__ far, const double* __restrict__ x,
+                                                  long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T_) gather2d_one<T>(A, grid, far, x, i, out, flags);
+}
+
+// Many 2D instances in one launch: instance i owns blocks [blk0_i, blk0_{i+1}) and
+// targets [t0_i, t1_i) of the concatenated target array.
+struct GatherInst {
+  GArgs A;
+  long off, foff;     // first element of the instance's near grid / far slab
+  long t0, t1;
+  long blk0;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather2d_multi(const GatherInst* __restrict__ inst, int n_inst,
+                                                        const cplx<T>* __restrict__ grid,
+                                                        const cplx<T>* __restrict__ far,
+                                                        const double* __restrict__ x, cplx<T>* __restrict__ out,
+                                                        uint8_t* __restrict__ flags) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].blk0 <= (long)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const GatherInst I = inst[lo];
+  const long i = I.t0 + ((long)blockIdx.x - I.blk0) * blockDim.x + threadIdx.x;
+  if (i < I.t1) gather2d_one<T>(I.A, grid + I.off, far + I.foff, x, i, out, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -770,6 +802,53 @@ hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
     P.bin_keycap = nkeys;
   }
   return hipSuccess;
+}
+
+void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long t0, long t1, long blk0,
+                    void* dst) {
+  GatherInst I;
+  GArgs& A = I.A;
+  A.k = k;
+  A.a1 = a;
+  A.a2 = 0.0;
+  A.c = P.p.c;
+  A.c_tilde = P.p.c_tilde;
+  A.eps = P.p.eps;
+  A.rmin = P.p.lattice_rmin;
+  A.M1 = M1;
+  A.M2 = P.M2;
+  A.M3 = 1;
+  A.h1 = kPi / (M1 / 2);
+  A.h2 = P.p.c_tilde / (P.M2 / 2);
+  A.h3 = 0.0;
+  A.ih1 = 1.0 / A.h1;
+  A.ih2 = 1.0 / A.h2;
+  A.ih3 = 0.0;
+  A.hf = P.p.far_h;
+  A.S = P.S;
+  A.fs = (long)M1 * P.M2;
+  A.ffs = (long)M1 * P.S;
+  I.off = off;
+  I.foff = foff;
+  I.t0 = t0;
+  I.t1 = t1;
+  I.blk0 = blk0;
+  *static_cast<GatherInst*>(dst) = I;
+}
+size_t gather_inst_size() { return sizeof(GatherInst); }
+
+hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, const void* grid,
+                                 const void* far, const double* x, void* out, uint8_t* flags) {
+  const auto* in = static_cast<const GatherInst*>(dinst);
+  if (P.p.prec == QPGF_C128)
+    hipLaunchKernelGGL(k_gather2d_multi<double>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst,
+                       static_cast<const double2*>(grid), static_cast<const double2*>(far), x,
+                       static_cast<double2*>(out), flags);
+  else
+    hipLaunchKernelGGL(k_gather2d_multi<float>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst,
+                       static_cast<const float2*>(grid), static_cast<const float2*>(far), x,
+                       static_cast<float2*>(out), flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {

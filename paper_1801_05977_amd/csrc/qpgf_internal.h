@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,17 @@ __host__ __device__ inline double cut_Y2(double r, double eps) { return -smooth_
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// One batched inverse-FFT segment (see k_fft_multi): `nbatch` transforms of
+// length n = 2^log2n starting at element `off`; transform b starts at
+// (b / b_in) * s_out + (b % b_in) * s_in, elements `es` apart; `tile` transforms
+// per block; the segment's first block is blk0.
+struct FftSeg {
+  long off;
+  int n, log2n;
+  long es, nbatch, b_in, s_in, s_out;
+  int tile;
+  long blk0;
+};
 constexpr int kMaxLog2 = 12;   // m <= 4096
 
 struct Plan {
@@ -135,6 +147,22 @@ struct Plan {
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count
 
+  // FFT tiles chosen by the autotuner: key (n << 2) | rows | c64 << 1
+  std::map<int, int> fft_tiles;
+
+  // batched 2D: instance grids, descriptors, the captured graph
+  void* b_grid = nullptr;
+  void* b_far = nullptr;
+  size_t b_grid_cap = 0, b_far_cap = 0;   // bytes
+  void* b_desc = nullptr;                  // device descriptors
+  void* b_host = nullptr;                  // pinned staging for them
+  size_t b_desc_cap = 0;
+  hipEvent_t b_upload_done = nullptr;
+  hipStream_t b_capture = nullptr;
+  hipGraph_t b_graph = nullptr;
+  hipGraphExec_t b_exec = nullptr;
+  std::vector<int64_t> b_sig;              // n, m1[], t_off[], pointers of the captured graph
+
   // per-kernel timing (qpgf_plan_enable_timing)
   struct Pending { int id; hipEvent_t a, b; };
   bool timing = false;
@@ -169,6 +197,18 @@ hipError_t launch_fill(Plan& P, double k, double a1, double a2);
 hipError_t launch_far(Plan& P, double k, double a1, double a2);
 hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
                       long s_out);
+int fft_tile(const Plan& P, int n, bool rows, long nbatch);
+// batched 2D (one launch per stage for many instances)
+void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long blk0, void* dst);
+size_t fill_inst_size();
+hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base);
+hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base);
+void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long t0, long t1, long blk0,
+                    void* dst);
+size_t gather_inst_size();
+hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, const void* grid,
+                                 const void* far, const double* x, void* out, uint8_t* flags);
+hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, long nblocks, long lds_elems);
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
 

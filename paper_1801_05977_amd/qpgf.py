@@ -44,8 +44,8 @@ class PlanInfo(ctypes.Structure):
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
            "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
-           "qpgf_last_error", "qpgf_version"]
-TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin"]
+           "qpgf_g2d_batched", "qpgf_plan_autotune", "qpgf_last_error", "qpgf_version"]
+TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch"]
 
 _lib = None
 
@@ -77,11 +77,15 @@ def lib():
     L.qpgf_plan_enable_timing.argtypes = [P, ctypes.c_int]
     L.qpgf_plan_get_timing.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+    L.qpgf_g2d_batched.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64), VP, VP, U8P]
+    L.qpgf_plan_autotune.argtypes = [P, ctypes.c_char_p]
     L.qpgf_last_error.restype = ctypes.c_char_p
     L.qpgf_version.restype = ctypes.c_char_p
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
                  "qpgf_prepare_stage", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
-                 "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing"):
+                 "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing", "qpgf_g2d_batched",
+                 "qpgf_plan_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -168,6 +172,26 @@ class Plan:
         else:
             _check(lib().qpgf_maxwell3d(self._h, k, a1, a2, px, T, po, pf))
         return out
+
+    def batched(self, k, alpha, m1, t_off, x, out=None, flags=None):
+        """qpgf_g2d_batched: instances (k[i], alpha[i], m1[i]) own targets x[t_off[i]:t_off[i+1]]."""
+        n = len(k)
+        T = int(t_off[-1])
+        if out is None:
+            out = self.out_tensor(T)
+        arr = lambda ct, v: (ct * len(v))(*v)
+        self._stream()
+        _check(lib().qpgf_g2d_batched(self._h, n, arr(ctypes.c_double, [float(v) for v in k]),
+                                      arr(ctypes.c_double, [float(v) for v in alpha]),
+                                      arr(ctypes.c_int, [int(v) for v in m1]),
+                                      arr(ctypes.c_int64, [int(v) for v in t_off]),
+                                      _ptr(x, torch.float64, "x"), _ptr(out, self.cdtype, "out"),
+                                      _ptr(flags, torch.uint8, "flags")))
+        return out
+
+    def autotune(self, cache_path=None):
+        self._stream()
+        _check(lib().qpgf_plan_autotune(self._h, cache_path.encode() if cache_path else None))
 
     def enable_timing(self, on=True):
         _check(lib().qpgf_plan_enable_timing(self._h, int(on)))

@@ -1,0 +1,73 @@
+"""Batched 2D instances (qpgf_g2d_batched): identical to one plan per instance,
+and at parity with the CPU oracle; graph replay with new (k, alpha); autotuner."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import method
+from paper_1801_05977_amd import qpgf, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qpgf.C128: 1e-10, qpgf.C64: 1e-5}
+
+
+def parity(g, o):
+    s = np.sqrt(np.mean(np.abs(o) ** 2))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), s)))
+
+
+def _instances(n, seed):
+    k, a = workloads.instances_2d(n, seed, k_range=(1.0, 20.0), n2_max=32)
+    return k, a
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_batched_equals_single_instance_plans(prec, tmp_path):
+    M2 = 64
+    m1 = [256, 512, 64, 1024, 128, 256]
+    counts = [3000, 1500, 0, 4000, 2500, 777]
+    t_off = np.concatenate([[0], np.cumsum(counts)])
+    k, a = _instances(len(m1), seed=1)
+    x = workloads.targets(int(t_off[-1]), 2, seed=4)
+    xd = torch.from_numpy(x).cuda()
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, max(m1), M2)
+    flags = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    for rep in range(2):
+        if rep == 1:
+            k, a = _instances(len(m1), seed=2)       # replay of the captured graph, new instances
+        g = P.batched(k, a, m1, t_off, xd, flags=flags).cpu().numpy()
+        f = flags.cpu().numpy()
+        for i, M in enumerate(m1):
+            sl = slice(int(t_off[i]), int(t_off[i + 1]))
+            if counts[i] == 0:
+                continue
+            Pi = qpgf.Plan(qpgf.KIND_G2D, prec, M, M2)
+            fi = torch.empty(counts[i], dtype=torch.uint8, device="cuda")
+            gi = Pi(k[i], a[i], 0.0, xd[sl].contiguous(), flags=fi).cpu().numpy()
+            np.testing.assert_array_equal(g[sl], gi)
+            np.testing.assert_array_equal(f[sl], fi.cpu().numpy())
+            Pi.close()
+        for i in (0, 3):
+            sl = slice(int(t_off[i]), int(t_off[i + 1]))
+            o = method.eval_g2d(k[i], a[i], x[sl], m1[i] // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+            assert parity(g[sl], o) <= TOL[prec], (rep, i)
+    # the autotuner changes only how transforms are grouped into blocks, not results
+    P.autotune(str(tmp_path / "tune.txt"))
+    g2 = P.batched(k, a, m1, t_off, xd).cpu().numpy()
+    np.testing.assert_array_equal(g2, g)
+    assert (tmp_path / "tune.txt").read_text().count("\n") >= 1
+
+
+def test_batched_rejects_bad_instances():
+    P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C64, 256, 64)
+    x = torch.zeros((10, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(qpgf.QpgfError) as e:
+        P.batched([2.1, 1.3], [0.3, 0.3], [256, 256], [0, 5, 10], x)       # instance 1: Wood anomaly
+    assert e.value.status == 2 and "instance 1" in str(e.value)
+    with pytest.raises(qpgf.QpgfError) as e:
+        P.batched([2.1], [0.3], [512], [0, 10], x)                         # m1 above the plan's
+    assert e.value.status == 4
