@@ -9,6 +9,8 @@ near grid and the far slab (Algorithm 3.1 step 1), and the calculation step
 for all 1e7 targets (step 2), with targets already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec c64|c128]
+    python bench.py --workload batched2d     # 64 2D instances, uneven x1 sizes, 1e6 targets each
+    python bench.py --workload maxwell3d     # Maxwell tensor, 512 x 512 modes, 32 slices, 1e6 targets
 
 Prints one JSON line.  The per-kernel durations behind ``roofline`` are HIP
 events recorded by the library on the stream its kernels run on.
@@ -81,6 +83,7 @@ def main():
     ap.add_argument("--modes", default="256,256,64")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d"], default="gd3d")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -93,6 +96,12 @@ def main():
     import torch
     from paper_1801_05977_amd import qpgf, workloads
 
+    if args.workload == "batched2d":
+        print(json.dumps(run_batched2d(args)), flush=True)
+        return
+    if args.workload == "maxwell3d":
+        print(json.dumps(run_maxwell3d(args)), flush=True)
+        return
     m1, m2, m3 = (int(v) for v in args.modes.split(","))
     T = args.targets
     prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
@@ -170,6 +179,78 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_batched2d(args):
+    """64 instances k ~ U[1,20], alpha ~ U[-0.5,0.5] (Wood and special cases rejected),
+    x1 sizes 256 * 2^U{0..3}, 128 transverse slices, 1e6 targets each, complex64."""
+    import numpy as np
+    import torch
+    from paper_1801_05977_amd import qpgf, workloads
+    n, per, M2 = 64, 1_000_000, 128
+    k, a = workloads.instances_2d(n, seed=1, k_range=(1.0, 20.0), n2_max=M2 // 2)
+    m1 = [int(256 << v) for v in np.random.default_rng(1).integers(0, 4, n)]
+    t_off = np.arange(n + 1, dtype=np.int64) * per
+    x = torch.from_numpy(workloads.targets(n * per, 2, seed=1)).cuda()
+    prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, max(m1), M2)
+    P.autotune(os.path.join(os.environ.get("TMPDIR", "/tmp"), "qpgf_tune.txt"))
+    out = P.out_tensor(n * per)
+    t_batched = _timed(lambda: P.batched(k, a, m1, t_off, x, out), args.steps, args.warmup)
+    # the same work as a loop of single-instance calls (one plan per x1 size)
+    plans = {M: qpgf.Plan(qpgf.KIND_G2D, prec, M, M2) for M in sorted(set(m1))}
+    for p_ in plans.values():
+        p_.autotune(os.path.join(os.environ.get("TMPDIR", "/tmp"), "qpgf_tune.txt"))
+    xs = [x[i * per:(i + 1) * per] for i in range(n)]
+    outs = [out[i * per:(i + 1) * per] for i in range(n)]
+
+    def loop():
+        for i in range(n):
+            plans[m1[i]](k[i], a[i], 0.0, xs[i], outs[i])
+    t_loop = _timed(loop, max(1, args.steps // 2), 1)
+    T = n * per
+    return {"metric": "Green's evals/sec, batched 2D instances", "value": T / t_batched, "unit": "evals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batched * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+            "data": "synthetic",
+            "config": {"workload": "g2d batched: 64 instances k~U[1,20] alpha~U[-0.5,0.5]",
+                       "x1_modes": sorted(set(m1)), "slices": M2, "targets": T, "method": "batched+graph"},
+            "loop_of_single_instances": {"value": T / t_loop, "ms_per_step": t_loop * 1e3}}
+
+
+def run_maxwell3d(args):
+    """Maxwell tensor: k = 5.3, alpha = (0.1, 0.4), 512 x 512 modes, 32 slices, 1e6 targets, complex64."""
+    import torch
+    from paper_1801_05977_amd import qpgf, workloads
+    T = 1_000_000
+    x = torch.from_numpy(workloads.targets(T, 3, seed=3)).cuda()
+    prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
+    P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, 512, 512, 32)
+    out = P.out_tensor(T)
+    t = _timed(lambda: P(5.3, 0.1, 0.4, x, out), args.steps, args.warmup)
+    P.enable_timing(True)
+    for _ in range(args.steps):
+        P(5.3, 0.1, 0.4, x, out)
+    torch.cuda.synchronize()
+    kern = {k_: round(v[0] / v[1], 5) for k_, v in P.timing().items() if v[1]}
+    return {"metric": "Maxwell tensor evals/sec (6 components)", "value": T / t, "unit": "evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+            "config": {"workload": "maxwell3d k=5.3 alpha=(0.1,0.4)", "modes": [512, 512], "slices": 32,
+                       "targets": T, "method": "plain"},
+            "kernels_avg_ms": kern}
 
 
 if __name__ == "__main__":

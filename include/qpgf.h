@@ -74,8 +74,8 @@ typedef enum {
 /* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
  * size per axis: m1 = 2 N1 modes in x1; 2D: m2 = 2 N2 transverse (x2) modes;
  * 3D: m2 = 2 N2 modes in x2 and m3 = 2 N3 transverse (x3) modes.  Each must be
- * a power of two in [16, 4096] (m3 unused in 2D); with complex128 at most 2048,
- * and axes transformed as columns (2D: m2; 3D: m2, m3) at most half the limit.  Grid spacing: pi/N1, pi/N2
+ * a power of two in [16, 4096] (m3 unused in 2D); with complex128 the axes
+ * transformed as columns (2D: m2; 3D: m2, m3) at most 2048.  Grid spacing: pi/N1, pi/N2
  * (3D) and c_tilde/N_t in the transverse direction.
  * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
  * eps = 0.2, cut-offs: C^8 smoothstep I_u(9,9) transitions (Section 6 states C^8),

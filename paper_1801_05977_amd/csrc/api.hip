@@ -111,11 +111,11 @@ qpgf_status validate(const qpgf_params* p) {
     return fail(QPGF_E_SIZE, "m3 must be a power of two in [16, 4096]");
   {
     // one transform of the longest axis must fit the 64 KiB LDS of a block (two buffers)
-    // rows (x1) up to lim; column axes (x2, and x3 in 3D) have padded LDS rows: up to lim / 2
-    const int lim = p->prec == QPGF_C128 ? 2048 : 4096;
+    // one transform (padded for column axes) must fit the 64 KiB LDS buffer of a block
+    const int lim = p->prec == QPGF_C128 ? 4096 : 8192;
     const bool bad = p->m1 > lim || p->m2 > lim / 2 || (p->kind != QPGF_KIND_G2D && p->m3 > lim / 2);
     if (bad)
-      return fail(QPGF_E_SIZE, "m1 <= 2048 (complex128) / 4096 (complex64); m2, m3 at most half of that");
+      return fail(QPGF_E_SIZE, "m1 <= 4096; complex128 column axes (m2, and m3 in 3D) <= 2048");
   }
   if (!(p->c > 0.0) || !(p->c_tilde > p->c)) return fail(QPGF_E_ARG, "need 0 < c < c_tilde");
   if (!(p->eps > 0.0) || !(2.0 * p->eps <= p->c_tilde)) return fail(QPGF_E_ARG, "need 0 < 2 eps <= c_tilde");
@@ -612,8 +612,8 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   Lo.segT_blocks = tb;
   Lo.segR_blocks = rrb;
   Lo.segF_blocks = frb;
-  // LDS of one k_fft_multi launch: two buffers for its largest tile * (n + 1)
-  if ((size_t)2 * std::max(Lo.lds_T, std::max(Lo.lds_R, Lo.lds_F)) * P.esize > 65536)
+  // LDS of one k_fft_multi launch: one in-place buffer for its largest tile * pitch
+  if ((size_t)std::max(Lo.lds_T, std::max(Lo.lds_R, Lo.lds_F)) * P.esize > 65536)
     return fail(QPGF_E_SIZE, "FFT tile choice exceeds the LDS of one block");
   const hipStream_t user = P.stream;
   HIP_TRY(hipMemcpyAsync(P.b_desc, P.b_host, Lo.bytes, hipMemcpyHostToDevice, user));
@@ -727,7 +727,7 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
     int best = 0;
     double best_us = 1e30;
     for (int tile = 1; tile <= 64; tile <<= 1) {
-      if (tile > s.batch || (size_t)2 * tile * (s.n + (s.rows ? 0 : 1)) * P.esize > 65536) break;
+      if (tile > s.batch || (size_t)tile * (s.n + (s.rows ? 0 : 1)) * P.esize > 65536) break;
       P.fft_tiles[mkey] = tile;
       // rows: batches contiguous; cols: element stride = batch count, adjacent batches
       const long es = s.rows ? 1 : s.batch;

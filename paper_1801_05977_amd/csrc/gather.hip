@@ -308,7 +308,9 @@ __global__ __launch_bounds__(256) void k_gather3d_tiled(GArgs A, TileArgs B, con
   constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
   __shared__ cplx<T> lds[NF * FSZ];
   constexpr int NO = (NF == 1) ? 1 : 6;
-  const int key = (int)xcd_block();
+  // far tiles (more targets each, keys >= nnear) first, then near tiles; blocks go
+  // round-robin over the XCDs so every XCD gets the same mix
+  const int key = B.nkeys - 1 - (int)blockIdx.x;
   const uint32_t cnt = hist[key];
   if (cnt == 0) return;
   const long start = offs[key];
@@ -711,12 +713,19 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   B.M2 = P.M2;
   B.M3 = P.M3;
   B.S = P.S;
-  // tile edges: 8 nodes per axis, fewer where the staged footprint of the
-  // Maxwell fields would not fit in 64 KiB of LDS
+  // tile edges: 16 x 16 x 8 nodes for one field; for the seven Maxwell fields
+  // 8 x 8 x 4 (complex64) or 8 x 4 x 4 (complex128) so the staged footprint fits
+  // in 64 KiB of LDS.  Must match the instantiations of k_gather3d_tiled below.
   TileArgs& Tl = B.t;
-  Tl.tb1 = 3;   // must match the instantiations of k_gather3d_tiled below
-  Tl.tb2 = (P.nf == 7 && sizeof(T) == 8) ? 2 : 3;
-  Tl.tb3 = (P.nf == 7) ? 2 : 3;
+  if (P.nf == 7) {
+    Tl.tb1 = 3;
+    Tl.tb2 = sizeof(T) == 8 ? 2 : 3;
+    Tl.tb3 = 2;
+  } else {
+    Tl.tb1 = 4;
+    Tl.tb2 = 4;
+    Tl.tb3 = 3;
+  }
   Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
   Tl.nt2 = std::max(1, P.M2 >> Tl.tb2);
   Tl.nt3n = std::max(1, P.M3 >> Tl.tb3);
@@ -757,7 +766,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     if (sizeof(T) == 8) QPGF_TILED(7, 3, 2, 2);
     else QPGF_TILED(7, 3, 3, 2);
   } else {
-    QPGF_TILED(1, 3, 3, 3);
+    QPGF_TILED(1, 4, 4, 3);
   }
 #undef QPGF_TILED
   if (P.nf == 7)
