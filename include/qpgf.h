@@ -171,6 +171,55 @@ qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const double* k, const
  * re-timed.  Synchronous; call after plan creation. */
 qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_path);
 
+/* The interpolated smooth part L_N(t) of Algorithm 3.1 step 2d (K_d minus the
+ * singular part F, without the phase) at T targets of the last prepared GD3D
+ * instance; NaN for far targets (|x3| > c).  out: device complex [T] in the plan
+ * precision.  Training data for the surrogate below. */
+qpgf_status qpgf_evaluate_smooth(qpgf_plan* plan, const double* x, int64_t T, void* out);
+
+/* MLP surrogate of the smooth part L_d(x; k, alpha1, alpha2) of G_d in the near
+ * region |x3| <= 0.6 (c = 0.6, c~ = 1).  Architecture: 64 input features of
+ * (x1, x2, x3, k, alpha1, alpha2) (harmonics of the reduced coordinates and of
+ * k x, alpha x), four hidden layers of 256 with GELU, a 2-output head (Re, Im of
+ * 10 L_d).  Hidden layers run on the matrix cores with bf16 operands and fp32
+ * accumulation; parameters, gradients and Adam moments are fp32.  `members`
+ * independently initialised networks form an ensemble whose spread is the error
+ * estimate.  Queries q are device float64 [B][6] rows (x1, x2, x3, k, alpha1,
+ * alpha2).  Parameters are a flat float32 vector of qpgf_mlp_param_count()
+ * entries per member: W0 [256][64], b0, W1 [256][256], b1, W2, b2, W3, b3,
+ * W4 [2][256], b4 (row-major; layer l computes z = W a + b). */
+typedef struct qpgf_mlp qpgf_mlp;
+long qpgf_mlp_param_count(void);
+qpgf_status qpgf_mlp_create(int members, int64_t max_batch, uint64_t seed, qpgf_mlp** out);
+void qpgf_mlp_destroy(qpgf_mlp* m);
+qpgf_status qpgf_mlp_set_stream(qpgf_mlp* m, void* hip_stream);
+qpgf_status qpgf_mlp_get_params(qpgf_mlp* m, int member, float* dst);       /* device [param_count] */
+qpgf_status qpgf_mlp_set_params(qpgf_mlp* m, int member, const float* src); /* device [param_count] */
+/* y: device float32 [B][2], the network output (10 L_d) for member `member`. */
+qpgf_status qpgf_mlp_forward(qpgf_mlp* m, int member, const double* q, int64_t B, float* y);
+/* Gradient of 0.5 mean_b |net(q_b) - y_b|^2 into grad (device [param_count]) and the
+ * loss into loss (device float, may be NULL); B a multiple of 64, <= max_batch. */
+qpgf_status qpgf_mlp_gradient(qpgf_mlp* m, int member, const double* q, const float* y, int64_t B, float* grad,
+                              float* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss. */
+qpgf_status qpgf_mlp_train_step(qpgf_mlp* m, int member, const double* q, const float* y, int64_t B, float lr,
+                                float* loss);
+const char* qpgf_mlp_last_error(void);
+/* G_d from the surrogate for n_inst instances (host k, a1, a2, t_off as in
+ * qpgf_g2d_batched; device targets x [t_off[n]][3]) with fallback: a target takes
+ * the plain method (the GD3D plan `plan`, whose precision sets out's type) when it
+ * is far (|x3| > 0.6, flag 2), when the ensemble spread of L_d exceeds tol (flag 4),
+ * when its instance is within wood_tol of a Wood anomaly (flag 8), or within
+ * rmin of a lattice point (flag 16).  fell_back: device uint8 [T] of those flags
+ * (0 = surrogate value); *n_fallback (host, may be NULL) receives their count.
+ * Synchronises the model's stream once (to size the fallback work) and sets the
+ * plan's stream to the model's.  Errors: E_ARG (NULLs, plan not GD3D or not
+ * c = 0.6, c~ = 1), E_WOOD/E_SPECIAL from the plain method on a fallback instance
+ * (message names the instance), E_HIP/E_NOMEM. */
+qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double wood_tol, double rmin, int n_inst,
+                                const double* k, const double* a1, const double* a2, const int64_t* t_off,
+                                const double* x, void* out, uint8_t* fell_back, int64_t* n_fallback);
+
 /* Stage outputs for parity checks.  qpgf_prepare_stage runs the preparation only
  * up to `stage`: 0 = coefficient fill (A L-hat_j with A the basis normalisation
  * 1/(2 sqrt(pi c~)) in 2D, 1/sqrt(8 pi^2 c~) in 3D, in FFT order: index j mod m

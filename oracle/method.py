@@ -427,6 +427,27 @@ def evaluate_3d(st, x):
     return out
 
 
+def smooth_3d(st, x):
+    """The interpolated smooth part L_N(t) of Algorithm 3.1 step 2d at targets x [T,3] (near
+    branch, |x3| <= c; NaN elsewhere), without the phase e^{i alpha.x'} or the add-back."""
+    c, c_tilde = st["c"], st["c_tilde"]
+    N1, N2, N3 = st["N"]
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    M1, M2, M3 = 2 * N1, 2 * N2, 2 * N3
+    h1, h2, h3 = math.pi / N1, math.pi / N2, c_tilde / N3
+    t1, _ = _reduce(x[:, 0])
+    t2, _ = _reduce(x[:, 1])
+    x3 = x[:, 2]
+    out = np.full(len(x), np.nan + 0j)
+    near = np.abs(x3) <= c
+    if near.any():
+        i1, w1 = _stencil((t1[near] + math.pi) / h1, M1)
+        i2, w2 = _stencil((t2[near] + math.pi) / h2, M2)
+        i3, w3 = _stencil((x3[near] + c_tilde) / h3, M3)
+        out[near] = _interp3(st["grids"][:1], i1, w1, i2, w2, i3, w3)[0]
+    return out
+
+
 def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
             eps=co.EPS, q=ORACLE_Q):
     """Algorithm 3.1 (G_d, returns [T]) or Algorithm 4.1 (Maxwell, returns [T,6])."""

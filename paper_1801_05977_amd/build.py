@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpgf.so")
-SOURCES = ["api.hip", "fill.hip", "fft.hip", "gather.hip"]
+SOURCES = ["api.hip", "fill.hip", "fft.hip", "gather.hip", "mlp.hip", "surrogate.hip"]
 ARCH = os.environ.get("QPGF_ARCH", "gfx950")
 
 FLAGS = [

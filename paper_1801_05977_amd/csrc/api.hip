@@ -777,6 +777,20 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
 
 extern "C" {
 
+qpgf_status qpgf_evaluate_smooth(qpgf_plan* plan, const double* x, int64_t T, void* out) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, QPGF_KIND_GD3D);
+  if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
+  if (T < 0) return fail(QPGF_E_ARG, "T < 0");
+  if (T == 0) return QPGF_OK;
+  if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
+  if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
+  if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  HIP_TRY(launch_gather_smooth(P, x, T, out));
+  return QPGF_OK;
+}
+
 qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst) {
   g_err.clear();
   qpgf_status st = check_plan(plan, -1);

@@ -22,6 +22,7 @@ struct GArgs {
   double hf;               // far-slab spacing
   int S;                   // far-slab slices
   long fs, ffs;            // field strides (near, far)
+  int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
 };
 
 // cubic Lagrange weights at nodes -1, 0, 1, 2
@@ -124,6 +125,11 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
     fetch(true, (int)q1, (int)q2, (int)q, w1, w2, w3, L);
   } else {
     fl |= 2;
+    if (A.smooth) {
+#pragma unroll
+      for (int o = 0; o < NO; ++o) res[o] = nan2();
+      return;
+    }
     const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
     double s0 = floor(v);
     if (s0 > A.S - 3) {
@@ -135,6 +141,12 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
     s0 = fmax(s0, 1.0);
     lag4(v - s0, w3);
     fetch(false, (int)q1, (int)q2, (int)s0, w1, w2, w3, L);
+  }
+  if (A.smooth) {
+    // the smooth part L_N(t) of Algorithm 3.1 step 2d (near branch only)
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = L[o < NF ? o : 0];
+    return;
   }
   double ps, pc;
   sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
@@ -659,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __r
 }
 
 template <typename T>
-hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {
+hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags, int smooth = 0) {
   GArgs A;
   A.k = P.last_k;
   A.a1 = P.last_a1;
@@ -686,10 +698,16 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.S = P.S;
   A.fs = (long)P.ncell;
   A.ffs = (long)P.nfar;
+  A.smooth = smooth;
   const auto* g = static_cast<const cplx<T>*>(P.grid);
   const auto* f = static_cast<const cplx<T>*>(P.far);
   auto* o = static_cast<cplx<T>*>(out);
   const dim3 grid((unsigned)((T_ + 255) / 256));
+  if (smooth) {
+    KernelTimer t(P, QPGF_T_GATHER);
+    hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    return hipGetLastError();
+  }
   if (P.dim == 2) {
     KernelTimer t(P, QPGF_T_GATHER);
     hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
@@ -837,6 +855,7 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.S = P.S;
   A.fs = (long)M1 * P.M2;
   A.ffs = (long)M1 * P.S;
+  A.smooth = 0;
   I.off = off;
   I.foff = foff;
   I.t0 = t0;
@@ -858,6 +877,12 @@ hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nb
                        static_cast<const float2*>(grid), static_cast<const float2*>(far), x,
                        static_cast<float2*>(out), flags);
   return hipGetLastError();
+}
+
+hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T_, void* out) {
+  if (T_ <= 0) return hipSuccess;
+  return P.p.prec == QPGF_C128 ? gather_impl<double>(P, x, T_, out, nullptr, 1)
+                               : gather_impl<float>(P, x, T_, out, nullptr, 1);
 }
 
 hipError_t launch_gather(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {

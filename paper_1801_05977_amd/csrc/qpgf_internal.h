@@ -211,5 +211,6 @@ hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nb
 hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, long nblocks, long lds_elems);
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
+hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
 
 }  // namespace qpgf

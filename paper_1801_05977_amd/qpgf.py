@@ -44,7 +44,10 @@ class PlanInfo(ctypes.Structure):
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
            "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
-           "qpgf_g2d_batched", "qpgf_plan_autotune", "qpgf_last_error", "qpgf_version"]
+           "qpgf_g2d_batched", "qpgf_plan_autotune", "qpgf_last_error", "qpgf_version", "qpgf_evaluate_smooth",
+           "qpgf_mlp_param_count", "qpgf_mlp_create", "qpgf_mlp_destroy", "qpgf_mlp_set_stream",
+           "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
+           "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch"]
 
 _lib = None
@@ -82,10 +85,28 @@ def lib():
     L.qpgf_plan_autotune.argtypes = [P, ctypes.c_char_p]
     L.qpgf_last_error.restype = ctypes.c_char_p
     L.qpgf_version.restype = ctypes.c_char_p
+    L.qpgf_evaluate_smooth.argtypes = [P, VP, I64, VP]
+    L.qpgf_mlp_param_count.argtypes = []
+    L.qpgf_mlp_param_count.restype = ctypes.c_long
+    L.qpgf_mlp_create.argtypes = [ctypes.c_int, I64, ctypes.c_uint64, ctypes.POINTER(P)]
+    L.qpgf_mlp_destroy.argtypes = [P]
+    L.qpgf_mlp_destroy.restype = None
+    L.qpgf_mlp_set_stream.argtypes = [P, VP]
+    L.qpgf_mlp_get_params.argtypes = [P, ctypes.c_int, VP]
+    L.qpgf_mlp_set_params.argtypes = [P, ctypes.c_int, VP]
+    L.qpgf_mlp_forward.argtypes = [P, ctypes.c_int, VP, I64, VP]
+    L.qpgf_mlp_gradient.argtypes = [P, ctypes.c_int, VP, VP, I64, VP, VP]
+    L.qpgf_mlp_train_step.argtypes = [P, ctypes.c_int, VP, VP, I64, ctypes.c_float, VP]
+    L.qpgf_mlp_last_error.restype = ctypes.c_char_p
+    DP = ctypes.POINTER(ctypes.c_double)
+    L.qpgf_surrogate_eval.argtypes = [P, P, D, D, D, ctypes.c_int, DP, DP, DP, ctypes.POINTER(ctypes.c_int64), VP,
+                                      VP, U8P, ctypes.POINTER(ctypes.c_int64)]
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
                  "qpgf_prepare_stage", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
                  "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing", "qpgf_g2d_batched",
-                 "qpgf_plan_autotune"):
+                 "qpgf_plan_autotune", "qpgf_evaluate_smooth", "qpgf_mlp_create", "qpgf_mlp_set_stream",
+                 "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
+                 "qpgf_mlp_train_step", "qpgf_surrogate_eval"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -94,6 +115,11 @@ def lib():
 def _check(status):
     if status != 0:
         raise QpgfError(status, lib().qpgf_last_error().decode())
+
+
+def _check_mlp(status):
+    if status != 0:
+        raise QpgfError(status, lib().qpgf_mlp_last_error().decode())
 
 
 def default_params(kind, prec, m1, m2, m3=0, **overrides):
@@ -189,6 +215,15 @@ class Plan:
                                       _ptr(flags, torch.uint8, "flags")))
         return out
 
+    def smooth(self, x, out=None):
+        """qpgf_evaluate_smooth: the interpolated smooth part L_N at x (GD3D, after prepare)."""
+        T = x.shape[0]
+        if out is None:
+            out = torch.empty((T,), dtype=self.cdtype, device="cuda")
+        self._stream()
+        _check(lib().qpgf_evaluate_smooth(self._h, _ptr(x, torch.float64, "x"), T, _ptr(out, self.cdtype, "out")))
+        return out
+
     def autotune(self, cache_path=None):
         self._stream()
         _check(lib().qpgf_plan_autotune(self._h, cache_path.encode() if cache_path else None))
@@ -224,3 +259,83 @@ def gd3d(k, a1, a2, x, m1, m2, m3, prec=C128, **kw):
 
 def maxwell3d(k, a1, a2, x, m1, m2, m3, prec=C128, **kw):
     return Plan(KIND_MAXWELL3D, prec, m1, m2, m3, **kw)(k, a1, a2, x)
+
+
+class Mlp:
+    """Ensemble MLP surrogate of the smooth part L_d (qpgf_mlp_*), on torch's current stream."""
+
+    def __init__(self, members=1, max_batch=65536, seed=0):
+        torch.cuda.init()
+        self._h = ctypes.c_void_p()
+        _check_mlp(lib().qpgf_mlp_create(members, max_batch, seed, ctypes.byref(self._h)))
+        self.members, self.max_batch = members, max_batch
+        self.n_params = lib().qpgf_mlp_param_count()
+
+    def close(self):
+        if self._h:
+            lib().qpgf_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        _check_mlp(lib().qpgf_mlp_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def params(self, member=0):
+        dst = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_get_params(self._h, member, _ptr(dst, torch.float32, "dst")))
+        return dst
+
+    def set_params(self, p, member=0):
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_set_params(self._h, member, _ptr(p, torch.float32, "src")))
+
+    def forward(self, q, member=0):
+        y = torch.empty((q.shape[0], 2), dtype=torch.float32, device="cuda")
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_forward(self._h, member, _ptr(q, torch.float64, "q"), q.shape[0],
+                                          _ptr(y, torch.float32, "y")))
+        return y
+
+    def gradient(self, q, y, member=0):
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_gradient(self._h, member, _ptr(q, torch.float64, "q"), _ptr(y, torch.float32, "y"),
+                                           q.shape[0], _ptr(g, torch.float32, "grad"),
+                                           _ptr(loss, torch.float32, "loss")))
+        return g, loss
+
+    def train_step(self, q, y, lr, member=0, loss=None):
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_train_step(self._h, member, _ptr(q, torch.float64, "q"),
+                                             _ptr(y, torch.float32, "y"), q.shape[0], float(lr),
+                                             _ptr(loss, torch.float32, "loss")))
+
+    def evaluate(self, plan, k, a1, a2, t_off, x, tol, wood_tol=1e-3, rmin=1e-3, out=None, fell_back=None):
+        """qpgf_surrogate_eval: G_d for instances (k[i], a1[i], a2[i]) on x[t_off[i]:t_off[i+1]], falling
+        back to the plain method of `plan` where flagged.  Returns (out, fell_back, n_fallback)."""
+        n = len(k)
+        T = int(t_off[-1])
+        if out is None:
+            out = plan.out_tensor(T)
+        if fell_back is None:
+            fell_back = torch.empty(T, dtype=torch.uint8, device="cuda")
+        arr = lambda ct, v: (ct * len(v))(*v)
+        nf = ctypes.c_int64()
+        self._stream()
+        _check_mlp(lib().qpgf_surrogate_eval(self._h, plan._h, float(tol), float(wood_tol), float(rmin), n,
+                                             arr(ctypes.c_double, [float(v) for v in k]),
+                                             arr(ctypes.c_double, [float(v) for v in a1]),
+                                             arr(ctypes.c_double, [float(v) for v in a2]),
+                                             arr(ctypes.c_int64, [int(v) for v in t_off]),
+                                             _ptr(x, torch.float64, "x"), _ptr(out, plan.cdtype, "out"),
+                                             _ptr(fell_back, torch.uint8, "fell_back"), ctypes.byref(nf)))
+        return out, fell_back, nf.value

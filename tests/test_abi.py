@@ -73,3 +73,21 @@ def test_null_arguments():
     assert L.qpgf_prepare(None, 1.0, 0.1, 0.2) == 1
     assert L.qpgf_evaluate(None, None, 0, None, None) == 1
     assert L.qpgf_version().decode().startswith("qpgf")
+
+
+def test_surrogate_entry_points_validate_before_touching_the_device():
+    import ctypes
+    from oracle import mlp as ref
+    L = qpgf.lib()
+    assert L.qpgf_mlp_param_count() == ref.N_PARAM
+    h = ctypes.c_void_p()
+    assert L.qpgf_mlp_create(0, 64, 0, ctypes.byref(h)) == 1
+    assert L.qpgf_mlp_create(1, 100, 0, ctypes.byref(h)) == 1      # max_batch not a multiple of 64
+    assert L.qpgf_mlp_create(9, 64, 0, ctypes.byref(h)) == 1
+    assert not h.value
+    assert L.qpgf_mlp_forward(None, 0, None, 0, None) == 1
+    assert L.qpgf_mlp_gradient(None, 0, None, None, 64, None, None) == 1
+    assert L.qpgf_mlp_last_error().decode()
+    assert L.qpgf_evaluate_smooth(None, None, 0, None) == 1
+    assert L.qpgf_surrogate_eval(None, None, 0.0, 0.0, 0.0, 0, None, None, None, None, None, None, None,
+                                 None) == 1

@@ -1,0 +1,232 @@
+"""GPU checks of the MLP surrogate of the smooth part L_d (matrix-core network,
+training step, inference with fallback) against the CPU reference network and
+the oracle's plain method.
+
+Bars.  The network takes bfloat16 operands on the matrix cores with float32
+accumulation; the CPU reference rounds the same operands to bfloat16 and does
+everything else in float64.  What is left between them is float32 versus
+float64 accumulation and GELU (relative 1e-6) and the rare bf16 rounding that
+falls the other way because of it (one bf16 ulp, 2^-8 relative, in a handful of
+the 10^5-10^6 rounded values): a few 1e-4 of the output scale.  The bars are
+2e-3 of the output scale for outputs and 2e-3 relative (L2, per parameter
+block) for gradients.  Targets that fall back take the plain method and meet
+its own bar against the oracle (1e-10 in complex128).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import method, mlp
+from paper_1801_05977_amd import qpgf, workloads
+
+pytestmark = pytest.mark.gpu
+
+SCALE = 2e-3
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def parity(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    s = np.sqrt(np.mean(np.abs(o) ** 2))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), s)))
+
+
+def queries(B, seed, zmax=0.6):
+    rng = np.random.default_rng(seed)
+    return np.column_stack([rng.uniform(-7, 7, B), rng.uniform(-7, 7, B), rng.uniform(-zmax, zmax, B),
+                            rng.uniform(1, 10, B), rng.uniform(-0.5, 0.5, B), rng.uniform(-0.5, 0.5, B)])
+
+
+def model(members, max_batch, seed0=20):
+    m = qpgf.Mlp(members, max_batch, seed=1)
+    ps = [mlp.init_params(seed0 + e) for e in range(members)]
+    for e, p in enumerate(ps):
+        m.set_params(dev(p.astype(np.float32)), e)
+    return m, ps
+
+
+def test_param_count_and_roundtrip():
+    m, ps = model(2, 128)
+    assert m.n_params == mlp.N_PARAM
+    for e in range(2):
+        assert np.array_equal(m.params(e).cpu().numpy().astype(np.float64), ps[e])
+
+
+@pytest.mark.parametrize("B", [1, 64, 1000])
+def test_forward_matches_bf16_reference(B):
+    """Ragged batches (padding to 64 rows) and more rows than one pass holds (max_batch 512)."""
+    m, ps = model(2, 512)
+    q = queries(B, 30 + B)
+    for e in range(2):
+        y = m.forward(dev(q), e).cpu().numpy().astype(np.float64)
+        ref, _ = mlp.forward(ps[e], q, bf16_ops=True)
+        assert np.max(np.abs(y - ref)) <= SCALE * np.max(np.abs(ref))
+        ref64, _ = mlp.forward(ps[e], q)
+        assert np.max(np.abs(y - ref64)) <= 3e-2 * np.max(np.abs(ref64))
+
+
+@pytest.mark.parametrize("B", [64, 2048])
+def test_gradient_matches_bf16_reference(B):
+    """B = 2048 splits the weight-gradient products over the batch (partial sums reduced after)."""
+    m, ps = model(1, 4096)
+    q = queries(B, 40 + B)
+    y = np.random.default_rng(41).normal(size=(B, 2)).astype(np.float32)
+    g, loss = m.gradient(dev(q), dev(y))
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(ps[0], q, y.astype(np.float64), bf16_ops=True)
+    assert abs(loss.item() - lref) <= 1e-4 * lref
+    for off, shape in mlp.layout()[0]:
+        n = int(np.prod(shape))
+        a, b = g[off:off + n], gref[off:off + n]
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b), (off, shape)
+
+
+def test_adam_first_step():
+    """Step 1 of Adam with bias correction moves each parameter by lr * g / (|g| + 1e-8)."""
+    m, ps = model(1, 256)
+    B, lr = 256, 1e-3
+    q = queries(B, 50)
+    y = np.random.default_rng(51).normal(size=(B, 2)).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    m.train_step(dev(q), dev(y), lr, loss=loss)
+    p1 = m.params().cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(ps[0], q, y.astype(np.float64), bf16_ops=True)
+    assert abs(loss.item() - lref) <= 1e-4 * lref
+    big = np.abs(gref) > 1e-2 * np.abs(gref).max()
+    step = p1 - ps[0]
+    assert np.max(np.abs(step[big] + lr * np.sign(gref[big]))) <= 2e-3 * lr + 1e-7
+    assert np.max(np.abs(step)) <= lr * (1 + 1e-3) + 1e-7
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_smooth_part_matches_oracle(prec):
+    """qpgf_evaluate_smooth = the interpolated L_N of Algorithm 3.1 step 2d; NaN for far targets."""
+    M1, M2, M3 = 32, 32, 16
+    k, a1, a2 = 4.3, -0.15, 0.4
+    x = workloads.targets(5000, 3, seed=60)
+    P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
+    P.prepare(k, a1, a2)
+    L = P.smooth(dev(x)).cpu().numpy()
+    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    o = method.smooth_3d(st, x)
+    near = np.abs(x[:, 2]) <= 0.6
+    assert np.all(np.isnan(L[~near]))
+    assert parity(L[near], o[near]) <= (1e-10 if prec == qpgf.C128 else 1e-5)
+
+
+def _instances():
+    # instance 2 sits 5e-4 from a Wood anomaly: |alpha + (1, 0)| = 1.25 exactly
+    k = [3.7, 8.2, math.sqrt(1.25 ** 2 + 5e-4 ** 2)]
+    a1 = [0.2, -0.45, 0.2]
+    a2 = [0.35, 0.1, 0.35]
+    return k, a1, a2
+
+
+def _targets(n_inst, per, seed):
+    xs = [workloads.targets(per + 7 * i, 3, seed=seed + i) for i in range(n_inst)]
+    xs[0][5] = (2 * math.pi, 0.0, 0.0)                  # on a lattice point
+    xs[1][9] = (-2 * math.pi + 2e-4, 2 * math.pi, 0.0)  # within rmin of one
+    t_off = np.concatenate([[0], np.cumsum([len(x) for x in xs])])
+    return np.concatenate(xs), t_off
+
+
+def _plain(k, a1, a2, x, t_off, M, far_h, far_S):
+    outs = []
+    for i in range(len(k)):
+        xi = x[t_off[i]:t_off[i + 1]]
+        outs.append(method.eval_gd3d(k[i], a1[i], a2[i], xi, M[0] // 2, M[1] // 2, M[2] // 2, far_h, far_S))
+    return np.concatenate(outs)
+
+
+def test_surrogate_eval_with_fallback():
+    """Accepted targets: G_d from the ensemble mean plus the FP64 add-back, against the CPU reference
+    network; far, near-Wood and near-lattice targets fall back to the plain method, against the oracle."""
+    M = (32, 32, 16)
+    k, a1, a2 = _instances()
+    x, t_off = _targets(3, 3000, 70)
+    T = len(x)
+    m, ps = model(3, 1024)                   # 1024 rows per pass: several passes and a ragged one
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M, wood_tol=1e-5)
+    rmin = 1e-3
+    out, fell, nf = m.evaluate(P, k, a1, a2, t_off, dev(x), tol=1e30, wood_tol=1e-3, rmin=rmin)
+    out, fell = out.cpu().numpy(), fell.cpu().numpy()
+    inst = np.searchsorted(t_off, np.arange(T), side="right") - 1
+    q = np.column_stack([x, np.asarray(k)[inst], np.asarray(a1)[inst], np.asarray(a2)[inst]])
+    t1, _ = method._reduce(x[:, 0])
+    t2, _ = method._reduce(x[:, 1])
+    r = np.sqrt(t1 ** 2 + t2 ** 2 + x[:, 2] ** 2)
+    want = np.where(np.abs(x[:, 2]) > 0.6, 2, 0) | np.where(inst == 2, 8, 0) | np.where(r <= rmin, 16, 0)
+    assert np.array_equal(fell, want)
+    assert nf == int(np.count_nonzero(want))
+    acc = want == 0
+    ys = [mlp.forward(p, q[acc], bf16_ops=True)[0] for p in ps]
+    ym = np.mean(ys, axis=0)
+    L = 0.1 * (ym[:, 0] + 1j * ym[:, 1])
+    G = mlp.g_from_smooth(q[acc], L)
+    assert np.max(np.abs(out[acc] - G)) <= SCALE * np.max(np.abs(L))
+    plain = _plain(k, a1, a2, x, t_off, M, P.info.far_h, P.info.far_slices)
+    fb = ~acc & (r > 0)          # the plan's own lattice_rmin is 0: only r = 0 gives NaN there
+    wood = inst == 2
+    assert parity(out[fb & ~wood], plain[fb & ~wood]) <= 1e-10
+    # 5e-4 from a Wood anomaly the problem is ill-conditioned: a 2e-16 relative change of k moves the
+    # oracle's own result by 9e-7.  There the fallback must equal the plain method of the same plan
+    # exactly, and agree with the oracle to that conditioning.
+    assert parity(out[wood], plain[wood]) <= 1e-5
+    g2 = P(k[2], a1[2], a2[2], dev(x[wood])).cpu().numpy()
+    assert np.array_equal(out[wood], g2)
+    assert np.all(np.isnan(out[r == 0])) and np.count_nonzero(r == 0) == 1
+
+
+def test_surrogate_zero_tolerance_is_the_plain_method():
+    """tol = 0: the ensemble spread exceeds it everywhere, every target takes the plain method and the
+    result equals qpgf_gd3d per instance."""
+    M = (32, 32, 16)
+    k, a1, a2 = _instances()
+    x, t_off = _targets(3, 2000, 80)
+    m, _ = model(2, 4096)
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C64, *M, wood_tol=1e-5)
+    out, fell, nf = m.evaluate(P, k, a1, a2, t_off, dev(x), tol=0.0, wood_tol=1e-3, rmin=1e-3)
+    fell = fell.cpu().numpy()
+    assert nf == len(x) and np.all(fell & 4)
+    out = out.cpu().numpy()
+    for i in range(3):
+        xi = dev(x[t_off[i]:t_off[i + 1]])
+        gi = P(k[i], a1[i], a2[i], xi).cpu().numpy()
+        assert np.array_equal(np.isnan(out[t_off[i]:t_off[i + 1]]), np.isnan(gi))
+        ok = ~np.isnan(gi)
+        assert np.array_equal(out[t_off[i]:t_off[i + 1]][ok], gi[ok])
+
+
+def test_training_on_plain_method_data_reduces_the_loss():
+    """Training data: 10 L_N from qpgf_evaluate_smooth over random instances (k ~ U[1,10], alpha ~ U[-1/2,1/2]^2)."""
+    M = (32, 32, 16)
+    rng = np.random.default_rng(90)
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M)
+    qs, ys = [], []
+    while len(qs) < 8:
+        k, a1, a2 = rng.uniform(1, 10), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5)
+        try:
+            P.prepare(k, a1, a2)
+        except qpgf.QpgfError:
+            continue                                   # Wood anomaly or special case: draw again
+        x = workloads.targets(512, 3, seed=91 + len(qs), zmax=0.6)
+        L = P.smooth(dev(x)).cpu().numpy()
+        qs.append(np.column_stack([x, np.full((512, 3), (k, a1, a2))]))
+        ys.append(np.column_stack([10 * L.real, 10 * L.imag]).astype(np.float32))
+    q, y = dev(np.concatenate(qs)), dev(np.concatenate(ys))
+    m = qpgf.Mlp(1, 4096, seed=3)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for it in range(300):
+        m.train_step(q, y, 1e-3, loss=loss)
+        if it % 50 == 0 or it == 299:
+            hist.append(loss.item())
+    print("loss", hist)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.1 * hist[0]
