@@ -11,6 +11,7 @@ for all 1e7 targets (step 2), with targets already resident in HBM.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec c64|c128]
     python bench.py --workload batched2d     # 64 2D instances, uneven x1 sizes, 1e6 targets each
     python bench.py --workload maxwell3d     # Maxwell tensor, 512 x 512 modes, 32 slices, 1e6 targets
+    python bench.py --workload surrogate     # MLP surrogate vs the plain method, 1e4 instances x 1e4 targets
 
 Prints one JSON line.  The per-kernel durations behind ``roofline`` are HIP
 events recorded by the library on the stream its kernels run on.
@@ -83,7 +84,14 @@ def main():
     ap.add_argument("--modes", default="256,256,64")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d"], default="gd3d")
+    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate"], default="gd3d")
+    ap.add_argument("--train-instances", type=int, default=2000)
+    ap.add_argument("--train-per", type=int, default=8192)
+    ap.add_argument("--train-epochs", type=float, default=4.0)
+    ap.add_argument("--members", type=int, default=3)
+    ap.add_argument("--query-instances", type=int, default=10000)
+    ap.add_argument("--query-per", type=int, default=10000)
+    ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -98,6 +106,9 @@ def main():
 
     if args.workload == "batched2d":
         print(json.dumps(run_batched2d(args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(run_surrogate(args)), flush=True)
         return
     if args.workload == "maxwell3d":
         print(json.dumps(run_maxwell3d(args)), flush=True)
@@ -251,6 +262,141 @@ def run_maxwell3d(args):
             "config": {"workload": "maxwell3d k=5.3 alpha=(0.1,0.4)", "modes": [512, 512], "slices": 32,
                        "targets": T, "method": "plain"},
             "kernels_avg_ms": kern}
+
+
+def _instances_3d(n, seed, k_range=(1.0, 10.0), a_range=(-0.5, 0.5), min_beta=1e-3):
+    """n (k, alpha1, alpha2) with every |k^2 - |alpha + n|^2|^(1/2) >= min_beta (Wood anomalies redrawn)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        k, a1, a2 = rng.uniform(*k_range), rng.uniform(*a_range), rng.uniform(*a_range)
+        j = np.arange(-12, 13)
+        d = k * k - (a1 + j[:, None]) ** 2 - (a2 + j[None, :]) ** 2
+        if np.sqrt(np.abs(d)).min() >= min_beta:
+            out.append((k, a1, a2))
+    return np.array(out)
+
+
+def run_surrogate(args):
+    """MLP surrogate of the smooth part vs the plain method (Algorithm 3.1, 256 x 256 x 64, complex64).
+
+    Training: `train_instances` instances (k ~ U[1,10], alpha ~ U[-1/2,1/2]^2, seed 4) x `train_per`
+    near-region targets, labels 10 L_N from qpgf_evaluate_smooth; Adam with a cosine learning rate, one
+    data order per ensemble member.  Queries: `query_instances` fresh instances (seed 5) x `query_per`
+    targets uniform in [0, 2pi]^2 x [-1, 1]; far, near-lattice and high-spread targets take the plain
+    method.  A step is all queries through qpgf_surrogate_eval; the plain method is timed on the same
+    queries as one qpgf_gd3d call per instance."""
+    import numpy as np
+    import torch
+    from paper_1801_05977_amd import qpgf, workloads
+    M = (256, 256, 64)
+    prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
+    P = qpgf.Plan(qpgf.KIND_GD3D, prec, *M)
+    # ---- training data from the plain method
+    t0 = time.perf_counter()
+    tr = _instances_3d(args.train_instances, seed=4)
+    per = args.train_per
+    xtr = torch.from_numpy(workloads.targets(per * 64, 3, seed=40, zmax=0.6)).cuda()
+    rng = np.random.default_rng(41)
+    q = torch.empty((len(tr) * per, 6), dtype=torch.float64, device="cuda")
+    y = torch.empty((len(tr) * per, 2), dtype=torch.float32, device="cuda")
+    for i, (k, a1, a2) in enumerate(tr):
+        sel = torch.from_numpy(rng.choice(xtr.shape[0], per, replace=False)).cuda()
+        xi = xtr[sel].contiguous()
+        P.prepare(k, a1, a2)
+        L = P.smooth(xi)
+        q[i * per:(i + 1) * per, :3] = xi
+        q[i * per:(i + 1) * per, 3:] = torch.tensor([k, a1, a2], dtype=torch.float64, device="cuda")
+        y[i * per:(i + 1) * per, 0] = 10.0 * L.real.float()
+        y[i * per:(i + 1) * per, 1] = 10.0 * L.imag.float()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    # ---- training
+    B = 16384
+    n = q.shape[0]
+    steps = max(1, int(args.train_epochs * n / B))
+    mdl = qpgf.Mlp(args.members, 65536, seed=7)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    t0 = time.perf_counter()
+    for e in range(args.members):
+        gen.manual_seed(100 + e)
+        perm = torch.randperm(n, device="cuda", generator=gen)
+        pos = 0
+        for s_ in range(steps):
+            if pos + B > n:
+                perm = torch.randperm(n, device="cuda", generator=gen)
+                pos = 0
+            idx = perm[pos:pos + B]
+            pos += B
+            lr = 1e-5 + 0.5 * (2e-3 - 1e-5) * (1 + math.cos(math.pi * s_ / steps))
+            mdl.train_step(q[idx].contiguous(), y[idx].contiguous(), lr, member=e, loss=loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    final_loss = loss.item()
+    del q, y
+    # ---- queries
+    qi = _instances_3d(args.query_instances, seed=5)
+    nq, pq = len(qi), args.query_per
+    T = nq * pq
+    x = torch.from_numpy(workloads.targets(T, 3, seed=5)).cuda()
+    t_off = np.arange(nq + 1, dtype=np.int64) * pq
+    out = P.out_tensor(T)
+    fell = torch.empty(T, dtype=torch.uint8, device="cuda")
+    nfb = [0]
+
+    def surrogate():
+        nfb[0] = mdl.evaluate(P, qi[:, 0], qi[:, 1], qi[:, 2], t_off, x, args.tol, wood_tol=1e-3, rmin=1e-3,
+                              out=out, fell_back=fell)[2]
+    t_s = _timed(surrogate, args.steps, args.warmup)
+    out_plain = P.out_tensor(T)
+
+    def plain():
+        for i in range(nq):
+            P(qi[i, 0], qi[i, 1], qi[i, 2], x[i * pq:(i + 1) * pq], out_plain[i * pq:(i + 1) * pq])
+    t_p = _timed(plain, max(1, args.steps), 1)
+    # forward alone (all members, all queries) for the matrix-core roofline
+    qall = torch.empty((min(T, 65536 * 16), 6), dtype=torch.float64, device="cuda")
+    qall[:, :3] = x[:qall.shape[0]]
+    qall[:, 3:] = torch.tensor(qi[0], dtype=torch.float64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mdl.forward(qall, 0)
+    ev0.record()
+    for e in range(args.members):
+        mdl.forward(qall, e)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_fwd = ev0.elapsed_time(ev1) / 1e3
+    flop_q = 2 * (64 * 256 + 3 * 256 * 256 + 2 * 256)
+    fwd_tflops = flop_q * qall.shape[0] * args.members / t_fwd / 1e12
+    # accuracy of accepted surrogate values against the plain method in complex128 (sample)
+    ref_plan = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M)
+    errs = []
+    fl = fell.cpu().numpy()
+    for i in range(0, nq, max(1, nq // 20)):
+        sl = slice(i * pq, (i + 1) * pq)
+        ref = ref_plan(qi[i, 0], qi[i, 1], qi[i, 2], x[sl]).cpu().numpy()
+        got = out[sl].cpu().numpy().astype(np.complex128)
+        ok = (fl[sl] == 0) & np.isfinite(ref)
+        scale = np.sqrt(np.mean(np.abs(ref[np.isfinite(ref)]) ** 2))
+        errs.append(np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), scale))
+    errs = np.concatenate(errs) if errs else np.zeros(1)
+    return {"metric": "Green's evals/sec, 3D G_d through the MLP surrogate (with fallback)", "value": T / t_s,
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_s * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network, " + args.prec,
+            "data": "synthetic",
+            "config": {"workload": f"gd3d surrogate: {nq} instances x {pq} targets, k~U[1,10] alpha~U[-0.5,0.5]^2",
+                       "modes": [256, 256], "slices": 64, "members": args.members, "tol": args.tol,
+                       "train_samples": int(len(tr) * per), "train_steps_per_member": steps, "batch": B},
+            "fallback_fraction": nfb[0] / T,
+            "plain_method": {"value": T / t_p, "ms_per_step": t_p * 1e3},
+            "gain_vs_plain": t_p / t_s,
+            "accepted_rel_err": {"p50": float(np.percentile(errs, 50)), "p99": float(np.percentile(errs, 99)),
+                                 "max": float(errs.max()), "n": int(errs.size)},
+            "training": {"data_s": t_data, "train_s": t_train, "final_loss": final_loss},
+            "roofline": {"bound": "mfma", "kernel": "forward (all members)", "achieved": fwd_tflops,
+                         "peak": 2500.0, "unit": "TFLOP/s", "frac": fwd_tflops / 2500.0, "traffic": None}}
 
 
 if __name__ == "__main__":
