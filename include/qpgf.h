@@ -247,9 +247,11 @@ typedef enum {
   QPGF_T_FAR = 5,      /* far-slab coefficient fill                              */
   QPGF_T_FAR_FFT = 6,  /* inverse FFTs of the far slab                           */
   QPGF_T_GATHER = 7,   /* interpolation gather, add-back and phase               */
-  QPGF_T_BIN = 8,      /* target binning by grid tile (key, scan, scatter)       */
+  QPGF_T_BIN = 8,      /* target binning by grid tile: counts and offset scans   */
   QPGF_T_BATCH = 9,    /* one replay of the batched 2D graph (all stages)        */
-  QPGF_T_COUNT = 10
+  QPGF_T_BIN_PLACE = 10, /* binning: scatter of target records into tile order   */
+  QPGF_T_OVERFLOW = 11,  /* targets handed over by the tiled gather              */
+  QPGF_T_COUNT = 12
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
 qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches);

@@ -25,13 +25,15 @@ struct GArgs {
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
 };
 
-// cubic Lagrange weights at nodes -1, 0, 1, 2
-__device__ __forceinline__ void lag4(double f, double w[4]) {
-  const double fm1 = f - 1.0, fm2 = f - 2.0, fp1 = f + 1.0;
-  w[0] = -f * fm1 * fm2 * (1.0 / 6.0);
-  w[1] = fp1 * fm1 * fm2 * 0.5;
-  w[2] = -fp1 * f * fm2 * 0.5;
-  w[3] = fp1 * f * fm1 * (1.0 / 6.0);
+// cubic Lagrange weights at nodes -1, 0, 1, 2 (W = float on the complex64
+// path: the fraction is formed in FP64, the weights in FP32)
+template <typename W>
+__device__ __forceinline__ void lag4(W f, W w[4]) {
+  const W fm1 = f - W(1), fm2 = f - W(2), fp1 = f + W(1);
+  w[0] = -f * fm1 * fm2 * W(1.0 / 6.0);
+  w[1] = fp1 * fm1 * fm2 * W(0.5);
+  w[2] = -fp1 * f * fm2 * W(0.5);
+  w[3] = fp1 * f * fm1 * W(1.0 / 6.0);
 }
 
 // x = 2 pi n + t, t in [-pi, pi) (up to rounding at the cell edge, where the
@@ -71,8 +73,8 @@ struct GlobalFetch {
   const cplx<T>* far;
   long fs, ffs;
   int M1, M2, M3;
-  __device__ void operator()(bool near, int p1, int p2, int p3, const double w1[4], const double w2[4],
-                             const double w3[4], double2 L[NF]) const {
+  __device__ void operator()(bool near, int p1, int p2, int p3, const T w1[4], const T w2[4], const T w3[4],
+                             double2 L[NF]) const {
     const cplx<T>* g = near ? grid : far;
     const long st = near ? fs : ffs;
     Acc<T> acc[NF];
@@ -82,10 +84,10 @@ struct GlobalFetch {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const long row = (i3 * M2 + ((p2 - 1 + b) & (M2 - 1))) * (long)M1;
-        const T wcb = (T)(w3[c] * w2[b]);
+        const T wcb = w3[c] * w2[b];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const T w = wcb * (T)w1[a];
+          const T w = wcb * w1[a];
           const long o = row + ((p1 - 1 + a) & (M1 - 1));
 #pragma unroll
           for (int f = 0; f < NF; ++f) acc[f].add(w, g[f * st + o]);
@@ -112,16 +114,16 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
   }
   double n1, n2;
   const double t1 = reduce_cell(x1, n1), t2 = reduce_cell(x2, n2);
-  double w1[4], w2[4], w3[4];
+  T w1[4], w2[4], w3[4];
   const double u1 = t1 * A.ih1, q1 = floor(u1);
-  lag4(u1 - q1, w1);
+  lag4<T>((T)(u1 - q1), w1);
   const double u2 = t2 * A.ih2, q2 = floor(u2);
-  lag4(u2 - q2, w2);
+  lag4<T>((T)(u2 - q2), w2);
   double2 L[NF];
   const bool is_near = fabs(x3) <= A.c;
   if (is_near) {
     const double u = x3 * A.ih3, q = floor(u);
-    lag4(u - q, w3);
+    lag4<T>((T)(u - q), w3);
     fetch(true, (int)q1, (int)q2, (int)q, w1, w2, w3, L);
   } else {
     fl |= 2;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
       return;
     }
     s0 = fmax(s0, 1.0);
-    lag4(v - s0, w3);
+    lag4<T>((T)(v - s0), w3);
     fetch(false, (int)q1, (int)q2, (int)s0, w1, w2, w3, L);
   }
   if (A.smooth) {
@@ -162,12 +164,14 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
     }
   }
   if (is_near) {
-    const double r = sqrt(t1 * t1 + t2 * t2 + x3 * x3);
-    if (r <= A.rmin || r == 0.0) {
+    // the square root only inside the support of the singular part
+    const double r2 = t1 * t1 + t2 * t2 + x3 * x3;
+    if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
       fl |= 1;
 #pragma unroll
       for (int f = 0; f < NF; ++f) G[f] = nan2();
-    } else if (r < 2.0 * A.eps) {
+    } else if (r2 < 4.0 * A.eps * A.eps) {
+      const double r = sqrt(r2);
       // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
       double sn, cn;
       sincos(A.k * r, &sn, &cn);
@@ -265,8 +269,8 @@ struct LdsFetch {
   bool near_tile;
   int M1, M2, M3;
   mutable bool miss;
-  __device__ void operator()(bool near, int p1, int p2, int p3, const double w1[4], const double w2[4],
-                             const double w3[4], double2 L[NF]) const {
+  __device__ void operator()(bool near, int p1, int p2, int p3, const T w1[4], const T w2[4], const T w3[4],
+                             double2 L[NF]) const {
     const int l1 = (p1 - 1 - o1) & (M1 - 1), l2 = (p2 - 1 - o2) & (M2 - 1);
     const int l3 = near ? ((p3 - 1 - o3) & (M3 - 1)) : (p3 - 1 - o3);
     if (near != near_tile || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4) {
@@ -275,13 +279,9 @@ struct LdsFetch {
     }
     constexpr int FSZ = F1 * F2 * F3;
     const cplx<T>* base = lds + (l3 * F2 + l2) * F1 + l1;
-    T a1[4], a2[4], a3[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      a1[a] = (T)w1[a];
-      a2[a] = (T)w2[a];
-      a3[a] = (T)w3[a];
-    }
+    const T* a1 = w1;
+    const T* a2 = w2;
+    const T* a3 = w3;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       T accx = 0, accy = 0;
@@ -309,8 +309,8 @@ struct LdsFetch {
   }
 };
 
-template <typename T, int NF, int TB1, int TB2, int TB3>
-__global__ __launch_bounds__(256) void k_gather3d_tiled(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+template <typename T, int NF, int TB1, int TB2, int TB3, int BS>
+__global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
                                                         const cplx<T>* __restrict__ far,
                                                         const TRec* __restrict__ rec,
                                                         const uint32_t* __restrict__ hist,
@@ -368,20 +368,27 @@ __global__ __launch_bounds__(256) void k_gather3d_tiled(GArgs A, TileArgs B, con
     lds[idx] = v;
   }
   __syncthreads();
-  for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
-    const TRec r = rec[j];
+  // the next record is loaded before the current one is evaluated
+  const long end = start + (long)cnt;
+  long j = start + threadIdx.x;
+  TRec r{};
+  if (j < end) r = rec[j];
+  for (; j < end; j += BS) {
+    TRec rn = r;
+    if (j + BS < end) rn = rec[j + BS];
     double2 res[NO];
     uint8_t fl;
     lf.miss = false;
     eval3d_target<T, NF>(A, r.x, r.y, r.z, lf, res, fl);
     if (lf.miss) {
       ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
-      continue;
-    }
-    const long i = r.i;
+    } else {
+      const long i = r.i;
 #pragma unroll
-    for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
-    if (flags) flags[i] = fl;
+      for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
+      if (flags) flags[i] = fl;
+    }
+    r = rn;
   }
 }
 
@@ -607,29 +614,46 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ 
 //  (4) each block re-derives its keys and scatters its targets to
 //      offs[key] + cnt[block][key] + (LDS-atomic rank within the block).
 constexpr int kBinBlocks = 256;
-constexpr int kBinLdsKeys = 16384;
+constexpr int kMinPerTile = 1500;   // targets per tile below which the larger tiles are used
+constexpr int kBinUnroll = 4;
+constexpr int kBinLdsKeys = 32768;   // 128 KiB of LDS: one 1024-thread block per CU
 
 __global__ __launch_bounds__(1024) void k_bin_count(BinArgs B, const double* __restrict__ x, long T_, long chunk,
                                                     uint32_t* __restrict__ cnt) {
-  extern __shared__ uint32_t h[];
+  __shared__ uint32_t h[kBinLdsKeys];
   const int nk = B.t.nkeys;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) h[k] = 0u;
   __syncthreads();
   const long lo = (long)blockIdx.x * chunk, hi = min(T_, lo + chunk);
-  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    atomicAdd(&h[tile_key(B, x[3 * i], x[3 * i + 1], x[3 * i + 2])], 1u);
+  // kBinUnroll independent coordinate loads in flight per thread
+  for (long i0 = lo + threadIdx.x; i0 < hi; i0 += (long)kBinUnroll * blockDim.x) {
+    double a[kBinUnroll], b[kBinUnroll], c[kBinUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      const long i = i0 + (long)u * blockDim.x;
+      if (i < hi) {
+        a[u] = x[3 * i];
+        b[u] = x[3 * i + 1];
+        c[u] = x[3 * i + 2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u)
+      if (i0 + (long)u * blockDim.x < hi) atomicAdd(&h[tile_key(B, a[u], b[u], c[u])], 1u);
+  }
   __syncthreads();
   uint32_t* row = cnt + (long)blockIdx.x * nk;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) row[k] = h[k];
 }
 
-// 64 keys per block; 4 groups of 64 threads each scan a quarter of the blocks.
-__global__ __launch_bounds__(256) void k_bin_colscan(uint32_t* __restrict__ cnt, int nk, int nblk,
-                                                     uint32_t* __restrict__ total) {
-  __shared__ uint32_t part[4][64];
+// 64 keys per block; 16 groups of 64 threads each scan a sixteenth of the blocks.
+constexpr int kColGroups = 16;
+__global__ __launch_bounds__(64 * kColGroups) void k_bin_colscan(uint32_t* __restrict__ cnt, int nk, int nblk,
+                                                                 uint32_t* __restrict__ total) {
+  __shared__ uint32_t part[kColGroups][64];
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
-  const int per = (nblk + 3) / 4, b0 = grp * per, b1 = min(nblk, b0 + per);
+  const int per = (nblk + kColGroups - 1) / kColGroups, b0 = grp * per, b1 = min(nblk, b0 + per);
   uint32_t s = 0;
   if (k < nk)
     for (int b = b0; b < b1; ++b) s += cnt[(long)b * nk + k];
@@ -644,29 +668,44 @@ __global__ __launch_bounds__(256) void k_bin_colscan(uint32_t* __restrict__ cnt,
       cnt[o] = run;
       run += c;
     }
-    if (grp == 3) total[k] = run;
+    if (grp == kColGroups - 1) total[k] = run;
   }
 }
 
 __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __restrict__ x, long T_, long chunk,
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ offs, TRec* __restrict__ rec) {
-  extern __shared__ uint32_t cur[];
+  __shared__ uint32_t cur[kBinLdsKeys];
   const int nk = B.t.nkeys;
   const uint32_t* row = cnt + (long)blockIdx.x * nk;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) cur[k] = offs[k] + row[k];
   __syncthreads();
   const long lo = (long)blockIdx.x * chunk, hi = min(T_, lo + chunk);
-  for (long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double a = x[3 * i], b = x[3 * i + 1], c = x[3 * i + 2];
-    const long pos = atomicAdd(&cur[tile_key(B, a, b, c)], 1u);
-    TRec r;
-    r.x = a;
-    r.y = b;
-    r.z = c;
-    r.i = (uint32_t)i;
-    r.pad = 0u;
-    rec[pos] = r;
+  for (long i0 = lo + threadIdx.x; i0 < hi; i0 += (long)kBinUnroll * blockDim.x) {
+    double a[kBinUnroll], b[kBinUnroll], c[kBinUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      const long i = i0 + (long)u * blockDim.x;
+      if (i < hi) {
+        a[u] = x[3 * i];
+        b[u] = x[3 * i + 1];
+        c[u] = x[3 * i + 2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      const long i = i0 + (long)u * blockDim.x;
+      if (i < hi) {
+        const long pos = atomicAdd(&cur[tile_key(B, a[u], b[u], c[u])], 1u);
+        TRec r;
+        r.x = a[u];
+        r.y = b[u];
+        r.z = c[u];
+        r.i = (uint32_t)i;
+        r.pad = 0u;
+        rec[pos] = r;
+      }
+    }
   }
 }
 
@@ -731,62 +770,88 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   B.M2 = P.M2;
   B.M3 = P.M3;
   B.S = P.S;
-  // tile edges: 16 x 16 x 8 nodes for one field; for the seven Maxwell fields
-  // 8 x 8 x 4 (complex64) or 8 x 4 x 4 (complex128) so the staged footprint fits
-  // in 64 KiB of LDS.  Must match the instantiations of k_gather3d_tiled below.
+  // Tile edges.  One field: 16 x 16 x 8 nodes (several 256-thread blocks per
+  // CU, so one block's staging overlaps the others' interpolation), or, when
+  // that leaves fewer than kMinPerTile targets per tile on average (fine grids),
+  // 32 x 32 x 8 (complex64, 108 KiB, 1024 threads) or 32 x 16 x 8 (complex128,
+  // 117 KiB, 512 threads) so the staging is spread over more targets.  Seven
+  // Maxwell fields: 8 x 8 x 4 (complex64) or 8 x 4 x 4 (complex128) so the
+  // staged footprint fits in 64 KiB.  Must match the instantiations of
+  // k_gather3d_tiled below.
   TileArgs& Tl = B.t;
+  auto set_tiles = [&](int a, int b, int c) {
+    Tl.tb1 = a;
+    Tl.tb2 = b;
+    Tl.tb3 = c;
+    Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
+    Tl.nt2 = std::max(1, P.M2 >> Tl.tb2);
+    Tl.nt3n = std::max(1, P.M3 >> Tl.tb3);
+    Tl.nnear = Tl.nt1 * Tl.nt2 * Tl.nt3n;
+    Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
+  };
+  bool big = false;
   if (P.nf == 7) {
-    Tl.tb1 = 3;
-    Tl.tb2 = sizeof(T) == 8 ? 2 : 3;
-    Tl.tb3 = 2;
+    set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
   } else {
-    Tl.tb1 = 4;
-    Tl.tb2 = 4;
-    Tl.tb3 = 3;
+    set_tiles(4, 4, 3);
+    if (T_ < (int64_t)kMinPerTile * Tl.nkeys) {
+      big = true;
+      set_tiles(5, sizeof(T) == 8 ? 4 : 5, 3);
+    }
   }
-  Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
-  Tl.nt2 = std::max(1, P.M2 >> Tl.tb2);
-  Tl.nt3n = std::max(1, P.M3 >> Tl.tb3);
-  Tl.nnear = Tl.nt1 * Tl.nt2 * Tl.nt3n;
-  Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
   hipError_t e = ensure_bin_scratch(P, T_, Tl.nkeys);
   if (e != hipSuccess) return e;
   TRec* rec = reinterpret_cast<TRec*>(P.bin_rec);
+  const bool lds_bins = Tl.nkeys <= kBinLdsKeys;
+  const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
   {
     KernelTimer t(P, QPGF_T_BIN);
-    if (Tl.nkeys <= kBinLdsKeys) {
-      const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
-      const size_t lds = (size_t)Tl.nkeys * sizeof(uint32_t);
-      hipLaunchKernelGGL(k_bin_count, dim3(kBinBlocks), dim3(1024), lds, P.stream, B, x, (long)T_, chunk, P.bin_cnt);
-      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(256), 0, P.stream, P.bin_cnt, Tl.nkeys,
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.bin_novf, 1L);
+    if (lds_bins) {
+      hipLaunchKernelGGL(k_bin_count, dim3(kBinBlocks), dim3(1024), 0, P.stream, B, x, (long)T_, chunk, P.bin_cnt);
+      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, P.stream, P.bin_cnt,
+                         Tl.nkeys,
                          kBinBlocks, P.bin_hist);
-      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
-      hipLaunchKernelGGL(k_bin_place, dim3(kBinBlocks), dim3(1024), lds, P.stream, B, x, (long)T_, chunk, P.bin_cnt,
-                         P.bin_offs, rec);
     } else {
       // large key spaces: one global atomic rank per target
       hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, P.stream, P.bin_hist,
                          (long)Tl.nkeys);
       hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, P.stream, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
-      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
-      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
     }
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  {
+    KernelTimer t(P, QPGF_T_BIN_PLACE);
+    if (lds_bins)
+      hipLaunchKernelGGL(k_bin_place, dim3(kBinBlocks), dim3(1024), 0, P.stream, B, x, (long)T_, chunk, P.bin_cnt,
+                         P.bin_offs, rec);
+    else
+      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
   KernelTimer t(P, QPGF_T_GATHER);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.bin_novf, 1L);
   const dim3 tg(Tl.nkeys);
-#define QPGF_TILED(NF_, A1_, A2_, A3_)                                                                           \
-  hipLaunchKernelGGL((k_gather3d_tiled<T, NF_, A1_, A2_, A3_>), tg, dim3(256), 0, P.stream, A, Tl, g, f, rec,      \
+#define QPGF_TILED(NF_, A1_, A2_, A3_, BS_)                                                                      \
+  hipLaunchKernelGGL((k_gather3d_tiled<T, NF_, A1_, A2_, A3_, BS_>), tg, dim3(BS_), 0, P.stream, A, Tl, g, f, rec, \
                      P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
-  if (P.nf == 7) {
-    if (sizeof(T) == 8) QPGF_TILED(7, 3, 2, 2);
-    else QPGF_TILED(7, 3, 3, 2);
+  if constexpr (sizeof(T) == 8) {
+    if (P.nf == 7) QPGF_TILED(7, 3, 2, 2, 256);
+    else if (big) QPGF_TILED(1, 5, 4, 3, 512);
+    else QPGF_TILED(1, 4, 4, 3, 256);
   } else {
-    QPGF_TILED(1, 4, 4, 3);
+    if (P.nf == 7) QPGF_TILED(7, 3, 3, 2, 256);
+    else if (big) QPGF_TILED(1, 5, 5, 3, 1024);
+    else QPGF_TILED(1, 4, 4, 3, 256);
   }
 #undef QPGF_TILED
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  }
+  KernelTimer t(P, QPGF_T_OVERFLOW);
   if (P.nf == 7)
     hipLaunchKernelGGL((k_gather3d_overflow<T, 7>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
                        P.bin_novf, o, flags);

@@ -130,11 +130,14 @@ def test_maxwell3d_small(prec):
 
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
-@pytest.mark.parametrize("kind", [qpgf.KIND_GD3D, qpgf.KIND_MAXWELL3D])
-def test_binned_gather_large_target_count(prec, kind):
+@pytest.mark.parametrize("kind,shape", [(qpgf.KIND_GD3D, (64, 32, 32)), (qpgf.KIND_MAXWELL3D, (64, 32, 32)),
+                                        (qpgf.KIND_GD3D, (128, 128, 64))])
+def test_binned_gather_large_target_count(prec, kind, shape):
     """T >= 65536 takes the binned path (targets sorted by grid tile); includes
-    targets beyond the far slab and on the lattice, whose flags must follow them."""
-    M1, M2, M3, T = 64, 32, 32, 120_001
+    targets beyond the far slab and on the lattice, whose flags must follow them.
+    On 128 x 128 x 64 the 16 x 16 x 8 tiles would hold about 170 targets each, so
+    the larger 32-node tiles are used."""
+    (M1, M2, M3), T = shape, 120_001
     k, a1, a2 = 5.3, 0.1, 0.4
     x = workloads.targets(T, 3, seed=9, zmax=1.2)
     x[17] = [0.0, 2 * math.pi, 0.0]
@@ -172,6 +175,36 @@ def test_prepare_then_evaluate_in_chunks_matches_single_call():
 
 
 # ----------------------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("T", [3000, 70_000])
+def test_lattice_rmin_flags_and_values_3d(prec, T):
+    """lattice_rmin > 0: targets within it of a lattice point give NaN and flag bit 0, targets just
+    outside are evaluated (with the singular add-back) and match the oracle; both the unsorted and
+    the tile-binned (T >= 65536) gathers."""
+    M1, M2, M3 = 32, 32, 16
+    k, a1, a2 = 3.7, 0.2, 0.35
+    rmin = 1e-2
+    x = workloads.targets(T, 3, seed=13)
+    rng = np.random.default_rng(14)
+    d = rng.normal(size=(40, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    cells = 2 * math.pi * rng.integers(-1, 3, (40, 2))
+    rad = np.where(np.arange(40) % 2 == 0, 0.5 * rmin, 2 * rmin)
+    x[:40, :2] = cells + rad[:, None] * d[:, :2]
+    x[:40, 2] = rad * d[:, 2]
+    P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3, lattice_rmin=rmin)
+    flags = torch.empty(T, dtype=torch.uint8, device="cuda")
+    g = P(k, a1, a2, dev(x), flags=flags).cpu().numpy()
+    f = flags.cpu().numpy()
+    inside = np.zeros(T, bool)
+    inside[:40:2] = True
+    np.testing.assert_array_equal((f & 1) == 1, inside)
+    assert np.all(np.isnan(g[inside])) and np.all(np.isfinite(g[~inside]))
+    o = method.eval_gd3d(k, a1, a2, x[:2000], M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    sel = ~inside[:2000]
+    assert parity(g[:2000][sel], o[sel]) <= TOL[prec]
+
 
 def test_edge_targets_and_status_codes():
     M1, M2 = 64, 32
