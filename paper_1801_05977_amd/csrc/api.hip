@@ -192,11 +192,13 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage) {
     KernelTimer t(P, QPGF_T_HTABLE);
     HIP_TRY(launch_htable(P, k));
   }
+  // from stage 1 on, the 3D single-field fill also runs the transverse transform
+  const bool fused = stage >= 1 && fill_fuses_transverse(P);
   {
     KernelTimer t(P, QPGF_T_FILL);
-    HIP_TRY(launch_fill(P, k, a1, a2));
+    HIP_TRY(launch_fill(P, k, a1, a2, fused));
   }
-  if (stage >= 1) {
+  if (stage >= 1 && !fused) {
     const long nf = P.nf;
     KernelTimer t(P, QPGF_T_FFT_T);
     if (P.dim == 2) {

@@ -1,0 +1,136 @@
+// Device building blocks of the inverse DFTs (unnormalised, e^{+2 pi i jp/n},
+// power-of-two lengths): radix-8/4/2 butterflies in registers and one
+// in-place Stockham autosort pass over transforms held in LDS.  Shared by the
+// FFT kernels and by the 3D fill, which transforms its pencils along the
+// transverse axis before writing them.
+#pragma once
+
+#include "qpgf_internal.h"
+
+namespace qpgf {
+namespace fftdev {
+
+template <typename V> __device__ __forceinline__ V c_add(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V c_sub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __device__ __forceinline__ V c_mul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// a + i b, a - i b
+template <typename V> __device__ __forceinline__ V c_addi(V a, V b) { V r; r.x = a.x - b.y; r.y = a.y + b.x; return r; }
+template <typename V> __device__ __forceinline__ V c_subi(V a, V b) { V r; r.x = a.x + b.y; r.y = a.y - b.x; return r; }
+
+// inverse radix-8 DFT in registers: y_m = sum_r v_r e^{+2 pi i r m / 8}
+template <typename V, typename T>
+__device__ __forceinline__ void dft8(V v[8]) {
+  const T h = (T)0.70710678118654752440;
+  const V a0 = c_add(v[0], v[4]), a1 = c_sub(v[0], v[4]), a2 = c_add(v[2], v[6]), a3 = c_sub(v[2], v[6]);
+  const V a4 = c_add(v[1], v[5]), a5 = c_sub(v[1], v[5]), a6 = c_add(v[3], v[7]), a7 = c_sub(v[3], v[7]);
+  const V e0 = c_add(a0, a2), e2 = c_sub(a0, a2), e1 = c_addi(a1, a3), e3 = c_subi(a1, a3);
+  const V o0 = c_add(a4, a6), o2 = c_sub(a4, a6), o1 = c_addi(a5, a7), o3 = c_subi(a5, a7);
+  // w^1 o1 = (1 + i)/sqrt2 o1, w^2 o2 = i o2, w^3 o3 = (-1 + i)/sqrt2 o3
+  V w1, w3;
+  w1.x = h * (o1.x - o1.y);
+  w1.y = h * (o1.x + o1.y);
+  w3.x = -h * (o3.x + o3.y);
+  w3.y = h * (o3.x - o3.y);
+  v[0] = c_add(e0, o0);
+  v[4] = c_sub(e0, o0);
+  v[1] = c_add(e1, w1);
+  v[5] = c_sub(e1, w1);
+  v[2] = c_addi(e2, o2);
+  v[6] = c_subi(e2, o2);
+  v[3] = c_add(e3, w3);
+  v[7] = c_sub(e3, w3);
+}
+
+template <typename V>
+__device__ __forceinline__ void dft4(V v[4]) {
+  const V a0 = c_add(v[0], v[2]), a1 = c_sub(v[0], v[2]), a2 = c_add(v[1], v[3]), a3 = c_sub(v[1], v[3]);
+  v[0] = c_add(a0, a2);
+  v[1] = c_addi(a1, a3);
+  v[2] = c_sub(a0, a2);
+  v[3] = c_subi(a1, a3);
+}
+
+template <typename V>
+__device__ __forceinline__ void dft2(V v[2]) {
+  const V a = v[0];
+  v[0] = c_add(a, v[1]);
+  v[1] = c_sub(a, v[1]);
+}
+
+template <int R, typename V, typename T>
+__device__ __forceinline__ void dftR(V v[R]) {
+  if constexpr (R == 8) dft8<V, T>(v);
+  else if constexpr (R == 4) dft4<V>(v);
+  else dft2<V>(v);
+}
+
+// One in-place Stockham pass of radix R over `ntile` transforms of length n
+// held in LDS (row pitch `pitch`): every thread first reads its butterflies'
+// inputs into registers, the block synchronises, then writes the outputs.
+// At most MAXB butterflies per thread (256 threads).
+template <typename T, int R, int MAXB>
+__device__ __forceinline__ void stockham_pass(cplx<T>* buf, int n, int pitch, int ntile, int Ns, int lr,
+                                              const cplx<T>* __restrict__ tw, int twlog2) {
+  using V = cplx<T>;
+  const int nb = n / R;
+  const int total = ntile * nb;
+  const int step_log = twlog2 - (__builtin_ctz(Ns) + lr);   // NT / (Ns R)
+  V v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int idx = threadIdx.x + q * 256;
+    if (idx < total) {
+      const int t = idx / nb, j = idx - t * nb;
+      const V* src = buf + t * pitch + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int idx = threadIdx.x + q * 256;
+    if (idx < total) {
+      const int t = idx / nb, j = idx - t * nb;
+      const int kk = j & (Ns - 1);
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw[(r * kk) << step_log]);
+      }
+      dftR<R, V, T>(v[q]);
+      V* dst = buf + t * pitch + ((j - kk) << lr) + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// LDS capacity of one block, in complex elements (64 KiB).
+template <typename T> constexpr int lds_cap() { return 65536 / (int)sizeof(cplx<T>); }
+
+
+// All passes of inverse DFTs of length n = 2^log2n over `ntile` transforms in
+// LDS (row pitch `pitch`): radix-8 passes, then one radix-4 or radix-2 pass for
+// the remaining factor.  256 threads; ntile * n <= lds_cap<T>().
+template <typename T>
+__device__ __forceinline__ void inverse_dft_lds(cplx<T>* buf, int n, int log2n, int pitch, int ntile,
+                                                const cplx<T>* __restrict__ tw, int twlog2) {
+  constexpr int CAP = lds_cap<T>();
+  int Ns = 1, rem = log2n;
+  while (rem >= 3) {
+    stockham_pass<T, 8, CAP / (8 * 256)>(buf, n, pitch, ntile, Ns, 3, tw, twlog2);
+    Ns <<= 3;
+    rem -= 3;
+  }
+  if (rem == 2) stockham_pass<T, 4, CAP / (4 * 256)>(buf, n, pitch, ntile, Ns, 2, tw, twlog2);
+  else if (rem == 1) stockham_pass<T, 2, CAP / (2 * 256)>(buf, n, pitch, ntile, Ns, 1, tw, twlog2);
+}
+
+}  // namespace fftdev
+}  // namespace qpgf

@@ -7,6 +7,7 @@
 // stored at index j mod M ("FFT order"), so the grid sums become plain
 // unnormalised inverse DFTs.  Near fields: [jt'][j2'][j1'] (3D) or [j2'][j1']
 // (2D), j1 fastest; far slab: [s][j2'][j1'] or [s][j1'].
+#include "fft_device.h"
 #include "qpgf_internal.h"
 
 namespace qpgf {
@@ -64,6 +65,7 @@ __device__ __forceinline__ void pencil_weights(const FillArgs& A, int j1p0, int 
 __device__ __forceinline__ double2 xprime_term(const double2* __restrict__ ap, const double2* __restrict__ csr, int Q,
                                                double sgn, double J, double2 b) {
   double2 C = mk(0.0, 0.0), S = mk(0.0, 0.0);
+#pragma unroll 8
   for (int q = 0; q < Q; ++q) {
     double2 a = ap[q * TP], t = csr[q];
     C.x = fma(a.x, t.x, C.x);
@@ -93,11 +95,13 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
   suf[7] = 1.0;
 #pragma unroll
   for (int a = 6; a >= 0; --a) suf[a] = suf[a + 1] * (f - (double)(a - 2));
-  const double den[8] = {-5040.0, 720.0, -240.0, 144.0, -144.0, 240.0, -720.0, 5040.0};
+  // reciprocals of the node products prod_{b != a} (a - b) for nodes -3..4
+  const double rden[8] = {-1.0 / 5040.0, 1.0 / 720.0, -1.0 / 240.0, 1.0 / 144.0,
+                          -1.0 / 144.0,  1.0 / 240.0, -1.0 / 720.0, 1.0 / 5040.0};
   double2 acc = mk(0.0, 0.0);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    double w = pre[a] * suf[a] / den[a];
+    double w = pre[a] * suf[a] * rden[a];
     double2 h = tab[m0 + a];
     acc.x = fma(w, h.x, acc.x);
     acc.y = fma(w, h.y, acc.y);
@@ -108,21 +112,31 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
 // 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF == 7):
 // L-hat_dj = A3 [ I-terms + H(|xi|) / (|xi|^2 - k^2) ], i.e. K-hat_dj of (3.3)
 // minus F-hat_j of (3.5) with the common 1/(|xi|^2-k^2) cancelled exactly.
-template <typename T, int NF>
+//
+// FUSE: the block also runs the transverse inverse DFT of its TP pencils
+// (Algorithm 3.1 step 1c) in LDS and writes grid values instead of
+// coefficients, saving one pass over the grid (one field only; the transform
+// is the same sequence of passes and twiddles as the separate FFT kernel).
+template <typename T, int NF, bool FUSE>
 __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __restrict__ xq,
                                                 const double* __restrict__ wxq, const double2* __restrict__ cs,
-                                                const double2* __restrict__ htab, cplx<T>* __restrict__ out) {
+                                                const double2* __restrict__ htab, cplx<T>* __restrict__ out,
+                                                const cplx<T>* __restrict__ tw, int twlog2) {
   extern __shared__ double2 sa[];
+  // FUSE: the pencils, [pencil][jt'] with pitch Mt + 1, after the weights
+  cplx<T>* pen = reinterpret_cast<cplx<T>*>(sa + TP * A.Q);
+  const int pitch = A.Mt + 1;
   const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
   const int j1p0 = blockIdx.x * TP, j2p = blockIdx.y;
   const int j1p = j1p0 + ip;
-  pencil_weights<3>(A, j1p0, j2p, xq, wxq, sa);
-  __syncthreads();
-  if (j1p >= A.M1) return;
-  const double xi1 = A.a1 + centered(j1p, A.M1), xi2 = A.a2 + centered(j2p, A.M2);
+  const double xi1 = A.a1 + centered(min(j1p, A.M1 - 1), A.M1), xi2 = A.a2 + centered(j2p, A.M2);
   const double rp2 = xi1 * xi1 + xi2 * xi2;
   const double2 b = beta_of(A.k, sqrt(rp2));
   const bool use_I = b.y * A.c < 41.5;   // else |I| < e^{-c Im beta} < 1e-18
+  // the pencil weights only where some pencil of the block needs the X'-integrals
+  if (__syncthreads_or(use_I && j1p < A.M1)) pencil_weights<3>(A, j1p0, j2p, xq, wxq, sa);
+  __syncthreads();
+  if (!FUSE && j1p >= A.M1) return;
   const double2* ap = sa + ip;
   const double k2 = A.k * A.k;
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
@@ -133,6 +147,10 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
     const double rho2 = rp2 + J * J;
     const double2 H = h_interp(htab, A.hd, sqrt(rho2));
     const double2 L = cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A);
+    if constexpr (FUSE) {
+      store_c<T>(pen, (size_t)ip * pitch + jtp, L);
+      continue;
+    }
     const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
     store_c<T>(out, o, L);
     if (NF == 7) {
@@ -141,6 +159,16 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
       const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
       for (int f = 0; f < 6; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+    }
+  }
+  if constexpr (FUSE) {
+    __syncthreads();
+    fftdev::inverse_dft_lds<T>(pen, A.Mt, __builtin_ctz((unsigned)A.Mt), pitch, TP, tw, twlog2);
+    // grid values [i3][j2'][j1'], TP consecutive j1' per slice
+    const int np = min(TP, A.M1 - j1p0);
+    for (int idx = threadIdx.x; idx < TP * A.Mt; idx += blockDim.x) {
+      const int p = idx % TP, i3 = idx / TP;
+      if (p < np) out[((size_t)i3 * A.M2 + j2p) * A.M1 + j1p0 + p] = pen[p * pitch + i3];
     }
   }
 }
@@ -156,13 +184,13 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
   const int j1p0 = blk * TP;
   const int j1p = j1p0 + ip;
-  pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
-  __syncthreads();
-  if (j1p >= A.M1) return;
-  const int j1 = centered(j1p, A.M1);
+  const int j1 = centered(min(j1p, A.M1 - 1), A.M1);
   const double a = A.a1 + j1;
   const double2 b = beta_of(A.k, fabs(a));
   const bool use_I = b.y * A.c < 41.5;
+  if (__syncthreads_or(use_I && j1p < A.M1)) pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
+  __syncthreads();
+  if (j1p >= A.M1) return;
   const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
   const int jt_tab = j1 & (M1t - 1);
@@ -327,7 +355,7 @@ __global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, int
 }
 
 template <typename T>
-hipError_t fill_impl(Plan& P, double k, double a1, double a2) {
+hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse) {
   FillArgs A;
   A.k = k;
   A.a1 = a1;
@@ -349,10 +377,18 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2) {
   } else {
     A.A = 1.0 / sqrt(8.0 * kPi * kPi * A.c_tilde);
     dim3 grid((P.M1 + TP - 1) / TP, P.M2);
+    const cplx<T>* tw = nullptr;
+    if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
     if (P.nf == 7)
-      hipLaunchKernelGGL((k_fill3d<T, 7>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab, out);
+      hipLaunchKernelGGL((k_fill3d<T, 7, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab,
+                         out, tw, P.twlog2);
+    else if (fuse)
+      hipLaunchKernelGGL((k_fill3d<T, 1, true>), grid, dim3(TP * TL),
+                         shm + (size_t)TP * (P.Mt + 1) * sizeof(cplx<T>), P.stream, A, P.xq, P.wxq, P.cs, P.htab,
+                         out, tw, P.twlog2);
     else
-      hipLaunchKernelGGL((k_fill3d<T, 1>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab, out);
+      hipLaunchKernelGGL((k_fill3d<T, 1, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab,
+                         out, tw, P.twlog2);
   }
   return hipGetLastError();
 }
@@ -438,8 +474,16 @@ hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nbloc
   return hipGetLastError();
 }
 
-hipError_t launch_fill(Plan& P, double k, double a1, double a2) {
-  return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2) : fill_impl<float>(P, k, a1, a2);
+// The fill can take the transverse transform over for one 3D field when its TP
+// pencils and the pencil weights fit together in 64 KiB of LDS.
+bool fill_fuses_transverse(const Plan& P) {
+  const size_t lds = (size_t)TP * P.p.quad_q * sizeof(double2) + (size_t)TP * (P.Mt + 1) * P.esize;
+  return P.dim == 3 && P.nf == 1 && P.Mt > 1 && lds <= 65536;
+}
+
+hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse) {
+  fuse = fuse && fill_fuses_transverse(P);
+  return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2, fuse) : fill_impl<float>(P, k, a1, a2, fuse);
 }
 
 hipError_t launch_far(Plan& P, double k, double a1, double a2) {
