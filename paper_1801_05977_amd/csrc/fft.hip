@@ -105,10 +105,10 @@ hipError_t fft_multi_impl(Plan& P, void* base, const FftSeg* dsegs, int nseg, lo
 
 }  // namespace
 
-// Transforms per block: as many as fill 64 KiB of LDS (one in-place buffer), at
-// most 64, unless the autotuner has recorded a faster choice for this length
-// and axis.  Never more than fit: the passes hold at most 64 KiB / (R * 256)
-// butterflies per thread in registers.
+// Transforms per block: about 2048 elements, at most 64 transforms and never
+// more than fit 64 KiB of LDS (the passes hold at most 64 KiB / (R * 256)
+// butterflies per thread in registers), unless the autotuner has recorded a
+// faster choice for this length and axis.
 int fft_tile(const Plan& P, int n, bool rows, long nbatch) {
   const int pitch = n + (rows ? 0 : 1);
   const int cap = (int)(65536 / P.esize) / pitch;
@@ -117,12 +117,16 @@ int fft_tile(const Plan& P, int n, bool rows, long nbatch) {
   auto it = P.fft_tiles.find(key);
   if (it != P.fft_tiles.end()) tile = it->second;
   if (tile <= 0 || tile > cap) {
-    tile = cap;
+    // about 2048 elements per block (16 KiB complex64): several blocks per CU,
+    // so one block's LDS passes overlap the others' global loads and stores
+    // (the autotuner's choices on gfx950 cluster there)
+    // column groups of at least 64 bytes so the loads stay coalesced
+    const int min_tile = rows ? 1 : std::max(1, (int)(64 / P.esize));
+    tile = std::max(1, std::min(cap, std::max(2048 / n, min_tile)));
     if (tile > 64) tile = 64;
     // columns: whole aligned groups of adjacent columns
     if (!rows) tile = 1 << (31 - __builtin_clz((unsigned)tile));
-    // keep at least ~1024 blocks in flight (4 per CU) while groups stay >= 64 bytes
-    const int min_tile = rows ? 1 : std::max(1, (int)(64 / P.esize));
+    // keep at least ~1024 blocks in flight (4 per CU)
     while (tile > min_tile && (nbatch + tile - 1) / tile < 1024) tile >>= 1;
   }
   if (tile < 1) tile = 1;
