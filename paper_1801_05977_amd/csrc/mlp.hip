@@ -231,16 +231,11 @@ __global__ void k_refresh_bf16(const float* __restrict__ W, int N, int K, __bf16
   if (WTb) WTb[(long)k * N + n] = v;
 }
 
-// 64 input features of a query (x1, x2, x3, k, alpha1, alpha2), in bf16, and transposed.
-__global__ void k_features(const double* __restrict__ q, long M, double c, double c_tilde, __bf16* __restrict__ F,
-                           __bf16* __restrict__ FT) {
-  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const double* Q = q + 6 * m;
+// The 64 input features of one query (x1, x2, x3, k, alpha1, alpha2).
+__device__ __forceinline__ void features_row(const double* __restrict__ Q, double c, double c_tilde, float f[64]) {
   const double x1 = Q[0], x2 = Q[1], x3 = Q[2], k = Q[3], a1 = Q[4], a2 = Q[5];
   const double t1 = x1 - 2.0 * kPi * floor((x1 + kPi) * (0.5 / kPi));
   const double t2 = x2 - 2.0 * kPi * floor((x2 + kPi) * (0.5 / kPi));
-  float f[64];
   int o = 0;
   for (int h = 1; h <= 8; ++h) {
     f[o++] = (float)cos(h * t1);
@@ -265,10 +260,113 @@ __global__ void k_features(const double* __restrict__ q, long M, double c, doubl
     f[o++] = (float)cos(args[h]);
     f[o++] = (float)sin(args[h]);
   }
+}
+
+// Features of M queries in bf16, row-major, and optionally transposed.
+__global__ void k_features(const double* __restrict__ q, long M, double c, double c_tilde, __bf16* __restrict__ F,
+                           __bf16* __restrict__ FT) {
+  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float f[64];
+  features_row(q + 6 * m, c, c_tilde, f);
   for (int h = 0; h < 64; ++h) {
     const __bf16 v = (__bf16)f[h];
     F[m * 64 + h] = v;
     if (FT) FT[(long)h * M + m] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: one block takes 128 queries through every ensemble member.
+// Features, then four hidden layers with the activations of the tile held in
+// LDS (two ping-pong buffers), weights read from L2, bias + GELU in the MFMA
+// epilogue, and the fp32 head.  Four waves; wave w computes output columns
+// [64 w, 64 w + 64) of a hidden layer for all 128 rows (8 x 4 tiles of 16 x 16).
+// The rounding points are those of the layer-by-layer path: bf16 features,
+// fp32 accumulation plus fp32 bias, GELU in fp32, bf16 activations.
+// ---------------------------------------------------------------------------
+constexpr int kIR = 128;                 // rows per block
+constexpr int kIP0 = 64 + 8, kIP = 256 + 8;   // LDS row pitches (bf16) of features / activations
+constexpr int kMaxMembers = 8;
+
+struct InferArgs {
+  const __bf16* wb[kMaxMembers];   // hidden weights [4][256][K] (K = 64 for layer 0, 256 after)
+  const float* p[kMaxMembers];     // fp32 parameters: biases and the head
+  long off_b[4], off_w4, off_b4;   // offsets in p
+  int members;
+  double c, c_tilde;
+};
+
+template <int K>
+__device__ __forceinline__ void infer_layer(const __bf16* __restrict__ X, int pitchX, const __bf16* __restrict__ W,
+                                            const float* __restrict__ bias, __bf16* __restrict__ Y) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x4*>(W + (long)(64 * w + 16 * j + lr) * K + k0 + 4 * lg);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(X + (16 * i + lr) * pitchX + k0 + 4 * lg);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = 64 * w + 16 * j + lr;
+    const float bb = bias[col];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Y[(16 * i + 4 * lg + r) * kIP + col] = (__bf16)gelu(acc[i][j][r] + bb);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A, const double* __restrict__ q, long M,
+                                                   float* __restrict__ y, long ystride) {
+  __shared__ __bf16 X0[kIR * kIP0];
+  __shared__ __bf16 B1[kIR * kIP];
+  __shared__ __bf16 B2[kIR * kIP];
+  const long r0 = (long)blockIdx.x * kIR;
+  if (threadIdx.x < kIR) {
+    const long m = r0 + threadIdx.x;
+    float f[64];
+    if (m < M) features_row(q + 6 * m, A.c, A.c_tilde, f);
+    else
+      for (int h = 0; h < 64; ++h) f[h] = 0.f;
+    for (int h = 0; h < 64; ++h) X0[threadIdx.x * kIP0 + h] = (__bf16)f[h];
+  }
+  __syncthreads();
+  for (int e = 0; e < A.members; ++e) {
+    const __bf16* wb = A.wb[e];
+    const float* p = A.p[e];
+    infer_layer<64>(X0, kIP0, wb, p + A.off_b[0], B1);
+    __syncthreads();
+    infer_layer<256>(B1, kIP, wb + 256 * 256, p + A.off_b[1], B2);
+    __syncthreads();
+    infer_layer<256>(B2, kIP, wb + 2 * 256 * 256, p + A.off_b[2], B1);
+    __syncthreads();
+    infer_layer<256>(B1, kIP, wb + 3 * 256 * 256, p + A.off_b[3], B2);
+    __syncthreads();
+    // head: thread t -> row t / 2, output t % 2
+    {
+      const int row = threadIdx.x >> 1, o = threadIdx.x & 1;
+      const float* W4 = p + A.off_w4 + o * 256;
+      float s_ = p[A.off_b4 + o];
+      const __bf16* a = B2 + row * kIP;
+      for (int k = 0; k < 256; ++k) s_ = fmaf((float)a[k], W4[k], s_);
+      const long m = r0 + row;
+      if (m < M) y[(long)e * ystride + 2 * m + o] = s_;
+    }
+    __syncthreads();
   }
 }
 
@@ -431,6 +529,24 @@ hipError_t mlp_refresh_bf16(hipStream_t st, const float* W, int N, int K, __bf16
 }
 hipError_t mlp_features(hipStream_t st, const double* q, long M, double c, double c_tilde, __bf16* F, __bf16* FT) {
   hipLaunchKernelGGL(k_features, dim3(nb(M)), dim3(256), 0, st, q, M, c, c_tilde, F, FT);
+  return hipGetLastError();
+}
+hipError_t mlp_infer(hipStream_t st, const __bf16* const* wb, const float* const* p, int members, const long off_b[4],
+                     long off_w4, long off_b4, double c, double c_tilde, const double* q, long M, float* y,
+                     long ystride) {
+  if (members < 1 || members > kMaxMembers) return hipErrorInvalidValue;
+  InferArgs A;
+  for (int e = 0; e < kMaxMembers; ++e) {
+    A.wb[e] = e < members ? wb[e] : nullptr;
+    A.p[e] = e < members ? p[e] : nullptr;
+  }
+  for (int l = 0; l < 4; ++l) A.off_b[l] = off_b[l];
+  A.off_w4 = off_w4;
+  A.off_b4 = off_b4;
+  A.members = members;
+  A.c = c;
+  A.c_tilde = c_tilde;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((M + kIR - 1) / kIR)), dim3(256), 0, st, A, q, M, y, ystride);
   return hipGetLastError();
 }
 size_t mlp_qinst_size() { return sizeof(QInst); }

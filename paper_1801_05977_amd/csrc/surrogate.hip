@@ -31,6 +31,9 @@ hipError_t mlp_make_queries(hipStream_t st, const void* inst, int n, const doubl
 hipError_t mlp_combine(hipStream_t st, int prec, const double* q, long M, const float* y, int members, long ystride,
                        double c, double eps, double tol, double wood_tol, double rmin, void* out, uint8_t* fell);
 hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
+hipError_t mlp_infer(hipStream_t st, const __bf16* const* wb, const float* const* p, int members, const long off_b[4],
+                     long off_w4, long off_b4, double c, double c_tilde, const double* q, long M, float* y,
+                     long ystride);
 }  // namespace qpgf
 
 using namespace qpgf;
@@ -298,13 +301,11 @@ qpgf_status qpgf_mlp_forward(qpgf_mlp* m, int member, const double* q, int64_t B
   qpgf_status st = check_mlp(m, member);
   if (st != QPGF_OK) return st;
   if (B < 0 || (B > 0 && (!q || !y))) return sfail(QPGF_E_ARG, "bad arguments");
-  for (int64_t b0 = 0; b0 < B; b0 += m->maxb) {
-    const long n = (long)std::min<int64_t>(m->maxb, B - b0), np = (n + 63) / 64 * 64;
-    S_TRY(mlp_features(m->stream, q + 6 * b0, n, kC, kCt, m->F, nullptr));
-    if (np > n) S_TRY(hipMemsetAsync(m->F + n * D_IN, 0, (np - n) * D_IN * sizeof(__bf16), m->stream));
-    S_TRY(forward(m, member, np, m->out));
-    S_TRY(hipMemcpyAsync(y + 2 * b0, m->out, n * 2 * sizeof(float), hipMemcpyDeviceToDevice, m->stream));
-  }
+  if (B == 0) return QPGF_OK;
+  // the fused inference kernel: no intermediate buffers, any B
+  const __bf16* wb[1] = {m->wb[member]};
+  const float* pp[1] = {m->p[member]};
+  S_TRY(mlp_infer(m->stream, wb, pp, 1, B_OFF, OFF_W4, OFF_B4, kC, kCt, q, (long)B, y, 0));
   return QPGF_OK;
 }
 
@@ -425,12 +426,13 @@ qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double
   }
   S_TRY(mlp_make_queries(m->stream, m->qinst, n_inst, x, T, m->qall));
   const size_t esz = info.prec == QPGF_C128 ? 16 : 8;
-  // network on chunks of max_batch rows; ensemble outputs side by side in ybuf
+  // network on chunks of max_batch rows (fused kernel, every member per tile);
+  // ensemble outputs side by side in ybuf
+  const long ystride = m->maxb * 2;
   for (int64_t b0 = 0; b0 < T; b0 += m->maxb) {
-    const long n = (long)std::min<int64_t>(m->maxb, T - b0), np = (n + 63) / 64 * 64;
-    S_TRY(mlp_features(m->stream, m->qall + 6 * b0, n, info.c, info.c_tilde, m->F, nullptr));
-    if (np > n) S_TRY(hipMemsetAsync(m->F + n * D_IN, 0, (np - n) * D_IN * sizeof(__bf16), m->stream));
-    for (int e = 0; e < m->members; ++e) S_TRY(forward(m, e, np, m->ybuf + (long)e * m->maxb * 2));
+    const long n = (long)std::min<int64_t>(m->maxb, T - b0);
+    S_TRY(mlp_infer(m->stream, m->wb.data(), m->p.data(), m->members, B_OFF, OFF_W4, OFF_B4, info.c, info.c_tilde,
+                    m->qall + 6 * b0, n, m->ybuf, ystride));
     S_TRY(mlp_combine(m->stream, info.prec, m->qall + 6 * b0, n, m->ybuf, m->members, m->maxb * 2, info.c, info.eps,
                       tol, wood_tol, rmin, static_cast<char*>(out) + b0 * esz, fell_back + b0));
   }
