@@ -99,6 +99,146 @@ struct GlobalFetch {
   }
 };
 
+// The steps of eval3d_target (below) split in two, for kernels that compute the
+// stencil sums between them (k_gather3d_fields): the stencil of one target
+// (Algorithm 3.1 / 4.1 step 2: cell reduction, branch, base nodes and the three
+// 4-point weight sets), and the finish from the sums to the result.  The
+// single-function form stays for the other kernels, where it compiles to far
+// fewer registers with seven fields.
+template <typename T>
+struct Stencil3 {
+  double t1, t2, n1, n2;
+  bool near;
+  int p1, p2, p3;
+  T w1[4], w2[4], w3[4];
+};
+
+// false: the result is NaN without a stencil sum (non-finite input, beyond the
+// far slab, or a far target when only the smooth part is asked for); res, fl set.
+template <typename T, int NO>
+__device__ __forceinline__ bool stencil3d(const GArgs& A, double x1, double x2, double x3, Stencil3<T>& s,
+                                          double2* res, uint8_t& fl) {
+  fl = 0;
+  if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) {
+    fl = 8;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return false;
+  }
+  s.t1 = reduce_cell(x1, s.n1);
+  s.t2 = reduce_cell(x2, s.n2);
+  const double u1 = s.t1 * A.ih1, q1 = floor(u1);
+  lag4<T>((T)(u1 - q1), s.w1);
+  const double u2 = s.t2 * A.ih2, q2 = floor(u2);
+  lag4<T>((T)(u2 - q2), s.w2);
+  s.p1 = (int)q1;
+  s.p2 = (int)q2;
+  s.near = fabs(x3) <= A.c;
+  if (s.near) {
+    const double u = x3 * A.ih3, q = floor(u);
+    lag4<T>((T)(u - q), s.w3);
+    s.p3 = (int)q;
+    return true;
+  }
+  fl |= 2;
+  if (A.smooth) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return false;
+  }
+  const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
+  double s0 = floor(v);
+  if (s0 > A.S - 3) {
+    fl |= 4;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return false;
+  }
+  s0 = fmax(s0, 1.0);
+  lag4<T>((T)(v - s0), s.w3);
+  s.p3 = (int)s0;
+  return true;
+}
+
+// From the stencil sums L (NF fields) to the result: phase, exact FP64 add-back
+// of the singular part (and its Hessian), Maxwell assembly (eq. 4.1).
+template <typename T, int NF>
+__device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, double x3, const Stencil3<T>& s,
+                                         const double2 L[NF], double2* res, uint8_t& fl) {
+  constexpr int NO = (NF == 1) ? 1 : 6;
+  if (A.smooth) {
+    // the smooth part L_N(t) of Algorithm 3.1 step 2d (near branch only)
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = L[o < NF ? o : 0];
+    return;
+  }
+  const double t1 = s.t1, t2 = s.t2, n1 = s.n1, n2 = s.n2;
+  const bool is_near = s.near;
+  double ps, pc;
+  sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
+  const double2 phase = mk(pc, ps);
+  double2 G[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
+  if (!is_near && NF == 7) {
+    // d/dx3 of e^{i beta |x3|} carries sgn(x3): components 13 and 23
+    if (x3 < 0) {
+      G[5] = cscale(G[5], -1.0);
+      G[6] = cscale(G[6], -1.0);
+    }
+  }
+  if (is_near) {
+    // the square root only inside the support of the singular part
+    const double r2 = t1 * t1 + t2 * t2 + x3 * x3;
+    if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+      fl |= 1;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) G[f] = nan2();
+    } else if (r2 < 4.0 * A.eps * A.eps) {
+      const double r = sqrt(r2);
+      // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
+      double sn, cn;
+      sincos(A.k * r, &sn, &cn);
+      const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
+      double ls, lc;
+      sincospi(2.0 * (A.a1 * n1 + A.a2 * n2), &ls, &lc);
+      const double2 lat = mk(lc, ls);
+      const double Y = cut_Y(r, A.eps);
+      G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
+      if (NF == 7) {
+        // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
+        const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
+        const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
+        const double2 g1 = cmul(g, ikr);
+        const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
+        const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
+        const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
+        const double t[3] = {t1, t2, x3};
+        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const double tp = t[P[f]], tq = t[Qp[f]];
+          const double a = tp * tq / (r * r);
+          const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
+          G[f + 1] = cadd(G[f + 1], cmul(lat, cadd(cscale(d2, a), cscale(d1, bcoef))));
+        }
+      }
+    }
+  }
+  if (NF == 1) {
+    res[0] = G[0];
+  } else {
+    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1)
+    const double ik2 = 1.0 / (A.k * A.k);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      double2 v = cscale(G[f + 1], ik2);
+      if (f < 3) v = cadd(v, G[0]);
+      res[f] = v;
+    }
+  }
+}
+
 // One target of Algorithm 3.1 / 4.1 step 2 (G_d, or the six Maxwell entries).
 // `fetch` performs the 64-point stencil sum of the near grid or the far slab.
 template <typename T, int NF, typename Fetch>
@@ -258,6 +398,33 @@ struct TileArgs {
   int nnear, nkeys;
 };
 
+// 64-point stencil sum of one field from an LDS footprint with row length F1
+// and F2 rows per slice; base points at node (p1 - 1, p2 - 1, p3 - 1).
+template <typename T, int F1, int F2>
+__device__ __forceinline__ double2 lds_sum(const cplx<T>* base, const T a1[4], const T a2[4], const T a3[4]) {
+  T accx = 0, accy = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    T px = 0, py = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const cplx<T>* row = base + (c * F2 + b) * F1;
+      T rx = 0, ry = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const cplx<T> v = row[a];
+        rx += a1[a] * v.x;
+        ry += a1[a] * v.y;
+      }
+      px += a2[b] * rx;
+      py += a2[b] * ry;
+    }
+    accx += a3[c] * px;
+    accy += a3[c] * py;
+  }
+  return mk((double)accx, (double)accy);
+}
+
 // Stencil sum from the LDS-staged footprint of one tile (compile-time footprint
 // F1 x F2 x F3 so every LDS address is a base plus an immediate offset).  A
 // target whose stencil does not lie in the footprint (a rounding disagreement
@@ -279,33 +446,8 @@ struct LdsFetch {
     }
     constexpr int FSZ = F1 * F2 * F3;
     const cplx<T>* base = lds + (l3 * F2 + l2) * F1 + l1;
-    const T* a1 = w1;
-    const T* a2 = w2;
-    const T* a3 = w3;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      T accx = 0, accy = 0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        T px = 0, py = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const cplx<T>* row = base + f * FSZ + (c * F2 + b) * F1;
-          T rx = 0, ry = 0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const cplx<T> v = row[a];
-            rx += a1[a] * v.x;
-            ry += a1[a] * v.y;
-          }
-          px += a2[b] * rx;
-          py += a2[b] * ry;
-        }
-        accx += a3[c] * px;
-        accy += a3[c] * py;
-      }
-      L[f] = mk((double)accx, (double)accy);
-    }
+    for (int f = 0; f < NF; ++f) L[f] = lds_sum<T, F1, F2>(base + f * FSZ, w1, w2, w3);
   }
 };
 
@@ -389,6 +531,95 @@ __global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, cons
       if (flags) flags[i] = fl;
     }
     r = rn;
+  }
+}
+
+// Maxwell tensor over targets sorted by tile, one field at a time: the tile's
+// footprint of field f is staged in LDS, every target of the tile takes its
+// stencil sum of field f, then the next field replaces it.  Used when the tiles
+// hold few targets (fewer than about two blocks' worth), so a footprint of all
+// seven fields would not fit LDS at a useful tile size.  Up to 256 targets per
+// pass; a tile with more runs several passes, staging again.
+template <typename T, int TB1, int TB2, int TB3>
+__global__ __launch_bounds__(256) void k_gather3d_fields(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+                                                         const cplx<T>* __restrict__ far,
+                                                         const TRec* __restrict__ rec,
+                                                         const uint32_t* __restrict__ hist,
+                                                         const uint32_t* __restrict__ offs,
+                                                         cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
+                                                         uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+  constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
+  constexpr int NF = 7, NO = 6;
+  __shared__ cplx<T> lds[FSZ];
+  const int key = B.nkeys - 1 - (int)blockIdx.x;
+  const uint32_t cnt = hist[key];
+  if (cnt == 0) return;
+  const long start = offs[key];
+  if (key >= B.nkeys - 1) {
+    const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
+      const TRec r = rec[j];
+      double2 res[NO];
+      uint8_t fl;
+      eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, res[o]);
+      if (flags) flags[r.i] = fl;
+    }
+    return;
+  }
+  const bool near = key < B.nnear;
+  const int kk = near ? key : key - B.nnear;
+  const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
+  const int o1 = (b1 << TB1) - 1, o2 = (b2 << TB2) - 1, o3 = (b3 << TB3) - 1;
+  for (long c0 = 0; c0 < (long)cnt; c0 += blockDim.x) {
+    const long j = start + c0 + threadIdx.x;
+    const bool valid = c0 + (long)threadIdx.x < (long)cnt;
+    TRec r{};
+    Stencil3<T> st;
+    double2 res[NO];
+    uint8_t fl = 0;
+    bool go = false, miss = false;
+    int l1 = 0, l2 = 0, l3 = 0;
+    if (valid) {
+      r = rec[j];
+      go = stencil3d<T, NO>(A, r.x, r.y, r.z, st, res, fl);
+      if (go) {
+        l1 = (st.p1 - 1 - o1) & (A.M1 - 1);
+        l2 = (st.p2 - 1 - o2) & (A.M2 - 1);
+        l3 = st.near ? ((st.p3 - 1 - o3) & (A.M3 - 1)) : (st.p3 - 1 - o3);
+        miss = st.near != near || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4;
+      }
+    }
+    double2 L[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      __syncthreads();   // the previous field's sums are done
+      for (int idx = threadIdx.x; idx < FSZ; idx += blockDim.x) {
+        const int z = idx / (F1 * F2), y = (idx / F1) % F2, xx = idx % F1;
+        const int g1 = (o1 + xx) & (A.M1 - 1), g2 = (o2 + y) & (A.M2 - 1);
+        cplx<T> v;
+        if (near) {
+          const int g3 = (o3 + z) & (A.M3 - 1);
+          v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+        } else {
+          const int g3 = min(max(o3 + z, 0), A.S - 1);
+          v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+        }
+        lds[idx] = v;
+      }
+      __syncthreads();
+      if (go && !miss) L[f] = lds_sum<T, F1, F2>(lds + (l3 * F2 + l2) * F1 + l1, st.w1, st.w2, st.w3);
+    }
+    if (!valid) continue;
+    if (go && miss) {
+      ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
+      continue;
+    }
+    if (go) finish3d<T, NF>(A, r.x, r.y, r.z, st, L, res, fl);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, res[o]);
+    if (flags) flags[r.i] = fl;
   }
 }
 
@@ -615,6 +846,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ 
 //      offs[key] + cnt[block][key] + (LDS-atomic rank within the block).
 constexpr int kBinBlocks = 256;
 constexpr int kMinPerTile = 1500;   // targets per tile below which the larger tiles are used
+constexpr int kMaxPerFieldTile = 512;   // Maxwell: targets per 16 x 16 x 8 tile below which fields are staged one by one
 constexpr int kBinUnroll = 4;
 constexpr int kBinLdsKeys = 32768;   // 128 KiB of LDS: one 1024-thread block per CU
 
@@ -789,9 +1021,12 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     Tl.nnear = Tl.nt1 * Tl.nt2 * Tl.nt3n;
     Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
   };
-  bool big = false;
+  bool big = false, fields = false;
   if (P.nf == 7) {
-    set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
+    // few targets per tile: 16 x 16 x 8 tiles staged one field at a time
+    set_tiles(4, 4, 3);
+    fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nkeys;
+    if (!fields) set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
   } else {
     set_tiles(4, 4, 3);
     if (T_ < (int64_t)kMinPerTile * Tl.nkeys) {
@@ -838,7 +1073,10 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 #define QPGF_TILED(NF_, A1_, A2_, A3_, BS_)                                                                      \
   hipLaunchKernelGGL((k_gather3d_tiled<T, NF_, A1_, A2_, A3_, BS_>), tg, dim3(BS_), 0, P.stream, A, Tl, g, f, rec, \
                      P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
-  if constexpr (sizeof(T) == 8) {
+  if (fields) {
+    hipLaunchKernelGGL((k_gather3d_fields<T, 4, 4, 3>), tg, dim3(256), 0, P.stream, A, Tl, g, f, rec, P.bin_hist,
+                       P.bin_offs, o, flags, P.bin_ovf, P.bin_novf);
+  } else if constexpr (sizeof(T) == 8) {
     if (P.nf == 7) QPGF_TILED(7, 3, 2, 2, 256);
     else if (big) QPGF_TILED(1, 5, 4, 3, 512);
     else QPGF_TILED(1, 4, 4, 3, 256);

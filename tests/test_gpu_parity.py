@@ -131,12 +131,13 @@ def test_maxwell3d_small(prec):
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
 @pytest.mark.parametrize("kind,shape", [(qpgf.KIND_GD3D, (64, 32, 32)), (qpgf.KIND_MAXWELL3D, (64, 32, 32)),
-                                        (qpgf.KIND_GD3D, (128, 128, 64))])
+                                        (qpgf.KIND_GD3D, (128, 128, 64)), (qpgf.KIND_MAXWELL3D, (128, 128, 32))])
 def test_binned_gather_large_target_count(prec, kind, shape):
     """T >= 65536 takes the binned path (targets sorted by grid tile); includes
     targets beyond the far slab and on the lattice, whose flags must follow them.
     On 128 x 128 x 64 the 16 x 16 x 8 tiles would hold about 170 targets each, so
-    the larger 32-node tiles are used."""
+    the larger 32-node tiles are used; Maxwell on 128 x 128 x 32 (about 310
+    targets per tile) stages the seven fields one at a time."""
     (M1, M2, M3), T = shape, 120_001
     k, a1, a2 = 5.3, 0.1, 0.4
     x = workloads.targets(T, 3, seed=9, zmax=1.2)
