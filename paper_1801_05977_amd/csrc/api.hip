@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "fft_device.h"
 #include "qpgf_internal.h"
 
 using namespace qpgf;
@@ -595,13 +596,15 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
     FftSeg sT{(long)goff, P.M2, __builtin_ctz((unsigned)P.M2), (long)M, (long)M, (long)M, 1, 0,
               fft_tile(P, P.M2, false, M), tb};
     tb += (sT.nbatch + sT.tile - 1) / sT.tile;
-    Lo.lds_T = std::max(Lo.lds_T, (long)sT.tile * (sT.n + 1));   // column transforms: padded rows
+    // column transforms: padded rows; plus the twiddles when they fit
+    Lo.lds_T = std::max(Lo.lds_T, (long)sT.tile * (sT.n + 1) +
+                                      (fft_twiddles_in_lds(sT.tile, sT.n + 1, sT.n, P.esize) ? sT.n : 0));
     FftSeg sR{(long)goff, M, __builtin_ctz((unsigned)M), 1, (long)P.M2, 1, 0, (long)M, fft_tile(P, M, true, P.M2), rrb};
     rrb += (sR.nbatch + sR.tile - 1) / sR.tile;
-    Lo.lds_R = std::max(Lo.lds_R, (long)sR.tile * sR.n);
+    Lo.lds_R = std::max(Lo.lds_R, (long)sR.tile * sR.n + (fft_twiddles_in_lds(sR.tile, sR.n, sR.n, P.esize) ? sR.n : 0));
     FftSeg sF{(long)foff, M, __builtin_ctz((unsigned)M), 1, (long)P.S, 1, 0, (long)M, fft_tile(P, M, true, P.S), frb};
     frb += (sF.nbatch + sF.tile - 1) / sF.tile;
-    Lo.lds_F = std::max(Lo.lds_F, (long)sF.tile * sF.n);
+    Lo.lds_F = std::max(Lo.lds_F, (long)sF.tile * sF.n + (fft_twiddles_in_lds(sF.tile, sF.n, sF.n, P.esize) ? sF.n : 0));
     std::memcpy(h + Lo.segT_off + i * sizeof(FftSeg), &sT, sizeof sT);
     std::memcpy(h + Lo.segR_off + i * sizeof(FftSeg), &sR, sizeof sR);
     std::memcpy(h + Lo.segF_off + i * sizeof(FftSeg), &sF, sizeof sF);

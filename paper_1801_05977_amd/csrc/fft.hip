@@ -40,7 +40,15 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, int 
     }
   }
   __syncthreads();
-  inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, tw, twlog2);
+  if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
+    // the n twiddles of this length, read once into LDS after the block's data
+    V* twl = buf + tile * pitch;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j << (twlog2 - log2n)];
+    __syncthreads();
+    inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, twl, log2n);
+  } else {
+    inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, tw, twlog2);
+  }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int t, e;
     if (es == 1) { t = idx / n; e = idx - t * n; }
@@ -84,7 +92,9 @@ hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in,
   if (n <= 1 || nbatch <= 0) return hipSuccess;
   const int log2n = __builtin_ctz((unsigned)n);
   int tile = fft_tile(P, n, es == 1, nbatch);
-  const size_t shm = (size_t)tile * (n + (es == 1 ? 0 : 1)) * sizeof(cplx<T>);
+  const int pitch = n + (es == 1 ? 0 : 1);
+  const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
+                     sizeof(cplx<T>);
   const long nblk = (nbatch + tile - 1) / tile;
   const cplx<T>* tw = nullptr;
   if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;

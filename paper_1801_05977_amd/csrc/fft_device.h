@@ -8,6 +8,14 @@
 #include "qpgf_internal.h"
 
 namespace qpgf {
+
+// A block of `tile` transforms of length n (row pitch `pitch`) also holds the n
+// twiddles of that length in LDS when both fit in 64 KiB; otherwise the passes
+// read the plan's twiddle table from global memory.
+__host__ __device__ inline bool fft_twiddles_in_lds(long tile, int pitch, int n, size_t esize) {
+  return ((size_t)tile * pitch + (size_t)n) * esize <= 65536;
+}
+
 namespace fftdev {
 
 template <typename V> __device__ __forceinline__ V c_add(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
