@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--query-instances", type=int, default=10000)
     ap.add_argument("--query-per", type=int, default=10000)
     ap.add_argument("--tol", type=float, default=1e-2)
+    ap.add_argument("--surrogate-wood", type=float, default=0.3,
+                    help="surrogate domain: instances with min |beta| below this take the plain method")
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the second timing at the grid that meets p99 <= 1e-6 against the lattice sum")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,26 +326,33 @@ def run_maxwell3d(args):
             "kernels_avg_ms": kern}
 
 
-def _instances_3d(n, seed, k_range=(1.0, 10.0), a_range=(-0.5, 0.5), min_beta=1e-3):
-    """n (k, alpha1, alpha2) with every |k^2 - |alpha + n|^2|^(1/2) >= min_beta (Wood anomalies redrawn)."""
+def _instances_3d(n, seed, k_range=(1.0, 10.0), a_range=(-0.5, 0.5), min_beta=1e-3, special_tol=1e-6, m3=64):
+    """n (k, alpha1, alpha2) with every |k^2 - |alpha + n|^2|^(1/2) >= min_beta (Wood anomalies redrawn) and
+    no propagating beta within special_tol of j3 pi (c~ = 1, |j3| <= m3 / 2; special coefficients redrawn)."""
     import numpy as np
     rng = np.random.default_rng(seed)
     out = []
+    j = np.arange(-12, 13)
+    J = np.arange(0, m3 // 2 + 1) * math.pi
     while len(out) < n:
         k, a1, a2 = rng.uniform(*k_range), rng.uniform(*a_range), rng.uniform(*a_range)
-        j = np.arange(-12, 13)
         d = k * k - (a1 + j[:, None]) ** 2 - (a2 + j[None, :]) ** 2
-        if np.sqrt(np.abs(d)).min() >= min_beta:
-            out.append((k, a1, a2))
+        if np.sqrt(np.abs(d)).min() < min_beta:
+            continue
+        b = np.sqrt(d[d > 0])
+        if b.size and np.abs(b[:, None] - J[None, :]).min() < special_tol:
+            continue
+        out.append((k, a1, a2))
     return np.array(out)
 
 
 def run_surrogate(args):
     """MLP surrogate of the smooth part vs the plain method (Algorithm 3.1, 256 x 256 x 64, complex64).
 
-    Training: `train_instances` instances (k ~ U[1,10], alpha ~ U[-1/2,1/2]^2, seed 4) x `train_per`
-    near-region targets, labels 10 L_N from qpgf_evaluate_smooth; Adam with a cosine learning rate, one
-    data order per ensemble member.  Queries: `query_instances` fresh instances (seed 5) x `query_per`
+    Training: `train_instances` instances (k ~ U[1,10], alpha ~ U[-1/2,1/2]^2, seed 4, min |beta| >=
+    `surrogate_wood`: near a Wood anomaly one mode's amplitude 1/beta is near-singular in (k, alpha), so
+    those instances are outside the surrogate's domain and fall back) x `train_per` near-region targets,
+    labels 10 L_N from qpgf_evaluate_smooth; Adam with a cosine learning rate, one data order per member.  Queries: `query_instances` fresh instances (seed 5) x `query_per`
     targets uniform in [0, 2pi]^2 x [-1, 1]; far, near-lattice and high-spread targets take the plain
     method.  A step is all queries through qpgf_surrogate_eval; the plain method is timed on the same
     queries as one qpgf_gd3d call per instance."""
@@ -355,7 +364,7 @@ def run_surrogate(args):
     P = qpgf.Plan(qpgf.KIND_GD3D, prec, *M)
     # ---- training data from the plain method
     t0 = time.perf_counter()
-    tr = _instances_3d(args.train_instances, seed=4)
+    tr = _instances_3d(args.train_instances, seed=4, min_beta=args.surrogate_wood)
     per = args.train_per
     xtr = torch.from_numpy(workloads.targets(per * 64, 3, seed=40, zmax=0.6)).cuda()
     rng = np.random.default_rng(41)
@@ -407,8 +416,8 @@ def run_surrogate(args):
     nfb = [0]
 
     def surrogate():
-        nfb[0] = mdl.evaluate(P, qi[:, 0], qi[:, 1], qi[:, 2], t_off, x, args.tol, wood_tol=1e-3, rmin=1e-3,
-                              out=out, fell_back=fell)[2]
+        nfb[0] = mdl.evaluate(P, qi[:, 0], qi[:, 1], qi[:, 2], t_off, x, args.tol, wood_tol=args.surrogate_wood,
+                              rmin=1e-3, out=out, fell_back=fell)[2]
     t_s = _timed(surrogate, args.steps, args.warmup)
     out_plain = P.out_tensor(T)
 
@@ -448,6 +457,7 @@ def run_surrogate(args):
             "data": "synthetic",
             "config": {"workload": f"gd3d surrogate: {nq} instances x {pq} targets, k~U[1,10] alpha~U[-0.5,0.5]^2",
                        "modes": [256, 256], "slices": 64, "members": args.members, "tol": args.tol,
+                       "surrogate_wood": args.surrogate_wood,
                        "train_samples": int(len(tr) * per), "train_steps_per_member": steps, "batch": B},
             "fallback_fraction": nfb[0] / T,
             "plain_method": {"value": T / t_p, "ms_per_step": t_p * 1e3},
