@@ -19,7 +19,7 @@ struct GArgs {
   int M1, M2, M3;          // 2D: M2 = transverse size, M3 = 1
   double h1, h2, h3;       // 2D: h2 = transverse spacing
   double ih1, ih2, ih3;    // reciprocals of the spacings
-  double hf;               // far-slab spacing
+  double hf, ihf;          // far-slab spacing and its reciprocal
   int S;                   // far-slab slices
   long fs, ffs;            // field strides (near, far)
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
@@ -146,7 +146,7 @@ __device__ __forceinline__ bool stencil3d(const GArgs& A, double x1, double x2, 
     for (int o = 0; o < NO; ++o) res[o] = nan2();
     return false;
   }
-  const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
+  const double v = (fabs(x3) - (A.c - A.hf)) * A.ihf;
   double s0 = floor(v);
   if (s0 > A.S - 3) {
     fl |= 4;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
       for (int o = 0; o < NO; ++o) res[o] = nan2();
       return;
     }
-    const double v = (fabs(x3) - (A.c - A.hf)) / A.hf;
+    const double v = (fabs(x3) - (A.c - A.hf)) * A.ihf;
     double s0 = floor(v);
     if (s0 > A.S - 3) {
       fl |= 4;
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(256) void k_gather2d_multi(const GatherInst* __rest
 // inside each tile, one-block exclusive scan, scatter into tile order.
 // ---------------------------------------------------------------------------
 struct BinArgs {
-  double c, ih1, ih2, ih3, hf;
+  double c, ih1, ih2, ih3, hf, ihf;
   int M1, M2, M3, S;
   TileArgs t;
 };
@@ -777,7 +777,7 @@ __device__ __forceinline__ uint32_t tile_key(const BinArgs& B, double x1, double
     const int b3 = (((int)floor(x3 * B.ih3)) & (B.M3 - 1)) >> B.t.tb3;
     return (uint32_t)((b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
   }
-  const double s0 = floor((fabs(x3) - (B.c - B.hf)) / B.hf);
+  const double s0 = floor((fabs(x3) - (B.c - B.hf)) * B.ihf);
   if (s0 > B.S - 3) return B.t.nkeys - 1;
   const int b3 = ((int)fmax(s0, 1.0)) >> B.t.tb3;
   return (uint32_t)(B.t.nnear + (b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
@@ -966,6 +966,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.ih2 = 1.0 / A.h2;
   A.ih3 = A.h3 > 0.0 ? 1.0 / A.h3 : 0.0;
   A.hf = P.p.far_h;
+  A.ihf = 1.0 / A.hf;
   A.S = P.S;
   A.fs = (long)P.ncell;
   A.ffs = (long)P.nfar;
@@ -998,6 +999,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   B.ih2 = A.ih2;
   B.ih3 = A.ih3;
   B.hf = A.hf;
+  B.ihf = A.ihf;
   B.M1 = P.M1;
   B.M2 = P.M2;
   B.M3 = P.M3;
@@ -1155,6 +1157,7 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.ih2 = 1.0 / A.h2;
   A.ih3 = 0.0;
   A.hf = P.p.far_h;
+  A.ihf = 1.0 / A.hf;
   A.S = P.S;
   A.fs = (long)M1 * P.M2;
   A.ffs = (long)M1 * P.S;
