@@ -91,6 +91,9 @@ void free_batch(Plan& P) {
 
 void free_plan(Plan& P) {
   free_batch(P);
+  if (P.side) (void)hipStreamDestroy(P.side);
+  if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
+  if (P.ev_join) (void)hipEventDestroy(P.ev_join);
   if (P.b_capture) (void)hipStreamDestroy(P.b_capture);
   if (P.b_upload_done) (void)hipEventDestroy(P.b_upload_done);
   if (P.b_host) (void)hipHostFree(P.b_host);
@@ -111,7 +114,6 @@ qpgf_status validate(const qpgf_params* p) {
   if (p->kind != QPGF_KIND_G2D && !pow2_in(p->m3, 16, 4096))
     return fail(QPGF_E_SIZE, "m3 must be a power of two in [16, 4096]");
   {
-    // one transform of the longest axis must fit the 64 KiB LDS of a block (two buffers)
     // one transform (padded for column axes) must fit the 64 KiB LDS buffer of a block
     const int lim = p->prec == QPGF_C128 ? 4096 : 8192;
     const bool bad = p->m1 > lim || p->m2 > lim / 2 || (p->kind != QPGF_KIND_G2D && p->m3 > lim / 2);
@@ -476,11 +478,34 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
   g_err.clear();
   qpgf_status st = check_plan(plan, kind);
   if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
   if (T < 0) return fail(QPGF_E_ARG, "T < 0");
   if (T > 0 && (!x || !out)) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
-  st = run_prepare(plan->P, k, a1, a2, 2);
+  if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  // The binning of the targets depends on the targets and the grid geometry
+  // only: it runs on a second stream while the grids are prepared (fork after
+  // the work already on the plan's stream, join before the gather).
+  const bool overlap = T > 0 && gather_uses_bins(P, T);
+  if (overlap) {
+    if (!P.side) HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+    if (!P.ev_fork) HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
+    if (!P.ev_join) HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(P.ev_fork, P.stream));
+    HIP_TRY(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+    HIP_TRY(launch_bin3d(P, x, T, P.side));
+    HIP_TRY(hipEventRecord(P.ev_join, P.side));
+  }
+  st = run_prepare(P, k, a1, a2, 2);
+  if (overlap) {
+    // the plan's stream owns the bin scratch again, also when the preparation failed
+    HIP_TRY(hipStreamWaitEvent(P.stream, P.ev_join, 0));
+  }
   if (st != QPGF_OK) return st;
-  return run_evaluate(plan->P, x, T, out, flags);
+  if (overlap) {
+    HIP_TRY(launch_gather_binned(P, x, T, out, flags));
+    return QPGF_OK;
+  }
+  return run_evaluate(P, x, T, out, flags);
 }
 
 qpgf_status qpgf_g2d(qpgf_plan* plan, double k, double alpha, const double* x, int64_t T, void* out,

@@ -850,9 +850,10 @@ constexpr int kMaxPerFieldTile = 512;   // Maxwell: targets per 16 x 16 x 8 tile
 constexpr int kBinUnroll = 4;
 constexpr int kBinLdsKeys = 32768;   // 128 KiB of LDS: one 1024-thread block per CU
 
+template <int KEYS>
 __global__ __launch_bounds__(1024) void k_bin_count(BinArgs B, const double* __restrict__ x, long T_, long chunk,
                                                     uint32_t* __restrict__ cnt) {
-  __shared__ uint32_t h[kBinLdsKeys];
+  __shared__ uint32_t h[KEYS];
   const int nk = B.t.nkeys;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) h[k] = 0u;
   __syncthreads();
@@ -904,10 +905,11 @@ __global__ __launch_bounds__(64 * kColGroups) void k_bin_colscan(uint32_t* __res
   }
 }
 
+template <int KEYS>
 __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __restrict__ x, long T_, long chunk,
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ offs, TRec* __restrict__ rec) {
-  __shared__ uint32_t cur[kBinLdsKeys];
+  __shared__ uint32_t cur[KEYS];
   const int nk = B.t.nkeys;
   const uint32_t* row = cnt + (long)blockIdx.x * nk;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) cur[k] = offs[k] + row[k];
@@ -941,8 +943,11 @@ __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __r
   }
 }
 
+enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
+
 template <typename T>
-hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags, int smooth = 0) {
+hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags, int smooth = 0,
+                       int mode = kGatherAll, hipStream_t bin_stream = nullptr) {
   GArgs A;
   A.k = P.last_k;
   A.a1 = P.last_a1;
@@ -1024,51 +1029,90 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
   };
   bool big = false, fields = false;
-  if (P.nf == 7) {
-    // few targets per tile: 16 x 16 x 8 tiles staged one field at a time
-    set_tiles(4, 4, 3);
-    fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nkeys;
-    if (!fields) set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
+  hipError_t e = hipSuccess;
+  if (mode == kGatherBinned) {
+    // the configuration launch_bin3d used for these targets
+    if (P.bt_T != T_ || P.bt_x != x) return hipErrorInvalidValue;
+    Tl.tb1 = P.bt[0];
+    Tl.tb2 = P.bt[1];
+    Tl.tb3 = P.bt[2];
+    Tl.nt1 = P.bt[3];
+    Tl.nt2 = P.bt[4];
+    Tl.nt3n = P.bt[5];
+    Tl.nnear = P.bt[6];
+    Tl.nkeys = P.bt[7];
+    big = P.bt_big;
+    fields = P.bt_fields;
   } else {
-    set_tiles(4, 4, 3);
-    if (T_ < (int64_t)kMinPerTile * Tl.nkeys) {
-      big = true;
-      set_tiles(5, sizeof(T) == 8 ? 4 : 5, 3);
+    if (P.nf == 7) {
+      // few targets per tile: 16 x 16 x 8 tiles staged one field at a time
+      set_tiles(4, 4, 3);
+      fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nkeys;
+      if (!fields) set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
+    } else {
+      set_tiles(4, 4, 3);
+      if (T_ < (int64_t)kMinPerTile * Tl.nkeys) {
+        big = true;
+        set_tiles(5, sizeof(T) == 8 ? 4 : 5, 3);
+      }
     }
+    e = ensure_bin_scratch(P, T_, Tl.nkeys);
+    if (e != hipSuccess) return e;
+    const int bt[8] = {Tl.tb1, Tl.tb2, Tl.tb3, Tl.nt1, Tl.nt2, Tl.nt3n, Tl.nnear, Tl.nkeys};
+    for (int q = 0; q < 8; ++q) P.bt[q] = bt[q];
+    P.bt_big = big;
+    P.bt_fields = fields;
+    P.bt_T = T_;
+    P.bt_x = x;
   }
-  hipError_t e = ensure_bin_scratch(P, T_, Tl.nkeys);
-  if (e != hipSuccess) return e;
   TRec* rec = reinterpret_cast<TRec*>(P.bin_rec);
   const bool lds_bins = Tl.nkeys <= kBinLdsKeys;
   const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
+  const hipStream_t bs = bin_stream ? bin_stream : P.stream;
+  if (mode != kGatherBinned) {
   {
-    KernelTimer t(P, QPGF_T_BIN);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.bin_novf, 1L);
+    KernelTimer t(P, QPGF_T_BIN, bs);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.bin_novf, 1L);
     if (lds_bins) {
-      hipLaunchKernelGGL(k_bin_count, dim3(kBinBlocks), dim3(1024), 0, P.stream, B, x, (long)T_, chunk, P.bin_cnt);
-      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, P.stream, P.bin_cnt,
+      // LDS histogram sized to the key count (small ones leave LDS to kernels running beside)
+      if (Tl.nkeys <= 4096)
+        hipLaunchKernelGGL(k_bin_count<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt);
+      else if (Tl.nkeys <= 16384)
+        hipLaunchKernelGGL(k_bin_count<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt);
+      else
+        hipLaunchKernelGGL(k_bin_count<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                           P.bin_cnt);
+      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.bin_cnt,
                          Tl.nkeys,
                          kBinBlocks, P.bin_hist);
     } else {
       // large key spaces: one global atomic rank per target
-      hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, P.stream, P.bin_hist,
+      hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, bs, P.bin_hist,
                          (long)Tl.nkeys);
-      hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, P.stream, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
+      hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, bs, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
     }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, P.stream, P.bin_hist, P.bin_offs, Tl.nkeys);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, bs, P.bin_hist, P.bin_offs, Tl.nkeys);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
-    KernelTimer t(P, QPGF_T_BIN_PLACE);
-    if (lds_bins)
-      hipLaunchKernelGGL(k_bin_place, dim3(kBinBlocks), dim3(1024), 0, P.stream, B, x, (long)T_, chunk, P.bin_cnt,
+    KernelTimer t(P, QPGF_T_BIN_PLACE, bs);
+    if (lds_bins && Tl.nkeys <= 4096)
+      hipLaunchKernelGGL(k_bin_place<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt,
                          P.bin_offs, rec);
+    else if (lds_bins && Tl.nkeys <= 16384)
+      hipLaunchKernelGGL(k_bin_place<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt,
+                         P.bin_offs, rec);
+    else if (lds_bins)
+      hipLaunchKernelGGL(k_bin_place<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                         P.bin_cnt, P.bin_offs, rec);
     else
-      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, P.stream, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
+      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  }
+  if (mode == kBinOnly) return hipSuccess;
   {
   KernelTimer t(P, QPGF_T_GATHER);
   const dim3 tg(Tl.nkeys);
@@ -1194,6 +1238,22 @@ hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T_, void* out)
 hipError_t launch_gather(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {
   if (T_ <= 0) return hipSuccess;
   return P.p.prec == QPGF_C128 ? gather_impl<double>(P, x, T_, out, flags) : gather_impl<float>(P, x, T_, out, flags);
+}
+
+bool gather_uses_bins(const Plan& P, int64_t T_) {
+  return P.dim == 3 && P.bin_min_targets >= 0 && T_ >= P.bin_min_targets;
+}
+
+hipError_t launch_bin3d(Plan& P, const double* x, int64_t T_, hipStream_t stream) {
+  if (!gather_uses_bins(P, T_)) return hipErrorInvalidValue;
+  return P.p.prec == QPGF_C128 ? gather_impl<double>(P, x, T_, nullptr, nullptr, 0, kBinOnly, stream)
+                               : gather_impl<float>(P, x, T_, nullptr, nullptr, 0, kBinOnly, stream);
+}
+
+hipError_t launch_gather_binned(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags) {
+  if (!gather_uses_bins(P, T_)) return hipErrorInvalidValue;
+  return P.p.prec == QPGF_C128 ? gather_impl<double>(P, x, T_, out, flags, 0, kGatherBinned)
+                               : gather_impl<float>(P, x, T_, out, flags, 0, kGatherBinned);
 }
 
 }  // namespace qpgf

@@ -146,6 +146,14 @@ struct Plan {
   uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count
+  // tile configuration of the last binning (launch_bin3d), used by launch_gather_binned
+  int bt[8] = {};                      // tb1, tb2, tb3, nt1, nt2, nt3n, nnear, nkeys
+  bool bt_big = false, bt_fields = false;
+  int64_t bt_T = -1;
+  const double* bt_x = nullptr;
+  // second stream for the binning while the grids are prepared, and its events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // FFT tiles chosen by the autotuner: key (n << 2) | rows | c64 << 1
   std::map<int, int> fft_tiles;
@@ -175,16 +183,18 @@ struct Plan {
 struct KernelTimer {
   Plan& P;
   int id;
+  hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  KernelTimer(Plan& p, int i) : P(p), id(i) {
+  // events on stream st (default: the plan's stream)
+  KernelTimer(Plan& p, int i, hipStream_t st = nullptr) : P(p), id(i), s(st ? st : p.stream) {
     if (P.timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-      (void)hipEventRecord(a, P.stream);
+      (void)hipEventRecord(a, s);
     else
       a = b = nullptr;
   }
   ~KernelTimer() {
     if (a && b) {
-      (void)hipEventRecord(b, P.stream);
+      (void)hipEventRecord(b, s);
       P.pending.push_back({id, a, b});
     }
   }
@@ -213,5 +223,11 @@ hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, 
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
 hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
+// The 3D calculation step in two halves: binning of the targets by grid tile
+// (needs only the targets and the plan's geometry, so it may run on another
+// stream while the grids are prepared) and the tiled gather on the plan's stream.
+bool gather_uses_bins(const Plan& P, int64_t T);
+hipError_t launch_bin3d(Plan& P, const double* x, int64_t T, hipStream_t stream);
+hipError_t launch_gather_binned(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 
 }  // namespace qpgf
