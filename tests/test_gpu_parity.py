@@ -175,6 +175,31 @@ def test_prepare_then_evaluate_in_chunks_matches_single_call():
     assert torch.equal(whole, again)            # deterministic
 
 
+def test_overlapped_binning_back_to_back_and_after_a_failed_prepare():
+    """qpgf_gd3d bins the targets on a second stream while the grids are prepared.  Calls issued back to
+    back on one plan (different targets, no host synchronisation), and a call after a preparation that
+    failed (Wood anomaly), give exactly what the sequential prepare + evaluate path gives."""
+    M = (64, 64, 32)
+    xa = dev(workloads.targets(70_000, 3, seed=21))
+    xb = dev(workloads.targets(90_000, 3, seed=22))
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C64, *M)
+    ga = P(3.7, 0.2, 0.35, xa)
+    gb = P(5.1, -0.3, 0.1, xb)
+    with pytest.raises(qpgf.QpgfError) as e:
+        P(1.25, 0.2, 0.35, xa)            # |alpha + (1, 0)| = 1.25: beta = 0
+    assert e.value.status == 2
+    gc = P(3.7, 0.2, 0.35, xa)
+    Q = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C64, *M)
+    Q.prepare(3.7, 0.2, 0.35)
+    ra = Q.evaluate(xa)
+    Q.prepare(5.1, -0.3, 0.1)
+    rb = Q.evaluate(xb)
+    for g, r in ((ga, ra), (gb, rb), (gc, ra)):
+        assert torch.equal(torch.isnan(g), torch.isnan(r))
+        ok = ~torch.isnan(g)
+        assert torch.equal(g[ok], r[ok])
+
+
 # ----------------------------------------------------------------------------- edge cases
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
