@@ -17,6 +17,7 @@ namespace qpgf {
 namespace {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
@@ -277,11 +278,11 @@ __global__ void k_features(const double* __restrict__ q, long M, double c, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: one block takes 128 queries through every ensemble member.
+// Fused inference: one block takes kIR queries through every ensemble member.
 // Features, then four hidden layers with the activations of the tile held in
-// LDS (two ping-pong buffers), weights read from L2, bias + GELU in the MFMA
-// epilogue, and the fp32 head.  Four waves; wave w computes output columns
-// [64 w, 64 w + 64) of a hidden layer for all 128 rows (8 x 4 tiles of 16 x 16).
+// LDS (two ping-pong buffers), weights read from L2, the K = 32 bf16 matrix
+// instruction, bias + GELU in the epilogue, and the fp32 head.  Four waves; wave w computes output columns
+// [64 w, 64 w + 64) of a hidden layer for all rows of the tile (16 x 16 tiles).
 // The rounding points are those of the layer-by-layer path: bf16 features,
 // fp32 accumulation plus fp32 bias, GELU in fp32, bf16 activations.
 // ---------------------------------------------------------------------------
@@ -302,21 +303,24 @@ __device__ __forceinline__ void infer_layer(const __bf16* __restrict__ X, int pi
                                             const float* __restrict__ bias, __bf16* __restrict__ Y) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  f32x4 acc[8][4];
+  constexpr int RT = kIR / 16;   // row tiles of 16
+  f32x4 acc[RT][4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 b[4];
+  // v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) + r] and
+  // B[8 (l / 16) + r][l % 16], r < 8 (16-byte fragments)
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 b[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      b[j] = *reinterpret_cast<const bf16x4*>(W + (long)(64 * w + 16 * j + lr) * K + k0 + 4 * lg);
+      b[j] = *reinterpret_cast<const bf16x8*>(W + (long)(64 * w + 16 * j + lr) * K + k0 + 8 * lg);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(X + (16 * i + lr) * pitchX + k0 + 4 * lg);
+    for (int i = 0; i < RT; ++i) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(X + (16 * i + lr) * pitchX + k0 + 8 * lg);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -324,7 +328,7 @@ __device__ __forceinline__ void infer_layer(const __bf16* __restrict__ X, int pi
     const int col = 64 * w + 16 * j + lr;
     const float bb = bias[col];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) Y[(16 * i + 4 * lg + r) * kIP + col] = (__bf16)gelu(acc[i][j][r] + bb);
   }
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A, const double* __
     infer_layer<256>(B1, kIP, wb + 3 * 256 * 256, p + A.off_b[3], B2);
     __syncthreads();
     // head: thread t -> row t / 2, output t % 2
-    {
+    if (threadIdx.x < 2 * kIR) {
       const int row = threadIdx.x >> 1, o = threadIdx.x & 1;
       const float* W4 = p + A.off_w4 + o * 256;
       float s_ = p[A.off_b4 + o];
