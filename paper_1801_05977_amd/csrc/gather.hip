@@ -355,14 +355,6 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
   }
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD runs a
-// contiguous range of logical blocks (neighbouring grid tiles) and its L2 holds
-// one region of the grid.
-__device__ __forceinline__ long xcd_block() {
-  const unsigned nb = gridDim.x, b = blockIdx.x, x = b & 7u, per = nb >> 3, rem = nb & 7u;
-  return (long)x * per + min(x, rem) + (b >> 3);
-}
-
 // 3D, unsorted targets: one thread per target, stencil read from global memory.
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_gather3d(GArgs A, const cplx<T>* __restrict__ grid,

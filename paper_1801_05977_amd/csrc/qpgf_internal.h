@@ -37,7 +37,6 @@ __host__ __device__ inline double2 cdiv(double2 a, double2 b) {
   double r = b.x / b.y, d = b.x * r + b.y;
   return mk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
 }
-__host__ __device__ inline double2 crecip(double2 b) { return cdiv(mk(1.0, 0.0), b); }
 // e^{i z} for complex z.
 __device__ inline double2 cexpi(double2 z) {
   double s, c;
