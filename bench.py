@@ -85,8 +85,8 @@ def cpu_baseline(x_np, info, n_sample):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
     ap.add_argument("--targets", type=int, default=10_000_000)
     ap.add_argument("--modes", default="256,256,64")
