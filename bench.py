@@ -110,8 +110,8 @@ def main():
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 FETCH/WRITE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "single-GPU build: this benchmark runs on exactly one GPU (--gpus 1); "
-                                   "the multi-GPU decomposition is a design note, not implemented"}))
+        print(json.dumps({"error": "this implementation runs on exactly one GPU (--gpus 1); "
+                                   "the decomposition over several GPUs is described, not implemented"}))
         sys.exit(2)
 
     import numpy as np

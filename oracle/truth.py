@@ -120,7 +120,7 @@ def _lattice(a1, a2, R):
 
 
 def _sum3d(k, a1, a2, x, tol, order, weights, max_terms, chunk=1 << 21):
-    """Shared driver: sum over the lattice of beta^-1 e^{...} times weights(xi1,xi2,b,sgn)."""
+    """Shared summation: over the lattice of beta^-1 e^{...} times weights(xi1,xi2,b,sgn)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     ncomp = weights(np.zeros(1), np.zeros(1), np.ones(1, complex), 1.0).shape[0]
     out = np.zeros((len(x), ncomp), dtype=np.complex128)

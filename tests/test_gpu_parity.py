@@ -2,7 +2,7 @@
 
 Stage checks compare coefficient fills, grids and far slabs element by element;
 end-to-end checks compare G, G_d and the Maxwell tensor at seeded targets.
-Bars (spec tolerances): complex128 path max parity error <= 1e-10,
+Bars: complex128 path max parity error <= 1e-10,
 complex64 path <= 1e-5, where the parity error of a result set is
 max_i |g_i - o_i| / max(|o_i|, s), s = RMS |o| over the set (a pointwise
 relative error that does not blow up at isolated zeros of G).
