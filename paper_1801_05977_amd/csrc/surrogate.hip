@@ -344,23 +344,46 @@ const char* qpgf_mlp_last_error(void) { return s_err.c_str(); }
 // ---------------------------------------------------------------------------
 namespace {
 
+// Targets of one instance are contiguous, so the lanes of a wave that belong to the same
+// instance form one run of lanes; each run adds its fallback count with one atomic (one atomic
+// per target on a single counter per instance serialises the whole pass).
 __global__ void k_count_fallback(const uint8_t* __restrict__ fell, const void* __restrict__ qinst, int n_inst,
                                  size_t isz, size_t t0off, long T, uint32_t* __restrict__ counts,
                                  uint32_t* __restrict__ cursor, const uint32_t* __restrict__ offs,
                                  uint32_t* __restrict__ fidx, int pass) {
   const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= T || !fell[m]) return;
-  // instance of target m: binary search on the instances' first target
-  int lo = 0, hi = n_inst - 1;
-  const char* base = static_cast<const char*>(qinst);
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const long t0 = *reinterpret_cast<const long*>(base + mid * isz + t0off);
-    if (t0 <= m) lo = mid;
-    else hi = mid - 1;
+  const bool in = m < T;
+  const bool f = in && fell[m];
+  int lo = n_inst;  // lanes past the end form a run of their own that counts nothing
+  if (in) {
+    // instance of target m: binary search on the instances' first target
+    int l = 0, hi = n_inst - 1;
+    const char* base = static_cast<const char*>(qinst);
+    while (l < hi) {
+      const int mid = (l + hi + 1) >> 1;
+      const long t0 = *reinterpret_cast<const long*>(base + mid * isz + t0off);
+      if (t0 <= m) l = mid;
+      else hi = mid - 1;
+    }
+    lo = l;
   }
-  if (pass == 0) atomicAdd(&counts[lo], 1u);
-  else fidx[offs[lo] + atomicAdd(&cursor[lo], 1u)] = (uint32_t)m;
+  const int lane = __lane_id();
+  const int prev = __shfl_up(lo, 1);
+  const unsigned long long H = __ballot(lane == 0 || prev != lo);  // first lane of each run
+  const unsigned long long F = __ballot(f);
+  const unsigned long long upto = (2ull << lane) - 1;  // lanes 0..lane
+  const int s = 63 - __clzll(H & upto);
+  const unsigned long long after = H & ~upto;
+  const int e = after ? __ffsll((long long)after) - 1 : 64;
+  const unsigned long long run = (e == 64 ? ~0ull : ((1ull << e) - 1)) & ~((1ull << s) - 1);
+  const unsigned n = (unsigned)__popcll(F & run);
+  unsigned first = 0;
+  if (lane == s && n && lo < n_inst) {
+    if (pass == 0) atomicAdd(&counts[lo], n);
+    else first = atomicAdd(&cursor[lo], n);
+  }
+  first = __shfl(first, s);
+  if (pass == 1 && f) fidx[offs[lo] + first + (unsigned)__popcll(F & run & ((1ull << lane) - 1))] = (uint32_t)m;
 }
 
 __global__ void k_pick(const double* __restrict__ x, const uint32_t* __restrict__ idx, long n, double* __restrict__ y) {
