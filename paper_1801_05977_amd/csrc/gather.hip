@@ -640,6 +640,60 @@ __global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T
 }
 
 // 2D: G (Algorithm 2.1).
+// 4 x 4 stencil sum of a 2D grid: rows[b] is the first element of stencil row b, i0 the
+// first x1 node (periodic in x1).
+template <typename T>
+__device__ __forceinline__ double2 stencil2d_scalar(const cplx<T>* __restrict__ g, const long rows[4], int i0,
+                                                    int M1, const T w1[4], const T w2[4]) {
+  Acc<T> acc;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc.add(w2[b] * w1[a], g[rows[b] + ((i0 + a) & (M1 - 1))]);
+  return acc.get();
+}
+template <typename T>
+__device__ __forceinline__ double2 stencil2d(const cplx<T>* __restrict__ g, const long rows[4], int i0, int M1,
+                                             const T w1[4], const T w2[4]) {
+  return stencil2d_scalar<T>(g, rows, i0, M1, w1, w2);
+}
+// complex64 stencil rows.  Scattered targets make every load of a lane a cache lookup of its
+// own, so a row of 4 nodes that does not wrap in x1 (32 contiguous bytes, 8-byte aligned) is
+// read with two 16-byte loads instead of four 8-byte ones.
+struct __attribute__((aligned(8))) F4a8 {
+  float a, b, c, d;
+};
+// sum_a w[a] r[a] over the 4 nodes at r
+__device__ __forceinline__ float2 row4(const float2* __restrict__ r, const float w[4]) {
+  const F4a8 lo = *reinterpret_cast<const F4a8*>(r);
+  const F4a8 hi = *reinterpret_cast<const F4a8*>(r + 2);
+  float re = w[0] * lo.a, im = w[0] * lo.b;
+  re = fmaf(w[1], lo.c, re);
+  im = fmaf(w[1], lo.d, im);
+  re = fmaf(w[2], hi.a, re);
+  im = fmaf(w[2], hi.b, im);
+  re = fmaf(w[3], hi.c, re);
+  im = fmaf(w[3], hi.d, im);
+  return make_float2(re, im);
+}
+
+template <>
+__device__ __forceinline__ double2 stencil2d<float>(const float2* __restrict__ g, const long rows[4], int i0, int M1,
+                                                    const float w1[4], const float w2[4]) {
+  if (i0 > M1 - 4) return stencil2d_scalar<float>(g, rows, i0, M1, w1, w2);
+  float2 rs[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) rs[b] = row4(g + rows[b] + i0, w1);
+  float re = 0.f, im = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    re = fmaf(w2[b], rs[b].x, re);
+    im = fmaf(w2[b], rs[b].y, im);
+  }
+  return mk(re, im);
+}
+
+// One target of Algorithm 2.1 step 2.
 template <typename T>
 __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                              const cplx<T>* __restrict__ far, const double* __restrict__ x, long i,
@@ -653,14 +707,10 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
   } else {
     double n1;
     const double t = reduce_cell(x1, n1);
-    double w1[4], w2[4];
-    int i1[4];
-    {
-      const double u = t / A.h1, p = floor(u);
-      lag4(u - p, w1);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) i1[a] = ((int)p - 1 + a) & (A.M1 - 1);
-    }
+    T w1[4], w2[4];
+    const double u = t * A.ih1, p = floor(u);
+    lag4<T>((T)(u - p), w1);
+    const int i0 = ((int)p - 1) & (A.M1 - 1);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
     const double2 phase = mk(pc, ps);
@@ -669,21 +719,21 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
     const cplx<T>* g = grid;
     bool bad = false;
     if (is_near) {
-      const double u = x2 / A.h2, p = floor(u);
-      lag4(u - p, w2);
+      const double u2 = x2 * A.ih2, p2 = floor(u2);
+      lag4<T>((T)(u2 - p2), w2);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p - 1 + b) & (A.M2 - 1)) * A.M1;
+      for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
     } else {
       fl |= 2;
       g = far;
-      const double v = (fabs(x2) - (A.c - A.hf)) / A.hf;
+      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
       double s0 = floor(v);
       if (s0 > A.S - 3) {
         bad = true;
         fl |= 4;
       } else {
         s0 = fmax(s0, 1.0);
-        lag4(v - s0, w2);
+        lag4<T>((T)(v - s0), w2);
 #pragma unroll
         for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
       }
@@ -691,12 +741,7 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
     if (bad) {
       res = nan2();
     } else {
-      Acc<T> acc;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc.add((T)(w2[b] * w1[a]), g[rows[b] + i1[a]]);
-      double2 Lt = acc.get();
+      double2 Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
       if (is_near) {
         const double r = sqrt(t * t + x2 * x2);
         if (r <= A.rmin || r == 0.0) {
