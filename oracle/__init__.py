@@ -19,8 +19,12 @@ Two oracles live here:
   direct (non-FFT) DFT sums, tensor-product cubic Lagrange interpolation and
   the exact singular add-back.  This judges *parity*.
 
+* ``grad2d`` -- the same for the first derivatives of the 2D G (Section
+  2.4.1): differentiated coefficients, the singular parts h1, h2 and their
+  Fourier coefficients by Hankel transforms, add-back at the target.
+
 ``cutoffs`` holds the smooth cut-off functions X and Y_eps (Section 6 states
 only that they are C^8; the reading used is documented there).
 """
 
-from . import cutoffs, truth, method  # noqa: F401
+from . import cutoffs, truth, method, grad2d  # noqa: F401

@@ -107,6 +107,43 @@ def g2d(k, alpha, x, tol=1e-17, max_terms=2_000_000):
     return out
 
 
+def _radius_2d_grad(k, z, tol):
+    """Smallest A >= k + 1 with 2 m(A) e^{-(A - k) z} / (1 - e^{-z}) <= tol, m(A) = A / sqrt(A^2 - k^2).
+
+    Bounds the tail of the differentiated series: a term of |alpha_n| >= A has
+    |alpha_n| / kappa_n <= m(A) and |beta_n| / kappa_n = 1, and e^{-kappa_n z} <= e^{-(|alpha_n| - k) z}.
+    """
+    k = abs(k)
+    A = k + 1.0
+    for _ in range(2000):
+        m = A / math.sqrt(A * A - k * k)
+        if 2.0 * m * math.exp(-(A - k) * z) / (-math.expm1(-z)) <= tol:
+            return A
+        A = max(A * 1.05, A + 1.0)
+    raise ValueError("2D series: point too close to the plane x2 = 0")
+
+
+def g2d_grad(k, alpha, x, tol=1e-17, max_terms=4_000_000):
+    """(dG/dx1, dG/dx2) of (1.2) at targets x[T,2] (x2 != 0), differentiated term by term:
+    d/dx1 multiplies a term by i alpha_n, d/dx2 by i beta_n sgn(x2)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    out = np.empty((len(x), 2), dtype=np.complex128)
+    for i, (x1, x2) in enumerate(x):
+        z = abs(x2)
+        if z == 0.0:
+            raise ValueError("2D series needs x2 != 0")
+        A = _radius_2d_grad(k, z, tol)
+        n = np.arange(math.ceil(-A - alpha), math.floor(A - alpha) + 1, dtype=np.float64)
+        if n.size > max_terms:
+            raise ValueError("2D series: too many terms")
+        an = alpha + n
+        b = beta(k, an)
+        e = 1j / (4 * math.pi) * np.exp(1j * an * x1 + 1j * b * z) / b
+        out[i, 0] = np.sum(1j * an * e)
+        out[i, 1] = np.sign(x2) * np.sum(1j * b * e)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # 3D: eigenfunction expansion (1.3) and the Maxwell tensor (1.4)
 # ----------------------------------------------------------------------------
