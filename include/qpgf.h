@@ -68,7 +68,8 @@ typedef enum { QPGF_C128 = 0, QPGF_C64 = 1 } qpgf_prec;
 typedef enum {
   QPGF_KIND_G2D = 0,       /* Algorithm 2.1 */
   QPGF_KIND_GD3D = 1,      /* Algorithm 3.1 */
-  QPGF_KIND_MAXWELL3D = 2  /* Algorithm 4.1 */
+  QPGF_KIND_MAXWELL3D = 2, /* Algorithm 4.1 */
+  QPGF_KIND_G2D_GRAD = 3   /* first derivatives of the 2D G (Section 2.4.1) */
 } qpgf_kind;
 
 /* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
@@ -115,7 +116,9 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
 /* Validate *p, allocate the plan's device buffers on the current HIP device and
  * compute its parameter-only tables (quadrature nodes, FFT twiddles, and in 2D
  * the k- and alpha-independent singular coefficients F-hat_1, F-hat_2 of
- * eqs. 2.4 / 2.5, which Remark 2.1 lets one precompute once).  Synchronous.
+ * eqs. 2.4 / 2.5, which Remark 2.1 lets one precompute once; for
+ * QPGF_KIND_G2D_GRAD instead the k- and alpha-independent parts of the
+ * coefficients of the singular parts h1, h2 of Section 2.4.1).  Synchronous.
  * *out receives the plan; release it with qpgf_plan_destroy. */
 qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out);
 
@@ -136,7 +139,8 @@ qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2);
 
 /* Calculation step (Algorithm 2.1 / 3.1 / 4.1 step 2) for T targets against the
  * last prepared instance.  x: device float64 [T][dim]; out: device complex
- * ([T] or [T][6]); flags: device uint8 [T] or NULL.  T = 0 is a no-op. */
+ * ([T], [T][6] for MAXWELL3D, [T][2] for G2D_GRAD); flags: device uint8 [T] or
+ * NULL.  T = 0 is a no-op. */
 qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags);
 
 /* prepare + evaluate: G (kind G2D), G_d (GD3D) and GG (MAXWELL3D) at T targets. */
@@ -146,6 +150,25 @@ qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
                       const double* x, int64_t T, void* out, uint8_t* flags);
 qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alpha2,
                            const double* x, int64_t T, void* out, uint8_t* flags);
+
+/* prepare + evaluate of the gradient of the 2D G (Section 2.4.1), plan of kind
+ * QPGF_KIND_G2D_GRAD.  K1 = e^{-i alpha x1} dG/dx1 and K2 = e^{-i alpha x1} dG/dx2
+ * are periodic like K; the plan's two fields hold K_p - h_p (coefficients
+ * i(alpha + j1) K-hat_j - H-hat_1j and i j2 (pi/c~) K-hat_j - H-hat_2j, the
+ * Fourier coefficients H-hat of the singular parts h1, h2 from the plan's
+ * tables), and the far slab the series (1.2) differentiated term by term.  At a
+ * target the 16-point interpolant of each field plus h_p in FP64 (r < 2 eps),
+ * times e^{i alpha x1}; beyond c the far slab, times sgn(x2) for x2.  h2 is
+ * taken with x2 ln|x| as its logarithmic term (the expansion of
+ * d/dx2 H0(k|x|)).  x: device float64 [T][2]; out: device complex [T][2] =
+ * (dG/dx1, dG/dx2) per target, in the plan's precision; flags as for qpgf_g2d
+ * (1: within lattice_rmin of a lattice point, 2: far branch, 4: beyond the far
+ * slab, 8: non-finite input; the flagged results are NaN).  Ownership: the
+ * caller owns x, out and flags; the call is stream-ordered on the plan's stream.
+ * Errors: QPGF_E_ARG for a plan of another kind, T < 0 or NULL pointers with
+ * T > 0; QPGF_E_WOOD / QPGF_E_SPECIAL for excluded instances (before any launch). */
+qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha,
+                          const double* x, int64_t T, void* out, uint8_t* flags);
 
 /* Batched form of Algorithm 2.1: n_inst independent instances in one call.
  * Instance i has wavenumber k[i], alpha[i] and x1 size m1[i] (a power of two,

@@ -100,23 +100,25 @@ void free_plan(Plan& P) {
   for (void* q : {P.b_grid, P.b_far, P.b_desc})
     if (q) (void)hipFree(q);
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
-                  P.twf,  P.F1,  P.F2,   P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
+                  P.twf,  P.F1,  P.F2,   P.D2, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
 
+bool kind_is_2d(int kind) { return kind == QPGF_KIND_G2D || kind == QPGF_KIND_G2D_GRAD; }
+
 qpgf_status validate(const qpgf_params* p) {
   if (!p) return fail(QPGF_E_ARG, "params is NULL");
-  if (p->kind < 0 || p->kind > 2) return fail(QPGF_E_ARG, "unknown kind");
+  if (p->kind < 0 || p->kind > 3) return fail(QPGF_E_ARG, "unknown kind");
   if (p->prec != QPGF_C128 && p->prec != QPGF_C64) return fail(QPGF_E_ARG, "unknown precision");
   if (!pow2_in(p->m1, 16, 4096) || !pow2_in(p->m2, 16, 4096))
     return fail(QPGF_E_SIZE, "m1 and m2 must be powers of two in [16, 4096]");
-  if (p->kind != QPGF_KIND_G2D && !pow2_in(p->m3, 16, 4096))
+  if (!kind_is_2d(p->kind) && !pow2_in(p->m3, 16, 4096))
     return fail(QPGF_E_SIZE, "m3 must be a power of two in [16, 4096]");
   {
     // one transform (padded for column axes) must fit the 64 KiB LDS buffer of a block
     const int lim = p->prec == QPGF_C128 ? 4096 : 8192;
-    const bool bad = p->m1 > lim || p->m2 > lim / 2 || (p->kind != QPGF_KIND_G2D && p->m3 > lim / 2);
+    const bool bad = p->m1 > lim || p->m2 > lim / 2 || (!kind_is_2d(p->kind) && p->m3 > lim / 2);
     if (bad)
       return fail(QPGF_E_SIZE, "m1 <= 4096; complex128 column axes (m2, and m3 in 3D) <= 2048");
   }
@@ -283,7 +285,7 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
   p->c_tilde = 1.0;
   p->eps = 0.2;
   p->quad_q = 64;
-  const int mt = (kind == QPGF_KIND_G2D) ? m2 : m3;
+  const int mt = kind_is_2d(kind) ? m2 : m3;
   p->far_h = mt > 0 ? p->c_tilde / (mt / 2) : 0.0;
   p->far_zmax = p->c_tilde;
   p->wood_tol = 1e-3;
@@ -301,8 +303,8 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   if (!plan) return fail(QPGF_E_NOMEM, "host allocation failed");
   Plan& P = plan->P;
   P.p = *p;
-  P.dim = (p->kind == QPGF_KIND_G2D) ? 2 : 3;
-  P.nf = (p->kind == QPGF_KIND_MAXWELL3D) ? 7 : 1;
+  P.dim = kind_is_2d(p->kind) ? 2 : 3;
+  P.nf = (p->kind == QPGF_KIND_MAXWELL3D) ? 7 : (p->kind == QPGF_KIND_G2D_GRAD) ? 2 : 1;
   P.M1 = p->m1;
   P.M2 = p->m2;
   P.M3 = (P.dim == 3) ? p->m3 : 1;
@@ -385,7 +387,33 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
     PLAN_ST(upload(&P.tw, tw));
     PLAN_ST(upload(&P.twf, twf));
   }
-  if (P.dim == 2) {
+  if (p->kind == QPGF_KIND_G2D_GRAD) {
+    // gradient tables: Gauss-Legendre rule on [eps, 2 eps] for |eta| up to the grid's corner
+    // (about |eta| eps nodes beyond the plain rule resolve the Bessel oscillations)
+    const double e1 = P.M1 / 2, e2 = (P.M2 / 2) * M_PI / p->c_tilde;
+    const int Qg = std::max(Q, (int)std::ceil(std::sqrt(e1 * e1 + e2 * e2) * p->eps) + 64);
+    std::vector<long double> hx, hw;
+    gauss_legendre(Qg, hx, hw);
+    std::vector<double> rg(Qg), wyg(Qg);
+    const long double e = p->eps;
+    for (int q = 0; q < Qg; ++q) {
+      rg[q] = (double)(e + 0.5L * e * (hx[q] + 1.0L));
+      wyg[q] = (double)(0.5L * e * hw[q] * (long double)cut_Y(rg[q], p->eps));
+    }
+    double *drg = nullptr, *dwyg = nullptr;
+    PLAN_ST(upload(&drg, rg));
+    qpgf_status su = upload(&dwyg, wyg);
+    if (su != QPGF_OK) {
+      (void)hipFree(drg);
+      return bail(su);
+    }
+    hipError_t e2r = hipMalloc(reinterpret_cast<void**>(&P.D2), 8 * P.ncell * sizeof(double));
+    if (e2r == hipSuccess) e2r = launch_sing2d_grad(P, Qg, drg, dwyg);
+    if (e2r == hipSuccess) e2r = hipDeviceSynchronize();
+    (void)hipFree(drg);
+    (void)hipFree(dwyg);
+    PLAN_TRY(e2r);
+  } else if (P.dim == 2) {
     // Phi_1(r) = (2 + ln r) Y'(r)/r + Y''(r) ln r at the radial nodes, times the weights
     std::vector<double> wphi(Q);
     long double f1tail = 0.0L;
@@ -511,6 +539,11 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
 qpgf_status qpgf_g2d(qpgf_plan* plan, double k, double alpha, const double* x, int64_t T, void* out,
                      uint8_t* flags) {
   return both(plan, QPGF_KIND_G2D, k, alpha, 0.0, x, T, out, flags);
+}
+
+qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha, const double* x, int64_t T, void* out,
+                          uint8_t* flags) {
+  return both(plan, QPGF_KIND_G2D_GRAD, k, alpha, 0.0, x, T, out, flags);
 }
 
 qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double a1, double a2, const double* x, int64_t T, void* out,
@@ -708,10 +741,10 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
   struct Shape { int n; bool rows; long batch; };
   std::vector<Shape> shapes;
   if (P.dim == 2) {
-    shapes.push_back({P.M2, false, (long)P.M1});
+    shapes.push_back({P.M2, false, (long)P.M1 * P.nf});
     for (int n = 16; n <= P.M1; n <<= 1) {
-      shapes.push_back({n, true, (long)P.M2});
-      shapes.push_back({n, true, (long)P.S});
+      shapes.push_back({n, true, (long)P.M2 * P.nf});
+      shapes.push_back({n, true, (long)P.S * P.nf});
     }
   } else {
     shapes.push_back({P.M3, false, (long)P.M1 * P.M2 * P.nf});

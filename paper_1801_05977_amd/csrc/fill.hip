@@ -275,6 +275,109 @@ __global__ void k_sing2d(int M1, int M2, double c_tilde, double A2, int Q, const
   F2[idx] = mk(0.0, (-2.0 * e1 * f1 - A2 * (e1 / eta) * i1) / eta2);
 }
 
+// Gradient tables (Section 2.4.1): the Fourier coefficients of the singular parts
+//   h1 = -(1/2pi) [-(k^2/2) x1 ln r + x1/r^2 - i alpha x1^2/r^2 - (alpha^2/2) x1^3/r^2] Y(r),
+//   h2 = -(1/2pi) [-(k^2/2) x2 ln r + x2/r^2 - i alpha x1 x2/r^2 - (alpha^2/2) x1^2 x2/r^2] Y(r)
+// split by their k- and alpha-dependence, H-hat_p = i (k^2 a_p + P_p - alpha Q_p - (alpha^2/2) R_p),
+// so the eight real tables a1 P1 Q1 R1 a2 P2 Q2 R2 ([8][M2][M1], A2 included) serve every
+// (k, alpha).  Each term is a radial function times cos(n theta) or sin(n theta); its
+// coefficient is 2 pi (-i)^n cos(n phi) (or sin) times int g(r) J_n(|eta| r) r dr, phi the angle
+// of eta = (j1, j2 pi / c~).  Y = 1 on [0, eps], where the six radial integrals have closed
+// forms (recurrences and d/dz[z^n J_n] = z^n J_{n-1}); on [eps, 2 eps] a Gauss-Legendre rule
+// (weights times Y at the nodes) fine enough for the highest |eta| of the grid.
+__global__ void k_sing2d_grad(int M1, int M2, double c_tilde, double A2, double eps, int Qg,
+                              const double* __restrict__ rg, const double* __restrict__ wyg, double* __restrict__ D) {
+  const long n = (long)M1 * M2;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int j1p = (int)(idx % M1), j2p = (int)(idx / M1);
+  const double e1 = centered(j1p, M1), J = centered(j2p, M2) * kPi / c_tilde;
+  const double rho = sqrt(e1 * e1 + J * J);
+  double t[8];
+  if (rho == 0.0) {
+    // only the n = 0 term survives: Q1 = -(A2/2) int_0^{2eps} Y r dr
+    double tc0 = 0.5 * eps * eps;
+    for (int q = 0; q < Qg; ++q) tc0 = fma(wyg[q], rg[q], tc0);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) t[m] = 0.0;
+    t[2] = -0.5 * A2 * tc0;
+  } else {
+    // [0, eps]
+    const double ze = rho * eps, J0e = j0(ze), J1e = j1(ze), J2e = jn(2, ze), ir = 1.0 / rho;
+    double TB = (1.0 - J0e) * ir;                              // int J1(rho r) dr
+    double TC0 = eps * J1e * ir;                               // int J0 r dr
+    const double c20 = 2.0 * (1.0 - J0e) * ir * ir - eps * J1e * ir;
+    double TC2 = c20;                                          // int J2 r dr
+    const double d10 = eps * eps * J2e * ir;
+    double TD1 = d10;                                          // int J1 r^2 dr
+    double TD3 = 4.0 * ir * c20 - d10;                         // int J3 r^2 dr
+    double TA = log(eps) * d10 - ir * c20;                     // int ln r J1 r^2 dr
+    // [eps, 2 eps]
+    for (int q = 0; q < Qg; ++q) {
+      const double r = rg[q], w = wyg[q], z = rho * r;
+      const double b0 = j0(z), b1 = j1(z), b2 = jn(2, z), b3 = jn(3, z);
+      const double wr = w * r, wr2 = wr * r;
+      TA = fma(wr2 * log(r), b1, TA);
+      TB = fma(w, b1, TB);
+      TC0 = fma(wr, b0, TC0);
+      TC2 = fma(wr, b2, TC2);
+      TD1 = fma(wr2, b1, TD1);
+      TD3 = fma(wr2, b3, TD3);
+    }
+    const double cp = e1 * ir, sp = J * ir;
+    const double c2p = cp * cp - sp * sp, s2p = 2.0 * sp * cp;
+    const double c3p = cp * (4.0 * cp * cp - 3.0), s3p = sp * (3.0 - 4.0 * sp * sp);
+    t[0] = -0.5 * A2 * cp * TA;
+    t[1] = A2 * cp * TB;
+    t[2] = -0.5 * A2 * (TC0 - c2p * TC2);
+    t[3] = -0.25 * A2 * (c3p * TD3 - 3.0 * cp * TD1);
+    t[4] = -0.5 * A2 * sp * TA;
+    t[5] = A2 * sp * TB;
+    t[6] = 0.5 * A2 * s2p * TC2;
+    t[7] = -0.25 * A2 * (s3p * TD3 - sp * TD1);
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) D[m * n + idx] = t[m];
+}
+
+// 2D gradient fill (Section 2.4.1): the two fields
+//   L-hat_1 = i(alpha + j1) K-hat - H-hat_1,  L-hat_2 = i j2 (pi/c~) K-hat - H-hat_2,
+// K-hat of (2.1) as in the fill of G, H-hat_p from the gradient tables.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill2d_grad(FillArgs A, const double* __restrict__ xq,
+                                                     const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                                     const double* __restrict__ D, cplx<T>* __restrict__ out) {
+  extern __shared__ double2 sa[];
+  const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
+  const int j1p0 = blockIdx.x * TP;
+  const int j1p = j1p0 + ip;
+  const int j1 = centered(min(j1p, A.M1 - 1), A.M1);
+  const double a = A.a1 + j1;
+  const double2 b = beta_of(A.k, fabs(a));
+  const bool use_I = b.y * A.c < 41.5;
+  if (__syncthreads_or(use_I && j1p < A.M1)) pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
+  __syncthreads();
+  if (j1p >= A.M1) return;
+  const double2* ap = sa + ip;
+  const double lead0 = a * a - A.k * A.k;
+  const size_t n = (size_t)A.M1 * A.Mt;
+  const double k2 = A.k * A.k, al = A.a1, ha2 = 0.5 * A.a1 * A.a1;
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+    const double2 K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    const size_t o = (size_t)jtp * A.M1 + j1p;
+    // H-hat_p = i s_p
+    const double s1 = k2 * D[o] + D[n + o] - al * D[2 * n + o] - ha2 * D[3 * n + o];
+    const double s2 = k2 * D[4 * n + o] + D[5 * n + o] - al * D[6 * n + o] - ha2 * D[7 * n + o];
+    // times the basis normalisation A2 (the grid sum)
+    store_c<T>(out, o, cscale(mk(-a * K.y, a * K.x - s1), A.A));
+    store_c<T>(out + A.fstride, o, cscale(mk(-J * K.y, J * K.x - s2), A.A));
+  }
+}
+
 // H(rho) = rho^-1 int_eps^{2eps} e^{ikr} (2ik Y' + Y'') sin(rho r) dr (the radial
 // form of the integral in eq. 3.5), tabulated on rho = (m - 4) hd, m in [0, hn).
 __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int Q, const double* __restrict__ rq,
@@ -340,6 +443,23 @@ __global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf,
   store_c<T>(out, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
 }
 
+// Far slab of the 2D gradient: the coefficients of the series (1.2) differentiated,
+// i(alpha + n) (i/4pi) beta_n^-1 e^{i beta_n z_s} for x1 and i beta_n (i/4pi) beta_n^-1 e^{i beta_n z_s}
+// = -(1/4pi) e^{i beta_n z_s} for x2 (the factor sgn(x2) is applied at the target).
+template <typename T>
+__global__ void k_far2d_grad(double k, double a, int M1, int S, double z0, double hf, long fstride,
+                             cplx<T>* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M1 * S) return;
+  const int j1p = (int)(idx % M1), s = (int)(idx / M1);
+  const double an = a + centered(j1p, M1);
+  const double2 b = beta_of(k, fabs(an));
+  const double2 e = cexpi(cscale(b, z0 + s * hf));
+  const double2 f = cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), e);
+  store_c<T>(out, idx, mk(-an * f.y, an * f.x));
+  store_c<T>(out + fstride, idx, cscale(e, -1.0 / (4.0 * kPi)));
+}
+
 // Far slab of many 2D instances: instance i owns blocks [blk0_i, blk0_{i+1}) of 256 threads.
 template <typename T>
 __global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, int S, double z0, double hf,
@@ -373,7 +493,10 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse) {
   if (P.dim == 2) {
     A.A = 1.0 / (2.0 * sqrt(kPi * A.c_tilde));
     dim3 grid((P.M1 + TP - 1) / TP, 1);
-    hipLaunchKernelGGL(k_fill2d<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2, out);
+    if (P.nf == 2)
+      hipLaunchKernelGGL(k_fill2d_grad<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2, out);
+    else
+      hipLaunchKernelGGL(k_fill2d<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2, out);
   } else {
     A.A = 1.0 / sqrt(8.0 * kPi * kPi * A.c_tilde);
     dim3 grid((P.M1 + TP - 1) / TP, P.M2);
@@ -399,7 +522,11 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
   const double hf = P.p.far_h, z0 = P.p.c - hf;
   if (P.dim == 2) {
     long n = (long)P.M1 * P.S;
-    hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
+    if (P.nf == 2)
+      hipLaunchKernelGGL(k_far2d_grad<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf,
+                         (long)P.nfar, out);
+    else
+      hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
   } else {
     long n = (long)P.M1 * P.M2 * P.S;
     if (P.nf == 7)
@@ -419,6 +546,14 @@ hipError_t launch_sing2d(Plan& P, double f1zero) {
   const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
   hipLaunchKernelGGL(k_sing2d, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
                      P.p.quad_q, P.rq, P.wrq, f1zero, P.F1, P.F2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* wyg) {
+  const long n = (long)P.M1 * P.M2;
+  const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
+  hipLaunchKernelGGL(k_sing2d_grad, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
+                     P.p.eps, Qg, rg, wyg, P.D2);
   return hipGetLastError();
 }
 

@@ -768,6 +768,97 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
   if (i < T_) gather2d_one<T>(A, grid, far, x, i, out, flags);
 }
 
+// One target of the 2D gradient (Section 2.4.1): both fields interpolated with one
+// stencil, the singular parts h1, h2 added back in FP64 inside 2 eps, the phase
+// e^{i alpha x1}; beyond c the differentiated far slab, the x2 field times sgn(x2).
+// out[2i] = dG/dx1, out[2i+1] = dG/dx2.
+template <typename T>
+__device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+                                                  const cplx<T>* __restrict__ far, const double* __restrict__ x,
+                                                  long i, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
+  const double x1 = x[2 * i], x2 = x[2 * i + 1];
+  uint8_t fl = 0;
+  double2 d1, d2;
+  if (!(isfinite(x1) && isfinite(x2))) {
+    fl = 8;
+    d1 = d2 = nan2();
+  } else {
+    double n1;
+    const double t = reduce_cell(x1, n1);
+    T w1[4], w2[4];
+    const double u = t * A.ih1, p = floor(u);
+    lag4<T>((T)(u - p), w1);
+    const int i0 = ((int)p - 1) & (A.M1 - 1);
+    double ps, pc;
+    sincos(A.a1 * x1, &ps, &pc);
+    const double2 phase = mk(pc, ps);
+    const bool is_near = fabs(x2) <= A.c;
+    long rows[4];
+    const cplx<T>* g = grid;
+    long fst = A.fs;
+    bool bad = false;
+    if (is_near) {
+      const double u2 = x2 * A.ih2, p2 = floor(u2);
+      lag4<T>((T)(u2 - p2), w2);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
+    } else {
+      fl |= 2;
+      g = far;
+      fst = A.ffs;
+      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
+      double s0 = floor(v);
+      if (s0 > A.S - 3) {
+        bad = true;
+        fl |= 4;
+      } else {
+        s0 = fmax(s0, 1.0);
+        lag4<T>((T)(v - s0), w2);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
+      }
+    }
+    if (bad) {
+      d1 = d2 = nan2();
+    } else {
+      double2 L1 = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
+      double2 L2 = stencil2d<T>(g + fst, rows, i0, A.M1, w1, w2);
+      if (is_near) {
+        const double r2 = t * t + x2 * x2;
+        if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+          fl |= 1;
+          L1 = L2 = nan2();
+        } else if (r2 < 4.0 * A.eps * A.eps) {
+          // h_p = -(Y/2pi) [ -(k^2/2) x_p ln r + x_p/r^2 - i alpha t x_p/r^2 - (alpha^2/2) t^2 x_p/r^2 ],
+          // x_1 = t, x_2 = x2 (the cell coordinates of the target)
+          const double r = sqrt(r2), ir2 = 1.0 / r2;
+          const double c = -cut_Y(r, A.eps) / (2.0 * kPi);
+          const double re = -0.5 * A.k * A.k * log(r) + ir2 - 0.5 * A.a1 * A.a1 * t * t * ir2;
+          const double im = -A.a1 * t * ir2;
+          L1 = cadd(L1, mk(c * re * t, c * im * t));
+          L2 = cadd(L2, mk(c * re * x2, c * im * x2));
+        }
+      } else if (x2 < 0.0) {
+        L2 = cscale(L2, -1.0);
+      }
+      d1 = cmul(phase, L1);
+      d2 = cmul(phase, L2);
+    }
+  }
+  store_out<T>(out, 2 * i, d1);
+  store_out<T>(out, 2 * i + 1, d2);
+  if (flags) flags[i] = fl;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* __restrict__ grid,
+                                                       const cplx<T>* __restrict__ far, const double* __restrict__ x,
+                                                       long T_, cplx<T>* __restrict__ out,
+                                                       uint8_t* __restrict__ flags) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T_) gather2d_grad_one<T>(A, grid, far, x, i, out, flags);
+}
+
 // Many 2D instances in one launch: instance i owns blocks [blk0_i, blk0_{i+1}) and
 // targets [t0_i, t1_i) of the concatenated target array.
 struct GatherInst {
@@ -1024,7 +1115,10 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   }
   if (P.dim == 2) {
     KernelTimer t(P, QPGF_T_GATHER);
-    hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    if (P.nf == 2)
+      hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    else
+      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     return hipGetLastError();
   }
   if (P.bin_min_targets < 0 || T_ < P.bin_min_targets) {

@@ -128,6 +128,7 @@ struct Plan {
   int twlog2 = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
+  double* D2 = nullptr;        // 2D gradient tables [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2)
   double2* htab = nullptr;     // 3D: H(rho) on rho = (m - 4) dh
   int hn = 0;
   double hd = 0.05;
@@ -200,6 +201,7 @@ struct KernelTimer {
 };
 
 // kernel launchers (fill.hip, fft.hip, gather.hip)
+hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d(Plan& P, double f1_zero);
 hipError_t launch_htable(Plan& P, double k);
 hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse_transverse);
