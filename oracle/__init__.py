@@ -23,8 +23,11 @@ Two oracles live here:
   2.4.1): differentiated coefficients, the singular parts h1, h2 and their
   Fourier coefficients by Hankel transforms, add-back at the target.
 
+* ``hess2d`` -- the differences of second derivatives of the 2D G for two
+  wavenumbers (Section 2.4.2), the same way.
+
 ``cutoffs`` holds the smooth cut-off functions X and Y_eps (Section 6 states
 only that they are C^8; the reading used is documented there).
 """
 
-from . import cutoffs, truth, method, grad2d  # noqa: F401
+from . import cutoffs, truth, method, grad2d, hess2d  # noqa: F401

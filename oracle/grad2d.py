@@ -74,9 +74,12 @@ def h_grad(k, alpha, t, z, eps=co.EPS, printed_h2=False):
 # ----------------------------------------------------------------------------
 
 def _radial_rules(rho_max, eps, q):
-    """Gauss-Legendre nodes/weights on [0, eps] and [eps, 2 eps], enough for |eta| <= rho_max."""
+    """Radial nodes/weights on [0, eps] and [eps, 2 eps], enough for |eta| <= rho_max: Gauss-Legendre,
+    on [0, eps] in u with r = eps u^3 (the ln r factors of the integrands are then integrated to
+    rounding; plain Gauss-Legendre leaves about 1e-10)."""
     n = max(q, int(math.ceil(rho_max * eps)) + 64)
-    r0, w0 = gauss_legendre(0.0, eps, n)
+    u, wu = gauss_legendre(0.0, 1.0, n)
+    r0, w0 = eps * u ** 3, wu * 3 * eps * u * u
     r1, w1 = gauss_legendre(eps, 2 * eps, n)
     r = np.concatenate([r0, r1])
     w = np.concatenate([w0, w1])

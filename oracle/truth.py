@@ -144,6 +144,47 @@ def g2d_grad(k, alpha, x, tol=1e-17, max_terms=4_000_000):
     return out
 
 
+def _radius_2d_hess(k, z, tol):
+    """Smallest A >= k + 1 whose tail bound for the twice-differentiated series is <= tol.
+
+    A term of |alpha_n| = A + m >= A has alpha_n^2 / kappa_n, |alpha_n beta_n| / kappa_n and
+    |beta_n|^2 / kappa_n all <= (A + m) m(A), m(A) = A / sqrt(A^2 - k^2), and
+    e^{-kappa_n z} <= e^{-(A + m - k) z}; sum_m (A + m) q^m = A/(1 - q) + q/(1 - q)^2, q = e^{-z}.
+    """
+    k = abs(k)
+    q = math.exp(-z)
+    A = k + 1.0
+    for _ in range(4000):
+        m = A / math.sqrt(A * A - k * k)
+        tail = 2.0 * m * math.exp(-(A - k) * z) * (A / (1 - q) + q / (1 - q) ** 2)
+        if tail <= tol:
+            return A
+        A = max(A * 1.05, A + 1.0)
+    raise ValueError("2D series: point too close to the plane x2 = 0")
+
+
+def g2d_hess(k, alpha, x, tol=1e-17, max_terms=8_000_000):
+    """(d11 G, d12 G, d22 G) of (1.2) at targets x[T,2] (x2 != 0), differentiated term by term:
+    -alpha_n^2, -alpha_n beta_n sgn(x2), -beta_n^2."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    out = np.empty((len(x), 3), dtype=np.complex128)
+    for i, (x1, x2) in enumerate(x):
+        z = abs(x2)
+        if z == 0.0:
+            raise ValueError("2D series needs x2 != 0")
+        A = _radius_2d_hess(k, z, tol)
+        n = np.arange(math.ceil(-A - alpha), math.floor(A - alpha) + 1, dtype=np.float64)
+        if n.size > max_terms:
+            raise ValueError("2D series: too many terms")
+        an = alpha + n
+        b = beta(k, an)
+        e = 1j / (4 * math.pi) * np.exp(1j * an * x1 + 1j * b * z) / b
+        out[i, 0] = np.sum(-(an * an) * e)
+        out[i, 1] = -np.sign(x2) * np.sum(an * b * e)
+        out[i, 2] = np.sum(-(b * b) * e)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # 3D: eigenfunction expansion (1.3) and the Maxwell tensor (1.4)
 # ----------------------------------------------------------------------------
