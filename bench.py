@@ -13,6 +13,7 @@ for all 1e7 targets (step 2), with targets already resident in HBM.
     python bench.py --workload maxwell3d     # Maxwell tensor, 512 x 512 modes, 32 slices, 1e6 targets
     python bench.py --workload surrogate     # MLP surrogate vs the plain method, 1e4 instances x 1e4 targets
     python bench.py --workload g2d_grad      # gradient of the 2D G, 1024 x-modes, 128 slices, 1e7 targets
+    python bench.py --workload g2d_hess_diff # second-derivative differences, two wavenumbers, same grid
 
 Prints one JSON line.  The per-kernel durations behind ``roofline`` are HIP
 events recorded by the library on the stream its kernels run on.
@@ -93,7 +94,7 @@ def main():
     ap.add_argument("--modes", default="256,256,64")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate", "g2d_grad"], default="gd3d")
+    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate", "g2d_grad", "g2d_hess_diff"], default="gd3d")
     ap.add_argument("--train-instances", type=int, default=2000)
     ap.add_argument("--train-per", type=int, default=8192)
     ap.add_argument("--train-epochs", type=float, default=4.0)
@@ -130,6 +131,9 @@ def main():
         return
     if args.workload == "g2d_grad":
         print(json.dumps(run_g2d_grad(args)), flush=True)
+        return
+    if args.workload == "g2d_hess_diff":
+        print(json.dumps(run_g2d_hess_diff(args)), flush=True)
         return
     m1, m2, m3 = (int(v) for v in args.modes.split(","))
     T = args.targets
@@ -371,6 +375,37 @@ def run_g2d_grad(args):
             "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
             "config": {"workload": "g2d gradient k=2.1 alpha=0.3", "x1_modes": M1, "slices": M2, "targets": T,
                        "method": "plain"},
+            "kernels_avg_ms": kern,
+            "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}
+
+
+def run_g2d_hess_diff(args):
+    """Differences of second derivatives of the 2D G (Section 2.4.2): k1 = 2.1, k2 = 4.35, alpha = 0.3,
+    1024 x-modes, 128 slices, 1e7 targets U([0, 2pi] x [-1, 1]), complex64; one prepare + evaluate per step."""
+    import torch
+    from paper_1801_05977_amd import qpgf, workloads
+    T, M1, M2 = 10_000_000, 1024, 128
+    x = torch.from_numpy(workloads.targets(T, 2, seed=0)).cuda()
+    prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
+    P = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, prec, M1, M2)
+    out = P.out_tensor(T)
+    t = _timed(lambda: P.hess_diff(2.1, 4.35, 0.3, x, out), args.steps, args.warmup)
+    P.enable_timing(True)
+    for _ in range(args.steps):
+        P.hess_diff(2.1, 4.35, 0.3, x, out)
+    torch.cuda.synchronize()
+    kern = {k_: round(v[0] / v[1], 5) for k_, v in P.timing().items() if v[1]}
+    esize = 8 if prec == qpgf.C64 else 16
+    # gather: 16 B in, three results and a flag byte out per target, the three fields once
+    alg = T * (16 + 3 * esize + 1) + 3 * (P.info.grid_bytes + P.info.far_grid_bytes)
+    ach = alg / (kern["gather"] * 1e-3) / 1e9
+    return {"metric": "2D second-derivative-difference evals/sec (d11, d12, d22 of G_k1 - G_k2)", "value": T / t,
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+            "data": "synthetic",
+            "config": {"workload": "g2d second-derivative differences k1=2.1 k2=4.35 alpha=0.3", "x1_modes": M1,
+                       "slices": M2, "targets": T, "method": "plain"},
             "kernels_avg_ms": kern,
             "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}

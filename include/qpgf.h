@@ -69,7 +69,9 @@ typedef enum {
   QPGF_KIND_G2D = 0,       /* Algorithm 2.1 */
   QPGF_KIND_GD3D = 1,      /* Algorithm 3.1 */
   QPGF_KIND_MAXWELL3D = 2, /* Algorithm 4.1 */
-  QPGF_KIND_G2D_GRAD = 3   /* first derivatives of the 2D G (Section 2.4.1) */
+  QPGF_KIND_G2D_GRAD = 3,  /* first derivatives of the 2D G (Section 2.4.1) */
+  QPGF_KIND_G2D_HESS_DIFF = 4  /* differences of second derivatives of the 2D G for two
+                                  wavenumbers (Section 2.4.2) */
 } qpgf_kind;
 
 /* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
@@ -117,8 +119,9 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
  * compute its parameter-only tables (quadrature nodes, FFT twiddles, and in 2D
  * the k- and alpha-independent singular coefficients F-hat_1, F-hat_2 of
  * eqs. 2.4 / 2.5, which Remark 2.1 lets one precompute once; for
- * QPGF_KIND_G2D_GRAD instead the k- and alpha-independent parts of the
- * coefficients of the singular parts h1, h2 of Section 2.4.1).  Synchronous.
+ * QPGF_KIND_G2D_GRAD and QPGF_KIND_G2D_HESS_DIFF instead the k- and
+ * alpha-independent parts of the coefficients of the singular parts of Sections
+ * 2.4.1 / 2.4.2).  Synchronous.
  * *out receives the plan; release it with qpgf_plan_destroy. */
 qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out);
 
@@ -139,8 +142,8 @@ qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2);
 
 /* Calculation step (Algorithm 2.1 / 3.1 / 4.1 step 2) for T targets against the
  * last prepared instance.  x: device float64 [T][dim]; out: device complex
- * ([T], [T][6] for MAXWELL3D, [T][2] for G2D_GRAD); flags: device uint8 [T] or
- * NULL.  T = 0 is a no-op. */
+ * ([T], [T][6] for MAXWELL3D, [T][2] for G2D_GRAD, [T][3] for G2D_HESS_DIFF);
+ * flags: device uint8 [T] or NULL.  T = 0 is a no-op. */
 qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags);
 
 /* prepare + evaluate: G (kind G2D), G_d (GD3D) and GG (MAXWELL3D) at T targets. */
@@ -169,6 +172,29 @@ qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alph
  * T > 0; QPGF_E_WOOD / QPGF_E_SPECIAL for excluded instances (before any launch). */
 qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha,
                           const double* x, int64_t T, void* out, uint8_t* flags);
+
+/* Differences of second derivatives of the 2D G for two wavenumbers (Section 2.4.2),
+ * plan of kind QPGF_KIND_G2D_HESS_DIFF: per target the three values
+ * d_p d_q G_{k1}(x) - d_p d_q G_{k2}(x), pq = 11, 12, 22, with one alpha.  The
+ * plan's three fields hold T_pq - h_pq, T_pq = e^{-i alpha x1} times that difference
+ * (coefficients m_pq (K-hat^{(k1)}_j - K-hat^{(k2)}_j) - H-hat_pq,j with
+ * m = -(alpha + j1)^2, -(alpha + j1) j2 pi/c~, -(j2 pi/c~)^2; the k-independent
+ * 1/|x|^2 singularities cancel in the difference and the remaining singular parts
+ * h_pq, of the logarithm and x_p x_q/|x|^2, come from the plan's tables).  h_pq is
+ * taken with the constant +(k1^2 - k2^2)/(2 pi) (the expansion of the difference of
+ * the two Hankel functions; the printed definitions carry a minus sign).  The far
+ * slab holds the series (1.2) differentiated twice term by term.  x: device float64
+ * [T][2]; out: device complex [T][3] (11, 12, 22) in the plan's precision; flags as
+ * for qpgf_g2d.  k1 = k2 gives zeros.  Errors as for qpgf_g2d_grad, Wood / special
+ * checks for both wavenumbers. */
+qpgf_status qpgf_g2d_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha,
+                               const double* x, int64_t T, void* out, uint8_t* flags);
+
+/* Preparation alone (stage 0: coefficients; 1: after the transverse transform; 2:
+ * grids and far slab, ready for qpgf_evaluate) for a plan of kind
+ * QPGF_KIND_G2D_HESS_DIFF, which qpgf_prepare and qpgf_prepare_stage refuse
+ * (QPGF_E_ARG) because it needs two wavenumbers. */
+qpgf_status qpgf_prepare_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha, int stage);
 
 /* Batched form of Algorithm 2.1: n_inst independent instances in one call.
  * Instance i has wavenumber k[i], alpha[i] and x1 size m1[i] (a power of two,

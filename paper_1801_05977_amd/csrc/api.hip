@@ -105,11 +105,13 @@ void free_plan(Plan& P) {
     if (p) (void)hipFree(p);
 }
 
-bool kind_is_2d(int kind) { return kind == QPGF_KIND_G2D || kind == QPGF_KIND_G2D_GRAD; }
+bool kind_is_2d(int kind) {
+  return kind == QPGF_KIND_G2D || kind == QPGF_KIND_G2D_GRAD || kind == QPGF_KIND_G2D_HESS_DIFF;
+}
 
 qpgf_status validate(const qpgf_params* p) {
   if (!p) return fail(QPGF_E_ARG, "params is NULL");
-  if (p->kind < 0 || p->kind > 3) return fail(QPGF_E_ARG, "unknown kind");
+  if (p->kind < 0 || p->kind > 4) return fail(QPGF_E_ARG, "unknown kind");
   if (p->prec != QPGF_C128 && p->prec != QPGF_C64) return fail(QPGF_E_ARG, "unknown precision");
   if (!pow2_in(p->m1, 16, 4096) || !pow2_in(p->m2, 16, 4096))
     return fail(QPGF_E_SIZE, "m1 and m2 must be powers of two in [16, 4096]");
@@ -125,6 +127,8 @@ qpgf_status validate(const qpgf_params* p) {
   if (!(p->c > 0.0) || !(p->c_tilde > p->c)) return fail(QPGF_E_ARG, "need 0 < c < c_tilde");
   if (!(p->eps > 0.0) || !(2.0 * p->eps <= p->c_tilde)) return fail(QPGF_E_ARG, "need 0 < 2 eps <= c_tilde");
   if (p->quad_q < 16 || p->quad_q > 256) return fail(QPGF_E_ARG, "quad_q must be in [16, 256]");
+  if (p->kind == QPGF_KIND_G2D_HESS_DIFF && p->quad_q > 128)
+    return fail(QPGF_E_ARG, "quad_q must be <= 128 for QPGF_KIND_G2D_HESS_DIFF (two wavenumbers' weights in LDS)");
   if (!(p->far_h > 0.0) || !(p->far_zmax >= p->c)) return fail(QPGF_E_ARG, "need far_h > 0 and far_zmax >= c");
   if (!(p->wood_tol >= 0.0) || !(p->special_tol >= 0.0) || !(p->lattice_rmin >= 0.0))
     return fail(QPGF_E_ARG, "tolerances must be >= 0");
@@ -176,9 +180,14 @@ qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int
   return QPGF_OK;
 }
 
-qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage) {
+qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, double k2 = 0.0) {
   qpgf_status st = check_instance(P, k, a1, a2);
   if (st != QPGF_OK) return st;
+  if (P.p.kind == QPGF_KIND_G2D_HESS_DIFF) {
+    st = check_instance(P, k2, a1, a2);
+    if (st != QPGF_OK) return st;
+  }
+  P.last_k2 = k2;
   P.last_k = k;
   P.last_a1 = a1;
   P.last_a2 = a2;
@@ -304,7 +313,10 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   Plan& P = plan->P;
   P.p = *p;
   P.dim = kind_is_2d(p->kind) ? 2 : 3;
-  P.nf = (p->kind == QPGF_KIND_MAXWELL3D) ? 7 : (p->kind == QPGF_KIND_G2D_GRAD) ? 2 : 1;
+  P.nf = (p->kind == QPGF_KIND_MAXWELL3D)       ? 7
+         : (p->kind == QPGF_KIND_G2D_HESS_DIFF) ? 3
+         : (p->kind == QPGF_KIND_G2D_GRAD)      ? 2
+                                                : 1;
   P.M1 = p->m1;
   P.M2 = p->m2;
   P.M3 = (P.dim == 3) ? p->m3 : 1;
@@ -387,8 +399,8 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
     PLAN_ST(upload(&P.tw, tw));
     PLAN_ST(upload(&P.twf, twf));
   }
-  if (p->kind == QPGF_KIND_G2D_GRAD) {
-    // gradient tables: Gauss-Legendre rule on [eps, 2 eps] for |eta| up to the grid's corner
+  if (p->kind == QPGF_KIND_G2D_GRAD || p->kind == QPGF_KIND_G2D_HESS_DIFF) {
+    // derivative tables: Gauss-Legendre rule on [eps, 2 eps] for |eta| up to the grid's corner
     // (about |eta| eps nodes beyond the plain rule resolve the Bessel oscillations)
     const double e1 = P.M1 / 2, e2 = (P.M2 / 2) * M_PI / p->c_tilde;
     const int Qg = std::max(Q, (int)std::ceil(std::sqrt(e1 * e1 + e2 * e2) * p->eps) + 64);
@@ -407,8 +419,9 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
       (void)hipFree(drg);
       return bail(su);
     }
-    hipError_t e2r = hipMalloc(reinterpret_cast<void**>(&P.D2), 8 * P.ncell * sizeof(double));
-    if (e2r == hipSuccess) e2r = launch_sing2d_grad(P, Qg, drg, dwyg);
+    const bool grad = p->kind == QPGF_KIND_G2D_GRAD;
+    hipError_t e2r = hipMalloc(reinterpret_cast<void**>(&P.D2), (grad ? 8 : 6) * P.ncell * sizeof(double));
+    if (e2r == hipSuccess) e2r = grad ? launch_sing2d_grad(P, Qg, drg, dwyg) : launch_sing2d_hess(P, Qg, drg, dwyg);
     if (e2r == hipSuccess) e2r = hipDeviceSynchronize();
     (void)hipFree(drg);
     (void)hipFree(dwyg);
@@ -483,6 +496,8 @@ qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2) {
   g_err.clear();
   qpgf_status st = check_plan(plan, -1);
   if (st != QPGF_OK) return st;
+  if (plan->P.p.kind == QPGF_KIND_G2D_HESS_DIFF)
+    return fail(QPGF_E_ARG, "a plan of kind G2D_HESS_DIFF takes two wavenumbers: qpgf_prepare_hess_diff");
   return run_prepare(plan->P, k, a1, plan->P.dim == 3 ? a2 : 0.0, 2);
 }
 
@@ -490,8 +505,18 @@ qpgf_status qpgf_prepare_stage(qpgf_plan* plan, double k, double a1, double a2, 
   g_err.clear();
   qpgf_status st = check_plan(plan, -1);
   if (st != QPGF_OK) return st;
+  if (plan->P.p.kind == QPGF_KIND_G2D_HESS_DIFF)
+    return fail(QPGF_E_ARG, "a plan of kind G2D_HESS_DIFF takes two wavenumbers: qpgf_prepare_hess_diff");
   if (stage < 0 || stage > 2) return fail(QPGF_E_ARG, "stage must be 0, 1 or 2");
   return run_prepare(plan->P, k, a1, plan->P.dim == 3 ? a2 : 0.0, stage);
+}
+
+qpgf_status qpgf_prepare_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha, int stage) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, QPGF_KIND_G2D_HESS_DIFF);
+  if (st != QPGF_OK) return st;
+  if (stage < 0 || stage > 2) return fail(QPGF_E_ARG, "stage must be 0, 1 or 2");
+  return run_prepare(plan->P, k1, alpha, 0.0, stage, k2);
 }
 
 qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags) {
@@ -502,7 +527,7 @@ qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out
 }
 
 static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a2, const double* x, int64_t T,
-                        void* out, uint8_t* flags) {
+                        void* out, uint8_t* flags, double k2 = 0.0) {
   g_err.clear();
   qpgf_status st = check_plan(plan, kind);
   if (st != QPGF_OK) return st;
@@ -523,7 +548,7 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
     HIP_TRY(launch_bin3d(P, x, T, P.side));
     HIP_TRY(hipEventRecord(P.ev_join, P.side));
   }
-  st = run_prepare(P, k, a1, a2, 2);
+  st = run_prepare(P, k, a1, a2, 2, k2);
   if (overlap) {
     // the plan's stream owns the bin scratch again, also when the preparation failed
     HIP_TRY(hipStreamWaitEvent(P.stream, P.ev_join, 0));
@@ -544,6 +569,11 @@ qpgf_status qpgf_g2d(qpgf_plan* plan, double k, double alpha, const double* x, i
 qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha, const double* x, int64_t T, void* out,
                           uint8_t* flags) {
   return both(plan, QPGF_KIND_G2D_GRAD, k, alpha, 0.0, x, T, out, flags);
+}
+
+qpgf_status qpgf_g2d_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha, const double* x, int64_t T,
+                               void* out, uint8_t* flags) {
+  return both(plan, QPGF_KIND_G2D_HESS_DIFF, k1, alpha, 0.0, x, T, out, flags, k2);
 }
 
 qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double a1, double a2, const double* x, int64_t T, void* out,

@@ -28,6 +28,7 @@ template <> __device__ __forceinline__ void store_c<float>(float2* p, size_t i, 
 
 struct FillArgs {
   double k, a1, a2;
+  double k2;                 // second wavenumber (differences of second derivatives, 2D)
   double c, c_tilde, A;      // A = A2 = 1/(2 sqrt(pi c~)) or A3 = 1/sqrt(8 pi^2 c~)
                              // (the basis normalisation: L-hat carries one factor A,
                              // the grid sum L_N = sum L-hat_j phi_j another; both are
@@ -285,6 +286,43 @@ __global__ void k_sing2d(int M1, int M2, double c_tilde, double A2, int Q, const
 // of eta = (j1, j2 pi / c~).  Y = 1 on [0, eps], where the six radial integrals have closed
 // forms (recurrences and d/dz[z^n J_n] = z^n J_{n-1}); on [eps, 2 eps] a Gauss-Legendre rule
 // (weights times Y at the nodes) fine enough for the highest |eta| of the grid.
+// Radial integrals of the singular parts' coefficients at |eta| = rho > 0, over [0, 2 eps]:
+//   TA = int ln r Y J1 r^2,  TB = int Y J1,  TC0 = int Y J0 r,  TC2 = int Y J2 r,
+//   TD1 = int Y J1 r^2,  TD3 = int Y J3 r^2,  TL = int ln r Y J0 r   (dr).
+// Y = 1 on [0, eps], where they have closed forms (the recurrence of J_n, d/dz[z^n J_n] =
+// z^n J_{n-1}, integration by parts for the ln r ones); on [eps, 2 eps] a Gauss-Legendre rule
+// whose weights carry Y at the nodes.
+struct Radial {
+  double TA, TB, TC0, TC2, TD1, TD3, TL;
+};
+__device__ Radial radial_integrals(double rho, double eps, int Qg, const double* __restrict__ rg,
+                                   const double* __restrict__ wyg) {
+  const double ze = rho * eps, J0e = j0(ze), J1e = j1(ze), J2e = jn(2, ze), ir = 1.0 / rho, le = log(eps);
+  Radial R;
+  R.TB = (1.0 - J0e) * ir;
+  R.TC0 = eps * J1e * ir;
+  const double c20 = 2.0 * (1.0 - J0e) * ir * ir - eps * J1e * ir;
+  R.TC2 = c20;
+  const double d10 = eps * eps * J2e * ir;
+  R.TD1 = d10;
+  R.TD3 = 4.0 * ir * c20 - d10;
+  R.TA = le * d10 - ir * c20;
+  R.TL = le * R.TC0 - R.TB * ir;
+  for (int q = 0; q < Qg; ++q) {
+    const double r = rg[q], w = wyg[q], z = rho * r, lr = log(r);
+    const double b0 = j0(z), b1 = j1(z), b2 = jn(2, z), b3 = jn(3, z);
+    const double wr = w * r, wr2 = wr * r;
+    R.TA = fma(wr2 * lr, b1, R.TA);
+    R.TB = fma(w, b1, R.TB);
+    R.TC0 = fma(wr, b0, R.TC0);
+    R.TC2 = fma(wr, b2, R.TC2);
+    R.TD1 = fma(wr2, b1, R.TD1);
+    R.TD3 = fma(wr2, b3, R.TD3);
+    R.TL = fma(wr * lr, b0, R.TL);
+  }
+  return R;
+}
+
 __global__ void k_sing2d_grad(int M1, int M2, double c_tilde, double A2, double eps, int Qg,
                               const double* __restrict__ rg, const double* __restrict__ wyg, double* __restrict__ D) {
   const long n = (long)M1 * M2;
@@ -302,42 +340,64 @@ __global__ void k_sing2d_grad(int M1, int M2, double c_tilde, double A2, double 
     for (int m = 0; m < 8; ++m) t[m] = 0.0;
     t[2] = -0.5 * A2 * tc0;
   } else {
-    // [0, eps]
-    const double ze = rho * eps, J0e = j0(ze), J1e = j1(ze), J2e = jn(2, ze), ir = 1.0 / rho;
-    double TB = (1.0 - J0e) * ir;                              // int J1(rho r) dr
-    double TC0 = eps * J1e * ir;                               // int J0 r dr
-    const double c20 = 2.0 * (1.0 - J0e) * ir * ir - eps * J1e * ir;
-    double TC2 = c20;                                          // int J2 r dr
-    const double d10 = eps * eps * J2e * ir;
-    double TD1 = d10;                                          // int J1 r^2 dr
-    double TD3 = 4.0 * ir * c20 - d10;                         // int J3 r^2 dr
-    double TA = log(eps) * d10 - ir * c20;                     // int ln r J1 r^2 dr
-    // [eps, 2 eps]
-    for (int q = 0; q < Qg; ++q) {
-      const double r = rg[q], w = wyg[q], z = rho * r;
-      const double b0 = j0(z), b1 = j1(z), b2 = jn(2, z), b3 = jn(3, z);
-      const double wr = w * r, wr2 = wr * r;
-      TA = fma(wr2 * log(r), b1, TA);
-      TB = fma(w, b1, TB);
-      TC0 = fma(wr, b0, TC0);
-      TC2 = fma(wr, b2, TC2);
-      TD1 = fma(wr2, b1, TD1);
-      TD3 = fma(wr2, b3, TD3);
-    }
-    const double cp = e1 * ir, sp = J * ir;
+    const Radial R = radial_integrals(rho, eps, Qg, rg, wyg);
+    const double cp = e1 / rho, sp = J / rho;
     const double c2p = cp * cp - sp * sp, s2p = 2.0 * sp * cp;
     const double c3p = cp * (4.0 * cp * cp - 3.0), s3p = sp * (3.0 - 4.0 * sp * sp);
-    t[0] = -0.5 * A2 * cp * TA;
-    t[1] = A2 * cp * TB;
-    t[2] = -0.5 * A2 * (TC0 - c2p * TC2);
-    t[3] = -0.25 * A2 * (c3p * TD3 - 3.0 * cp * TD1);
-    t[4] = -0.5 * A2 * sp * TA;
-    t[5] = A2 * sp * TB;
-    t[6] = 0.5 * A2 * s2p * TC2;
-    t[7] = -0.25 * A2 * (s3p * TD3 - sp * TD1);
+    t[0] = -0.5 * A2 * cp * R.TA;
+    t[1] = A2 * cp * R.TB;
+    t[2] = -0.5 * A2 * (R.TC0 - c2p * R.TC2);
+    t[3] = -0.25 * A2 * (c3p * R.TD3 - 3.0 * cp * R.TD1);
+    t[4] = -0.5 * A2 * sp * R.TA;
+    t[5] = A2 * sp * R.TB;
+    t[6] = 0.5 * A2 * s2p * R.TC2;
+    t[7] = -0.25 * A2 * (s3p * R.TD3 - sp * R.TD1);
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) D[m * n + idx] = t[m];
+}
+
+// Tables of the second-derivative differences (Section 2.4.2): the singular parts
+//   h11 = C (ln r/2 - i alpha x1 ln r/2 + x1^2/(2r^2) - i alpha x1^3/(2r^2)) Y,
+//   h12 = C (x1 x2/(2r^2) - i alpha x1^2 x2/(2r^2)) Y,
+//   h22 = C (ln r/2 - i alpha x1 ln r/2 + x2^2/(2r^2) - i alpha x1 x2^2/(2r^2)) Y,
+// C = (k1^2 - k2^2)/(2 pi), have real coefficients H-hat_pq = C (u_pq + alpha v_pq) (the
+// alpha-terms are odd in x1, so their transforms are imaginary and i alpha makes them real):
+// six real tables u11 v11 u12 v12 u22 v22, [6][M2][M1], A2 and pi included.
+__global__ void k_sing2d_hess(int M1, int M2, double c_tilde, double A2, double eps, int Qg,
+                              const double* __restrict__ rg, const double* __restrict__ wyg, double* __restrict__ D) {
+  const long n = (long)M1 * M2;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int j1p = (int)(idx % M1), j2p = (int)(idx / M1);
+  const double e1 = centered(j1p, M1), J = centered(j2p, M2) * kPi / c_tilde;
+  const double rho = sqrt(e1 * e1 + J * J);
+  const double s = A2 * kPi;
+  double t[6];
+  if (rho == 0.0) {
+    // n = 0 terms only: TL(0) = int ln r Y r dr, TC0(0) = int Y r dr
+    double tl = eps * eps * (0.5 * log(eps) - 0.25), tc0 = 0.5 * eps * eps;
+    for (int q = 0; q < Qg; ++q) {
+      tl = fma(wyg[q] * rg[q], log(rg[q]), tl);
+      tc0 = fma(wyg[q], rg[q], tc0);
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) t[m] = 0.0;
+    t[0] = t[4] = s * (tl + 0.5 * tc0);
+  } else {
+    const Radial R = radial_integrals(rho, eps, Qg, rg, wyg);
+    const double cp = e1 / rho, sp = J / rho;
+    const double c2p = cp * cp - sp * sp, s2p = 2.0 * sp * cp;
+    const double c3p = cp * (4.0 * cp * cp - 3.0), s3p = sp * (3.0 - 4.0 * sp * sp);
+    t[0] = s * (R.TL + 0.5 * (R.TC0 - c2p * R.TC2));
+    t[1] = s * (-cp * R.TA + 0.25 * (c3p * R.TD3 - 3.0 * cp * R.TD1));
+    t[2] = s * (-0.5 * s2p * R.TC2);
+    t[3] = s * (0.25 * (s3p * R.TD3 - sp * R.TD1));
+    t[4] = s * (R.TL + 0.5 * (R.TC0 + c2p * R.TC2));
+    t[5] = s * (-cp * R.TA - 0.25 * (cp * R.TD1 + c3p * R.TD3));
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) D[m * n + idx] = t[m];
 }
 
 // 2D gradient fill (Section 2.4.1): the two fields
@@ -432,6 +492,52 @@ __global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, d
   }
 }
 
+// Fill of the second-derivative differences (Section 2.4.2): three fields
+//   L-hat_pq = m_pq (K-hat^{(k1)} - K-hat^{(k2)}) - H-hat_pq,
+// m_11 = -(alpha + j1)^2, m_12 = -(alpha + j1) J, m_22 = -J^2 (J = j2 pi/c~), K-hat of (2.1)
+// for both wavenumbers (two sets of pencil weights in LDS); the difference of the leading
+// terms 1/(|xi|^2 - k^2) is formed exactly as (k1^2 - k2^2)/((|xi|^2 - k1^2)(|xi|^2 - k2^2)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* __restrict__ xq,
+                                                     const double* __restrict__ wxq, const double2* __restrict__ cs,
+                                                     const double* __restrict__ D, cplx<T>* __restrict__ out) {
+  extern __shared__ double2 sa[];
+  const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
+  const int j1p0 = blockIdx.x * TP;
+  const int j1p = j1p0 + ip;
+  const int j1 = centered(min(j1p, A.M1 - 1), A.M1);
+  const double a = A.a1 + j1;
+  FillArgs B = A;
+  B.k = A.k2;
+  const double2 b1 = beta_of(A.k, fabs(a)), b2 = beta_of(A.k2, fabs(a));
+  const bool use1 = b1.y * A.c < 41.5, use2 = b2.y * A.c < 41.5;
+  double2* sa2 = sa + TP * A.Q;
+  if (__syncthreads_or(use1 && j1p < A.M1)) pencil_weights<2>(A, j1p0, 0, xq, wxq, sa);
+  if (__syncthreads_or(use2 && j1p < A.M1)) pencil_weights<2>(B, j1p0, 0, xq, wxq, sa2);
+  __syncthreads();
+  if (j1p >= A.M1) return;
+  const size_t n = (size_t)A.M1 * A.Mt;
+  const double k1s = A.k * A.k, k2s = A.k2 * A.k2;
+  const double C = (k1s - k2s) / (2.0 * kPi);
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    const double d = a * a + J * J;
+    const double sg = jt < 0 ? -1.0 : 1.0;
+    double2 dK = mk((k1s - k2s) / ((d - k1s) * (d - k2s)), 0.0);
+    if (use1) dK = cadd(dK, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
+    if (use2) dK = csub(dK, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+    dK = cscale(dK, A.A);
+    const size_t o = (size_t)jtp * A.M1 + j1p;
+    const double h11 = C * (D[o] + A.a1 * D[n + o]);
+    const double h12 = C * (D[2 * n + o] + A.a1 * D[3 * n + o]);
+    const double h22 = C * (D[4 * n + o] + A.a1 * D[5 * n + o]);
+    store_c<T>(out, o, cscale(mk(-a * a * dK.x - h11, -a * a * dK.y), A.A));
+    store_c<T>(out + A.fstride, o, cscale(mk(-a * J * dK.x - h12, -a * J * dK.y), A.A));
+    store_c<T>(out + 2 * A.fstride, o, cscale(mk(-J * J * dK.x - h22, -J * J * dK.y), A.A));
+  }
+}
+
 // Far slab, 2D: (i/4pi) beta_n^-1 e^{i beta_n z_s} of the series (1.2).
 template <typename T>
 __global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf, cplx<T>* __restrict__ out) {
@@ -458,6 +564,29 @@ __global__ void k_far2d_grad(double k, double a, int M1, int S, double z0, doubl
   const double2 f = cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), e);
   store_c<T>(out, idx, mk(-an * f.y, an * f.x));
   store_c<T>(out + fstride, idx, cscale(e, -1.0 / (4.0 * kPi)));
+}
+
+// Far slab of the second-derivative differences: the coefficients of (1.2) times -alpha_n^2,
+// -alpha_n beta_n (sgn(x2) at the target) and -beta_n^2, for k1 minus for k2.
+template <typename T>
+__global__ void k_far2d_hess(double k1, double k2, double a, int M1, int S, double z0, double hf, long fstride,
+                             cplx<T>* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M1 * S) return;
+  const int j1p = (int)(idx % M1), s = (int)(idx / M1);
+  const double an = a + centered(j1p, M1), z = z0 + s * hf;
+  double2 f11 = mk(0.0, 0.0), f12 = mk(0.0, 0.0), f22 = mk(0.0, 0.0);
+  for (int w = 0; w < 2; ++w) {
+    const double k = w == 0 ? k1 : k2, sg = w == 0 ? 1.0 : -1.0;
+    const double2 b = beta_of(k, fabs(an));
+    const double2 f = cscale(cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))), sg);
+    f11 = cadd(f11, cscale(f, -an * an));
+    f12 = csub(f12, cscale(cmul(b, f), an));
+    f22 = csub(f22, cmul(cmul(b, b), f));
+  }
+  store_c<T>(out, idx, f11);
+  store_c<T>(out + fstride, idx, f12);
+  store_c<T>(out + 2 * fstride, idx, f22);
 }
 
 // Far slab of many 2D instances: instance i owns blocks [blk0_i, blk0_{i+1}) of 256 threads.
@@ -493,8 +622,12 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse) {
   if (P.dim == 2) {
     A.A = 1.0 / (2.0 * sqrt(kPi * A.c_tilde));
     dim3 grid((P.M1 + TP - 1) / TP, 1);
+    A.k2 = P.last_k2;
     if (P.nf == 2)
       hipLaunchKernelGGL(k_fill2d_grad<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2, out);
+    else if (P.nf == 3)
+      hipLaunchKernelGGL(k_fill2d_hess<T>, grid, dim3(TP * TL), 2 * shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2,
+                         out);
     else
       hipLaunchKernelGGL(k_fill2d<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2, out);
   } else {
@@ -525,6 +658,9 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
     if (P.nf == 2)
       hipLaunchKernelGGL(k_far2d_grad<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf,
                          (long)P.nfar, out);
+    else if (P.nf == 3)
+      hipLaunchKernelGGL(k_far2d_hess<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, P.last_k2, a1, P.M1,
+                         P.S, z0, hf, (long)P.nfar, out);
     else
       hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
   } else {
@@ -553,6 +689,14 @@ hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* w
   const long n = (long)P.M1 * P.M2;
   const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
   hipLaunchKernelGGL(k_sing2d_grad, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
+                     P.p.eps, Qg, rg, wyg, P.D2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sing2d_hess(Plan& P, int Qg, const double* rg, const double* wyg) {
+  const long n = (long)P.M1 * P.M2;
+  const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
+  hipLaunchKernelGGL(k_sing2d_hess, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
                      P.p.eps, Qg, rg, wyg, P.D2);
   return hipGetLastError();
 }

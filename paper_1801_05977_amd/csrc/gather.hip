@@ -16,6 +16,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 
 struct GArgs {
   double k, a1, a2, c, c_tilde, eps, rmin;
+  double k2;               // second wavenumber (differences of second derivatives, 2D)
   int M1, M2, M3;          // 2D: M2 = transverse size, M3 = 1
   double h1, h2, h3;       // 2D: h2 = transverse spacing
   double ih1, ih2, ih3;    // reciprocals of the spacings
@@ -859,6 +860,97 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
   if (i < T_) gather2d_grad_one<T>(A, grid, far, x, i, out, flags);
 }
 
+// One target of the second-derivative differences (Section 2.4.2): three fields with one
+// stencil, h_pq added back in FP64 inside 2 eps, the phase e^{i alpha x1}; beyond c the far
+// slab, the 12 field times sgn(x2).  out[3i + p] = d_p d_q G_k1 - d_p d_q G_k2, pq = 11, 12, 22.
+template <typename T>
+__device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+                                                  const cplx<T>* __restrict__ far, const double* __restrict__ x,
+                                                  long i, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
+  const double x1 = x[2 * i], x2 = x[2 * i + 1];
+  uint8_t fl = 0;
+  double2 d[3];
+  if (!(isfinite(x1) && isfinite(x2))) {
+    fl = 8;
+    d[0] = d[1] = d[2] = nan2();
+  } else {
+    double n1;
+    const double t = reduce_cell(x1, n1);
+    T w1[4], w2[4];
+    const double u = t * A.ih1, p = floor(u);
+    lag4<T>((T)(u - p), w1);
+    const int i0 = ((int)p - 1) & (A.M1 - 1);
+    double ps, pc;
+    sincos(A.a1 * x1, &ps, &pc);
+    const double2 phase = mk(pc, ps);
+    const bool is_near = fabs(x2) <= A.c;
+    long rows[4];
+    const cplx<T>* g = grid;
+    long fst = A.fs;
+    bool bad = false;
+    if (is_near) {
+      const double u2 = x2 * A.ih2, p2 = floor(u2);
+      lag4<T>((T)(u2 - p2), w2);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
+    } else {
+      fl |= 2;
+      g = far;
+      fst = A.ffs;
+      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
+      double s0 = floor(v);
+      if (s0 > A.S - 3) {
+        bad = true;
+        fl |= 4;
+      } else {
+        s0 = fmax(s0, 1.0);
+        lag4<T>((T)(v - s0), w2);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
+      }
+    }
+    if (bad) {
+      d[0] = d[1] = d[2] = nan2();
+    } else {
+      double2 L[3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) L[f] = stencil2d<T>(g + f * fst, rows, i0, A.M1, w1, w2);
+      if (is_near) {
+        const double r2 = t * t + x2 * x2;
+        if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+          fl |= 1;
+          L[0] = L[1] = L[2] = nan2();
+        } else if (r2 < 4.0 * A.eps * A.eps) {
+          // h_pq = C Y [ (ln r/2 + x_p x_q/(2r^2)) or x1 x2/(2r^2), minus i alpha x1 times the same ]
+          const double r = sqrt(r2), ir2 = 0.5 / r2, hl = 0.5 * log(r);
+          const double C = (A.k * A.k - A.k2 * A.k2) / (2.0 * kPi) * cut_Y(r, A.eps);
+          const double s11 = hl + t * t * ir2, s12 = t * x2 * ir2, s22 = hl + x2 * x2 * ir2;
+          const double at = -A.a1 * t;
+          L[0] = cadd(L[0], mk(C * s11, C * at * s11));
+          L[1] = cadd(L[1], mk(C * s12, C * at * s12));
+          L[2] = cadd(L[2], mk(C * s22, C * at * s22));
+        }
+      } else if (x2 < 0.0) {
+        L[1] = cscale(L[1], -1.0);
+      }
+#pragma unroll
+      for (int f = 0; f < 3; ++f) d[f] = cmul(phase, L[f]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) store_out<T>(out, 3 * i + f, d[f]);
+  if (flags) flags[i] = fl;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather2d_hess(GArgs A, const cplx<T>* __restrict__ grid,
+                                                       const cplx<T>* __restrict__ far, const double* __restrict__ x,
+                                                       long T_, cplx<T>* __restrict__ out,
+                                                       uint8_t* __restrict__ flags) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T_) gather2d_hess_one<T>(A, grid, far, x, i, out, flags);
+}
+
 // Many 2D instances in one launch: instance i owns blocks [blk0_i, blk0_{i+1}) and
 // targets [t0_i, t1_i) of the concatenated target array.
 struct GatherInst {
@@ -1078,6 +1170,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
                        int mode = kGatherAll, hipStream_t bin_stream = nullptr) {
   GArgs A;
   A.k = P.last_k;
+  A.k2 = P.last_k2;
   A.a1 = P.last_a1;
   A.a2 = P.last_a2;
   A.c = P.p.c;
@@ -1117,6 +1210,8 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     KernelTimer t(P, QPGF_T_GATHER);
     if (P.nf == 2)
       hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    else if (P.nf == 3)
+      hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     else
       hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     return hipGetLastError();

@@ -128,11 +128,13 @@ struct Plan {
   int twlog2 = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
-  double* D2 = nullptr;        // 2D gradient tables [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2)
+  double* D2 = nullptr;        // 2D derivative tables: gradient [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2),
+                               // second-derivative differences [6][j2'][j1'] (u11 v11 u12 v12 u22 v22)
   double2* htab = nullptr;     // 3D: H(rho) on rho = (m - 4) dh
   int hn = 0;
   double hd = 0.05;
   double last_k = 0, last_a1 = 0, last_a2 = 0;
+  double last_k2 = 0;          // second wavenumber (differences of second derivatives)
   bool prepared = false;
 
   // target binning scratch (3D), grown on demand
@@ -201,6 +203,7 @@ struct KernelTimer {
 };
 
 // kernel launchers (fill.hip, fft.hip, gather.hip)
+hipError_t launch_sing2d_hess(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d(Plan& P, double f1_zero);
 hipError_t launch_htable(Plan& P, double k);

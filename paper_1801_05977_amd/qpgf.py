@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqpgf.so")
 
 C128, C64 = 0, 1
-KIND_G2D, KIND_GD3D, KIND_MAXWELL3D, KIND_G2D_GRAD = 0, 1, 2, 3
+KIND_G2D, KIND_GD3D, KIND_MAXWELL3D, KIND_G2D_GRAD, KIND_G2D_HESS_DIFF = 0, 1, 2, 3, 4
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_WOOD", 3: "E_SPECIAL", 4: "E_SIZE", 5: "E_HIP", 6: "E_NOMEM",
           7: "E_UNSUPPORTED"}
 
@@ -43,7 +43,7 @@ class PlanInfo(ctypes.Structure):
 
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
-           "qpgf_g2d_grad", "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
+           "qpgf_g2d_grad", "qpgf_g2d_hess_diff", "qpgf_prepare_hess_diff", "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
            "qpgf_g2d_batched", "qpgf_plan_autotune", "qpgf_last_error", "qpgf_version", "qpgf_evaluate_smooth",
            "qpgf_mlp_param_count", "qpgf_mlp_create", "qpgf_mlp_destroy", "qpgf_mlp_set_stream",
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
@@ -76,6 +76,8 @@ def lib():
     L.qpgf_evaluate.argtypes = [P, VP, I64, VP, U8P]
     L.qpgf_g2d.argtypes = [P, D, D, VP, I64, VP, U8P]
     L.qpgf_g2d_grad.argtypes = [P, D, D, VP, I64, VP, U8P]
+    L.qpgf_g2d_hess_diff.argtypes = [P, D, D, D, VP, I64, VP, U8P]
+    L.qpgf_prepare_hess_diff.argtypes = [P, D, D, D, ctypes.c_int]
     L.qpgf_gd3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
     L.qpgf_maxwell3d.argtypes = [P, D, D, D, VP, I64, VP, U8P]
     L.qpgf_copy_field.argtypes = [P, ctypes.c_int, ctypes.c_int, VP]
@@ -152,7 +154,7 @@ class Plan:
         _check(lib().qpgf_plan_get_info(self._h, ctypes.byref(info)))
         self.info = info
         self.kind, self.prec = kind, prec
-        self.dim = 2 if kind in (KIND_G2D, KIND_G2D_GRAD) else 3
+        self.dim = 2 if kind in (KIND_G2D, KIND_G2D_GRAD, KIND_G2D_HESS_DIFF) else 3
         self.cdtype = torch.complex128 if prec == C128 else torch.complex64
 
     def close(self):
@@ -170,7 +172,7 @@ class Plan:
         _check(lib().qpgf_plan_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
     def out_tensor(self, T):
-        shape = {KIND_MAXWELL3D: (T, 6), KIND_G2D_GRAD: (T, 2)}.get(self.kind, (T,))
+        shape = {KIND_MAXWELL3D: (T, 6), KIND_G2D_GRAD: (T, 2), KIND_G2D_HESS_DIFF: (T, 3)}.get(self.kind, (T,))
         return torch.empty(shape, dtype=self.cdtype, device="cuda")
 
     def prepare(self, k, a1, a2=0.0, stage=2):
@@ -194,6 +196,8 @@ class Plan:
             out = self.out_tensor(T)
         self._stream()
         px, po, pf = _ptr(x, torch.float64, "x"), _ptr(out, self.cdtype, "out"), _ptr(flags, torch.uint8, "flags")
+        if self.kind == KIND_G2D_HESS_DIFF:
+            raise ValueError("a KIND_G2D_HESS_DIFF plan takes two wavenumbers: use Plan.hess_diff")
         if self.kind == KIND_G2D:
             _check(lib().qpgf_g2d(self._h, k, a1, px, T, po, pf))
         elif self.kind == KIND_G2D_GRAD:
@@ -202,6 +206,21 @@ class Plan:
             _check(lib().qpgf_gd3d(self._h, k, a1, a2, px, T, po, pf))
         else:
             _check(lib().qpgf_maxwell3d(self._h, k, a1, a2, px, T, po, pf))
+        return out
+
+    def prepare_hess_diff(self, k1, k2, alpha, stage=2):
+        """qpgf_prepare_hess_diff (plans of kind KIND_G2D_HESS_DIFF)."""
+        self._stream()
+        _check(lib().qpgf_prepare_hess_diff(self._h, k1, k2, alpha, stage))
+
+    def hess_diff(self, k1, k2, alpha, x, out=None, flags=None):
+        """qpgf_g2d_hess_diff: [T, 3] = d11, d12, d22 of G_k1 - G_k2 at x [T, 2]."""
+        T = x.shape[0]
+        if out is None:
+            out = self.out_tensor(T)
+        self._stream()
+        _check(lib().qpgf_g2d_hess_diff(self._h, k1, k2, alpha, _ptr(x, torch.float64, "x"), T,
+                                        _ptr(out, self.cdtype, "out"), _ptr(flags, torch.uint8, "flags")))
         return out
 
     def batched(self, k, alpha, m1, t_off, x, out=None, flags=None):
