@@ -96,7 +96,39 @@ def xprime_integrals(b, J, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
 
 def _coef_K(A, k, b, J, lead_den, Im, Ip):
     """A [ 1/(|xi|^2 - k^2) + I(b-J)/(2b(J-b)) - I(b+J)/(2b(J+b)) ]  (eqs. 2.1, 3.3)."""
-    return A * (1.0 / lead_den + Im / (2 * b * (J - b)) - Ip / (2 * b * (J + b)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return A * (1.0 / lead_den + Im / (2 * b * (J - b)) - Ip / (2 * b * (J + b)))
+
+
+# The special coefficients beta = -+J of Sections 2.1 / 3.1, where the integration by parts
+# behind (2.1) / (3.3) divides by zero (and loses digits close to it): there the coefficient
+# is taken from the integral that defines it,
+#     K-hat_j = A (i / (2 beta)) [ I0(beta - J) + I0(beta + J) ],   I0(g) = int_0^{c~} e^{igx} X(x) dx,
+# which is the paper's special-case formula (its g = 0 term is int X) for every g.
+SPECIAL_SWITCH = 1e-2
+
+
+def x_integral(g, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
+    """I0(g) = int_0^{c~} e^{igx} X(x) dx for an array of g (X = 1 on [0, c], 0 beyond (c + c~)/2)."""
+    x0, w0 = gauss_legendre(0.0, c, q)
+    x1, w1 = gauss_legendre(c, 0.5 * (c + c_tilde), q)
+    x = np.concatenate([x0, x1])
+    w = np.concatenate([w0, w1 * co.X(x1, c, c_tilde)])
+    g = np.asarray(g, dtype=np.complex128)
+    return (np.exp(1j * g.ravel()[:, None] * x[None, :]) @ w).reshape(g.shape)
+
+
+def _special(b, J):
+    """Coefficients with a propagating beta within SPECIAL_SWITCH of |J|."""
+    return (np.imag(b) == 0) & (np.abs(np.real(b) - np.abs(J)) < SPECIAL_SWITCH)
+
+
+def _special_fix(K, A, b, J, c, c_tilde, q):
+    m = _special(b, J)
+    if m.any():
+        bb, JJ = np.broadcast_to(b, m.shape)[m], np.broadcast_to(J, m.shape)[m]
+        K[m] = A * (1j / (2 * bb)) * (x_integral(bb - JJ, c, c_tilde, q) + x_integral(bb + JJ, c, c_tilde, q))
+    return K
 
 
 # ----------------------------------------------------------------------------
@@ -111,7 +143,8 @@ def khat_2d(k, alpha, N1, N2, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
     b = beta(k, a)
     Im, Ip = xprime_integrals(b, J, c, c_tilde, q)
     B, JJ = b[:, None], J[None, :]
-    return _coef_K(A2, k, B, JJ, a[:, None] ** 2 + JJ ** 2 - k * k, Im, Ip)
+    K = _coef_K(A2, k, B, JJ, a[:, None] ** 2 + JJ ** 2 - k * k, Im, Ip)
+    return _special_fix(K, A2, B, JJ, c, c_tilde, q)
 
 
 def phi1(r, eps=co.EPS):
@@ -278,6 +311,7 @@ def khat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, q=ORACLE_Q):
     Im, Ip = xprime_integrals(b, J, c, c_tilde, q)
     den = rp2[:, None] + J[None, :] ** 2 - k * k
     K = _coef_K(A3, k, b[:, None], J[None, :], den, Im, Ip)
+    K = _special_fix(K, A3, b[:, None], J[None, :], c, c_tilde, q)
     return K.reshape(2 * N1, 2 * N2, 2 * N3)
 
 
@@ -287,7 +321,19 @@ def fhat_3d(k, a1, a2, N1, N2, N3, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
     rp2, J = _xi_3d(a1, a2, N1, N2, N3, c_tilde)
     xi2 = rp2[:, None] + J[None, :] ** 2
     H = radial_H(k, np.sqrt(xi2), eps, q)
-    return (A3 * (1.0 - H) / (xi2 - k * k)).reshape(2 * N1, 2 * N2, 2 * N3)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = A3 * (1.0 - H) / (xi2 - k * k)
+    # |xi| = k (the special coefficients): (1 - H)/(|xi|^2 - k^2) is 0/0 there; take the
+    # radial form of the transform of e^{ikr} Y / (4 pi r) itself, (1/|xi|) int e^{ikr} Y sin(|xi| r) dr
+    m = np.abs(np.sqrt(xi2) - k) < SPECIAL_SWITCH
+    if m.any():
+        rho = np.sqrt(xi2[m])
+        r0, w0 = gauss_legendre(0.0, eps, q)
+        r1, w1 = gauss_legendre(eps, 2 * eps, q)
+        r = np.concatenate([r0, r1])
+        w = np.concatenate([w0, w1]) * co.Y(r, eps) * np.exp(1j * k * r)
+        F[m] = A3 * (np.sin(np.outer(rho, r)) @ w) / rho
+    return F.reshape(2 * N1, 2 * N2, 2 * N3)
 
 
 def lhat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
