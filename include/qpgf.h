@@ -55,8 +55,8 @@ typedef enum {
   QPGF_OK = 0,
   QPGF_E_ARG = 1,          /* invalid argument (null pointer, bad size, wrong plan kind) */
   QPGF_E_WOOD = 2,         /* min_n |beta_n| < wood_tol: Wood anomaly (Section 1)        */
-  QPGF_E_SPECIAL = 3,      /* |beta -+ j pi / c~| < special_tol: the integration by parts
-                              behind eqs. 2.1 / 3.3 is singular (Sections 2.1, 3.1)      */
+  QPGF_E_SPECIAL = 3,      /* kept for the ABI; no longer returned: the special
+                              coefficients beta = -+j pi/c~ are evaluated (special_tol)  */
   QPGF_E_SIZE = 4,         /* unsupported grid size                                      */
   QPGF_E_HIP = 5,          /* a HIP runtime call failed                                  */
   QPGF_E_NOMEM = 6,        /* device allocation failed                                   */
@@ -83,7 +83,14 @@ typedef enum {
  * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
  * eps = 0.2, cut-offs: C^8 smoothstep I_u(9,9) transitions (Section 6 states C^8),
  * quad_q = 64, far_h = c_tilde / N_t, far_zmax = c_tilde, wood_tol = 1e-3,
- * special_tol = 1e-6, lattice_rmin = 0. */
+ * special_tol = 1e-2, lattice_rmin = 0.
+ * special_tol: a coefficient whose propagating beta lies within special_tol of |J|
+ * (J = j_t pi / c~; the special cases of Sections 2.1 / 3.1, where the integration
+ * by parts behind eqs. 2.1 / 3.3 divides by beta -+ J and loses digits close to it)
+ * is computed from the integral that defines it, (i/(2 beta)) [I0(beta - J) +
+ * I0(beta + J)] A, I0(g) = int_0^{c~} e^{igx} X(x) dx (the paper's special-case
+ * formula), and in 3D the singular part's coefficient, 0/0 at |xi| = k in eq. 3.5,
+ * from the radial transform of e^{ikr} Y/(4 pi r).  No instance is refused for it. */
 typedef struct {
   int kind;                /* qpgf_kind */
   int prec;                /* qpgf_prec: precision of grids, FFTs, gather and output */
@@ -136,8 +143,8 @@ qpgf_status qpgf_plan_get_info(const qpgf_plan* plan, qpgf_plan_info* info);
 /* Preparation step of Algorithm 2.1 / 3.1 / 4.1 for one instance: fill the
  * coefficients L-hat (and L-hat^{pq}) in FP64, inverse-FFT them to the near
  * grid, and build the far-slab grid.  a2 is ignored in 2D.  The grids stay in
- * the plan until the next prepare.  Returns QPGF_E_WOOD / QPGF_E_SPECIAL when
- * the instance is excluded (checked on the host before any launch). */
+ * the plan until the next prepare.  Returns QPGF_E_WOOD when the instance is
+ * excluded (checked on the host before any launch). */
 qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2);
 
 /* Calculation step (Algorithm 2.1 / 3.1 / 4.1 step 2) for T targets against the
@@ -169,7 +176,7 @@ qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double alpha1, double alph
  * slab, 8: non-finite input; the flagged results are NaN).  Ownership: the
  * caller owns x, out and flags; the call is stream-ordered on the plan's stream.
  * Errors: QPGF_E_ARG for a plan of another kind, T < 0 or NULL pointers with
- * T > 0; QPGF_E_WOOD / QPGF_E_SPECIAL for excluded instances (before any launch). */
+ * T > 0; QPGF_E_WOOD for excluded instances (before any launch). */
 qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha,
                           const double* x, int64_t T, void* out, uint8_t* flags);
 
@@ -185,8 +192,8 @@ qpgf_status qpgf_g2d_grad(qpgf_plan* plan, double k, double alpha,
  * the two Hankel functions; the printed definitions carry a minus sign).  The far
  * slab holds the series (1.2) differentiated twice term by term.  x: device float64
  * [T][2]; out: device complex [T][3] (11, 12, 22) in the plan's precision; flags as
- * for qpgf_g2d.  k1 = k2 gives zeros.  Errors as for qpgf_g2d_grad, Wood / special
- * checks for both wavenumbers. */
+ * for qpgf_g2d.  k1 = k2 gives zeros.  Errors as for qpgf_g2d_grad, Wood checks for
+ * both wavenumbers. */
 qpgf_status qpgf_g2d_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha,
                                const double* x, int64_t T, void* out, uint8_t* flags);
 
@@ -208,7 +215,7 @@ qpgf_status qpgf_prepare_hess_diff(qpgf_plan* plan, double k1, double k2, double
  * m1[], t_off[], x, out and flags (k and alpha may differ).  The 2D singular
  * tables of the plan serve every instance (they depend on the coefficient index
  * only, Remark 2.1).  Needs a plan of kind QPGF_KIND_G2D; every instance is
- * checked for Wood anomalies and special coefficients before any launch. */
+ * checked for Wood anomalies before any launch. */
 qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const double* k, const double* alpha, const int* m1,
                              const int64_t* t_off, const double* x, void* out, uint8_t* flags);
 
@@ -263,7 +270,7 @@ const char* qpgf_mlp_last_error(void);
  * (0 = surrogate value); *n_fallback (host, may be NULL) receives their count.
  * Synchronises the model's stream once (to size the fallback work) and sets the
  * plan's stream to the model's.  Errors: E_ARG (NULLs, plan not GD3D or not
- * c = 0.6, c~ = 1), E_WOOD/E_SPECIAL from the plain method on a fallback instance
+ * c = 0.6, c~ = 1), E_WOOD from the plain method on a fallback instance
  * (message names the instance), E_HIP/E_NOMEM. */
 qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double wood_tol, double rmin, int n_inst,
                                 const double* k, const double* a1, const double* a2, const int64_t* t_off,

@@ -99,7 +99,7 @@ void free_plan(Plan& P) {
   if (P.b_host) (void)hipHostFree(P.b_host);
   for (void* q : {P.b_grid, P.b_far, P.b_desc})
     if (q) (void)hipFree(q);
-  void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
+  void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.wXq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
                   P.twf,  P.F1,  P.F2,   P.D2, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -143,33 +143,22 @@ qpgf_status check_instance(const Plan& P, double k, double a1, double a2) {
 }
 
 qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int M1) {
+  (void)M1;
   if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(a1) || !std::isfinite(a2))
     return fail(QPGF_E_ARG, "need finite k > 0 and finite alpha");
-  const double wt = P.p.wood_tol, st = P.p.special_tol;
-  const int Nt = P.Mt / 2;
-  auto special = [&](double rho) -> bool {
-    // |beta - |J|| for a propagating beta against every transverse index of the grid
-    if (rho >= k) return false;
-    double b = sqrt((k - rho) * (k + rho));
-    double jt = std::round(b * P.p.c_tilde / M_PI);
-    if (jt > Nt) return false;
-    return fabs(b - jt * M_PI / P.p.c_tilde) < st;
-  };
+  // the special coefficients beta = -+j pi / c~ are evaluated by the fills (Sections 2.1 / 3.1)
+  const double wt = P.p.wood_tol;
   double minb = 1e300;
   if (P.dim == 2) {
     for (long n = (long)floor(-k - a1) - 1; n <= (long)ceil(k - a1) + 1; ++n) {
       double rho = fabs(a1 + n);
       minb = std::min(minb, sqrt(fabs((k - rho) * (k + rho))));
-      if (n >= -M1 / 2 && n < M1 / 2 && special(rho))
-        return fail(QPGF_E_SPECIAL, "beta_j1 = j2 pi / c_tilde within special_tol (perturb c_tilde)");
     }
   } else {
     for (long n1 = (long)floor(-k - a1) - 1; n1 <= (long)ceil(k - a1) + 1; ++n1)
       for (long n2 = (long)floor(-k - a2) - 1; n2 <= (long)ceil(k - a2) + 1; ++n2) {
         double rho = sqrt((a1 + n1) * (a1 + n1) + (a2 + n2) * (a2 + n2));
         minb = std::min(minb, sqrt(fabs((k - rho) * (k + rho))));
-        if (n1 >= -M1 / 2 && n1 < M1 / 2 && n2 >= -P.M2 / 2 && n2 < P.M2 / 2 && special(rho))
-          return fail(QPGF_E_SPECIAL, "beta_j1j2 = j3 pi / c_tilde within special_tol (perturb c_tilde)");
       }
   }
   if (minb < wt) {
@@ -180,6 +169,37 @@ qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int
   return QPGF_OK;
 }
 
+// Whether some coefficient of the grid (x1 index within M1, transverse index within Mt) has
+// a propagating beta within special_tol of |J| (J = j pi / c~): only then do the fills compile
+// in the special-case path.  A little wider than the fills' own test, so that rounding
+// cannot put a coefficient on the other side.
+bool has_special(const Plan& P, double k, double a1, double a2, int M1) {
+  const long double tol = (long double)P.p.special_tol * 1.01L + 1e-12L;
+  const long double step = (long double)M_PI / P.p.c_tilde;
+  const long Nt = P.Mt / 2;
+  auto near_J = [&](long double rho) -> bool {
+    if (rho >= k) return false;
+    const long double b = sqrtl(((long double)k - rho) * ((long double)k + rho));
+    long j = (long)floorl(b / step);
+    for (long jj = j; jj <= j + 1; ++jj)
+      if (jj <= Nt && fabsl(b - jj * step) < tol) return true;
+    return false;
+  };
+  const long lo1 = std::max((long)floor(-k - a1) - 1, (long)(-M1 / 2)), hi1 = std::min((long)ceil(k - a1) + 1, (long)(M1 / 2 - 1));
+  if (P.dim == 2) {
+    for (long n = lo1; n <= hi1; ++n)
+      if (near_J(fabsl((long double)a1 + n))) return true;
+    return false;
+  }
+  const long lo2 = std::max((long)floor(-k - a2) - 1, (long)(-P.M2 / 2)), hi2 = std::min((long)ceil(k - a2) + 1, (long)(P.M2 / 2 - 1));
+  for (long n1 = lo1; n1 <= hi1; ++n1)
+    for (long n2 = lo2; n2 <= hi2; ++n2) {
+      const long double e1 = (long double)a1 + n1, e2 = (long double)a2 + n2;
+      if (near_J(sqrtl(e1 * e1 + e2 * e2))) return true;
+    }
+  return false;
+}
+
 qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, double k2 = 0.0) {
   qpgf_status st = check_instance(P, k, a1, a2);
   if (st != QPGF_OK) return st;
@@ -188,6 +208,8 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
     if (st != QPGF_OK) return st;
   }
   P.last_k2 = k2;
+  P.spec = has_special(P, k, a1, a2, P.M1) ||
+           (P.p.kind == QPGF_KIND_G2D_HESS_DIFF && has_special(P, k2, a1, a2, P.M1));
   P.last_k = k;
   P.last_a1 = a1;
   P.last_a2 = a2;
@@ -298,7 +320,7 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
   p->far_h = mt > 0 ? p->c_tilde / (mt / 2) : 0.0;
   p->far_zmax = p->c_tilde;
   p->wood_tol = 1e-3;
-  p->special_tol = 1e-6;
+  p->special_tol = 1e-2;
   p->lattice_rmin = 0.0;
 }
 
@@ -351,15 +373,17 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   // X'-integral rule on [c, (c + c~)/2]: X'(x) = -S'((x - c)/w)/w, w = (c~ - c)/2
   {
     const long double c = p->c, w = 0.5L * (p->c_tilde - p->c);
-    std::vector<double> xq(Q), wxq(Q);
+    std::vector<double> xq(Q), wxq(Q), wXq(Q);
     for (int q = 0; q < Q; ++q) {
       long double x = c + 0.5L * w * (gx[q] + 1.0L);
       long double u = (x - c) / w;
       xq[q] = (double)x;
       wxq[q] = (double)(0.5L * w * gw[q] * (-(long double)smooth_S1((double)u) / w));
+      wXq[q] = (double)(0.5L * w * gw[q] * (1.0L - (long double)smooth_S((double)u)));
     }
     PLAN_ST(upload(&P.xq, xq));
     PLAN_ST(upload(&P.wxq, wxq));
+    PLAN_ST(upload(&P.wXq, wXq));
     const int Nt = P.Mt / 2;
     std::vector<double2> cs((size_t)(Nt + 1) * Q);
     for (int j = 0; j <= Nt; ++j)
@@ -712,9 +736,12 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   HIP_TRY(hipMemcpyAsync(P.b_desc, P.b_host, Lo.bytes, hipMemcpyHostToDevice, user));
   HIP_TRY(hipEventRecord(P.b_upload_done, user));
 
+  bool spec = false;
+  for (int i = 0; i < n_inst && !spec; ++i) spec = has_special(P, k[i], alpha[i], 0.0, m1[i]);
   std::vector<int64_t> sig;
   sig.push_back(n_inst);
   sig.push_back(P.p.prec);
+  sig.push_back(spec);
   for (int i = 0; i < n_inst; ++i) sig.push_back(m1[i]);
   for (int i = 0; i <= n_inst; ++i) sig.push_back(t_off[i]);
   for (const void* q : {(const void*)x, (const void*)out, (const void*)flags, (const void*)P.b_grid,
@@ -728,7 +755,7 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
     P.stream = P.b_capture;
     char* d = static_cast<char*>(P.b_desc);
     hipError_t e = hipStreamBeginCapture(P.b_capture, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_fill2d_multi(P, d + Lo.fill_off, n_inst, Lo.fill_blocks, P.b_grid);
+    if (e == hipSuccess) e = launch_fill2d_multi(P, d + Lo.fill_off, n_inst, Lo.fill_blocks, P.b_grid, spec);
     if (e == hipSuccess)
       e = launch_fft_multi(P, P.b_grid, reinterpret_cast<const FftSeg*>(d + Lo.segT_off), n_inst, Lo.segT_blocks,
                            Lo.lds_T);

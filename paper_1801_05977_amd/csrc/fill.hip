@@ -36,6 +36,12 @@ struct FillArgs {
   int M1, M2, Mt, Q;
   double hd;                 // H table spacing (3D)
   long fstride;              // elements per field
+  // special coefficients (a propagating beta within stol of |J|, Sections 2.1 / 3.1)
+  double stol;
+  const double* wXq;         // w_q X(x_q) at the X'-rule nodes on [c, (c + c~)/2]
+  const double* rq;          // radial rule on [eps, 2 eps] (3D singular part)
+  const double* wrq;
+  double eps;
 };
 
 // a_q = w_q X'(x_q) e^{i beta x_q} for the TP pencils of this block, into LDS.
@@ -83,6 +89,54 @@ __device__ __forceinline__ double2 xprime_term(const double2* __restrict__ ap, c
   return csub(cdiv(Im, dm), cdiv(Ip, dp));
 }
 
+// ---- special coefficients: beta = -+J (Sections 2.1 / 3.1) ----
+// There the integration by parts behind (2.1) / (3.3) divides by beta -+ J (and loses digits
+// close to it); the coefficient is taken from the integral that defines it,
+//   K-hat_j / A = (i / (2 beta)) [I0(beta - J) + I0(beta + J)],   I0(g) = int_0^{c~} e^{igx} X(x) dx,
+// the paper's special-case formula (its g = 0 term is int X) for every g near the special point.
+__device__ __forceinline__ bool special_coef(double2 b, double J, double stol) {
+  return b.y == 0.0 && fabs(b.x - fabs(J)) < stol;
+}
+// (e^{i th} - 1) / (i th), without cancellation for small th
+__device__ __forceinline__ double2 e1i(double th) {
+  if (th == 0.0) return mk(1.0, 0.0);
+  const double h = sin(0.5 * th);
+  return mk(sin(th) / th, 2.0 * h * h / th);
+}
+// I0(g) = c E1(i g c) + sum_q w_q X(x_q) e^{i g x_q}  (X = 1 on [0, c], 0 beyond (c + c~)/2)
+__device__ double2 x_integral0(double g, const FillArgs& A, const double* __restrict__ xq) {
+  double2 s = cscale(e1i(g * A.c), A.c);
+  for (int q = 0; q < A.Q; ++q) {
+    double sn, cn;
+    sincos(g * xq[q], &sn, &cn);
+    s.x = fma(A.wXq[q], cn, s.x);
+    s.y = fma(A.wXq[q], sn, s.y);
+  }
+  return s;
+}
+__device__ double2 khat_direct(double beta, double J, const FillArgs& A, const double* __restrict__ xq) {
+  const double2 I = cadd(x_integral0(beta - J, A, xq), x_integral0(beta + J, A, xq));
+  return cmul(mk(0.0, 0.5 / beta), I);
+}
+// 3D: at |xi| = k the singular part's coefficient (1 - H)/(|xi|^2 - k^2) is 0/0; its value is
+// the radial transform of e^{ikr} Y / (4 pi r), (1/rho) int_0^{2 eps} e^{ikr} Y(r) sin(rho r) dr:
+// closed form on [0, eps] (Y = 1), the radial rule on [eps, 2 eps].
+__device__ double2 fhat_direct(double k, double rho, const FillArgs& A) {
+  const double e = A.eps;
+  // int_0^eps e^{ikr} sin(rho r) dr = (eps / 2i) [E1(i(k + rho) eps) - E1(i(k - rho) eps)]
+  const double2 d = csub(e1i((k + rho) * e), e1i((k - rho) * e));
+  double2 s = mk(0.5 * e * d.y, -0.5 * e * d.x);
+  for (int q = 0; q < A.Q; ++q) {
+    const double r = A.rq[q];
+    double sn, cn;
+    sincos(k * r, &sn, &cn);
+    const double w = A.wrq[q] * cut_Y(r, e) * sin(rho * r);
+    s.x = fma(w, cn, s.x);
+    s.y = fma(w, sn, s.y);
+  }
+  return cscale(s, 1.0 / rho);
+}
+
 // H(rho) by 8-point Lagrange interpolation of the table H(m hd - 4 hd).
 __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, double hd, double rho) {
   double u = rho / hd;
@@ -118,7 +172,7 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
 // (Algorithm 3.1 step 1c) in LDS and writes grid values instead of
 // coefficients, saving one pass over the grid (one field only; the transform
 // is the same sequence of passes and twiddles as the separate FFT kernel).
-template <typename T, int NF, bool FUSE>
+template <typename T, int NF, bool FUSE, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __restrict__ xq,
                                                 const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                 const double2* __restrict__ htab, cplx<T>* __restrict__ out,
@@ -143,11 +197,19 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
-    double2 term = mk(0.0, 0.0);
-    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
     const double rho2 = rp2 + J * J;
-    const double2 H = h_interp(htab, A.hd, sqrt(rho2));
-    const double2 L = cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A);
+    double2 L;
+    bool special = false;
+    if constexpr (SPEC) special = special_coef(b, J, A.stol);
+    if (special) {
+      // L-hat = K-hat - F-hat, each from its defining integral
+      L = cscale(csub(khat_direct(b.x, J, A, xq), fhat_direct(A.k, sqrt(rho2), A)), A.A * A.A);
+    } else {
+      double2 term = mk(0.0, 0.0);
+      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+      const double2 H = h_interp(htab, A.hd, sqrt(rho2));
+      L = cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A);
+    }
     if constexpr (FUSE) {
       store_c<T>(pen, (size_t)ip * pitch + jtp, L);
       continue;
@@ -177,7 +239,7 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
 // 2D near fill (Algorithm 2.1 steps 1a-1b): L-hat = K-hat (2.1) - F1 + i alpha F2 (2.3).
 // F1, F2: singular tables for x1 size M1t >= A.M1 (entry j at j mod M1t), shared by
 // every instance whose x1 size divides into the same table.
-template <typename T>
+template <typename T, bool SPEC>
 __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const double* __restrict__ xq,
                                             const double* __restrict__ wxq, const double2* __restrict__ cs,
                                             const double2* __restrict__ F1, const double2* __restrict__ F2, int M1t,
@@ -198,9 +260,16 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
-    double2 term = mk(0.0, 0.0);
-    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
-    const double2 K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    double2 K;
+    bool special = false;
+    if constexpr (SPEC) special = special_coef(b, J, A.stol);
+    if (special) {
+      K = cscale(khat_direct(b.x, J, A, xq), A.A);
+    } else {
+      double2 term = mk(0.0, 0.0);
+      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+      K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    }
     const size_t ot = (size_t)jtp * M1t + jt_tab;
     const double2 f1 = F1[ot], f2 = F2[ot];
     // L = K - F1 + i alpha F2, times the basis normalisation A2
@@ -209,13 +278,13 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   }
 }
 
-template <typename T>
+template <typename T, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __restrict__ xq,
                                                 const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                 const double2* __restrict__ F1, const double2* __restrict__ F2,
                                                 cplx<T>* __restrict__ out) {
   extern __shared__ double2 sa[];
-  fill2d_body<T>(A, blockIdx.x, xq, wxq, cs, F1, F2, A.M1, out, sa);
+  fill2d_body<T, SPEC>(A, blockIdx.x, xq, wxq, cs, F1, F2, A.M1, out, sa);
 }
 
 // Many 2D instances in one launch: instance i owns blocks [inst[i].blk0, inst[i+1].blk0).
@@ -236,7 +305,7 @@ __device__ __forceinline__ int find_inst(const FillInst* __restrict__ inst, int 
   return lo;
 }
 
-template <typename T>
+template <typename T, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill2d_multi(const FillInst* __restrict__ inst, int n_inst,
                                                       const double* __restrict__ xq, const double* __restrict__ wxq,
                                                       const double2* __restrict__ cs, const double2* __restrict__ F1,
@@ -245,7 +314,7 @@ __global__ __launch_bounds__(256) void k_fill2d_multi(const FillInst* __restrict
   extern __shared__ double2 sa[];
   const int i = find_inst(inst, n_inst, blockIdx.x);
   const FillInst I = inst[i];
-  fill2d_body<T>(I.A, (int)(blockIdx.x - I.blk0), xq, wxq, cs, F1, F2, M1t, base + I.off, sa);
+  fill2d_body<T, SPEC>(I.A, (int)(blockIdx.x - I.blk0), xq, wxq, cs, F1, F2, M1t, base + I.off, sa);
 }
 
 // 2D singular tables (eqs. 2.4, 2.5), k- and alpha-independent (Remark 2.1):
@@ -403,7 +472,7 @@ __global__ void k_sing2d_hess(int M1, int M2, double c_tilde, double A2, double 
 // 2D gradient fill (Section 2.4.1): the two fields
 //   L-hat_1 = i(alpha + j1) K-hat - H-hat_1,  L-hat_2 = i j2 (pi/c~) K-hat - H-hat_2,
 // K-hat of (2.1) as in the fill of G, H-hat_p from the gradient tables.
-template <typename T>
+template <typename T, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill2d_grad(FillArgs A, const double* __restrict__ xq,
                                                      const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                      const double* __restrict__ D, cplx<T>* __restrict__ out) {
@@ -425,9 +494,16 @@ __global__ __launch_bounds__(256) void k_fill2d_grad(FillArgs A, const double* _
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
-    double2 term = mk(0.0, 0.0);
-    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
-    const double2 K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    double2 K;
+    bool special = false;
+    if constexpr (SPEC) special = special_coef(b, J, A.stol);
+    if (special) {
+      K = cscale(khat_direct(b.x, J, A, xq), A.A);
+    } else {
+      double2 term = mk(0.0, 0.0);
+      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+      K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
+    }
     const size_t o = (size_t)jtp * A.M1 + j1p;
     // H-hat_p = i s_p
     const double s1 = k2 * D[o] + D[n + o] - al * D[2 * n + o] - ha2 * D[3 * n + o];
@@ -497,7 +573,7 @@ __global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, d
 // m_11 = -(alpha + j1)^2, m_12 = -(alpha + j1) J, m_22 = -J^2 (J = j2 pi/c~), K-hat of (2.1)
 // for both wavenumbers (two sets of pencil weights in LDS); the difference of the leading
 // terms 1/(|xi|^2 - k^2) is formed exactly as (k1^2 - k2^2)/((|xi|^2 - k1^2)(|xi|^2 - k2^2)).
-template <typename T>
+template <typename T, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* __restrict__ xq,
                                                      const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                      const double* __restrict__ D, cplx<T>* __restrict__ out) {
@@ -524,9 +600,33 @@ __global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* _
     const double J = jt * kPi / A.c_tilde;
     const double d = a * a + J * J;
     const double sg = jt < 0 ? -1.0 : 1.0;
-    double2 dK = mk((k1s - k2s) / ((d - k1s) * (d - k2s)), 0.0);
-    if (use1) dK = cadd(dK, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
-    if (use2) dK = csub(dK, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+    double2 dK;
+    bool s1 = false, s2 = false;
+    if constexpr (SPEC) {
+      s1 = special_coef(b1, J, A.stol);
+      s2 = special_coef(b2, J, A.stol);
+    }
+    if (s1 || s2) {
+      // a special coefficient of either wavenumber: the two K-hat separately
+      double2 K1, K2;
+      if (s1) {
+        K1 = khat_direct(b1.x, J, A, xq);
+      } else {
+        K1 = mk(1.0 / (d - k1s), 0.0);
+        if (use1) K1 = cadd(K1, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
+      }
+      if (s2) {
+        K2 = khat_direct(b2.x, J, A, xq);
+      } else {
+        K2 = mk(1.0 / (d - k2s), 0.0);
+        if (use2) K2 = cadd(K2, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+      }
+      dK = csub(K1, K2);
+    } else {
+      dK = mk((k1s - k2s) / ((d - k1s) * (d - k2s)), 0.0);
+      if (use1) dK = cadd(dK, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
+      if (use2) dK = csub(dK, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+    }
     dK = cscale(dK, A.A);
     const size_t o = (size_t)jtp * A.M1 + j1p;
     const double h11 = C * (D[o] + A.a1 * D[n + o]);
@@ -604,7 +704,7 @@ __global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, int
 }
 
 template <typename T>
-hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse) {
+hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool spec) {
   FillArgs A;
   A.k = k;
   A.a1 = a1;
@@ -617,34 +717,68 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse) {
   A.Q = P.p.quad_q;
   A.hd = P.hd;
   A.fstride = (long)P.ncell;
+  A.stol = P.p.special_tol;
+  A.wXq = P.wXq;
+  A.rq = P.rq;
+  A.wrq = P.wrq;
+  A.eps = P.p.eps;
   const size_t shm = (size_t)TP * A.Q * sizeof(double2);
   auto* out = static_cast<cplx<T>*>(P.grid);
   if (P.dim == 2) {
     A.A = 1.0 / (2.0 * sqrt(kPi * A.c_tilde));
     dim3 grid((P.M1 + TP - 1) / TP, 1);
     A.k2 = P.last_k2;
-    if (P.nf == 2)
-      hipLaunchKernelGGL(k_fill2d_grad<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2, out);
-    else if (P.nf == 3)
-      hipLaunchKernelGGL(k_fill2d_hess<T>, grid, dim3(TP * TL), 2 * shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2,
-                         out);
-    else
-      hipLaunchKernelGGL(k_fill2d<T>, grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2, out);
+    // the special-coefficient path is compiled in only for instances that have one
+    if (P.nf == 2) {
+      if (spec)
+        hipLaunchKernelGGL((k_fill2d_grad<T, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.D2,
+                           out);
+      else
+        hipLaunchKernelGGL((k_fill2d_grad<T, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.D2, out);
+    } else if (P.nf == 3) {
+      if (spec)
+        hipLaunchKernelGGL((k_fill2d_hess<T, true>), grid, dim3(TP * TL), 2 * shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.D2, out);
+      else
+        hipLaunchKernelGGL((k_fill2d_hess<T, false>), grid, dim3(TP * TL), 2 * shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.D2, out);
+    } else {
+      if (spec)
+        hipLaunchKernelGGL((k_fill2d<T, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1, P.F2,
+                           out);
+      else
+        hipLaunchKernelGGL((k_fill2d<T, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.F1,
+                           P.F2, out);
+    }
   } else {
     A.A = 1.0 / sqrt(8.0 * kPi * kPi * A.c_tilde);
     dim3 grid((P.M1 + TP - 1) / TP, P.M2);
     const cplx<T>* tw = nullptr;
     if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
-    if (P.nf == 7)
-      hipLaunchKernelGGL((k_fill3d<T, 7, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab,
-                         out, tw, P.twlog2);
-    else if (fuse)
-      hipLaunchKernelGGL((k_fill3d<T, 1, true>), grid, dim3(TP * TL),
-                         shm + (size_t)TP * (P.Mt + 1) * sizeof(cplx<T>), P.stream, A, P.xq, P.wxq, P.cs, P.htab,
-                         out, tw, P.twlog2);
-    else
-      hipLaunchKernelGGL((k_fill3d<T, 1, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs, P.htab,
-                         out, tw, P.twlog2);
+    const size_t shf = shm + (size_t)TP * (P.Mt + 1) * sizeof(cplx<T>);
+    if (P.nf == 7) {
+      if (spec)
+        hipLaunchKernelGGL((k_fill3d<T, 7, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+      else
+        hipLaunchKernelGGL((k_fill3d<T, 7, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+    } else if (fuse) {
+      if (spec)
+        hipLaunchKernelGGL((k_fill3d<T, 1, true, true>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+      else
+        hipLaunchKernelGGL((k_fill3d<T, 1, true, false>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+    } else {
+      if (spec)
+        hipLaunchKernelGGL((k_fill3d<T, 1, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+      else
+        hipLaunchKernelGGL((k_fill3d<T, 1, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+    }
   }
   return hipGetLastError();
 }
@@ -722,6 +856,12 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff
   I.A.Q = P.p.quad_q;
   I.A.hd = P.hd;
   I.A.fstride = (long)M1 * P.M2;
+  I.A.stol = P.p.special_tol;
+  I.A.wXq = P.wXq;
+  I.A.rq = P.rq;
+  I.A.wrq = P.wrq;
+  I.A.eps = P.p.eps;
+  I.A.k2 = 0.0;
   I.off = off;
   I.foff = foff;
   I.blk0 = blk0;
@@ -729,15 +869,27 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff
 }
 size_t fill_inst_size() { return sizeof(FillInst); }
 
-hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base) {
+hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base, bool spec) {
   const size_t shm = (size_t)TP * P.p.quad_q * sizeof(double2);
   const auto* in = static_cast<const FillInst*>(dinst);
-  if (P.p.prec == QPGF_C128)
-    hipLaunchKernelGGL(k_fill2d_multi<double>, dim3((unsigned)nblocks), dim3(TP * TL), shm, P.stream, in, n_inst,
-                       P.xq, P.wxq, P.cs, P.F1, P.F2, P.M1, static_cast<double2*>(base));
-  else
-    hipLaunchKernelGGL(k_fill2d_multi<float>, dim3((unsigned)nblocks), dim3(TP * TL), shm, P.stream, in, n_inst,
-                       P.xq, P.wxq, P.cs, P.F1, P.F2, P.M1, static_cast<float2*>(base));
+  const dim3 g((unsigned)nblocks), b(TP * TL);
+  if (P.p.prec == QPGF_C128) {
+    auto* o = static_cast<double2*>(base);
+    if (spec)
+      hipLaunchKernelGGL((k_fill2d_multi<double, true>), g, b, shm, P.stream, in, n_inst, P.xq, P.wxq, P.cs, P.F1,
+                         P.F2, P.M1, o);
+    else
+      hipLaunchKernelGGL((k_fill2d_multi<double, false>), g, b, shm, P.stream, in, n_inst, P.xq, P.wxq, P.cs, P.F1,
+                         P.F2, P.M1, o);
+  } else {
+    auto* o = static_cast<float2*>(base);
+    if (spec)
+      hipLaunchKernelGGL((k_fill2d_multi<float, true>), g, b, shm, P.stream, in, n_inst, P.xq, P.wxq, P.cs, P.F1,
+                         P.F2, P.M1, o);
+    else
+      hipLaunchKernelGGL((k_fill2d_multi<float, false>), g, b, shm, P.stream, in, n_inst, P.xq, P.wxq, P.cs, P.F1,
+                         P.F2, P.M1, o);
+  }
   return hipGetLastError();
 }
 
@@ -762,7 +914,9 @@ bool fill_fuses_transverse(const Plan& P) {
 
 hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse) {
   fuse = fuse && fill_fuses_transverse(P);
-  return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2, fuse) : fill_impl<float>(P, k, a1, a2, fuse);
+  const bool spec = P.spec;
+  return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2, fuse, spec)
+                               : fill_impl<float>(P, k, a1, a2, fuse, spec);
 }
 
 hipError_t launch_far(Plan& P, double k, double a1, double a2) {

@@ -118,6 +118,7 @@ struct Plan {
   void* far = nullptr;         // nf * nfar complex
   double* xq = nullptr;        // X' quadrature nodes on [c, (c+c~)/2]
   double* wxq = nullptr;       // weights * X'(node)
+  double* wXq = nullptr;       // weights * X(node) (special coefficients)
   double2* cs = nullptr;       // [Nt+1][Q]: (cos, sin)(j pi/c~ * xq)
   double* rq = nullptr;        // radial quadrature nodes on [eps, 2 eps]
   double* wrq = nullptr;       // weights
@@ -135,6 +136,7 @@ struct Plan {
   double hd = 0.05;
   double last_k = 0, last_a1 = 0, last_a2 = 0;
   double last_k2 = 0;          // second wavenumber (differences of second derivatives)
+  bool spec = false;           // the prepared instance has a special coefficient (fills take that path)
   bool prepared = false;
 
   // target binning scratch (3D), grown on demand
@@ -216,7 +218,7 @@ int fft_tile(const Plan& P, int n, bool rows, long nbatch);
 // batched 2D (one launch per stage for many instances)
 void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long blk0, void* dst);
 size_t fill_inst_size();
-hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base);
+hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base, bool spec);
 hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base);
 void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long t0, long t1, long blk0,
                     void* dst);

@@ -260,10 +260,11 @@ def test_edge_targets_and_status_codes():
     with pytest.raises(qpgf.QpgfError) as e:
         P(1.3, 0.3, 0.0, dev(x))
     assert e.value.status == 2
-    # special coefficient: beta_0 = pi (j2 = 1, c~ = 1) for k^2 = alpha^2 + pi^2
-    with pytest.raises(qpgf.QpgfError) as e:
-        P(math.sqrt(0.3 ** 2 + math.pi ** 2), 0.3, 0.0, dev(x))
-    assert e.value.status == 3
+    # special coefficient beta_0 = pi (j2 = 1, c~ = 1) for k^2 = alpha^2 + pi^2: evaluated, not refused
+    ks = math.sqrt(0.3 ** 2 + math.pi ** 2)
+    gs = P(ks, 0.3, 0.0, dev(x[[2, 3, 4, 5, 8]])).cpu().numpy()
+    os_ = method.eval_g2d(ks, 0.3, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    assert parity(gs, os_) <= 1e-10
     # wrong entry point for the plan kind
     P3 = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, 32, 32, 32)
     with pytest.raises(qpgf.QpgfError) as e:
