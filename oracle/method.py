@@ -342,14 +342,20 @@ def lhat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORA
             - fhat_3d(k, a1, a2, N1, N2, N3, c_tilde, eps, q))
 
 
+# The second-derivative fields the method carries (Algorithm 4.1): 11, 22, 12, 13, 23.  GG_33
+# follows from the trace, GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the
+# Helmholtz equation, off the lattice), which spares a field and the x3 truncation error of a
+# direct 33 field (whose coefficients carry (j3 pi / c~)^2 against the cut-off X in x3).
+FIELD_PAIRS = ((0, 0), (1, 1), (0, 1), (0, 2), (1, 2))
+
+
 def maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde=co.C_TILDE):
-    """-c^p c^q for the pairs 11,22,33,12,13,23 (Section 4), each [2N1,2N2,2N3]."""
+    """-c^p c^q for the field pairs 11, 22, 12, 13, 23 (Section 4), each [2N1,2N2,2N3]."""
     c1 = (a1 + np.arange(-N1, N1, dtype=np.float64))[:, None, None]
     c2 = (a2 + np.arange(-N2, N2, dtype=np.float64))[None, :, None]
     c3 = (np.arange(-N3, N3, dtype=np.float64) * math.pi / c_tilde)[None, None, :]
     cc = (c1, c2, c3)
-    from .truth import MAXWELL_PAIRS
-    return [-(cc[p] * cc[q]) for p, q in MAXWELL_PAIRS]
+    return [-(cc[p] * cc[q]) for p, q in FIELD_PAIRS]
 
 
 def grid_3d(Lhat, c_tilde=co.C_TILDE):
@@ -402,8 +408,7 @@ def _psi_derivs(k, r, eps):
 
 def prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
                eps=co.EPS, q=ORACLE_Q):
-    """Algorithm 3.1 / 4.1 step 1: the near grids (1 or 7 fields) and the far-slab grids."""
-    from .truth import MAXWELL_PAIRS
+    """Algorithm 3.1 / 4.1 step 1: the near grids (1 or 6 fields) and the far-slab grids."""
     L = lhat_3d(k, a1, a2, N1, N2, N3, c, c_tilde, eps, q)
     fields = [L] + ([m * L for m in maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde)] if maxwell else [])
     grids = [grid_3d(f, c_tilde) for f in fields]
@@ -412,7 +417,7 @@ def prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_til
     if maxwell:
         def mk(p, qq):
             return lambda xi1, xi2, b: -((xi1, xi2, b)[p] * (xi1, xi2, b)[qq])
-        mults += [mk(p, qq) for p, qq in MAXWELL_PAIRS]
+        mults += [mk(p, qq) for p, qq in FIELD_PAIRS]
     fgrids = [far_grid_3d(k, a1, a2, N1, N2, z, m) for m in mults]
     return dict(k=k, a1=a1, a2=a2, N=(N1, N2, N3), far_h=far_h, far_S=far_S, maxwell=maxwell, c=c,
                 c_tilde=c_tilde, eps=eps, grids=grids, fgrids=fgrids)
@@ -423,7 +428,6 @@ def evaluate_3d(st, x):
 
     Returns G_d [T] or the Maxwell components [T,6] (11, 22, 33, 12, 13, 23).
     """
-    from .truth import MAXWELL_PAIRS
     k, a1, a2, c, c_tilde, eps = st["k"], st["a1"], st["a2"], st["c"], st["c_tilde"], st["eps"]
     N1, N2, N3 = st["N"]
     far_h, far_S, maxwell = st["far_h"], st["far_S"], st["maxwell"]
@@ -449,7 +453,7 @@ def evaluate_3d(st, x):
         psi, d1, d2 = _psi_derivs(k, r, eps)
         lat = np.exp(2j * math.pi * (a1 * n1[near] + a2 * n2[near]))
         vals[near, 0] = phase[near] * Ls[0] + lat * psi
-        for f, (p, qq) in enumerate(MAXWELL_PAIRS[: nfield - 1]):
+        for f, (p, qq) in enumerate(FIELD_PAIRS[: nfield - 1]):
             tp, tq = tt[:, p], tt[:, qq]
             hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
             vals[near, f + 1] = phase[near] * Ls[f + 1] + lat * hess
@@ -462,15 +466,15 @@ def evaluate_3d(st, x):
         sg = np.sign(x3[far])
         for f in range(nfield):
             v = phase[far] * Ls[f]
-            if f >= 1 and 2 in MAXWELL_PAIRS[f - 1] and MAXWELL_PAIRS[f - 1] != (2, 2):
+            if f >= 1 and 2 in FIELD_PAIRS[f - 1]:
                 v = v * sg                     # d/dx3 of e^{i beta |x3|} brings sgn(x3)
             v[bad] = np.nan
             vals[far, f] = v
     if not maxwell:
         return vals[:, 0]
-    out = vals[:, 1:] / k ** 2
-    out[:, :3] += vals[:, :1]
-    return out
+    G, d = vals[:, 0], vals[:, 1:] / k ** 2          # d: k^-2 d_p d_q G_d for 11, 22, 12, 13, 23
+    g11, g22 = G + d[:, 0], G + d[:, 1]
+    return np.stack([g11, g22, 2 * G - g11 - g22, d[:, 2], d[:, 3], d[:, 4]], axis=1)
 
 
 def smooth_3d(st, x):

@@ -144,6 +144,15 @@ def _cquad(f, a, b):
     return complex(re, im)
 
 
+def test_maxwell_trace_identity():
+    # GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice (the Helmholtz
+    # equation): the identity the method uses for GG_33, on the lattice sums themselves.
+    x = np.array([[0.9, -0.7, 0.3], [2.0, 1.0, 0.8], [0.5, 0.4, -0.7], [4.0, 5.5, 0.05]])
+    gg = truth.maxwell3d(K3, A31, A32, x)
+    g = truth.gd3d(K3, A31, A32, x)
+    assert np.max(np.abs(gg[:, 0] + gg[:, 1] + gg[:, 2] - 2 * g) / np.abs(g)) < 1e-11
+
+
 def test_xprime_integrals_against_adaptive_quadrature():
     b = np.array([1.3, 0.0 + 4.0j, 3.7])
     J = np.array([0.0, math.pi, 7 * math.pi])
