@@ -31,7 +31,11 @@
  *  - Targets are float64, row-major [T][dim].  Outputs are interleaved complex
  *    (re, im) in the caller's target order: complex128 when the plan precision is
  *    QPGF_C128, complex64 when QPGF_C64.  Maxwell outputs are [T][6] complex in
- *    the order 11, 22, 33, 12, 13, 23.
+ *    the order 11, 22, 33, 12, 13, 23; the plan carries the fields of G_d and of its
+ *    second derivatives 11, 22, 12, 13, 23 (Algorithm 4.1), and GG_33 follows from the
+ *    trace, GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz
+ *    equation off the lattice), one field fewer than the direct 33 field and free of
+ *    its x3 truncation error.
  *  - Per-target flags (optional, may be NULL), uint8 [T]:
  *      bit 0  the target lies within params.lattice_rmin of a lattice point
  *             (output NaN); with lattice_rmin = 0 only an exact hit is flagged,
@@ -114,7 +118,8 @@ typedef struct {
   int far_slices;          /* S_f */
   double far_h;
   double c, c_tilde, eps;
-  int n_fields;            /* 1, or 7 for Maxwell (L and the six L^{pq}) */
+  int n_fields;            /* 1; 6 for Maxwell (L and L^{pq}, pq = 11 22 12 13 23);
+                              2 for G2D_GRAD; 3 for G2D_HESS_DIFF */
   size_t grid_bytes;       /* bytes of one near-grid field */
   size_t far_grid_bytes;   /* bytes of one far-slab field */
 } qpgf_plan_info;

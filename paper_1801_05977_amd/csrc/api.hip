@@ -335,7 +335,7 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   Plan& P = plan->P;
   P.p = *p;
   P.dim = kind_is_2d(p->kind) ? 2 : 3;
-  P.nf = (p->kind == QPGF_KIND_MAXWELL3D)       ? 7
+  P.nf = (p->kind == QPGF_KIND_MAXWELL3D)       ? kMxF
          : (p->kind == QPGF_KIND_G2D_HESS_DIFF) ? 3
          : (p->kind == QPGF_KIND_G2D_GRAD)      ? 2
                                                 : 1;

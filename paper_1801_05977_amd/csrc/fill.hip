@@ -164,7 +164,7 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
   return acc;
 }
 
-// 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF == 7):
+// 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF == kMxF):
 // L-hat_dj = A3 [ I-terms + H(|xi|) / (|xi|^2 - k^2) ], i.e. K-hat_dj of (3.3)
 // minus F-hat_j of (3.5) with the common 1/(|xi|^2-k^2) cancelled exactly.
 //
@@ -216,12 +216,12 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
     }
     const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
     store_c<T>(out, o, L);
-    if (NF == 7) {
-      // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~)
+    if (NF == kMxF) {
+      // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~), pq = 11 22 12 13 23
       const double cc[3] = {xi1, xi2, J};
-      const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+      const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
 #pragma unroll
-      for (int f = 0; f < 6; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+      for (int f = 0; f < 5; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
     }
   }
   if constexpr (FUSE) {
@@ -557,11 +557,11 @@ __global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, d
   const double z = z0 + s * hf;
   const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
   store_c<T>(out, idx, v);
-  if (NF == 7) {
+  if (NF == kMxF) {
     const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
-    const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+    const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < 5; ++f) {
       double2 m = cmul(cc[P[f]], cc[Qp[f]]);
       store_c<T>(out, (f + 1) * fstride + idx, cmul(v, mk(-m.x, -m.y)));
     }
@@ -757,12 +757,12 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
     const cplx<T>* tw = nullptr;
     if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
     const size_t shf = shm + (size_t)TP * (P.Mt + 1) * sizeof(cplx<T>);
-    if (P.nf == 7) {
+    if (P.nf == kMxF) {
       if (spec)
-        hipLaunchKernelGGL((k_fill3d<T, 7, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+        hipLaunchKernelGGL((k_fill3d<T, kMxF, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
                            P.htab, out, tw, P.twlog2);
       else
-        hipLaunchKernelGGL((k_fill3d<T, 7, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+        hipLaunchKernelGGL((k_fill3d<T, kMxF, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
                            P.htab, out, tw, P.twlog2);
     } else if (fuse) {
       if (spec)
@@ -799,8 +799,8 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
       hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
   } else {
     long n = (long)P.M1 * P.M2 * P.S;
-    if (P.nf == 7)
-      hipLaunchKernelGGL((k_far3d<T, 7>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
+    if (P.nf == kMxF)
+      hipLaunchKernelGGL((k_far3d<T, kMxF>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
                          z0, hf, (long)P.nfar, out);
     else
       hipLaunchKernelGGL((k_far3d<T, 1>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,

@@ -105,7 +105,7 @@ struct GlobalFetch {
 // (Algorithm 3.1 / 4.1 step 2: cell reduction, branch, base nodes and the three
 // 4-point weight sets), and the finish from the sums to the result.  The
 // single-function form stays for the other kernels, where it compiles to far
-// fewer registers with seven fields.
+// fewer registers with six fields.
 template <typename T>
 struct Stencil3 {
   double t1, t2, n1, n2;
@@ -181,11 +181,11 @@ __device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, d
   double2 G[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
-  if (!is_near && NF == 7) {
-    // d/dx3 of e^{i beta |x3|} carries sgn(x3): components 13 and 23
+  if (!is_near && NF == kMxF) {
+    // d/dx3 of e^{i beta |x3|} carries sgn(x3): fields 13 and 23
     if (x3 < 0) {
+      G[4] = cscale(G[4], -1.0);
       G[5] = cscale(G[5], -1.0);
-      G[6] = cscale(G[6], -1.0);
     }
   }
   if (is_near) {
@@ -206,7 +206,7 @@ __device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, d
       const double2 lat = mk(lc, ls);
       const double Y = cut_Y(r, A.eps);
       G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
-      if (NF == 7) {
+      if (NF == kMxF) {
         // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
         const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
         const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
@@ -215,9 +215,9 @@ __device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, d
         const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
         const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
         const double t[3] = {t1, t2, x3};
-        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 0; f < 5; ++f) {
           const double tp = t[P[f]], tq = t[Qp[f]];
           const double a = tp * tq / (r * r);
           const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
@@ -229,14 +229,14 @@ __device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, d
   if (NF == 1) {
     res[0] = G[0];
   } else {
-    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1)
+    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1); fields 11 22 12 13 23, and GG_33 from
+    // the trace: tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz equation, off the lattice)
     const double ik2 = 1.0 / (A.k * A.k);
+    res[0] = cadd(G[0], cscale(G[1], ik2));
+    res[1] = cadd(G[0], cscale(G[2], ik2));
+    res[2] = csub(cscale(G[0], 2.0), cadd(res[0], res[1]));
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      double2 v = cscale(G[f + 1], ik2);
-      if (f < 3) v = cadd(v, G[0]);
-      res[f] = v;
-    }
+    for (int f = 3; f < 6; ++f) res[f] = cscale(G[f], ik2);
   }
 }
 
@@ -297,11 +297,11 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
   double2 G[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
-  if (!is_near && NF == 7) {
-    // d/dx3 of e^{i beta |x3|} carries sgn(x3): components 13 and 23
+  if (!is_near && NF == kMxF) {
+    // d/dx3 of e^{i beta |x3|} carries sgn(x3): fields 13 and 23
     if (x3 < 0) {
+      G[4] = cscale(G[4], -1.0);
       G[5] = cscale(G[5], -1.0);
-      G[6] = cscale(G[6], -1.0);
     }
   }
   if (is_near) {
@@ -322,7 +322,7 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
       const double2 lat = mk(lc, ls);
       const double Y = cut_Y(r, A.eps);
       G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
-      if (NF == 7) {
+      if (NF == kMxF) {
         // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
         const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
         const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
@@ -331,9 +331,9 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
         const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
         const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
         const double t[3] = {t1, t2, x3};
-        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 0; f < 5; ++f) {
           const double tp = t[P[f]], tq = t[Qp[f]];
           const double a = tp * tq / (r * r);
           const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
@@ -345,14 +345,14 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
   if (NF == 1) {
     res[0] = G[0];
   } else {
-    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1)
+    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1); fields 11 22 12 13 23, and GG_33 from
+    // the trace: tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz equation, off the lattice)
     const double ik2 = 1.0 / (A.k * A.k);
+    res[0] = cadd(G[0], cscale(G[1], ik2));
+    res[1] = cadd(G[0], cscale(G[2], ik2));
+    res[2] = csub(cscale(G[0], 2.0), cadd(res[0], res[1]));
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      double2 v = cscale(G[f + 1], ik2);
-      if (f < 3) v = cadd(v, G[0]);
-      res[f] = v;
-    }
+    for (int f = 3; f < 6; ++f) res[f] = cscale(G[f], ik2);
   }
 }
 
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, cons
 // footprint of field f is staged in LDS, every target of the tile takes its
 // stencil sum of field f, then the next field replaces it.  Used when the tiles
 // hold few targets (fewer than about two blocks' worth), so a footprint of all
-// seven fields would not fit LDS at a useful tile size.  Up to 256 targets per
+// six fields would not fit LDS at a useful tile size.  Up to 256 targets per
 // pass; a tile with more runs several passes, staging again.
 template <typename T, int TB1, int TB2, int TB3>
 __global__ __launch_bounds__(256) void k_gather3d_fields(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_gather3d_fields(GArgs A, TileArgs B, co
                                                          cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
                                                          uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
   constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
-  constexpr int NF = 7, NO = 6;
+  constexpr int NF = kMxF, NO = 6;
   __shared__ cplx<T> lds[FSZ];
   const int key = B.nkeys - 1 - (int)blockIdx.x;
   const uint32_t cnt = hist[key];
@@ -1218,8 +1218,8 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   }
   if (P.bin_min_targets < 0 || T_ < P.bin_min_targets) {
     KernelTimer t(P, QPGF_T_GATHER);
-    if (P.nf == 7)
-      hipLaunchKernelGGL((k_gather3d<T, 7>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    if (P.nf == kMxF)
+      hipLaunchKernelGGL((k_gather3d<T, kMxF>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     else
       hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     return hipGetLastError();
@@ -1270,7 +1270,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     big = P.bt_big;
     fields = P.bt_fields;
   } else {
-    if (P.nf == 7) {
+    if (P.nf == kMxF) {
       // few targets per tile: 16 x 16 x 8 tiles staged one field at a time
       set_tiles(4, 4, 3);
       fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nkeys;
@@ -1349,11 +1349,11 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     hipLaunchKernelGGL((k_gather3d_fields<T, 4, 4, 3>), tg, dim3(256), 0, P.stream, A, Tl, g, f, rec, P.bin_hist,
                        P.bin_offs, o, flags, P.bin_ovf, P.bin_novf);
   } else if constexpr (sizeof(T) == 8) {
-    if (P.nf == 7) QPGF_TILED(7, 3, 2, 2, 256);
+    if (P.nf == kMxF) QPGF_TILED(kMxF, 3, 2, 2, 256);
     else if (big) QPGF_TILED(1, 5, 4, 3, 512);
     else QPGF_TILED(1, 4, 4, 3, 256);
   } else {
-    if (P.nf == 7) QPGF_TILED(7, 3, 3, 2, 256);
+    if (P.nf == kMxF) QPGF_TILED(kMxF, 3, 3, 2, 256);
     else if (big) QPGF_TILED(1, 5, 5, 3, 1024);
     else QPGF_TILED(1, 4, 4, 3, 256);
   }
@@ -1362,8 +1362,8 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   if (e != hipSuccess) return e;
   }
   KernelTimer t(P, QPGF_T_OVERFLOW);
-  if (P.nf == 7)
-    hipLaunchKernelGGL((k_gather3d_overflow<T, 7>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
+  if (P.nf == kMxF)
+    hipLaunchKernelGGL((k_gather3d_overflow<T, kMxF>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
                        P.bin_novf, o, flags);
   else
     hipLaunchKernelGGL((k_gather3d_overflow<T, 1>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,

@@ -16,6 +16,10 @@ namespace qpgf {
 // ---------------------------------------------------------------------------
 // complex helpers (FP64 work is done in double2; bulk storage in T2)
 // ---------------------------------------------------------------------------
+// Maxwell fields: L_d and its second-derivative fields 11, 22, 12, 13, 23 (the 33 entry of the
+// tensor follows from the trace, tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice).
+constexpr int kMxF = 6;
+
 template <typename T> struct C2;
 template <> struct C2<double> { using type = double2; };
 template <> struct C2<float> { using type = float2; };
@@ -104,7 +108,7 @@ constexpr int kMaxLog2 = 12;   // m <= 4096
 
 struct Plan {
   qpgf_params p;
-  int dim = 2, nf = 1;         // nf: number of fields (7 for Maxwell)
+  int dim = 2, nf = 1;         // nf: number of fields (kMxF for Maxwell)
   int M1 = 0, M2 = 0, M3 = 1;  // 2D: M3 = 1, M2 = transverse
   int Mt = 0;                  // transverse size (M2 in 2D, M3 in 3D)
   int S = 0;                   // far-slab slices
