@@ -26,8 +26,11 @@ Two oracles live here:
 * ``hess2d`` -- the differences of second derivatives of the 2D G for two
   wavenumbers (Section 2.4.2), the same way.
 
+* ``highorder2d`` -- the 2D G with the terms of degree 2 and 3 of the
+  logarithmic singularity's Taylor factor removed as well (Remark 5.3).
+
 ``cutoffs`` holds the smooth cut-off functions X and Y_eps (Section 6 states
 only that they are C^8; the reading used is documented there).
 """
 
-from . import cutoffs, truth, method, grad2d, hess2d  # noqa: F401
+from . import cutoffs, truth, method, grad2d, hess2d, highorder2d  # noqa: F401
