@@ -132,6 +132,8 @@ qpgf_status validate(const qpgf_params* p) {
   if (!(p->far_h > 0.0) || !(p->far_zmax >= p->c)) return fail(QPGF_E_ARG, "need far_h > 0 and far_zmax >= c");
   if (!(p->wood_tol >= 0.0) || !(p->special_tol >= 0.0) || !(p->lattice_rmin >= 0.0))
     return fail(QPGF_E_ARG, "tolerances must be >= 0");
+  if (!(p->special_tol < 0.25 * M_PI / p->c_tilde))
+    return fail(QPGF_E_ARG, "special_tol must be below pi / (4 c_tilde)");
   return QPGF_OK;
 }
 

@@ -94,8 +94,21 @@ __device__ __forceinline__ double2 xprime_term(const double2* __restrict__ ap, c
 // close to it); the coefficient is taken from the integral that defines it,
 //   K-hat_j / A = (i / (2 beta)) [I0(beta - J) + I0(beta + J)],   I0(g) = int_0^{c~} e^{igx} X(x) dx,
 // the paper's special-case formula (its g = 0 term is int X) for every g near the special point.
-__device__ __forceinline__ bool special_coef(double2 b, double J, double stol) {
-  return b.y == 0.0 && fabs(b.x - fabs(J)) < stol;
+// The fills compute every coefficient by the integrated form in their main loop and then
+// overwrite a pencil's (at most two) special ones, so the loop is the same as without them.
+
+// The FFT-order transverse indices of the (at most two) special coefficients of a pencil:
+// jt = +-js with |beta - js pi / c~| < stol for a propagating beta; -1 where there is none.
+// special_tol < pi / (4 c~) (checked at plan creation), so js is unique.
+__device__ __forceinline__ void special_jts(double2 b, const FillArgs& A, int js_idx[2]) {
+  js_idx[0] = js_idx[1] = -1;
+  if (b.y != 0.0) return;
+  const double step = kPi / A.c_tilde;
+  const int js = (int)rint(b.x / step);
+  if (js > A.Mt / 2 || !(fabs(b.x - js * step) < A.stol)) return;
+  js_idx[0] = js & (A.Mt - 1);
+  js_idx[1] = (-js) & (A.Mt - 1);
+  if (js_idx[1] == js_idx[0]) js_idx[1] = -1;
 }
 // (e^{i th} - 1) / (i th), without cancellation for small th
 __device__ __forceinline__ double2 e1i(double th) {
@@ -194,34 +207,41 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   if (!FUSE && j1p >= A.M1) return;
   const double2* ap = sa + ip;
   const double k2 = A.k * A.k;
+  // coefficient jt' of this pencil: into the LDS pencil (FUSE) or the near grid (and the Maxwell fields)
+  auto put = [&](int jtp, double J, double2 L) {
+    if constexpr (FUSE) {
+      store_c<T>(pen, (size_t)ip * pitch + jtp, L);
+    } else {
+      const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
+      store_c<T>(out, o, L);
+      if (NF == kMxF) {
+        // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~), pq = 11 22 12 13 23
+        const double cc[3] = {xi1, xi2, J};
+        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
+#pragma unroll
+        for (int f = 0; f < 5; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+      }
+    }
+  };
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
     const double rho2 = rp2 + J * J;
-    double2 L;
-    bool special = false;
-    if constexpr (SPEC) special = special_coef(b, J, A.stol);
-    if (special) {
-      // L-hat = K-hat - F-hat, each from its defining integral
-      L = cscale(csub(khat_direct(b.x, J, A, xq), fhat_direct(A.k, sqrt(rho2), A)), A.A * A.A);
-    } else {
-      double2 term = mk(0.0, 0.0);
-      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
-      const double2 H = h_interp(htab, A.hd, sqrt(rho2));
-      L = cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A);
-    }
-    if constexpr (FUSE) {
-      store_c<T>(pen, (size_t)ip * pitch + jtp, L);
-      continue;
-    }
-    const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
-    store_c<T>(out, o, L);
-    if (NF == kMxF) {
-      // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~), pq = 11 22 12 13 23
-      const double cc[3] = {xi1, xi2, J};
-      const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
-#pragma unroll
-      for (int f = 0; f < 5; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+    const double2 H = h_interp(htab, A.hd, sqrt(rho2));
+    put(jtp, J, cscale(cadd(term, cscale(H, 1.0 / (rho2 - k2))), A.A * A.A));
+  }
+  if constexpr (SPEC) {
+    // the special coefficients of this pencil, recomputed over what the loop wrote:
+    // L-hat = K-hat - F-hat, each from its defining integral
+    int js[2];
+    special_jts(b, A, js);
+    for (int s = 0; s < 2; ++s) {
+      if (js[s] < 0 || j1p >= A.M1 || js[s] % TL != lane) continue;
+      const double J = centered(js[s], A.Mt) * kPi / A.c_tilde;
+      const double rho = sqrt(rp2 + J * J);
+      put(js[s], J, cscale(csub(khat_direct(b.x, J, A, xq), fhat_direct(A.k, rho, A)), A.A * A.A));
     }
   }
   if constexpr (FUSE) {
@@ -257,24 +277,28 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
   const int jt_tab = j1 & (M1t - 1);
-  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
-    const int jt = centered(jtp, A.Mt);
-    const double J = jt * kPi / A.c_tilde;
-    double2 K;
-    bool special = false;
-    if constexpr (SPEC) special = special_coef(b, J, A.stol);
-    if (special) {
-      K = cscale(khat_direct(b.x, J, A, xq), A.A);
-    } else {
-      double2 term = mk(0.0, 0.0);
-      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
-      K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
-    }
+  auto put = [&](int jtp, double2 K) {
     const size_t ot = (size_t)jtp * M1t + jt_tab;
     const double2 f1 = F1[ot], f2 = F2[ot];
     // L = K - F1 + i alpha F2, times the basis normalisation A2
     const double2 L = cscale(mk(K.x - f1.x - A.a1 * f2.y, K.y - f1.y + A.a1 * f2.x), A.A);
     store_c<T>(out, (size_t)jtp * A.M1 + j1p, L);
+  };
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+    put(jtp, cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A));
+  }
+  if constexpr (SPEC) {
+    // the special coefficients of this pencil, recomputed from their defining integral
+    int js[2];
+    special_jts(b, A, js);
+    for (int s = 0; s < 2; ++s) {
+      if (js[s] < 0 || js[s] % TL != lane) continue;
+      put(js[s], cscale(khat_direct(b.x, centered(js[s], A.Mt) * kPi / A.c_tilde, A, xq), A.A));
+    }
   }
 }
 
@@ -491,19 +515,7 @@ __global__ __launch_bounds__(256) void k_fill2d_grad(FillArgs A, const double* _
   const double lead0 = a * a - A.k * A.k;
   const size_t n = (size_t)A.M1 * A.Mt;
   const double k2 = A.k * A.k, al = A.a1, ha2 = 0.5 * A.a1 * A.a1;
-  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
-    const int jt = centered(jtp, A.Mt);
-    const double J = jt * kPi / A.c_tilde;
-    double2 K;
-    bool special = false;
-    if constexpr (SPEC) special = special_coef(b, J, A.stol);
-    if (special) {
-      K = cscale(khat_direct(b.x, J, A, xq), A.A);
-    } else {
-      double2 term = mk(0.0, 0.0);
-      if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
-      K = cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A);
-    }
+  auto put = [&](int jtp, double J, double2 K) {
     const size_t o = (size_t)jtp * A.M1 + j1p;
     // H-hat_p = i s_p
     const double s1 = k2 * D[o] + D[n + o] - al * D[2 * n + o] - ha2 * D[3 * n + o];
@@ -511,6 +523,22 @@ __global__ __launch_bounds__(256) void k_fill2d_grad(FillArgs A, const double* _
     // times the basis normalisation A2 (the grid sum)
     store_c<T>(out, o, cscale(mk(-a * K.y, a * K.x - s1), A.A));
     store_c<T>(out + A.fstride, o, cscale(mk(-J * K.y, J * K.x - s2), A.A));
+  };
+  for (int jtp = lane; jtp < A.Mt; jtp += TL) {
+    const int jt = centered(jtp, A.Mt);
+    const double J = jt * kPi / A.c_tilde;
+    double2 term = mk(0.0, 0.0);
+    if (use_I) term = xprime_term(ap, cs + (size_t)abs(jt) * A.Q, A.Q, jt < 0 ? -1.0 : 1.0, J, b);
+    put(jtp, J, cscale(cadd(term, mk(1.0 / (lead0 + J * J), 0.0)), A.A));
+  }
+  if constexpr (SPEC) {
+    int js[2];
+    special_jts(b, A, js);
+    for (int s = 0; s < 2; ++s) {
+      if (js[s] < 0 || js[s] % TL != lane) continue;
+      const double J = centered(js[s], A.Mt) * kPi / A.c_tilde;
+      put(js[s], J, cscale(khat_direct(b.x, J, A, xq), A.A));
+    }
   }
 }
 
@@ -595,19 +623,40 @@ __global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* _
   const size_t n = (size_t)A.M1 * A.Mt;
   const double k1s = A.k * A.k, k2s = A.k2 * A.k2;
   const double C = (k1s - k2s) / (2.0 * kPi);
+  auto put = [&](int jtp, double J, double2 dK) {
+    dK = cscale(dK, A.A);
+    const size_t o = (size_t)jtp * A.M1 + j1p;
+    const double h11 = C * (D[o] + A.a1 * D[n + o]);
+    const double h12 = C * (D[2 * n + o] + A.a1 * D[3 * n + o]);
+    const double h22 = C * (D[4 * n + o] + A.a1 * D[5 * n + o]);
+    store_c<T>(out, o, cscale(mk(-a * a * dK.x - h11, -a * a * dK.y), A.A));
+    store_c<T>(out + A.fstride, o, cscale(mk(-a * J * dK.x - h12, -a * J * dK.y), A.A));
+    store_c<T>(out + 2 * A.fstride, o, cscale(mk(-J * J * dK.x - h22, -J * J * dK.y), A.A));
+  };
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
     const int jt = centered(jtp, A.Mt);
     const double J = jt * kPi / A.c_tilde;
     const double d = a * a + J * J;
     const double sg = jt < 0 ? -1.0 : 1.0;
-    double2 dK;
-    bool s1 = false, s2 = false;
-    if constexpr (SPEC) {
-      s1 = special_coef(b1, J, A.stol);
-      s2 = special_coef(b2, J, A.stol);
-    }
-    if (s1 || s2) {
-      // a special coefficient of either wavenumber: the two K-hat separately
+    double2 dK = mk((k1s - k2s) / ((d - k1s) * (d - k2s)), 0.0);
+    if (use1) dK = cadd(dK, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
+    if (use2) dK = csub(dK, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+    put(jtp, J, dK);
+  }
+  if constexpr (SPEC) {
+    // a special coefficient of either wavenumber: the two K-hat separately, the special
+    // one(s) from the defining integral
+    int js[4];
+    special_jts(b1, A, js);
+    special_jts(b2, A, js + 2);
+    for (int s = 0; s < 4; ++s) {
+      const int jtp = js[s];
+      if (jtp < 0 || jtp % TL != lane || (s >= 2 && (jtp == js[0] || jtp == js[1]))) continue;
+      const int jt = centered(jtp, A.Mt);
+      const double J = jt * kPi / A.c_tilde;
+      const double d = a * a + J * J;
+      const double sg = jt < 0 ? -1.0 : 1.0;
+      const bool s1 = jtp == js[0] || jtp == js[1], s2 = jtp == js[2] || jtp == js[3];
       double2 K1, K2;
       if (s1) {
         K1 = khat_direct(b1.x, J, A, xq);
@@ -621,20 +670,8 @@ __global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* _
         K2 = mk(1.0 / (d - k2s), 0.0);
         if (use2) K2 = cadd(K2, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
       }
-      dK = csub(K1, K2);
-    } else {
-      dK = mk((k1s - k2s) / ((d - k1s) * (d - k2s)), 0.0);
-      if (use1) dK = cadd(dK, xprime_term(sa + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b1));
-      if (use2) dK = csub(dK, xprime_term(sa2 + ip, cs + (size_t)abs(jt) * A.Q, A.Q, sg, J, b2));
+      put(jtp, J, csub(K1, K2));
     }
-    dK = cscale(dK, A.A);
-    const size_t o = (size_t)jtp * A.M1 + j1p;
-    const double h11 = C * (D[o] + A.a1 * D[n + o]);
-    const double h12 = C * (D[2 * n + o] + A.a1 * D[3 * n + o]);
-    const double h22 = C * (D[4 * n + o] + A.a1 * D[5 * n + o]);
-    store_c<T>(out, o, cscale(mk(-a * a * dK.x - h11, -a * a * dK.y), A.A));
-    store_c<T>(out + A.fstride, o, cscale(mk(-a * J * dK.x - h12, -a * J * dK.y), A.A));
-    store_c<T>(out + 2 * A.fstride, o, cscale(mk(-J * J * dK.x - h22, -J * J * dK.y), A.A));
   }
 }
 
