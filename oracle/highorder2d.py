@@ -38,6 +38,16 @@ plane-wave expansion, a radial g(r) times cos(n theta) has the coefficient
 
 so four radial integrals serve every (k, alpha):  T03 = int r^3 ln r Y J0,  T23 = int
 r^3 ln r Y J2,  T14 = int r^4 ln r Y J1,  T34 = int r^4 ln r Y J3 (dr over [0, 2 eps]).
+
+The cut-off ring (``ring=True``).  L = K - f Y_eps is smooth, but across eps < r < 2 eps it
+carries the steep transition of Y_eps times the logarithm, and the 16-point stencil's error
+there is far larger than anywhere else (Remark 5.6 traces the accuracy to the smoothness of
+the cut-offs).  K itself is smooth in the ring.  So for a near target with eps < r < 2 eps +
+2 sqrt(2) h, h = max(h1, h2), the stencil interpolates K = L + f Y at its nodes instead of L,
+and nothing is added back: G = e^{i alpha x1} sum_ab w_a w_b (L + f Y)(node_ab).  Beyond
+2 eps + 2 sqrt(2) h every node has Y = 0 and both forms coincide; inside r <= eps the paper's
+form is kept (there K is close to its singularity, L is smooth).  A node's position is its
+offset from the lattice point, (p1 h1, p2 h2) with the stencil's own base indices.
 """
 
 import math
@@ -111,9 +121,16 @@ def lhat_ho(k, alpha, N1, N2, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=O
     return lhat_2d(k, alpha, N1, N2, c, c_tilde, eps, q) - ehat(k, alpha, N1, N2, order, c_tilde, eps, q)
 
 
+def ring_zone(t, z, h1, h2, eps=co.EPS):
+    """Near targets whose stencil interpolates K (``ring=True``): eps < r < 2 eps + 2 sqrt(2) max(h1, h2)."""
+    r = np.sqrt(t * t + z * z)
+    return (r > eps) & (r < 2 * eps + 2 * math.sqrt(2.0) * max(h1, h2))
+
+
 def eval_g2d_ho(k, alpha, x, N1, N2, far_h, far_S, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
-                q=ORACLE_Q):
-    """G at targets x[T,2] with f^(m) removed (NaN beyond the far slab); order 1 is Algorithm 2.1."""
+                q=ORACLE_Q, ring=False):
+    """G at targets x[T,2] with f^(m) removed (NaN beyond the far slab); order 1 is Algorithm 2.1.
+    ``ring``: K interpolated in the cut-off ring (see above)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2 = 2 * N1, 2 * N2
     h1, h2 = math.pi / N1, c_tilde / N2
@@ -125,8 +142,20 @@ def eval_g2d_ho(k, alpha, x, N1, N2, far_h, far_S, order, c=co.C, c_tilde=co.C_T
         z = x[near, 1]
         i1, w1 = _stencil((t + math.pi) / h1, M1)
         i2, w2 = _stencil((z + c_tilde) / h2, M2)
-        L = np.einsum("ta,tb,tab->t", w1, w2, grid[i1[:, :, None], i2[:, None, :]])
-        out[near] = np.exp(1j * alpha * x[near, 0]) * (L + f_removed(k, alpha, t, z, order, eps))
+        vals = grid[i1[:, :, None], i2[:, None, :]]
+        L = np.einsum("ta,tb,tab->t", w1, w2, vals)
+        g = L + f_removed(k, alpha, t, z, order, eps)
+        if ring:
+            zn = ring_zone(t, z, h1, h2, eps)
+            if zn.any():
+                # node offsets from the lattice point: base index floor(t / h) - 1 + a
+                p1 = np.floor(t[zn] / h1)[:, None] - 1 + np.arange(4)
+                p2 = np.floor(z[zn] / h2)[:, None] - 1 + np.arange(4)
+                TN = (p1 * h1)[:, :, None] + 0 * p2[:, None, :]
+                ZN = (p2 * h2)[:, None, :] + 0 * p1[:, :, None]
+                fn = f_removed(k, alpha, TN, ZN, order, eps)
+                g[zn] = np.einsum("ta,tb,tab->t", w1[zn], w2[zn], vals[zn] + fn)
+        out[near] = np.exp(1j * alpha * x[near, 0]) * g
     if (~near).any():
         # beyond c nothing is removed: the far slab of Algorithm 2.1
         out[~near] = eval_g2d(k, alpha, x[~near], N1, N2, far_h, far_S, c, c_tilde, eps, q)
