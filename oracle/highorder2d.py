@@ -42,12 +42,14 @@ r^3 ln r Y J2,  T14 = int r^4 ln r Y J1,  T34 = int r^4 ln r Y J3 (dr over [0, 2
 The cut-off ring (``ring=True``).  L = K - f Y_eps is smooth, but across eps < r < 2 eps it
 carries the steep transition of Y_eps times the logarithm, and the 16-point stencil's error
 there is far larger than anywhere else (Remark 5.6 traces the accuracy to the smoothness of
-the cut-offs).  K itself is smooth in the ring.  So for a near target with eps < r < 2 eps +
-2 sqrt(2) h, h = max(h1, h2), the stencil interpolates K = L + f Y at its nodes instead of L,
-and nothing is added back: G = e^{i alpha x1} sum_ab w_a w_b (L + f Y)(node_ab).  Beyond
-2 eps + 2 sqrt(2) h every node has Y = 0 and both forms coincide; inside r <= eps the paper's
-form is kept (there K is close to its singularity, L is smooth).  A node's position is its
-offset from the lattice point, (p1 h1, p2 h2) with the stencil's own base indices.
+the cut-offs).  K itself is smooth in the ring.  So for a near target with r_lo < r < r_hi,
+r_hi = 2 eps + 2 sqrt(2) h, r_lo = max(eps, eps/2 + 2 sqrt(2) h), h = max(h1, h2), the stencil
+interpolates K = L + f Y at its nodes instead of L, and nothing is added back:
+G = e^{i alpha x1} sum_ab w_a w_b (L + f Y)(node_ab).  Beyond r_hi every node has Y = 0 and
+both forms coincide; below r_lo the paper's form is kept (there K is close to its
+singularity, L is smooth; r_lo keeps every node of a zone target at least eps/2 from the
+lattice point).  A node's position is its offset from the lattice point, (p1 h1, p2 h2)
+with the stencil's own base indices.
 """
 
 import math
@@ -121,10 +123,19 @@ def lhat_ho(k, alpha, N1, N2, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=O
     return lhat_2d(k, alpha, N1, N2, c, c_tilde, eps, q) - ehat(k, alpha, N1, N2, order, c_tilde, eps, q)
 
 
+def ring_bounds(h1, h2, eps=co.EPS):
+    """(r_lo, r_hi) of the ring zone: r_hi = 2 eps + 2 sqrt(2) h, r_lo = max(eps, eps/2 + 2 sqrt(2) h),
+    h = max(h1, h2); every node of a zone target's stencil (within 2 sqrt(2) h of it) then stays at
+    least eps/2 from the lattice point, where K is singular."""
+    reach = 2 * math.sqrt(2.0) * max(h1, h2)
+    return max(eps, 0.5 * eps + reach), 2 * eps + reach
+
+
 def ring_zone(t, z, h1, h2, eps=co.EPS):
-    """Near targets whose stencil interpolates K (``ring=True``): eps < r < 2 eps + 2 sqrt(2) max(h1, h2)."""
+    """Near targets whose stencil interpolates K (``ring=True``): r_lo < r < r_hi."""
+    lo, hi = ring_bounds(h1, h2, eps)
     r = np.sqrt(t * t + z * z)
-    return (r > eps) & (r < 2 * eps + 2 * math.sqrt(2.0) * max(h1, h2))
+    return (r > lo) & (r < hi)
 
 
 def eval_g2d_ho(k, alpha, x, N1, N2, far_h, far_S, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
