@@ -14,6 +14,7 @@ for all 1e7 targets (step 2), with targets already resident in HBM.
     python bench.py --workload surrogate     # MLP surrogate vs the plain method, 1e4 instances x 1e4 targets
     python bench.py --workload g2d_grad      # gradient of the 2D G, 1024 x-modes, 128 slices, 1e7 targets
     python bench.py --workload g2d_hess_diff # second-derivative differences, two wavenumbers, same grid
+    python bench.py --workload g2d_ho        # 2D G with the degree-2 and -3 log terms removed, same grid
 
 Prints one JSON line.  The per-kernel durations behind ``roofline`` are HIP
 events recorded by the library on the stream its kernels run on.
@@ -94,7 +95,7 @@ def main():
     ap.add_argument("--modes", default="256,256,64")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate", "g2d_grad", "g2d_hess_diff"], default="gd3d")
+    ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate", "g2d_grad", "g2d_hess_diff", "g2d_ho"], default="gd3d")
     ap.add_argument("--train-instances", type=int, default=2000)
     ap.add_argument("--train-per", type=int, default=8192)
     ap.add_argument("--train-epochs", type=float, default=4.0)
@@ -134,6 +135,9 @@ def main():
         return
     if args.workload == "g2d_hess_diff":
         print(json.dumps(run_g2d_hess_diff(args)), flush=True)
+        return
+    if args.workload == "g2d_ho":
+        print(json.dumps(run_g2d_ho(args)), flush=True)
         return
     m1, m2, m3 = (int(v) for v in args.modes.split(","))
     T = args.targets
@@ -407,6 +411,47 @@ def run_g2d_hess_diff(args):
             "config": {"workload": "g2d second-derivative differences k1=2.1 k2=4.35 alpha=0.3", "x1_modes": M1,
                        "slices": M2, "targets": T, "method": "plain"},
             "kernels_avg_ms": kern,
+            "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}
+
+
+def run_g2d_ho(args):
+    """The 2D G with the terms of degree 2 and 3 of the log singularity removed as well
+    (sing_order = 3, Remark 5.3) and K interpolated in the cut-off ring (ring_interp = 1):
+    k = 2.1, alpha = 0.3, 1024 x-modes, 128 slices, 1e7 targets U([0, 2pi] x [-1, 1]); one
+    prepare + evaluate per step.  The same step with sing_order 3 alone and with the paper's
+    Algorithm 2.1 (sing_order 1, ring_interp 0) is timed beside it."""
+    import torch
+    from paper_1801_05977_amd import qpgf, workloads
+    T, M1, M2 = 10_000_000, 1024, 128
+    x = torch.from_numpy(workloads.targets(T, 2, seed=0)).cuda()
+    prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
+    res = {}
+    for order, ring in ((3, 1), (3, 0), (1, 0)):
+        P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2, sing_order=order, ring_interp=ring)
+        out = P.out_tensor(T)
+        t = _timed(lambda: P(2.1, 0.3, 0.0, x, out), args.steps, args.warmup)
+        P.enable_timing(True)
+        for _ in range(args.steps):
+            P(2.1, 0.3, 0.0, x, out)
+        torch.cuda.synchronize()
+        kern = {k_: round(v[0] / v[1], 5) for k_, v in P.timing().items() if v[1]}
+        res[order, ring] = (t, kern, P.info.grid_bytes + P.info.far_grid_bytes)
+        P.close()
+    t, kern, gb = res[3, 1]
+    esize = 8 if prec == qpgf.C64 else 16
+    # gather: 16 B in, one result and a flag byte out per target, the near field and far slab once
+    alg = T * (16 + esize + 1) + gb
+    ach = alg / (kern["gather"] * 1e-3) / 1e9
+    return {"metric": "2D G evals/sec, degree-3 singular removal and ring interpolation", "value": T / t,
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+            "data": "synthetic",
+            "config": {"workload": "g2d k=2.1 alpha=0.3, sing_order 3, ring_interp 1", "x1_modes": M1,
+                       "slices": M2, "targets": T, "method": "plain"},
+            "kernels_avg_ms": kern,
+            "sing_order_3_only": {"ms_per_step": res[3, 0][0] * 1e3, "kernels_avg_ms": res[3, 0][1]},
+            "algorithm_2_1": {"ms_per_step": res[1, 0][0] * 1e3, "kernels_avg_ms": res[1, 0][1]},
             "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}
 

@@ -108,6 +108,22 @@ typedef struct {
   double wood_tol;
   double special_tol;
   double lattice_rmin;
+  int sing_order;          /* QPGF_KIND_G2D: highest degree m of the Taylor factor of the removed log
+                              singularity -(1/2pi) ln r J0(k r) e^{-i alpha x1} (Remark 5.3).  1 (default)
+                              removes 1 - i alpha x1 (f1, f2 of Section 2.2, Algorithm 2.1 as printed); 2
+                              adds -(alpha^2/2) x1^2 - (k^2/4) r^2; 3 adds i (alpha^3/6) x1^3 + i (alpha k^2/4)
+                              x1 r^2.  The remainder is O(r^{m+1} ln r), so near a lattice point the error
+                              falls like N^-(m+1) instead of N^-2.  Every other kind requires 1. */
+  int ring_interp;         /* QPGF_KIND_G2D, single-instance calls: 1 interpolates K = L + f Y (f the removed
+                              singular part) instead of L for near targets with r_lo < r < r_hi, r_hi =
+                              2 eps + 2 sqrt(2) h, r_lo = max(eps, eps/2 + 2 sqrt(2) h), h = max(h1, h2) (every
+                              stencil node then stays eps/2 or more from the lattice point), and adds nothing
+                              back there.  L carries the steep transition of
+                              Y_eps times the logarithm across that ring, K does not (Remark 5.6 ties the
+                              accuracy to the cut-offs' smoothness): the ring's error falls by two to three
+                              orders of magnitude.  Those targets are collected by the gather and corrected by
+                              a second pass.  0 (default): Algorithm 2.1 as printed.  Every other kind, and
+                              qpgf_g2d_batched, require 0. */
 } qpgf_params;
 
 typedef struct qpgf_plan qpgf_plan;
@@ -312,7 +328,9 @@ typedef enum {
   QPGF_T_BATCH = 9,    /* one replay of the batched 2D graph (all stages)        */
   QPGF_T_BIN_PLACE = 10, /* binning: scatter of target records into tile order   */
   QPGF_T_OVERFLOW = 11,  /* targets handed over by the tiled gather              */
-  QPGF_T_COUNT = 12
+  QPGF_T_LAYOUT = 12,    /* 2D derivative kinds: fields interleaved per grid node  */
+  QPGF_T_RING = 13,      /* 2D G with ring_interp: the cut-off-ring correction     */
+  QPGF_T_COUNT = 14
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
 qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches);

@@ -97,10 +97,10 @@ void free_plan(Plan& P) {
   if (P.b_capture) (void)hipStreamDestroy(P.b_capture);
   if (P.b_upload_done) (void)hipEventDestroy(P.b_upload_done);
   if (P.b_host) (void)hipHostFree(P.b_host);
-  for (void* q : {P.b_grid, P.b_far, P.b_desc})
+  for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI, P.farI})
     if (q) (void)hipFree(q);
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.wXq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
-                  P.twf,  P.F1,  P.F2,   P.D2, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
+                  P.twf,  P.F1,  P.F2,   P.D2, P.E2, P.ring_cnt, P.ring_idx, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -134,6 +134,10 @@ qpgf_status validate(const qpgf_params* p) {
     return fail(QPGF_E_ARG, "tolerances must be >= 0");
   if (!(p->special_tol < 0.25 * M_PI / p->c_tilde))
     return fail(QPGF_E_ARG, "special_tol must be below pi / (4 c_tilde)");
+  if (p->sing_order < 1 || p->sing_order > 3) return fail(QPGF_E_ARG, "sing_order must be 1, 2 or 3");
+  if (p->sing_order != 1 && p->kind != QPGF_KIND_G2D) return fail(QPGF_E_ARG, "sing_order above 1 needs QPGF_KIND_G2D");
+  if (p->ring_interp != 0 && p->ring_interp != 1) return fail(QPGF_E_ARG, "ring_interp must be 0 or 1");
+  if (p->ring_interp && p->kind != QPGF_KIND_G2D) return fail(QPGF_E_ARG, "ring_interp needs QPGF_KIND_G2D");
   return QPGF_OK;
 }
 
@@ -268,6 +272,11 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
         HIP_TRY(launch_fft(P, P.far, P.M2, P.M1, (long)P.M1 * P.S * nf, P.M1, 1, (long)P.M1 * P.M2));
       HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)(P.dim == 3 ? P.M2 : 1) * P.S * nf, 1, 0, P.M1));
     }
+    if (P.dim == 2 && nf > 1) {
+      // the gather reads all fields of a stencil row as one contiguous run
+      KernelTimer t(P, QPGF_T_LAYOUT);
+      HIP_TRY(launch_interleave2d(P));
+    }
     P.prepared = true;
   }
   return QPGF_OK;
@@ -324,6 +333,8 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
   p->wood_tol = 1e-3;
   p->special_tol = 1e-2;
   p->lattice_rmin = 0.0;
+  p->sing_order = 1;
+  p->ring_interp = 0;
 }
 
 qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
@@ -368,6 +379,10 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
 
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
   PLAN_TRY(hipMalloc(&P.far, P.nf * P.nfar * P.esize));
+  if (P.dim == 2 && P.nf > 1) {
+    PLAN_TRY(hipMalloc(&P.gridI, P.nf * P.ncell * P.esize));
+    PLAN_TRY(hipMalloc(&P.farI, P.nf * P.nfar * P.esize));
+  }
 
   const int Q = p->quad_q;
   std::vector<long double> gx, gw;
@@ -425,8 +440,9 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
     PLAN_ST(upload(&P.tw, tw));
     PLAN_ST(upload(&P.twf, twf));
   }
-  if (p->kind == QPGF_KIND_G2D_GRAD || p->kind == QPGF_KIND_G2D_HESS_DIFF) {
-    // derivative tables: Gauss-Legendre rule on [eps, 2 eps] for |eta| up to the grid's corner
+  const bool ho = p->kind == QPGF_KIND_G2D && p->sing_order > 1;
+  if (p->kind == QPGF_KIND_G2D_GRAD || p->kind == QPGF_KIND_G2D_HESS_DIFF || ho) {
+    // derivative and higher-order tables: Gauss-Legendre rule on [eps, 2 eps] for |eta| up to the grid's corner
     // (about |eta| eps nodes beyond the plain rule resolve the Bessel oscillations)
     const double e1 = P.M1 / 2, e2 = (P.M2 / 2) * M_PI / p->c_tilde;
     const int Qg = std::max(Q, (int)std::ceil(std::sqrt(e1 * e1 + e2 * e2) * p->eps) + 64);
@@ -445,14 +461,21 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
       (void)hipFree(drg);
       return bail(su);
     }
-    const bool grad = p->kind == QPGF_KIND_G2D_GRAD;
-    hipError_t e2r = hipMalloc(reinterpret_cast<void**>(&P.D2), (grad ? 8 : 6) * P.ncell * sizeof(double));
-    if (e2r == hipSuccess) e2r = grad ? launch_sing2d_grad(P, Qg, drg, dwyg) : launch_sing2d_hess(P, Qg, drg, dwyg);
+    hipError_t e2r;
+    if (ho) {
+      e2r = hipMalloc(reinterpret_cast<void**>(&P.E2), 4 * P.ncell * sizeof(double));
+      if (e2r == hipSuccess) e2r = launch_sing2d_ho(P, Qg, drg, dwyg);
+    } else {
+      const bool grad = p->kind == QPGF_KIND_G2D_GRAD;
+      e2r = hipMalloc(reinterpret_cast<void**>(&P.D2), (grad ? 8 : 6) * P.ncell * sizeof(double));
+      if (e2r == hipSuccess) e2r = grad ? launch_sing2d_grad(P, Qg, drg, dwyg) : launch_sing2d_hess(P, Qg, drg, dwyg);
+    }
     if (e2r == hipSuccess) e2r = hipDeviceSynchronize();
     (void)hipFree(drg);
     (void)hipFree(dwyg);
     PLAN_TRY(e2r);
-  } else if (P.dim == 2) {
+  }
+  if (p->kind == QPGF_KIND_G2D) {
     // Phi_1(r) = (2 + ln r) Y'(r)/r + Y''(r) ln r at the radial nodes, times the weights
     std::vector<double> wphi(Q);
     long double f1tail = 0.0L;
@@ -647,6 +670,7 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   qpgf_status st = check_plan(plan, QPGF_KIND_G2D);
   if (st != QPGF_OK) return st;
   Plan& P = plan->P;
+  if (P.p.ring_interp) return fail(QPGF_E_ARG, "ring_interp is not available in qpgf_g2d_batched");
   if (n_inst <= 0 || !k || !alpha || !m1 || !t_off) return fail(QPGF_E_ARG, "need n_inst > 0 and host k, alpha, m1, t_off");
   if (t_off[0] != 0) return fail(QPGF_E_ARG, "t_off[0] must be 0");
   for (int i = 0; i < n_inst; ++i) {

@@ -42,6 +42,9 @@ struct FillArgs {
   const double* rq;          // radial rule on [eps, 2 eps] (3D singular part)
   const double* wrq;
   double eps;
+  // 2D G: tables of the removed degree-2 and degree-3 terms (Remark 5.3), nullptr for sing_order 1
+  const double* E;
+  int sing_order;
 };
 
 // a_q = w_q X'(x_q) e^{i beta x_q} for the TP pencils of this block, into LDS.
@@ -277,11 +280,22 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
   const int jt_tab = j1 & (M1t - 1);
+  // E-hat = -(alpha^2/2) e_tt - (k^2/4) e_rr - (alpha^3/6) e_ttt - (alpha k^2/4) e_trr (real)
+  const double ka = A.k * A.k;
+  const double ce0 = -0.5 * A.a1 * A.a1, ce1 = -0.25 * ka;
+  const double ce2 = A.sing_order >= 3 ? -A.a1 * A.a1 * A.a1 / 6.0 : 0.0;
+  const double ce3 = A.sing_order >= 3 ? -0.25 * A.a1 * ka : 0.0;
+  const size_t en = (size_t)A.Mt * M1t;
   auto put = [&](int jtp, double2 K) {
     const size_t ot = (size_t)jtp * M1t + jt_tab;
     const double2 f1 = F1[ot], f2 = F2[ot];
-    // L = K - F1 + i alpha F2, times the basis normalisation A2
-    const double2 L = cscale(mk(K.x - f1.x - A.a1 * f2.y, K.y - f1.y + A.a1 * f2.x), A.A);
+    // L = K - F1 + i alpha F2 (- E-hat), times the basis normalisation A2
+    double lx = K.x - f1.x - A.a1 * f2.y;
+    if (A.E) {
+      const double* e = A.E + ot;
+      lx -= ce0 * e[0] + ce1 * e[en] + ce2 * e[2 * en] + ce3 * e[3 * en];
+    }
+    const double2 L = cscale(mk(lx, K.y - f1.y + A.a1 * f2.x), A.A);
     store_c<T>(out, (size_t)jtp * A.M1 + j1p, L);
   };
   for (int jtp = lane; jtp < A.Mt; jtp += TL) {
@@ -388,6 +402,66 @@ __global__ void k_sing2d(int M1, int M2, double c_tilde, double A2, int Q, const
 struct Radial {
   double TA, TB, TC0, TC2, TD1, TD3, TL;
 };
+
+// Higher-order 2D tables (Remark 5.3): the Fourier coefficients of the degree-2 and
+// degree-3 terms of the removed -(1/2pi) ln r Y(r) P_m(x1, r),
+//   -(alpha^2/2) x1^2 - (k^2/4) r^2 + i (alpha^3/6) x1^3 + i (alpha k^2/4) x1 r^2,
+// split by their k- and alpha-dependence into four real tables ([4][M2][M1], A2 and -1/2pi
+// included): e_tt (x1^2 ln r), e_rr (r^2 ln r) and the imaginary parts e_ttt (x1^3 ln r),
+// e_trr (x1 r^2 ln r), so that E-hat = -(alpha^2/2) e_tt - (k^2/4) e_rr - (alpha^3/6) e_ttt
+// - (alpha k^2/4) e_trr.  With x1^2 = r^2 (1 + cos 2 theta)/2, x1^3 = r^3 (3 cos theta +
+// cos 3 theta)/4 and the plane-wave expansion (a radial g times cos n theta has the
+// coefficient 2 pi (-i)^n cos n phi int g J_n(|eta| r) r dr), four radial integrals serve:
+//   T03 = int r^3 ln r Y J0,  T23 = int r^3 ln r Y J2,  T14 = int r^4 ln r Y J1,  T34 = int r^4 ln r Y J3.
+// On [0, eps] (Y = 1) integration by parts against the antiderivatives int z^3 J0 = z^3 J1 -
+// 2 z^2 J2, int z^{n+1} J_n = z^{n+1} J_{n+1}, int z^4 J1 = z^4 J2 - 2 z^3 J3 and the closed
+// forms of int z J2, int z^2 J3, int z^3 J4 gives them exactly; on [eps, 2 eps] the
+// Gauss-Legendre rule of the derivative tables.
+__global__ void k_sing2d_ho(int M1, int M2, double c_tilde, double A2, double eps, int Qg,
+                            const double* __restrict__ rg, const double* __restrict__ wyg, double* __restrict__ E) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)M1 * M2;
+  if (idx >= n) return;
+  const int j1p = (int)(idx % M1), j2p = (int)(idx / M1);
+  const double e1 = centered(j1p, M1), J = centered(j2p, M2) * kPi / c_tilde;
+  const double rho2 = e1 * e1 + J * J;
+  const double le = log(eps), e2 = eps * eps, e3 = e2 * eps, e4 = e3 * eps;
+  if (rho2 == 0.0) {
+    // |eta| = 0: only J0 survives; int_0^eps r^3 ln r dr = eps^4 (ln eps / 4 - 1/16)
+    double T03 = e4 * (0.25 * le - 0.0625);
+    for (int q = 0; q < Qg; ++q) {
+      const double r = rg[q];
+      T03 = fma(wyg[q] * r * r * r, log(r), T03);
+    }
+    E[idx] = -0.5 * A2 * T03;
+    E[n + idx] = -A2 * T03;
+    E[2 * n + idx] = 0.0;
+    E[3 * n + idx] = 0.0;
+    return;
+  }
+  const double rho = sqrt(rho2), ir = 1.0 / rho, ze = rho * eps;
+  const double J0e = j0(ze), J1e = j1(ze), J2e = jn(2, ze), J3e = jn(3, ze), J4e = jn(4, ze);
+  // int_0^eps r J2 and int_0^eps r^2 J3 (as in the derivative tables)
+  const double c2 = 2.0 * (1.0 - J0e) * ir * ir - eps * J1e * ir;
+  const double d3 = 4.0 * ir * c2 - e2 * J2e * ir;
+  double T03 = le * (e3 * J1e * ir - 2.0 * e2 * J2e * ir * ir) - e2 * J2e * ir * ir + 2.0 * c2 * ir * ir;
+  double T23 = le * e3 * J3e * ir - d3 * ir;
+  double T14 = le * (e4 * J2e * ir - 2.0 * e3 * J3e * ir * ir) - e3 * J3e * ir * ir + 2.0 * d3 * ir * ir;
+  double T34 = le * e4 * J4e * ir - (6.0 * d3 * ir - e3 * J3e * ir) * ir;
+  for (int q = 0; q < Qg; ++q) {
+    const double r = rg[q], z = rho * r;
+    const double w3 = wyg[q] * r * r * r * log(r), w4 = w3 * r;
+    T03 = fma(w3, j0(z), T03);
+    T23 = fma(w3, jn(2, z), T23);
+    T14 = fma(w4, j1(z), T14);
+    T34 = fma(w4, jn(3, z), T34);
+  }
+  const double cp = e1 * ir, c2p = (e1 * e1 - J * J) / rho2, c3p = cp * (4.0 * cp * cp - 3.0);
+  E[idx] = -0.5 * A2 * (T03 - c2p * T23);
+  E[n + idx] = -A2 * T03;
+  E[2 * n + idx] = 0.25 * A2 * (3.0 * cp * T14 - c3p * T34);
+  E[3 * n + idx] = A2 * cp * T14;
+}
 __device__ Radial radial_integrals(double rho, double eps, int Qg, const double* __restrict__ rg,
                                    const double* __restrict__ wyg) {
   const double ze = rho * eps, J0e = j0(ze), J1e = j1(ze), J2e = jn(2, ze), ir = 1.0 / rho, le = log(eps);
@@ -759,6 +833,8 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
   A.rq = P.rq;
   A.wrq = P.wrq;
   A.eps = P.p.eps;
+  A.E = P.E2;
+  A.sing_order = P.p.sing_order;
   const size_t shm = (size_t)TP * A.Q * sizeof(double2);
   auto* out = static_cast<cplx<T>*>(P.grid);
   if (P.dim == 2) {
@@ -856,6 +932,14 @@ hipError_t launch_sing2d(Plan& P, double f1zero) {
   return hipGetLastError();
 }
 
+hipError_t launch_sing2d_ho(Plan& P, int Qg, const double* rg, const double* wyg) {
+  const long n = (long)P.M1 * P.M2;
+  const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
+  hipLaunchKernelGGL(k_sing2d_ho, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
+                     P.p.eps, Qg, rg, wyg, P.E2);
+  return hipGetLastError();
+}
+
 hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* wyg) {
   const long n = (long)P.M1 * P.M2;
   const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
@@ -899,6 +983,8 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff
   I.A.wrq = P.wrq;
   I.A.eps = P.p.eps;
   I.A.k2 = 0.0;
+  I.A.E = P.E2;
+  I.A.sing_order = P.p.sing_order;
   I.off = off;
   I.foff = foff;
   I.blk0 = blk0;

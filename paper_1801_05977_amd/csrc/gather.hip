@@ -24,6 +24,11 @@ struct GArgs {
   int S;                   // far-slab slices
   long fs, ffs;            // field strides (near, far)
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
+  int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
+  // 2D G, ring_interp: near targets with eps < r < ring_hi are appended to ring_idx
+  uint32_t* ring_cnt;
+  uint32_t* ring_idx;
+  double ring_lo, ring_hi;
 };
 
 // cubic Lagrange weights at nodes -1, 0, 1, 2 (W = float on the complex64
@@ -694,13 +699,92 @@ __device__ __forceinline__ double2 stencil2d<float>(const float2* __restrict__ g
   return mk(re, im);
 }
 
+// NF fields interleaved per node (g[node * NF + f]): one 4 x 4 stencil gives all of them,
+// and a stencil row of all fields is one contiguous run of 4 NF values.
+template <typename T, int NF>
+__device__ __forceinline__ void stencil2d_multi(const cplx<T>* __restrict__ g, const long rows[4], int i0, int M1,
+                                                const T w1[4], const T w2[4], double2 L[NF]) {
+  Acc<T> acc[NF];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const cplx<T>* q = g + (rows[b] + ((i0 + a) & (M1 - 1))) * NF;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f].add(w2[b] * w1[a], q[f]);
+    }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+}
+// complex64: a row that does not wrap in x1 is 4 NF float2 = 2 NF 16-byte loads
+template <int NF>
+__device__ __forceinline__ void stencil2d_multi_f32(const float2* __restrict__ g, const long rows[4], int i0, int M1,
+                                                    const float w1[4], const float w2[4], double2 L[NF]) {
+  if (i0 > M1 - 4) {
+    stencil2d_multi<float, NF>(g, rows, i0, M1, w1, w2, L);
+    return;
+  }
+  float re[NF], im[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) re[f] = im[f] = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const F4a8* r = reinterpret_cast<const F4a8*>(g + (rows[b] + i0) * NF);
+    float v[8 * NF];
+#pragma unroll
+    for (int q = 0; q < 2 * NF; ++q) {
+      const F4a8 t = r[q];
+      v[4 * q] = t.a;
+      v[4 * q + 1] = t.b;
+      v[4 * q + 2] = t.c;
+      v[4 * q + 3] = t.d;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      float sr = w1[0] * v[2 * f], si = w1[0] * v[2 * f + 1];
+#pragma unroll
+      for (int a = 1; a < 4; ++a) {
+        sr = fmaf(w1[a], v[2 * (a * NF + f)], sr);
+        si = fmaf(w1[a], v[2 * (a * NF + f) + 1], si);
+      }
+      re[f] = fmaf(w2[b], sr, re[f]);
+      im[f] = fmaf(w2[b], si, im[f]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) L[f] = mk(re[f], im[f]);
+}
+template <typename T, int NF>
+__device__ __forceinline__ void stencil2d_fields(const cplx<T>* __restrict__ g, const long rows[4], int i0, int M1,
+                                                 const T w1[4], const T w2[4], double2 L[NF]) {
+  if constexpr (sizeof(T) == 4)
+    stencil2d_multi_f32<NF>(g, rows, i0, M1, w1, w2, L);
+  else
+    stencil2d_multi<T, NF>(g, rows, i0, M1, w1, w2, L);
+}
+
 // One target of Algorithm 2.1 step 2.
+// Append target i to the ring list when take is set: one atomic per wave (ballot, prefix count).
+// Called with the whole wave's active lanes together.
+__device__ __forceinline__ void ring_append(uint32_t* __restrict__ cnt, uint32_t* __restrict__ idx, bool take,
+                                            long i) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  if (take) idx[base + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+}
+
 template <typename T>
 __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                              const cplx<T>* __restrict__ far, const double* __restrict__ x, long i,
                                              cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
   uint8_t fl = 0;
+  bool in_ring = false;
   double2 res;
   if (!(isfinite(x1) && isfinite(x2))) {
     fl = 8;
@@ -751,7 +835,19 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
         } else if (r < 2.0 * A.eps) {
           // K_N = L_N + f1 - i alpha f2 = L_N - (1/2pi) ln r Y(r) (1 - i alpha t)
           const double s = -log(r) * cut_Y(r, A.eps) / (2.0 * kPi);
-          Lt = cadd(Lt, mk(s, -A.a1 * t * s));
+          in_ring = r > A.ring_lo;
+          if (A.sing_order <= 1) {
+            Lt = cadd(Lt, mk(s, -A.a1 * t * s));
+          } else {
+            // the higher-order factor P_m: 1 - i a t - (a^2/2) t^2 - (k^2/4) r^2 + i (a^3/6) t^3 + i (a k^2/4) t r^2
+            const double a = A.a1, kk = 0.25 * A.k * A.k, r2 = t * t + x2 * x2;
+            const double pr = 1.0 - 0.5 * a * a * t * t - kk * r2;
+            double pim = -a * t;
+            if (A.sing_order >= 3) pim += a * t * (a * a * t * t / 6.0 + kk * r2);
+            Lt = cadd(Lt, mk(s * pr, s * pim));
+          }
+        } else if (r < A.ring_hi) {
+          in_ring = r > A.ring_lo;
         }
       }
       res = cmul(phase, Lt);
@@ -759,6 +855,61 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
   }
   store_out<T>(out, i, res);
   if (flags) flags[i] = fl;
+  if (A.ring_idx) ring_append(A.ring_cnt, A.ring_idx, in_ring, i);
+}
+
+// The cut-off ring (ring_interp): for the collected targets (r_lo < r < r_hi, every stencil node at
+// least eps/2 from the lattice point) the stencil's sum of f Y over its
+// nodes replaces f Y at the target, so that the result is the interpolant of K = L + f Y:
+// out += e^{i alpha x1} (sum_ab w_a w_b (f Y)(node_ab) - (f Y)(target)), f the removed singular
+// part of the plan's order and a node's position its offset (p1 h1, p2 h2) from the lattice
+// point.  FP64 throughout; a grid-stride loop over the list (its length is read on the device).
+__device__ __forceinline__ double2 fy_removed(const GArgs& A, double t, double z) {
+  const double r2 = t * t + z * z;
+  const double r = sqrt(r2);
+  if (!(r < 2.0 * A.eps) || r2 == 0.0) return mk(0.0, 0.0);
+  const double s = -log(r) * cut_Y(r, A.eps) / (2.0 * kPi);
+  const double a = A.a1;
+  double pr = 1.0, pim = -a * t;
+  if (A.sing_order >= 2) {
+    const double kk = 0.25 * A.k * A.k;
+    pr -= 0.5 * a * a * t * t + kk * r2;
+    if (A.sing_order >= 3) pim += a * t * (a * a * t * t / 6.0 + kk * r2);
+  }
+  return mk(s * pr, s * pim);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x,
+                                                const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ idx,
+                                                cplx<T>* __restrict__ out) {
+  const uint32_t n = *cnt;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const long i = idx[j];
+    const double x1 = x[2 * i], x2 = x[2 * i + 1];
+    double n1;
+    const double t = reduce_cell(x1, n1);
+    const double u = t * A.ih1, p = floor(u), u2 = x2 * A.ih2, p2 = floor(u2);
+    double w1[4], w2[4];
+    lag4<double>(u - p, w1);
+    lag4<double>(u2 - p2, w2);
+    double2 acc = mk(0.0, 0.0);
+    for (int b = 0; b < 4; ++b) {
+      const double zn = (p2 - 1.0 + b) * A.h2;
+      double2 row = mk(0.0, 0.0);
+      for (int a = 0; a < 4; ++a) {
+        const double2 f = fy_removed(A, (p - 1.0 + a) * A.h1, zn);
+        row = mk(fma(w1[a], f.x, row.x), fma(w1[a], f.y, row.y));
+      }
+      acc = mk(fma(w2[b], row.x, acc.x), fma(w2[b], row.y, acc.y));
+    }
+    const double2 d = csub(acc, fy_removed(A, t, x2));
+    double ps, pc;
+    sincos(A.a1 * x1, &ps, &pc);
+    const double2 corr = cmul(mk(pc, ps), d);
+    const cplx<T> o = out[i];
+    store_out<T>(out, i, mk((double)o.x + corr.x, (double)o.y + corr.y));
+  }
 }
 
 template <typename T>
@@ -772,7 +923,7 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
 // One target of the 2D gradient (Section 2.4.1): both fields interpolated with one
 // stencil, the singular parts h1, h2 added back in FP64 inside 2 eps, the phase
 // e^{i alpha x1}; beyond c the differentiated far slab, the x2 field times sgn(x2).
-// out[2i] = dG/dx1, out[2i+1] = dG/dx2.
+// grid and far hold the two fields interleaved per node.  out[2i] = dG/dx1, out[2i+1] = dG/dx2.
 template <typename T>
 __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
@@ -796,7 +947,6 @@ __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>*
     const bool is_near = fabs(x2) <= A.c;
     long rows[4];
     const cplx<T>* g = grid;
-    long fst = A.fs;
     bool bad = false;
     if (is_near) {
       const double u2 = x2 * A.ih2, p2 = floor(u2);
@@ -806,7 +956,6 @@ __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>*
     } else {
       fl |= 2;
       g = far;
-      fst = A.ffs;
       const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
       double s0 = floor(v);
       if (s0 > A.S - 3) {
@@ -822,8 +971,9 @@ __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>*
     if (bad) {
       d1 = d2 = nan2();
     } else {
-      double2 L1 = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
-      double2 L2 = stencil2d<T>(g + fst, rows, i0, A.M1, w1, w2);
+      double2 L[2];
+      stencil2d_fields<T, 2>(g, rows, i0, A.M1, w1, w2, L);
+      double2 L1 = L[0], L2 = L[1];
       if (is_near) {
         const double r2 = t * t + x2 * x2;
         if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
@@ -862,7 +1012,8 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
 
 // One target of the second-derivative differences (Section 2.4.2): three fields with one
 // stencil, h_pq added back in FP64 inside 2 eps, the phase e^{i alpha x1}; beyond c the far
-// slab, the 12 field times sgn(x2).  out[3i + p] = d_p d_q G_k1 - d_p d_q G_k2, pq = 11, 12, 22.
+// slab, the 12 field times sgn(x2).  grid and far hold the three fields interleaved per node.
+// out[3i + p] = d_p d_q G_k1 - d_p d_q G_k2, pq = 11, 12, 22.
 template <typename T>
 __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
@@ -886,7 +1037,6 @@ __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>*
     const bool is_near = fabs(x2) <= A.c;
     long rows[4];
     const cplx<T>* g = grid;
-    long fst = A.fs;
     bool bad = false;
     if (is_near) {
       const double u2 = x2 * A.ih2, p2 = floor(u2);
@@ -896,7 +1046,6 @@ __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>*
     } else {
       fl |= 2;
       g = far;
-      fst = A.ffs;
       const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
       double s0 = floor(v);
       if (s0 > A.S - 3) {
@@ -913,8 +1062,7 @@ __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>*
       d[0] = d[1] = d[2] = nan2();
     } else {
       double2 L[3];
-#pragma unroll
-      for (int f = 0; f < 3; ++f) L[f] = stencil2d<T>(g + f * fst, rows, i0, A.M1, w1, w2);
+      stencil2d_fields<T, 3>(g, rows, i0, A.M1, w1, w2, L);
       if (is_near) {
         const double r2 = t * t + x2 * x2;
         if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
@@ -1163,6 +1311,18 @@ __global__ __launch_bounds__(1024) void k_bin_place(BinArgs B, const double* __r
   }
 }
 
+// [field][node] -> [node][field] for the near grid and the far slab of the 2D derivative
+// kinds (one thread per output element: coalesced writes, NF coalesced read streams).
+template <typename T>
+__global__ __launch_bounds__(256) void k_interleave(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                    long n, int nf) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nf) return;
+  const long node = e / nf;
+  const int f = (int)(e - node * nf);
+  out[e] = in[f * n + node];
+}
+
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
 
 template <typename T>
@@ -1197,6 +1357,14 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.fs = (long)P.ncell;
   A.ffs = (long)P.nfar;
   A.smooth = smooth;
+  A.sing_order = P.p.sing_order;
+  A.ring_cnt = nullptr;
+  A.ring_idx = nullptr;
+  // the ring zone r_lo < r < r_hi: r_hi = 2 eps + 2 sqrt(2) h, beyond which every stencil node has
+  // Y = 0; r_lo = max(eps, eps/2 + 2 sqrt(2) h) keeps every node at least eps/2 from the lattice point
+  const double reach = 2.0 * sqrt(2.0) * fmax(A.h1, A.h2);
+  A.ring_lo = fmax(A.eps, 0.5 * A.eps + reach);
+  A.ring_hi = 2.0 * A.eps + reach;
   const auto* g = static_cast<const cplx<T>*>(P.grid);
   const auto* f = static_cast<const cplx<T>*>(P.far);
   auto* o = static_cast<cplx<T>*>(out);
@@ -1208,12 +1376,27 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   }
   if (P.dim == 2) {
     KernelTimer t(P, QPGF_T_GATHER);
+    const auto* gi = static_cast<const cplx<T>*>(P.gridI);
+    const auto* fi = static_cast<const cplx<T>*>(P.farI);
     if (P.nf == 2)
-      hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+      hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
     else if (P.nf == 3)
-      hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
-    else
+      hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
+    else if (!P.p.ring_interp)
       hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    else {
+      if (T_ > (int64_t)UINT32_MAX) return hipErrorInvalidValue;   // the ring list holds 32-bit indices
+      hipError_t e = ensure_ring_scratch(P, T_);
+      if (e != hipSuccess) return e;
+      A.ring_cnt = P.ring_cnt;
+      A.ring_idx = P.ring_idx;
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.ring_cnt, 1L);
+      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      KernelTimer tr(P, QPGF_T_RING);
+      const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
+      hipLaunchKernelGGL(k_ring2d<T>, dim3(nb), dim3(256), 0, P.stream, A, x, P.ring_cnt, P.ring_idx, o);
+    }
     return hipGetLastError();
   }
   if (P.bin_min_targets < 0 || T_ < P.bin_min_targets) {
@@ -1373,6 +1556,37 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 
 }  // namespace
 
+hipError_t launch_interleave2d(Plan& P) {
+  if (P.dim != 2 || P.nf < 2 || !P.gridI || !P.farI) return hipErrorInvalidValue;
+  auto go = [&](auto tag, const void* in, void* out, long n) {
+    using T = decltype(tag);
+    const long tot = n * P.nf;
+    hipLaunchKernelGGL(k_interleave<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
+                       static_cast<const cplx<T>*>(in), static_cast<cplx<T>*>(out), n, P.nf);
+  };
+  if (P.esize == 16) {
+    go(double(), P.grid, P.gridI, (long)P.ncell);
+    go(double(), P.far, P.farI, (long)P.nfar);
+  } else {
+    go(float(), P.grid, P.gridI, (long)P.ncell);
+    go(float(), P.far, P.farI, (long)P.nfar);
+  }
+  return hipGetLastError();
+}
+
+hipError_t ensure_ring_scratch(Plan& P, int64_t T_) {
+  hipError_t e;
+  if (!P.ring_cnt && (e = hipMalloc(reinterpret_cast<void**>(&P.ring_cnt), sizeof(uint32_t))) != hipSuccess) return e;
+  if (T_ > P.ring_cap) {
+    if (P.ring_idx) (void)hipFree(P.ring_idx);
+    P.ring_idx = nullptr;
+    P.ring_cap = 0;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.ring_idx), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
+    P.ring_cap = T_;
+  }
+  return hipSuccess;
+}
+
 hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
   if (T_ > P.bin_cap) {
     for (void* q : {(void*)P.bin_keyrank, (void*)P.bin_rec, (void*)P.bin_ovf})
@@ -1432,6 +1646,10 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.fs = (long)M1 * P.M2;
   A.ffs = (long)M1 * P.S;
   A.smooth = 0;
+  A.sing_order = P.p.sing_order;
+  A.ring_cnt = nullptr;
+  A.ring_idx = nullptr;
+  A.ring_lo = A.ring_hi = 0.0;
   I.off = off;
   I.foff = foff;
   I.t0 = t0;

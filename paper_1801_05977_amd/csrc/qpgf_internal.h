@@ -133,6 +133,10 @@ struct Plan {
   int twlog2 = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
+  void* gridI = nullptr;       // 2D derivative kinds: the near fields interleaved, [i2][i1][field]
+  void* farI = nullptr;        // and the far slab, [s][i1][field]
+  double* E2 = nullptr;        // 2D G with sing_order >= 2: [4][j2'][j1'] real tables of the removed
+                               // degree-2 and degree-3 terms (e_tt, e_rr, e_ttt, e_trr)
   double* D2 = nullptr;        // 2D derivative tables: gradient [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2),
                                // second-derivative differences [6][j2'][j1'] (u11 v11 u12 v12 u22 v22)
   double2* htab = nullptr;     // 3D: H(rho) on rho = (m - 4) dh
@@ -152,6 +156,9 @@ struct Plan {
   uint32_t* bin_hist = nullptr;
   uint32_t* bin_offs = nullptr;
   uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
+  uint32_t* ring_cnt = nullptr;        // 2D G, ring_interp: targets collected for the ring pass
+  uint32_t* ring_idx = nullptr;
+  int64_t ring_cap = 0;
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count
   // tile configuration of the last binning (launch_bin3d), used by launch_gather_binned
@@ -209,6 +216,8 @@ struct KernelTimer {
 };
 
 // kernel launchers (fill.hip, fft.hip, gather.hip)
+hipError_t launch_interleave2d(Plan& P);
+hipError_t launch_sing2d_ho(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d_hess(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d_grad(Plan& P, int Qg, const double* rg, const double* wyg);
 hipError_t launch_sing2d(Plan& P, double f1_zero);
@@ -232,6 +241,7 @@ hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nb
 hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, long nblocks, long lds_elems);
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
+hipError_t ensure_ring_scratch(Plan& P, int64_t T);
 hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
 // The 3D calculation step in two halves: binning of the targets by grid tile
 // (needs only the targets and the plan's geometry, so it may run on another

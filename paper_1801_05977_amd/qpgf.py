@@ -31,7 +31,8 @@ class Params(ctypes.Structure):
                 ("m3", ctypes.c_int), ("c", ctypes.c_double), ("c_tilde", ctypes.c_double),
                 ("eps", ctypes.c_double), ("quad_q", ctypes.c_int), ("far_h", ctypes.c_double),
                 ("far_zmax", ctypes.c_double), ("wood_tol", ctypes.c_double), ("special_tol", ctypes.c_double),
-                ("lattice_rmin", ctypes.c_double)]
+                ("lattice_rmin", ctypes.c_double), ("sing_order", ctypes.c_int),
+                ("ring_interp", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +50,7 @@ EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
            "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch", "bin_place",
-          "overflow"]
+          "overflow", "layout", "ring"]
 
 _lib = None
 

@@ -1,0 +1,122 @@
+"""GPU parity and accuracy of the 2D cut-off-ring option (ring_interp = 1): K interpolated for
+near targets in the ring r_lo < r < r_hi around eps < r < 2 eps, through a list the gather
+fills and a second pass.
+
+Bars as for the other paths: complex128 <= 1e-10, complex64 <= 1e-5 in the parity measure
+max_i |g_i - o_i| / max(|o_i|, RMS |o|).
+"""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import highorder2d as ho
+from oracle import truth
+from paper_1801_05977_amd import qpgf, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qpgf.C128: 1e-10, qpgf.C64: 1e-5}
+K, AL = 2.1, 0.3
+
+
+def parity(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    s = np.sqrt(np.mean(np.abs(o) ** 2))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), s)))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _ring_dense(n, seed):
+    """Targets around the lattice points (0, 0) and (2 pi n, 0) at r in [0.1, 0.55]: most of them in
+    the ring, some on either side of it, both signs of x1 and x2."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.1, 0.55, n)
+    th = rng.uniform(0, 2 * math.pi, n)
+    shift = 2 * math.pi * rng.integers(-2, 3, n)
+    return np.column_stack([r * np.cos(th) + shift, r * np.sin(th)])
+
+
+def _edge_targets():
+    return np.array([[0.0, 0.0], [np.nan, 0.1], [0.5, np.inf], [1.0, 1.5], [0.2, 0.0], [0.0, -0.2],
+                     [0.2 + 1e-12, 0.0], [0.41, 0.0], [0.0, 0.43], [1e-3, 1e-3]], dtype=np.float64)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001)])
+def test_ring_end_to_end(prec, order, shape, T):
+    M1, M2 = shape
+    x = np.vstack([workloads.targets(T, 2, seed=7), _ring_dense(3000, seed=8), _edge_targets()])
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2, sing_order=order, ring_interp=1)
+    flags = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    g = P(K, AL, 0.0, dev(x), flags=flags).cpu().numpy()
+    f = flags.cpu().numpy()
+    bad = (f & 13) != 0
+    assert np.all(np.isnan(g[bad]))
+    o = ho.eval_g2d_ho(K, AL, x[~bad], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, order, ring=True)
+    assert parity(g[~bad], o) <= TOL[prec]
+    # every other target is the plain plan's result, bit for bit; the flags are the same
+    P0 = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2, sing_order=order)
+    f0 = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    g0 = P0(K, AL, 0.0, dev(x), flags=f0).cpu().numpy()
+    np.testing.assert_array_equal(f, f0.cpu().numpy())
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    lo, hi = ho.ring_bounds(math.pi / (M1 // 2), 1.0 / (M2 // 2))
+    r = np.sqrt(t * t + x[:, 1] ** 2)
+    away = ~bad & ~((r > lo * (1 - 1e-12)) & (r < hi * (1 + 1e-12)))
+    assert away.sum() > 500 and (~away & ~bad).sum() > 500
+    np.testing.assert_array_equal(g[away], g0[away])
+
+
+def test_ring_accuracy_against_the_series():
+    """complex128, 512 x 256: the ring's worst error against (1.2), with and without the option."""
+    x = _ring_dense(150, seed=5)
+    x = x[(np.abs(x[:, 1]) >= 0.02) & (np.abs(x[:, 1]) <= 0.6)]
+    gt = truth.g2d(K, AL, x)
+    err = {}
+    for ring in (0, 1):
+        P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C128, 512, 256, sing_order=3, ring_interp=ring)
+        err[ring] = np.max(np.abs(P(K, AL, 0.0, dev(x)).cpu().numpy() - gt) / np.abs(gt))
+        P.close()
+    assert err[0] > 1e-5
+    assert err[1] < 3e-6 and err[1] < err[0] / 100
+
+
+def test_ring_many_targets_sampled():
+    """1e6 uniform targets, complex64, 1024 x 128 (the list holds about 4 % of them): sampled
+    outputs against the oracle."""
+    T = 1_000_000
+    x = workloads.targets(T, 2, seed=0)
+    P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C64, 1024, 128, sing_order=3, ring_interp=1)
+    g = P(K, AL, 0.0, dev(x)).cpu().numpy()
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    r = np.hypot(t, x[:, 1])
+    ring = np.nonzero((r > 0.2) & (r < 0.45))[0]
+    assert len(ring) > 20000
+    rng = np.random.default_rng(1)
+    pick = np.concatenate([rng.choice(ring, 300, replace=False), rng.choice(T, 300, replace=False)])
+    o = ho.eval_g2d_ho(K, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, 3, ring=True)
+    assert parity(g[pick], o) <= TOL[qpgf.C64]
+    # a second, smaller call on the same plan reuses the list
+    g2 = P(K, AL, 0.0, dev(x[:5000])).cpu().numpy()
+    np.testing.assert_array_equal(g2, g[:5000])
+
+
+def test_ring_parameter_checks():
+    L = qpgf.lib()
+    for kind, dims, ring in ((qpgf.KIND_G2D, (64, 32, 0), 2), (qpgf.KIND_GD3D, (32, 32, 16), 1),
+                             (qpgf.KIND_G2D_GRAD, (64, 32, 0), 1)):
+        p = qpgf.default_params(kind, qpgf.C128, *dims, ring_interp=ring)
+        h = ctypes.c_void_p()
+        assert L.qpgf_plan_create(ctypes.byref(p), ctypes.byref(h)) == 1, (kind, ring)
+    P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C64, 256, 64, ring_interp=1)
+    x = dev(workloads.targets(100, 2, seed=1))
+    with pytest.raises(qpgf.QpgfError):
+        P.batched([K], [AL], [256], [0, 100], x)
