@@ -25,9 +25,12 @@ struct GArgs {
   long fs, ffs;            // field strides (near, far)
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
   int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
-  // 2D G, ring_interp: near targets with eps < r < ring_hi are appended to ring_idx
+  // 2D G, ring_interp: near targets with ring_lo < r < ring_hi are collected into kRingLists
+  // lists (wave w appends to list w mod kRingLists: ring_idx[list * ring_cap ..], its length in
+  // ring_cnt[list * kRingPad])
   uint32_t* ring_cnt;
   uint32_t* ring_idx;
+  long ring_cap;
   double ring_lo, ring_hi;
 };
 
@@ -763,23 +766,31 @@ __device__ __forceinline__ void stencil2d_fields(const cplx<T>* __restrict__ g, 
     stencil2d_multi<T, NF>(g, rows, i0, M1, w1, w2, L);
 }
 
-// One target of Algorithm 2.1 step 2.
-// Append target i to the ring list when take is set: one atomic per wave (ballot, prefix count).
-// Called with the whole wave's active lanes together.
-__device__ __forceinline__ void ring_append(uint32_t* __restrict__ cnt, uint32_t* __restrict__ idx, bool take,
-                                            long i) {
+// Ring lists: wave w appends to list w mod kRingLists, so the appends of the launch spread over
+// that many counters (each on its own 128-byte line) instead of contending for one, and a list
+// never holds more than 64 entries per wave it serves.
+constexpr int kRingLists = 256;
+constexpr int kRingPad = 32;
+static_assert(kRingLists == 256, "k_ring2d scans the list lengths with one thread per list");
+
+// Append target i when take is set: one atomic per wave (ballot, prefix count).  Called with the
+// whole wave's active lanes together.
+__device__ __forceinline__ void ring_append(const GArgs& A, bool take, long i) {
   const unsigned long long m = __ballot(take);
   if (m == 0) return;
+  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int list = (int)(wave & (kRingLists - 1));
   const int lane = __lane_id();
   const int leader = __ffsll((long long)m) - 1;
   uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+  if (lane == leader) base = atomicAdd(A.ring_cnt + list * kRingPad, (uint32_t)__popcll(m));
   base = __shfl(base, leader);
-  if (take) idx[base + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+  if (take) A.ring_idx[(size_t)list * A.ring_cap + base + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
 }
 
+// One target of Algorithm 2.1 step 2; returns whether it lies in the cut-off ring.
 template <typename T>
-__device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+__device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                              const cplx<T>* __restrict__ far, const double* __restrict__ x, long i,
                                              cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
@@ -855,7 +866,7 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
   }
   store_out<T>(out, i, res);
   if (flags) flags[i] = fl;
-  if (A.ring_idx) ring_append(A.ring_cnt, A.ring_idx, in_ring, i);
+  return in_ring;
 }
 
 // The cut-off ring (ring_interp): for the collected targets (r_lo < r < r_hi, every stencil node at
@@ -863,7 +874,8 @@ __device__ __forceinline__ void gather2d_one(const GArgs& A, const cplx<T>* __re
 // nodes replaces f Y at the target, so that the result is the interpolant of K = L + f Y:
 // out += e^{i alpha x1} (sum_ab w_a w_b (f Y)(node_ab) - (f Y)(target)), f the removed singular
 // part of the plan's order and a node's position its offset (p1 h1, p2 h2) from the lattice
-// point.  FP64 throughout; a grid-stride loop over the list (its length is read on the device).
+// point.  FP64 throughout; a grid-stride loop over the lists' entries, numbered through in list
+// order (each block scans the kRingLists lengths in LDS first).
 __device__ __forceinline__ double2 fy_removed(const GArgs& A, double t, double z) {
   const double r2 = t * t + z * z;
   const double r = sqrt(r2);
@@ -880,12 +892,28 @@ __device__ __forceinline__ double2 fy_removed(const GArgs& A, double t, double z
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x,
-                                                const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ idx,
-                                                cplx<T>* __restrict__ out) {
-  const uint32_t n = *cnt;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    const long i = idx[j];
+__global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x, cplx<T>* __restrict__ out) {
+  __shared__ uint32_t s_off[kRingLists + 1];
+  const int tid = threadIdx.x;
+  s_off[tid + 1] = A.ring_cnt[tid * kRingPad];
+  if (tid == 0) s_off[0] = 0;
+  __syncthreads();
+  for (int d = 1; d < kRingLists; d <<= 1) {
+    const uint32_t v = tid >= d ? s_off[tid + 1 - d] : 0u;
+    __syncthreads();
+    s_off[tid + 1] += v;
+    __syncthreads();
+  }
+  const uint32_t n = s_off[kRingLists];
+  for (uint32_t j = blockIdx.x * blockDim.x + tid; j < n; j += gridDim.x * blockDim.x) {
+    // the list holding entry j: the last list whose first entry is at or before j
+    int lo = 0, hi = kRingLists - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    const long i = A.ring_idx[(size_t)lo * A.ring_cap + (j - s_off[lo])];
     const double x1 = x[2 * i], x2 = x[2 * i + 1];
     double n1;
     const double t = reduce_cell(x1, n1);
@@ -917,7 +945,8 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
                                                   long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < T_) gather2d_one<T>(A, grid, far, x, i, out, flags);
+  const bool in_ring = i < T_ && gather2d_one<T>(A, grid, far, x, i, out, flags);
+  if (A.ring_idx) ring_append(A, in_ring, i);
 }
 
 // One target of the 2D gradient (Section 2.4.1): both fields interpolated with one
@@ -1360,6 +1389,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.sing_order = P.p.sing_order;
   A.ring_cnt = nullptr;
   A.ring_idx = nullptr;
+  A.ring_cap = 0;
   // the ring zone r_lo < r < r_hi: r_hi = 2 eps + 2 sqrt(2) h, beyond which every stencil node has
   // Y = 0; r_lo = max(eps, eps/2 + 2 sqrt(2) h) keeps every node at least eps/2 from the lattice point
   const double reach = 2.0 * sqrt(2.0) * fmax(A.h1, A.h2);
@@ -1390,12 +1420,14 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
       if (e != hipSuccess) return e;
       A.ring_cnt = P.ring_cnt;
       A.ring_idx = P.ring_idx;
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.stream, P.ring_cnt, 1L);
+      A.ring_cap = (long)P.ring_cap;
+      hipLaunchKernelGGL(k_zero_u32, dim3(kRingLists * kRingPad / 256), dim3(256), 0, P.stream, P.ring_cnt,
+                         (long)kRingLists * kRingPad);
       hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
       const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
-      hipLaunchKernelGGL(k_ring2d<T>, dim3(nb), dim3(256), 0, P.stream, A, x, P.ring_cnt, P.ring_idx, o);
+      hipLaunchKernelGGL(k_ring2d<T>, dim3(nb), dim3(256), 0, P.stream, A, x, o);
     }
     return hipGetLastError();
   }
@@ -1576,13 +1608,20 @@ hipError_t launch_interleave2d(Plan& P) {
 
 hipError_t ensure_ring_scratch(Plan& P, int64_t T_) {
   hipError_t e;
-  if (!P.ring_cnt && (e = hipMalloc(reinterpret_cast<void**>(&P.ring_cnt), sizeof(uint32_t))) != hipSuccess) return e;
-  if (T_ > P.ring_cap) {
+  if (!P.ring_cnt &&
+      (e = hipMalloc(reinterpret_cast<void**>(&P.ring_cnt), (size_t)kRingLists * kRingPad * sizeof(uint32_t))) !=
+          hipSuccess)
+    return e;
+  // list l serves the waves w = l mod kRingLists: at most ceil(waves / kRingLists) of them
+  const int64_t cap = ((T_ + 63) / 64 + kRingLists - 1) / kRingLists * 64;
+  if (cap > P.ring_cap) {
     if (P.ring_idx) (void)hipFree(P.ring_idx);
     P.ring_idx = nullptr;
     P.ring_cap = 0;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.ring_idx), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
-    P.ring_cap = T_;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P.ring_idx), (size_t)cap * kRingLists * sizeof(uint32_t))) !=
+        hipSuccess)
+      return e;
+    P.ring_cap = cap;
   }
   return hipSuccess;
 }
@@ -1649,6 +1688,7 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.sing_order = P.p.sing_order;
   A.ring_cnt = nullptr;
   A.ring_idx = nullptr;
+  A.ring_cap = 0;
   A.ring_lo = A.ring_hi = 0.0;
   I.off = off;
   I.foff = foff;

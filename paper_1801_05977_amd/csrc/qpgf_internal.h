@@ -156,8 +156,8 @@ struct Plan {
   uint32_t* bin_hist = nullptr;
   uint32_t* bin_offs = nullptr;
   uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
-  uint32_t* ring_cnt = nullptr;        // 2D G, ring_interp: targets collected for the ring pass
-  uint32_t* ring_idx = nullptr;
+  uint32_t* ring_idx = nullptr;        // 2D G, ring_interp: targets collected for the ring pass in
+  uint32_t* ring_cnt = nullptr;        // several lists, ring_cap entries each, and their lengths
   int64_t ring_cap = 0;
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count

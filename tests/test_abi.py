@@ -59,6 +59,7 @@ def test_params_default_values():
     ("far_h", 0.0, 1), ("kind", 9, 1), ("prec", 5, 1), ("sing_order", 0, 1), ("sing_order", 4, 1),
     ("sing_order", 2, 1),     # above 1 only for the 2D G (this plan is 3D)
     ("ring_interp", 2, 1), ("ring_interp", 1, 1),
+    ("special_tol", 0.79, 1),  # at most two special coefficients per pencil needs special_tol < pi / (4 c~)
 ])
 def test_plan_create_rejects_bad_params(field, value, status):
     L = qpgf.lib()
