@@ -48,6 +48,12 @@ from .method import (ORACLE_Q, _far_stencil, _reduce, _stencil, dft_matrix, far_
 from .truth import beta
 
 
+def ring_zone(t, z, h1, h2, eps=co.EPS):
+    """The cut-off ring of the ``ring`` option, as for G (``highorder2d.ring_zone``)."""
+    from .highorder2d import ring_zone as rz
+    return rz(t, z, h1, h2, eps)
+
+
 # ----------------------------------------------------------------------------
 # the singular parts h1, h2
 # ----------------------------------------------------------------------------
@@ -149,8 +155,14 @@ def far_grids_grad_2d(k, alpha, N1, z):
 # evaluation
 # ----------------------------------------------------------------------------
 
-def eval_g2d_grad(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q):
-    """(dG/dx1, dG/dx2) at targets x[T,2] as [T, 2] (NaN beyond the far slab)."""
+def eval_g2d_grad(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q,
+                  ring=False):
+    """(dG/dx1, dG/dx2) at targets x[T,2] as [T, 2] (NaN beyond the far slab).
+
+    ``ring``: in the cut-off ring (``highorder2d.ring_zone``) the stencil interpolates
+    K_p = L_p + h_p at its nodes instead of L_p, and nothing is added back there (the same
+    reading of Remark 5.6 as for G: L_p carries the steep transition of Y_eps times the 1/r
+    and logarithmic terms of h_p, K_p is smooth in the ring)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2 = 2 * N1, 2 * N2
     h1, h2 = math.pi / N1, c_tilde / N2
@@ -166,10 +178,20 @@ def eval_g2d_grad(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE,
         i1, w1 = _stencil((tn + math.pi) / h1, M1)
         i2, w2 = _stencil((zn + c_tilde) / h2, M2)
         hs = h_grad(k, alpha, tn, zn, eps)
+        zone = ring_zone(tn, zn, h1, h2, eps) if ring else np.zeros(len(tn), dtype=bool)
+        if zone.any():
+            # node offsets from the lattice point: base index floor(t / h) - 1 + a
+            p1 = np.floor(tn[zone] / h1)[:, None] - 1 + np.arange(4)
+            p2 = np.floor(zn[zone] / h2)[:, None] - 1 + np.arange(4)
+            hn = h_grad(k, alpha, (p1 * h1)[:, :, None] + 0 * p2[:, None, :],
+                        (p2 * h2)[:, None, :] + 0 * p1[:, :, None], eps)
         for p in range(2):
             vals = grids[p][i1[:, :, None], i2[:, None, :]]
             L = np.einsum("ta,tb,tab->t", w1, w2, vals)
-            out[near, p] = phase[near] * (L + hs[p])
+            g = L + hs[p]
+            if zone.any():
+                g[zone] = np.einsum("ta,tb,tab->t", w1[zone], w2[zone], vals[zone] + hn[p])
+            out[near, p] = phase[near] * g
     far = ~near
     if far.any():
         zf = far_slices(far_h, far_S, c)

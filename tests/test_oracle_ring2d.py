@@ -67,3 +67,32 @@ def test_ring_accuracy_against_the_series():
     assert err[True, 256] < err[False, 256] / 100
     assert err[True, 256] < 5e-6
     assert err[True, 256] < err[True, 128] / 10
+
+
+# ----------------------------------------------------------------------------- the gradient (Section 2.4.1)
+
+def test_grad_ring_agrees_with_plain_form_at_grid_nodes():
+    from oracle import grad2d
+    N1, N2 = 64, 32
+    h1, h2 = math.pi / N1, 1.0 / N2
+    p = np.array([[5, 4], [-6, 5], [3, -9], [-2, -10], [7, 2]])
+    x = p * [h1, h2]
+    a = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, 17)
+    b = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, 17, ring=True)
+    assert np.all(ho.ring_zone(x[:, 0], x[:, 1], h1, h2))
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+
+
+def test_grad_ring_accuracy_against_the_series():
+    from oracle import grad2d
+    x = _ring_targets(120, seed=6, lo=0.15, hi=0.5)
+    x = x[np.abs(x[:, 1]) <= 0.6]
+    gt = truth.g2d_grad(K, AL, x)
+    err = {}
+    for ring in (False, True):
+        for N1, N2 in ((128, 64), (256, 128)):
+            g = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, ring=ring)
+            err[ring, N1] = np.max(np.abs(g - gt) / np.abs(gt))
+    assert err[True, 256] < err[False, 256] / 15
+    assert err[True, 256] < 5e-5
+    assert err[True, 256] < err[True, 128] / 8
