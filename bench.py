@@ -369,6 +369,15 @@ def run_g2d_grad(args):
         P(2.1, 0.3, 0.0, x, out)
     torch.cuda.synchronize()
     kern = {k_: round(v[0] / v[1], 5) for k_, v in P.timing().items() if v[1]}
+    # the same step with the cut-off ring interpolated (ring_interp), beside
+    Pr = qpgf.Plan(qpgf.KIND_G2D_GRAD, prec, M1, M2, ring_interp=1)
+    tr = _timed(lambda: Pr(2.1, 0.3, 0.0, x, out), args.steps, args.warmup)
+    Pr.enable_timing(True)
+    for _ in range(args.steps):
+        Pr(2.1, 0.3, 0.0, x, out)
+    torch.cuda.synchronize()
+    kern_r = {k_: round(v[0] / v[1], 5) for k_, v in Pr.timing().items() if v[1]}
+    Pr.close()
     esize = 8 if prec == qpgf.C64 else 16
     # gather: 16 B in, two results and a flag byte out per target, both near fields and far slabs once
     grid_bytes = 2 * (P.info.grid_bytes + P.info.far_grid_bytes)
@@ -380,6 +389,7 @@ def run_g2d_grad(args):
             "config": {"workload": "g2d gradient k=2.1 alpha=0.3", "x1_modes": M1, "slices": M2, "targets": T,
                        "method": "plain"},
             "kernels_avg_ms": kern,
+            "ring_interp_1": {"ms_per_step": tr * 1e3, "kernels_avg_ms": kern_r},
             "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}
 

@@ -891,7 +891,22 @@ __device__ __forceinline__ double2 fy_removed(const GArgs& A, double t, double z
   return mk(s * pr, s * pim);
 }
 
-template <typename T>
+// The gradient's singular parts (Section 2.4.1) at cell point (t, z), zero beyond 2 eps:
+// h_p = -(Y/2pi) [ -(k^2/2) x_p ln r + x_p/r^2 - i alpha t x_p/r^2 - (alpha^2/2) t^2 x_p/r^2 ],
+// x_1 = t, x_2 = z.
+__device__ __forceinline__ void hgrad_at(const GArgs& A, double t, double z, double2& h1, double2& h2) {
+  const double r2 = t * t + z * z;
+  h1 = h2 = mk(0.0, 0.0);
+  if (!(r2 < 4.0 * A.eps * A.eps) || r2 == 0.0) return;
+  const double r = sqrt(r2), ir2 = 1.0 / r2;
+  const double c = -cut_Y(r, A.eps) / (2.0 * kPi);
+  const double re = -0.5 * A.k * A.k * log(r) + ir2 - 0.5 * A.a1 * A.a1 * t * t * ir2;
+  const double im = -A.a1 * t * ir2;
+  h1 = mk(c * re * t, c * im * t);
+  h2 = mk(c * re * z, c * im * z);
+}
+
+template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x, cplx<T>* __restrict__ out) {
   __shared__ uint32_t s_off[kRingLists + 1];
   const int tid = threadIdx.x;
@@ -921,22 +936,35 @@ __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restric
     double w1[4], w2[4];
     lag4<double>(u - p, w1);
     lag4<double>(u2 - p2, w2);
-    double2 acc = mk(0.0, 0.0);
+    // NF = 1: f Y of the 2D G; NF = 2: the gradient's h1, h2
+    double2 acc[NF], at[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = mk(0.0, 0.0);
     for (int b = 0; b < 4; ++b) {
       const double zn = (p2 - 1.0 + b) * A.h2;
-      double2 row = mk(0.0, 0.0);
+      double2 row[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) row[f] = mk(0.0, 0.0);
       for (int a = 0; a < 4; ++a) {
-        const double2 f = fy_removed(A, (p - 1.0 + a) * A.h1, zn);
-        row = mk(fma(w1[a], f.x, row.x), fma(w1[a], f.y, row.y));
+        double2 v[NF];
+        if constexpr (NF == 1) v[0] = fy_removed(A, (p - 1.0 + a) * A.h1, zn);
+        else hgrad_at(A, (p - 1.0 + a) * A.h1, zn, v[0], v[1]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) row[f] = mk(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
       }
-      acc = mk(fma(w2[b], row.x, acc.x), fma(w2[b], row.y, acc.y));
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f] = mk(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
     }
-    const double2 d = csub(acc, fy_removed(A, t, x2));
+    if constexpr (NF == 1) at[0] = fy_removed(A, t, x2);
+    else hgrad_at(A, t, x2, at[0], at[1]);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
-    const double2 corr = cmul(mk(pc, ps), d);
-    const cplx<T> o = out[i];
-    store_out<T>(out, i, mk((double)o.x + corr.x, (double)o.y + corr.y));
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double2 corr = cmul(mk(pc, ps), csub(acc[f], at[f]));
+      const cplx<T> o = out[i * NF + f];
+      store_out<T>(out, i * NF + f, mk((double)o.x + corr.x, (double)o.y + corr.y));
+    }
   }
 }
 
@@ -953,12 +981,14 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
 // stencil, the singular parts h1, h2 added back in FP64 inside 2 eps, the phase
 // e^{i alpha x1}; beyond c the differentiated far slab, the x2 field times sgn(x2).
 // grid and far hold the two fields interleaved per node.  out[2i] = dG/dx1, out[2i+1] = dG/dx2.
+// Returns whether the target lies in the cut-off ring (when the plan collects them).
 template <typename T>
-__device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+__device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
                                                   long i, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
   uint8_t fl = 0;
+  bool in_ring = false;
   double2 d1, d2;
   if (!(isfinite(x1) && isfinite(x2))) {
     fl = 8;
@@ -1008,15 +1038,17 @@ __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>*
         if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
           fl |= 1;
           L1 = L2 = nan2();
-        } else if (r2 < 4.0 * A.eps * A.eps) {
-          // h_p = -(Y/2pi) [ -(k^2/2) x_p ln r + x_p/r^2 - i alpha t x_p/r^2 - (alpha^2/2) t^2 x_p/r^2 ],
-          // x_1 = t, x_2 = x2 (the cell coordinates of the target)
-          const double r = sqrt(r2), ir2 = 1.0 / r2;
-          const double c = -cut_Y(r, A.eps) / (2.0 * kPi);
-          const double re = -0.5 * A.k * A.k * log(r) + ir2 - 0.5 * A.a1 * A.a1 * t * t * ir2;
-          const double im = -A.a1 * t * ir2;
-          L1 = cadd(L1, mk(c * re * t, c * im * t));
-          L2 = cadd(L2, mk(c * re * x2, c * im * x2));
+        } else {
+          if (r2 < 4.0 * A.eps * A.eps) {
+            double2 h1, h2;
+            hgrad_at(A, t, x2, h1, h2);
+            L1 = cadd(L1, h1);
+            L2 = cadd(L2, h2);
+          }
+          if (A.ring_idx) {
+            const double r = sqrt(r2);
+            in_ring = r > A.ring_lo && r < A.ring_hi;
+          }
         }
       } else if (x2 < 0.0) {
         L2 = cscale(L2, -1.0);
@@ -1028,6 +1060,7 @@ __device__ __forceinline__ void gather2d_grad_one(const GArgs& A, const cplx<T>*
   store_out<T>(out, 2 * i, d1);
   store_out<T>(out, 2 * i + 1, d2);
   if (flags) flags[i] = fl;
+  return in_ring;
 }
 
 template <typename T>
@@ -1036,7 +1069,8 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
                                                        long T_, cplx<T>* __restrict__ out,
                                                        uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < T_) gather2d_grad_one<T>(A, grid, far, x, i, out, flags);
+  const bool in_ring = i < T_ && gather2d_grad_one<T>(A, grid, far, x, i, out, flags);
+  if (A.ring_idx) ring_append(A, in_ring, i);
 }
 
 // One target of the second-derivative differences (Section 2.4.2): three fields with one
@@ -1408,7 +1442,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     KernelTimer t(P, QPGF_T_GATHER);
     const auto* gi = static_cast<const cplx<T>*>(P.gridI);
     const auto* fi = static_cast<const cplx<T>*>(P.farI);
-    if (P.nf == 2)
+    if (P.nf == 2 && !P.p.ring_interp)
       hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
     else if (P.nf == 3)
       hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
@@ -1423,11 +1457,17 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
       A.ring_cap = (long)P.ring_cap;
       hipLaunchKernelGGL(k_zero_u32, dim3(kRingLists * kRingPad / 256), dim3(256), 0, P.stream, P.ring_cnt,
                          (long)kRingLists * kRingPad);
-      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+      if (P.nf == 2)
+        hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
+      else
+        hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
       const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
-      hipLaunchKernelGGL(k_ring2d<T>, dim3(nb), dim3(256), 0, P.stream, A, x, o);
+      if (P.nf == 2)
+        hipLaunchKernelGGL((k_ring2d<T, 2>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
+      else
+        hipLaunchKernelGGL((k_ring2d<T, 1>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
     }
     return hipGetLastError();
   }
