@@ -14,6 +14,7 @@ import pytest
 import torch
 
 from oracle import grad2d, hess2d, method, truth
+from oracle import highorder2d as ho
 from paper_1801_05977_amd import qpgf, workloads
 
 pytestmark = pytest.mark.gpu
@@ -69,6 +70,27 @@ def test_special_2d_accuracy_vs_series():
     e = np.abs(g - gt) / np.abs(gt)
     # as accurate as at a regular k (the oracle: p50 4.7e-8, max 1.2e-3 here; 2.5e-8, 1.0e-3 at k = 2.1)
     assert np.median(e) < 2e-7 and e.max() < 5e-3
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_special_2d_with_higher_order_and_ring(prec):
+    """The special epilogue also subtracts the higher-order tables; the ring pass is unaffected."""
+    M1, M2 = 128, 64
+    x = np.vstack([workloads.targets(3_001, 2, seed=24), [[0.25, 0.1], [0.3, -0.15], [-0.2, 0.25]]])
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2, sing_order=3, ring_interp=1)
+    P.prepare(K2S, AL, 0.0, stage=0)
+    if prec == qpgf.C128:
+        g = np.fft.fftshift(P.field().cpu().numpy().reshape(M2, M1).T, axes=(0, 1))
+        ref = A2 * ho.lhat_ho(K2S, AL, M1 // 2, M2 // 2, 3)
+        assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max()
+    g = P(K2S, AL, 0.0, dev(x)).cpu().numpy()
+    o = ho.eval_g2d_ho(K2S, AL, x, M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, 3, ring=True)
+    assert parity(g, o) <= TOL[prec]
+    Pg = qpgf.Plan(qpgf.KIND_G2D_GRAD, prec, M1, M2, ring_interp=1)
+    g = Pg(K2S, AL, 0.0, dev(x)).cpu().numpy()
+    o = grad2d.eval_g2d_grad(K2S, AL, x, M1 // 2, M2 // 2, Pg.info.far_h, Pg.info.far_slices, ring=True)
+    for p in range(2):
+        assert parity(g[:, p], o[:, p]) <= TOL[prec]
 
 
 def test_special_2d_derivative_kinds():
