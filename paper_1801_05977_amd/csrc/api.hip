@@ -273,8 +273,8 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
         HIP_TRY(launch_fft(P, P.far, P.M2, P.M1, (long)P.M1 * P.S * nf, P.M1, 1, (long)P.M1 * P.M2));
       HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)(P.dim == 3 ? P.M2 : 1) * P.S * nf, 1, 0, P.M1));
     }
-    if (P.dim == 2 && nf > 1) {
-      // the gather reads all fields of a stencil row as one contiguous run
+    if (P.dim == 2 && P.gridI) {
+      // the gather reads a stencil row (of all fields) as one contiguous, aligned run
       KernelTimer t(P, QPGF_T_LAYOUT);
       HIP_TRY(launch_interleave2d(P));
     }
@@ -380,9 +380,12 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
 
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
   PLAN_TRY(hipMalloc(&P.far, P.nf * P.nfar * P.esize));
-  if (P.dim == 2 && P.nf > 1) {
-    PLAN_TRY(hipMalloc(&P.gridI, P.nf * P.ncell * P.esize));
-    PLAN_TRY(hipMalloc(&P.farI, P.nf * P.nfar * P.esize));
+  if (P.dim == 2 && (P.nf > 1 || P.p.prec == QPGF_C64)) {
+    // derivative kinds: the fields interleaved per node; the complex64 G: each node's quad of
+    // x1-neighbours (4 values, 32 bytes)
+    const size_t per = P.nf > 1 ? (size_t)P.nf : 4;
+    PLAN_TRY(hipMalloc(&P.gridI, per * P.ncell * P.esize));
+    PLAN_TRY(hipMalloc(&P.farI, per * P.nfar * P.esize));
   }
 
   const int Q = p->quad_q;

@@ -25,6 +25,7 @@ struct GArgs {
   long fs, ffs;            // field strides (near, far)
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
   int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
+  int quad;                // 2D G, complex64: grid and far are node quads (4 x1-neighbours per node)
   // 2D G, ring_interp: near targets with ring_lo < r < ring_hi are collected into kRingLists
   // lists (wave w appends to list w mod kRingLists: ring_idx[list * ring_cap ..], its length in
   // ring_cnt[list * kRingPad])
@@ -672,32 +673,60 @@ __device__ __forceinline__ double2 stencil2d(const cplx<T>* __restrict__ g, cons
 struct __attribute__((aligned(8))) F4a8 {
   float a, b, c, d;
 };
-// sum_a w[a] r[a] over the 4 nodes at r
+// sum_a w[a] v[a] in a fixed order (every complex64 row sum takes it, so that the contiguous,
+// the wrapped and the node-quad forms of a row give the same bits)
+__device__ __forceinline__ float2 row4v(float2 v0, float2 v1, float2 v2, float2 v3, const float w[4]) {
+  float re = w[0] * v0.x, im = w[0] * v0.y;
+  re = fmaf(w[1], v1.x, re);
+  im = fmaf(w[1], v1.y, im);
+  re = fmaf(w[2], v2.x, re);
+  im = fmaf(w[2], v2.y, im);
+  re = fmaf(w[3], v3.x, re);
+  im = fmaf(w[3], v3.y, im);
+  return make_float2(re, im);
+}
+// sum_a w[a] r[a] over the 4 contiguous nodes at r
 __device__ __forceinline__ float2 row4(const float2* __restrict__ r, const float w[4]) {
   const F4a8 lo = *reinterpret_cast<const F4a8*>(r);
   const F4a8 hi = *reinterpret_cast<const F4a8*>(r + 2);
-  float re = w[0] * lo.a, im = w[0] * lo.b;
-  re = fmaf(w[1], lo.c, re);
-  im = fmaf(w[1], lo.d, im);
-  re = fmaf(w[2], hi.a, re);
-  im = fmaf(w[2], hi.b, im);
-  re = fmaf(w[3], hi.c, re);
-  im = fmaf(w[3], hi.d, im);
-  return make_float2(re, im);
+  return row4v(make_float2(lo.a, lo.b), make_float2(lo.c, lo.d), make_float2(hi.a, hi.b), make_float2(hi.c, hi.d),
+               w);
 }
 
 template <>
 __device__ __forceinline__ double2 stencil2d<float>(const float2* __restrict__ g, const long rows[4], int i0, int M1,
                                                     const float w1[4], const float w2[4]) {
-  if (i0 > M1 - 4) return stencil2d_scalar<float>(g, rows, i0, M1, w1, w2);
   float2 rs[4];
+  if (i0 > M1 - 4) {
+    // the row wraps in x1: four single loads, the same sums
 #pragma unroll
-  for (int b = 0; b < 4; ++b) rs[b] = row4(g + rows[b] + i0, w1);
+    for (int b = 0; b < 4; ++b)
+      rs[b] = row4v(g[rows[b] + i0], g[rows[b] + ((i0 + 1) & (M1 - 1))], g[rows[b] + ((i0 + 2) & (M1 - 1))],
+                    g[rows[b] + ((i0 + 3) & (M1 - 1))], w1);
+  } else {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rs[b] = row4(g + rows[b] + i0, w1);
+  }
   float re = 0.f, im = 0.f;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     re = fmaf(w2[b], rs[b].x, re);
     im = fmaf(w2[b], rs[b].y, im);
+  }
+  return mk(re, im);
+}
+
+// complex64 node quads (q[4 node + a] = node + a along x1, wrapped): a stencil row is one
+// 32-byte aligned run, so each row costs one memory sector instead of one or two, and rows
+// that wrap in x1 need no special case.
+__device__ __forceinline__ double2 stencil2d_quad(const float2* __restrict__ q, const long rows[4], int i0,
+                                                  const float w1[4], const float w2[4]) {
+  float re = 0.f, im = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const float2 r = row4(q + (rows[b] + i0) * 4, w1);
+    re = fmaf(w2[b], r.x, re);
+    im = fmaf(w2[b], r.y, im);
   }
   return mk(re, im);
 }
@@ -837,7 +866,13 @@ __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __re
     if (bad) {
       res = nan2();
     } else {
-      double2 Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
+      double2 Lt;
+      if constexpr (sizeof(T) == 4) {
+        if (A.quad) Lt = stencil2d_quad(g, rows, i0, w1, w2);
+        else Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
+      } else {
+        Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
+      }
       if (is_near) {
         const double r = sqrt(t * t + x2 * x2);
         if (r <= A.rmin || r == 0.0) {
@@ -1386,6 +1421,19 @@ __global__ __launch_bounds__(256) void k_interleave(const cplx<T>* __restrict__ 
   out[e] = in[f * n + node];
 }
 
+// Node quads of a complex64 2D grid or far slab with rows of M1 nodes: q[4 e + a] = in[row of e,
+// x1 index of e + a, wrapped] (one thread per output value: coalesced writes).
+__global__ __launch_bounds__(256) void k_quads(const float2* __restrict__ in, float2* __restrict__ q, long n,
+                                               int M1) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= 4 * n) return;
+  const long e = v >> 2;
+  const int a = (int)(v & 3);
+  const long row = e / M1;
+  const int i1 = (int)(e - row * M1);
+  q[v] = in[row * M1 + ((i1 + a) & (M1 - 1))];
+}
+
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
 
 template <typename T>
@@ -1421,6 +1469,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.ffs = (long)P.nfar;
   A.smooth = smooth;
   A.sing_order = P.p.sing_order;
+  A.quad = P.dim == 2 && P.nf == 1 && P.gridI != nullptr;
   A.ring_cnt = nullptr;
   A.ring_idx = nullptr;
   A.ring_cap = 0;
@@ -1447,7 +1496,8 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     else if (P.nf == 3)
       hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
     else if (!P.p.ring_interp)
-      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
+                         (long)T_, o, flags);
     else {
       if (T_ > (int64_t)UINT32_MAX) return hipErrorInvalidValue;   // the ring list holds 32-bit indices
       hipError_t e = ensure_ring_scratch(P, T_);
@@ -1460,7 +1510,8 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
       if (P.nf == 2)
         hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
       else
-        hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+        hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
+                           (long)T_, o, flags);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
       const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
@@ -1629,7 +1680,18 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 }  // namespace
 
 hipError_t launch_interleave2d(Plan& P) {
-  if (P.dim != 2 || P.nf < 2 || !P.gridI || !P.farI) return hipErrorInvalidValue;
+  if (P.dim != 2 || !P.gridI || !P.farI) return hipErrorInvalidValue;
+  if (P.nf == 1) {
+    // complex64 G: node quads of the near grid and of the far slab
+    if (P.esize != 8) return hipErrorInvalidValue;
+    auto quads = [&](const void* in, void* out, long n) {
+      hipLaunchKernelGGL(k_quads, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, P.stream,
+                         static_cast<const float2*>(in), static_cast<float2*>(out), n, P.M1);
+    };
+    quads(P.grid, P.gridI, (long)P.ncell);
+    quads(P.far, P.farI, (long)P.nfar);
+    return hipGetLastError();
+  }
   auto go = [&](auto tag, const void* in, void* out, long n) {
     using T = decltype(tag);
     const long tot = n * P.nf;
@@ -1726,6 +1788,8 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.ffs = (long)M1 * P.S;
   A.smooth = 0;
   A.sing_order = P.p.sing_order;
+  A.quad = 0;   // the batched graph keeps the instances' grids row by row (node quads of all
+                // instances cost more than they save: four times the grids no longer stay in L2)
   A.ring_cnt = nullptr;
   A.ring_idx = nullptr;
   A.ring_cap = 0;

@@ -133,8 +133,8 @@ struct Plan {
   int twlog2 = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
-  void* gridI = nullptr;       // 2D derivative kinds: the near fields interleaved, [i2][i1][field]
-  void* farI = nullptr;        // and the far slab, [s][i1][field]
+  void* gridI = nullptr;       // 2D derivative kinds: the near fields interleaved, [i2][i1][field];
+  void* farI = nullptr;        // complex64 G: node quads [i2][i1][a] = grid[i2][i1 + a]; far slab alike
   double* E2 = nullptr;        // 2D G with sing_order >= 2: [4][j2'][j1'] real tables of the removed
                                // degree-2 and degree-3 terms (e_tt, e_rr, e_ttt, e_trr)
   double* D2 = nullptr;        // 2D derivative tables: gradient [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2),
