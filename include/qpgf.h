@@ -329,7 +329,8 @@ typedef enum {
   QPGF_T_BATCH = 9,    /* one replay of the batched 2D graph (all stages)        */
   QPGF_T_BIN_PLACE = 10, /* binning: scatter of target records into tile order   */
   QPGF_T_OVERFLOW = 11,  /* targets handed over by the tiled gather              */
-  QPGF_T_LAYOUT = 12,    /* 2D derivative kinds: fields interleaved per grid node  */
+  QPGF_T_LAYOUT = 12,    /* 2D: derivative fields interleaved per node, or the     */
+                         /* complex64 G's node quads (4 x1-neighbours per node)  */
   QPGF_T_RING = 13,      /* 2D G with ring_interp: the cut-off-ring correction     */
   QPGF_T_COUNT = 14
 } qpgf_timer_id;
