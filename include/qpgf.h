@@ -331,7 +331,7 @@ typedef enum {
   QPGF_T_OVERFLOW = 11,  /* targets handed over by the tiled gather              */
   QPGF_T_LAYOUT = 12,    /* 2D: derivative fields interleaved per node, or the     */
                          /* complex64 G's node quads (4 x1-neighbours per node)  */
-  QPGF_T_RING = 13,      /* 2D G with ring_interp: the cut-off-ring correction     */
+  QPGF_T_RING = 13,      /* 2D G / gradient with ring_interp: the ring correction  */
   QPGF_T_COUNT = 14
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
