@@ -380,9 +380,11 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
 
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
   PLAN_TRY(hipMalloc(&P.far, P.nf * P.nfar * P.esize));
-  if (P.dim == 2 && (P.nf > 1 || P.p.prec == QPGF_C64)) {
-    // derivative kinds: the fields interleaved per node; the complex64 G: each node's quad of
-    // x1-neighbours (4 values, 32 bytes)
+  // complex64 G: each node's quad of x1-neighbours (4 values, 32 bytes) while the quads stay about
+  // L2-sized (measured: 4.4 MB of quads read 30 % faster than the grid row by row, 8.8 MB slower)
+  const bool quads = P.dim == 2 && P.nf == 1 && P.p.prec == QPGF_C64 && 32 * (P.ncell + P.nfar) <= (5u << 20);
+  if (P.dim == 2 && (P.nf > 1 || quads)) {
+    // derivative kinds: the fields interleaved per node; the complex64 G: node quads
     const size_t per = P.nf > 1 ? (size_t)P.nf : 4;
     PLAN_TRY(hipMalloc(&P.gridI, per * P.ncell * P.esize));
     PLAN_TRY(hipMalloc(&P.farI, per * P.nfar * P.esize));

@@ -103,6 +103,23 @@ def test_g2d_small_workload(prec):
     assert not np.any(f & 13)
 
 
+def test_g2d_large_grid_row_major_path():
+    """complex64 G on a grid whose node quads would outgrow L2 (2048 x 256): the gather reads the grid
+    row by row; sampled targets against the oracle, wrapped rows included."""
+    M1, M2 = 2048, 256
+    k, al = 2.1, 0.3
+    x = workloads.targets(100_000, 2, seed=12)
+    P = qpgf.Plan(qpgf.KIND_G2D, qpgf.C64, M1, M2)
+    g = P(k, al, 0.0, dev(x)).cpu().numpy()
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    wrap = np.nonzero(t > math.pi - 2 * (2 * math.pi / M1))[0]
+    rng = np.random.default_rng(3)
+    pick = np.concatenate([wrap[:50], rng.choice(len(x), 250, replace=False)])
+    o = method.eval_g2d(k, al, x[pick], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    assert len(wrap) >= 50
+    assert parity(g[pick], o) <= TOL[qpgf.C64]
+
+
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
 @pytest.mark.parametrize("shape", [(64, 64, 32), (32, 128, 64)])
 def test_gd3d_small(prec, shape):
