@@ -132,8 +132,12 @@ def far_grids_hess_diff(k1, k2, alpha, N1, z):
 
 
 def eval_g2d_hess_diff(k1, k2, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
-                       q=ORACLE_Q):
-    """(d11, d12, d22) of G_{k1} - G_{k2} at targets x[T,2] as [T, 3] (NaN beyond the far slab)."""
+                       q=ORACLE_Q, ring=False):
+    """(d11, d12, d22) of G_{k1} - G_{k2} at targets x[T,2] as [T, 3] (NaN beyond the far slab).
+
+    ``ring``: in the cut-off ring (``highorder2d.ring_zone``) the stencil interpolates
+    T_pq = L_pq + h_pq at its nodes instead of L_pq, and nothing is added back there (the
+    reading of Remark 5.6 taken for G and its gradient)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2 = 2 * N1, 2 * N2
     h1, h2 = math.pi / N1, c_tilde / N2
@@ -148,10 +152,23 @@ def eval_g2d_hess_diff(k1, k2, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=c
         i1, w1 = _stencil((tn + math.pi) / h1, M1)
         i2, w2 = _stencil((zn + c_tilde) / h2, M2)
         hs = h_hess_diff(k1, k2, alpha, tn, zn, eps)
+        zone = np.zeros(len(tn), dtype=bool)
+        if ring:
+            from .highorder2d import ring_zone
+            zone = ring_zone(tn, zn, h1, h2, eps)
+        if zone.any():
+            # node offsets from the lattice point: base index floor(t / h) - 1 + a
+            p1 = np.floor(tn[zone] / h1)[:, None] - 1 + np.arange(4)
+            p2 = np.floor(zn[zone] / h2)[:, None] - 1 + np.arange(4)
+            hn = h_hess_diff(k1, k2, alpha, (p1 * h1)[:, :, None] + 0 * p2[:, None, :],
+                             (p2 * h2)[:, None, :] + 0 * p1[:, :, None], eps)
         for p in range(3):
             vals = grids[p][i1[:, :, None], i2[:, None, :]]
             L = np.einsum("ta,tb,tab->t", w1, w2, vals)
-            out[near, p] = phase[near] * (L + hs[p])
+            g = L + hs[p]
+            if zone.any():
+                g[zone] = np.einsum("ta,tb,tab->t", w1[zone], w2[zone], vals[zone] + hn[p])
+            out[near, p] = phase[near] * g
     far = ~near
     if far.any():
         zf = far_slices(far_h, far_S, c)

@@ -96,3 +96,31 @@ def test_grad_ring_accuracy_against_the_series():
     assert err[True, 256] < err[False, 256] / 15
     assert err[True, 256] < 5e-5
     assert err[True, 256] < err[True, 128] / 8
+
+
+# ----------------------------------------------------------------------------- second-derivative differences (Section 2.4.2)
+
+def test_hess_ring_agrees_with_plain_form_at_grid_nodes():
+    from oracle import hess2d
+    N1, N2 = 64, 32
+    h1, h2 = math.pi / N1, 1.0 / N2
+    p = np.array([[5, 4], [-6, 5], [3, -9], [-2, -10], [7, 2]])
+    x = p * [h1, h2]
+    a = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, 17)
+    b = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, 17, ring=True)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+
+
+def test_hess_ring_accuracy_against_the_series():
+    from oracle import hess2d
+    x = _ring_targets(100, seed=7, lo=0.15, hi=0.5)
+    x = x[np.abs(x[:, 1]) <= 0.55]
+    gt = truth.g2d_hess(K, AL, x) - truth.g2d_hess(4.35, AL, x)
+    err = {}
+    for ring in (False, True):
+        for N1, N2 in ((128, 64), (256, 128)):
+            g = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, ring=ring)
+            err[ring, N1] = np.max(np.abs(g - gt) / np.abs(gt), axis=0)
+    assert np.all(err[True, 256] < err[False, 256] / 15)
+    assert np.all(err[True, 256] < 5e-5)
+    assert np.all(err[True, 256] < err[True, 128] / 8)
