@@ -114,8 +114,9 @@ typedef struct {
                               adds -(alpha^2/2) x1^2 - (k^2/4) r^2; 3 adds i (alpha^3/6) x1^3 + i (alpha k^2/4)
                               x1 r^2.  The remainder is O(r^{m+1} ln r), so near a lattice point the error
                               falls like N^-(m+1) instead of N^-2.  Every other kind requires 1. */
-  int ring_interp;         /* QPGF_KIND_G2D (single-instance calls) and QPGF_KIND_G2D_GRAD: 1 interpolates
-                              K = L + f Y (f the removed singular part; for the gradient K_p = L_p + h_p)
+  int ring_interp;         /* QPGF_KIND_G2D (single-instance calls), QPGF_KIND_G2D_GRAD, QPGF_KIND_G2D_HESS_DIFF:
+                              1 interpolates K = L + f Y (f the removed singular part; for the derivative
+                              kinds L_p + h_p, L_pq + h_pq)
                               instead of L for near targets with r_lo < r < r_hi, r_hi =
                               2 eps + 2 sqrt(2) h, r_lo = max(eps, eps/2 + 2 sqrt(2) h), h = max(h1, h2) (every
                               stencil node then stays eps/2 or more from the lattice point), and adds nothing
@@ -123,7 +124,7 @@ typedef struct {
                               Y_eps times the logarithm across that ring, K does not (Remark 5.6 ties the
                               accuracy to the cut-offs' smoothness): the ring's error falls by two to three
                               orders of magnitude.  Those targets are collected by the gather and corrected by
-                              a second pass.  0 (default): Algorithm 2.1 / Section 2.4.1 as printed.  Every
+                              a second pass.  0 (default): Algorithm 2.1 / Section 2.4 as printed.  Every
                               other kind, and qpgf_g2d_batched, require 0. */
 } qpgf_params;
 
@@ -331,7 +332,7 @@ typedef enum {
   QPGF_T_OVERFLOW = 11,  /* targets handed over by the tiled gather              */
   QPGF_T_LAYOUT = 12,    /* 2D: derivative fields interleaved per node, or the     */
                          /* complex64 G's node quads (4 x1-neighbours per node)  */
-  QPGF_T_RING = 13,      /* 2D G / gradient with ring_interp: the ring correction  */
+  QPGF_T_RING = 13,      /* 2D kinds with ring_interp: the cut-off-ring correction */
   QPGF_T_COUNT = 14
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);

@@ -137,8 +137,8 @@ qpgf_status validate(const qpgf_params* p) {
   if (p->sing_order < 1 || p->sing_order > 3) return fail(QPGF_E_ARG, "sing_order must be 1, 2 or 3");
   if (p->sing_order != 1 && p->kind != QPGF_KIND_G2D) return fail(QPGF_E_ARG, "sing_order above 1 needs QPGF_KIND_G2D");
   if (p->ring_interp != 0 && p->ring_interp != 1) return fail(QPGF_E_ARG, "ring_interp must be 0 or 1");
-  if (p->ring_interp && p->kind != QPGF_KIND_G2D && p->kind != QPGF_KIND_G2D_GRAD)
-    return fail(QPGF_E_ARG, "ring_interp needs QPGF_KIND_G2D or QPGF_KIND_G2D_GRAD");
+  if (p->ring_interp && p->kind != QPGF_KIND_G2D && p->kind != QPGF_KIND_G2D_GRAD && p->kind != QPGF_KIND_G2D_HESS_DIFF)
+    return fail(QPGF_E_ARG, "ring_interp needs a 2D kind");
   return QPGF_OK;
 }
 

@@ -941,6 +941,22 @@ __device__ __forceinline__ void hgrad_at(const GArgs& A, double t, double z, dou
   h2 = mk(c * re * z, c * im * z);
 }
 
+// The second-derivative differences' singular parts (Section 2.4.2) at cell point (t, z), zero
+// beyond 2 eps: h_pq = C Y [ s_pq - i alpha t s_pq ], C = (k1^2 - k2^2)/(2pi),
+// s_11 = ln r/2 + t^2/(2r^2), s_12 = t z/(2r^2), s_22 = ln r/2 + z^2/(2r^2).
+__device__ __forceinline__ void hhess_at(const GArgs& A, double t, double z, double2 h[3]) {
+  const double r2 = t * t + z * z;
+  h[0] = h[1] = h[2] = mk(0.0, 0.0);
+  if (!(r2 < 4.0 * A.eps * A.eps) || r2 == 0.0) return;
+  const double r = sqrt(r2), ir2 = 0.5 / r2, hl = 0.5 * log(r);
+  const double C = (A.k * A.k - A.k2 * A.k2) / (2.0 * kPi) * cut_Y(r, A.eps);
+  const double s11 = hl + t * t * ir2, s12 = t * z * ir2, s22 = hl + z * z * ir2;
+  const double at = -A.a1 * t;
+  h[0] = mk(C * s11, C * at * s11);
+  h[1] = mk(C * s12, C * at * s12);
+  h[2] = mk(C * s22, C * at * s22);
+}
+
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x, cplx<T>* __restrict__ out) {
   __shared__ uint32_t s_off[kRingLists + 1];
@@ -971,7 +987,7 @@ __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restric
     double w1[4], w2[4];
     lag4<double>(u - p, w1);
     lag4<double>(u2 - p2, w2);
-    // NF = 1: f Y of the 2D G; NF = 2: the gradient's h1, h2
+    // NF = 1: f Y of the 2D G; NF = 2: the gradient's h1, h2; NF = 3: h_11, h_12, h_22
     double2 acc[NF], at[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = mk(0.0, 0.0);
@@ -983,7 +999,8 @@ __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restric
       for (int a = 0; a < 4; ++a) {
         double2 v[NF];
         if constexpr (NF == 1) v[0] = fy_removed(A, (p - 1.0 + a) * A.h1, zn);
-        else hgrad_at(A, (p - 1.0 + a) * A.h1, zn, v[0], v[1]);
+        else if constexpr (NF == 2) hgrad_at(A, (p - 1.0 + a) * A.h1, zn, v[0], v[1]);
+        else hhess_at(A, (p - 1.0 + a) * A.h1, zn, v);
 #pragma unroll
         for (int f = 0; f < NF; ++f) row[f] = mk(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
       }
@@ -991,7 +1008,8 @@ __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restric
       for (int f = 0; f < NF; ++f) acc[f] = mk(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
     }
     if constexpr (NF == 1) at[0] = fy_removed(A, t, x2);
-    else hgrad_at(A, t, x2, at[0], at[1]);
+    else if constexpr (NF == 2) hgrad_at(A, t, x2, at[0], at[1]);
+    else hhess_at(A, t, x2, at);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
 #pragma unroll
@@ -1113,11 +1131,12 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
 // slab, the 12 field times sgn(x2).  grid and far hold the three fields interleaved per node.
 // out[3i + p] = d_p d_q G_k1 - d_p d_q G_k2, pq = 11, 12, 22.
 template <typename T>
-__device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>* __restrict__ grid,
+__device__ __forceinline__ bool gather2d_hess_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
                                                   long i, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
   uint8_t fl = 0;
+  bool in_ring = false;
   double2 d[3];
   if (!(isfinite(x1) && isfinite(x2))) {
     fl = 8;
@@ -1166,15 +1185,17 @@ __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>*
         if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
           fl |= 1;
           L[0] = L[1] = L[2] = nan2();
-        } else if (r2 < 4.0 * A.eps * A.eps) {
-          // h_pq = C Y [ (ln r/2 + x_p x_q/(2r^2)) or x1 x2/(2r^2), minus i alpha x1 times the same ]
-          const double r = sqrt(r2), ir2 = 0.5 / r2, hl = 0.5 * log(r);
-          const double C = (A.k * A.k - A.k2 * A.k2) / (2.0 * kPi) * cut_Y(r, A.eps);
-          const double s11 = hl + t * t * ir2, s12 = t * x2 * ir2, s22 = hl + x2 * x2 * ir2;
-          const double at = -A.a1 * t;
-          L[0] = cadd(L[0], mk(C * s11, C * at * s11));
-          L[1] = cadd(L[1], mk(C * s12, C * at * s12));
-          L[2] = cadd(L[2], mk(C * s22, C * at * s22));
+        } else {
+          if (r2 < 4.0 * A.eps * A.eps) {
+            double2 h[3];
+            hhess_at(A, t, x2, h);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) L[f] = cadd(L[f], h[f]);
+          }
+          if (A.ring_idx) {
+            const double r = sqrt(r2);
+            in_ring = r > A.ring_lo && r < A.ring_hi;
+          }
         }
       } else if (x2 < 0.0) {
         L[1] = cscale(L[1], -1.0);
@@ -1186,6 +1207,7 @@ __device__ __forceinline__ void gather2d_hess_one(const GArgs& A, const cplx<T>*
 #pragma unroll
   for (int f = 0; f < 3; ++f) store_out<T>(out, 3 * i + f, d[f]);
   if (flags) flags[i] = fl;
+  return in_ring;
 }
 
 template <typename T>
@@ -1194,7 +1216,8 @@ __global__ __launch_bounds__(256) void k_gather2d_hess(GArgs A, const cplx<T>* _
                                                        long T_, cplx<T>* __restrict__ out,
                                                        uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < T_) gather2d_hess_one<T>(A, grid, far, x, i, out, flags);
+  const bool in_ring = i < T_ && gather2d_hess_one<T>(A, grid, far, x, i, out, flags);
+  if (A.ring_idx) ring_append(A, in_ring, i);
 }
 
 // Many 2D instances in one launch: instance i owns blocks [blk0_i, blk0_{i+1}) and
@@ -1493,7 +1516,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     const auto* fi = static_cast<const cplx<T>*>(P.farI);
     if (P.nf == 2 && !P.p.ring_interp)
       hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
-    else if (P.nf == 3)
+    else if (P.nf == 3 && !P.p.ring_interp)
       hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
     else if (!P.p.ring_interp)
       hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
@@ -1509,13 +1532,17 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
                          (long)kRingLists * kRingPad);
       if (P.nf == 2)
         hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
+      else if (P.nf == 3)
+        hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
       else
         hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
                            (long)T_, o, flags);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
       const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
-      if (P.nf == 2)
+      if (P.nf == 3)
+        hipLaunchKernelGGL((k_ring2d<T, 3>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
+      else if (P.nf == 2)
         hipLaunchKernelGGL((k_ring2d<T, 2>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
       else
         hipLaunchKernelGGL((k_ring2d<T, 1>), dim3(nb), dim3(256), 0, P.stream, A, x, o);

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import grad2d
+from oracle import grad2d, hess2d
 from oracle import highorder2d as ho
 from oracle import truth
 from paper_1801_05977_amd import qpgf, workloads
@@ -113,7 +113,7 @@ def test_ring_many_targets_sampled():
 def test_ring_parameter_checks():
     L = qpgf.lib()
     for kind, dims, ring in ((qpgf.KIND_G2D, (64, 32, 0), 2), (qpgf.KIND_GD3D, (32, 32, 16), 1),
-                             (qpgf.KIND_G2D_HESS_DIFF, (64, 32, 0), 1), (qpgf.KIND_G2D_GRAD, (64, 32, 0), 2)):
+                             (qpgf.KIND_G2D_HESS_DIFF, (64, 32, 0), 2), (qpgf.KIND_G2D_GRAD, (64, 32, 0), 2)):
         p = qpgf.default_params(kind, qpgf.C128, *dims, ring_interp=ring)
         h = ctypes.c_void_p()
         assert L.qpgf_plan_create(ctypes.byref(p), ctypes.byref(h)) == 1, (kind, ring)
@@ -164,3 +164,45 @@ def test_grad_ring_accuracy_against_the_series():
         P.close()
     assert err[0] > 1e-4
     assert err[1] < 5e-5 and err[1] < err[0] / 15
+
+
+# ----------------------------------------------------------------------------- second-derivative differences (Section 2.4.2)
+
+K2 = 4.35
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001)])
+def test_hess_ring_end_to_end(prec, shape, T):
+    M1, M2 = shape
+    x = np.vstack([workloads.targets(T, 2, seed=7), _ring_dense(3000, seed=10), _edge_targets()])
+    P = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, prec, M1, M2, ring_interp=1)
+    flags = torch.empty(len(x), dtype=torch.uint8, device="cuda")
+    g = P.hess_diff(K, K2, AL, dev(x), flags=flags).cpu().numpy()
+    f = flags.cpu().numpy()
+    bad = (f & 13) != 0
+    assert np.all(np.isnan(g[bad]))
+    o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[~bad], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, ring=True)
+    for p in range(3):
+        assert parity(g[~bad, p], o[:, p]) <= TOL[prec], p
+    P0 = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, prec, M1, M2)
+    g0 = P0.hess_diff(K, K2, AL, dev(x)).cpu().numpy()
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    lo, hi = ho.ring_bounds(math.pi / (M1 // 2), 1.0 / (M2 // 2))
+    r = np.sqrt(t * t + x[:, 1] ** 2)
+    away = ~bad & ~((r > lo * (1 - 1e-12)) & (r < hi * (1 + 1e-12)))
+    assert away.sum() > 500 and (~away & ~bad).sum() > 500
+    np.testing.assert_array_equal(g[away], g0[away])
+
+
+def test_hess_ring_accuracy_against_the_series():
+    x = _ring_dense(150, seed=11)
+    x = x[(np.abs(x[:, 1]) >= 0.02) & (np.abs(x[:, 1]) <= 0.55)]
+    gt = truth.g2d_hess(K, AL, x) - truth.g2d_hess(K2, AL, x)
+    err = {}
+    for ring in (0, 1):
+        P = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, qpgf.C128, 512, 256, ring_interp=ring)
+        err[ring] = np.max(np.abs(P.hess_diff(K, K2, AL, dev(x)).cpu().numpy() - gt) / np.abs(gt), axis=0)
+        P.close()
+    assert np.all(err[0] > 5e-5)
+    assert np.all(err[1] < 5e-5) and np.all(err[1] < err[0] / 15)
