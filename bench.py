@@ -410,6 +410,15 @@ def run_g2d_hess_diff(args):
         P.hess_diff(2.1, 4.35, 0.3, x, out)
     torch.cuda.synchronize()
     kern = {k_: round(v[0] / v[1], 5) for k_, v in P.timing().items() if v[1]}
+    # the same step with the cut-off ring interpolated (ring_interp), beside
+    Pr = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, prec, M1, M2, ring_interp=1)
+    tr = _timed(lambda: Pr.hess_diff(2.1, 4.35, 0.3, x, out), args.steps, args.warmup)
+    Pr.enable_timing(True)
+    for _ in range(args.steps):
+        Pr.hess_diff(2.1, 4.35, 0.3, x, out)
+    torch.cuda.synchronize()
+    kern_r = {k_: round(v[0] / v[1], 5) for k_, v in Pr.timing().items() if v[1]}
+    Pr.close()
     esize = 8 if prec == qpgf.C64 else 16
     # gather: 16 B in, three results and a flag byte out per target, the three fields once
     alg = T * (16 + 3 * esize + 1) + 3 * (P.info.grid_bytes + P.info.far_grid_bytes)
@@ -421,6 +430,7 @@ def run_g2d_hess_diff(args):
             "config": {"workload": "g2d second-derivative differences k1=2.1 k2=4.35 alpha=0.3", "x1_modes": M1,
                        "slices": M2, "targets": T, "method": "plain"},
             "kernels_avg_ms": kern,
+            "ring_interp_1": {"ms_per_step": tr * 1e3, "kernels_avg_ms": kern_r},
             "roofline": {"bound": "hbm", "kernel": "gather", "achieved": round(ach, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None}}
 

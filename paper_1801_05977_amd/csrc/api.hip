@@ -100,7 +100,7 @@ void free_plan(Plan& P) {
   for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI, P.farI})
     if (q) (void)hipFree(q);
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.wXq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
-                  P.twf,  P.F1,  P.F2,   P.D2, P.E2, P.ring_idx, P.ring_cnt, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
+                  P.twf,  P.F1,  P.F2,   P.D2, P.E2, P.ring_mask, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -26,12 +26,9 @@ struct GArgs {
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
   int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
   int quad;                // 2D G, complex64: grid and far are node quads (4 x1-neighbours per node)
-  // 2D G, ring_interp: near targets with ring_lo < r < ring_hi are collected into kRingLists
-  // lists (wave w appends to list w mod kRingLists: ring_idx[list * ring_cap ..], its length in
-  // ring_cnt[list * kRingPad])
-  uint32_t* ring_cnt;
-  uint32_t* ring_idx;
-  long ring_cap;
+  // 2D kinds, ring_interp: bit i of ring_mask marks target i (a near target with
+  // ring_lo < r < ring_hi) for the ring pass
+  unsigned long long* ring_mask;
   double ring_lo, ring_hi;
 };
 
@@ -795,26 +792,12 @@ __device__ __forceinline__ void stencil2d_fields(const cplx<T>* __restrict__ g, 
     stencil2d_multi<T, NF>(g, rows, i0, M1, w1, w2, L);
 }
 
-// Ring lists: wave w appends to list w mod kRingLists, so the appends of the launch spread over
-// that many counters (each on its own 128-byte line) instead of contending for one, and a list
-// never holds more than 64 entries per wave it serves.
-constexpr int kRingLists = 256;
-constexpr int kRingPad = 32;
-static_assert(kRingLists == 256, "k_ring2d scans the list lengths with one thread per list");
-
-// Append target i when take is set: one atomic per wave (ballot, prefix count).  Called with the
-// whole wave's active lanes together.
-__device__ __forceinline__ void ring_append(const GArgs& A, bool take, long i) {
+// Mark the wave's targets that lie in the cut-off ring: the wave's 64 consecutive targets own
+// one word of the mask, which its first lane writes whole, so the mask needs neither clearing nor
+// atomics.  Called by every lane of the wave (take false beyond the last target).
+__device__ __forceinline__ void ring_mark(const GArgs& A, bool take, long i, long T_) {
   const unsigned long long m = __ballot(take);
-  if (m == 0) return;
-  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int list = (int)(wave & (kRingLists - 1));
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(A.ring_cnt + list * kRingPad, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  if (take) A.ring_idx[(size_t)list * A.ring_cap + base + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = (uint32_t)i;
+  if (__lane_id() == 0 && i < T_) A.ring_mask[i >> 6] = m;
 }
 
 // One target of Algorithm 2.1 step 2; returns whether it lies in the cut-off ring.
@@ -904,117 +887,172 @@ __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __re
   return in_ring;
 }
 
-// The cut-off ring (ring_interp): for the collected targets (r_lo < r < r_hi, every stencil node at
+// The cut-off ring (ring_interp): for the marked targets (r_lo < r < r_hi, every stencil node at
 // least eps/2 from the lattice point) the stencil's sum of f Y over its
 // nodes replaces f Y at the target, so that the result is the interpolant of K = L + f Y:
 // out += e^{i alpha x1} (sum_ab w_a w_b (f Y)(node_ab) - (f Y)(target)), f the removed singular
 // part of the plan's order and a node's position its offset (p1 h1, p2 h2) from the lattice
-// point.  FP64 throughout; a grid-stride loop over the lists' entries, numbered through in list
-// order (each block scans the kRingLists lengths in LDS first).
-__device__ __forceinline__ double2 fy_removed(const GArgs& A, double t, double z) {
-  const double r2 = t * t + z * z;
-  const double r = sqrt(r2);
-  if (!(r < 2.0 * A.eps) || r2 == 0.0) return mk(0.0, 0.0);
-  const double s = -log(r) * cut_Y(r, A.eps) / (2.0 * kPi);
-  const double a = A.a1;
-  double pr = 1.0, pim = -a * t;
-  if (A.sing_order >= 2) {
-    const double kk = 0.25 * A.k * A.k;
-    pr -= 0.5 * a * a * t * t + kk * r2;
-    if (A.sing_order >= 3) pim += a * t * (a * a * t * t / 6.0 + kk * r2);
+// point.  The complex128 path computes in FP64, the complex64 path in FP32 (the correction is a
+// small part of a result kept to single precision; the phase stays FP64).  Each block takes
+// kRingSpan consecutive targets: its first wave reads their mask words and collects the marked
+// offsets in LDS, then all lanes correct them (kRingSpan targets per block: fewer, fuller blocks
+// measured faster than small ones whose waves stay mostly idle).
+template <typename C>
+__device__ __forceinline__ cplx<C> cv(C re, C im) {
+  cplx<C> v;
+  v.x = re;
+  v.y = im;
+  return v;
+}
+
+template <typename C>
+__device__ __forceinline__ C ring_log(C r) {
+  if constexpr (sizeof(C) == 8) return log(r);
+  else return __logf(r);
+}
+
+// Y_eps(r); in FP32 as S((2 eps - r)/eps) (S(1 - u) = 1 - S(u) for the symmetric Beta(9, 9)
+// transition), which avoids the cancellation of 1 - S near the ring's outer edge.
+template <typename C>
+__device__ __forceinline__ C ring_cutY(const GArgs& A, C r) {
+  if constexpr (sizeof(C) == 8) {
+    return cut_Y(r, A.eps);
+  } else {
+    const float u = (2.0f * (float)A.eps - r) * (float)(1.0 / A.eps);
+    if (u <= 0.0f) return 0.0f;
+    if (u >= 1.0f) return 1.0f;
+    const float binom[9] = {24310.0f, 19448.0f, 12376.0f, 6188.0f, 2380.0f, 680.0f, 136.0f, 17.0f, 1.0f};
+    const float v = 1.0f - u;
+    float uj = u * u * u;
+    uj = uj * uj * uj;                                  // u^9
+    float vp[9];
+    vp[0] = 1.0f;
+#pragma unroll
+    for (int j = 1; j < 9; ++j) vp[j] = vp[j - 1] * v;  // v^0..v^8
+    float sum = 0.0f;
+#pragma unroll
+    for (int j = 9; j <= 17; ++j) {
+      sum += binom[j - 9] * uj * vp[17 - j];
+      uj *= u;
+    }
+    return sum;
   }
-  return mk(s * pr, s * pim);
+}
+
+template <typename C>
+__device__ __forceinline__ cplx<C> fy_removed(const GArgs& A, C t, C z) {
+  const C r2 = t * t + z * z;
+  const C r = sqrt(r2);
+  if (!(r < (C)(2.0 * A.eps)) || r2 == C(0)) return cv<C>(0, 0);
+  const C s = -ring_log(r) * ring_cutY(A, r) / (C)(2.0 * kPi);
+  const C a = (C)A.a1;
+  C pr = 1, pim = -a * t;
+  if (A.sing_order >= 2) {
+    const C kk = (C)(0.25 * A.k * A.k);
+    pr -= C(0.5) * a * a * t * t + kk * r2;
+    if (A.sing_order >= 3) pim += a * t * (a * a * t * t / C(6) + kk * r2);
+  }
+  return cv<C>(s * pr, s * pim);
 }
 
 // The gradient's singular parts (Section 2.4.1) at cell point (t, z), zero beyond 2 eps:
 // h_p = -(Y/2pi) [ -(k^2/2) x_p ln r + x_p/r^2 - i alpha t x_p/r^2 - (alpha^2/2) t^2 x_p/r^2 ],
 // x_1 = t, x_2 = z.
-__device__ __forceinline__ void hgrad_at(const GArgs& A, double t, double z, double2& h1, double2& h2) {
-  const double r2 = t * t + z * z;
-  h1 = h2 = mk(0.0, 0.0);
-  if (!(r2 < 4.0 * A.eps * A.eps) || r2 == 0.0) return;
-  const double r = sqrt(r2), ir2 = 1.0 / r2;
-  const double c = -cut_Y(r, A.eps) / (2.0 * kPi);
-  const double re = -0.5 * A.k * A.k * log(r) + ir2 - 0.5 * A.a1 * A.a1 * t * t * ir2;
-  const double im = -A.a1 * t * ir2;
-  h1 = mk(c * re * t, c * im * t);
-  h2 = mk(c * re * z, c * im * z);
+template <typename C>
+__device__ __forceinline__ void hgrad_at(const GArgs& A, C t, C z, cplx<C>& h1, cplx<C>& h2) {
+  const C r2 = t * t + z * z;
+  h1 = h2 = cv<C>(0, 0);
+  if (!(r2 < (C)(4.0 * A.eps * A.eps)) || r2 == C(0)) return;
+  const C r = sqrt(r2), ir2 = C(1) / r2;
+  const C c = -ring_cutY(A, r) / (C)(2.0 * kPi);
+  const C re = (C)(-0.5 * A.k * A.k) * ring_log(r) + ir2 - (C)(0.5 * A.a1 * A.a1) * t * t * ir2;
+  const C im = (C)(-A.a1) * t * ir2;
+  h1 = cv<C>(c * re * t, c * im * t);
+  h2 = cv<C>(c * re * z, c * im * z);
 }
 
 // The second-derivative differences' singular parts (Section 2.4.2) at cell point (t, z), zero
 // beyond 2 eps: h_pq = C Y [ s_pq - i alpha t s_pq ], C = (k1^2 - k2^2)/(2pi),
 // s_11 = ln r/2 + t^2/(2r^2), s_12 = t z/(2r^2), s_22 = ln r/2 + z^2/(2r^2).
-__device__ __forceinline__ void hhess_at(const GArgs& A, double t, double z, double2 h[3]) {
-  const double r2 = t * t + z * z;
-  h[0] = h[1] = h[2] = mk(0.0, 0.0);
-  if (!(r2 < 4.0 * A.eps * A.eps) || r2 == 0.0) return;
-  const double r = sqrt(r2), ir2 = 0.5 / r2, hl = 0.5 * log(r);
-  const double C = (A.k * A.k - A.k2 * A.k2) / (2.0 * kPi) * cut_Y(r, A.eps);
-  const double s11 = hl + t * t * ir2, s12 = t * z * ir2, s22 = hl + z * z * ir2;
-  const double at = -A.a1 * t;
-  h[0] = mk(C * s11, C * at * s11);
-  h[1] = mk(C * s12, C * at * s12);
-  h[2] = mk(C * s22, C * at * s22);
+template <typename C>
+__device__ __forceinline__ void hhess_at(const GArgs& A, C t, C z, cplx<C> h[3]) {
+  const C r2 = t * t + z * z;
+  h[0] = h[1] = h[2] = cv<C>(0, 0);
+  if (!(r2 < (C)(4.0 * A.eps * A.eps)) || r2 == C(0)) return;
+  const C r = sqrt(r2), ir2 = C(0.5) / r2, hl = C(0.5) * ring_log(r);
+  const C Cy = (C)((A.k * A.k - A.k2 * A.k2) / (2.0 * kPi)) * ring_cutY(A, r);
+  const C s11 = hl + t * t * ir2, s12 = t * z * ir2, s22 = hl + z * z * ir2;
+  const C at = (C)(-A.a1) * t;
+  h[0] = cv<C>(Cy * s11, Cy * at * s11);
+  h[1] = cv<C>(Cy * s12, Cy * at * s12);
+  h[2] = cv<C>(Cy * s22, Cy * at * s22);
 }
 
+constexpr int kRingWords = 256;                 // mask words per block of the ring pass (one per thread)
+constexpr int kRingSpan = 64 * kRingWords;      // targets per block
+static_assert(kRingSpan <= 65536, "k_ring2d keeps 16-bit offsets in LDS");
+
 template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x, cplx<T>* __restrict__ out) {
-  __shared__ uint32_t s_off[kRingLists + 1];
+__global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restrict__ x, long T_,
+                                                cplx<T>* __restrict__ out) {
+  __shared__ uint32_t s_n;
+  __shared__ uint16_t s_off[kRingSpan];
   const int tid = threadIdx.x;
-  s_off[tid + 1] = A.ring_cnt[tid * kRingPad];
-  if (tid == 0) s_off[0] = 0;
+  if (tid == 0) s_n = 0;
   __syncthreads();
-  for (int d = 1; d < kRingLists; d <<= 1) {
-    const uint32_t v = tid >= d ? s_off[tid + 1 - d] : 0u;
-    __syncthreads();
-    s_off[tid + 1] += v;
-    __syncthreads();
-  }
-  const uint32_t n = s_off[kRingLists];
-  for (uint32_t j = blockIdx.x * blockDim.x + tid; j < n; j += gridDim.x * blockDim.x) {
-    // the list holding entry j: the last list whose first entry is at or before j
-    int lo = 0, hi = kRingLists - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= j) lo = mid;
-      else hi = mid - 1;
+  const long base = (long)blockIdx.x * kRingSpan;
+  if (tid < kRingWords) {
+    const long w = (base >> 6) + tid;
+    unsigned long long m = w < (T_ + 63) >> 6 ? A.ring_mask[w] : 0ull;
+    if (m) {
+      uint32_t pos = atomicAdd(&s_n, (uint32_t)__popcll(m));
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        s_off[pos++] = (uint16_t)(tid * 64 + b);
+        m &= m - 1;
+      }
     }
-    const long i = A.ring_idx[(size_t)lo * A.ring_cap + (j - s_off[lo])];
+  }
+  __syncthreads();
+  const uint32_t n = s_n;
+  for (uint32_t j = tid; j < n; j += 256) {
+    const long i = base + s_off[j];
     const double x1 = x[2 * i], x2 = x[2 * i + 1];
     double n1;
     const double t = reduce_cell(x1, n1);
     const double u = t * A.ih1, p = floor(u), u2 = x2 * A.ih2, p2 = floor(u2);
-    double w1[4], w2[4];
-    lag4<double>(u - p, w1);
-    lag4<double>(u2 - p2, w2);
+    T w1[4], w2[4];
+    lag4<T>((T)(u - p), w1);
+    lag4<T>((T)(u2 - p2), w2);
     // NF = 1: f Y of the 2D G; NF = 2: the gradient's h1, h2; NF = 3: h_11, h_12, h_22
-    double2 acc[NF], at[NF];
+    cplx<T> acc[NF], at[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = mk(0.0, 0.0);
+    for (int f = 0; f < NF; ++f) acc[f] = cv<T>(0, 0);
     for (int b = 0; b < 4; ++b) {
-      const double zn = (p2 - 1.0 + b) * A.h2;
-      double2 row[NF];
+      const T zn = (T)((p2 - 1.0 + b) * A.h2);
+      cplx<T> row[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) row[f] = mk(0.0, 0.0);
+      for (int f = 0; f < NF; ++f) row[f] = cv<T>(0, 0);
       for (int a = 0; a < 4; ++a) {
-        double2 v[NF];
-        if constexpr (NF == 1) v[0] = fy_removed(A, (p - 1.0 + a) * A.h1, zn);
-        else if constexpr (NF == 2) hgrad_at(A, (p - 1.0 + a) * A.h1, zn, v[0], v[1]);
-        else hhess_at(A, (p - 1.0 + a) * A.h1, zn, v);
+        const T tn = (T)((p - 1.0 + a) * A.h1);
+        cplx<T> v[NF];
+        if constexpr (NF == 1) v[0] = fy_removed<T>(A, tn, zn);
+        else if constexpr (NF == 2) hgrad_at<T>(A, tn, zn, v[0], v[1]);
+        else hhess_at<T>(A, tn, zn, v);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) row[f] = mk(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
+        for (int f = 0; f < NF; ++f) row[f] = cv<T>(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
       }
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] = mk(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
+      for (int f = 0; f < NF; ++f) acc[f] = cv<T>(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
     }
-    if constexpr (NF == 1) at[0] = fy_removed(A, t, x2);
-    else if constexpr (NF == 2) hgrad_at(A, t, x2, at[0], at[1]);
-    else hhess_at(A, t, x2, at);
+    if constexpr (NF == 1) at[0] = fy_removed<T>(A, (T)t, (T)x2);
+    else if constexpr (NF == 2) hgrad_at<T>(A, (T)t, (T)x2, at[0], at[1]);
+    else hhess_at<T>(A, (T)t, (T)x2, at);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const double2 corr = cmul(mk(pc, ps), csub(acc[f], at[f]));
+      const double2 corr = cmul(mk(pc, ps), mk((double)(acc[f].x - at[f].x), (double)(acc[f].y - at[f].y)));
       const cplx<T> o = out[i * NF + f];
       store_out<T>(out, i * NF + f, mk((double)o.x + corr.x, (double)o.y + corr.y));
     }
@@ -1027,14 +1065,14 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
                                                   long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in_ring = i < T_ && gather2d_one<T>(A, grid, far, x, i, out, flags);
-  if (A.ring_idx) ring_append(A, in_ring, i);
+  if (A.ring_mask) ring_mark(A, in_ring, i, T_);
 }
 
 // One target of the 2D gradient (Section 2.4.1): both fields interpolated with one
 // stencil, the singular parts h1, h2 added back in FP64 inside 2 eps, the phase
 // e^{i alpha x1}; beyond c the differentiated far slab, the x2 field times sgn(x2).
 // grid and far hold the two fields interleaved per node.  out[2i] = dG/dx1, out[2i+1] = dG/dx2.
-// Returns whether the target lies in the cut-off ring (when the plan collects them).
+// Returns whether the target lies in the cut-off ring (when the plan marks them).
 template <typename T>
 __device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
@@ -1098,7 +1136,7 @@ __device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>*
             L1 = cadd(L1, h1);
             L2 = cadd(L2, h2);
           }
-          if (A.ring_idx) {
+          if (A.ring_mask) {
             const double r = sqrt(r2);
             in_ring = r > A.ring_lo && r < A.ring_hi;
           }
@@ -1123,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
                                                        uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in_ring = i < T_ && gather2d_grad_one<T>(A, grid, far, x, i, out, flags);
-  if (A.ring_idx) ring_append(A, in_ring, i);
+  if (A.ring_mask) ring_mark(A, in_ring, i, T_);
 }
 
 // One target of the second-derivative differences (Section 2.4.2): three fields with one
@@ -1192,7 +1230,7 @@ __device__ __forceinline__ bool gather2d_hess_one(const GArgs& A, const cplx<T>*
 #pragma unroll
             for (int f = 0; f < 3; ++f) L[f] = cadd(L[f], h[f]);
           }
-          if (A.ring_idx) {
+          if (A.ring_mask) {
             const double r = sqrt(r2);
             in_ring = r > A.ring_lo && r < A.ring_hi;
           }
@@ -1217,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_gather2d_hess(GArgs A, const cplx<T>* _
                                                        uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in_ring = i < T_ && gather2d_hess_one<T>(A, grid, far, x, i, out, flags);
-  if (A.ring_idx) ring_append(A, in_ring, i);
+  if (A.ring_mask) ring_mark(A, in_ring, i, T_);
 }
 
 // Many 2D instances in one launch: instance i owns blocks [blk0_i, blk0_{i+1}) and
@@ -1493,9 +1531,7 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.smooth = smooth;
   A.sing_order = P.p.sing_order;
   A.quad = P.dim == 2 && P.nf == 1 && P.gridI != nullptr;
-  A.ring_cnt = nullptr;
-  A.ring_idx = nullptr;
-  A.ring_cap = 0;
+  A.ring_mask = nullptr;
   // the ring zone r_lo < r < r_hi: r_hi = 2 eps + 2 sqrt(2) h, beyond which every stencil node has
   // Y = 0; r_lo = max(eps, eps/2 + 2 sqrt(2) h) keeps every node at least eps/2 from the lattice point
   const double reach = 2.0 * sqrt(2.0) * fmax(A.h1, A.h2);
@@ -1522,14 +1558,9 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
       hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
                          (long)T_, o, flags);
     else {
-      if (T_ > (int64_t)UINT32_MAX) return hipErrorInvalidValue;   // the ring list holds 32-bit indices
       hipError_t e = ensure_ring_scratch(P, T_);
       if (e != hipSuccess) return e;
-      A.ring_cnt = P.ring_cnt;
-      A.ring_idx = P.ring_idx;
-      A.ring_cap = (long)P.ring_cap;
-      hipLaunchKernelGGL(k_zero_u32, dim3(kRingLists * kRingPad / 256), dim3(256), 0, P.stream, P.ring_cnt,
-                         (long)kRingLists * kRingPad);
+      A.ring_mask = P.ring_mask;
       if (P.nf == 2)
         hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
       else if (P.nf == 3)
@@ -1539,13 +1570,13 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
                            (long)T_, o, flags);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
-      const unsigned nb = (unsigned)std::min<int64_t>((T_ + 255) / 256, 1024);
+      const dim3 nb((unsigned)((T_ + kRingSpan - 1) / kRingSpan));
       if (P.nf == 3)
-        hipLaunchKernelGGL((k_ring2d<T, 3>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
+        hipLaunchKernelGGL((k_ring2d<T, 3>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
       else if (P.nf == 2)
-        hipLaunchKernelGGL((k_ring2d<T, 2>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
+        hipLaunchKernelGGL((k_ring2d<T, 2>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
       else
-        hipLaunchKernelGGL((k_ring2d<T, 1>), dim3(nb), dim3(256), 0, P.stream, A, x, o);
+        hipLaunchKernelGGL((k_ring2d<T, 1>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
     }
     return hipGetLastError();
   }
@@ -1736,22 +1767,14 @@ hipError_t launch_interleave2d(Plan& P) {
 }
 
 hipError_t ensure_ring_scratch(Plan& P, int64_t T_) {
-  hipError_t e;
-  if (!P.ring_cnt &&
-      (e = hipMalloc(reinterpret_cast<void**>(&P.ring_cnt), (size_t)kRingLists * kRingPad * sizeof(uint32_t))) !=
-          hipSuccess)
-    return e;
-  // list l serves the waves w = l mod kRingLists: at most ceil(waves / kRingLists) of them
-  const int64_t cap = ((T_ + 63) / 64 + kRingLists - 1) / kRingLists * 64;
-  if (cap > P.ring_cap) {
-    if (P.ring_idx) (void)hipFree(P.ring_idx);
-    P.ring_idx = nullptr;
-    P.ring_cap = 0;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.ring_idx), (size_t)cap * kRingLists * sizeof(uint32_t))) !=
-        hipSuccess)
-      return e;
-    P.ring_cap = cap;
-  }
+  const int64_t words = (T_ + 63) / 64;
+  if (words <= P.ring_words) return hipSuccess;
+  if (P.ring_mask) (void)hipFree(P.ring_mask);
+  P.ring_mask = nullptr;
+  P.ring_words = 0;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&P.ring_mask), (size_t)words * sizeof(unsigned long long));
+  if (e != hipSuccess) return e;
+  P.ring_words = words;
   return hipSuccess;
 }
 
@@ -1817,9 +1840,7 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long fo
   A.sing_order = P.p.sing_order;
   A.quad = 0;   // the batched graph keeps the instances' grids row by row (node quads of all
                 // instances cost more than they save: four times the grids no longer stay in L2)
-  A.ring_cnt = nullptr;
-  A.ring_idx = nullptr;
-  A.ring_cap = 0;
+  A.ring_mask = nullptr;
   A.ring_lo = A.ring_hi = 0.0;
   I.off = off;
   I.foff = foff;

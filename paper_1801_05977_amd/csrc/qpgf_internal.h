@@ -156,9 +156,8 @@ struct Plan {
   uint32_t* bin_hist = nullptr;
   uint32_t* bin_offs = nullptr;
   uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
-  uint32_t* ring_idx = nullptr;        // 2D G, ring_interp: targets collected for the ring pass in
-  uint32_t* ring_cnt = nullptr;        // several lists, ring_cap entries each, and their lengths
-  int64_t ring_cap = 0;
+  unsigned long long* ring_mask = nullptr;  // 2D kinds, ring_interp: one bit per target, set for the
+  int64_t ring_words = 0;                   // targets of the cut-off ring (ring_words 64-bit words)
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count
   // tile configuration of the last binning (launch_bin3d), used by launch_gather_binned
