@@ -91,7 +91,7 @@ def test_ring_accuracy_against_the_series():
 
 
 def test_ring_many_targets_sampled():
-    """1e6 uniform targets, complex64, 1024 x 128 (the list holds about 4 % of them): sampled
+    """1e6 uniform targets, complex64, 1024 x 128 (about 4 % of them in the ring): sampled
     outputs against the oracle."""
     T = 1_000_000
     x = workloads.targets(T, 2, seed=0)
@@ -105,9 +105,27 @@ def test_ring_many_targets_sampled():
     pick = np.concatenate([rng.choice(ring, 300, replace=False), rng.choice(T, 300, replace=False)])
     o = ho.eval_g2d_ho(K, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, 3, ring=True)
     assert parity(g[pick], o) <= TOL[qpgf.C64]
-    # a second, smaller call on the same plan reuses the list
-    g2 = P(K, AL, 0.0, dev(x[:5000])).cpu().numpy()
-    np.testing.assert_array_equal(g2, g[:5000])
+    # smaller calls on the same plan reuse the mask (never cleared: each call writes the words it
+    # reads); counts on both sides of a mask word (64 targets) and of a ring block (16384 targets)
+    xd = dev(x)
+    for n in (5000, 1, 63, 64, 65, 16383, 16384, 16385, 40000):
+        g2 = P(K, AL, 0.0, xd[:n].contiguous()).cpu().numpy()
+        np.testing.assert_array_equal(g2, g[:n], err_msg=str(n))
+
+
+@pytest.mark.parametrize("kind", [qpgf.KIND_G2D_GRAD, qpgf.KIND_G2D_HESS_DIFF])
+def test_ring_derivative_kinds_prefix_calls(kind):
+    """The derivative kinds' ring pass, complex128: calls of every count give the first outputs
+    of a larger call bitwise, and a larger call after smaller ones is unchanged."""
+    x = _ring_dense(20_000, seed=4)
+    P = qpgf.Plan(kind, qpgf.C128, 256, 64, ring_interp=1)
+    call = (lambda xx: P.hess_diff(K, 4.35, AL, xx)) if kind == qpgf.KIND_G2D_HESS_DIFF else \
+        (lambda xx: P(K, AL, 0.0, xx))
+    xd = dev(x)
+    g = call(xd).cpu().numpy()
+    for n in (1, 65, 16385):
+        np.testing.assert_array_equal(call(xd[:n].contiguous()).cpu().numpy(), g[:n], err_msg=str(n))
+    np.testing.assert_array_equal(call(xd).cpu().numpy(), g)
 
 
 def test_ring_parameter_checks():
