@@ -1547,20 +1547,15 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
     return hipGetLastError();
   }
   if (P.dim == 2) {
-    KernelTimer t(P, QPGF_T_GATHER);
     const auto* gi = static_cast<const cplx<T>*>(P.gridI);
     const auto* fi = static_cast<const cplx<T>*>(P.farI);
-    if (P.nf == 2 && !P.p.ring_interp)
-      hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
-    else if (P.nf == 3 && !P.p.ring_interp)
-      hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
-    else if (!P.p.ring_interp)
-      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
-                         (long)T_, o, flags);
-    else {
+    if (P.p.ring_interp) {
       hipError_t e = ensure_ring_scratch(P, T_);
       if (e != hipSuccess) return e;
       A.ring_mask = P.ring_mask;
+    }
+    {
+      KernelTimer t(P, QPGF_T_GATHER);   // the gather alone; the ring pass has its own timer
       if (P.nf == 2)
         hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
       else if (P.nf == 3)
@@ -1568,7 +1563,10 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
       else
         hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
                            (long)T_, o, flags);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (P.p.ring_interp) {
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
       KernelTimer tr(P, QPGF_T_RING);
       const dim3 nb((unsigned)((T_ + kRingSpan - 1) / kRingSpan));
       if (P.nf == 3)
