@@ -113,7 +113,7 @@ def test_ring_many_targets_sampled():
         np.testing.assert_array_equal(g2, g[:n], err_msg=str(n))
 
 
-@pytest.mark.parametrize("kind", [qpgf.KIND_G2D_GRAD, qpgf.KIND_G2D_HESS_DIFF])
+@pytest.mark.parametrize("kind", [qpgf.KIND_G2D_GRAD, qpgf.KIND_G2D_HESS_DIFF], ids=["grad", "hess"])
 def test_ring_derivative_kinds_prefix_calls(kind):
     """The derivative kinds' ring pass, complex128: calls of every count give the first outputs
     of a larger call bitwise, and a larger call after smaller ones is unchanged."""
@@ -224,3 +224,29 @@ def test_hess_ring_accuracy_against_the_series():
         P.close()
     assert np.all(err[0] > 5e-5)
     assert np.all(err[1] < 5e-5) and np.all(err[1] < err[0] / 15)
+
+
+@pytest.mark.parametrize("kind", [qpgf.KIND_G2D_GRAD, qpgf.KIND_G2D_HESS_DIFF], ids=["grad", "hess"])
+def test_ring_derivative_kinds_many_targets_sampled(kind):
+    """The derivative kinds at the benchmarked size: 1e6 uniform targets, complex64, 1024 x 128
+    (the ring corrected in FP32), sampled outputs against the oracle, per component."""
+    T = 1_000_000
+    x = workloads.targets(T, 2, seed=0)
+    P = qpgf.Plan(kind, qpgf.C64, 1024, 128, ring_interp=1)
+    if kind == qpgf.KIND_G2D_HESS_DIFF:
+        g = P.hess_diff(K, K2, AL, dev(x)).cpu().numpy()
+    else:
+        g = P(K, AL, 0.0, dev(x)).cpu().numpy()
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    lo, hi = ho.ring_bounds(math.pi / 512, 1.0 / 64)
+    r = np.hypot(t, x[:, 1])
+    ring = np.nonzero((r > lo) & (r < hi))[0]
+    assert len(ring) > 20000
+    rng = np.random.default_rng(3)
+    pick = np.concatenate([rng.choice(ring, 250, replace=False), rng.choice(T, 250, replace=False)])
+    if kind == qpgf.KIND_G2D_HESS_DIFF:
+        o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, ring=True)
+    else:
+        o = grad2d.eval_g2d_grad(K, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, ring=True)
+    for p in range(o.shape[1]):
+        assert parity(g[pick, p], o[:, p]) <= TOL[qpgf.C64], p
