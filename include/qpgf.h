@@ -124,7 +124,8 @@ typedef struct {
                               Y_eps times the logarithm across that ring, K does not (Remark 5.6 ties the
                               accuracy to the cut-offs' smoothness): the ring's error falls by two to three
                               orders of magnitude.  The gather marks those targets (one bit per target in a
-                              plan-owned mask of T/8 bytes, grown on demand) and a second pass corrects them.
+                              plan-owned mask of T/8 bytes, grown on demand) and a second pass corrects them
+                              (in FP64 for complex128, in FP32 for complex64).
                               0 (default): Algorithm 2.1 / Section 2.4 as printed.  Every
                               other kind, and qpgf_g2d_batched, require 0. */
 } qpgf_params;
