@@ -26,8 +26,8 @@ Steps, in the order of Section 2.4.1:
    Gauss-Legendre rules fine enough for the highest |eta| of the grid.
 3. Grid values by direct DFT sums (``method.grid_2d``).
 4. Targets: reduction, near/far branch, 4 x 4 Lagrange interpolation, exact
-   add-back of h_p, phase.  Far branch: the series' own per-slice coefficients
-   times i(alpha + n) (x1) or i beta_n sgn(x2) (x2).
+   add-back of h_p, phase.  Far branch (|x2| > c): the series (1.2) differentiated
+   term by term, i(alpha + n) for x1 and i beta_n sgn(x2) for x2.
 
 Readings of Section 2.4.1 taken here:
 * the second definition printed as K_1 = dK/dx2 is K_2;
@@ -43,9 +43,8 @@ import numpy as np
 from scipy.special import jv
 
 from . import cutoffs as co
-from .method import (ORACLE_Q, _far_stencil, _reduce, _stencil, dft_matrix, far_slices, gauss_legendre,
-                     grid_2d, khat_2d)
-from .truth import beta
+from . import truth
+from .method import ORACLE_Q, _reduce, _stencil, gauss_legendre, grid_2d, khat_2d
 
 
 def ring_zone(t, z, h1, h2, eps=co.EPS):
@@ -141,23 +140,14 @@ def lhat_grad_2d(k, alpha, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORA
     return m1 * K - H1, m2 * K - H2
 
 
-def far_grids_grad_2d(k, alpha, N1, z):
-    """Far-slab grids [S, 2N1] of K1 and K2 / sgn(x2): the coefficients (i/4pi) beta_n^-1 e^{i beta_n z_s}
-    of the series (1.2) times i(alpha + n) and i beta_n."""
-    a = alpha + np.arange(-N1, N1, dtype=np.float64)
-    b = beta(k, a)
-    base = 1j / (4 * math.pi) * np.exp(1j * np.outer(z, b)) / b       # [S, M1]
-    E = dft_matrix(N1).T
-    return (1j * a * base) @ E, (1j * b * base) @ E
-
-
 # ----------------------------------------------------------------------------
 # evaluation
 # ----------------------------------------------------------------------------
 
-def eval_g2d_grad(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q,
+def eval_g2d_grad(k, alpha, x, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q,
                   ring=False):
-    """(dG/dx1, dG/dx2) at targets x[T,2] as [T, 2] (NaN beyond the far slab).
+    """(dG/dx1, dG/dx2) at targets x[T,2] as [T, 2]; far targets (|x2| > c) take the series (1.2)
+    differentiated term by term.
 
     ``ring``: in the cut-off ring (``highorder2d.ring_zone``) the stencil interpolates
     K_p = L_p + h_p at its nodes instead of L_p, and nothing is added back there (the same
@@ -194,16 +184,5 @@ def eval_g2d_grad(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE,
             out[near, p] = phase[near] * g
     far = ~near
     if far.any():
-        zf = far_slices(far_h, far_S, c)
-        fg = far_grids_grad_2d(k, alpha, N1, zf)                       # 2 x [s, p1]
-        tf, z = t[far], np.abs(x2[far])
-        i1, w1 = _stencil((tf + math.pi) / h1, M1)
-        i2, w2, bad = _far_stencil(z, far_h, far_S, c)
-        sgn = np.sign(x2[far])
-        for p in range(2):
-            vals = fg[p][i2[:, None, :], i1[:, :, None]]
-            L = np.einsum("ta,tb,tab->t", w1, w2, vals)
-            g = phase[far] * L * (sgn if p == 1 else 1.0)
-            g[bad] = np.nan
-            out[far, p] = g
+        out[far] = truth.g2d_grad(k, alpha, x[far])
     return out

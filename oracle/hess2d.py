@@ -43,7 +43,8 @@ from scipy.special import jv
 
 from . import cutoffs as co
 from .grad2d import _radial_rules
-from .method import (ORACLE_Q, _far_stencil, _reduce, _stencil, dft_matrix, far_slices, grid_2d, khat_2d)
+from . import truth
+from .method import ORACLE_Q, _reduce, _stencil, grid_2d, khat_2d
 from .truth import beta
 
 PAIRS = ((0, 0), (0, 1), (1, 1))     # 11, 12, 22
@@ -117,23 +118,10 @@ def lhat_hess_diff(k1, k2, alpha, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS
     return [m * dK - h for m, h in zip(multipliers(alpha, N1, N2, c_tilde), H)]
 
 
-def far_grids_hess_diff(k1, k2, alpha, N1, z):
-    """Far-slab grids [S, 2N1] of T_11, T_12 / sgn(x2), T_22: the coefficients (i/4pi) beta_n^-1 e^{i beta_n z_s}
-    of (1.2) times -alpha_n^2, -alpha_n beta_n, -beta_n^2, for k1 minus for k2."""
-    a = alpha + np.arange(-N1, N1, dtype=np.float64)
-    E = dft_matrix(N1).T
-    out = [0.0, 0.0, 0.0]
-    for k, sgn in ((k1, 1.0), (k2, -1.0)):
-        b = beta(k, a)
-        base = 1j / (4 * math.pi) * np.exp(1j * np.outer(z, b)) / b
-        for p, m in enumerate((-(a * a), -(a * b), -(b * b))):
-            out[p] = out[p] + sgn * (m * base)
-    return [o @ E for o in out]
-
-
-def eval_g2d_hess_diff(k1, k2, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
+def eval_g2d_hess_diff(k1, k2, alpha, x, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
                        q=ORACLE_Q, ring=False):
-    """(d11, d12, d22) of G_{k1} - G_{k2} at targets x[T,2] as [T, 3] (NaN beyond the far slab).
+    """(d11, d12, d22) of G_{k1} - G_{k2} at targets x[T,2] as [T, 3]; far targets (|x2| > c) take
+    the series (1.2) differentiated twice term by term, for k1 minus for k2.
 
     ``ring``: in the cut-off ring (``highorder2d.ring_zone``) the stencil interpolates
     T_pq = L_pq + h_pq at its nodes instead of L_pq, and nothing is added back there (the
@@ -171,16 +159,5 @@ def eval_g2d_hess_diff(k1, k2, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=c
             out[near, p] = phase[near] * g
     far = ~near
     if far.any():
-        zf = far_slices(far_h, far_S, c)
-        fg = far_grids_hess_diff(k1, k2, alpha, N1, zf)
-        tf, z = t[far], np.abs(x2[far])
-        i1, w1 = _stencil((tf + math.pi) / h1, M1)
-        i2, w2, bad = _far_stencil(z, far_h, far_S, c)
-        sgn = np.sign(x2[far])
-        for p in range(3):
-            vals = fg[p][i2[:, None, :], i1[:, :, None]]
-            L = np.einsum("ta,tb,tab->t", w1, w2, vals)
-            g = phase[far] * L * (sgn if p == 1 else 1.0)
-            g[bad] = np.nan
-            out[far, p] = g
+        out[far] = truth.g2d_hess(k1, alpha, x[far]) - truth.g2d_hess(k2, alpha, x[far])
     return out

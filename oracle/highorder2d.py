@@ -138,9 +138,9 @@ def ring_zone(t, z, h1, h2, eps=co.EPS):
     return (r > lo) & (r < hi)
 
 
-def eval_g2d_ho(k, alpha, x, N1, N2, far_h, far_S, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
+def eval_g2d_ho(k, alpha, x, N1, N2, order, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
                 q=ORACLE_Q, ring=False):
-    """G at targets x[T,2] with f^(m) removed (NaN beyond the far slab); order 1 is Algorithm 2.1.
+    """G at targets x[T,2] with f^(m) removed; order 1 is Algorithm 2.1 (far targets: the series).
     ``ring``: K interpolated in the cut-off ring (see above)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2 = 2 * N1, 2 * N2
@@ -168,6 +168,6 @@ def eval_g2d_ho(k, alpha, x, N1, N2, far_h, far_S, order, c=co.C, c_tilde=co.C_T
                 g[zn] = np.einsum("ta,tb,tab->t", w1[zn], w2[zn], vals[zn] + fn)
         out[near] = np.exp(1j * alpha * x[near, 0]) * g
     if (~near).any():
-        # beyond c nothing is removed: the far slab of Algorithm 2.1
-        out[~near] = eval_g2d(k, alpha, x[~near], N1, N2, far_h, far_S, c, c_tilde, eps, q)
+        # beyond c nothing is removed: the series (1.2), as in Algorithm 2.1
+        out[~near] = eval_g2d(k, alpha, x[~near], N1, N2, c, c_tilde, eps, q)
     return out

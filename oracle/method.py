@@ -18,11 +18,16 @@ step by step in the paper's order:
    near/far branch on |x_t| <= c (step 2b), tensor-product 4-point Lagrange
    interpolation (the 16- and 64-point stencils of Sections 2.3 and 3.3), exact
    add-back of the singular part and the quasi-periodic phase.
-   The far branch (|x_t| > c), where the paper sums the eigenfunction series,
-   uses a far slab: the series' own per-slice coefficients
-   (i/4pi) beta^-1 e^{i beta z} (2D) or (i/8pi^2) beta^-1 e^{i beta z} (3D),
-   turned into grids over the periodic axes by direct DFT and interpolated the
-   same way.
+   The far branch (|x_t| > c) sums the eigenfunction series itself, as step 2b
+   of Algorithms 2.1, 3.1 and 4.1 prescribes: (1.2) for G, (1.3) for G_d and
+   (1.3) differentiated term by term for the Maxwell tensor, each with its
+   explicit tail bound (``truth``).
+6. Maxwell (Algorithm 4.1): L_d and the six second-derivative fields
+   L^{pq}, pq = 11, 22, 33, 12, 13, 23, each interpolated ("seven
+   interpolation processes", Section 4).  ``trace33=True`` is the variant that
+   drops the 33 field and takes GG_33 = 2 G_d - GG_11 - GG_22 from the trace
+   (tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice); it is an
+   option, not Algorithm 4.1.
 
 Readings of the paper taken here (its silent or garbled points):
 * cut-offs: C^8 smoothstep (see ``cutoffs``), c = 0.6, c~ = 1, eps = 0.2;
@@ -47,6 +52,7 @@ import numpy as np
 from scipy.special import j0 as bessel_j0, j1 as bessel_j1
 
 from . import cutoffs as co
+from . import truth
 from .truth import beta
 
 ORACLE_Q = 160          # Gauss-Legendre nodes for every 1D integral
@@ -200,14 +206,6 @@ def grid_2d(Lhat, c_tilde=co.C_TILDE):
     return A2 * dft_matrix(M1 // 2) @ Lhat @ dft_matrix(M2 // 2).T
 
 
-def far_grid_2d(k, alpha, N1, z):
-    """Far-slab grid [S, 2N1]: (i/4pi) sum_n beta_n^-1 e^{i beta_n z_s} e^{i n x1_p} (series 1.2)."""
-    a = alpha + np.arange(-N1, N1, dtype=np.float64)
-    b = beta(k, a)
-    coef = 1j / (4 * math.pi) * np.exp(1j * np.outer(z, b)) / b      # [S, M1]
-    return coef @ dft_matrix(N1).T
-
-
 def _reduce(x):
     """x = 2 pi n + t with t in [-pi, pi) (Alg. 2.1 step 2c)."""
     n = np.floor((x + math.pi) / (2 * math.pi))
@@ -222,33 +220,18 @@ def _stencil(u, M):
     return idx, lagrange4(f)
 
 
-def _far_stencil(z, hf, S, c=co.C):
-    """Far-slab transverse stencil: slices z_s = c - hf + s hf, s in [0, S)."""
-    v = (z - (c - hf)) / hf
-    s0 = np.floor(v)
-    bad = s0 > S - 3
-    s0 = np.clip(s0, 1, S - 3)
-    idx = s0.astype(np.int64)[:, None] + np.arange(-1, 3)[None, :]
-    return idx, lagrange4(v - s0), bad
-
-
-def far_slices(hf, S, c=co.C):
-    return c - hf + hf * np.arange(S, dtype=np.float64)
-
-
-def eval_g2d(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS,
-             q=ORACLE_Q, F=None, return_parts=False):
-    """Algorithm 2.1 at targets x[T,2]; G_N(x) (NaN beyond the far slab)."""
+def eval_g2d(k, alpha, x, N1, N2, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORACLE_Q, F=None):
+    """Algorithm 2.1 at targets x[T,2]; G_N(x).  Far targets (|x2| > c): the series (1.2)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2 = 2 * N1, 2 * N2
     h1, h2 = math.pi / N1, c_tilde / N2
-    grid = grid_2d(lhat_2d(k, alpha, N1, N2, c, c_tilde, eps, q, F), c_tilde)   # [p1, p2]
     t, _ = _reduce(x[:, 0])
     x2 = x[:, 1]
     out = np.full(len(x), np.nan + 0j)
     near = np.abs(x2) <= c
     # near: bicubic on L_N, then K_N = L_N + f1 - i alpha f2, G = e^{i alpha x1} K_N
     if near.any():
+        grid = grid_2d(lhat_2d(k, alpha, N1, N2, c, c_tilde, eps, q, F), c_tilde)   # [p1, p2]
         tn, zn = t[near], x2[near]
         i1, w1 = _stencil((tn + math.pi) / h1, M1)
         i2, w2 = _stencil((zn + c_tilde) / h2, M2)
@@ -259,16 +242,8 @@ def eval_g2d(k, alpha, x, N1, N2, far_h, far_S, c=co.C, c_tilde=co.C_TILDE, eps=
         out[near] = np.exp(1j * alpha * x[near, 0]) * (L + sing)
     far = ~near
     if far.any():
-        zf = far_slices(far_h, far_S, c)
-        fg = far_grid_2d(k, alpha, N1, zf)                    # [s, p1]
-        tf, z = t[far], np.abs(x2[far])
-        i1, w1 = _stencil((tf + math.pi) / h1, M1)
-        i2, w2, bad = _far_stencil(z, far_h, far_S, c)
-        vals = fg[i2[:, None, :], i1[:, :, None]]
-        L = np.einsum("ta,tb,tab->t", w1, w2, vals)
-        g = np.exp(1j * alpha * x[far, 0]) * L
-        g[bad] = np.nan
-        out[far] = g
+        # step 2b: |x2| > c takes the eigenfunction series (1.2)
+        out[far] = truth.g2d(k, alpha, x[far])
     return out
 
 
@@ -342,20 +317,21 @@ def lhat_3d(k, a1, a2, N1, N2, N3, c=co.C, c_tilde=co.C_TILDE, eps=co.EPS, q=ORA
             - fhat_3d(k, a1, a2, N1, N2, N3, c_tilde, eps, q))
 
 
-# The second-derivative fields the method carries (Algorithm 4.1): 11, 22, 12, 13, 23.  GG_33
-# follows from the trace, GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the
-# Helmholtz equation, off the lattice), which spares a field and the x3 truncation error of a
-# direct 33 field (whose coefficients carry (j3 pi / c~)^2 against the cut-off X in x3).
-FIELD_PAIRS = ((0, 0), (1, 1), (0, 1), (0, 2), (1, 2))
+# The second-derivative fields of Algorithm 4.1: L^{pq} for pq = 11, 22, 33, 12, 13, 23 (the
+# order of the Maxwell output).  TRACE_PAIRS is the option that drops the 33 field and takes
+# GG_33 from the trace, GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz
+# equation, off the lattice).
+FIELD_PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+TRACE_PAIRS = ((0, 0), (1, 1), (0, 1), (0, 2), (1, 2))
 
 
-def maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde=co.C_TILDE):
-    """-c^p c^q for the field pairs 11, 22, 12, 13, 23 (Section 4), each [2N1,2N2,2N3]."""
+def maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde=co.C_TILDE, pairs=FIELD_PAIRS):
+    """-c^p c^q for the given field pairs (Section 4), each [2N1,2N2,2N3]."""
     c1 = (a1 + np.arange(-N1, N1, dtype=np.float64))[:, None, None]
     c2 = (a2 + np.arange(-N2, N2, dtype=np.float64))[None, :, None]
     c3 = (np.arange(-N3, N3, dtype=np.float64) * math.pi / c_tilde)[None, None, :]
     cc = (c1, c2, c3)
-    return [-(cc[p] * cc[q]) for p, q in FIELD_PAIRS]
+    return [-(cc[p] * cc[q]) for p, q in pairs]
 
 
 def grid_3d(Lhat, c_tilde=co.C_TILDE):
@@ -368,31 +344,11 @@ def grid_3d(Lhat, c_tilde=co.C_TILDE):
     return A3 * np.transpose(g, (2, 1, 0))
 
 
-def far_grid_3d(k, a1, a2, N1, N2, z, mult=None):
-    """Far-slab grids [S, 2N1, 2N2] of (i/8pi^2) beta^-1 e^{i beta z_s} (series 1.3).
-
-    ``mult(xi1, xi2, beta)`` optionally multiplies each coefficient (Maxwell).
-    """
-    xi1 = (a1 + np.arange(-N1, N1, dtype=np.float64))[:, None]
-    xi2 = (a2 + np.arange(-N2, N2, dtype=np.float64))[None, :]
-    b = beta(k, np.sqrt(xi1 ** 2 + xi2 ** 2))
-    m = 1.0 if mult is None else mult(xi1, xi2, b)
-    E1, E2 = dft_matrix(N1), dft_matrix(N2)
-    out = np.empty((len(z), 2 * N1, 2 * N2), dtype=np.complex128)
-    for s, zs in enumerate(z):
-        coef = 1j / (8 * math.pi ** 2) * m * np.exp(1j * b * zs) / b
-        out[s] = E1 @ coef @ E2.T
-    return out
-
-
-def _interp3(grids, i1, w1, i2, w2, i3, w3, slice_first=False):
+def _interp3(grids, i1, w1, i2, w2, i3, w3):
     """Tensor Lagrange over 64 nodes for each grid in ``grids``."""
     res = []
     for g in grids:
-        if slice_first:
-            v = g[i3[:, None, None, :], i1[:, :, None, None], i2[:, None, :, None]]
-        else:
-            v = g[i1[:, :, None, None], i2[:, None, :, None], i3[:, None, None, :]]
+        v = g[i1[:, :, None, None], i2[:, None, :, None], i3[:, None, None, :]]
         res.append(np.einsum("ta,tb,tc,tabc->t", w1, w2, w3, v))
     return res
 
@@ -406,21 +362,16 @@ def _psi_derivs(k, r, eps):
     return g * y, g1 * y + g * y1, g2 * y + 2 * g1 * y1 + g * y2
 
 
-def prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
+def prepare_3d(k, a1, a2, N1, N2, N3, maxwell=False, trace33=False, c=co.C, c_tilde=co.C_TILDE,
                eps=co.EPS, q=ORACLE_Q):
-    """Algorithm 3.1 / 4.1 step 1: the near grids (1 or 6 fields) and the far-slab grids."""
+    """Algorithm 3.1 / 4.1 step 1: the near grids (L_d; for Maxwell also the six fields L^{pq},
+    or five with ``trace33``)."""
     L = lhat_3d(k, a1, a2, N1, N2, N3, c, c_tilde, eps, q)
-    fields = [L] + ([m * L for m in maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde)] if maxwell else [])
+    pairs = TRACE_PAIRS if trace33 else FIELD_PAIRS
+    fields = [L] + ([m * L for m in maxwell_multipliers(a1, a2, N1, N2, N3, c_tilde, pairs)] if maxwell else [])
     grids = [grid_3d(f, c_tilde) for f in fields]
-    z = far_slices(far_h, far_S, c)
-    mults = [None]
-    if maxwell:
-        def mk(p, qq):
-            return lambda xi1, xi2, b: -((xi1, xi2, b)[p] * (xi1, xi2, b)[qq])
-        mults += [mk(p, qq) for p, qq in FIELD_PAIRS]
-    fgrids = [far_grid_3d(k, a1, a2, N1, N2, z, m) for m in mults]
-    return dict(k=k, a1=a1, a2=a2, N=(N1, N2, N3), far_h=far_h, far_S=far_S, maxwell=maxwell, c=c,
-                c_tilde=c_tilde, eps=eps, grids=grids, fgrids=fgrids)
+    return dict(k=k, a1=a1, a2=a2, N=(N1, N2, N3), maxwell=maxwell, pairs=pairs if maxwell else (), c=c,
+                c_tilde=c_tilde, eps=eps, grids=grids)
 
 
 def evaluate_3d(st, x):
@@ -430,9 +381,7 @@ def evaluate_3d(st, x):
     """
     k, a1, a2, c, c_tilde, eps = st["k"], st["a1"], st["a2"], st["c"], st["c_tilde"], st["eps"]
     N1, N2, N3 = st["N"]
-    far_h, far_S, maxwell = st["far_h"], st["far_S"], st["maxwell"]
-    grids, fgrids = st["grids"], st["fgrids"]
-    nfield = len(grids)
+    maxwell, pairs, grids = st["maxwell"], st["pairs"], st["grids"]
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     M1, M2, M3 = 2 * N1, 2 * N2, 2 * N3
     h1, h2, h3 = math.pi / N1, math.pi / N2, c_tilde / N3
@@ -440,8 +389,7 @@ def evaluate_3d(st, x):
     t2, n2 = _reduce(x[:, 1])
     x3 = x[:, 2]
     T = len(x)
-    vals = np.full((T, nfield), np.nan + 0j)
-    phase = np.exp(1j * (a1 * x[:, 0] + a2 * x[:, 1]))
+    out = np.full((T, 6 if maxwell else 1), np.nan + 0j)
     near = np.abs(x3) <= c
     if near.any():
         i1, w1 = _stencil((t1[near] + math.pi) / h1, M1)
@@ -451,30 +399,37 @@ def evaluate_3d(st, x):
         tt = np.stack([t1[near], t2[near], x3[near]], axis=1)
         r = np.linalg.norm(tt, axis=1)
         psi, d1, d2 = _psi_derivs(k, r, eps)
+        phase = np.exp(1j * (a1 * x[near, 0] + a2 * x[near, 1]))
         lat = np.exp(2j * math.pi * (a1 * n1[near] + a2 * n2[near]))
-        vals[near, 0] = phase[near] * Ls[0] + lat * psi
-        for f, (p, qq) in enumerate(FIELD_PAIRS[: nfield - 1]):
-            tp, tq = tt[:, p], tt[:, qq]
-            hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
-            vals[near, f + 1] = phase[near] * Ls[f + 1] + lat * hess
+        # steps 2e/2g: G_d = e^{i alpha.x'} (L_dN + F); steps 2f/2h: d_p d_q G_d likewise with F^{pq}
+        G = phase * Ls[0] + lat * psi
+        if not maxwell:
+            out[near, 0] = G
+        else:
+            dd = {}
+            for f, (p, qq) in enumerate(pairs):
+                tp, tq = tt[:, p], tt[:, qq]
+                hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
+                dd[(p, qq)] = phase * Ls[f + 1] + lat * hess
+            out[near] = _assemble(k, G, dd)
     far = ~near
     if far.any():
-        i1, w1 = _stencil((t1[far] + math.pi) / h1, M1)
-        i2, w2 = _stencil((t2[far] + math.pi) / h2, M2)
-        i3, w3, bad = _far_stencil(np.abs(x3[far]), far_h, far_S, c)
-        Ls = _interp3(fgrids, i1, w1, i2, w2, i3, w3, slice_first=True)
-        sg = np.sign(x3[far])
-        for f in range(nfield):
-            v = phase[far] * Ls[f]
-            if f >= 1 and 2 in FIELD_PAIRS[f - 1]:
-                v = v * sg                     # d/dx3 of e^{i beta |x3|} brings sgn(x3)
-            v[bad] = np.nan
-            vals[far, f] = v
-    if not maxwell:
-        return vals[:, 0]
-    G, d = vals[:, 0], vals[:, 1:] / k ** 2          # d: k^-2 d_p d_q G_d for 11, 22, 12, 13, 23
-    g11, g22 = G + d[:, 0], G + d[:, 1]
-    return np.stack([g11, g22, 2 * G - g11 - g22, d[:, 2], d[:, 3], d[:, 4]], axis=1)
+        # step 2b: |x3| > c takes the series (1.3), for Maxwell differentiated term by term
+        xf = x[far]
+        if not maxwell:
+            out[far, 0] = truth.gd3d(k, a1, a2, xf)
+        else:
+            out[far] = truth.maxwell3d(k, a1, a2, xf)
+    return out[:, 0] if not maxwell else out
+
+
+def _assemble(k, G, dd):
+    """GG_pq = delta_pq G_d + k^-2 d_p d_q G_d (eq. 4.1) in the order 11, 22, 33, 12, 13, 23; without a 33
+    field (the trace option) GG_33 = 2 G_d - GG_11 - GG_22."""
+    g11 = G + dd[(0, 0)] / k ** 2
+    g22 = G + dd[(1, 1)] / k ** 2
+    g33 = G + dd[(2, 2)] / k ** 2 if (2, 2) in dd else 2 * G - g11 - g22
+    return np.stack([g11, g22, g33, dd[(0, 1)] / k ** 2, dd[(0, 2)] / k ** 2, dd[(1, 2)] / k ** 2], axis=1)
 
 
 def smooth_3d(st, x):
@@ -498,16 +453,16 @@ def smooth_3d(st, x):
     return out
 
 
-def eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, c=co.C, c_tilde=co.C_TILDE,
+def eval_3d(k, a1, a2, x, N1, N2, N3, maxwell=False, trace33=False, c=co.C, c_tilde=co.C_TILDE,
             eps=co.EPS, q=ORACLE_Q):
     """Algorithm 3.1 (G_d, returns [T]) or Algorithm 4.1 (Maxwell, returns [T,6])."""
-    st = prepare_3d(k, a1, a2, N1, N2, N3, far_h, far_S, maxwell, c, c_tilde, eps, q)
+    st = prepare_3d(k, a1, a2, N1, N2, N3, maxwell, trace33, c, c_tilde, eps, q)
     return evaluate_3d(st, x)
 
 
-def eval_gd3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, **kw):
-    return eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=False, **kw)
+def eval_gd3d(k, a1, a2, x, N1, N2, N3, **kw):
+    return eval_3d(k, a1, a2, x, N1, N2, N3, maxwell=False, **kw)
 
 
-def eval_maxwell3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, **kw):
-    return eval_3d(k, a1, a2, x, N1, N2, N3, far_h, far_S, maxwell=True, **kw)
+def eval_maxwell3d(k, a1, a2, x, N1, N2, N3, trace33=False, **kw):
+    return eval_3d(k, a1, a2, x, N1, N2, N3, maxwell=True, trace33=trace33, **kw)

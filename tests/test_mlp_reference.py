@@ -73,7 +73,7 @@ def test_smooth_part_plus_add_back_is_the_method():
     """G_d = e^{i alpha.x'} L_N + e^{i 2 pi alpha.n} psi (Algorithm 3.1 step 2e), with L_N from smooth_3d,
     reproduces evaluate_3d in the near region; far targets give NaN."""
     k, a1, a2 = 3.7, 0.2, 0.35
-    st = method.prepare_3d(k, a1, a2, 8, 8, 8, 0.05, 12)
+    st = method.prepare_3d(k, a1, a2, 8, 8, 8)
     rng = np.random.default_rng(8)
     x = np.column_stack([rng.uniform(-7, 7, 400), rng.uniform(-7, 7, 400), rng.uniform(-1, 1, 400)])
     x[:20, :2] = 2 * math.pi * rng.integers(-1, 2, (20, 2)) + rng.uniform(-0.05, 0.05, (20, 2))

@@ -16,11 +16,6 @@ from oracle import grad2d, method, truth
 K2, AL2 = 2.1, 0.3
 
 
-def _far(N_t):
-    hf = 1.0 / N_t
-    return hf, math.ceil(0.4 / hf) + 4
-
-
 # ---------------------------------------------------------------- the singular parts h1, h2
 
 def _annulus_residual(r0, k, alpha, printed_h2=False):
@@ -107,14 +102,13 @@ def test_g2d_grad_series_symmetries():
     assert np.allclose(gm[:, 1], -g[:, 1], rtol=1e-13, atol=0)
 
 
-def test_far_slab_grad_matches_series():
-    # Far branch: the far-slab grids of the differentiated coefficients, interpolated
-    # (a derivative weighs mode n by |n|, so both axes are twice as fine as for G).
+def test_far_branch_is_the_differentiated_series():
+    # Section 2.4.1 / Algorithm 2.1 step 2b: beyond |x2| = c the derivatives are those of the series
+    # (1.2) itself; at |x2| = c the target is near (the method's grid, which differs from the series).
     x = np.array([[0.3, 0.7], [2.0, -0.95], [5.0, 0.61], [1.1, -0.8]])
-    gt = truth.g2d_grad(K2, AL2, x)
-    e = [np.max(np.abs(grad2d.eval_g2d_grad(K2, AL2, x, N1, N2, *_far(N2)) - gt) / np.abs(gt))
-         for N1, N2 in ((128, 32), (256, 64))]
-    assert e[1] < 1e-6 and e[1] < e[0] / 8
+    np.testing.assert_array_equal(grad2d.eval_g2d_grad(K2, AL2, x, 64, 32), truth.g2d_grad(K2, AL2, x))
+    xb = np.array([[0.3, 0.6], [0.3, -0.6]])
+    assert np.all(grad2d.eval_g2d_grad(K2, AL2, xb, 64, 32) != truth.g2d_grad(K2, AL2, xb))
 
 
 def test_g2d_grad_method_converges_to_truth():
@@ -126,7 +120,7 @@ def test_g2d_grad_method_converges_to_truth():
     gt = truth.g2d_grad(K2, AL2, x)
     errs, meds = [], []
     for N1, N2 in ((64, 32), (128, 64)):
-        g = grad2d.eval_g2d_grad(K2, AL2, x, N1, N2, *_far(N2))
+        g = grad2d.eval_g2d_grad(K2, AL2, x, N1, N2)
         e = np.abs(g - gt) / np.abs(gt)
         errs.append(e.max())
         meds.append(np.median(e))

@@ -45,8 +45,8 @@ def test_remainder_order_per_removed_degree(k, alpha):
 
 def test_order_one_is_algorithm_2_1():
     x = np.array([[0.1, 0.05], [-0.2, 0.3], [2.0, -0.4], [0.5, 0.8], [1.0, -0.9]])
-    a = ho.eval_g2d_ho(K, AL, x, 32, 16, 1.0 / 16, 12, 1)
-    b = method.eval_g2d(K, AL, x, 32, 16, 1.0 / 16, 12)
+    a = ho.eval_g2d_ho(K, AL, x, 32, 16, 1)
+    b = method.eval_g2d(K, AL, x, 32, 16)
     assert np.array_equal(a, b)
 
 
@@ -92,7 +92,7 @@ def test_higher_order_converges_faster_near_the_lattice_point():
     err = {}
     for order in (1, 3):
         for N1, N2 in ((128, 64), (256, 128)):
-            g = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, order)
+            g = ho.eval_g2d_ho(K, AL, x, N1, N2, order)
             err[order, N1] = np.abs(g - gt).max()
     assert err[3, 128] < err[1, 128] / 10
     assert err[3, 256] < err[1, 256] / 100
@@ -106,7 +106,7 @@ def test_higher_order_elsewhere_no_worse():
                          rng.uniform(0.02, 0.55, 60) * rng.choice([-1.0, 1.0], 60)])
     x = np.vstack([x, [[1.0, 0.8], [-2.0, -0.7]]])                 # two far-branch targets
     gt = truth.g2d(K, AL, x)
-    e1 = np.abs(ho.eval_g2d_ho(K, AL, x, 128, 64, 1.0 / 64, 30, 1) - gt) / np.abs(gt)
-    e3 = np.abs(ho.eval_g2d_ho(K, AL, x, 128, 64, 1.0 / 64, 30, 3) - gt) / np.abs(gt)
+    e1 = np.abs(ho.eval_g2d_ho(K, AL, x, 128, 64, 1) - gt) / np.abs(gt)
+    e3 = np.abs(ho.eval_g2d_ho(K, AL, x, 128, 64, 3) - gt) / np.abs(gt)
     assert np.median(e3) <= 1.05 * np.median(e1) and e3.max() <= 1.05 * e1.max()
     assert np.array_equal(e1[-2:], e3[-2:])

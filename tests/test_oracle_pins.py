@@ -279,11 +279,6 @@ def test_lagrange_exact_on_cubics_and_nodes():
 
 # ---------------------------------------------------------------- whole chain vs truth
 
-def _far(N_t):
-    hf = 1.0 / N_t
-    return hf, math.ceil(0.4 / hf) + 4
-
-
 def test_g2d_method_converges_to_truth():
     rng = np.random.default_rng(7)
     x = np.stack([rng.uniform(0, 2 * math.pi, 16), rng.uniform(-1, 1, 16)], 1)
@@ -291,7 +286,7 @@ def test_g2d_method_converges_to_truth():
     gt = truth.g2d(K2, AL2, x)
     errs = []
     for N1, N2 in ((128, 32), (256, 64)):
-        g = method.eval_g2d(K2, AL2, x, N1, N2, *_far(N2))
+        g = method.eval_g2d(K2, AL2, x, N1, N2)
         errs.append(np.max(np.abs(g - gt) / np.abs(gt)))
     assert errs[0] < 5e-3
     assert errs[1] < errs[0] / 4 and errs[1] < 1e-3
@@ -305,7 +300,7 @@ def test_gd3d_method_converges_to_truth():
     gt = truth.gd3d(K3, A31, A32, x)
     errs = []
     for N, N3 in ((16, 16), (32, 32)):
-        g = method.eval_gd3d(K3, A31, A32, x, N, N, N3, *_far(N3))
+        g = method.eval_gd3d(K3, A31, A32, x, N, N, N3)
         errs.append(np.max(np.abs(g - gt) / np.abs(gt)))
     assert errs[1] < errs[0] / 4 and errs[1] < 2e-2
 
@@ -318,17 +313,21 @@ def test_maxwell_method_against_truth():
     gt = truth.maxwell3d(K3, A31, A32, x)
     rel = []
     for N in (32, 48):
-        g = method.eval_maxwell3d(K3, A31, A32, x, N, N, N, *_far(N))
+        g = method.eval_maxwell3d(K3, A31, A32, x, N, N, N)
         rel.append((np.abs(g - gt).max(axis=1) / np.abs(gt).max(axis=1)).max())
     assert rel[1] < 2e-3 and rel[1] < rel[0] / 4
 
 
-def test_far_slab_matches_series():
-    # Far branch: the far-slab grid of the series' own coefficients, interpolated.
+def test_far_branch_is_the_series():
+    # Algorithms 2.1, 3.1, 4.1 step 2b: beyond |x_t| = c the series itself, (1.2), (1.3) and (1.3)
+    # differentiated term by term; |x_t| = c exactly is near (R8).
     x = np.array([[0.3, 0.7], [2.0, -0.95], [5.0, 0.61]])
-    gt = truth.g2d(K2, AL2, x)
-    g = method.eval_g2d(K2, AL2, x, 128, 32, *_far(32))
-    assert np.max(np.abs(g - gt) / np.abs(gt)) < 1e-6
+    np.testing.assert_array_equal(method.eval_g2d(K2, AL2, x, 32, 16), truth.g2d(K2, AL2, x))
+    xb = np.array([[0.3, 0.6], [0.3, -0.6]])
+    assert np.all(method.eval_g2d(K2, AL2, xb, 32, 16) != truth.g2d(K2, AL2, xb))
+    x3 = np.array([[0.3, 1.1, 0.7], [2.0, -4.0, -0.95]])
+    np.testing.assert_array_equal(method.eval_gd3d(K3, A31, A32, x3, 8, 8, 8), truth.gd3d(K3, A31, A32, x3))
+    np.testing.assert_array_equal(method.eval_maxwell3d(K3, A31, A32, x3, 8, 8, 8), truth.maxwell3d(K3, A31, A32, x3))
 
 
 # ---------------------------------------------------------------- the paper's printed errors
@@ -349,6 +348,6 @@ def test_paper_table_points_2d_order_of_magnitude():
     for tab, k, al, N, p, x1, x2, err in _golden("paper_tables_2d.txt"):
         k, al, N, x1, x2, err = float(k), float(al), int(N), float(x1), float(x2), float(err)
         x = np.array([[x1, x2]])
-        g = method.eval_g2d(k, al, x, N, N, *_far(N))
+        g = method.eval_g2d(k, al, x, N, N)
         ours = abs(g[0] - truth.g2d(k, al, x)[0]) / abs(truth.g2d(k, al, x)[0])
         assert ours < 10 * err, (tab, N, p, ours, err)

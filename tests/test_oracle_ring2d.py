@@ -31,8 +31,8 @@ def test_ring_agrees_with_plain_form_at_grid_nodes(order):
     h1, h2 = math.pi / N1, 1.0 / N2
     p = np.array([[5, 4], [-6, 5], [3, -9], [-2, -10], [7, 2]])        # r between 0.22 and 0.35
     x = p * [h1, h2]
-    a = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, 17, order)
-    b = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, 17, order, ring=True)
+    a = ho.eval_g2d_ho(K, AL, x, N1, N2, order)
+    b = ho.eval_g2d_ho(K, AL, x, N1, N2, order, ring=True)
     assert np.all(ho.ring_zone(x[:, 0], x[:, 1], h1, h2))
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
 
@@ -42,8 +42,8 @@ def test_ring_changes_only_ring_targets():
     h1, h2 = math.pi / N1, 1.0 / N2
     rng = np.random.default_rng(2)
     x = np.column_stack([rng.uniform(-math.pi, math.pi, 400), rng.uniform(-0.9, 0.9, 400)])
-    a = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, 17, 3)
-    b = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, 17, 3, ring=True)
+    a = ho.eval_g2d_ho(K, AL, x, N1, N2, 3)
+    b = ho.eval_g2d_ho(K, AL, x, N1, N2, 3, ring=True)
     t = x[:, 0]
     near = np.abs(x[:, 1]) <= 0.6
     zone = near & ho.ring_zone(t, x[:, 1], h1, h2)
@@ -62,7 +62,7 @@ def test_ring_accuracy_against_the_series():
     err = {}
     for ring in (False, True):
         for N1, N2 in ((128, 64), (256, 128)):
-            g = ho.eval_g2d_ho(K, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, 3, ring=ring)
+            g = ho.eval_g2d_ho(K, AL, x, N1, N2, 3, ring=ring)
             err[ring, N1] = np.max(np.abs(g - gt) / np.abs(gt))
     assert err[True, 256] < err[False, 256] / 100
     assert err[True, 256] < 5e-6
@@ -77,8 +77,8 @@ def test_grad_ring_agrees_with_plain_form_at_grid_nodes():
     h1, h2 = math.pi / N1, 1.0 / N2
     p = np.array([[5, 4], [-6, 5], [3, -9], [-2, -10], [7, 2]])
     x = p * [h1, h2]
-    a = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, 17)
-    b = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, 17, ring=True)
+    a = grad2d.eval_g2d_grad(K, AL, x, N1, N2)
+    b = grad2d.eval_g2d_grad(K, AL, x, N1, N2, ring=True)
     assert np.all(ho.ring_zone(x[:, 0], x[:, 1], h1, h2))
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
 
@@ -91,7 +91,7 @@ def test_grad_ring_accuracy_against_the_series():
     err = {}
     for ring in (False, True):
         for N1, N2 in ((128, 64), (256, 128)):
-            g = grad2d.eval_g2d_grad(K, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, ring=ring)
+            g = grad2d.eval_g2d_grad(K, AL, x, N1, N2, ring=ring)
             err[ring, N1] = np.max(np.abs(g - gt) / np.abs(gt))
     assert err[True, 256] < err[False, 256] / 15
     assert err[True, 256] < 5e-5
@@ -106,8 +106,8 @@ def test_hess_ring_agrees_with_plain_form_at_grid_nodes():
     h1, h2 = math.pi / N1, 1.0 / N2
     p = np.array([[5, 4], [-6, 5], [3, -9], [-2, -10], [7, 2]])
     x = p * [h1, h2]
-    a = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, 17)
-    b = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, 17, ring=True)
+    a = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2)
+    b = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, ring=True)
     assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
 
 
@@ -119,7 +119,7 @@ def test_hess_ring_accuracy_against_the_series():
     err = {}
     for ring in (False, True):
         for N1, N2 in ((128, 64), (256, 128)):
-            g = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, 1.0 / N2, math.ceil(0.4 * N2) + 4, ring=ring)
+            g = hess2d.eval_g2d_hess_diff(K, 4.35, AL, x, N1, N2, ring=ring)
             err[ring, N1] = np.max(np.abs(g - gt) / np.abs(gt), axis=0)
     assert np.all(err[True, 256] < err[False, 256] / 15)
     assert np.all(err[True, 256] < 5e-5)

@@ -91,6 +91,6 @@ def test_method_at_a_special_instance_converges_to_truth():
     errs = []
     for N1, N2 in ((128, 32), (256, 64)):
         hf = 1.0 / N2
-        g = method.eval_g2d(K2S, AL2, x, N1, N2, hf, math.ceil(0.4 / hf) + 4)
+        g = method.eval_g2d(K2S, AL2, x, N1, N2)
         errs.append(np.max(np.abs(g - gt) / np.abs(gt)))
     assert errs[0] < 5e-3 and errs[1] < errs[0] / 4 and errs[1] < 1e-3
