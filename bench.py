@@ -73,7 +73,7 @@ def cpu_baseline(x_np, info, n_sample):
     import threadpoolctl
     from oracle import method
     t0 = time.perf_counter()
-    st = method.prepare_3d(K, A1, A2, info.m1 // 2, info.m2 // 2, info.m3 // 2, info.far_h, info.far_slices)
+    st = method.prepare_3d(K, A1, A2, info.m1 // 2, info.m2 // 2, info.m3 // 2)
     t1 = time.perf_counter()
     method.evaluate_3d(st, x_np[:n_sample])
     t2 = time.perf_counter()

@@ -17,8 +17,13 @@
  * period cell, interpolates the grid with the 4-point cubic Lagrange rule per
  * axis (16 / 64 points) and adds back the removed singular part exactly and the
  * quasi-periodic phase.  Targets with |x_t| > c (x_t = x2 in 2D, x3 in 3D) take
- * the far branch: a grid of the eigenfunction series itself on slices
- * z_s = c - h_f + s h_f, s = 0 .. S_f-1, interpolated the same way.
+ * the far branch, where step 2b of the algorithms uses the eigenfunction series
+ * itself: the series' terms are summed by inverse FFT on a far slab of slices
+ * z_s = c - 3 h_f + s h_f, s = 0 .. S_f-1, with far_m modes per periodic axis,
+ * and the slab is interpolated with the 8-point Lagrange rule per axis (64 / 512
+ * nodes).  No singular part exists there; with the defaults (far_m >= 256,
+ * h_f <= c~/64) the far branch agrees with the direct sum of the series to about
+ * 1e-11 relative for k up to about 6.
  *
  * Conventions for every entry point:
  *  - All bulk arrays (targets, outputs, flags) are DEVICE pointers owned by the
@@ -31,16 +36,15 @@
  *  - Targets are float64, row-major [T][dim].  Outputs are interleaved complex
  *    (re, im) in the caller's target order: complex128 when the plan precision is
  *    QPGF_C128, complex64 when QPGF_C64.  Maxwell outputs are [T][6] complex in
- *    the order 11, 22, 33, 12, 13, 23; the plan carries the fields of G_d and of its
- *    second derivatives 11, 22, 12, 13, 23 (Algorithm 4.1), and GG_33 follows from the
- *    trace, GG_11 + GG_22 + GG_33 = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz
- *    equation off the lattice), one field fewer than the direct 33 field and free of
- *    its x3 truncation error.
+ *    the order 11, 22, 33, 12, 13, 23.  The plan carries the seven fields of
+ *    Algorithm 4.1 (L_d and L^{pq} for pq = 11, 22, 33, 12, 13, 23), unless
+ *    params.maxwell_trace asks for the six-field variant.
  *  - Per-target flags (optional, may be NULL), uint8 [T]:
  *      bit 0  the target lies within params.lattice_rmin of a lattice point
  *             (output NaN); with lattice_rmin = 0 only an exact hit is flagged,
  *      bit 1  far branch (|x_t| > c),
- *      bit 2  |x_t| beyond the far slab, i.e. > c + (S_f - 3) h_f (output NaN),
+ *      bit 2  |x_t| beyond the far slab, i.e. >= c + (S_f - 7) h_f (output NaN;
+ *             the slab covers |x_t| <= params.far_zmax),
  *      bit 3  non-finite target coordinate (output NaN).
  *  - On error the call returns a nonzero qpgf_status and qpgf_last_error()
  *    describes it; nothing is launched.
@@ -86,8 +90,9 @@ typedef enum {
  * (3D) and c_tilde/N_t in the transverse direction.
  * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
  * eps = 0.2, cut-offs: C^8 smoothstep I_u(9,9) transitions (Section 6 states C^8),
- * quad_q = 64, far_h = c_tilde / N_t, far_zmax = c_tilde, wood_tol = 1e-3,
- * special_tol = 1e-2, lattice_rmin = 0.
+ * quad_q = 64, far_h = 0 and far_m = 0 (the far slab's geometry follows each instance's
+ * wavenumber, see far_m), far_zmax = c_tilde, wood_tol = 1e-3, special_tol = 1e-2,
+ * lattice_rmin = 0, maxwell_trace = 0.
  * special_tol: a coefficient whose propagating beta lies within special_tol of |J|
  * (J = j_t pi / c~; the special cases of Sections 2.1 / 3.1, where the integration
  * by parts behind eqs. 2.1 / 3.3 divides by beta -+ J and loses digits close to it)
@@ -103,7 +108,7 @@ typedef struct {
   double c_tilde;          /* periodisation half-length in the transverse axis, c_tilde > c */
   double eps;              /* singular cut-off Y_eps: 1 on [0, eps], 0 beyond 2 eps; 2 eps <= c_tilde */
   int quad_q;              /* Gauss-Legendre nodes for the X'- and radial integrals, 16..256 */
-  double far_h;            /* far-slab slice spacing h_f (> 0) */
+  double far_h;            /* far-slab slice spacing h_f; 0: automatic, the largest 2^-j <= min(1/64, x/k) */
   double far_zmax;         /* largest |x_t| the far slab must cover */
   double wood_tol;
   double special_tol;
@@ -128,6 +133,22 @@ typedef struct {
                               (in FP64 for complex128, in FP32 for complex64).
                               0 (default): Algorithm 2.1 / Section 2.4 as printed.  Every
                               other kind, and qpgf_g2d_batched, require 0. */
+  int far_m;               /* modes per periodic axis of the far slab (a power of two in [16, 4096],
+                              complex128 x2 axis <= 2048); 0: automatic per prepared instance, the
+                              largest of m1 (3D: m2), a floor, and the smallest power of two >= 2 pi k / x,
+                              x = 0.0977 for complex128 and 0.3 for complex64 (k: the instance's largest
+                              wavenumber).  The floor is 256 modes, 512 for the complex128 Maxwell and
+                              derivative kinds.  The far slab holds the terms of the series with
+                              |j| < far_m / 2; the 8-point rule interpolates a term of wavenumber q to
+                              about (q h)^8 / 1000, h = 2 pi / far_m or h_f, which the automatic choice keeps
+                              near 1e-11 (complex128) or 1e-7 (complex64) relative.  The slab is allocated
+                              at plan creation for the smallest geometry and grown (synchronously) by
+                              an instance that needs more. */
+  int maxwell_trace;       /* QPGF_KIND_MAXWELL3D: 0 (default) carries the seven fields of Algorithm 4.1;
+                              1 drops the 33 field and takes GG_33 = 2 G_d - GG_11 - GG_22 from the trace
+                              (tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice: the Helmholtz
+                              equation); one transform and one interpolated field fewer, a different
+                              approximation of GG_33 near the plane.  Other kinds require 0. */
 } qpgf_params;
 
 typedef struct qpgf_plan qpgf_plan;
@@ -138,10 +159,13 @@ typedef struct {
   int far_slices;          /* S_f */
   double far_h;
   double c, c_tilde, eps;
-  int n_fields;            /* 1; 6 for Maxwell (L and L^{pq}, pq = 11 22 12 13 23);
-                              2 for G2D_GRAD; 3 for G2D_HESS_DIFF */
+  int n_fields;            /* near fields: 1; 7 for Maxwell (L and L^{pq}, pq = 11 22 33 12 13 23),
+                              6 with maxwell_trace (no 33); 2 for G2D_GRAD; 3 for G2D_HESS_DIFF */
   size_t grid_bytes;       /* bytes of one near-grid field */
   size_t far_grid_bytes;   /* bytes of one far-slab field */
+  int far_m1, far_m2;      /* far-slab modes per periodic axis (far_m2 = 1 in 2D) */
+  int far_fields;          /* far-slab fields: as n_fields, except Maxwell: 6, the tensor entries
+                              GG_pq of the series (11 22 33 12 13 23; 13 and 23 for x3 > 0) */
 } qpgf_plan_info;
 
 /* Fill *p with the defaults above for the given kind, precision and sizes. */
@@ -305,11 +329,14 @@ qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double
  * up to `stage`: 0 = coefficient fill (A L-hat_j with A the basis normalisation
  * 1/(2 sqrt(pi c~)) in 2D, 1/sqrt(8 pi^2 c~) in 3D, in FFT order: index j mod m
  * per axis), 1 = after the transverse inverse FFT, 2 = complete near grid
- * L_N(x_p) (grid point p mod m per axis, x = p h).  qpgf_copy_field copies field `field`
- * (0 = L, 1..6 = L^{pq} in the order 11,22,33,12,13,23) of the near grid buffer
- * (which = 0) or the far-slab buffer (which = 1) to the device pointer dst,
- * which must hold info.grid_bytes / info.far_grid_bytes.  Layout: [i3][i2][i1]
- * (3D) or [i2][i1] (2D) with i1 fastest; far slab: [s][i2][i1] or [s][i1]. */
+ * L_N(x_p) (grid point p mod m per axis, x = p h) and far slab.  qpgf_copy_field
+ * copies field `field` of the near grid buffer (which = 0; 0 = L, then L^{pq} in
+ * the order 11,22,33,12,13,23, without 33 under maxwell_trace) or of the far slab
+ * (which = 1; info.far_fields fields) to the device pointer dst, which must hold
+ * info.grid_bytes / info.far_grid_bytes.  Layout: [i3][i2][i1] (3D) or [i2][i1]
+ * (2D) with i1 fastest; far slab: [s][i2][i1] or [s][i1] on its own far_m1 x far_m2
+ * periodic grid, slice s at |x_t| = c - 3 h_f + s h_f; a far-slab value times
+ * e^{i alpha.x'} is the series (G, G_d or GG_pq) at that node. */
 qpgf_status qpgf_prepare_stage(qpgf_plan* plan, double k, double a1, double a2, int stage);
 qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst);
 

@@ -97,7 +97,7 @@ void free_plan(Plan& P) {
   if (P.b_capture) (void)hipStreamDestroy(P.b_capture);
   if (P.b_upload_done) (void)hipEventDestroy(P.b_upload_done);
   if (P.b_host) (void)hipHostFree(P.b_host);
-  for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI, P.farI})
+  for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI})
     if (q) (void)hipFree(q);
   void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.wXq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
                   P.twf,  P.F1,  P.F2,   P.D2, P.E2, P.ring_mask, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
@@ -129,7 +129,8 @@ qpgf_status validate(const qpgf_params* p) {
   if (p->quad_q < 16 || p->quad_q > 256) return fail(QPGF_E_ARG, "quad_q must be in [16, 256]");
   if (p->kind == QPGF_KIND_G2D_HESS_DIFF && p->quad_q > 128)
     return fail(QPGF_E_ARG, "quad_q must be <= 128 for QPGF_KIND_G2D_HESS_DIFF (two wavenumbers' weights in LDS)");
-  if (!(p->far_h > 0.0) || !(p->far_zmax >= p->c)) return fail(QPGF_E_ARG, "need far_h > 0 and far_zmax >= c");
+  if (!(p->far_h >= 0.0) || !(p->far_zmax >= p->c)) return fail(QPGF_E_ARG, "need far_h >= 0 and far_zmax >= c");
+  if (p->far_h > 0.0 && (p->far_zmax - p->c) / p->far_h > 65536.0) return fail(QPGF_E_ARG, "far_h too small");
   if (!(p->wood_tol >= 0.0) || !(p->special_tol >= 0.0) || !(p->lattice_rmin >= 0.0))
     return fail(QPGF_E_ARG, "tolerances must be >= 0");
   if (!(p->special_tol < 0.25 * M_PI / p->c_tilde))
@@ -139,7 +140,79 @@ qpgf_status validate(const qpgf_params* p) {
   if (p->ring_interp != 0 && p->ring_interp != 1) return fail(QPGF_E_ARG, "ring_interp must be 0 or 1");
   if (p->ring_interp && p->kind != QPGF_KIND_G2D && p->kind != QPGF_KIND_G2D_GRAD && p->kind != QPGF_KIND_G2D_HESS_DIFF)
     return fail(QPGF_E_ARG, "ring_interp needs a 2D kind");
+  if (p->far_m != 0) {
+    if (!pow2_in(p->far_m, 16, 4096)) return fail(QPGF_E_SIZE, "far_m must be 0 or a power of two in [16, 4096]");
+    if (!kind_is_2d(p->kind) && p->prec == QPGF_C128 && p->far_m > 2048)
+      return fail(QPGF_E_SIZE, "complex128 3D plans: far_m <= 2048 (its x2 axis is transformed as columns)");
+  }
+  if (p->maxwell_trace != 0 && p->maxwell_trace != 1) return fail(QPGF_E_ARG, "maxwell_trace must be 0 or 1");
+  if (p->maxwell_trace && p->kind != QPGF_KIND_MAXWELL3D) return fail(QPGF_E_ARG, "maxwell_trace needs QPGF_KIND_MAXWELL3D");
   return QPGF_OK;
+}
+
+}  // namespace
+
+// Far-slab geometry (Algorithm 2.1 / 3.1 / 4.1 step 2b: the series on the slab, interpolated with
+// the 8-point rule).  The rule's error for a term of wavenumber q along an axis of spacing h is
+// about (q h)^8 / 1000: with h = 2 pi / Mf and the propagating terms (q <= k), Mf >= 2 pi k / x
+// keeps it near 1e-11 (complex128, x = 0.0977) or 1e-7 (complex64, x = 0.3); the evanescent terms
+// the series keeps at |x_t| >= c - 3 hf set the floors, 256 modes and hf <= 1/64, and for the
+// derivative kinds, whose terms carry xi (and xi^2), 512 modes on the complex128 path (measured
+// against the direct sum of the series).  Slices z_s = c - 3 hf + s hf, s < S: a target at
+// |x_t| = z uses slices floor((z - z_0) / hf) - 3 .. + 4, so S = ceil((zmax - c) / hf) + 8 covers
+// every z <= zmax.  params.far_m and params.far_h override the modes and the spacing.
+FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
+  const bool c128 = P.p.prec == QPGF_C128;
+  const double x = c128 ? 0.0977 : 0.3;
+  const int kind = P.p.kind;
+  int floor_m = 256;
+  if (c128 && (kind == QPGF_KIND_MAXWELL3D || kind == QPGF_KIND_G2D_GRAD || kind == QPGF_KIND_G2D_HESS_DIFF))
+    floor_m = 512;
+  const double want = 2.0 * M_PI * std::max(kmax, 0.0) / x;
+  int mk = floor_m;
+  while (mk < want && mk < 4096) mk <<= 1;
+  const int cap = (P.dim == 3 && c128) ? 2048 : 4096;   // the 3D far slab's x2 axis is a column axis
+  FarGeom g;
+  g.Mf1 = P.p.far_m ? P.p.far_m : std::min(std::max(M1, mk), 4096);
+  g.Mf2 = P.dim == 3 ? (P.p.far_m ? P.p.far_m : std::min(std::max(P.M2, mk), cap)) : 1;
+  if (P.p.far_h > 0.0) {
+    g.hf = P.p.far_h;
+  } else {
+    double inv = 64.0;
+    const double need = std::max(kmax, 0.0) / x;
+    while (inv < need && inv < 4096.0) inv *= 2.0;
+    g.hf = 1.0 / inv;
+  }
+  g.S = (int)std::ceil((P.p.far_zmax - P.p.c) / g.hf - 1e-12) + kFarLo + 5;
+  return g;
+}
+
+namespace {
+
+// Take the far-slab geometry of an instance with largest wavenumber kmax, growing the slab's
+// allocation if it needs more (hipFree / hipMalloc: synchronous, only when the slab grows).
+hipError_t set_far_geometry(Plan& P, double kmax) {
+  const FarGeom g = far_geometry(P, kmax, P.M1);
+  const size_t nfar = (size_t)g.Mf1 * g.Mf2 * g.S;
+  const size_t bytes = (size_t)P.nfo * nfar * P.esize;
+  if (bytes > P.far_cap) {
+    if (P.far) {
+      hipError_t e = hipFree(P.far);
+      if (e != hipSuccess) return e;
+    }
+    P.far = nullptr;
+    P.far_cap = 0;
+    hipError_t e = hipMalloc(&P.far, bytes);
+    if (e != hipSuccess) return e;
+    P.far_cap = bytes;
+  }
+  P.Mf1 = g.Mf1;
+  P.Mf2 = g.Mf2;
+  P.S = g.S;
+  P.hf = g.hf;
+  P.fz0 = P.p.c - kFarLo * g.hf;
+  P.nfar = nfar;
+  return hipSuccess;
 }
 
 // Wood anomaly: beta_n = 0 for some mode n (Section 1).  Only lattice points with
@@ -214,6 +287,7 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
     st = check_instance(P, k2, a1, a2);
     if (st != QPGF_OK) return st;
   }
+  HIP_TRY(set_far_geometry(P, std::max(k, k2)));
   P.last_k2 = k2;
   P.spec = has_special(P, k, a1, a2, P.M1) ||
            (P.p.kind == QPGF_KIND_G2D_HESS_DIFF && has_special(P, k2, a1, a2, P.M1));
@@ -268,10 +342,12 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
       HIP_TRY(launch_far(P, k, a1, a2));
     }
     {
+      // the far slab on its own periodic grid Mf1 x Mf2: columns (x2, 3D), then rows (x1)
       KernelTimer t(P, QPGF_T_FAR_FFT);
+      const long nfo = P.nfo;
       if (P.dim == 3)
-        HIP_TRY(launch_fft(P, P.far, P.M2, P.M1, (long)P.M1 * P.S * nf, P.M1, 1, (long)P.M1 * P.M2));
-      HIP_TRY(launch_fft(P, P.far, P.M1, 1, (long)(P.dim == 3 ? P.M2 : 1) * P.S * nf, 1, 0, P.M1));
+        HIP_TRY(launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2));
+      HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * nfo, 1, 0, P.Mf1));
     }
     if (P.dim == 2 && P.gridI) {
       // the gather reads a stencil row (of all fields) as one contiguous, aligned run
@@ -328,8 +404,7 @@ void qpgf_params_default(qpgf_params* p, int kind, int prec, int m1, int m2, int
   p->c_tilde = 1.0;
   p->eps = 0.2;
   p->quad_q = 64;
-  const int mt = kind_is_2d(kind) ? m2 : m3;
-  p->far_h = mt > 0 ? p->c_tilde / (mt / 2) : 0.0;
+  p->far_h = 0.0;   // automatic: see far_geometry
   p->far_zmax = p->c_tilde;
   p->wood_tol = 1e-3;
   p->special_tol = 1e-2;
@@ -349,7 +424,7 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   Plan& P = plan->P;
   P.p = *p;
   P.dim = kind_is_2d(p->kind) ? 2 : 3;
-  P.nf = (p->kind == QPGF_KIND_MAXWELL3D)       ? kMxF
+  P.nf = (p->kind == QPGF_KIND_MAXWELL3D)       ? (p->maxwell_trace ? kMxT : kMxF)
          : (p->kind == QPGF_KIND_G2D_HESS_DIFF) ? 3
          : (p->kind == QPGF_KIND_G2D_GRAD)      ? 2
                                                 : 1;
@@ -358,9 +433,8 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   P.M3 = (P.dim == 3) ? p->m3 : 1;
   P.Mt = (P.dim == 3) ? P.M3 : P.M2;
   P.esize = (p->prec == QPGF_C128) ? 16 : 8;
-  P.S = (int)std::ceil((p->far_zmax - p->c) / p->far_h - 1e-12) + 4;
+  P.nfo = p->kind == QPGF_KIND_MAXWELL3D ? kMxO : P.nf;
   P.ncell = (size_t)P.M1 * P.M2 * P.M3;
-  P.nfar = (size_t)P.M1 * (P.dim == 3 ? P.M2 : 1) * P.S;
 
   auto bail = [&](qpgf_status s) {
     free_plan(P);
@@ -379,15 +453,14 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   } while (0)
 
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
-  PLAN_TRY(hipMalloc(&P.far, P.nf * P.nfar * P.esize));
+  PLAN_TRY(set_far_geometry(P, 0.0));   // the smallest slab; instances that need more grow it
   // complex64 G: each node's quad of x1-neighbours (4 values, 32 bytes) while the quads stay about
   // L2-sized (measured: 4.4 MB of quads read 30 % faster than the grid row by row, 8.8 MB slower)
-  const bool quads = P.dim == 2 && P.nf == 1 && P.p.prec == QPGF_C64 && 32 * (P.ncell + P.nfar) <= (5u << 20);
+  const bool quads = P.dim == 2 && P.nf == 1 && P.p.prec == QPGF_C64 && 32 * P.ncell <= (5u << 20);
   if (P.dim == 2 && (P.nf > 1 || quads)) {
-    // derivative kinds: the fields interleaved per node; the complex64 G: node quads
+    // derivative kinds: the near fields interleaved per node; the complex64 G: node quads
     const size_t per = P.nf > 1 ? (size_t)P.nf : 4;
     PLAN_TRY(hipMalloc(&P.gridI, per * P.ncell * P.esize));
-    PLAN_TRY(hipMalloc(&P.farI, per * P.nfar * P.esize));
   }
 
   const int Q = p->quad_q;
@@ -434,7 +507,8 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   }
   // twiddles e^{+2 pi i j / NT}
   {
-    int NT = std::max(P.M1, std::max(P.M2, P.M3));
+    // every transform length up to 4096 (far slabs grow with k) reads this table with a stride
+    const int NT = 1 << kMaxLog2;
     P.twlog2 = __builtin_ctz((unsigned)NT);
     std::vector<double2> tw(NT);
     std::vector<float2> twf(NT);
@@ -537,13 +611,16 @@ qpgf_status qpgf_plan_get_info(const qpgf_plan* plan, qpgf_plan_info* info) {
   info->m2 = P.M2;
   info->m3 = P.dim == 3 ? P.M3 : 0;
   info->far_slices = P.S;
-  info->far_h = P.p.far_h;
+  info->far_h = P.hf;
   info->c = P.p.c;
   info->c_tilde = P.p.c_tilde;
   info->eps = P.p.eps;
   info->n_fields = P.nf;
   info->grid_bytes = P.ncell * P.esize;
   info->far_grid_bytes = P.nfar * P.esize;
+  info->far_m1 = P.Mf1;
+  info->far_m2 = P.Mf2;
+  info->far_fields = P.nfo;
   return QPGF_OK;
 }
 
@@ -595,6 +672,9 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
   // the work already on the plan's stream, join before the gather).
   const bool overlap = T > 0 && gather_uses_bins(P, T);
   if (overlap) {
+    // the tile keys of far targets depend on the instance's far slab
+    if (!std::isfinite(k) || !std::isfinite(k2)) return fail(QPGF_E_ARG, "need finite k");
+    HIP_TRY(set_far_geometry(P, std::max(k, k2)));
     if (!P.side) HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     if (!P.ev_fork) HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
     if (!P.ev_join) HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
@@ -703,10 +783,13 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   Lo.segR_off = align_up(Lo.segT_off + n_inst * sizeof(FftSeg));
   Lo.segF_off = align_up(Lo.segR_off + n_inst * sizeof(FftSeg));
   Lo.bytes = align_up(Lo.segF_off + n_inst * sizeof(FftSeg));
+  // each instance's far slab on its own geometry (modes and slices follow its wavenumber)
+  std::vector<FarGeom> fg(n_inst);
   size_t grid_elems = 0, far_elems = 0;
   for (int i = 0; i < n_inst; ++i) {
+    fg[i] = far_geometry(P, k[i], m1[i]);
     grid_elems += (size_t)m1[i] * P.M2;
-    far_elems += (size_t)m1[i] * P.S;
+    far_elems += (size_t)fg[i].Mf1 * fg[i].S;
   }
   HIP_TRY(grow(&P.b_grid, P.b_grid_cap, grid_elems * P.esize));
   HIP_TRY(grow(&P.b_far, P.b_far_cap, far_elems * P.esize));
@@ -729,12 +812,12 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   size_t goff = 0, foff = 0;
   Lo.lds_T = Lo.lds_R = Lo.lds_F = 0;
   for (int i = 0; i < n_inst; ++i) {
-    const int M = m1[i];
-    fill_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, fb, h + Lo.fill_off + i * fsz);
+    const int M = m1[i], MF = fg[i].Mf1, SF = fg[i].S;
+    fill_inst_2d(P, k[i], alpha[i], M, fg[i], (long)goff, (long)foff, fb, h + Lo.fill_off + i * fsz);
     fb += (M + 15) / 16;
-    fill_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, rb, h + Lo.far_off + i * fsz);
-    rb += ((long)M * P.S + 255) / 256;
-    gather_inst_2d(P, k[i], alpha[i], M, (long)goff, (long)foff, (long)t_off[i], (long)t_off[i + 1], gb,
+    fill_inst_2d(P, k[i], alpha[i], M, fg[i], (long)goff, (long)foff, rb, h + Lo.far_off + i * fsz);
+    rb += ((long)MF * SF + 255) / 256;
+    gather_inst_2d(P, k[i], alpha[i], M, fg[i], (long)goff, (long)foff, (long)t_off[i], (long)t_off[i + 1], gb,
                    h + Lo.gat_off + i * gsz);
     gb += (long)((t_off[i + 1] - t_off[i] + 255) / 256);
     FftSeg sT{(long)goff, P.M2, __builtin_ctz((unsigned)P.M2), (long)M, (long)M, (long)M, 1, 0,
@@ -746,14 +829,14 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
     FftSeg sR{(long)goff, M, __builtin_ctz((unsigned)M), 1, (long)P.M2, 1, 0, (long)M, fft_tile(P, M, true, P.M2), rrb};
     rrb += (sR.nbatch + sR.tile - 1) / sR.tile;
     Lo.lds_R = std::max(Lo.lds_R, (long)sR.tile * sR.n + (fft_twiddles_in_lds(sR.tile, sR.n, sR.n, P.esize) ? sR.n : 0));
-    FftSeg sF{(long)foff, M, __builtin_ctz((unsigned)M), 1, (long)P.S, 1, 0, (long)M, fft_tile(P, M, true, P.S), frb};
+    FftSeg sF{(long)foff, MF, __builtin_ctz((unsigned)MF), 1, (long)SF, 1, 0, (long)MF, fft_tile(P, MF, true, SF), frb};
     frb += (sF.nbatch + sF.tile - 1) / sF.tile;
     Lo.lds_F = std::max(Lo.lds_F, (long)sF.tile * sF.n + (fft_twiddles_in_lds(sF.tile, sF.n, sF.n, P.esize) ? sF.n : 0));
     std::memcpy(h + Lo.segT_off + i * sizeof(FftSeg), &sT, sizeof sT);
     std::memcpy(h + Lo.segR_off + i * sizeof(FftSeg), &sR, sizeof sR);
     std::memcpy(h + Lo.segF_off + i * sizeof(FftSeg), &sF, sizeof sF);
     goff += (size_t)M * P.M2;
-    foff += (size_t)M * P.S;
+    foff += (size_t)MF * SF;
   }
   Lo.fill_blocks = fb;
   Lo.far_blocks = rb;
@@ -774,7 +857,10 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   sig.push_back(n_inst);
   sig.push_back(P.p.prec);
   sig.push_back(spec);
-  for (int i = 0; i < n_inst; ++i) sig.push_back(m1[i]);
+  for (int i = 0; i < n_inst; ++i) {
+    sig.push_back(m1[i]);
+    sig.push_back(((int64_t)fg[i].Mf1 << 32) | fg[i].S);   // the far slabs' shapes follow k
+  }
   for (int i = 0; i <= n_inst; ++i) sig.push_back(t_off[i]);
   for (const void* q : {(const void*)x, (const void*)out, (const void*)flags, (const void*)P.b_grid,
                         (const void*)P.b_far, (const void*)P.b_desc})
@@ -831,16 +917,14 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
   std::vector<Shape> shapes;
   if (P.dim == 2) {
     shapes.push_back({P.M2, false, (long)P.M1 * P.nf});
-    for (int n = 16; n <= P.M1; n <<= 1) {
-      shapes.push_back({n, true, (long)P.M2 * P.nf});
-      shapes.push_back({n, true, (long)P.S * P.nf});
-    }
+    for (int n = 16; n <= P.M1; n <<= 1) shapes.push_back({n, true, (long)P.M2 * P.nf});
+    for (int n = 16; n <= P.Mf1; n <<= 1) shapes.push_back({n, true, (long)P.S * P.nfo});
   } else {
     shapes.push_back({P.M3, false, (long)P.M1 * P.M2 * P.nf});
     shapes.push_back({P.M2, false, (long)P.M1 * P.M3 * P.nf});
     shapes.push_back({P.M1, true, (long)P.M2 * P.M3 * P.nf});
-    shapes.push_back({P.M2, false, (long)P.M1 * P.S * P.nf});
-    shapes.push_back({P.M1, true, (long)P.M2 * P.S * P.nf});
+    shapes.push_back({P.Mf2, false, (long)P.Mf1 * P.S * P.nfo});
+    shapes.push_back({P.Mf1, true, (long)P.Mf2 * P.S * P.nfo});
   }
   const char* arch = "gfx950";
   const char* prec = P.p.prec == QPGF_C128 ? "c128" : "c64";
@@ -950,7 +1034,7 @@ qpgf_status qpgf_copy_field(qpgf_plan* plan, int which, int field, void* dst) {
   Plan& P = plan->P;
   if (!dst) return fail(QPGF_E_ARG, "dst is NULL");
   if (which != 0 && which != 1) return fail(QPGF_E_ARG, "which must be 0 (near grid) or 1 (far slab)");
-  if (field < 0 || field >= P.nf) return fail(QPGF_E_ARG, "field out of range");
+  if (field < 0 || field >= (which == 0 ? P.nf : P.nfo)) return fail(QPGF_E_ARG, "field out of range");
   const size_t n = (which == 0 ? P.ncell : P.nfar) * P.esize;
   const char* src = static_cast<const char*>(which == 0 ? P.grid : P.far) + (size_t)field * n;
   HIP_TRY(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, P.stream));

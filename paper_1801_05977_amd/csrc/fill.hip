@@ -180,7 +180,7 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
   return acc;
 }
 
-// 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF == kMxF):
+// 3D near fill (Algorithm 3.1 steps 1a-1b; Algorithm 4.1 step 1c when NF is kMxF or kMxT):
 // L-hat_dj = A3 [ I-terms + H(|xi|) / (|xi|^2 - k^2) ], i.e. K-hat_dj of (3.3)
 // minus F-hat_j of (3.5) with the common 1/(|xi|^2-k^2) cancelled exactly.
 //
@@ -217,12 +217,17 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
     } else {
       const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
       store_c<T>(out, o, L);
-      if (NF == kMxF) {
-        // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~), pq = 11 22 12 13 23
+      if (NF == kMxF || NF == kMxT) {
+        // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~) (Algorithm 4.1 step 1c),
+        // pq = 11 22 33 12 13 23 (without 33 for the trace variant)
         const double cc[3] = {xi1, xi2, J};
-        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
+        constexpr int NP = NF - 1;
+        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-        for (int f = 0; f < 5; ++f) store_c<T>(out, (f + 1) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+        for (int f = 0, g = 0; f < 6; ++f) {
+          if (NP == 5 && f == 2) continue;
+          store_c<T>(out, (++g) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
+        }
       }
     }
   };
@@ -328,6 +333,8 @@ __global__ __launch_bounds__(256) void k_fill2d(FillArgs A, const double* __rest
 // Many 2D instances in one launch: instance i owns blocks [inst[i].blk0, inst[i+1].blk0).
 struct FillInst {
   FillArgs A;
+  int Mf1, Sf;   // modes and slices of the instance's far slab
+  double hf, z0; // its slice spacing and first slice
   long off;      // first element of the instance's near grid
   long foff;     // first element of its far slab
   long blk0;     // first block of the instance in this launch
@@ -643,9 +650,11 @@ __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int
   if (lane == 0) htab[m] = acc;
 }
 
-// Far slab, 3D: per-slice coefficients (i/8pi^2) beta^-1 e^{i beta z_s} of the
-// series (1.3) (times -xi_p xi_q, xi3 = beta, for the Maxwell fields).
-template <typename T, int NF>
+// Far slab, 3D (Algorithm 3.1 / 4.1 step 2b: the series (1.3)): per-slice coefficients
+// (i/8pi^2) beta^-1 e^{i beta z_s} of the Mf1 x Mf2 lowest modes, z_s = z0 + s hf.  NFO = kMxO:
+// the six entries of the Maxwell tensor (1.4) instead, the term times delta_pq - xi_p xi_q / k^2
+// with xi = (alpha1 + j1, alpha2 + j2, beta) (the entries 13 and 23 take sgn(x3) at the target).
+template <typename T, int NFO>
 __global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, double z0, double hf, long fstride,
                         cplx<T>* __restrict__ out) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -658,14 +667,16 @@ __global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, d
   const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
   const double z = z0 + s * hf;
   const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
-  store_c<T>(out, idx, v);
-  if (NF == kMxF) {
+  if (NFO == 1) {
+    store_c<T>(out, idx, v);
+  } else {
+    const double ik2 = 1.0 / (k * k);
     const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
-    const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
+    const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      double2 m = cmul(cc[P[f]], cc[Qp[f]]);
-      store_c<T>(out, (f + 1) * fstride + idx, cmul(v, mk(-m.x, -m.y)));
+    for (int f = 0; f < 6; ++f) {
+      const double2 m = cscale(cmul(cc[P[f]], cc[Qp[f]]), -ik2);
+      store_c<T>(out, f * fstride + idx, cmul(v, mk((f < 3 ? 1.0 : 0.0) + m.x, m.y)));
     }
   }
 }
@@ -749,7 +760,8 @@ __global__ __launch_bounds__(256) void k_fill2d_hess(FillArgs A, const double* _
   }
 }
 
-// Far slab, 2D: (i/4pi) beta_n^-1 e^{i beta_n z_s} of the series (1.2).
+// Far slab, 2D (Algorithm 2.1 step 2b: the series (1.2)): (i/4pi) beta_n^-1 e^{i beta_n z_s} of the
+// M1 lowest modes, z_s = z0 + s hf.
 template <typename T>
 __global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf, cplx<T>* __restrict__ out) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -802,15 +814,14 @@ __global__ void k_far2d_hess(double k1, double k2, double a, int M1, int S, doub
 
 // Far slab of many 2D instances: instance i owns blocks [blk0_i, blk0_{i+1}) of 256 threads.
 template <typename T>
-__global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, int S, double z0, double hf,
-                              cplx<T>* __restrict__ base) {
+__global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, cplx<T>* __restrict__ base) {
   const int i = find_inst(inst, n_inst, blockIdx.x);
   const FillInst I = inst[i];
   const long idx = (blockIdx.x - I.blk0) * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)I.A.M1 * S) return;
-  const int j1p = (int)(idx % I.A.M1), s = (int)(idx / I.A.M1);
-  const double2 b = beta_of(I.A.k, fabs(I.A.a1 + centered(j1p, I.A.M1)));
-  const double z = z0 + s * hf;
+  if (idx >= (long)I.Mf1 * I.Sf) return;
+  const int j1p = (int)(idx % I.Mf1), s = (int)(idx / I.Mf1);
+  const double2 b = beta_of(I.A.k, fabs(I.A.a1 + centered(j1p, I.Mf1)));
+  const double z = I.z0 + s * I.hf;
   store_c<T>(base + I.foff, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
 }
 
@@ -877,6 +888,13 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
       else
         hipLaunchKernelGGL((k_fill3d<T, kMxF, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
                            P.htab, out, tw, P.twlog2);
+    } else if (P.nf == kMxT) {
+      if (spec)
+        hipLaunchKernelGGL((k_fill3d<T, kMxT, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
+      else
+        hipLaunchKernelGGL((k_fill3d<T, kMxT, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
+                           P.htab, out, tw, P.twlog2);
     } else if (fuse) {
       if (spec)
         hipLaunchKernelGGL((k_fill3d<T, 1, true, true>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
@@ -899,25 +917,21 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
 template <typename T>
 hipError_t far_impl(Plan& P, double k, double a1, double a2) {
   auto* out = static_cast<cplx<T>*>(P.far);
-  const double hf = P.p.far_h, z0 = P.p.c - hf;
+  const double hf = P.hf, z0 = P.fz0;
+  const long n = (long)P.Mf1 * P.Mf2 * P.S;
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
   if (P.dim == 2) {
-    long n = (long)P.M1 * P.S;
     if (P.nf == 2)
-      hipLaunchKernelGGL(k_far2d_grad<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf,
-                         (long)P.nfar, out);
+      hipLaunchKernelGGL(k_far2d_grad<T>, g, b, 0, P.stream, k, a1, P.Mf1, P.S, z0, hf, (long)P.nfar, out);
     else if (P.nf == 3)
-      hipLaunchKernelGGL(k_far2d_hess<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, P.last_k2, a1, P.M1,
-                         P.S, z0, hf, (long)P.nfar, out);
+      hipLaunchKernelGGL(k_far2d_hess<T>, g, b, 0, P.stream, k, P.last_k2, a1, P.Mf1, P.S, z0, hf, (long)P.nfar, out);
     else
-      hipLaunchKernelGGL(k_far2d<T>, dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, P.M1, P.S, z0, hf, out);
+      hipLaunchKernelGGL(k_far2d<T>, g, b, 0, P.stream, k, a1, P.Mf1, P.S, z0, hf, out);
+  } else if (P.nfo == kMxO) {
+    hipLaunchKernelGGL((k_far3d<T, kMxO>), g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar,
+                       out);
   } else {
-    long n = (long)P.M1 * P.M2 * P.S;
-    if (P.nf == kMxF)
-      hipLaunchKernelGGL((k_far3d<T, kMxF>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
-                         z0, hf, (long)P.nfar, out);
-    else
-      hipLaunchKernelGGL((k_far3d<T, 1>), dim3((n + 255) / 256), dim3(256), 0, P.stream, k, a1, a2, P.M1, P.M2, P.S,
-                         z0, hf, (long)P.nfar, out);
+    hipLaunchKernelGGL((k_far3d<T, 1>), g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar, out);
   }
   return hipGetLastError();
 }
@@ -963,7 +977,8 @@ hipError_t launch_htable(Plan& P, double k) {
 }
 
 // host-side descriptor of one 2D instance for the batched launches
-void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long blk0, void* dst) {
+void fill_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, long off, long foff, long blk0,
+                  void* dst) {
   FillInst I;
   I.A.k = k;
   I.A.a1 = a;
@@ -985,6 +1000,10 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff
   I.A.k2 = 0.0;
   I.A.E = P.E2;
   I.A.sing_order = P.p.sing_order;
+  I.Mf1 = fg.Mf1;
+  I.Sf = fg.S;
+  I.hf = fg.hf;
+  I.z0 = P.p.c - kFarLo * fg.hf;
   I.off = off;
   I.foff = foff;
   I.blk0 = blk0;
@@ -1017,14 +1036,13 @@ hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblo
 }
 
 hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base) {
-  const double hf = P.p.far_h, z0 = P.p.c - hf;
   const auto* in = static_cast<const FillInst*>(dinst);
   if (P.p.prec == QPGF_C128)
-    hipLaunchKernelGGL(k_far2d_multi<double>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst, P.S, z0,
-                       hf, static_cast<double2*>(base));
+    hipLaunchKernelGGL(k_far2d_multi<double>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst,
+                       static_cast<double2*>(base));
   else
-    hipLaunchKernelGGL(k_far2d_multi<float>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst, P.S, z0,
-                       hf, static_cast<float2*>(base));
+    hipLaunchKernelGGL(k_far2d_multi<float>, dim3((unsigned)nblocks), dim3(256), 0, P.stream, in, n_inst,
+                       static_cast<float2*>(base));
   return hipGetLastError();
 }
 

@@ -2,9 +2,11 @@
 // target to the period cell (step 2c), branch on |x_t| <= c (step 2b),
 // interpolate the near grid with the tensor-product 4-point Lagrange rule
 // (16 / 64 nodes, step 2d), add back the removed singular part in FP64 and apply
-// the quasi-periodic phase (steps 2e-2f; Algorithm 4.1 steps 2e-2i).  Far
-// targets interpolate the far-slab grid of the eigenfunction series.
+// the quasi-periodic phase (steps 2e-2f; Algorithm 4.1 steps 2e-2i).  Far targets
+// take the eigenfunction series (step 2b), summed on the far slab and interpolated
+// there with the 8-point rule per axis (64 / 512 nodes).
 #include <algorithm>
+#include <cstring>
 
 #include "qpgf_internal.h"
 
@@ -20,12 +22,15 @@ struct GArgs {
   int M1, M2, M3;          // 2D: M2 = transverse size, M3 = 1
   double h1, h2, h3;       // 2D: h2 = transverse spacing
   double ih1, ih2, ih3;    // reciprocals of the spacings
-  double hf, ihf;          // far-slab spacing and its reciprocal
+  double hf, ihf;          // far-slab slice spacing and its reciprocal
+  double fz0;              // far-slab first slice, c - kFarLo hf
   int S;                   // far-slab slices
+  int Mf1, Mf2;            // far-slab periodic sizes (Mf2 = 1 in 2D)
+  double ihf1, ihf2;       // reciprocals of the far slab's periodic spacings 2 pi / Mf
   long fs, ffs;            // field strides (near, far)
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
   int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
-  int quad;                // 2D G, complex64: grid and far are node quads (4 x1-neighbours per node)
+  int quad;                // 2D G, complex64: the near grid is node quads (4 x1-neighbours per node)
   // 2D kinds, ring_interp: bit i of ring_mask marks target i (a near target with
   // ring_lo < r < ring_hi) for the ring pass
   unsigned long long* ring_mask;
@@ -72,186 +77,254 @@ template <> __device__ __forceinline__ void store_out<float>(float2* p, long i, 
 
 __device__ __forceinline__ double2 nan2() { return mk(__builtin_nan(""), __builtin_nan("")); }
 
-// Stencil sum over global memory: field f, base nodes p1, p2 (periodic) and p3
-// (near: periodic slice index; far: far-slab slice s0 >= 1).
-template <typename T, int NF>
-struct GlobalFetch {
-  const cplx<T>* grid;
-  const cplx<T>* far;
-  long fs, ffs;
-  int M1, M2, M3;
-  __device__ void operator()(bool near, int p1, int p2, int p3, const T w1[4], const T w2[4], const T w3[4],
-                             double2 L[NF]) const {
-    const cplx<T>* g = near ? grid : far;
-    const long st = near ? fs : ffs;
-    Acc<T> acc[NF];
+// 8-point Lagrange weights at nodes -3 .. 4 for the fraction f in [0, 1) (the far branch):
+// w_m = prod_{n != m} (f - (n - 3)) / prod_{n != m} (m - n), products before and after m.
+template <typename W>
+__device__ __forceinline__ void lag8(W f, W w[8]) {
+  W g[8], pre[8], suf[8];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const long i3 = near ? (long)((p3 - 1 + c) & (M3 - 1)) : (long)(p3 - 1 + c);
+  for (int m = 0; m < 8; ++m) g[m] = f + W(3 - m);
+  pre[0] = W(1);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const long row = (i3 * M2 + ((p2 - 1 + b) & (M2 - 1))) * (long)M1;
-        const T wcb = w3[c] * w2[b];
+  for (int m = 1; m < 8; ++m) pre[m] = pre[m - 1] * g[m - 1];
+  suf[7] = W(1);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const T w = wcb * w1[a];
-          const long o = row + ((p1 - 1 + a) & (M1 - 1));
+  for (int m = 6; m >= 0; --m) suf[m] = suf[m + 1] * g[m + 1];
+  const W inv[8] = {W(-1.0 / 5040.0), W(1.0 / 720.0), W(-1.0 / 240.0), W(1.0 / 144.0),
+                    W(-1.0 / 144.0),  W(1.0 / 240.0), W(-1.0 / 720.0), W(1.0 / 5040.0)};
 #pragma unroll
-          for (int f = 0; f < NF; ++f) acc[f].add(w, g[f * st + o]);
-        }
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
-  }
-};
+  for (int m = 0; m < 8; ++m) w[m] = pre[m] * suf[m] * inv[m];
+}
 
-// The steps of eval3d_target (below) split in two, for kernels that compute the
-// stencil sums between them (k_gather3d_fields): the stencil of one target
-// (Algorithm 3.1 / 4.1 step 2: cell reduction, branch, base nodes and the three
-// 4-point weight sets), and the finish from the sums to the result.  The
-// single-function form stays for the other kernels, where it compiles to far
-// fewer registers with six fields.
+// Far-slab slice stencil of |x_t| = z: base slice s0 = floor((z - fz0) / hf) (>= kFarLo for
+// z > c) and the fraction; false when the 8 slices s0 - 3 .. s0 + 4 leave the slab.
+__device__ __forceinline__ bool far_slice(const GArgs& A, double z, double& s0, double& f) {
+  const double v = (z - A.fz0) * A.ihf;
+  s0 = floor(v);
+  if (!(s0 <= A.S - 5)) return false;
+  s0 = fmax(s0, (double)kFarLo);
+  f = v - s0;
+  return true;
+}
+
+// Number of results per target: G_d, or the six Maxwell entries.
+template <int NF> struct NOut { static constexpr int v = NF == 1 ? 1 : 6; };
+
+// ---------------------------------------------------------------------------
+// 3D near branch (Algorithm 3.1 / 4.1 steps 2c-2i)
+// ---------------------------------------------------------------------------
+// The stencil of one near target: cell reduction (step 2c), base nodes and the three
+// 4-point weight sets (the tricubic rule of step 2d).
 template <typename T>
-struct Stencil3 {
+struct Near3 {
   double t1, t2, n1, n2;
-  bool near;
   int p1, p2, p3;
   T w1[4], w2[4], w3[4];
 };
 
-// false: the result is NaN without a stencil sum (non-finite input, beyond the
-// far slab, or a far target when only the smooth part is asked for); res, fl set.
-template <typename T, int NO>
-__device__ __forceinline__ bool stencil3d(const GArgs& A, double x1, double x2, double x3, Stencil3<T>& s,
-                                          double2* res, uint8_t& fl) {
-  fl = 0;
-  if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) {
-    fl = 8;
-#pragma unroll
-    for (int o = 0; o < NO; ++o) res[o] = nan2();
-    return false;
-  }
+template <typename T>
+__device__ __forceinline__ void near3_stencil(const GArgs& A, double x1, double x2, double x3, Near3<T>& s) {
   s.t1 = reduce_cell(x1, s.n1);
   s.t2 = reduce_cell(x2, s.n2);
   const double u1 = s.t1 * A.ih1, q1 = floor(u1);
-  lag4<T>((T)(u1 - q1), s.w1);
   const double u2 = s.t2 * A.ih2, q2 = floor(u2);
+  const double u3 = x3 * A.ih3, q3 = floor(u3);
+  lag4<T>((T)(u1 - q1), s.w1);
   lag4<T>((T)(u2 - q2), s.w2);
+  lag4<T>((T)(u3 - q3), s.w3);
   s.p1 = (int)q1;
   s.p2 = (int)q2;
-  s.near = fabs(x3) <= A.c;
-  if (s.near) {
-    const double u = x3 * A.ih3, q = floor(u);
-    lag4<T>((T)(u - q), s.w3);
-    s.p3 = (int)q;
-    return true;
-  }
-  fl |= 2;
-  if (A.smooth) {
-#pragma unroll
-    for (int o = 0; o < NO; ++o) res[o] = nan2();
-    return false;
-  }
-  const double v = (fabs(x3) - (A.c - A.hf)) * A.ihf;
-  double s0 = floor(v);
-  if (s0 > A.S - 3) {
-    fl |= 4;
-#pragma unroll
-    for (int o = 0; o < NO; ++o) res[o] = nan2();
-    return false;
-  }
-  s0 = fmax(s0, 1.0);
-  lag4<T>((T)(v - s0), s.w3);
-  s.p3 = (int)s0;
-  return true;
+  s.p3 = (int)q3;
 }
 
-// From the stencil sums L (NF fields) to the result: phase, exact FP64 add-back
-// of the singular part (and its Hessian), Maxwell assembly (eq. 4.1).
+// 64-point stencil sums of the NF near fields from global memory (periodic in every axis).
 template <typename T, int NF>
-__device__ __forceinline__ void finish3d(const GArgs& A, double x1, double x2, double x3, const Stencil3<T>& s,
-                                         const double2 L[NF], double2* res, uint8_t& fl) {
-  constexpr int NO = (NF == 1) ? 1 : 6;
+__device__ __forceinline__ void near3_sum_global(const GArgs& A, const cplx<T>* __restrict__ grid, const Near3<T>& s,
+                                                 double2 L[NF]) {
+  Acc<T> acc[NF];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long i3 = (long)((s.p3 - 1 + c) & (A.M3 - 1));
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long row = (i3 * A.M2 + ((s.p2 - 1 + b) & (A.M2 - 1))) * (long)A.M1;
+      const T wcb = s.w3[c] * s.w2[b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const T w = wcb * s.w1[a];
+        const long o = row + ((s.p1 - 1 + a) & (A.M1 - 1));
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f].add(w, grid[f * A.fs + o]);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+}
+
+// From the stencil sums L of the NF near fields to the result: phase e^{i alpha.x'} (step 2f,
+// with the original coordinates), exact FP64 add-back of the removed singular part
+// psi = e^{ikr} Y(r) / (4 pi r) and of its Hessian (steps 2e, 2g-2h), and the Maxwell tensor
+// GG_pq = delta_pq G_d + k^-2 d_p d_q G_d (eq. 4.1, step 2i).  NF = kMxF: fields 11 22 33 12 13 23;
+// NF = kMxT: 11 22 12 13 23 with GG_33 = 2 G_d - GG_11 - GG_22.
+template <typename T, int NF>
+__device__ __forceinline__ void near3_finish(const GArgs& A, double x1, double x2, double x3, const Near3<T>& s,
+                                             const double2 L[NF], double2* res, uint8_t& fl) {
+  constexpr int NO = NOut<NF>::v;
   if (A.smooth) {
-    // the smooth part L_N(t) of Algorithm 3.1 step 2d (near branch only)
+    // the smooth part L_N(t) of Algorithm 3.1 step 2d
 #pragma unroll
     for (int o = 0; o < NO; ++o) res[o] = L[o < NF ? o : 0];
     return;
   }
-  const double t1 = s.t1, t2 = s.t2, n1 = s.n1, n2 = s.n2;
-  const bool is_near = s.near;
   double ps, pc;
   sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
   const double2 phase = mk(pc, ps);
   double2 G[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
-  if (!is_near && NF == kMxF) {
-    // d/dx3 of e^{i beta |x3|} carries sgn(x3): fields 13 and 23
-    if (x3 < 0) {
-      G[4] = cscale(G[4], -1.0);
-      G[5] = cscale(G[5], -1.0);
-    }
+  const double r2 = s.t1 * s.t1 + s.t2 * s.t2 + x3 * x3;
+  if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+    fl |= 1;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return;
   }
-  if (is_near) {
+  if (r2 < 4.0 * A.eps * A.eps) {
     // the square root only inside the support of the singular part
-    const double r2 = t1 * t1 + t2 * t2 + x3 * x3;
-    if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
-      fl |= 1;
+    const double r = sqrt(r2);
+    double sn, cn;
+    sincos(A.k * r, &sn, &cn);
+    const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
+    double ls, lc;
+    sincospi(2.0 * (A.a1 * s.n1 + A.a2 * s.n2), &ls, &lc);
+    const double2 lat = mk(lc, ls);
+    const double Y = cut_Y(r, A.eps);
+    G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
+    if (NF > 1) {
+      // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
+      const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
+      const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
+      const double2 g1 = cmul(g, ikr);
+      const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
+      const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
+      const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
+      const double t[3] = {s.t1, s.t2, x3};
+      const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-      for (int f = 0; f < NF; ++f) G[f] = nan2();
-    } else if (r2 < 4.0 * A.eps * A.eps) {
-      const double r = sqrt(r2);
-      // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
-      double sn, cn;
-      sincos(A.k * r, &sn, &cn);
-      const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
-      double ls, lc;
-      sincospi(2.0 * (A.a1 * n1 + A.a2 * n2), &ls, &lc);
-      const double2 lat = mk(lc, ls);
-      const double Y = cut_Y(r, A.eps);
-      G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
-      if (NF == kMxF) {
-        // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
-        const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
-        const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
-        const double2 g1 = cmul(g, ikr);
-        const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
-        const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
-        const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
-        const double t[3] = {t1, t2, x3};
-        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          const double tp = t[P[f]], tq = t[Qp[f]];
-          const double a = tp * tq / (r * r);
-          const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
-          G[f + 1] = cadd(G[f + 1], cmul(lat, cadd(cscale(d2, a), cscale(d1, bcoef))));
-        }
+      for (int e = 0, f = 1; e < 6; ++e) {
+        if (NF == kMxT && e == 2) continue;
+        const double tp = t[P[e]], tq = t[Qp[e]];
+        const double a = tp * tq / r2;
+        const double bc = ((P[e] == Qp[e]) ? 1.0 / r : 0.0) - tp * tq / (r2 * r);
+        G[f] = cadd(G[f], cmul(lat, cadd(cscale(d2, a), cscale(d1, bc))));
+        ++f;
       }
     }
   }
   if (NF == 1) {
     res[0] = G[0];
   } else {
-    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1); fields 11 22 12 13 23, and GG_33 from
-    // the trace: tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz equation, off the lattice)
     const double ik2 = 1.0 / (A.k * A.k);
     res[0] = cadd(G[0], cscale(G[1], ik2));
     res[1] = cadd(G[0], cscale(G[2], ik2));
-    res[2] = csub(cscale(G[0], 2.0), cadd(res[0], res[1]));
+    if (NF == kMxF) {
+      res[2] = cadd(G[0], cscale(G[3], ik2));
 #pragma unroll
-    for (int f = 3; f < 6; ++f) res[f] = cscale(G[f], ik2);
+      for (int o = 3; o < 6; ++o) res[o] = cscale(G[o + 1], ik2);
+    } else {
+      // the trace variant: tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz equation)
+      res[2] = csub(cscale(G[0], 2.0), cadd(res[0], res[1]));
+#pragma unroll
+      for (int o = 3; o < 6; ++o) res[o] = cscale(G[o], ik2);
+    }
   }
 }
 
-// One target of Algorithm 3.1 / 4.1 step 2 (G_d, or the six Maxwell entries).
-// `fetch` performs the 64-point stencil sum of the near grid or the far slab.
-template <typename T, int NF, typename Fetch>
-__device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double x2, double x3, const Fetch& fetch,
+// ---------------------------------------------------------------------------
+// 3D far branch (step 2b: the series (1.3), and for Maxwell its term-wise derivatives)
+// ---------------------------------------------------------------------------
+// The far slab holds the series on its own periodic grid (Mf1 x Mf2, spacings 2 pi / Mf)
+// at slices z_s = fz0 + s hf: G_d, or the six tensor entries GG_pq (13 and 23 for x3 > 0).
+template <typename T>
+struct Far3 {
+  int p1, p2, s0;
+  T w1[8], w2[8], w3[8];
+};
+
+// false: |x3| beyond the slab
+template <typename T>
+__device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T>& s) {
+  double s0, f3;
+  if (!far_slice(A, fabs(x3), s0, f3)) return false;
+  double n;
+  const double u1 = reduce_cell(x1, n) * A.ihf1, q1 = floor(u1);
+  const double u2 = reduce_cell(x2, n) * A.ihf2, q2 = floor(u2);
+  lag8<T>((T)(u1 - q1), s.w1);
+  lag8<T>((T)(u2 - q2), s.w2);
+  lag8<T>((T)f3, s.w3);
+  s.p1 = (int)q1;
+  s.p2 = (int)q2;
+  s.s0 = (int)s0;
+  return true;
+}
+
+// 512-point stencil sums of the NFO far fields from global memory.
+template <typename T, int NFO>
+__device__ __forceinline__ void far3_sum_global(const GArgs& A, const cplx<T>* __restrict__ far, const Far3<T>& s,
+                                                double2 L[NFO]) {
+  Acc<T> acc[NFO];
+  // the slice loop stays rolled; its weight is the head of a copy shifted each step (static
+  // indices only, so the weights stay in registers)
+  T w3[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) w3[m] = s.w3[m];
+#pragma unroll 1
+  for (int c = 0; c < 8; ++c) {
+    const T wc = w3[0];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) w3[m] = w3[m + 1];
+    const long i3 = s.s0 - 3 + c;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const long row = (i3 * A.Mf2 + ((s.p2 - 3 + b) & (A.Mf2 - 1))) * (long)A.Mf1;
+      const T wcb = wc * s.w2[b];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const T w = wcb * s.w1[a];
+        const long o = row + ((s.p1 - 3 + a) & (A.Mf1 - 1));
+#pragma unroll
+        for (int f = 0; f < NFO; ++f) acc[f].add(w, far[f * A.ffs + o]);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NFO; ++f) L[f] = acc[f].get();
+}
+
+// From the far sums to the result: the phase e^{i alpha.x'}, and sgn(x3) for GG_13, GG_23
+// (d/dx3 of e^{i beta |x3|}).
+template <int NFO>
+__device__ __forceinline__ void far3_finish(const GArgs& A, double x1, double x2, double x3, const double2 L[NFO],
+                                            double2* res) {
+  double ps, pc;
+  sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
+  const double2 phase = mk(pc, ps);
+#pragma unroll
+  for (int o = 0; o < NFO; ++o) res[o] = cmul(phase, L[o]);
+  if (NFO == kMxO && x3 < 0.0) {
+    res[4] = cscale(res[4], -1.0);
+    res[5] = cscale(res[5], -1.0);
+  }
+}
+
+// One target from global memory, either branch (unsorted targets, the tiled kernels'
+// overflow and the key of non-finite or out-of-slab targets).  NFO = far fields.
+template <typename T, int NF>
+__device__ __forceinline__ void eval3d_global(const GArgs& A, const cplx<T>* __restrict__ grid,
+                                              const cplx<T>* __restrict__ far, double x1, double x2, double x3,
                                               double2* res, uint8_t& fl) {
-  constexpr int NO = (NF == 1) ? 1 : 6;
+  constexpr int NO = NOut<NF>::v;
   fl = 0;
   if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) {
     fl = 8;
@@ -259,131 +332,50 @@ __device__ __forceinline__ void eval3d_target(const GArgs& A, double x1, double 
     for (int o = 0; o < NO; ++o) res[o] = nan2();
     return;
   }
-  double n1, n2;
-  const double t1 = reduce_cell(x1, n1), t2 = reduce_cell(x2, n2);
-  T w1[4], w2[4], w3[4];
-  const double u1 = t1 * A.ih1, q1 = floor(u1);
-  lag4<T>((T)(u1 - q1), w1);
-  const double u2 = t2 * A.ih2, q2 = floor(u2);
-  lag4<T>((T)(u2 - q2), w2);
-  double2 L[NF];
-  const bool is_near = fabs(x3) <= A.c;
-  if (is_near) {
-    const double u = x3 * A.ih3, q = floor(u);
-    lag4<T>((T)(u - q), w3);
-    fetch(true, (int)q1, (int)q2, (int)q, w1, w2, w3, L);
-  } else {
-    fl |= 2;
-    if (A.smooth) {
-#pragma unroll
-      for (int o = 0; o < NO; ++o) res[o] = nan2();
-      return;
-    }
-    const double v = (fabs(x3) - (A.c - A.hf)) * A.ihf;
-    double s0 = floor(v);
-    if (s0 > A.S - 3) {
-      fl |= 4;
-#pragma unroll
-      for (int o = 0; o < NO; ++o) res[o] = nan2();
-      return;
-    }
-    s0 = fmax(s0, 1.0);
-    lag4<T>((T)(v - s0), w3);
-    fetch(false, (int)q1, (int)q2, (int)s0, w1, w2, w3, L);
-  }
-  if (A.smooth) {
-    // the smooth part L_N(t) of Algorithm 3.1 step 2d (near branch only)
-#pragma unroll
-    for (int o = 0; o < NO; ++o) res[o] = L[o < NF ? o : 0];
+  if (fabs(x3) <= A.c) {
+    Near3<T> s;
+    near3_stencil<T>(A, x1, x2, x3, s);
+    double2 L[NF];
+    near3_sum_global<T, NF>(A, grid, s, L);
+    near3_finish<T, NF>(A, x1, x2, x3, s, L, res, fl);
     return;
   }
-  double ps, pc;
-  sincos(A.a1 * x1 + A.a2 * x2, &ps, &pc);
-  const double2 phase = mk(pc, ps);
-  double2 G[NF];
+  fl |= 2;
+  Far3<T> s;
+  if (A.smooth || !far3_stencil<T>(A, x1, x2, x3, s)) {
+    if (!A.smooth) fl |= 4;
 #pragma unroll
-  for (int f = 0; f < NF; ++f) G[f] = cmul(phase, L[f]);
-  if (!is_near && NF == kMxF) {
-    // d/dx3 of e^{i beta |x3|} carries sgn(x3): fields 13 and 23
-    if (x3 < 0) {
-      G[4] = cscale(G[4], -1.0);
-      G[5] = cscale(G[5], -1.0);
-    }
+    for (int o = 0; o < NO; ++o) res[o] = nan2();
+    return;
   }
-  if (is_near) {
-    // the square root only inside the support of the singular part
-    const double r2 = t1 * t1 + t2 * t2 + x3 * x3;
-    if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
-      fl |= 1;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) G[f] = nan2();
-    } else if (r2 < 4.0 * A.eps * A.eps) {
-      const double r = sqrt(r2);
-      // psi = e^{ikr} Y(r) / (4 pi r): the removed singular part F, times e^{i alpha.x'}
-      double sn, cn;
-      sincos(A.k * r, &sn, &cn);
-      const double2 g = cscale(mk(cn, sn), 1.0 / (4.0 * kPi * r));
-      double ls, lc;
-      sincospi(2.0 * (A.a1 * n1 + A.a2 * n2), &ls, &lc);
-      const double2 lat = mk(lc, ls);
-      const double Y = cut_Y(r, A.eps);
-      G[0] = cadd(G[0], cmul(lat, cscale(g, Y)));
-      if (NF == kMxF) {
-        // psi', psi'' (radial); d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3)
-        const double Y1 = cut_Y1(r, A.eps), Y2 = cut_Y2(r, A.eps);
-        const double2 ikr = mk(-1.0 / r, A.k);  // ik - 1/r
-        const double2 g1 = cmul(g, ikr);
-        const double2 g2 = cmul(g, cadd(cmul(ikr, ikr), mk(1.0 / (r * r), 0.0)));
-        const double2 d1 = cadd(cscale(g1, Y), cscale(g, Y1));
-        const double2 d2 = cadd(cadd(cscale(g2, Y), cscale(g1, 2.0 * Y1)), cscale(g, Y2));
-        const double t[3] = {t1, t2, x3};
-        const int P[5] = {0, 1, 0, 0, 1}, Qp[5] = {0, 1, 1, 2, 2};
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          const double tp = t[P[f]], tq = t[Qp[f]];
-          const double a = tp * tq / (r * r);
-          const double bcoef = ((P[f] == Qp[f]) ? 1.0 / r : 0.0) - tp * tq / (r * r * r);
-          G[f + 1] = cadd(G[f + 1], cmul(lat, cadd(cscale(d2, a), cscale(d1, bcoef))));
-        }
-      }
-    }
-  }
-  if (NF == 1) {
-    res[0] = G[0];
-  } else {
-    // GG_pq = delta_pq G_d + k^-2 d_p d_q G_d  (eq. 4.1); fields 11 22 12 13 23, and GG_33 from
-    // the trace: tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d (the Helmholtz equation, off the lattice)
-    const double ik2 = 1.0 / (A.k * A.k);
-    res[0] = cadd(G[0], cscale(G[1], ik2));
-    res[1] = cadd(G[0], cscale(G[2], ik2));
-    res[2] = csub(cscale(G[0], 2.0), cadd(res[0], res[1]));
-#pragma unroll
-    for (int f = 3; f < 6; ++f) res[f] = cscale(G[f], ik2);
-  }
+  double2 L[NO];
+  far3_sum_global<T, NO>(A, far, s, L);
+  far3_finish<NO>(A, x1, x2, x3, L, res);
 }
 
-// 3D, unsorted targets: one thread per target, stencil read from global memory.
+// 3D, unsorted targets: one thread per target, stencils read from global memory.
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_gather3d(GArgs A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
                                                   long T_, cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T_) return;
-  constexpr int NO = (NF == 1) ? 1 : 6;
-  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+  constexpr int NO = NOut<NF>::v;
   double2 res[NO];
   uint8_t fl;
-  eval3d_target<T, NF>(A, x[3 * i], x[3 * i + 1], x[3 * i + 2], gf, res, fl);
+  eval3d_global<T, NF>(A, grid, far, x[3 * i], x[3 * i + 1], x[3 * i + 2], res, fl);
 #pragma unroll
   for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
   if (flags) flags[i] = fl;
 }
 
 // ---------------------------------------------------------------------------
-// Tiled gather over targets sorted by grid tile.  Tile key (see tile_key):
-// near  (b3 nt2 + b2) nt1 + b1,  far  nnear + (b3 nt2 + b2) nt1 + b1,  last = invalid.
-// A tile covers 2^tb nodes per axis; the stencils of its targets lie in the
-// (2^tb + 3)^3 footprint starting one node before the tile.
+// Tiled gathers over targets sorted by grid tile.  Keys (tile_key): near tiles
+// (b3 nt2 + b2) nt1 + b1 in [0, nnear); far tiles nnear + (b3 fnt2 + b2) fnt1 + b1;
+// the last key holds non-finite and out-of-slab targets.  A near tile covers 2^tb
+// nodes per axis and its targets' 4-point stencils lie in the (2^tb + 3)^3 footprint
+// starting one node before it; a far tile's 8-point stencils lie in (2^ftb + 7)^3
+// starting three nodes before it.
 // ---------------------------------------------------------------------------
 // A target in tile order: coordinates and caller index in one aligned 32-byte record.
 struct alignas(32) TRec {
@@ -392,9 +384,11 @@ struct alignas(32) TRec {
 };
 
 struct TileArgs {
-  int tb1, tb2, tb3;       // tile edge = 1 << tb
-  int nt1, nt2, nt3n;      // tiles along x1, x2, near x3
-  int nnear, nkeys;
+  int tb1, tb2, tb3;       // near tile edge = 1 << tb
+  int nt1, nt2, nt3n;      // near tiles along x1, x2, x3
+  int ftb1, ftb2, ftb3;    // far tile edge
+  int fnt1, fnt2, fnt3;    // far tiles along x1, x2 and the slab's slices
+  int nnear, nfar, nkeys;  // nkeys = nnear + nfar + 1
 };
 
 // 64-point stencil sum of one field from an LDS footprint with row length F1
@@ -424,92 +418,90 @@ __device__ __forceinline__ double2 lds_sum(const cplx<T>* base, const T a1[4], c
   return mk((double)accx, (double)accy);
 }
 
-// Stencil sum from the LDS-staged footprint of one tile (compile-time footprint
-// F1 x F2 x F3 so every LDS address is a base plus an immediate offset).  A
-// target whose stencil does not lie in the footprint (a rounding disagreement
-// with the key pass) is not evaluated here but appended to the overflow list.
-template <typename T, int NF, int F1, int F2, int F3>
-struct LdsFetch {
-  const cplx<T>* lds;      // [NF][F3][F2][F1]
-  int o1, o2, o3;
-  bool near_tile;
-  int M1, M2, M3;
-  mutable bool miss;
-  __device__ void operator()(bool near, int p1, int p2, int p3, const T w1[4], const T w2[4], const T w3[4],
-                             double2 L[NF]) const {
-    const int l1 = (p1 - 1 - o1) & (M1 - 1), l2 = (p2 - 1 - o2) & (M2 - 1);
-    const int l3 = near ? ((p3 - 1 - o3) & (M3 - 1)) : (p3 - 1 - o3);
-    if (near != near_tile || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4) {
-      miss = true;
-      return;
-    }
-    constexpr int FSZ = F1 * F2 * F3;
-    const cplx<T>* base = lds + (l3 * F2 + l2) * F1 + l1;
+// 512-point stencil sum of one far field from an LDS footprint (rows of F1, F2 rows per slice).
+template <typename T, int F1, int F2>
+__device__ __forceinline__ double2 lds_sum8(const cplx<T>* base, const T a1[8], const T a2[8], const T a3[8]) {
+  T accx = 0, accy = 0;
+  // slices in a rolled loop (the slice weight shifted into place, as in far3_sum_global); rows and
+  // nodes unrolled, so every LDS address is the slice base plus an immediate offset
+  T w3[8];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) L[f] = lds_sum<T, F1, F2>(base + f * FSZ, w1, w2, w3);
+  for (int m = 0; m < 8; ++m) w3[m] = a3[m];
+#pragma unroll 1
+  for (int c = 0; c < 8; ++c) {
+    const T wc = w3[0];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) w3[m] = w3[m + 1];
+    const cplx<T>* slice = base + c * (F2 * F1);
+    T px = 0, py = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const cplx<T>* row = slice + b * F1;
+      T rx = 0, ry = 0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const cplx<T> v = row[a];
+        rx += a1[a] * v.x;
+        ry += a1[a] * v.y;
+      }
+      px += a2[b] * rx;
+      py += a2[b] * ry;
+    }
+    accx += wc * px;
+    accy += wc * py;
   }
-};
+  return mk((double)accx, (double)accy);
+}
 
+// Stage field f's near footprint of a tile, (F1 x F2 x F3 nodes from (o1, o2, o3), periodic).
+template <typename T, int F1, int F2, int F3>
+__device__ __forceinline__ void stage_near(const GArgs& A, const cplx<T>* __restrict__ grid, int o1, int o2, int o3,
+                                           int nfield, cplx<T>* lds) {
+  constexpr int FSZ = F1 * F2 * F3;
+  for (int idx = threadIdx.x; idx < nfield * FSZ; idx += blockDim.x) {
+    const int f = idx / FSZ, r = idx - f * FSZ;
+    const int z = r / (F1 * F2), y = (r / F1) % F2, xx = r % F1;
+    const int g1 = (o1 + xx) & (A.M1 - 1), g2 = (o2 + y) & (A.M2 - 1), g3 = (o3 + z) & (A.M3 - 1);
+    lds[idx] = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+  }
+}
+
+// Stage far field f's footprint of a tile (periodic in x1, x2; slices clamped to the slab:
+// the clamped ones are never used by a stencil that lies in the slab).
+template <typename T, int F1, int F2, int F3>
+__device__ __forceinline__ void stage_far(const GArgs& A, const cplx<T>* __restrict__ far, int o1, int o2, int o3,
+                                          cplx<T>* lds) {
+  constexpr int FSZ = F1 * F2 * F3;
+  for (int idx = threadIdx.x; idx < FSZ; idx += blockDim.x) {
+    const int z = idx / (F1 * F2), y = (idx / F1) % F2, xx = idx % F1;
+    const int g1 = (o1 + xx) & (A.Mf1 - 1), g2 = (o2 + y) & (A.Mf2 - 1);
+    const int g3 = min(max(o3 + z, 0), A.S - 1);
+    lds[idx] = far[((long)g3 * A.Mf2 + g2) * A.Mf1 + g1];
+  }
+}
+
+// Near tiles: one block per tile, keys [0, nnear).  Stages the NF fields' footprint in LDS,
+// then interpolates its targets (the next record prefetched); FP32 weights on the complex64
+// path, FP64 add-back and phase, results in the caller's order.  A target whose stencil does
+// not lie in the footprint (a rounding disagreement with the key pass) goes to the overflow list.
 template <typename T, int NF, int TB1, int TB2, int TB3, int BS>
-__global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
-                                                        const cplx<T>* __restrict__ far,
-                                                        const TRec* __restrict__ rec,
-                                                        const uint32_t* __restrict__ hist,
-                                                        const uint32_t* __restrict__ offs,
-                                                        cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
-                                                        uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+__global__ __launch_bounds__(BS) void k_gather3d_near(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+                                                       const TRec* __restrict__ rec,
+                                                       const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ offs,
+                                                       cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
+                                                       uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
   constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
+  constexpr int NO = NOut<NF>::v;
   __shared__ cplx<T> lds[NF * FSZ];
-  constexpr int NO = (NF == 1) ? 1 : 6;
-  // far tiles (more targets each, keys >= nnear) first, then near tiles; blocks go
-  // round-robin over the XCDs so every XCD gets the same mix
-  const int key = B.nkeys - 1 - (int)blockIdx.x;
+  const int key = (int)blockIdx.x;
   const uint32_t cnt = hist[key];
   if (cnt == 0) return;
   const long start = offs[key];
-  if (key >= B.nkeys - 1) {
-    // non-finite targets and targets beyond the far slab: NaN and their flags
-    const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
-    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
-      const TRec r = rec[j];
-      const long i = r.i;
-      double2 res[NO];
-      uint8_t fl;
-      eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
-#pragma unroll
-      for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
-      if (flags) flags[i] = fl;
-    }
-    return;
-  }
-  LdsFetch<T, NF, F1, F2, F3> lf;
-  lf.lds = lds;
-  lf.M1 = A.M1;
-  lf.M2 = A.M2;
-  lf.M3 = A.M3;
-  const bool near = key < B.nnear;
-  const int kk = near ? key : key - B.nnear;
-  const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
-  lf.near_tile = near;
-  lf.o1 = (b1 << TB1) - 1;
-  lf.o2 = (b2 << TB2) - 1;
-  lf.o3 = (b3 << TB3) - 1;
-  for (int idx = threadIdx.x; idx < NF * FSZ; idx += blockDim.x) {
-    const int f = idx / FSZ, r = idx - f * FSZ;
-    const int z = r / (F1 * F2), y = (r / F1) % F2, xx = r % F1;
-    const int g1 = (lf.o1 + xx) & (A.M1 - 1), g2 = (lf.o2 + y) & (A.M2 - 1);
-    cplx<T> v;
-    if (near) {
-      const int g3 = (lf.o3 + z) & (A.M3 - 1);
-      v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-    } else {
-      const int g3 = min(max(lf.o3 + z, 0), A.S - 1);
-      v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-    }
-    lds[idx] = v;
-  }
+  const int b1 = key % B.nt1, b2 = (key / B.nt1) % B.nt2, b3 = key / (B.nt1 * B.nt2);
+  const int o1 = (b1 << TB1) - 1, o2 = (b2 << TB2) - 1, o3 = (b3 << TB3) - 1;
+  stage_near<T, F1, F2, F3>(A, grid, o1, o2, o3, NF, lds);
   __syncthreads();
-  // the next record is loaded before the current one is evaluated
   const long end = start + (long)cnt;
   long j = start + threadIdx.x;
   TRec r{};
@@ -517,13 +509,19 @@ __global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, cons
   for (; j < end; j += BS) {
     TRec rn = r;
     if (j + BS < end) rn = rec[j + BS];
-    double2 res[NO];
-    uint8_t fl;
-    lf.miss = false;
-    eval3d_target<T, NF>(A, r.x, r.y, r.z, lf, res, fl);
-    if (lf.miss) {
+    Near3<T> s;
+    near3_stencil<T>(A, r.x, r.y, r.z, s);
+    const int l1 = (s.p1 - 1 - o1) & (A.M1 - 1), l2 = (s.p2 - 1 - o2) & (A.M2 - 1), l3 = (s.p3 - 1 - o3) & (A.M3 - 1);
+    if (l1 > F1 - 4 || l2 > F2 - 4 || l3 > F3 - 4) {
       ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
     } else {
+      double2 L[NF];
+      const cplx<T>* base = lds + (l3 * F2 + l2) * F1 + l1;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) L[f] = lds_sum<T, F1, F2>(base + f * FSZ, s.w1, s.w2, s.w3);
+      double2 res[NO];
+      uint8_t fl = 0;
+      near3_finish<T, NF>(A, r.x, r.y, r.z, s, L, res, fl);
       const long i = r.i;
 #pragma unroll
       for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
@@ -533,97 +531,140 @@ __global__ __launch_bounds__(BS) void k_gather3d_tiled(GArgs A, TileArgs B, cons
   }
 }
 
-// Maxwell tensor over targets sorted by tile, one field at a time: the tile's
-// footprint of field f is staged in LDS, every target of the tile takes its
-// stencil sum of field f, then the next field replaces it.  Used when the tiles
-// hold few targets (fewer than about two blocks' worth), so a footprint of all
-// six fields would not fit LDS at a useful tile size.  Up to 256 targets per
-// pass; a tile with more runs several passes, staging again.
-template <typename T, int TB1, int TB2, int TB3>
-__global__ __launch_bounds__(256) void k_gather3d_fields(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
-                                                         const cplx<T>* __restrict__ far,
-                                                         const TRec* __restrict__ rec,
-                                                         const uint32_t* __restrict__ hist,
-                                                         const uint32_t* __restrict__ offs,
-                                                         cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
-                                                         uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+// Maxwell near tiles with few targets each: the fields are staged one after another into one
+// footprint, each target's stencil sums kept in registers; up to BS targets per pass.
+template <typename T, int NF, int TB1, int TB2, int TB3>
+__global__ __launch_bounds__(256) void k_gather3d_near_fields(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+                                                              const TRec* __restrict__ rec,
+                                                              const uint32_t* __restrict__ hist,
+                                                              const uint32_t* __restrict__ offs,
+                                                              cplx<T>* __restrict__ out,
+                                                              uint8_t* __restrict__ flags,
+                                                              uint32_t* __restrict__ ovf,
+                                                              uint32_t* __restrict__ novf) {
   constexpr int F1 = (1 << TB1) + 3, F2 = (1 << TB2) + 3, F3 = (1 << TB3) + 3, FSZ = F1 * F2 * F3;
-  constexpr int NF = kMxF, NO = 6;
+  constexpr int NO = NOut<NF>::v;
   __shared__ cplx<T> lds[FSZ];
-  const int key = B.nkeys - 1 - (int)blockIdx.x;
+  const int key = (int)blockIdx.x;
   const uint32_t cnt = hist[key];
   if (cnt == 0) return;
   const long start = offs[key];
-  if (key >= B.nkeys - 1) {
-    const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
-    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
-      const TRec r = rec[j];
-      double2 res[NO];
-      uint8_t fl;
-      eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
-#pragma unroll
-      for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, res[o]);
-      if (flags) flags[r.i] = fl;
-    }
-    return;
-  }
-  const bool near = key < B.nnear;
-  const int kk = near ? key : key - B.nnear;
-  const int b1 = kk % B.nt1, b2 = (kk / B.nt1) % B.nt2, b3 = kk / (B.nt1 * B.nt2);
+  const int b1 = key % B.nt1, b2 = (key / B.nt1) % B.nt2, b3 = key / (B.nt1 * B.nt2);
   const int o1 = (b1 << TB1) - 1, o2 = (b2 << TB2) - 1, o3 = (b3 << TB3) - 1;
   for (long c0 = 0; c0 < (long)cnt; c0 += blockDim.x) {
     const long j = start + c0 + threadIdx.x;
     const bool valid = c0 + (long)threadIdx.x < (long)cnt;
     TRec r{};
-    Stencil3<T> st;
-    double2 res[NO];
-    uint8_t fl = 0;
-    bool go = false, miss = false;
+    Near3<T> s;
+    bool miss = false;
     int l1 = 0, l2 = 0, l3 = 0;
     if (valid) {
       r = rec[j];
-      go = stencil3d<T, NO>(A, r.x, r.y, r.z, st, res, fl);
-      if (go) {
-        l1 = (st.p1 - 1 - o1) & (A.M1 - 1);
-        l2 = (st.p2 - 1 - o2) & (A.M2 - 1);
-        l3 = st.near ? ((st.p3 - 1 - o3) & (A.M3 - 1)) : (st.p3 - 1 - o3);
-        miss = st.near != near || l1 > F1 - 4 || l2 > F2 - 4 || l3 < 0 || l3 > F3 - 4;
-      }
+      near3_stencil<T>(A, r.x, r.y, r.z, s);
+      l1 = (s.p1 - 1 - o1) & (A.M1 - 1);
+      l2 = (s.p2 - 1 - o2) & (A.M2 - 1);
+      l3 = (s.p3 - 1 - o3) & (A.M3 - 1);
+      miss = l1 > F1 - 4 || l2 > F2 - 4 || l3 > F3 - 4;
     }
     double2 L[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       __syncthreads();   // the previous field's sums are done
-      for (int idx = threadIdx.x; idx < FSZ; idx += blockDim.x) {
-        const int z = idx / (F1 * F2), y = (idx / F1) % F2, xx = idx % F1;
-        const int g1 = (o1 + xx) & (A.M1 - 1), g2 = (o2 + y) & (A.M2 - 1);
-        cplx<T> v;
-        if (near) {
-          const int g3 = (o3 + z) & (A.M3 - 1);
-          v = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-        } else {
-          const int g3 = min(max(o3 + z, 0), A.S - 1);
-          v = far[f * A.ffs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
-        }
-        lds[idx] = v;
-      }
+      stage_near<T, F1, F2, F3>(A, grid + f * A.fs, o1, o2, o3, 1, lds);
       __syncthreads();
-      if (go && !miss) L[f] = lds_sum<T, F1, F2>(lds + (l3 * F2 + l2) * F1 + l1, st.w1, st.w2, st.w3);
+      if (valid && !miss) L[f] = lds_sum<T, F1, F2>(lds + (l3 * F2 + l2) * F1 + l1, s.w1, s.w2, s.w3);
     }
     if (!valid) continue;
-    if (go && miss) {
+    if (miss) {
       ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
       continue;
     }
-    if (go) finish3d<T, NF>(A, r.x, r.y, r.z, st, L, res, fl);
+    double2 res[NO];
+    uint8_t fl = 0;
+    near3_finish<T, NF>(A, r.x, r.y, r.z, s, L, res, fl);
 #pragma unroll
     for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, res[o]);
     if (flags) flags[r.i] = fl;
   }
 }
 
-// Targets the tiled kernel handed over (stencil outside its tile footprint):
-// evaluated from global memory.  The count is read on the device.
+// Far tiles: one block per far key (keys nnear .. nnear + nfar - 1), and one more block for
+// the last key (non-finite and out-of-slab targets, evaluated from global memory).  The 8-point
+// footprint of one field is staged at a time: for one field (G_d) once per tile; for the six
+// Maxwell entries field by field for each pass of BS targets, whose sums stay in registers.
+template <typename T, int NF, int FB1, int FB2, int FB3, int BS>
+__global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
+                                                      const cplx<T>* __restrict__ far,
+                                                      const TRec* __restrict__ rec,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ offs,
+                                                      cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
+                                                      uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+  constexpr int F1 = (1 << FB1) + 7, F2 = (1 << FB2) + 7, F3 = (1 << FB3) + 7;
+  constexpr int NO = NOut<NF>::v;
+  __shared__ cplx<T> lds[F1 * F2 * F3];
+  const int key = B.nnear + (int)blockIdx.x;
+  const uint32_t cnt = hist[key];
+  if (cnt == 0) return;
+  const long start = offs[key];
+  if (key == B.nkeys - 1) {
+    // non-finite coordinates (flag 8) and far targets beyond the slab (flags 2 and 4): NaN
+    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
+      const TRec r = rec[j];
+      const bool fin = isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, nan2());
+      if (flags) flags[r.i] = fin ? 6 : 8;
+    }
+    return;
+  }
+  const int kk = key - B.nnear;
+  const int b1 = kk % B.fnt1, b2 = (kk / B.fnt1) % B.fnt2, b3 = kk / (B.fnt1 * B.fnt2);
+  const int o1 = (b1 << FB1) - 3, o2 = (b2 << FB2) - 3, o3 = (b3 << FB3) - 3;
+  if (NO == 1) {
+    stage_far<T, F1, F2, F3>(A, far, o1, o2, o3, lds);
+    __syncthreads();
+  }
+  for (long c0 = 0; c0 < (long)cnt; c0 += BS) {
+    const long j = start + c0 + threadIdx.x;
+    const bool valid = c0 + (long)threadIdx.x < (long)cnt;
+    TRec r{};
+    Far3<T> s;
+    bool miss = false;
+    int l1 = 0, l2 = 0, l3 = 0;
+    if (valid) {
+      r = rec[j];
+      miss = !far3_stencil<T>(A, r.x, r.y, r.z, s);
+      l1 = (s.p1 - 3 - o1) & (A.Mf1 - 1);
+      l2 = (s.p2 - 3 - o2) & (A.Mf2 - 1);
+      l3 = s.s0 - 3 - o3;
+      miss = miss || l1 > F1 - 8 || l2 > F2 - 8 || l3 < 0 || l3 > F3 - 8;
+    }
+    double2 L[NO];
+#pragma unroll
+    for (int f = 0; f < NO; ++f) {
+      if (NO > 1) {
+        __syncthreads();   // the previous field's sums are done
+        stage_far<T, F1, F2, F3>(A, far + f * A.ffs, o1, o2, o3, lds);
+        __syncthreads();
+      }
+      if (valid && !miss) L[f] = lds_sum8<T, F1, F2>(lds + (l3 * F2 + l2) * F1 + l1, s.w1, s.w2, s.w3);
+    }
+    if (!valid) continue;
+    if (miss) {
+      ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
+      continue;
+    }
+    double2 res[NO];
+    far3_finish<NO>(A, r.x, r.y, r.z, L, res);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) store_out<T>(out, (long)r.i * NO + o, res[o]);
+    if (flags) flags[r.i] = 2;
+  }
+}
+
+// Targets the tiled kernels handed over (stencil outside the tile footprint): evaluated
+// from global memory.  The count is read on the device.
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T>* __restrict__ grid,
                                                            const cplx<T>* __restrict__ far,
@@ -631,15 +672,14 @@ __global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T
                                                            const uint32_t* __restrict__ ovf,
                                                            const uint32_t* __restrict__ novf,
                                                            cplx<T>* __restrict__ out, uint8_t* __restrict__ flags) {
-  constexpr int NO = (NF == 1) ? 1 : 6;
-  const GlobalFetch<T, NF> gf{grid, far, A.fs, A.ffs, A.M1, A.M2, A.M3};
+  constexpr int NO = NOut<NF>::v;
   const long n = *novf;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
     const TRec r = rec[ovf[q]];
     const long i = r.i;
     double2 res[NO];
     uint8_t fl;
-    eval3d_target<T, NF>(A, r.x, r.y, r.z, gf, res, fl);
+    eval3d_global<T, NF>(A, grid, far, r.x, r.y, r.z, res, fl);
 #pragma unroll
     for (int o = 0; o < NO; ++o) store_out<T>(out, i * NO + o, res[o]);
     if (flags) flags[i] = fl;
@@ -800,6 +840,37 @@ __device__ __forceinline__ void ring_mark(const GArgs& A, bool take, long i, lon
   if (__lane_id() == 0 && i < T_) A.ring_mask[i >> 6] = m;
 }
 
+// Far branch of the 2D kinds (Algorithm 2.1 step 2b, the series (1.2) and its term-wise
+// derivatives): the far slab [field][s][i1] (Mf1 modes, slices fz0 + s hf) interpolated with
+// 8 x 8 nodes.  false when |x2| lies beyond the slab.
+template <typename T, int NF>
+__device__ __forceinline__ bool far2d_sum(const GArgs& A, const cplx<T>* __restrict__ far, double t, double z,
+                                          double2 L[NF]) {
+  double s0, f2;
+  if (!far_slice(A, z, s0, f2)) return false;
+  T w1[8], w2[8];
+  const double u = t * A.ihf1, p = floor(u);
+  lag8<T>((T)(u - p), w1);
+  lag8<T>((T)f2, w2);
+  const int i0 = (int)p - 3;
+  const long r0 = (long)s0 - 3;
+  Acc<T> acc[NF];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const long row = (r0 + b) * A.Mf1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const T w = w2[b] * w1[a];
+      const long o = row + ((i0 + a) & (A.Mf1 - 1));
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f].add(w, far[f * A.ffs + o]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) L[f] = acc[f].get();
+  return true;
+}
+
 // One target of Algorithm 2.1 step 2; returns whether it lies in the cut-off ring.
 template <typename T>
 __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __restrict__ grid,
@@ -815,72 +886,55 @@ __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __re
   } else {
     double n1;
     const double t = reduce_cell(x1, n1);
-    T w1[4], w2[4];
-    const double u = t * A.ih1, p = floor(u);
-    lag4<T>((T)(u - p), w1);
-    const int i0 = ((int)p - 1) & (A.M1 - 1);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
     const double2 phase = mk(pc, ps);
-    const bool is_near = fabs(x2) <= A.c;
-    long rows[4];
-    const cplx<T>* g = grid;
-    bool bad = false;
-    if (is_near) {
+    double2 Lt;
+    if (fabs(x2) <= A.c) {
+      T w1[4], w2[4];
+      const double u = t * A.ih1, p = floor(u);
+      lag4<T>((T)(u - p), w1);
+      const int i0 = ((int)p - 1) & (A.M1 - 1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
+      long rows[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
+      if constexpr (sizeof(T) == 4) {
+        if (A.quad) Lt = stencil2d_quad(grid, rows, i0, w1, w2);
+        else Lt = stencil2d<T>(grid, rows, i0, A.M1, w1, w2);
+      } else {
+        Lt = stencil2d<T>(grid, rows, i0, A.M1, w1, w2);
+      }
+      const double r = sqrt(t * t + x2 * x2);
+      if (r <= A.rmin || r == 0.0) {
+        fl |= 1;
+        Lt = nan2();
+      } else if (r < 2.0 * A.eps) {
+        // K_N = L_N + f1 - i alpha f2 = L_N - (1/2pi) ln r Y(r) (1 - i alpha t)
+        const double s = -log(r) * cut_Y(r, A.eps) / (2.0 * kPi);
+        in_ring = r > A.ring_lo;
+        if (A.sing_order <= 1) {
+          Lt = cadd(Lt, mk(s, -A.a1 * t * s));
+        } else {
+          // the higher-order factor P_m: 1 - i a t - (a^2/2) t^2 - (k^2/4) r^2 + i (a^3/6) t^3 + i (a k^2/4) t r^2
+          const double a = A.a1, kk = 0.25 * A.k * A.k, r2 = t * t + x2 * x2;
+          const double pr = 1.0 - 0.5 * a * a * t * t - kk * r2;
+          double pim = -a * t;
+          if (A.sing_order >= 3) pim += a * t * (a * a * t * t / 6.0 + kk * r2);
+          Lt = cadd(Lt, mk(s * pr, s * pim));
+        }
+      } else if (r < A.ring_hi) {
+        in_ring = r > A.ring_lo;
+      }
     } else {
       fl |= 2;
-      g = far;
-      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
-      double s0 = floor(v);
-      if (s0 > A.S - 3) {
-        bad = true;
+      if (!far2d_sum<T, 1>(A, far, t, fabs(x2), &Lt)) {
         fl |= 4;
-      } else {
-        s0 = fmax(s0, 1.0);
-        lag4<T>((T)(v - s0), w2);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
+        Lt = nan2();
       }
     }
-    if (bad) {
-      res = nan2();
-    } else {
-      double2 Lt;
-      if constexpr (sizeof(T) == 4) {
-        if (A.quad) Lt = stencil2d_quad(g, rows, i0, w1, w2);
-        else Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
-      } else {
-        Lt = stencil2d<T>(g, rows, i0, A.M1, w1, w2);
-      }
-      if (is_near) {
-        const double r = sqrt(t * t + x2 * x2);
-        if (r <= A.rmin || r == 0.0) {
-          fl |= 1;
-          Lt = nan2();
-        } else if (r < 2.0 * A.eps) {
-          // K_N = L_N + f1 - i alpha f2 = L_N - (1/2pi) ln r Y(r) (1 - i alpha t)
-          const double s = -log(r) * cut_Y(r, A.eps) / (2.0 * kPi);
-          in_ring = r > A.ring_lo;
-          if (A.sing_order <= 1) {
-            Lt = cadd(Lt, mk(s, -A.a1 * t * s));
-          } else {
-            // the higher-order factor P_m: 1 - i a t - (a^2/2) t^2 - (k^2/4) r^2 + i (a^3/6) t^3 + i (a k^2/4) t r^2
-            const double a = A.a1, kk = 0.25 * A.k * A.k, r2 = t * t + x2 * x2;
-            const double pr = 1.0 - 0.5 * a * a * t * t - kk * r2;
-            double pim = -a * t;
-            if (A.sing_order >= 3) pim += a * t * (a * a * t * t / 6.0 + kk * r2);
-            Lt = cadd(Lt, mk(s * pr, s * pim));
-          }
-        } else if (r < A.ring_hi) {
-          in_ring = r > A.ring_lo;
-        }
-      }
-      res = cmul(phase, Lt);
-    }
+    res = cmul(phase, Lt);
   }
   store_out<T>(out, i, res);
   if (flags) flags[i] = fl;
@@ -1070,9 +1124,10 @@ __global__ __launch_bounds__(256) void k_gather2d(GArgs A, const cplx<T>* __rest
 
 // One target of the 2D gradient (Section 2.4.1): both fields interpolated with one
 // stencil, the singular parts h1, h2 added back in FP64 inside 2 eps, the phase
-// e^{i alpha x1}; beyond c the differentiated far slab, the x2 field times sgn(x2).
-// grid and far hold the two fields interleaved per node.  out[2i] = dG/dx1, out[2i+1] = dG/dx2.
-// Returns whether the target lies in the cut-off ring (when the plan marks them).
+// e^{i alpha x1}; beyond c the far slab of the differentiated series, the x2 field times
+// sgn(x2).  grid holds the two near fields interleaved per node, far the two far fields one
+// after the other.  out[2i] = dG/dx1, out[2i+1] = dG/dx2.  Returns whether the target lies in
+// the cut-off ring (when the plan marks them).
 template <typename T>
 __device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>* __restrict__ grid,
                                                   const cplx<T>* __restrict__ far, const double* __restrict__ x,
@@ -1087,66 +1142,48 @@ __device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>*
   } else {
     double n1;
     const double t = reduce_cell(x1, n1);
-    T w1[4], w2[4];
-    const double u = t * A.ih1, p = floor(u);
-    lag4<T>((T)(u - p), w1);
-    const int i0 = ((int)p - 1) & (A.M1 - 1);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
     const double2 phase = mk(pc, ps);
-    const bool is_near = fabs(x2) <= A.c;
-    long rows[4];
-    const cplx<T>* g = grid;
-    bool bad = false;
-    if (is_near) {
+    double2 L[2];
+    if (fabs(x2) <= A.c) {
+      T w1[4], w2[4];
+      const double u = t * A.ih1, p = floor(u);
+      lag4<T>((T)(u - p), w1);
+      const int i0 = ((int)p - 1) & (A.M1 - 1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
+      long rows[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
+      stencil2d_fields<T, 2>(grid, rows, i0, A.M1, w1, w2, L);
+      const double r2 = t * t + x2 * x2;
+      if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+        fl |= 1;
+        L[0] = L[1] = nan2();
+      } else {
+        if (r2 < 4.0 * A.eps * A.eps) {
+          double2 h1, h2;
+          hgrad_at(A, t, x2, h1, h2);
+          L[0] = cadd(L[0], h1);
+          L[1] = cadd(L[1], h2);
+        }
+        if (A.ring_mask) {
+          const double r = sqrt(r2);
+          in_ring = r > A.ring_lo && r < A.ring_hi;
+        }
+      }
     } else {
       fl |= 2;
-      g = far;
-      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
-      double s0 = floor(v);
-      if (s0 > A.S - 3) {
-        bad = true;
+      if (!far2d_sum<T, 2>(A, far, t, fabs(x2), L)) {
         fl |= 4;
-      } else {
-        s0 = fmax(s0, 1.0);
-        lag4<T>((T)(v - s0), w2);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
-      }
-    }
-    if (bad) {
-      d1 = d2 = nan2();
-    } else {
-      double2 L[2];
-      stencil2d_fields<T, 2>(g, rows, i0, A.M1, w1, w2, L);
-      double2 L1 = L[0], L2 = L[1];
-      if (is_near) {
-        const double r2 = t * t + x2 * x2;
-        if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
-          fl |= 1;
-          L1 = L2 = nan2();
-        } else {
-          if (r2 < 4.0 * A.eps * A.eps) {
-            double2 h1, h2;
-            hgrad_at(A, t, x2, h1, h2);
-            L1 = cadd(L1, h1);
-            L2 = cadd(L2, h2);
-          }
-          if (A.ring_mask) {
-            const double r = sqrt(r2);
-            in_ring = r > A.ring_lo && r < A.ring_hi;
-          }
-        }
+        L[0] = L[1] = nan2();
       } else if (x2 < 0.0) {
-        L2 = cscale(L2, -1.0);
+        L[1] = cscale(L[1], -1.0);
       }
-      d1 = cmul(phase, L1);
-      d2 = cmul(phase, L2);
     }
+    d1 = cmul(phase, L[0]);
+    d2 = cmul(phase, L[1]);
   }
   store_out<T>(out, 2 * i, d1);
   store_out<T>(out, 2 * i + 1, d2);
@@ -1166,7 +1203,8 @@ __global__ __launch_bounds__(256) void k_gather2d_grad(GArgs A, const cplx<T>* _
 
 // One target of the second-derivative differences (Section 2.4.2): three fields with one
 // stencil, h_pq added back in FP64 inside 2 eps, the phase e^{i alpha x1}; beyond c the far
-// slab, the 12 field times sgn(x2).  grid and far hold the three fields interleaved per node.
+// slab of the twice-differentiated series, the 12 field times sgn(x2).  grid holds the three
+// near fields interleaved per node, far the three far fields one after the other.
 // out[3i + p] = d_p d_q G_k1 - d_p d_q G_k2, pq = 11, 12, 22.
 template <typename T>
 __device__ __forceinline__ bool gather2d_hess_one(const GArgs& A, const cplx<T>* __restrict__ grid,
@@ -1175,75 +1213,57 @@ __device__ __forceinline__ bool gather2d_hess_one(const GArgs& A, const cplx<T>*
   const double x1 = x[2 * i], x2 = x[2 * i + 1];
   uint8_t fl = 0;
   bool in_ring = false;
-  double2 d[3];
+  double2 L[3];
   if (!(isfinite(x1) && isfinite(x2))) {
     fl = 8;
-    d[0] = d[1] = d[2] = nan2();
+    L[0] = L[1] = L[2] = nan2();
   } else {
     double n1;
     const double t = reduce_cell(x1, n1);
-    T w1[4], w2[4];
-    const double u = t * A.ih1, p = floor(u);
-    lag4<T>((T)(u - p), w1);
-    const int i0 = ((int)p - 1) & (A.M1 - 1);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
     const double2 phase = mk(pc, ps);
-    const bool is_near = fabs(x2) <= A.c;
-    long rows[4];
-    const cplx<T>* g = grid;
-    bool bad = false;
-    if (is_near) {
+    if (fabs(x2) <= A.c) {
+      T w1[4], w2[4];
+      const double u = t * A.ih1, p = floor(u);
+      lag4<T>((T)(u - p), w1);
+      const int i0 = ((int)p - 1) & (A.M1 - 1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
+      long rows[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) rows[b] = (long)(((int)p2 - 1 + b) & (A.M2 - 1)) * A.M1;
+      stencil2d_fields<T, 3>(grid, rows, i0, A.M1, w1, w2, L);
+      const double r2 = t * t + x2 * x2;
+      if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
+        fl |= 1;
+        L[0] = L[1] = L[2] = nan2();
+      } else {
+        if (r2 < 4.0 * A.eps * A.eps) {
+          double2 h[3];
+          hhess_at(A, t, x2, h);
+#pragma unroll
+          for (int f = 0; f < 3; ++f) L[f] = cadd(L[f], h[f]);
+        }
+        if (A.ring_mask) {
+          const double r = sqrt(r2);
+          in_ring = r > A.ring_lo && r < A.ring_hi;
+        }
+      }
     } else {
       fl |= 2;
-      g = far;
-      const double v = (fabs(x2) - (A.c - A.hf)) * A.ihf;
-      double s0 = floor(v);
-      if (s0 > A.S - 3) {
-        bad = true;
+      if (!far2d_sum<T, 3>(A, far, t, fabs(x2), L)) {
         fl |= 4;
-      } else {
-        s0 = fmax(s0, 1.0);
-        lag4<T>((T)(v - s0), w2);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rows[b] = ((long)s0 - 1 + b) * A.M1;
-      }
-    }
-    if (bad) {
-      d[0] = d[1] = d[2] = nan2();
-    } else {
-      double2 L[3];
-      stencil2d_fields<T, 3>(g, rows, i0, A.M1, w1, w2, L);
-      if (is_near) {
-        const double r2 = t * t + x2 * x2;
-        if (r2 <= A.rmin * A.rmin || r2 == 0.0) {
-          fl |= 1;
-          L[0] = L[1] = L[2] = nan2();
-        } else {
-          if (r2 < 4.0 * A.eps * A.eps) {
-            double2 h[3];
-            hhess_at(A, t, x2, h);
-#pragma unroll
-            for (int f = 0; f < 3; ++f) L[f] = cadd(L[f], h[f]);
-          }
-          if (A.ring_mask) {
-            const double r = sqrt(r2);
-            in_ring = r > A.ring_lo && r < A.ring_hi;
-          }
-        }
+        L[0] = L[1] = L[2] = nan2();
       } else if (x2 < 0.0) {
         L[1] = cscale(L[1], -1.0);
       }
-#pragma unroll
-      for (int f = 0; f < 3; ++f) d[f] = cmul(phase, L[f]);
     }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) L[f] = cmul(phase, L[f]);
   }
 #pragma unroll
-  for (int f = 0; f < 3; ++f) store_out<T>(out, 3 * i + f, d[f]);
+  for (int f = 0; f < 3; ++f) store_out<T>(out, 3 * i + f, L[f]);
   if (flags) flags[i] = fl;
   return in_ring;
 }
@@ -1289,25 +1309,31 @@ __global__ __launch_bounds__(256) void k_gather2d_multi(const GatherInst* __rest
 // inside each tile, one-block exclusive scan, scatter into tile order.
 // ---------------------------------------------------------------------------
 struct BinArgs {
-  double c, ih1, ih2, ih3, hf, ihf;
-  int M1, M2, M3, S;
+  double c, ih1, ih2, ih3;
+  double fz0, ihf, ihf1, ihf2;   // far slab: first slice, reciprocal spacings
+  int M1, M2, M3, S, Mf1, Mf2;
   TileArgs t;
 };
 
+// The tile of a target: the tile of its stencil's base node (near: the 4-point base on the
+// near grid; far: the 8-point base on the far slab), the same arithmetic as the gathers'.
 __device__ __forceinline__ uint32_t tile_key(const BinArgs& B, double x1, double x2, double x3) {
   if (!(isfinite(x1) && isfinite(x2) && isfinite(x3))) return B.t.nkeys - 1;
   double n;
   const double t1 = reduce_cell(x1, n), t2 = reduce_cell(x2, n);
-  const int b1 = (((int)floor(t1 * B.ih1)) & (B.M1 - 1)) >> B.t.tb1;
-  const int b2 = (((int)floor(t2 * B.ih2)) & (B.M2 - 1)) >> B.t.tb2;
   if (fabs(x3) <= B.c) {
+    const int b1 = (((int)floor(t1 * B.ih1)) & (B.M1 - 1)) >> B.t.tb1;
+    const int b2 = (((int)floor(t2 * B.ih2)) & (B.M2 - 1)) >> B.t.tb2;
     const int b3 = (((int)floor(x3 * B.ih3)) & (B.M3 - 1)) >> B.t.tb3;
     return (uint32_t)((b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
   }
-  const double s0 = floor((fabs(x3) - (B.c - B.hf)) * B.ihf);
-  if (s0 > B.S - 3) return B.t.nkeys - 1;
-  const int b3 = ((int)fmax(s0, 1.0)) >> B.t.tb3;
-  return (uint32_t)(B.t.nnear + (b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
+  double s0 = floor((fabs(x3) - B.fz0) * B.ihf);
+  if (!(s0 <= B.S - 5)) return B.t.nkeys - 1;
+  s0 = fmax(s0, (double)kFarLo);
+  const int b1 = (((int)floor(t1 * B.ihf1)) & (B.Mf1 - 1)) >> B.t.ftb1;
+  const int b2 = (((int)floor(t2 * B.ihf2)) & (B.Mf2 - 1)) >> B.t.ftb2;
+  const int b3 = (int)s0 >> B.t.ftb3;
+  return (uint32_t)(B.t.nnear + (b3 * B.t.fnt2 + b2) * B.t.fnt1 + b1);
 }
 
 __global__ void k_zero_u32(uint32_t* __restrict__ p, long n) {
@@ -1498,8 +1524,7 @@ __global__ __launch_bounds__(256) void k_quads(const float2* __restrict__ in, fl
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
 
 template <typename T>
-hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags, int smooth = 0,
-                       int mode = kGatherAll, hipStream_t bin_stream = nullptr) {
+GArgs make_gargs(const Plan& P, int smooth) {
   GArgs A;
   A.k = P.last_k;
   A.k2 = P.last_k2;
@@ -1523,9 +1548,14 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   A.ih1 = 1.0 / A.h1;
   A.ih2 = 1.0 / A.h2;
   A.ih3 = A.h3 > 0.0 ? 1.0 / A.h3 : 0.0;
-  A.hf = P.p.far_h;
-  A.ihf = 1.0 / A.hf;
+  A.hf = P.hf;
+  A.ihf = 1.0 / P.hf;
+  A.fz0 = P.fz0;
   A.S = P.S;
+  A.Mf1 = P.Mf1;
+  A.Mf2 = P.Mf2;
+  A.ihf1 = P.Mf1 / (2.0 * kPi);
+  A.ihf2 = P.Mf2 / (2.0 * kPi);
   A.fs = (long)P.ncell;
   A.ffs = (long)P.nfar;
   A.smooth = smooth;
@@ -1537,53 +1567,62 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   const double reach = 2.0 * sqrt(2.0) * fmax(A.h1, A.h2);
   A.ring_lo = fmax(A.eps, 0.5 * A.eps + reach);
   A.ring_hi = 2.0 * A.eps + reach;
+  return A;
+}
+
+template <typename T>
+hipError_t gather2d_impl(Plan& P, GArgs& A, const double* x, int64_t T_, void* out, uint8_t* flags) {
+  const auto* g = static_cast<const cplx<T>*>(P.grid);
+  const auto* f = static_cast<const cplx<T>*>(P.far);
+  const auto* gi = static_cast<const cplx<T>*>(P.gridI);
+  auto* o = static_cast<cplx<T>*>(out);
+  const dim3 grid((unsigned)((T_ + 255) / 256));
+  if (P.p.ring_interp) {
+    hipError_t e = ensure_ring_scratch(P, T_);
+    if (e != hipSuccess) return e;
+    A.ring_mask = P.ring_mask;
+  }
+  {
+    KernelTimer t(P, QPGF_T_GATHER);   // the gather alone; the ring pass has its own timer
+    if (P.nf == 2)
+      hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, f, x, (long)T_, o, flags);
+    else if (P.nf == 3)
+      hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, f, x, (long)T_, o, flags);
+    else
+      hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, f, x, (long)T_, o, flags);
+  }
+  if (P.p.ring_interp) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    KernelTimer tr(P, QPGF_T_RING);
+    const dim3 nb((unsigned)((T_ + kRingSpan - 1) / kRingSpan));
+    if (P.nf == 3)
+      hipLaunchKernelGGL((k_ring2d<T, 3>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
+    else if (P.nf == 2)
+      hipLaunchKernelGGL((k_ring2d<T, 2>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
+    else
+      hipLaunchKernelGGL((k_ring2d<T, 1>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
+  }
+  return hipGetLastError();
+}
+
+// Tile configuration of a binned 3D call (kept in the plan between the binning and the gather).
+struct TileCfg {
+  TileArgs t;
+  bool big, fields, far_big;
+};
+static_assert(sizeof(TileCfg) <= sizeof(int) * 24, "Plan::bt holds the tile configuration");
+
+template <typename T, int NF>
+hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, void* out, uint8_t* flags,
+                         int mode, hipStream_t bin_stream) {
   const auto* g = static_cast<const cplx<T>*>(P.grid);
   const auto* f = static_cast<const cplx<T>*>(P.far);
   auto* o = static_cast<cplx<T>*>(out);
   const dim3 grid((unsigned)((T_ + 255) / 256));
-  if (smooth) {
+  if (A.smooth || P.bin_min_targets < 0 || T_ < P.bin_min_targets) {
     KernelTimer t(P, QPGF_T_GATHER);
-    hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
-    return hipGetLastError();
-  }
-  if (P.dim == 2) {
-    const auto* gi = static_cast<const cplx<T>*>(P.gridI);
-    const auto* fi = static_cast<const cplx<T>*>(P.farI);
-    if (P.p.ring_interp) {
-      hipError_t e = ensure_ring_scratch(P, T_);
-      if (e != hipSuccess) return e;
-      A.ring_mask = P.ring_mask;
-    }
-    {
-      KernelTimer t(P, QPGF_T_GATHER);   // the gather alone; the ring pass has its own timer
-      if (P.nf == 2)
-        hipLaunchKernelGGL(k_gather2d_grad<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
-      else if (P.nf == 3)
-        hipLaunchKernelGGL(k_gather2d_hess<T>, grid, dim3(256), 0, P.stream, A, gi, fi, x, (long)T_, o, flags);
-      else
-        hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(256), 0, P.stream, A, A.quad ? gi : g, A.quad ? fi : f, x,
-                           (long)T_, o, flags);
-    }
-    if (P.p.ring_interp) {
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      KernelTimer tr(P, QPGF_T_RING);
-      const dim3 nb((unsigned)((T_ + kRingSpan - 1) / kRingSpan));
-      if (P.nf == 3)
-        hipLaunchKernelGGL((k_ring2d<T, 3>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
-      else if (P.nf == 2)
-        hipLaunchKernelGGL((k_ring2d<T, 2>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
-      else
-        hipLaunchKernelGGL((k_ring2d<T, 1>), nb, dim3(256), 0, P.stream, A, x, (long)T_, o);
-    }
-    return hipGetLastError();
-  }
-  if (P.bin_min_targets < 0 || T_ < P.bin_min_targets) {
-    KernelTimer t(P, QPGF_T_GATHER);
-    if (P.nf == kMxF)
-      hipLaunchKernelGGL((k_gather3d<T, kMxF>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
-    else
-      hipLaunchKernelGGL((k_gather3d<T, 1>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
+    hipLaunchKernelGGL((k_gather3d<T, NF>), grid, dim3(256), 0, P.stream, A, g, f, x, (long)T_, o, flags);
     return hipGetLastError();
   }
   BinArgs B;
@@ -1591,176 +1630,182 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
   B.ih1 = A.ih1;
   B.ih2 = A.ih2;
   B.ih3 = A.ih3;
-  B.hf = A.hf;
+  B.fz0 = A.fz0;
   B.ihf = A.ihf;
+  B.ihf1 = A.ihf1;
+  B.ihf2 = A.ihf2;
   B.M1 = P.M1;
   B.M2 = P.M2;
   B.M3 = P.M3;
   B.S = P.S;
-  // Tile edges.  One field: 16 x 16 x 8 nodes (several 256-thread blocks per
-  // CU, so one block's staging overlaps the others' interpolation), or, when
-  // that leaves fewer than kMinPerTile targets per tile on average (fine grids),
-  // 32 x 32 x 8 (complex64, 108 KiB, 1024 threads) or 32 x 16 x 8 (complex128,
-  // 117 KiB, 512 threads) so the staging is spread over more targets.  Seven
-  // Maxwell fields: 8 x 8 x 4 (complex64) or 8 x 4 x 4 (complex128) so the
-  // staged footprint fits in 64 KiB.  Must match the instantiations of
-  // k_gather3d_tiled below.
-  TileArgs& Tl = B.t;
-  auto set_tiles = [&](int a, int b, int c) {
+  B.Mf1 = P.Mf1;
+  B.Mf2 = P.Mf2;
+  // Near tiles.  One field: 16 x 16 x 8 nodes (several 256-thread blocks per CU, so one
+  // block's staging overlaps the others' interpolation), or, when that leaves fewer than
+  // kMinPerTile targets per tile on average (fine grids), 32 x 32 x 8 (complex64, 108 KiB,
+  // 1024 threads) or 32 x 16 x 8 (complex128, 117 KiB, 512 threads).  Maxwell: 8 x 8 x 4
+  // (complex64) or 8 x 4 x 4 (complex128) with every field staged (47 / 60 KiB for seven
+  // fields), or 16 x 16 x 8 staged field by field when the tiles hold few targets.
+  // Far tiles (8-point footprints, one field staged at a time): 8 x 8 x 8 nodes on far slabs of
+  // up to 256 x 256 modes, else 16 x 16 x 8 (complex64, 62 KiB) or 16 x 8 x 8 (complex128, 81 KiB).
+  // Must match the instantiations below.
+  TileCfg C{};
+  TileArgs& Tl = C.t;
+  auto set_near = [&](int a, int b, int c) {
     Tl.tb1 = a;
     Tl.tb2 = b;
     Tl.tb3 = c;
-    Tl.nt1 = std::max(1, P.M1 >> Tl.tb1);
-    Tl.nt2 = std::max(1, P.M2 >> Tl.tb2);
-    Tl.nt3n = std::max(1, P.M3 >> Tl.tb3);
+    Tl.nt1 = std::max(1, P.M1 >> a);
+    Tl.nt2 = std::max(1, P.M2 >> b);
+    Tl.nt3n = std::max(1, P.M3 >> c);
     Tl.nnear = Tl.nt1 * Tl.nt2 * Tl.nt3n;
-    Tl.nkeys = Tl.nnear + Tl.nt1 * Tl.nt2 * ((P.S >> Tl.tb3) + 1) + 1;
   };
-  bool big = false, fields = false;
   hipError_t e = hipSuccess;
   if (mode == kGatherBinned) {
     // the configuration launch_bin3d used for these targets
     if (P.bt_T != T_ || P.bt_x != x) return hipErrorInvalidValue;
-    Tl.tb1 = P.bt[0];
-    Tl.tb2 = P.bt[1];
-    Tl.tb3 = P.bt[2];
-    Tl.nt1 = P.bt[3];
-    Tl.nt2 = P.bt[4];
-    Tl.nt3n = P.bt[5];
-    Tl.nnear = P.bt[6];
-    Tl.nkeys = P.bt[7];
-    big = P.bt_big;
-    fields = P.bt_fields;
+    std::memcpy(&C, P.bt, sizeof C);
   } else {
-    if (P.nf == kMxF) {
-      // few targets per tile: 16 x 16 x 8 tiles staged one field at a time
-      set_tiles(4, 4, 3);
-      fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nkeys;
-      if (!fields) set_tiles(3, sizeof(T) == 8 ? 2 : 3, 2);
+    if (NF > 1) {
+      set_near(4, 4, 3);
+      C.fields = T_ < (int64_t)kMaxPerFieldTile * Tl.nnear;
+      if (!C.fields) set_near(3, sizeof(T) == 8 ? 2 : 3, 2);
     } else {
-      set_tiles(4, 4, 3);
-      if (T_ < (int64_t)kMinPerTile * Tl.nkeys) {
-        big = true;
-        set_tiles(5, sizeof(T) == 8 ? 4 : 5, 3);
+      set_near(4, 4, 3);
+      if (T_ < (int64_t)kMinPerTile * Tl.nnear) {
+        C.big = true;
+        set_near(5, sizeof(T) == 8 ? 4 : 5, 3);
       }
     }
+    C.far_big = P.Mf1 > 256 || P.Mf2 > 256;
+    Tl.ftb1 = C.far_big ? 4 : 3;
+    Tl.ftb2 = C.far_big && sizeof(T) == 4 ? 4 : 3;
+    Tl.ftb3 = 3;
+    Tl.fnt1 = std::max(1, P.Mf1 >> Tl.ftb1);
+    Tl.fnt2 = std::max(1, P.Mf2 >> Tl.ftb2);
+    Tl.fnt3 = ((P.S - 5) >> Tl.ftb3) + 1;
+    Tl.nfar = Tl.fnt1 * Tl.fnt2 * Tl.fnt3;
+    Tl.nkeys = Tl.nnear + Tl.nfar + 1;
     e = ensure_bin_scratch(P, T_, Tl.nkeys);
     if (e != hipSuccess) return e;
-    const int bt[8] = {Tl.tb1, Tl.tb2, Tl.tb3, Tl.nt1, Tl.nt2, Tl.nt3n, Tl.nnear, Tl.nkeys};
-    for (int q = 0; q < 8; ++q) P.bt[q] = bt[q];
-    P.bt_big = big;
-    P.bt_fields = fields;
+    std::memcpy(P.bt, &C, sizeof C);
     P.bt_T = T_;
     P.bt_x = x;
   }
+  B.t = Tl;
   TRec* rec = reinterpret_cast<TRec*>(P.bin_rec);
   const bool lds_bins = Tl.nkeys <= kBinLdsKeys;
   const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
   const hipStream_t bs = bin_stream ? bin_stream : P.stream;
   if (mode != kGatherBinned) {
-  {
-    KernelTimer t(P, QPGF_T_BIN, bs);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.bin_novf, 1L);
-    if (lds_bins) {
-      // LDS histogram sized to the key count (small ones leave LDS to kernels running beside)
-      if (Tl.nkeys <= 4096)
-        hipLaunchKernelGGL(k_bin_count<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt);
-      else if (Tl.nkeys <= 16384)
-        hipLaunchKernelGGL(k_bin_count<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt);
-      else
-        hipLaunchKernelGGL(k_bin_count<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.bin_cnt);
-      hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.bin_cnt,
-                         Tl.nkeys,
-                         kBinBlocks, P.bin_hist);
-    } else {
-      // large key spaces: one global atomic rank per target
-      hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, bs, P.bin_hist,
-                         (long)Tl.nkeys);
-      hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, bs, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
+    {
+      KernelTimer t(P, QPGF_T_BIN, bs);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.bin_novf, 1L);
+      if (lds_bins) {
+        // LDS histogram sized to the key count (small ones leave LDS to kernels running beside)
+        if (Tl.nkeys <= 4096)
+          hipLaunchKernelGGL(k_bin_count<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                             P.bin_cnt);
+        else if (Tl.nkeys <= 16384)
+          hipLaunchKernelGGL(k_bin_count<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                             P.bin_cnt);
+        else
+          hipLaunchKernelGGL(k_bin_count<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                             P.bin_cnt);
+        hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.bin_cnt,
+                           Tl.nkeys, kBinBlocks, P.bin_hist);
+      } else {
+        // large key spaces: one global atomic rank per target
+        hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, bs, P.bin_hist,
+                           (long)Tl.nkeys);
+        hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, bs, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
+      }
+      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, bs, P.bin_hist, P.bin_offs, Tl.nkeys);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, bs, P.bin_hist, P.bin_offs, Tl.nkeys);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  {
-    KernelTimer t(P, QPGF_T_BIN_PLACE, bs);
-    if (lds_bins && Tl.nkeys <= 4096)
-      hipLaunchKernelGGL(k_bin_place<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt,
-                         P.bin_offs, rec);
-    else if (lds_bins && Tl.nkeys <= 16384)
-      hipLaunchKernelGGL(k_bin_place<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.bin_cnt,
-                         P.bin_offs, rec);
-    else if (lds_bins)
-      hipLaunchKernelGGL(k_bin_place<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                         P.bin_cnt, P.bin_offs, rec);
-    else
-      hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+    {
+      KernelTimer t(P, QPGF_T_BIN_PLACE, bs);
+      if (lds_bins && Tl.nkeys <= 4096)
+        hipLaunchKernelGGL(k_bin_place<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                           P.bin_cnt, P.bin_offs, rec);
+      else if (lds_bins && Tl.nkeys <= 16384)
+        hipLaunchKernelGGL(k_bin_place<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                           P.bin_cnt, P.bin_offs, rec);
+      else if (lds_bins)
+        hipLaunchKernelGGL(k_bin_place<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
+                           P.bin_cnt, P.bin_offs, rec);
+      else
+        hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if (mode == kBinOnly) return hipSuccess;
   {
-  KernelTimer t(P, QPGF_T_GATHER);
-  const dim3 tg(Tl.nkeys);
-#define QPGF_TILED(NF_, A1_, A2_, A3_, BS_)                                                                      \
-  hipLaunchKernelGGL((k_gather3d_tiled<T, NF_, A1_, A2_, A3_, BS_>), tg, dim3(BS_), 0, P.stream, A, Tl, g, f, rec, \
+    KernelTimer t(P, QPGF_T_GATHER);
+    const dim3 tn(Tl.nnear), tf(Tl.nfar + 1);
+#define QPGF_NEAR(A1_, A2_, A3_, BS_)                                                                             \
+  hipLaunchKernelGGL((k_gather3d_near<T, NF, A1_, A2_, A3_, BS_>), tn, dim3(BS_), 0, P.stream, A, Tl, g, rec,     \
                      P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
-  if (fields) {
-    hipLaunchKernelGGL((k_gather3d_fields<T, 4, 4, 3>), tg, dim3(256), 0, P.stream, A, Tl, g, f, rec, P.bin_hist,
-                       P.bin_offs, o, flags, P.bin_ovf, P.bin_novf);
-  } else if constexpr (sizeof(T) == 8) {
-    if (P.nf == kMxF) QPGF_TILED(kMxF, 3, 2, 2, 256);
-    else if (big) QPGF_TILED(1, 5, 4, 3, 512);
-    else QPGF_TILED(1, 4, 4, 3, 256);
-  } else {
-    if (P.nf == kMxF) QPGF_TILED(kMxF, 3, 3, 2, 256);
-    else if (big) QPGF_TILED(1, 5, 5, 3, 1024);
-    else QPGF_TILED(1, 4, 4, 3, 256);
-  }
-#undef QPGF_TILED
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+#define QPGF_FAR(A1_, A2_, A3_)                                                                                    \
+  hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
+                     P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
+    // far tiles first (more targets and work each), then the near tiles
+    if (!C.far_big) QPGF_FAR(3, 3, 3);
+    else if constexpr (sizeof(T) == 8) QPGF_FAR(4, 3, 3);
+    else QPGF_FAR(4, 4, 3);
+    if constexpr (NF > 1) {
+      if (C.fields)
+        hipLaunchKernelGGL((k_gather3d_near_fields<T, NF, 4, 4, 3>), tn, dim3(256), 0, P.stream, A, Tl, g, rec,
+                           P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf);
+      else if constexpr (sizeof(T) == 8) QPGF_NEAR(3, 2, 2, 256);
+      else QPGF_NEAR(3, 3, 2, 256);
+    } else if (C.big) {
+      if constexpr (sizeof(T) == 8) QPGF_NEAR(5, 4, 3, 512);
+      else QPGF_NEAR(5, 5, 3, 1024);
+    } else {
+      QPGF_NEAR(4, 4, 3, 256);
+    }
+#undef QPGF_NEAR
+#undef QPGF_FAR
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   KernelTimer t(P, QPGF_T_OVERFLOW);
-  if (P.nf == kMxF)
-    hipLaunchKernelGGL((k_gather3d_overflow<T, kMxF>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
-                       P.bin_novf, o, flags);
-  else
-    hipLaunchKernelGGL((k_gather3d_overflow<T, 1>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
-                       P.bin_novf, o, flags);
+  hipLaunchKernelGGL((k_gather3d_overflow<T, NF>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
+                     P.bin_novf, o, flags);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t* flags, int smooth = 0,
+                       int mode = kGatherAll, hipStream_t bin_stream = nullptr) {
+  GArgs A = make_gargs<T>(P, smooth);
+  if (P.dim == 2) return gather2d_impl<T>(P, A, x, T_, out, flags);
+  if (P.nf == kMxF) return gather3d_impl<T, kMxF>(P, A, x, T_, out, flags, mode, bin_stream);
+  if (P.nf == kMxT) return gather3d_impl<T, kMxT>(P, A, x, T_, out, flags, mode, bin_stream);
+  return gather3d_impl<T, 1>(P, A, x, T_, out, flags, mode, bin_stream);
 }
 
 }  // namespace
 
 hipError_t launch_interleave2d(Plan& P) {
-  if (P.dim != 2 || !P.gridI || !P.farI) return hipErrorInvalidValue;
+  if (P.dim != 2 || !P.gridI) return hipErrorInvalidValue;
   if (P.nf == 1) {
-    // complex64 G: node quads of the near grid and of the far slab
+    // complex64 G: node quads of the near grid
     if (P.esize != 8) return hipErrorInvalidValue;
-    auto quads = [&](const void* in, void* out, long n) {
-      hipLaunchKernelGGL(k_quads, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, P.stream,
-                         static_cast<const float2*>(in), static_cast<float2*>(out), n, P.M1);
-    };
-    quads(P.grid, P.gridI, (long)P.ncell);
-    quads(P.far, P.farI, (long)P.nfar);
+    hipLaunchKernelGGL(k_quads, dim3((unsigned)((4 * P.ncell + 255) / 256)), dim3(256), 0, P.stream,
+                       static_cast<const float2*>(P.grid), static_cast<float2*>(P.gridI), (long)P.ncell, P.M1);
     return hipGetLastError();
   }
-  auto go = [&](auto tag, const void* in, void* out, long n) {
-    using T = decltype(tag);
-    const long tot = n * P.nf;
-    hipLaunchKernelGGL(k_interleave<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
-                       static_cast<const cplx<T>*>(in), static_cast<cplx<T>*>(out), n, P.nf);
-  };
-  if (P.esize == 16) {
-    go(double(), P.grid, P.gridI, (long)P.ncell);
-    go(double(), P.far, P.farI, (long)P.nfar);
-  } else {
-    go(float(), P.grid, P.gridI, (long)P.ncell);
-    go(float(), P.far, P.farI, (long)P.nfar);
-  }
+  const long tot = (long)P.ncell * P.nf;
+  if (P.esize == 16)
+    hipLaunchKernelGGL(k_interleave<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
+                       static_cast<const double2*>(P.grid), static_cast<double2*>(P.gridI), (long)P.ncell, P.nf);
+  else
+    hipLaunchKernelGGL(k_interleave<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
+                       static_cast<const float2*>(P.grid), static_cast<float2*>(P.gridI), (long)P.ncell, P.nf);
   return hipGetLastError();
 }
 
@@ -1809,33 +1854,26 @@ hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
   return hipSuccess;
 }
 
-void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long t0, long t1, long blk0,
-                    void* dst) {
+void gather_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, long off, long foff, long t0,
+                    long t1, long blk0, void* dst) {
   GatherInst I;
   GArgs& A = I.A;
+  A = make_gargs<double>(P, 0);
   A.k = k;
+  A.k2 = 0.0;
   A.a1 = a;
   A.a2 = 0.0;
-  A.c = P.p.c;
-  A.c_tilde = P.p.c_tilde;
-  A.eps = P.p.eps;
-  A.rmin = P.p.lattice_rmin;
   A.M1 = M1;
-  A.M2 = P.M2;
-  A.M3 = 1;
   A.h1 = kPi / (M1 / 2);
-  A.h2 = P.p.c_tilde / (P.M2 / 2);
-  A.h3 = 0.0;
   A.ih1 = 1.0 / A.h1;
-  A.ih2 = 1.0 / A.h2;
-  A.ih3 = 0.0;
-  A.hf = P.p.far_h;
-  A.ihf = 1.0 / A.hf;
-  A.S = P.S;
+  A.Mf1 = fg.Mf1;
+  A.ihf1 = fg.Mf1 / (2.0 * kPi);
+  A.S = fg.S;
+  A.hf = fg.hf;
+  A.ihf = 1.0 / fg.hf;
+  A.fz0 = P.p.c - kFarLo * fg.hf;
   A.fs = (long)M1 * P.M2;
-  A.ffs = (long)M1 * P.S;
-  A.smooth = 0;
-  A.sing_order = P.p.sing_order;
+  A.ffs = (long)fg.Mf1 * fg.S;
   A.quad = 0;   // the batched graph keeps the instances' grids row by row (node quads of all
                 // instances cost more than they save: four times the grids no longer stay in L2)
   A.ring_mask = nullptr;

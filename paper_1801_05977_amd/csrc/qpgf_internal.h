@@ -16,9 +16,17 @@ namespace qpgf {
 // ---------------------------------------------------------------------------
 // complex helpers (FP64 work is done in double2; bulk storage in T2)
 // ---------------------------------------------------------------------------
-// Maxwell fields: L_d and its second-derivative fields 11, 22, 12, 13, 23 (the 33 entry of the
-// tensor follows from the trace, tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice).
-constexpr int kMxF = 6;
+// Maxwell near fields: L_d and the second-derivative fields of Algorithm 4.1, pq = 11 22 33 12 13 23
+// (kMxF); with params.maxwell_trace the 33 field is dropped and GG_33 follows from the trace
+// tr GG = 3 G_d + k^-2 Laplacian G_d = 2 G_d off the lattice (kMxT).  The far slab of the Maxwell
+// kind holds the six tensor entries of the series directly (kMxO).
+constexpr int kMxF = 7;
+constexpr int kMxT = 6;
+constexpr int kMxO = 6;
+// Far branch: the far slab is interpolated with the 8-point Lagrange rule per axis, nodes
+// base - 3 .. base + 4; its first slice lies kFarLo spacings below c.
+constexpr int kFarP = 8;
+constexpr int kFarLo = 3;
 
 template <typename T> struct C2;
 template <> struct C2<double> { using type = double2; };
@@ -108,10 +116,14 @@ constexpr int kMaxLog2 = 12;   // m <= 4096
 
 struct Plan {
   qpgf_params p;
-  int dim = 2, nf = 1;         // nf: number of fields (kMxF for Maxwell)
+  int dim = 2, nf = 1;         // nf: number of near fields (kMxF or kMxT for Maxwell)
   int M1 = 0, M2 = 0, M3 = 1;  // 2D: M3 = 1, M2 = transverse
   int Mt = 0;                  // transverse size (M2 in 2D, M3 in 3D)
   int S = 0;                   // far-slab slices
+  int Mf1 = 0, Mf2 = 1;        // far-slab modes per periodic axis (Mf2 = 1 in 2D)
+  int nfo = 1;                 // far-slab fields (kMxO for Maxwell, else nf)
+  double hf = 0.0, fz0 = 0.0;  // far-slab slice spacing and first slice c - kFarLo hf
+  size_t far_cap = 0;          // bytes allocated for the far slab (grown when an instance needs more)
   size_t ncell = 0;            // points per near field
   size_t nfar = 0;             // points per far field
   size_t esize = 16;           // bytes per complex element
@@ -134,7 +146,7 @@ struct Plan {
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
   void* gridI = nullptr;       // 2D derivative kinds: the near fields interleaved, [i2][i1][field];
-  void* farI = nullptr;        // complex64 G: node quads [i2][i1][a] = grid[i2][i1 + a]; far slab alike
+                               // complex64 G: node quads [i2][i1][a] = grid[i2][i1 + a]
   double* E2 = nullptr;        // 2D G with sing_order >= 2: [4][j2'][j1'] real tables of the removed
                                // degree-2 and degree-3 terms (e_tt, e_rr, e_ttt, e_trr)
   double* D2 = nullptr;        // 2D derivative tables: gradient [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2),
@@ -161,8 +173,7 @@ struct Plan {
   uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
   uint32_t* bin_novf = nullptr;        // their count
   // tile configuration of the last binning (launch_bin3d), used by launch_gather_binned
-  int bt[8] = {};                      // tb1, tb2, tb3, nt1, nt2, nt3n, nnear, nkeys
-  bool bt_big = false, bt_fields = false;
+  int bt[24] = {};                     // the tile configuration (near and far tiles, key counts)
   int64_t bt_T = -1;
   const double* bt_x = nullptr;
   // second stream for the binning while the grids are prepared, and its events
@@ -214,6 +225,14 @@ struct KernelTimer {
   }
 };
 
+// Far-slab geometry for an instance whose largest wavenumber is kmax and whose x1 (2D) or x1, x2
+// (3D) near sizes are M1 (and P.M2): modes per periodic axis and slice spacing (api.hip).
+struct FarGeom {
+  int Mf1, Mf2, S;
+  double hf;
+};
+FarGeom far_geometry(const Plan& P, double kmax, int M1);
+
 // kernel launchers (fill.hip, fft.hip, gather.hip)
 hipError_t launch_interleave2d(Plan& P);
 hipError_t launch_sing2d_ho(Plan& P, int Qg, const double* rg, const double* wyg);
@@ -228,12 +247,13 @@ hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch,
                       long s_out);
 int fft_tile(const Plan& P, int n, bool rows, long nbatch);
 // batched 2D (one launch per stage for many instances)
-void fill_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long blk0, void* dst);
+void fill_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, long off, long foff, long blk0,
+                  void* dst);
 size_t fill_inst_size();
 hipError_t launch_fill2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base, bool spec);
 hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, void* base);
-void gather_inst_2d(const Plan& P, double k, double a, int M1, long off, long foff, long t0, long t1, long blk0,
-                    void* dst);
+void gather_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, long off, long foff, long t0,
+                    long t1, long blk0, void* dst);
 size_t gather_inst_size();
 hipError_t launch_gather2d_multi(Plan& P, const void* dinst, int n_inst, long nblocks, const void* grid,
                                  const void* far, const double* x, void* out, uint8_t* flags);

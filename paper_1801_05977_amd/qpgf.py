@@ -32,14 +32,15 @@ class Params(ctypes.Structure):
                 ("eps", ctypes.c_double), ("quad_q", ctypes.c_int), ("far_h", ctypes.c_double),
                 ("far_zmax", ctypes.c_double), ("wood_tol", ctypes.c_double), ("special_tol", ctypes.c_double),
                 ("lattice_rmin", ctypes.c_double), ("sing_order", ctypes.c_int),
-                ("ring_interp", ctypes.c_int)]
+                ("ring_interp", ctypes.c_int), ("far_m", ctypes.c_int), ("maxwell_trace", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("prec", ctypes.c_int), ("m1", ctypes.c_int), ("m2", ctypes.c_int),
                 ("m3", ctypes.c_int), ("far_slices", ctypes.c_int), ("far_h", ctypes.c_double),
                 ("c", ctypes.c_double), ("c_tilde", ctypes.c_double), ("eps", ctypes.c_double),
-                ("n_fields", ctypes.c_int), ("grid_bytes", ctypes.c_size_t), ("far_grid_bytes", ctypes.c_size_t)]
+                ("n_fields", ctypes.c_int), ("grid_bytes", ctypes.c_size_t), ("far_grid_bytes", ctypes.c_size_t),
+                ("far_m1", ctypes.c_int), ("far_m2", ctypes.c_int), ("far_fields", ctypes.c_int)]
 
 
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
@@ -151,12 +152,16 @@ class Plan:
         self._h = ctypes.c_void_p()
         torch.cuda.init()
         _check(lib().qpgf_plan_create(ctypes.byref(self.params), ctypes.byref(self._h)))
-        info = PlanInfo()
-        _check(lib().qpgf_plan_get_info(self._h, ctypes.byref(info)))
-        self.info = info
         self.kind, self.prec = kind, prec
         self.dim = 2 if kind in (KIND_G2D, KIND_G2D_GRAD, KIND_G2D_HESS_DIFF) else 3
         self.cdtype = torch.complex128 if prec == C128 else torch.complex64
+
+    @property
+    def info(self):
+        """qpgf_plan_get_info now (the far slab's geometry follows the last prepared instance)."""
+        info = PlanInfo()
+        _check(lib().qpgf_plan_get_info(self._h, ctypes.byref(info)))
+        return info
 
     def close(self):
         if self._h:

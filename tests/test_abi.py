@@ -34,14 +34,18 @@ def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qpgf.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(qpgf_params), offsetof(qpgf_params, lattice_rmin),"
-        " sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes), offsetof(qpgf_params, quad_q),"
-        " offsetof(qpgf_params, sing_order));return 0;}\n")
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qpgf_params),"
+        " offsetof(qpgf_params, lattice_rmin), sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes),"
+        " offsetof(qpgf_params, quad_q), offsetof(qpgf_params, sing_order), offsetof(qpgf_params, far_m),"
+        " offsetof(qpgf_params, maxwell_trace), offsetof(qpgf_plan_info, far_m1),"
+        " offsetof(qpgf_plan_info, far_fields));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(qpgf.Params), qpgf.Params.lattice_rmin.offset, ctypes.sizeof(qpgf.PlanInfo),
-            qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset, qpgf.Params.sing_order.offset]
+            qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset, qpgf.Params.sing_order.offset,
+            qpgf.Params.far_m.offset, qpgf.Params.maxwell_trace.offset, qpgf.PlanInfo.far_m1.offset,
+            qpgf.PlanInfo.far_fields.offset]
     assert got == want
 
 
@@ -49,17 +53,20 @@ def test_params_default_values():
     p = qpgf.default_params(qpgf.KIND_GD3D, qpgf.C64, 256, 256, 64)
     assert (p.kind, p.prec, p.m1, p.m2, p.m3) == (1, 1, 256, 256, 64)
     assert (p.c, p.c_tilde, p.eps, p.quad_q) == (0.6, 1.0, 0.2, 64)
-    assert p.far_h == pytest.approx(1.0 / 32)
+    assert p.far_h == 0.0                                # automatic, per instance
     assert p.far_zmax == 1.0 and p.wood_tol == 1e-3
     assert p.sing_order == 1 and p.ring_interp == 0
+    assert p.far_m == 0 and p.maxwell_trace == 0
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("m1", 100, 4), ("m2", 8, 4), ("m3", 3, 4), ("c", 1.5, 1), ("eps", 0.6, 1), ("quad_q", 4, 1),
-    ("far_h", 0.0, 1), ("kind", 9, 1), ("prec", 5, 1), ("sing_order", 0, 1), ("sing_order", 4, 1),
+    ("far_h", -1.0, 1), ("far_h", 1e-7, 1), ("kind", 9, 1), ("prec", 5, 1), ("sing_order", 0, 1), ("sing_order", 4, 1),
     ("sing_order", 2, 1),     # above 1 only for the 2D G (this plan is 3D)
     ("ring_interp", 2, 1), ("ring_interp", 1, 1),
     ("special_tol", 0.79, 1),  # at most two special coefficients per pencil needs special_tol < pi / (4 c~)
+    ("far_m", 100, 4), ("far_m", 8, 4), ("far_m", 4096, 4),   # complex128 3D: the far x2 axis is a column axis
+    ("maxwell_trace", 1, 1), ("maxwell_trace", 2, 1),        # the trace variant is a Maxwell option
 ])
 def test_plan_create_rejects_bad_params(field, value, status):
     L = qpgf.lib()

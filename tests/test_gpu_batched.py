@@ -53,7 +53,7 @@ def test_batched_equals_single_instance_plans(prec, tmp_path):
             Pi.close()
         for i in (0, 3):
             sl = slice(int(t_off[i]), int(t_off[i + 1]))
-            o = method.eval_g2d(k[i], a[i], x[sl], m1[i] // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+            o = method.eval_g2d(k[i], a[i], x[sl], m1[i] // 2, M2 // 2)
             assert parity(g[sl], o) <= TOL[prec], (rep, i)
     # the autotuner changes only how transforms are grouped into blocks, not results
     P.autotune(str(tmp_path / "tune.txt"))

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import slabcheck
 from oracle import grad2d, method, truth
 from paper_1801_05977_amd import qpgf, workloads
 
@@ -49,14 +50,15 @@ def test_grad2d_stages(prec):
         assert np.abs(g - ref_L[f]).max() <= tol * np.abs(ref_L[f]).max(), f
     P.prepare(K, AL, 0.0, stage=2)
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
-    S = P.info.far_slices
-    ref_F = grad2d.far_grids_grad_2d(K, AL, M1 // 2, method.far_slices(P.info.far_h, S))
     for f in range(2):
         g = cen(P.field(0, f).cpu().numpy().reshape(M2, M1).T, (0, 1))
         ref_G = method.grid_2d(ref_L[f] / A2)
         assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max(), f
-        far = P.field(1, f).cpu().numpy().reshape(S, M1)
-        assert np.abs(cen(far, (1,)) - ref_F[f]).max() <= tol * np.abs(ref_F[f]).max(), f
+    # far slab: at its nodes the differentiated series (1.2) (x2 > 0)
+    (si, pi), pts = slabcheck.nodes_2d(P.info, 60, seed=3)
+    ref_F = truth.g2d_grad(K, AL, pts) * np.exp(-1j * AL * pts[:, 0])[:, None]
+    for f in range(2):
+        assert slabcheck.rel(slabcheck.slab_2d(P, f)[si, pi], ref_F[:, f]) <= tol, f
 
 
 def _edge_targets(rng):
@@ -82,7 +84,7 @@ def test_grad2d_end_to_end(prec, shape, T):
     fin = np.all(np.isfinite(x), axis=1)
     o = np.full((len(x), 2), np.nan + 0j)
     with np.errstate(all="ignore"):
-        o[fin] = grad2d.eval_g2d_grad(K, AL, x[fin], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+        o[fin] = grad2d.eval_g2d_grad(K, AL, x[fin], M1 // 2, M2 // 2)
     f = flags.cpu().numpy()
     z = np.abs(x[:, 1])
     t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
@@ -91,7 +93,7 @@ def test_grad2d_end_to_end(prec, shape, T):
     np.testing.assert_array_equal((f & 2) != 0, fin & (z > 0.6))
     np.testing.assert_array_equal((f & 1) != 0, on_lattice)
     beyond = (f & 4) != 0
-    assert np.all(beyond == (fin & np.isnan(o[:, 0]) & ~on_lattice))
+    assert np.all(beyond == (fin & (z >= slabcheck.limit(P.info))))
     bad = (f & 13) != 0
     assert np.all(np.isnan(g[bad]))
     ok = ~bad

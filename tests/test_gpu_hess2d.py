@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+import slabcheck
 from oracle import hess2d, method, truth
 from paper_1801_05977_amd import qpgf, workloads
 
@@ -48,14 +49,15 @@ def test_hess2d_stages(prec):
         assert np.abs(g - ref_L[f]).max() <= tol * np.abs(ref_L[f]).max(), f
     P.prepare_hess_diff(K1, K2, AL, stage=2)
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
-    S = P.info.far_slices
-    ref_F = hess2d.far_grids_hess_diff(K1, K2, AL, M1 // 2, method.far_slices(P.info.far_h, S))
     for f in range(3):
         g = cen(P.field(0, f).cpu().numpy().reshape(M2, M1).T, (0, 1))
         ref_G = method.grid_2d(ref_L[f] / A2)
         assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max(), f
-        far = P.field(1, f).cpu().numpy().reshape(S, M1)
-        assert np.abs(cen(far, (1,)) - ref_F[f]).max() <= tol * np.abs(ref_F[f]).max(), f
+    # far slab: at its nodes the twice-differentiated series (1.2), k1 minus k2 (x2 > 0)
+    (si, pi), pts = slabcheck.nodes_2d(P.info, 60, seed=4)
+    ref_F = (truth.g2d_hess(K1, AL, pts) - truth.g2d_hess(K2, AL, pts)) * np.exp(-1j * AL * pts[:, 0])[:, None]
+    for f in range(3):
+        assert slabcheck.rel(slabcheck.slab_2d(P, f)[si, pi], ref_F[:, f]) <= tol, f
 
 
 def _edge_targets():
@@ -78,14 +80,14 @@ def test_hess2d_end_to_end(prec, shape, T):
     fin = np.all(np.isfinite(x), axis=1)
     o = np.full((len(x), 3), np.nan + 0j)
     with np.errstate(all="ignore"):
-        o[fin] = hess2d.eval_g2d_hess_diff(K1, K2, AL, x[fin], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+        o[fin] = hess2d.eval_g2d_hess_diff(K1, K2, AL, x[fin], M1 // 2, M2 // 2)
     f = flags.cpu().numpy()
     t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
     on_lattice = fin & (np.hypot(t, x[:, 1]) == 0)
     np.testing.assert_array_equal((f & 8) != 0, ~fin)
     np.testing.assert_array_equal((f & 2) != 0, fin & (np.abs(x[:, 1]) > 0.6))
     np.testing.assert_array_equal((f & 1) != 0, on_lattice)
-    assert np.all(((f & 4) != 0) == (fin & np.isnan(o[:, 0]) & ~on_lattice))
+    assert np.all(((f & 4) != 0) == (fin & (np.abs(x[:, 1]) >= slabcheck.limit(P.info))))
     bad = (f & 13) != 0
     assert np.all(np.isnan(g[bad]))
     ok = ~bad

@@ -14,7 +14,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import method
+import slabcheck
+from oracle import method, truth
 from paper_1801_05977_amd import qpgf, workloads
 
 pytestmark = pytest.mark.gpu
@@ -56,10 +57,11 @@ def test_fill2d_and_grid2d_stages(prec):
     ref_G = method.grid_2d(ref_L / A2)
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
-    far = P.field(which=1).cpu().numpy().reshape(P.info.far_slices, M1)
-    z = method.far_slices(P.info.far_h, P.info.far_slices)
-    ref_F = method.far_grid_2d(k, al, M1 // 2, z)
-    assert np.abs(cen(far, (1,)) - ref_F).max() <= tol * np.abs(ref_F).max()
+    # far slab: at its nodes the series (1.2) itself, on its own grid of far_m1 >= 256 modes
+    assert P.info.far_m1 == 256 and P.info.far_fields == 1
+    (si, pi), pts = slabcheck.nodes_2d(P.info, 60, seed=1)
+    ref_F = truth.g2d(k, al, pts) * np.exp(-1j * al * pts[:, 0])
+    assert slabcheck.rel(slabcheck.slab_2d(P)[si, pi], ref_F) <= tol
 
 
 # ----------------------------------------------------------------------------- 3D stages
@@ -79,10 +81,11 @@ def test_fill3d_and_grid3d_stages(prec):
     ref_G = method.grid_3d(ref_L / A3)
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
-    S = P.info.far_slices
-    far = P.field(which=1).cpu().numpy().reshape(S, M2, M1).transpose(0, 2, 1)
-    ref_F = method.far_grid_3d(k, a1, a2, M1 // 2, M2 // 2, method.far_slices(P.info.far_h, S))
-    assert np.abs(cen(far, (1, 2)) - ref_F).max() <= tol * np.abs(ref_F).max()
+    # far slab: at its nodes the series (1.3) itself
+    assert (P.info.far_m1, P.info.far_m2, P.info.far_fields) == (256, 256, 1)
+    idx, pts = slabcheck.nodes_3d(P.info, 30, seed=2)
+    ref_F = truth.gd3d(k, a1, a2, pts) * np.exp(-1j * (a1 * pts[:, 0] + a2 * pts[:, 1]))
+    assert slabcheck.rel(slabcheck.slab_3d(P)[idx], ref_F) <= tol
 
 
 # ----------------------------------------------------------------------------- end to end
@@ -96,7 +99,7 @@ def test_g2d_small_workload(prec):
     P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
     flags = torch.empty(T, dtype=torch.uint8, device="cuda")
     g = P(k, al, 0.0, dev(x), flags=flags).cpu().numpy()
-    o = method.eval_g2d(k, al, x, M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_g2d(k, al, x, M1 // 2, M2 // 2)
     assert parity(g, o) <= TOL[prec]
     f = flags.cpu().numpy()
     np.testing.assert_array_equal((f & 2) != 0, np.abs(x[:, 1]) > 0.6)
@@ -115,7 +118,7 @@ def test_g2d_large_grid_row_major_path():
     wrap = np.nonzero(t > math.pi - 2 * (2 * math.pi / M1))[0]
     rng = np.random.default_rng(3)
     pick = np.concatenate([wrap[:50], rng.choice(len(x), 250, replace=False)])
-    o = method.eval_g2d(k, al, x[pick], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_g2d(k, al, x[pick], M1 // 2, M2 // 2)
     assert len(wrap) >= 50
     assert parity(g[pick], o) <= TOL[qpgf.C64]
 
@@ -129,7 +132,7 @@ def test_gd3d_small(prec, shape):
     x = workloads.targets(T, 3, seed=2)
     P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
     g = P(k, a1, a2, dev(x)).cpu().numpy()
-    o = method.eval_gd3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_gd3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2)
     assert parity(g, o) <= TOL[prec]
 
 
@@ -141,20 +144,68 @@ def test_maxwell3d_small(prec):
     x = workloads.targets(T, 3, seed=3)
     P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3)
     g = P(k, a1, a2, dev(x)).cpu().numpy()
-    o = method.eval_maxwell3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_maxwell3d(k, a1, a2, x, M1 // 2, M2 // 2, M3 // 2)
     for comp in range(6):      # error per component, each with its own scale
         assert parity(g[:, comp], o[:, comp]) <= TOL[prec], comp
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+def test_maxwell_stages(prec):
+    """Algorithm 4.1 step 1: the seven near fields L and L^{pq} = -c^p c^q L (pq = 11 22 33 12 13 23)
+    element by element, and the far slab's six tensor entries against the series at its nodes."""
+    M1, M2, M3 = 32, 32, 16
+    k, a1, a2 = 5.3, 0.1, 0.4
+    P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3)
+    assert (P.info.n_fields, P.info.far_fields) == (7, 6)
+    assert P.info.far_m1 == (512 if prec == qpgf.C128 else 256)
+    L = method.lhat_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2)
+    refs = [A3 * L] + [A3 * m * L for m in method.maxwell_multipliers(a1, a2, M1 // 2, M2 // 2, M3 // 2)]
+    P.prepare(k, a1, a2, stage=0)
+    # the fill takes H(|xi|) from an 8-point Lagrange table of the radial transform (about 1e-13 of
+    # the largest coefficient at k = 5.3); the oracle integrates H at every coefficient
+    tol = 1e-12 if prec == qpgf.C128 else 1e-7
+    for f in range(7):
+        g = cen(P.field(0, f).cpu().numpy().reshape(M3, M2, M1).transpose(2, 1, 0), (0, 1, 2))
+        assert np.abs(g - refs[f]).max() <= tol * np.abs(refs[f]).max(), f
+    P.prepare(k, a1, a2, stage=2)
+    tol = 1e-12 if prec == qpgf.C128 else 2e-6
+    for f in range(7):
+        g = cen(P.field(0, f).cpu().numpy().reshape(M3, M2, M1).transpose(2, 1, 0), (0, 1, 2))
+        ref_G = method.grid_3d(refs[f] / A3)
+        assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max(), f
+    idx, pts = slabcheck.nodes_3d(P.info, 12, seed=5)
+    ref_F = truth.maxwell3d(k, a1, a2, pts) * np.exp(-1j * (a1 * pts[:, 0] + a2 * pts[:, 1]))[:, None]
+    for f in range(6):
+        assert slabcheck.rel(slabcheck.slab_3d(P, f)[idx], ref_F[:, f]) <= tol, f
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("T", [2000, 70_000])
+def test_maxwell3d_trace_option(prec, T):
+    """maxwell_trace = 1: six near fields (no 33) and GG_33 = 2 G_d - GG_11 - GG_22, against the oracle's
+    trace variant, in the unsorted and the tile-binned gathers (the oracle on a sample)."""
+    M1, M2, M3 = 32, 32, 32
+    k, a1, a2 = 5.3, 0.1, 0.4
+    x = workloads.targets(T, 3, seed=31)
+    P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3, maxwell_trace=1)
+    assert (P.info.n_fields, P.info.far_fields) == (6, 6)
+    g = P(k, a1, a2, dev(x)).cpu().numpy()
+    idx = np.random.default_rng(32).choice(T, 1500, replace=False)
+    o = method.eval_maxwell3d(k, a1, a2, x[idx], M1 // 2, M2 // 2, M3 // 2, trace33=True)
+    for comp in range(6):
+        assert parity(g[idx, comp], o[:, comp]) <= TOL[prec], comp
 
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
 @pytest.mark.parametrize("kind,shape", [(qpgf.KIND_GD3D, (64, 32, 32)), (qpgf.KIND_MAXWELL3D, (64, 32, 32)),
                                         (qpgf.KIND_GD3D, (128, 128, 64)), (qpgf.KIND_MAXWELL3D, (128, 128, 32))])
 def test_binned_gather_large_target_count(prec, kind, shape):
-    """T >= 65536 takes the binned path (targets sorted by grid tile); includes
-    targets beyond the far slab and on the lattice, whose flags must follow them.
-    On 128 x 128 x 64 the 16 x 16 x 8 tiles would hold about 170 targets each, so
-    the larger 32-node tiles are used; Maxwell on 128 x 128 x 32 (about 310
-    targets per tile) stages the seven fields one at a time."""
+    """T >= 65536 takes the binned path (targets sorted by grid tile, near and far tiles); includes
+    targets beyond the far slab and on the lattice, whose flags must follow them.  The flags are
+    checked for every target, the values against the oracle on a seeded sample of 2500 (the far
+    ones against the series).  On 128 x 128 x 64 the 16 x 16 x 8 tiles would hold about 170 targets
+    each, so the larger 32-node tiles are used; Maxwell on 128 x 128 x 32 (about 310 targets per
+    tile) stages the seven fields one at a time."""
     (M1, M2, M3), T = shape, 120_001
     k, a1, a2 = 5.3, 0.1, 0.4
     x = workloads.targets(T, 3, seed=9, zmax=1.2)
@@ -164,19 +215,23 @@ def test_binned_gather_large_target_count(prec, kind, shape):
     flags = torch.empty(T, dtype=torch.uint8, device="cuda")
     g = P(k, a1, a2, dev(x), flags=flags).cpu().numpy()
     f = flags.cpu().numpy()
-    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices,
-                           maxwell=(kind == qpgf.KIND_MAXWELL3D))
-    o = method.evaluate_3d(st, x)
-    ok = np.isfinite(o) if o.ndim == 1 else np.isfinite(o).all(axis=1)
-    np.testing.assert_array_equal(ok, (f & 5) == 0)
-    assert f[17] == 1 and f[T - 1] == 1
-    assert np.all(np.isnan(g[~ok]))
-    gg, oo = g[ok], o[ok]
+    z = np.abs(x[:, 2])
+    beyond = z >= slabcheck.limit(P.info)
+    on_lat = np.zeros(T, bool)
+    on_lat[[17, T - 1]] = True
+    np.testing.assert_array_equal(f, np.where(on_lat, 1, 0) | np.where(z > 0.6, 2, 0) | np.where(beyond, 4, 0))
+    bad = (f & 5) != 0
+    assert np.all(np.isnan(g[bad])) and np.all(np.isfinite(g[~bad]))
+    rng = np.random.default_rng(19)
+    idx = rng.choice(np.nonzero(~bad)[0], 2500, replace=False)
+    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, maxwell=(kind == qpgf.KIND_MAXWELL3D))
+    o = method.evaluate_3d(st, x[idx])
+    gg = g[idx]
     if gg.ndim == 1:
-        assert parity(gg, oo) <= TOL[prec]
+        assert parity(gg, o) <= TOL[prec]
     else:
         for comp in range(6):
-            assert parity(gg[:, comp], oo[:, comp]) <= TOL[prec], comp
+            assert parity(gg[:, comp], o[:, comp]) <= TOL[prec], comp
 
 
 def test_prepare_then_evaluate_in_chunks_matches_single_call():
@@ -244,7 +299,7 @@ def test_lattice_rmin_flags_and_values_3d(prec, T):
     inside[:40:2] = True
     np.testing.assert_array_equal((f & 1) == 1, inside)
     assert np.all(np.isnan(g[inside])) and np.all(np.isfinite(g[~inside]))
-    o = method.eval_gd3d(k, a1, a2, x[:2000], M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_gd3d(k, a1, a2, x[:2000], M1 // 2, M2 // 2, M3 // 2)
     sel = ~inside[:2000]
     assert parity(g[:2000][sel], o[sel]) <= TOL[prec]
 
@@ -267,7 +322,7 @@ def test_edge_targets_and_status_codes():
     f = flags.cpu().numpy()
     assert list(f) == [1, 1, 0, 0, 0, 2, 6, 8, 0]
     assert np.isnan(g[[0, 1, 6, 7]]).all() and np.isfinite(g[[2, 3, 4, 5, 8]]).all()
-    o = method.eval_g2d(k, al, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_g2d(k, al, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2)
     assert parity(g[[2, 3, 4, 5, 8]], o) <= 1e-10
     # quasi-periodicity of the reduction: G(x1 + 2 pi) = e^{i 2 pi alpha} G(x1)
     np.testing.assert_allclose(g[2], np.exp(2j * math.pi * al) * g[3], rtol=1e-12)
@@ -280,7 +335,7 @@ def test_edge_targets_and_status_codes():
     # special coefficient beta_0 = pi (j2 = 1, c~ = 1) for k^2 = alpha^2 + pi^2: evaluated, not refused
     ks = math.sqrt(0.3 ** 2 + math.pi ** 2)
     gs = P(ks, 0.3, 0.0, dev(x[[2, 3, 4, 5, 8]])).cpu().numpy()
-    os_ = method.eval_g2d(ks, 0.3, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    os_ = method.eval_g2d(ks, 0.3, x[[2, 3, 4, 5, 8]], M1 // 2, M2 // 2)
     assert parity(gs, os_) <= 1e-10
     # wrong entry point for the plan kind
     P3 = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, 32, 32, 32)
@@ -311,6 +366,6 @@ def test_gd3d_full_size_sampled():
         outs[prec] = P(k, a1, a2, xd)[torch.from_numpy(idx).cuda()].cpu().numpy()
         info = P.info
         P.close()
-    o = method.eval_gd3d(k, a1, a2, x[idx], M1 // 2, M2 // 2, M3 // 2, info.far_h, info.far_slices)
+    o = method.eval_gd3d(k, a1, a2, x[idx], M1 // 2, M2 // 2, M3 // 2)
     assert parity(outs[qpgf.C128], o) <= TOL[qpgf.C128]
     assert parity(outs[qpgf.C64], o) <= TOL[qpgf.C64]

@@ -61,7 +61,7 @@ def test_ring_end_to_end(prec, order, shape, T):
     f = flags.cpu().numpy()
     bad = (f & 13) != 0
     assert np.all(np.isnan(g[bad]))
-    o = ho.eval_g2d_ho(K, AL, x[~bad], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, order, ring=True)
+    o = ho.eval_g2d_ho(K, AL, x[~bad], M1 // 2, M2 // 2, order, ring=True)
     assert parity(g[~bad], o) <= TOL[prec]
     # every other target is the plain plan's result, bit for bit; the flags are the same
     P0 = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2, sing_order=order)
@@ -103,7 +103,7 @@ def test_ring_many_targets_sampled():
     assert len(ring) > 20000
     rng = np.random.default_rng(1)
     pick = np.concatenate([rng.choice(ring, 300, replace=False), rng.choice(T, 300, replace=False)])
-    o = ho.eval_g2d_ho(K, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, 3, ring=True)
+    o = ho.eval_g2d_ho(K, AL, x[pick], 512, 64, 3, ring=True)
     assert parity(g[pick], o) <= TOL[qpgf.C64]
     # smaller calls on the same plan reuse the mask (never cleared: each call writes the words it
     # reads); counts on both sides of a mask word (64 targets) and of a ring block (16384 targets)
@@ -154,7 +154,7 @@ def test_grad_ring_end_to_end(prec, shape, T):
     f = flags.cpu().numpy()
     bad = (f & 13) != 0
     assert np.all(np.isnan(g[bad]))
-    o = grad2d.eval_g2d_grad(K, AL, x[~bad], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, ring=True)
+    o = grad2d.eval_g2d_grad(K, AL, x[~bad], M1 // 2, M2 // 2, ring=True)
     for p in range(2):
         assert parity(g[~bad, p], o[:, p]) <= TOL[prec], p
     P0 = qpgf.Plan(qpgf.KIND_G2D_GRAD, prec, M1, M2)
@@ -200,7 +200,7 @@ def test_hess_ring_end_to_end(prec, shape, T):
     f = flags.cpu().numpy()
     bad = (f & 13) != 0
     assert np.all(np.isnan(g[bad]))
-    o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[~bad], M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, ring=True)
+    o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[~bad], M1 // 2, M2 // 2, ring=True)
     for p in range(3):
         assert parity(g[~bad, p], o[:, p]) <= TOL[prec], p
     P0 = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, prec, M1, M2)
@@ -245,8 +245,8 @@ def test_ring_derivative_kinds_many_targets_sampled(kind):
     rng = np.random.default_rng(3)
     pick = np.concatenate([rng.choice(ring, 250, replace=False), rng.choice(T, 250, replace=False)])
     if kind == qpgf.KIND_G2D_HESS_DIFF:
-        o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, ring=True)
+        o = hess2d.eval_g2d_hess_diff(K, K2, AL, x[pick], 512, 64, ring=True)
     else:
-        o = grad2d.eval_g2d_grad(K, AL, x[pick], 512, 64, P.info.far_h, P.info.far_slices, ring=True)
+        o = grad2d.eval_g2d_grad(K, AL, x[pick], 512, 64, ring=True)
     for p in range(o.shape[1]):
         assert parity(g[pick, p], o[:, p]) <= TOL[qpgf.C64], p

@@ -57,7 +57,7 @@ def test_special_2d_end_to_end(prec, k):
     x = workloads.targets(T, 2, seed=21)
     P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
     g = P(k, AL, 0.0, dev(x)).cpu().numpy()
-    o = method.eval_g2d(k, AL, x, M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_g2d(k, AL, x, M1 // 2, M2 // 2)
     assert parity(g, o) <= TOL[prec]
 
 
@@ -84,11 +84,11 @@ def test_special_2d_with_higher_order_and_ring(prec):
         ref = A2 * ho.lhat_ho(K2S, AL, M1 // 2, M2 // 2, 3)
         assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max()
     g = P(K2S, AL, 0.0, dev(x)).cpu().numpy()
-    o = ho.eval_g2d_ho(K2S, AL, x, M1 // 2, M2 // 2, P.info.far_h, P.info.far_slices, 3, ring=True)
+    o = ho.eval_g2d_ho(K2S, AL, x, M1 // 2, M2 // 2, 3, ring=True)
     assert parity(g, o) <= TOL[prec]
     Pg = qpgf.Plan(qpgf.KIND_G2D_GRAD, prec, M1, M2, ring_interp=1)
     g = Pg(K2S, AL, 0.0, dev(x)).cpu().numpy()
-    o = grad2d.eval_g2d_grad(K2S, AL, x, M1 // 2, M2 // 2, Pg.info.far_h, Pg.info.far_slices, ring=True)
+    o = grad2d.eval_g2d_grad(K2S, AL, x, M1 // 2, M2 // 2, ring=True)
     for p in range(2):
         assert parity(g[:, p], o[:, p]) <= TOL[prec]
 
@@ -99,13 +99,13 @@ def test_special_2d_derivative_kinds():
     x = workloads.targets(2_000, 2, seed=23)
     Pg = qpgf.Plan(qpgf.KIND_G2D_GRAD, qpgf.C128, M1, M2)
     g = Pg(K2S, AL, 0.0, dev(x)).cpu().numpy()
-    o = grad2d.eval_g2d_grad(K2S, AL, x, M1 // 2, M2 // 2, Pg.info.far_h, Pg.info.far_slices)
+    o = grad2d.eval_g2d_grad(K2S, AL, x, M1 // 2, M2 // 2)
     for p in range(2):
         assert parity(g[:, p], o[:, p]) <= 1e-10
     Ph = qpgf.Plan(qpgf.KIND_G2D_HESS_DIFF, qpgf.C128, M1, M2)
     for k1, k2 in ((K2S, 2.1), (2.1, K2S)):
         g = Ph.hess_diff(k1, k2, AL, dev(x)).cpu().numpy()
-        o = hess2d.eval_g2d_hess_diff(k1, k2, AL, x, M1 // 2, M2 // 2, Ph.info.far_h, Ph.info.far_slices)
+        o = hess2d.eval_g2d_hess_diff(k1, k2, AL, x, M1 // 2, M2 // 2)
         for p in range(3):
             assert parity(g[:, p], o[:, p]) <= 1e-10
 
@@ -126,7 +126,7 @@ def test_special_3d_end_to_end(prec):
     x = workloads.targets(T, 3, seed=24)
     P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
     g = P(K3S, A31, A32, dev(x)).cpu().numpy()
-    o = method.eval_gd3d(K3S, A31, A32, x, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    o = method.eval_gd3d(K3S, A31, A32, x, M1 // 2, M2 // 2, M3 // 2)
     assert parity(g, o) <= TOL[prec]
 
 

@@ -113,7 +113,7 @@ def test_smooth_part_matches_oracle(prec):
     P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
     P.prepare(k, a1, a2)
     L = P.smooth(dev(x)).cpu().numpy()
-    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, P.info.far_h, P.info.far_slices)
+    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2)
     o = method.smooth_3d(st, x)
     near = np.abs(x[:, 2]) <= 0.6
     assert np.all(np.isnan(L[~near]))
@@ -136,11 +136,11 @@ def _targets(n_inst, per, seed):
     return np.concatenate(xs), t_off
 
 
-def _plain(k, a1, a2, x, t_off, M, far_h, far_S):
+def _plain(k, a1, a2, x, t_off, M):
     outs = []
     for i in range(len(k)):
         xi = x[t_off[i]:t_off[i + 1]]
-        outs.append(method.eval_gd3d(k[i], a1[i], a2[i], xi, M[0] // 2, M[1] // 2, M[2] // 2, far_h, far_S))
+        outs.append(method.eval_gd3d(k[i], a1[i], a2[i], xi, M[0] // 2, M[1] // 2, M[2] // 2))
     return np.concatenate(outs)
 
 
@@ -170,7 +170,7 @@ def test_surrogate_eval_with_fallback():
     L = 0.1 * (ym[:, 0] + 1j * ym[:, 1])
     G = mlp.g_from_smooth(q[acc], L)
     assert np.max(np.abs(out[acc] - G)) <= SCALE * np.max(np.abs(L))
-    plain = _plain(k, a1, a2, x, t_off, M, P.info.far_h, P.info.far_slices)
+    plain = _plain(k, a1, a2, x, t_off, M)
     fb = ~acc & (r > 0)          # the plan's own lattice_rmin is 0: only r = 0 gives NaN there
     wood = inst == 2
     assert parity(out[fb & ~wood], plain[fb & ~wood]) <= 1e-10
