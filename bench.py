@@ -35,20 +35,25 @@ K, A1, A2 = 3.7, 0.2, 0.35
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(name, info, T, esize):
-    """Bytes a kernel class must move per launch (what the method reads/writes at least once)."""
-    m1, m2, m3, S, nf = info.m1, info.m2, info.m3, info.far_slices, info.n_fields
-    ncell, nfar = m1 * m2 * m3, m1 * m2 * S
-    if name == "gather":       # targets in (3 x f64) + result out, grids read once
-        return T * (24 + esize) + (ncell + nfar) * esize * nf
+def algorithmic_bytes(name, info, counts, esize):
+    """Bytes a kernel class must move per launch (what the method reads/writes at least once).
+    counts: targets in total, near (|x3| <= c) and far."""
+    m1, m2, m3, nf = info.m1, info.m2, info.m3, info.n_fields
+    ncell = m1 * m2 * m3
+    nfar, nfo = info.far_m1 * info.far_m2 * info.far_slices, info.far_fields
+    T, Tn, Tf = counts
+    if name == "gather":       # near tiles: their targets in (3 x f64) + result out, the near grid read once
+        return Tn * (24 + esize) + ncell * esize * nf
+    if name == "gather_far":   # far tiles: their targets + results, the far slab read once
+        return Tf * (24 + esize) + nfar * esize * nfo
     if name == "fill":         # coefficient write
         return ncell * esize * nf
     if name in ("fft_t", "fft_2", "fft_1"):
         return 2 * ncell * esize * nf
     if name == "far":
-        return nfar * esize * nf
+        return nfar * esize * nfo
     if name == "far_fft":      # two passes over the far slab
-        return 4 * nfar * esize * nf
+        return 4 * nfar * esize * nfo
     if name == "bin":          # coordinates read once (counts, then scans of the small count table)
         return T * 24
     if name == "bin_place":    # coordinates read, 32-byte tile-ordered record written per target
@@ -57,7 +62,7 @@ def algorithmic_bytes(name, info, T, esize):
 
 
 # timer classes that bracket exactly one kernel launch (candidates for the roofline kernel)
-SINGLE_KERNEL = ("fill", "fft_t", "fft_2", "fft_1", "far", "gather", "bin_place")
+SINGLE_KERNEL = ("fill", "fft_t", "fft_2", "fft_1", "far", "gather", "gather_far", "bin_place")
 
 
 def source_hash(files):
@@ -68,21 +73,39 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(x_np, info, n_sample):
-    """The oracle (unchanged) on the host: full-size preparation + a target sample, extrapolated to T."""
+def cpu_baseline(x_np, sample, info):
+    """The oracle as it stands, on the host: its full-size preparation (coefficients and direct-DFT
+    grids) plus the evaluation of a seeded sample of the targets (near ones by interpolation, far ones
+    by the series), the evaluation extrapolated linearly to all targets.  Returns the record and the
+    oracle's values at the sample (for the per-result parity of the GPU results)."""
     import threadpoolctl
     from oracle import method
     t0 = time.perf_counter()
     st = method.prepare_3d(K, A1, A2, info.m1 // 2, info.m2 // 2, info.m3 // 2)
     t1 = time.perf_counter()
-    method.evaluate_3d(st, x_np[:n_sample])
+    o = method.evaluate_3d(st, x_np[sample])
     t2 = time.perf_counter()
-    T = len(x_np)
+    T, n_sample = len(x_np), len(sample)
     t_full = (t1 - t0) + (t2 - t1) * T / n_sample
-    threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
-    return {"value": T / t_full, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"full-size preparation (fill + direct-DFT grids, {t1 - t0:.1f} s) + {n_sample} of {T} "
-                      f"targets ({t2 - t1:.2f} s), evaluation extrapolated linearly to {T} targets"}
+    blas = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
+    rec = {"value": T / t_full, "unit": "evals/s", "cores": blas, "kind": "oracle",
+           "host_cores": os.cpu_count(),
+           "threads": f"the direct-DFT grid sums (numpy tensordot) run on the BLAS pool of {blas} threads; "
+                      f"the coefficients, the interpolation and the series of the far branch are "
+                      f"single-threaded numpy",
+           "sample": f"full-size preparation (coefficients + direct-DFT grids, {t1 - t0:.1f} s) + a sample of "
+                     f"{n_sample} of {T} targets, seeded ({t2 - t1:.1f} s; far ones by the series), evaluation "
+                     f"extrapolated linearly to {T} targets"}
+    return rec, o
+
+
+def parity_err(g, o):
+    """max_i |g_i - o_i| / max(|o_i|, RMS |o|) over the finite oracle values."""
+    import numpy as np
+    ok = np.isfinite(o)
+    g, o = np.asarray(g)[ok].astype(np.complex128), o[ok]
+    s = np.sqrt(np.mean(np.abs(o) ** 2))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), s)))
 
 
 def main():
@@ -90,10 +113,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--prec", choices=["c64", "c128"], default=None,
+                    help="gd3d: precision of the headline value (default c128; the other one is timed beside "
+                         "it); other workloads: their precision (default c64)")
     ap.add_argument("--targets", type=int, default=10_000_000)
     ap.add_argument("--modes", default="256,256,64")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["gd3d", "batched2d", "maxwell3d", "surrogate", "g2d_grad", "g2d_hess_diff", "g2d_ho"], default="gd3d")
     ap.add_argument("--train-instances", type=int, default=2000)
@@ -112,6 +137,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprofv3 FETCH/WRITE counters)")
     args = ap.parse_args()
+    if args.prec is None:
+        args.prec = "c128" if args.workload == "gd3d" else "c64"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this implementation runs on exactly one GPU (--gpus 1); "
                                    "the decomposition over several GPUs is described, not implemented"}))
@@ -142,57 +169,67 @@ def main():
     m1, m2, m3 = (int(v) for v in args.modes.split(","))
     T = args.targets
     prec = qpgf.C64 if args.prec == "c64" else qpgf.C128
-    esize = 8 if prec == qpgf.C64 else 16
+    other = qpgf.C128 if prec == qpgf.C64 else qpgf.C64
+    pname = {qpgf.C128: "c128", qpgf.C64: "c64"}
     x_np = workloads.targets(T, 3, seed=2)
     x = torch.from_numpy(x_np).cuda()
-    plan = qpgf.Plan(qpgf.KIND_GD3D, prec, m1, m2, m3)
-    out = plan.out_tensor(T)
-    print(f"[bench] plan {m1}x{m2}x{m3} {args.prec}, T={T}, warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    Tn = int(np.count_nonzero(np.abs(x_np[:, 2]) <= 0.6))
+    counts = (T, Tn, T - Tn)
+    rng = np.random.default_rng(17)
+    sample = np.sort(rng.choice(T, args.cpu_sample, replace=False))
+    sample_d = torch.from_numpy(sample).cuda()
 
-    def step():
-        if args.sequential:
+    def run(pr):
+        """Time the step on precision pr; per-kernel durations; results at the parity sample."""
+        plan = qpgf.Plan(qpgf.KIND_GD3D, pr, m1, m2, m3)
+        out = plan.out_tensor(T)
+        esize = 8 if pr == qpgf.C64 else 16
+        print(f"[bench] plan {m1}x{m2}x{m3} {pname[pr]}, T={T}, warmup {args.warmup}, steps {args.steps}",
+              file=sys.stderr, flush=True)
+
+        def step():
+            if args.sequential:
+                plan.prepare(K, A1, A2)
+                plan.evaluate(x, out)
+            else:
+                plan(K, A1, A2, x, out)     # qpgf_gd3d: binning beside the preparation
+
+        t = _timed(step, args.steps, args.warmup)
+        print(f"[bench] {pname[pr]}: {t * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        at_sample = out[sample_d].cpu().numpy()
+        # per-kernel durations, from HIP events on the stream each kernel runs on; kernels
+        # one at a time (prepare, then evaluate), so no duration includes a neighbour's share
+        plan.enable_timing(True)
+        for _ in range(args.steps):
             plan.prepare(K, A1, A2)
             plan.evaluate(x, out)
-        else:
-            plan(K, A1, A2, x, out)     # qpgf_gd3d: binning beside the preparation
+        torch.cuda.synchronize()
+        tim = plan.timing()
+        plan.enable_timing(False)
+        kernels = {}
+        for name, (ms, n) in tim.items():
+            if n:
+                avg = ms / n
+                b = algorithmic_bytes(name, plan.info, counts, esize)
+                kernels[name] = {"avg_ms": round(avg, 5), "launches_per_step": n // args.steps,
+                                 "alg_bytes": b, "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+        for name, v in kernels.items():
+            print(f"[bench]   {name:10s} {v['avg_ms']:.4f} ms  {v['GBps']} GB/s", file=sys.stderr, flush=True)
+        acc = accuracy_vs_truth(plan)
+        info = plan.info
+        del out
+        plan.close()
+        return t, kernels, acc, at_sample, info
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = T * args.steps / (t1 - t0)
-    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # per-kernel durations, from HIP events on the stream each kernel runs on; kernels
-    # one at a time (prepare, then evaluate), so no duration includes a neighbour's share
-    plan.enable_timing(True)
-    for _ in range(args.steps):
-        plan.prepare(K, A1, A2)
-        plan.evaluate(x, out)
-    torch.cuda.synchronize()
-    tim = plan.timing()
-    plan.enable_timing(False)
-    kernels = {}
-    for name, (ms, n) in tim.items():
-        if n:
-            avg = ms / n
-            b = algorithmic_bytes(name, plan.info, T, esize)
-            kernels[name] = {"avg_ms": round(avg, 5), "launches_per_step": n // args.steps,
-                             "alg_bytes": b, "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
-    for name, v in kernels.items():
-        print(f"[bench] {name:8s} {v['avg_ms']:.4f} ms  {v['GBps']} GB/s", file=sys.stderr, flush=True)
+    t_main, kernels, acc, g_main, info = run(prec)
+    t_oth, kernels_oth, acc_oth, g_oth, _ = run(other)
+    value = T / t_main
     dom = max((n for n in kernels if n in SINGLE_KERNEL),
               key=lambda n: kernels[n]["avg_ms"] * kernels[n]["launches_per_step"])
     d = kernels[dom]
     achieved = d["alg_bytes"] / (d["avg_ms"] * 1e-3) / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{dom}_gd3d_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"{dom}_gd3d_{args.prec}_traffic.json")
     if os.path.exists(tfile):
         rec = json.load(open(tfile))
         if rec.get("source_hash") == source_hash(rec.get("sources", [])) and rec.get("prec") == args.prec:
@@ -200,10 +237,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
-    acc = accuracy_vs_truth(plan, prec)
     gate = None
     if not args.no_gate:
-        gate = run_gate(args, x, prec)
+        gate = {pname[prec]: run_gate(args, x, prec)}
+        gate[pname[other]] = run_gate(args, x, other)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -211,29 +248,37 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    del x
 
-    del out, x
-    plan.close()
-    base = None
+    base, parity = None, None
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         print(f"[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        base = cpu_baseline(x_np, plan.info, args.cpu_sample)
+        # the oracle evaluates the sampled targets (the first entries of the sample order)
+        base, o = cpu_baseline(x_np, sample, info)
+        parity = {pname[prec]: parity_err(g_main, o), pname[other]: parity_err(g_oth, o), "n": int(len(o)),
+                  "reference": "the FP64 oracle (near: the method computed plainly; far: the series) at a seeded "
+                               "sample of the benchmark targets; error max_i |g - o| / max(|o|, RMS |o|)"}
 
     line = {
         "metric": "Green's evals/sec at 1e-6 rel err (3D G_d), plain vs batched/surrogate",
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.prec, "data": "synthetic",
+        "ms_per_step": t_main * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": pname[prec], "data": "synthetic",
         "config": {"workload": "gd3d k=3.7 alpha=(0.2,0.35)", "modes": [m1, m2], "slices": m3,
                    "targets": T, "method": "plain, prepare + evaluate" if args.sequential else "plain",
                    "parallelism": "none"},
         "roofline": roofline,
         "cpu_baseline": base,
         "accuracy_vs_truth": acc,
+        "parity_vs_oracle": parity,
         "gate": gate,
+        f"value_{pname[other]}": T / t_oth,
+        f"ms_per_step_{pname[other]}": t_oth * 1e3,
+        f"accuracy_vs_truth_{pname[other]}": acc_oth,
         "kernel_timing": "HIP events per kernel, kernels one at a time (prepare, then evaluate); the timed "
                          "steps use the combined call, which bins the targets beside the preparation",
         "kernels": kernels,
+        f"kernels_{pname[other]}": kernels_oth,
     }
     print(json.dumps(line), flush=True)
 
@@ -242,7 +287,7 @@ TRUTH = os.path.join(ROOT, "tests", "golden", "truth_gd3d_k3.7.txt")
 GATE_MODES = (512, 512, 128)
 
 
-def accuracy_vs_truth(plan, prec):
+def accuracy_vs_truth(plan):
     """Error of the plan's G_d at the stored exact values (lattice sum at 2000 of the benchmark targets):
     |g - o| / max(|o|, RMS |o|), median / 99th percentile / max."""
     import numpy as np
@@ -266,7 +311,7 @@ def run_gate(args, x, prec):
     plan = qpgf.Plan(qpgf.KIND_GD3D, prec, *GATE_MODES)
     out = plan.out_tensor(x.shape[0])
     t = _timed(lambda: plan(K, A1, A2, x, out), args.steps, args.warmup)
-    acc = accuracy_vs_truth(plan, prec)
+    acc = accuracy_vs_truth(plan)
     plan.enable_timing(True)
     for _ in range(args.steps):     # kernels one at a time, as for the main configuration
         plan.prepare(K, A1, A2)

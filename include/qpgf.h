@@ -21,9 +21,9 @@
  * itself: the series' terms are summed by inverse FFT on a far slab of slices
  * z_s = c - 3 h_f + s h_f, s = 0 .. S_f-1, with far_m modes per periodic axis,
  * and the slab is interpolated with the 8-point Lagrange rule per axis (64 / 512
- * nodes).  No singular part exists there; with the defaults (far_m >= 256,
- * h_f <= c~/64) the far branch agrees with the direct sum of the series to about
- * 1e-11 relative for k up to about 6.
+ * nodes).  No singular part exists there; with the automatic slab geometry (far_m,
+ * far_h) the far branch agrees with the direct sum of the series to about 1e-11
+ * (complex128) or 1e-7 (complex64) relative.
  *
  * Conventions for every entry point:
  *  - All bulk arrays (targets, outputs, flags) are DEVICE pointers owned by the
@@ -137,8 +137,8 @@ typedef struct {
                               complex128 x2 axis <= 2048); 0: automatic per prepared instance, the
                               largest of m1 (3D: m2), a floor, and the smallest power of two >= 2 pi k / x,
                               x = 0.0977 for complex128 and 0.3 for complex64 (k: the instance's largest
-                              wavenumber).  The floor is 256 modes, 512 for the complex128 Maxwell and
-                              derivative kinds.  The far slab holds the terms of the series with
+                              wavenumber).  The floor is 512 modes for complex128 and 256 for complex64.
+                              The far slab holds the terms of the series with
                               |j| < far_m / 2; the 8-point rule interpolates a term of wavenumber q to
                               about (q h)^8 / 1000, h = 2 pi / far_m or h_f, which the automatic choice keeps
                               near 1e-11 (complex128) or 1e-7 (complex64) relative.  The slab is allocated
@@ -362,7 +362,8 @@ typedef enum {
   QPGF_T_LAYOUT = 12,    /* 2D: derivative fields interleaved per node, or the     */
                          /* complex64 G's node quads (4 x1-neighbours per node)  */
   QPGF_T_RING = 13,      /* 2D kinds with ring_interp: the cut-off-ring correction */
-  QPGF_T_COUNT = 14
+  QPGF_T_GATHER_FAR = 14,  /* 3D binned calls: the far-tile gather (QPGF_T_GATHER: near tiles) */
+  QPGF_T_COUNT = 15
 } qpgf_timer_id;
 qpgf_status qpgf_plan_enable_timing(qpgf_plan* plan, int on);
 qpgf_status qpgf_plan_get_timing(qpgf_plan* plan, int id, double* total_ms, int64_t* launches);

@@ -156,18 +156,15 @@ qpgf_status validate(const qpgf_params* p) {
 // the 8-point rule).  The rule's error for a term of wavenumber q along an axis of spacing h is
 // about (q h)^8 / 1000: with h = 2 pi / Mf and the propagating terms (q <= k), Mf >= 2 pi k / x
 // keeps it near 1e-11 (complex128, x = 0.0977) or 1e-7 (complex64, x = 0.3); the evanescent terms
-// the series keeps at |x_t| >= c - 3 hf set the floors, 256 modes and hf <= 1/64, and for the
-// derivative kinds, whose terms carry xi (and xi^2), 512 modes on the complex128 path (measured
-// against the direct sum of the series).  Slices z_s = c - 3 hf + s hf, s < S: a target at
+// the series keeps at |x_t| >= c - 3 hf set the floors, hf <= 1/64 and 512 modes on the complex128
+// path (256 leave up to 4e-11 of |G_d| near |x3| = c at k = 3.7; 512 leave 6e-13), 256 on the complex64
+// path (measured against the direct sum of the series).  Slices z_s = c - 3 hf + s hf, s < S: a target at
 // |x_t| = z uses slices floor((z - z_0) / hf) - 3 .. + 4, so S = ceil((zmax - c) / hf) + 8 covers
 // every z <= zmax.  params.far_m and params.far_h override the modes and the spacing.
 FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
   const bool c128 = P.p.prec == QPGF_C128;
   const double x = c128 ? 0.0977 : 0.3;
-  const int kind = P.p.kind;
-  int floor_m = 256;
-  if (c128 && (kind == QPGF_KIND_MAXWELL3D || kind == QPGF_KIND_G2D_GRAD || kind == QPGF_KIND_G2D_HESS_DIFF))
-    floor_m = 512;
+  const int floor_m = c128 ? 512 : 256;
   const double want = 2.0 * M_PI * std::max(kmax, 0.0) / x;
   int mk = floor_m;
   while (mk < want && mk < 4096) mk <<= 1;

@@ -1646,8 +1646,9 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   // 1024 threads) or 32 x 16 x 8 (complex128, 117 KiB, 512 threads).  Maxwell: 8 x 8 x 4
   // (complex64) or 8 x 4 x 4 (complex128) with every field staged (47 / 60 KiB for seven
   // fields), or 16 x 16 x 8 staged field by field when the tiles hold few targets.
-  // Far tiles (8-point footprints, one field staged at a time): 8 x 8 x 8 nodes on far slabs of
-  // up to 256 x 256 modes, else 16 x 16 x 8 (complex64, 62 KiB) or 16 x 8 x 8 (complex128, 81 KiB).
+  // Far tiles (8-point footprints, one field staged at a time): 8 x 8 x 8 nodes (27 / 53 KiB), or
+  // 16 x 16 x 8 (complex64, 62 KiB) or 16 x 8 x 8 (complex128, 81 KiB) when the 8-node tiles' keys
+  // would not fit the LDS histograms of the binning.
   // Must match the instantiations below.
   TileCfg C{};
   TileArgs& Tl = C.t;
@@ -1677,15 +1678,20 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
         set_near(5, sizeof(T) == 8 ? 4 : 5, 3);
       }
     }
-    C.far_big = P.Mf1 > 256 || P.Mf2 > 256;
-    Tl.ftb1 = C.far_big ? 4 : 3;
-    Tl.ftb2 = C.far_big && sizeof(T) == 4 ? 4 : 3;
-    Tl.ftb3 = 3;
-    Tl.fnt1 = std::max(1, P.Mf1 >> Tl.ftb1);
-    Tl.fnt2 = std::max(1, P.Mf2 >> Tl.ftb2);
-    Tl.fnt3 = ((P.S - 5) >> Tl.ftb3) + 1;
-    Tl.nfar = Tl.fnt1 * Tl.fnt2 * Tl.fnt3;
-    Tl.nkeys = Tl.nnear + Tl.nfar + 1;
+    auto set_far = [&](bool big) {
+      C.far_big = big;
+      Tl.ftb1 = big ? 4 : 3;
+      Tl.ftb2 = big && sizeof(T) == 4 ? 4 : 3;
+      Tl.ftb3 = 3;
+      Tl.fnt1 = std::max(1, P.Mf1 >> Tl.ftb1);
+      Tl.fnt2 = std::max(1, P.Mf2 >> Tl.ftb2);
+      Tl.fnt3 = ((P.S - 5) >> Tl.ftb3) + 1;
+      Tl.nfar = Tl.fnt1 * Tl.fnt2 * Tl.fnt3;
+      Tl.nkeys = Tl.nnear + Tl.nfar + 1;
+    };
+    // 8-node far tiles (several blocks per CU) unless their keys would overflow the LDS histograms
+    set_far(false);
+    if (Tl.nkeys > kBinLdsKeys) set_far(true);
     e = ensure_bin_scratch(P, T_, Tl.nkeys);
     if (e != hipSuccess) return e;
     std::memcpy(P.bt, &C, sizeof C);
@@ -1743,7 +1749,6 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   }
   if (mode == kBinOnly) return hipSuccess;
   {
-    KernelTimer t(P, QPGF_T_GATHER);
     const dim3 tn(Tl.nnear), tf(Tl.nfar + 1);
 #define QPGF_NEAR(A1_, A2_, A3_, BS_)                                                                             \
   hipLaunchKernelGGL((k_gather3d_near<T, NF, A1_, A2_, A3_, BS_>), tn, dim3(BS_), 0, P.stream, A, Tl, g, rec,     \
@@ -1752,9 +1757,13 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
                      P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
     // far tiles first (more targets and work each), then the near tiles
-    if (!C.far_big) QPGF_FAR(3, 3, 3);
-    else if constexpr (sizeof(T) == 8) QPGF_FAR(4, 3, 3);
-    else QPGF_FAR(4, 4, 3);
+    {
+      KernelTimer t(P, QPGF_T_GATHER_FAR);
+      if (!C.far_big) QPGF_FAR(3, 3, 3);
+      else if constexpr (sizeof(T) == 8) QPGF_FAR(4, 3, 3);
+      else QPGF_FAR(4, 4, 3);
+    }
+    KernelTimer t(P, QPGF_T_GATHER);
     if constexpr (NF > 1) {
       if (C.fields)
         hipLaunchKernelGGL((k_gather3d_near_fields<T, NF, 4, 4, 3>), tn, dim3(256), 0, P.stream, A, Tl, g, rec,

@@ -51,7 +51,7 @@ EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
            "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch", "bin_place",
-          "overflow", "layout", "ring"]
+          "overflow", "layout", "ring", "gather_far"]
 
 _lib = None
 

@@ -33,7 +33,9 @@ def _errors(g, o):
 
 
 # grid -> bounds on (p99, max), both precisions; measured values on this sample are about half of these.
-# 512 x 512 x 128 is the smallest of these grids whose p99 error is below 1e-6.
+# 512 x 512 x 128 is the smallest of these grids whose p99 error is below 1e-6 (complex128).  The
+# complex64 path adds its own rounding: the far branch sums 512 single-precision products per target,
+# about 1e-6 of |G| at the 99th percentile, so its p99 bound is at least 1.5e-6.
 GRIDS = [((256, 256, 64), (1.5e-3, 4e-3)), ((512, 512, 64), (1.5e-3, 3e-3)), ((256, 256, 128), (5e-6, 4e-3)),
          ((512, 512, 128), (1e-6, 5e-4)), ((1024, 1024, 256), (1e-6, 5e-5))]
 
@@ -56,7 +58,8 @@ def test_accuracy_against_the_lattice_sum():
                 for i in np.argsort(e)[-3:]:
                     t = np.mod(x[i, :2] + np.pi, 2 * np.pi) - np.pi
                     print(f"   worst: err {e[i]:.1e} x3 {x[i, 2]:+.4f} |t| {np.hypot(*t):.4f} |G| {abs(o[i]):.2e}")
-            assert p99 <= bound[0] and mx <= bound[1], (M1, M2, M3, prec)
+            p99_bound = bound[0] if prec == qpgf.C128 else max(bound[0], 1.5e-6)
+            assert p99 <= p99_bound and mx <= bound[1], (M1, M2, M3, prec)
             P.close()
             del P
             torch.cuda.empty_cache()

@@ -58,7 +58,7 @@ def test_fill2d_and_grid2d_stages(prec):
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
     # far slab: at its nodes the series (1.2) itself, on its own grid of far_m1 >= 256 modes
-    assert P.info.far_m1 == 256 and P.info.far_fields == 1
+    assert P.info.far_m1 == (512 if prec == qpgf.C128 else 256) and P.info.far_fields == 1
     (si, pi), pts = slabcheck.nodes_2d(P.info, 60, seed=1)
     ref_F = truth.g2d(k, al, pts) * np.exp(-1j * al * pts[:, 0])
     assert slabcheck.rel(slabcheck.slab_2d(P)[si, pi], ref_F) <= tol
@@ -82,7 +82,8 @@ def test_fill3d_and_grid3d_stages(prec):
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
     # far slab: at its nodes the series (1.3) itself
-    assert (P.info.far_m1, P.info.far_m2, P.info.far_fields) == (256, 256, 1)
+    mf = 512 if prec == qpgf.C128 else 256
+    assert (P.info.far_m1, P.info.far_m2, P.info.far_fields) == (mf, mf, 1)
     idx, pts = slabcheck.nodes_3d(P.info, 30, seed=2)
     ref_F = truth.gd3d(k, a1, a2, pts) * np.exp(-1j * (a1 * pts[:, 0] + a2 * pts[:, 1]))
     assert slabcheck.rel(slabcheck.slab_3d(P)[idx], ref_F) <= tol
