@@ -19,9 +19,9 @@
  * quasi-periodic phase.  Targets with |x_t| > c (x_t = x2 in 2D, x3 in 3D) take
  * the far branch, where step 2b of the algorithms uses the eigenfunction series
  * itself: the series' terms are summed by inverse FFT on a far slab of slices
- * z_s = c - 3 h_f + s h_f, s = 0 .. S_f-1, with far_m modes per periodic axis,
- * and the slab is interpolated with the 8-point Lagrange rule per axis (64 / 512
- * nodes).  No singular part exists there; with the automatic slab geometry (far_m,
+ * z_s = c - (P/2 - 1) h_f + s h_f, s = 0 .. S_f-1, with far_m modes per periodic
+ * axis, and the slab is interpolated with the P-point Lagrange rule per axis: P = 8
+ * (64 / 512 nodes), or P = 4 (64 nodes, on a finer slab) for complex64 in 3D.  No singular part exists there; with the automatic slab geometry (far_m,
  * far_h) the far branch agrees with the direct sum of the series to about 1e-11
  * (complex128) or 1e-7 (complex64) relative.
  *
@@ -43,7 +43,7 @@
  *      bit 0  the target lies within params.lattice_rmin of a lattice point
  *             (output NaN); with lattice_rmin = 0 only an exact hit is flagged,
  *      bit 1  far branch (|x_t| > c),
- *      bit 2  |x_t| beyond the far slab, i.e. >= c + (S_f - 7) h_f (output NaN;
+ *      bit 2  |x_t| beyond the far slab, i.e. >= c + (S_f - P + 1) h_f (output NaN;
  *             the slab covers |x_t| <= params.far_zmax),
  *      bit 3  non-finite target coordinate (output NaN).
  *  - On error the call returns a nonzero qpgf_status and qpgf_last_error()
@@ -166,6 +166,8 @@ typedef struct {
   int far_m1, far_m2;      /* far-slab modes per periodic axis (far_m2 = 1 in 2D) */
   int far_fields;          /* far-slab fields: as n_fields, except Maxwell: 6, the tensor entries
                               GG_pq of the series (11 22 33 12 13 23; 13 and 23 for x3 > 0) */
+  int far_points;          /* interpolation points per axis on the far slab: 8, or 4 for complex64
+                              in 3D; slice s lies at |x_t| = c - (far_points/2 - 1) h_f + s h_f */
 } qpgf_plan_info;
 
 /* Fill *p with the defaults above for the given kind, precision and sizes. */

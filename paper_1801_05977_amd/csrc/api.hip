@@ -153,34 +153,37 @@ qpgf_status validate(const qpgf_params* p) {
 }  // namespace
 
 // Far-slab geometry (Algorithm 2.1 / 3.1 / 4.1 step 2b: the series on the slab, interpolated with
-// the 8-point rule).  The rule's error for a term of wavenumber q along an axis of spacing h is
-// about (q h)^8 / 1000: with h = 2 pi / Mf and the propagating terms (q <= k), Mf >= 2 pi k / x
-// keeps it near 1e-11 (complex128, x = 0.0977) or 1e-7 (complex64, x = 0.3); the evanescent terms
-// the series keeps at |x_t| >= c - 3 hf set the floors, hf <= 1/64 and 512 modes on the complex128
-// path (256 leave up to 4e-11 of |G_d| near |x3| = c at k = 3.7; 512 leave 6e-13), 256 on the complex64
-// path (measured against the direct sum of the series).  Slices z_s = c - 3 hf + s hf, s < S: a target at
-// |x_t| = z uses slices floor((z - z_0) / hf) - 3 .. + 4, so S = ceil((zmax - c) / hf) + 8 covers
-// every z <= zmax.  params.far_m and params.far_h override the modes and the spacing.
+// the P-point Lagrange rule per axis).  The rule's error for a term of wavenumber q along an axis of
+// spacing h is about C_P (q h)^P, C_8 = 1e-3, C_4 = 0.023: with h = 2 pi / Mf and the propagating terms
+// (q <= k), Mf >= 2 pi k / x keeps it near 1e-11 for complex128 (P = 8, x = 0.0977), 1e-7 for
+// complex64 in 2D (P = 8, x = 0.3) and 1e-6 for complex64 in 3D (P = 4, x = 0.081: 64 nodes per target
+// instead of 512).  The evanescent terms the series keeps just below c set the floors: hf <= 1/64, and
+// 512 modes (complex128; 256 leave up to 4e-11 of |G_d| next to |x3| = c at k = 3.7, 512 leave 6e-13)
+// or 256 (complex64 in 2D) or 512 (complex64 in 3D, the 4-point rule: 1.2e-7).  Slices
+// z_s = c - (P/2 - 1) hf + s hf, s < S: a target at |x_t| = z uses slices floor((z - z_0) / hf)
+// - (P/2 - 1) .. + P/2, so S = ceil((zmax - c) / hf) + P covers every z <= zmax.  params.far_m and
+// params.far_h override the modes and the spacing.
 FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
   const bool c128 = P.p.prec == QPGF_C128;
-  const double x = c128 ? 0.0977 : 0.3;
-  const int floor_m = c128 ? 512 : 256;
+  FarGeom g;
+  g.P = (P.dim == 3 && !c128) ? 4 : 8;
+  const double x = c128 ? 0.0977 : (g.P == 4 ? 0.081 : 0.3);
+  const int floor_m = (c128 || P.dim == 3) ? 512 : 256;
   const double want = 2.0 * M_PI * std::max(kmax, 0.0) / x;
   int mk = floor_m;
   while (mk < want && mk < 4096) mk <<= 1;
   const int cap = (P.dim == 3 && c128) ? 2048 : 4096;   // the 3D far slab's x2 axis is a column axis
-  FarGeom g;
   g.Mf1 = P.p.far_m ? P.p.far_m : std::min(std::max(M1, mk), 4096);
   g.Mf2 = P.dim == 3 ? (P.p.far_m ? P.p.far_m : std::min(std::max(P.M2, mk), cap)) : 1;
   if (P.p.far_h > 0.0) {
     g.hf = P.p.far_h;
   } else {
     double inv = 64.0;
-    const double need = std::max(kmax, 0.0) / x;
+    const double need = std::max(kmax, 0.0) / (c128 ? 0.107 : x);
     while (inv < need && inv < 4096.0) inv *= 2.0;
     g.hf = 1.0 / inv;
   }
-  g.S = (int)std::ceil((P.p.far_zmax - P.p.c) / g.hf - 1e-12) + kFarLo + 5;
+  g.S = (int)std::ceil((P.p.far_zmax - P.p.c) / g.hf - 1e-12) + g.P;
   return g;
 }
 
@@ -206,8 +209,9 @@ hipError_t set_far_geometry(Plan& P, double kmax) {
   P.Mf1 = g.Mf1;
   P.Mf2 = g.Mf2;
   P.S = g.S;
+  P.fp = g.P;
   P.hf = g.hf;
-  P.fz0 = P.p.c - kFarLo * g.hf;
+  P.fz0 = P.p.c - (g.P / 2 - 1) * g.hf;
   P.nfar = nfar;
   return hipSuccess;
 }
@@ -618,6 +622,7 @@ qpgf_status qpgf_plan_get_info(const qpgf_plan* plan, qpgf_plan_info* info) {
   info->far_m1 = P.Mf1;
   info->far_m2 = P.Mf2;
   info->far_fields = P.nfo;
+  info->far_points = P.fp;
   return QPGF_OK;
 }
 

@@ -1003,7 +1003,7 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, 
   I.Mf1 = fg.Mf1;
   I.Sf = fg.S;
   I.hf = fg.hf;
-  I.z0 = P.p.c - kFarLo * fg.hf;
+  I.z0 = P.p.c - (fg.P / 2 - 1) * fg.hf;
   I.off = off;
   I.foff = foff;
   I.blk0 = blk0;

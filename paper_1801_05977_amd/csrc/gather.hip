@@ -23,8 +23,9 @@ struct GArgs {
   double h1, h2, h3;       // 2D: h2 = transverse spacing
   double ih1, ih2, ih3;    // reciprocals of the spacings
   double hf, ihf;          // far-slab slice spacing and its reciprocal
-  double fz0;              // far-slab first slice, c - kFarLo hf
+  double fz0;              // far-slab first slice, c - (fp/2 - 1) hf
   int S;                   // far-slab slices
+  int fp;                  // far-slab interpolation points per axis (4 or 8)
   int Mf1, Mf2;            // far-slab periodic sizes (Mf2 = 1 in 2D)
   double ihf1, ihf2;       // reciprocals of the far slab's periodic spacings 2 pi / Mf
   long fs, ffs;            // field strides (near, far)
@@ -77,32 +78,38 @@ template <> __device__ __forceinline__ void store_out<float>(float2* p, long i, 
 
 __device__ __forceinline__ double2 nan2() { return mk(__builtin_nan(""), __builtin_nan("")); }
 
-// 8-point Lagrange weights at nodes -3 .. 4 for the fraction f in [0, 1) (the far branch):
-// w_m = prod_{n != m} (f - (n - 3)) / prod_{n != m} (m - n), products before and after m.
-template <typename W>
-__device__ __forceinline__ void lag8(W f, W w[8]) {
-  W g[8], pre[8], suf[8];
+// P-point Lagrange weights at nodes -(P/2 - 1) .. P/2 for the fraction f in [0, 1) (the far
+// branch): w_m = prod_{n != m} (f - node_n) / prod_{n != m} (node_m - node_n), products before and
+// after m; prod_{n != m} (m - n) = (-1)^(P-1-m) m! (P-1-m)!.
+template <int P>
+__host__ __device__ constexpr double lag_inv_den(int m) {
+  double d = 1.0;
+  for (int n = 0; n < P; ++n)
+    if (n != m) d *= (double)(m - n);
+  return 1.0 / d;
+}
+template <typename W, int P>
+__device__ __forceinline__ void lagp(W f, W w[P]) {
+  W g[P], pre[P], suf[P];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) g[m] = f + W(3 - m);
+  for (int m = 0; m < P; ++m) g[m] = f + W(P / 2 - 1 - m);
   pre[0] = W(1);
 #pragma unroll
-  for (int m = 1; m < 8; ++m) pre[m] = pre[m - 1] * g[m - 1];
-  suf[7] = W(1);
+  for (int m = 1; m < P; ++m) pre[m] = pre[m - 1] * g[m - 1];
+  suf[P - 1] = W(1);
 #pragma unroll
-  for (int m = 6; m >= 0; --m) suf[m] = suf[m + 1] * g[m + 1];
-  const W inv[8] = {W(-1.0 / 5040.0), W(1.0 / 720.0), W(-1.0 / 240.0), W(1.0 / 144.0),
-                    W(-1.0 / 144.0),  W(1.0 / 240.0), W(-1.0 / 720.0), W(1.0 / 5040.0)};
+  for (int m = P - 2; m >= 0; --m) suf[m] = suf[m + 1] * g[m + 1];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) w[m] = pre[m] * suf[m] * inv[m];
+  for (int m = 0; m < P; ++m) w[m] = pre[m] * suf[m] * W(lag_inv_den<P>(m));
 }
 
-// Far-slab slice stencil of |x_t| = z: base slice s0 = floor((z - fz0) / hf) (>= kFarLo for
-// z > c) and the fraction; false when the 8 slices s0 - 3 .. s0 + 4 leave the slab.
+// Far-slab slice stencil of |x_t| = z: base slice s0 = floor((z - fz0) / hf) (>= fp/2 - 1 for
+// z > c) and the fraction; false when the fp slices s0 - (fp/2 - 1) .. s0 + fp/2 leave the slab.
 __device__ __forceinline__ bool far_slice(const GArgs& A, double z, double& s0, double& f) {
   const double v = (z - A.fz0) * A.ihf;
   s0 = floor(v);
-  if (!(s0 <= A.S - 5)) return false;
-  s0 = fmax(s0, (double)kFarLo);
+  if (!(s0 <= A.S - 1 - A.fp / 2)) return false;
+  s0 = fmax(s0, (double)(A.fp / 2 - 1));
   f = v - s0;
   return true;
 }
@@ -246,53 +253,55 @@ __device__ __forceinline__ void near3_finish(const GArgs& A, double x1, double x
 // ---------------------------------------------------------------------------
 // The far slab holds the series on its own periodic grid (Mf1 x Mf2, spacings 2 pi / Mf)
 // at slices z_s = fz0 + s hf: G_d, or the six tensor entries GG_pq (13 and 23 for x3 > 0).
-template <typename T>
+// FP = far_points_3d<T>() interpolation points per axis.
+template <typename T, int FP = far_points_3d<T>()>
 struct Far3 {
   int p1, p2, s0;
-  T w1[8], w2[8], w3[8];
+  T w1[FP], w2[FP], w3[FP];
 };
 
 // false: |x3| beyond the slab
-template <typename T>
-__device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T>& s) {
+template <typename T, int FP = far_points_3d<T>()>
+__device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T, FP>& s) {
   double s0, f3;
   if (!far_slice(A, fabs(x3), s0, f3)) return false;
   double n;
   const double u1 = reduce_cell(x1, n) * A.ihf1, q1 = floor(u1);
   const double u2 = reduce_cell(x2, n) * A.ihf2, q2 = floor(u2);
-  lag8<T>((T)(u1 - q1), s.w1);
-  lag8<T>((T)(u2 - q2), s.w2);
-  lag8<T>((T)f3, s.w3);
+  lagp<T, FP>((T)(u1 - q1), s.w1);
+  lagp<T, FP>((T)(u2 - q2), s.w2);
+  lagp<T, FP>((T)f3, s.w3);
   s.p1 = (int)q1;
   s.p2 = (int)q2;
   s.s0 = (int)s0;
   return true;
 }
 
-// 512-point stencil sums of the NFO far fields from global memory.
-template <typename T, int NFO>
-__device__ __forceinline__ void far3_sum_global(const GArgs& A, const cplx<T>* __restrict__ far, const Far3<T>& s,
-                                                double2 L[NFO]) {
+// FP^3-point stencil sums of the NFO far fields from global memory.
+template <typename T, int NFO, int FP = far_points_3d<T>()>
+__device__ __forceinline__ void far3_sum_global(const GArgs& A, const cplx<T>* __restrict__ far,
+                                                const Far3<T, FP>& s, double2 L[NFO]) {
+  constexpr int LO = FP / 2 - 1;
   Acc<T> acc[NFO];
   // the slice loop stays rolled; its weight is the head of a copy shifted each step (static
   // indices only, so the weights stay in registers)
-  T w3[8];
+  T w3[FP];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) w3[m] = s.w3[m];
+  for (int m = 0; m < FP; ++m) w3[m] = s.w3[m];
 #pragma unroll 1
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < FP; ++c) {
     const T wc = w3[0];
 #pragma unroll
-    for (int m = 0; m < 7; ++m) w3[m] = w3[m + 1];
-    const long i3 = s.s0 - 3 + c;
+    for (int m = 0; m < FP - 1; ++m) w3[m] = w3[m + 1];
+    const long i3 = s.s0 - LO + c;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const long row = (i3 * A.Mf2 + ((s.p2 - 3 + b) & (A.Mf2 - 1))) * (long)A.Mf1;
+    for (int b = 0; b < FP; ++b) {
+      const long row = (i3 * A.Mf2 + ((s.p2 - LO + b) & (A.Mf2 - 1))) * (long)A.Mf1;
       const T wcb = wc * s.w2[b];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
+      for (int a = 0; a < FP; ++a) {
         const T w = wcb * s.w1[a];
-        const long o = row + ((s.p1 - 3 + a) & (A.Mf1 - 1));
+        const long o = row + ((s.p1 - LO + a) & (A.Mf1 - 1));
 #pragma unroll
         for (int f = 0; f < NFO; ++f) acc[f].add(w, far[f * A.ffs + o]);
       }
@@ -418,28 +427,28 @@ __device__ __forceinline__ double2 lds_sum(const cplx<T>* base, const T a1[4], c
   return mk((double)accx, (double)accy);
 }
 
-// 512-point stencil sum of one far field from an LDS footprint (rows of F1, F2 rows per slice).
-template <typename T, int F1, int F2>
-__device__ __forceinline__ double2 lds_sum8(const cplx<T>* base, const T a1[8], const T a2[8], const T a3[8]) {
+// FP^3-point stencil sum of one far field from an LDS footprint (rows of F1, F2 rows per slice).
+template <typename T, int F1, int F2, int FP>
+__device__ __forceinline__ double2 lds_sump(const cplx<T>* base, const T a1[FP], const T a2[FP], const T a3[FP]) {
   T accx = 0, accy = 0;
   // slices in a rolled loop (the slice weight shifted into place, as in far3_sum_global); rows and
   // nodes unrolled, so every LDS address is the slice base plus an immediate offset
-  T w3[8];
+  T w3[FP];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) w3[m] = a3[m];
+  for (int m = 0; m < FP; ++m) w3[m] = a3[m];
 #pragma unroll 1
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < FP; ++c) {
     const T wc = w3[0];
 #pragma unroll
-    for (int m = 0; m < 7; ++m) w3[m] = w3[m + 1];
+    for (int m = 0; m < FP - 1; ++m) w3[m] = w3[m + 1];
     const cplx<T>* slice = base + c * (F2 * F1);
     T px = 0, py = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < FP; ++b) {
       const cplx<T>* row = slice + b * F1;
       T rx = 0, ry = 0;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
+      for (int a = 0; a < FP; ++a) {
         const cplx<T> v = row[a];
         rx += a1[a] * v.x;
         ry += a1[a] * v.y;
@@ -589,10 +598,10 @@ __global__ __launch_bounds__(256) void k_gather3d_near_fields(GArgs A, TileArgs 
 }
 
 // Far tiles: one block per far key (keys nnear .. nnear + nfar - 1), and one more block for
-// the last key (non-finite and out-of-slab targets, evaluated from global memory).  The 8-point
-// footprint of one field is staged at a time: for one field (G_d) once per tile; for the six
-// Maxwell entries field by field for each pass of BS targets, whose sums stay in registers.
-template <typename T, int NF, int FB1, int FB2, int FB3, int BS>
+// the last key (non-finite and out-of-slab targets: NaN).  The FP-point footprint of one field is
+// staged at a time: for one field (G_d) once per tile; for the six Maxwell entries field by field
+// for each pass of BS targets, whose sums stay in registers.
+template <typename T, int NF, int FB1, int FB2, int FB3, int BS, int FP = far_points_3d<T>()>
 __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
                                                       const cplx<T>* __restrict__ far,
                                                       const TRec* __restrict__ rec,
@@ -600,7 +609,8 @@ __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const 
                                                       const uint32_t* __restrict__ offs,
                                                       cplx<T>* __restrict__ out, uint8_t* __restrict__ flags,
                                                       uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
-  constexpr int F1 = (1 << FB1) + 7, F2 = (1 << FB2) + 7, F3 = (1 << FB3) + 7;
+  constexpr int F1 = (1 << FB1) + FP - 1, F2 = (1 << FB2) + FP - 1, F3 = (1 << FB3) + FP - 1;
+  constexpr int LO = FP / 2 - 1;
   constexpr int NO = NOut<NF>::v;
   __shared__ cplx<T> lds[F1 * F2 * F3];
   const int key = B.nnear + (int)blockIdx.x;
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const 
   }
   const int kk = key - B.nnear;
   const int b1 = kk % B.fnt1, b2 = (kk / B.fnt1) % B.fnt2, b3 = kk / (B.fnt1 * B.fnt2);
-  const int o1 = (b1 << FB1) - 3, o2 = (b2 << FB2) - 3, o3 = (b3 << FB3) - 3;
+  const int o1 = (b1 << FB1) - LO, o2 = (b2 << FB2) - LO, o3 = (b3 << FB3) - LO;
   if (NO == 1) {
     stage_far<T, F1, F2, F3>(A, far, o1, o2, o3, lds);
     __syncthreads();
@@ -629,16 +639,16 @@ __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const 
     const long j = start + c0 + threadIdx.x;
     const bool valid = c0 + (long)threadIdx.x < (long)cnt;
     TRec r{};
-    Far3<T> s;
+    Far3<T, FP> s;
     bool miss = false;
     int l1 = 0, l2 = 0, l3 = 0;
     if (valid) {
       r = rec[j];
-      miss = !far3_stencil<T>(A, r.x, r.y, r.z, s);
-      l1 = (s.p1 - 3 - o1) & (A.Mf1 - 1);
-      l2 = (s.p2 - 3 - o2) & (A.Mf2 - 1);
-      l3 = s.s0 - 3 - o3;
-      miss = miss || l1 > F1 - 8 || l2 > F2 - 8 || l3 < 0 || l3 > F3 - 8;
+      miss = !far3_stencil<T, FP>(A, r.x, r.y, r.z, s);
+      l1 = (s.p1 - LO - o1) & (A.Mf1 - 1);
+      l2 = (s.p2 - LO - o2) & (A.Mf2 - 1);
+      l3 = s.s0 - LO - o3;
+      miss = miss || l1 > F1 - FP || l2 > F2 - FP || l3 < 0 || l3 > F3 - FP;
     }
     double2 L[NO];
 #pragma unroll
@@ -648,7 +658,7 @@ __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const 
         stage_far<T, F1, F2, F3>(A, far + f * A.ffs, o1, o2, o3, lds);
         __syncthreads();
       }
-      if (valid && !miss) L[f] = lds_sum8<T, F1, F2>(lds + (l3 * F2 + l2) * F1 + l1, s.w1, s.w2, s.w3);
+      if (valid && !miss) L[f] = lds_sump<T, F1, F2, FP>(lds + (l3 * F2 + l2) * F1 + l1, s.w1, s.w2, s.w3);
     }
     if (!valid) continue;
     if (miss) {
@@ -850,8 +860,8 @@ __device__ __forceinline__ bool far2d_sum(const GArgs& A, const cplx<T>* __restr
   if (!far_slice(A, z, s0, f2)) return false;
   T w1[8], w2[8];
   const double u = t * A.ihf1, p = floor(u);
-  lag8<T>((T)(u - p), w1);
-  lag8<T>((T)f2, w2);
+  lagp<T, 8>((T)(u - p), w1);
+  lagp<T, 8>((T)f2, w2);
   const int i0 = (int)p - 3;
   const long r0 = (long)s0 - 3;
   Acc<T> acc[NF];
@@ -1312,6 +1322,7 @@ struct BinArgs {
   double c, ih1, ih2, ih3;
   double fz0, ihf, ihf1, ihf2;   // far slab: first slice, reciprocal spacings
   int M1, M2, M3, S, Mf1, Mf2;
+  int fp;                        // far-slab interpolation points per axis
   TileArgs t;
 };
 
@@ -1328,8 +1339,8 @@ __device__ __forceinline__ uint32_t tile_key(const BinArgs& B, double x1, double
     return (uint32_t)((b3 * B.t.nt2 + b2) * B.t.nt1 + b1);
   }
   double s0 = floor((fabs(x3) - B.fz0) * B.ihf);
-  if (!(s0 <= B.S - 5)) return B.t.nkeys - 1;
-  s0 = fmax(s0, (double)kFarLo);
+  if (!(s0 <= B.S - 1 - B.fp / 2)) return B.t.nkeys - 1;
+  s0 = fmax(s0, (double)(B.fp / 2 - 1));
   const int b1 = (((int)floor(t1 * B.ihf1)) & (B.Mf1 - 1)) >> B.t.ftb1;
   const int b2 = (((int)floor(t2 * B.ihf2)) & (B.Mf2 - 1)) >> B.t.ftb2;
   const int b3 = (int)s0 >> B.t.ftb3;
@@ -1552,6 +1563,7 @@ GArgs make_gargs(const Plan& P, int smooth) {
   A.ihf = 1.0 / P.hf;
   A.fz0 = P.fz0;
   A.S = P.S;
+  A.fp = P.fp;
   A.Mf1 = P.Mf1;
   A.Mf2 = P.Mf2;
   A.ihf1 = P.Mf1 / (2.0 * kPi);
@@ -1640,6 +1652,8 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   B.S = P.S;
   B.Mf1 = P.Mf1;
   B.Mf2 = P.Mf2;
+  B.fp = P.fp;
+  if (P.fp != far_points_3d<T>()) return hipErrorInvalidValue;
   // Near tiles.  One field: 16 x 16 x 8 nodes (several 256-thread blocks per CU, so one
   // block's staging overlaps the others' interpolation), or, when that leaves fewer than
   // kMinPerTile targets per tile on average (fine grids), 32 x 32 x 8 (complex64, 108 KiB,
@@ -1685,7 +1699,7 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
       Tl.ftb3 = 3;
       Tl.fnt1 = std::max(1, P.Mf1 >> Tl.ftb1);
       Tl.fnt2 = std::max(1, P.Mf2 >> Tl.ftb2);
-      Tl.fnt3 = ((P.S - 5) >> Tl.ftb3) + 1;
+      Tl.fnt3 = ((P.S - 1 - P.fp / 2) >> Tl.ftb3) + 1;
       Tl.nfar = Tl.fnt1 * Tl.fnt2 * Tl.fnt3;
       Tl.nkeys = Tl.nnear + Tl.nfar + 1;
     };
@@ -1880,7 +1894,8 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg
   A.S = fg.S;
   A.hf = fg.hf;
   A.ihf = 1.0 / fg.hf;
-  A.fz0 = P.p.c - kFarLo * fg.hf;
+  A.fp = fg.P;
+  A.fz0 = P.p.c - (fg.P / 2 - 1) * fg.hf;
   A.fs = (long)M1 * P.M2;
   A.ffs = (long)fg.Mf1 * fg.S;
   A.quad = 0;   // the batched graph keeps the instances' grids row by row (node quads of all

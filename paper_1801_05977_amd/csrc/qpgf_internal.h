@@ -23,10 +23,10 @@ namespace qpgf {
 constexpr int kMxF = 7;
 constexpr int kMxT = 6;
 constexpr int kMxO = 6;
-// Far branch: the far slab is interpolated with the 8-point Lagrange rule per axis, nodes
-// base - 3 .. base + 4; its first slice lies kFarLo spacings below c.
-constexpr int kFarP = 8;
-constexpr int kFarLo = 3;
+// Far branch: the far slab is interpolated with the P-point Lagrange rule per axis (nodes
+// base - (P/2 - 1) .. base + P/2; its first slice lies P/2 - 1 spacings below c): P = 8 in 2D and
+// for complex128 in 3D, P = 4 for complex64 in 3D (on a finer slab).
+template <typename T> constexpr int far_points_3d() { return sizeof(T) == 4 ? 4 : 8; }
 
 template <typename T> struct C2;
 template <> struct C2<double> { using type = double2; };
@@ -122,7 +122,8 @@ struct Plan {
   int S = 0;                   // far-slab slices
   int Mf1 = 0, Mf2 = 1;        // far-slab modes per periodic axis (Mf2 = 1 in 2D)
   int nfo = 1;                 // far-slab fields (kMxO for Maxwell, else nf)
-  double hf = 0.0, fz0 = 0.0;  // far-slab slice spacing and first slice c - kFarLo hf
+  int fp = 8;                  // far-slab interpolation points per axis
+  double hf = 0.0, fz0 = 0.0;  // far-slab slice spacing and first slice c - (fp/2 - 1) hf
   size_t far_cap = 0;          // bytes allocated for the far slab (grown when an instance needs more)
   size_t ncell = 0;            // points per near field
   size_t nfar = 0;             // points per far field
@@ -229,6 +230,7 @@ struct KernelTimer {
 // (3D) near sizes are M1 (and P.M2): modes per periodic axis and slice spacing (api.hip).
 struct FarGeom {
   int Mf1, Mf2, S;
+  int P;          // interpolation points per axis
   double hf;
 };
 FarGeom far_geometry(const Plan& P, double kmax, int M1);

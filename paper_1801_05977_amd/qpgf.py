@@ -40,7 +40,8 @@ class PlanInfo(ctypes.Structure):
                 ("m3", ctypes.c_int), ("far_slices", ctypes.c_int), ("far_h", ctypes.c_double),
                 ("c", ctypes.c_double), ("c_tilde", ctypes.c_double), ("eps", ctypes.c_double),
                 ("n_fields", ctypes.c_int), ("grid_bytes", ctypes.c_size_t), ("far_grid_bytes", ctypes.c_size_t),
-                ("far_m1", ctypes.c_int), ("far_m2", ctypes.c_int), ("far_fields", ctypes.c_int)]
+                ("far_m1", ctypes.c_int), ("far_m2", ctypes.c_int), ("far_fields", ctypes.c_int),
+                ("far_points", ctypes.c_int)]
 
 
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",

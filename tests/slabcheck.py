@@ -2,7 +2,7 @@
 
 A far-slab value times the phase e^{i alpha.x'} is the eigenfunction series at that node
 (Algorithms 2.1 / 3.1 / 4.1 step 2b), so sampled nodes are compared with the direct sum of the
-series (``oracle.truth``): slice s lies at |x_t| = c - 3 h_f + s h_f, x1 node p (FFT order) at
+series (``oracle.truth``): slice s lies at |x_t| = c - (P/2 - 1) h_f + s h_f (P = far_points), x1 node p (FFT order) at
 2 pi p / far_m1 (centred p), likewise x2 in 3D.
 """
 
@@ -23,7 +23,7 @@ def nodes_2d(info, n, seed):
     s = rng.integers(0, info.far_slices, n)
     p = rng.integers(0, info.far_m1, n)
     x1 = 2 * math.pi * _centred(p, info.far_m1) / info.far_m1
-    z = info.c - 3 * info.far_h + s * info.far_h
+    z = info.c - (info.far_points // 2 - 1) * info.far_h + s * info.far_h
     return (s, p), np.stack([x1, z], axis=1)
 
 
@@ -34,7 +34,7 @@ def nodes_3d(info, n, seed):
     p = rng.integers(0, info.far_m1, n)
     x1 = 2 * math.pi * _centred(p, info.far_m1) / info.far_m1
     x2 = 2 * math.pi * _centred(q, info.far_m2) / info.far_m2
-    z = info.c - 3 * info.far_h + s * info.far_h
+    z = info.c - (info.far_points // 2 - 1) * info.far_h + s * info.far_h
     return (s, q, p), np.stack([x1, x2, z], axis=1)
 
 
@@ -52,6 +52,6 @@ def rel(g, o):
 
 
 def limit(info):
-    """Smallest |x_t| beyond the far slab (flag bit 2): the 8 slices from floor((z - fz0)/hf) - 3 must
-    stay below S, fz0 = c - 3 hf."""
-    return info.c + (info.far_slices - 7) * info.far_h
+    """Smallest |x_t| beyond the far slab (flag bit 2): the P slices from floor((z - z0)/hf) - (P/2 - 1)
+    must stay below S, z0 = c - (P/2 - 1) hf, P = far_points."""
+    return info.c + (info.far_slices - info.far_points + 1) * info.far_h

@@ -38,14 +38,14 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(qpgf_params, lattice_rmin), sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes),"
         " offsetof(qpgf_params, quad_q), offsetof(qpgf_params, sing_order), offsetof(qpgf_params, far_m),"
         " offsetof(qpgf_params, maxwell_trace), offsetof(qpgf_plan_info, far_m1),"
-        " offsetof(qpgf_plan_info, far_fields));return 0;}\n")
+        " offsetof(qpgf_plan_info, far_points));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(qpgf.Params), qpgf.Params.lattice_rmin.offset, ctypes.sizeof(qpgf.PlanInfo),
             qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset, qpgf.Params.sing_order.offset,
             qpgf.Params.far_m.offset, qpgf.Params.maxwell_trace.offset, qpgf.PlanInfo.far_m1.offset,
-            qpgf.PlanInfo.far_fields.offset]
+            qpgf.PlanInfo.far_points.offset]
     assert got == want
 
 

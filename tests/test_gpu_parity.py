@@ -82,8 +82,8 @@ def test_fill3d_and_grid3d_stages(prec):
     tol = 1e-12 if prec == qpgf.C128 else 2e-6
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
     # far slab: at its nodes the series (1.3) itself
-    mf = 512 if prec == qpgf.C128 else 256
-    assert (P.info.far_m1, P.info.far_m2, P.info.far_fields) == (mf, mf, 1)
+    assert (P.info.far_m1, P.info.far_m2, P.info.far_fields) == (512, 512, 1)
+    assert P.info.far_points == (8 if prec == qpgf.C128 else 4)
     idx, pts = slabcheck.nodes_3d(P.info, 30, seed=2)
     ref_F = truth.gd3d(k, a1, a2, pts) * np.exp(-1j * (a1 * pts[:, 0] + a2 * pts[:, 1]))
     assert slabcheck.rel(slabcheck.slab_3d(P)[idx], ref_F) <= tol
@@ -158,7 +158,7 @@ def test_maxwell_stages(prec):
     k, a1, a2 = 5.3, 0.1, 0.4
     P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3)
     assert (P.info.n_fields, P.info.far_fields) == (7, 6)
-    assert P.info.far_m1 == (512 if prec == qpgf.C128 else 256)
+    assert P.info.far_m1 == 512
     L = method.lhat_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2)
     refs = [A3 * L] + [A3 * m * L for m in method.maxwell_multipliers(a1, a2, M1 // 2, M2 // 2, M3 // 2)]
     P.prepare(k, a1, a2, stage=0)
