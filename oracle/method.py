@@ -362,6 +362,20 @@ def _psi_derivs(k, r, eps):
     return g * y, g1 * y + g * y1, g2 * y + 2 * g1 * y1 + g * y2
 
 
+def singular_part_3d(k, t, eps=co.EPS, pairs=FIELD_PAIRS):
+    """The removed singular part F = psi (Section 3.2) at cell offsets t [T,3] and its second
+    derivatives d_p d_q psi = psi'' t_p t_q / r^2 + psi' (delta_pq / r - t_p t_q / r^3) for the given
+    pairs (the F^{pq} of Section 4): returns (psi [T], {pair: [T]})."""
+    t = np.atleast_2d(np.asarray(t, dtype=np.float64))
+    r = np.linalg.norm(t, axis=1)
+    psi, d1, d2 = _psi_derivs(k, r, eps)
+    hess = {}
+    for p, q in pairs:
+        tp, tq = t[:, p], t[:, q]
+        hess[(p, q)] = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == q else 0.0) / r - tp * tq / r ** 3)
+    return psi, hess
+
+
 def prepare_3d(k, a1, a2, N1, N2, N3, maxwell=False, trace33=False, c=co.C, c_tilde=co.C_TILDE,
                eps=co.EPS, q=ORACLE_Q):
     """Algorithm 3.1 / 4.1 step 1: the near grids (L_d; for Maxwell also the six fields L^{pq},
@@ -397,8 +411,7 @@ def evaluate_3d(st, x):
         i3, w3 = _stencil((x3[near] + c_tilde) / h3, M3)
         Ls = _interp3(grids, i1, w1, i2, w2, i3, w3)
         tt = np.stack([t1[near], t2[near], x3[near]], axis=1)
-        r = np.linalg.norm(tt, axis=1)
-        psi, d1, d2 = _psi_derivs(k, r, eps)
+        psi, hess = singular_part_3d(k, tt, eps, pairs)
         phase = np.exp(1j * (a1 * x[near, 0] + a2 * x[near, 1]))
         lat = np.exp(2j * math.pi * (a1 * n1[near] + a2 * n2[near]))
         # steps 2e/2g: G_d = e^{i alpha.x'} (L_dN + F); steps 2f/2h: d_p d_q G_d likewise with F^{pq}
@@ -407,10 +420,8 @@ def evaluate_3d(st, x):
             out[near, 0] = G
         else:
             dd = {}
-            for f, (p, qq) in enumerate(pairs):
-                tp, tq = tt[:, p], tt[:, qq]
-                hess = d2 * tp * tq / r ** 2 + d1 * ((1.0 if p == qq else 0.0) / r - tp * tq / r ** 3)
-                dd[(p, qq)] = phase * Ls[f + 1] + lat * hess
+            for f, pq in enumerate(pairs):
+                dd[pq] = phase * Ls[f + 1] + lat * hess[pq]
             out[near] = _assemble(k, G, dd)
     far = ~near
     if far.any():

@@ -318,6 +318,26 @@ def test_maxwell_method_against_truth():
     assert rel[1] < 2e-3 and rel[1] < rel[0] / 4
 
 
+@pytest.mark.slow
+def test_maxwell_trace_option_against_truth():
+    # The trace variant (a Section 4 option, not Algorithm 4.1): GG_33 = 2 G_d - GG_11 - GG_22 in place
+    # of the interpolated 33 field.  Away from the cut-off shell it converges to the lattice sums like
+    # the seven-field path, its 33 entry agrees with that path's to the method's error, and its trace
+    # is 2 G_d by construction.
+    x = np.array([[0.9, -0.7, 0.3], [2.0, 1.0, 0.8], [0.5, 0.4, -0.7]])
+    gt = truth.maxwell3d(K3, A31, A32, x)
+    rel, d33 = [], []
+    for N in (32, 48):
+        g = method.eval_maxwell3d(K3, A31, A32, x, N, N, N, trace33=True)
+        g7 = method.eval_maxwell3d(K3, A31, A32, x, N, N, N)
+        rel.append((np.abs(g - gt).max(axis=1) / np.abs(gt).max(axis=1)).max())
+        d33.append(np.max(np.abs(g[:, 2] - g7[:, 2]) / np.abs(gt).max(axis=1)))
+        gd = method.eval_gd3d(K3, A31, A32, x, N, N, N)
+        np.testing.assert_allclose(g[:, 0] + g[:, 1] + g[:, 2], 2 * gd, rtol=1e-12, atol=0)
+    assert rel[1] < 2e-3 and rel[1] < rel[0] / 4
+    assert d33[1] < 2e-3 and d33[1] < d33[0]
+
+
 def test_far_branch_is_the_series():
     # Algorithms 2.1, 3.1, 4.1 step 2b: beyond |x_t| = c the series itself, (1.2), (1.3) and (1.3)
     # differentiated term by term; |x_t| = c exactly is near (R8).
