@@ -68,7 +68,9 @@ typedef enum {
   QPGF_E_SIZE = 4,         /* unsupported grid size                                      */
   QPGF_E_HIP = 5,          /* a HIP runtime call failed                                  */
   QPGF_E_NOMEM = 6,        /* device allocation failed                                   */
-  QPGF_E_UNSUPPORTED = 7
+  QPGF_E_UNSUPPORTED = 7,
+  QPGF_E_IO = 8            /* a checkpoint file could not be opened, read or written, or
+                              is not a checkpoint of this model                          */
 } qpgf_status;
 
 typedef enum { QPGF_C128 = 0, QPGF_C64 = 1 } qpgf_prec;
@@ -312,11 +314,62 @@ qpgf_status qpgf_mlp_gradient(qpgf_mlp* m, int member, const double* q, const fl
 qpgf_status qpgf_mlp_train_step(qpgf_mlp* m, int member, const double* q, const float* y, int64_t B, float lr,
                                 float* loss);
 const char* qpgf_mlp_last_error(void);
+/* The error estimate of the surrogate is the ensemble spread s (largest distance
+ * of a member's L_d from the mean) times a calibration factor kappa fitted
+ * against the plain method: a value is accepted only if kappa s <= tol |G_d|.
+ * A new model has kappa = +inf and accepts nothing until calibrated (or until
+ * a checkpoint with a finite kappa is loaded); kappa is not applied to models
+ * of one member, which accept nothing.  set: kappa > 0 (+inf allowed). */
+qpgf_status qpgf_mlp_set_calibration(qpgf_mlp* m, double kappa);
+qpgf_status qpgf_mlp_get_calibration(const qpgf_mlp* m, double* kappa);
+/* Training rows from the plain method: for instance i (host k, a1, a2, t_off as
+ * in qpgf_g2d_batched) prepare `plan` (GD3D, c = 0.6, c~ = 1) and evaluate the
+ * interpolated smooth part L_N (qpgf_evaluate_smooth) at device targets
+ * x[t_off[i]..t_off[i+1])[3]; write q (device float64 [T][6]: x, k, alpha1,
+ * alpha2) and y (device float32 [T][2]: 10 Re L_N, 10 Im L_N).  Runs on the
+ * model's stream and synchronises it.  Errors: E_ARG, E_WOOD (the message
+ * names the instance), E_SIZE, E_HIP/E_NOMEM. */
+qpgf_status qpgf_surrogate_make_data(qpgf_mlp* m, qpgf_plan* plan, int n_inst, const double* k, const double* a1,
+                                     const double* a2, const int64_t* t_off, const double* x, double* q, float* y);
+typedef struct qpgf_train_cfg {
+  int64_t batch;     /* rows per Adam step: a multiple of 64, <= the model's max_batch */
+  int64_t steps;     /* Adam steps per member */
+  float lr_max;      /* cosine schedule: lr_min + (lr_max - lr_min)(1 + cos(pi t / steps)) / 2 */
+  float lr_min;
+  int32_t member;    /* the member to train, or -1 for every member in turn */
+  int32_t reserved;  /* 0 */
+  uint64_t seed;     /* data order: a fresh shuffle of the N rows per epoch, per member */
+} qpgf_train_cfg;
+/* Adam on the squared loss over device rows q [N][6], y [N][2] (as written by
+ * qpgf_surrogate_make_data), minibatches drawn without replacement.  The Adam
+ * step counts continue from the model's (so a loaded checkpoint resumes).
+ * loss: device float32 [members] or NULL, the last minibatch's loss of each
+ * trained member.  Synchronises the model's stream before returning. */
+qpgf_status qpgf_surrogate_train(qpgf_mlp* m, const double* q, const float* y, int64_t N, const qpgf_train_cfg* cfg,
+                                 float* loss);
+/* Fit kappa on held-out instances: for every near target (|x3| <= 0.6) of
+ * instance i the ratio |L_mean - L_N| / s against the plain method's smooth
+ * part of `plan`; kappa = safety times the `quantile` (0 < quantile <= 1; 1 =
+ * the largest) of those ratios, stored in the model and returned in *kappa
+ * (host, may be NULL).  Needs at least two members.  Allocates its scratch
+ * (T complex values and T doubles).  Errors as qpgf_surrogate_make_data. */
+qpgf_status qpgf_surrogate_calibrate(qpgf_mlp* m, qpgf_plan* plan, int n_inst, const double* k, const double* a1,
+                                     const double* a2, const int64_t* t_off, const double* x, double quantile,
+                                     double safety, double* kappa);
+/* Checkpoints: every member's float32 parameters, both Adam moments and step
+ * count, and kappa, in one binary file ("QPGFMLP1", int32 members, int64
+ * param_count, float64 kappa, then per member int64 step and 3 param_count
+ * float32: parameters, first moment, second moment; little-endian).  load
+ * requires a file of a model with the same number of members and leaves the
+ * model unchanged when the file is not such a checkpoint (E_IO). */
+qpgf_status qpgf_mlp_save(qpgf_mlp* m, const char* path);
+qpgf_status qpgf_mlp_load(qpgf_mlp* m, const char* path);
 /* G_d from the surrogate for n_inst instances (host k, a1, a2, t_off as in
  * qpgf_g2d_batched; device targets x [t_off[n]][3]) with fallback: a target takes
  * the plain method (the GD3D plan `plan`, whose precision sets out's type) when it
- * is far (|x3| > 0.6, flag 2), when the ensemble spread of L_d exceeds tol (flag 4),
- * when its instance is within wood_tol of a Wood anomaly (flag 8), or within
+ * is far (|x3| > 0.6, flag 2), when the calibrated error estimate exceeds tol
+ * |G_d| or the model is uncalibrated (flag 4), when its instance is within
+ * wood_tol of a Wood anomaly (flag 8), or within
  * rmin of a lattice point (flag 16).  fell_back: device uint8 [T] of those flags
  * (0 = surrogate value); *n_fallback (host, may be NULL) receives their count.
  * Synchronises the model's stream once (to size the fallback work) and sets the

@@ -416,39 +416,46 @@ __device__ double wood_distance(double k, double a1, double a2) {
   return best;
 }
 
-// Combine the ensemble (outputs y_e = 10 L_d per member) into G_d with the FP64
-// add-back, and decide fallback: far branch, Wood anomaly, lattice proximity,
-// or member spread above tol.
-template <typename T>
-__global__ void k_surrogate_combine(const double* __restrict__ q, long M, const float* __restrict__ y, int members,
-                                    long ystride, double c, double eps, double tol, double wood_tol, double rmin,
-                                    cplx<T>* __restrict__ out, uint8_t* __restrict__ fell) {
-  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const double* Q = q + 6 * m;
-  const double x1 = Q[0], x2 = Q[1], x3 = Q[2], k = Q[3], a1 = Q[4], a2 = Q[5];
-  double n1 = floor((x1 + kPi) * (0.5 / kPi)), n2 = floor((x2 + kPi) * (0.5 / kPi));
-  const double t1 = x1 - 2.0 * kPi * n1, t2 = x2 - 2.0 * kPi * n2;
-  double mr = 0.0, mi = 0.0;
+// Ensemble mean of L_d (the outputs are 10 L_d) and its spread: the largest distance of a member
+// from the mean.
+__device__ inline void ensemble_stats(const float* __restrict__ y, int members, long ystride, long m, double& mr,
+                                      double& mi, double& spread) {
+  mr = 0.0;
+  mi = 0.0;
   for (int e = 0; e < members; ++e) {
     mr += y[e * ystride + 2 * m];
     mi += y[e * ystride + 2 * m + 1];
   }
   mr /= members;
   mi /= members;
-  double spread = 0.0;
+  spread = 0.0;
   for (int e = 0; e < members; ++e) {
     const double dr = y[e * ystride + 2 * m] - mr, di = y[e * ystride + 2 * m + 1] - mi;
     spread = fmax(spread, sqrt(dr * dr + di * di));
   }
-  const double2 L = mk(0.1 * mr, 0.1 * mi);
+  mr *= 0.1;
+  mi *= 0.1;
   spread *= 0.1;
+}
+
+// Combine the ensemble into G_d with the FP64 add-back, and decide fallback: far branch, Wood
+// anomaly, lattice proximity, or an error estimate kappa * spread above tol |G_d|.  kappa comes from
+// calibration against the plain method; it is +inf until then (and the estimate is not formed with
+// fewer than two members), so an uncalibrated model accepts nothing.
+template <typename T>
+__global__ void k_surrogate_combine(const double* __restrict__ q, long M, const float* __restrict__ y, int members,
+                                    long ystride, double c, double eps, double tol, double kappa, double wood_tol,
+                                    double rmin, cplx<T>* __restrict__ out, uint8_t* __restrict__ fell) {
+  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const double* Q = q + 6 * m;
+  const double x1 = Q[0], x2 = Q[1], x3 = Q[2], k = Q[3], a1 = Q[4], a2 = Q[5];
+  double n1 = floor((x1 + kPi) * (0.5 / kPi)), n2 = floor((x2 + kPi) * (0.5 / kPi));
+  const double t1 = x1 - 2.0 * kPi * n1, t2 = x2 - 2.0 * kPi * n2;
+  double mr, mi, spread;
+  ensemble_stats(y, members, ystride, m, mr, mi, spread);
+  const double2 L = mk(mr, mi);
   const double r = sqrt(t1 * t1 + t2 * t2 + x3 * x3);
-  uint8_t fb = 0;
-  if (!(fabs(x3) <= c)) fb |= 2;
-  if (spread > tol) fb |= 4;
-  if (wood_distance(k, a1, a2) < wood_tol) fb |= 8;
-  if (r <= rmin) fb |= 16;
   double ps, pc;
   sincos(a1 * x1 + a2 * x2, &ps, &pc);
   double2 G = cmul(mk(pc, ps), L);
@@ -460,11 +467,61 @@ __global__ void k_surrogate_combine(const double* __restrict__ q, long M, const 
     const double s = cut_Y(r, eps) / (4.0 * kPi * r);
     G = cadd(G, cmul(mk(lc, ls), mk(cn * s, sn * s)));
   }
+  uint8_t fb = 0;
+  if (!(fabs(x3) <= c)) fb |= 2;
+  if (!(members >= 2 && kappa * spread <= tol * sqrt(G.x * G.x + G.y * G.y))) fb |= 4;
+  if (wood_distance(k, a1, a2) < wood_tol) fb |= 8;
+  if (r <= rmin) fb |= 16;
   cplx<T> v;
   v.x = (T)G.x;
   v.y = (T)G.y;
   out[m] = v;
   fell[m] = fb;
+}
+
+// Calibration: ratio[m] = |L_mean - L| / spread against the plain method's smooth part L (NaN where
+// L is NaN, i.e. far targets; +inf where the members agree exactly but the mean is off).
+template <typename T>
+__global__ void k_calib_ratio(long M, const float* __restrict__ y, int members, long ystride,
+                              const cplx<T>* __restrict__ Lp, double* __restrict__ ratio) {
+  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double mr, mi, spread;
+  ensemble_stats(y, members, ystride, m, mr, mi, spread);
+  const cplx<T> l = Lp[m];
+  const double dr = mr - (double)l.x, di = mi - (double)l.y;
+  const double err = sqrt(dr * dr + di * di);
+  ratio[m] = err != err ? err : (spread > 0.0 ? err / spread : (err > 0.0 ? __builtin_inf() : 0.0));
+}
+
+// Training rows of one instance: q = (x, k, alpha1, alpha2), y = 10 L (float32).
+template <typename T>
+__global__ void k_make_rows(const double* __restrict__ x, long n, double k, double a1, double a2,
+                            const cplx<T>* __restrict__ Lp, double* __restrict__ q, float* __restrict__ y) {
+  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double* Q = q + 6 * m;
+  Q[0] = x[3 * m];
+  Q[1] = x[3 * m + 1];
+  Q[2] = x[3 * m + 2];
+  Q[3] = k;
+  Q[4] = a1;
+  Q[5] = a2;
+  const cplx<T> l = Lp[m];
+  y[2 * m] = (float)(10.0 * (double)l.x);
+  y[2 * m + 1] = (float)(10.0 * (double)l.y);
+}
+
+// One minibatch: rows idx[0..B) of (q, y) side by side.
+__global__ void k_gather_rows(const double* __restrict__ q, const float* __restrict__ y,
+                              const uint32_t* __restrict__ idx, long B, double* __restrict__ qb,
+                              float* __restrict__ yb) {
+  const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= B) return;
+  const long r = idx[m];
+  for (int j = 0; j < 6; ++j) qb[6 * m + j] = q[6 * r + j];
+  yb[2 * m] = y[2 * r];
+  yb[2 * m + 1] = y[2 * r + 1];
 }
 
 }  // namespace
@@ -564,13 +621,39 @@ hipError_t mlp_make_queries(hipStream_t st, const void* inst, int n, const doubl
   return hipGetLastError();
 }
 hipError_t mlp_combine(hipStream_t st, int prec, const double* q, long M, const float* y, int members, long ystride,
-                       double c, double eps, double tol, double wood_tol, double rmin, void* out, uint8_t* fell) {
+                       double c, double eps, double tol, double kappa, double wood_tol, double rmin, void* out,
+                       uint8_t* fell) {
   if (prec == QPGF_C128)
     hipLaunchKernelGGL(k_surrogate_combine<double>, dim3(nb(M)), dim3(256), 0, st, q, M, y, members, ystride, c, eps,
-                       tol, wood_tol, rmin, static_cast<double2*>(out), fell);
+                       tol, kappa, wood_tol, rmin, static_cast<double2*>(out), fell);
   else
     hipLaunchKernelGGL(k_surrogate_combine<float>, dim3(nb(M)), dim3(256), 0, st, q, M, y, members, ystride, c, eps,
-                       tol, wood_tol, rmin, static_cast<float2*>(out), fell);
+                       tol, kappa, wood_tol, rmin, static_cast<float2*>(out), fell);
+  return hipGetLastError();
+}
+hipError_t mlp_calib_ratio(hipStream_t st, int prec, long M, const float* y, int members, long ystride, const void* L,
+                           double* ratio) {
+  if (prec == QPGF_C128)
+    hipLaunchKernelGGL(k_calib_ratio<double>, dim3(nb(M)), dim3(256), 0, st, M, y, members, ystride,
+                       static_cast<const double2*>(L), ratio);
+  else
+    hipLaunchKernelGGL(k_calib_ratio<float>, dim3(nb(M)), dim3(256), 0, st, M, y, members, ystride,
+                       static_cast<const float2*>(L), ratio);
+  return hipGetLastError();
+}
+hipError_t mlp_make_rows(hipStream_t st, int prec, const double* x, long n, double k, double a1, double a2,
+                         const void* L, double* q, float* y) {
+  if (prec == QPGF_C128)
+    hipLaunchKernelGGL(k_make_rows<double>, dim3(nb(n)), dim3(256), 0, st, x, n, k, a1, a2,
+                       static_cast<const double2*>(L), q, y);
+  else
+    hipLaunchKernelGGL(k_make_rows<float>, dim3(nb(n)), dim3(256), 0, st, x, n, k, a1, a2,
+                       static_cast<const float2*>(L), q, y);
+  return hipGetLastError();
+}
+hipError_t mlp_gather_rows(hipStream_t st, const double* q, const float* y, const uint32_t* idx, long B, double* qb,
+                           float* yb) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(nb(B)), dim3(256), 0, st, q, y, idx, B, qb, yb);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C ABI of the MLP surrogate: model state, training step (forward, backward,
 // Adam), inference for many instances with fallback to the plain method.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -29,7 +30,14 @@ size_t mlp_qinst_t0_offset();
 void mlp_qinst(double k, double a1, double a2, long t0, long t1, void* dst);
 hipError_t mlp_make_queries(hipStream_t st, const void* inst, int n, const double* x, long T, double* q);
 hipError_t mlp_combine(hipStream_t st, int prec, const double* q, long M, const float* y, int members, long ystride,
-                       double c, double eps, double tol, double wood_tol, double rmin, void* out, uint8_t* fell);
+                       double c, double eps, double tol, double kappa, double wood_tol, double rmin, void* out,
+                       uint8_t* fell);
+hipError_t mlp_calib_ratio(hipStream_t st, int prec, long M, const float* y, int members, long ystride, const void* L,
+                           double* ratio);
+hipError_t mlp_make_rows(hipStream_t st, int prec, const double* x, long n, double k, double a1, double a2,
+                         const void* L, double* q, float* y);
+hipError_t mlp_gather_rows(hipStream_t st, const double* q, const float* y, const uint32_t* idx, long B, double* qb,
+                           float* yb);
 hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
 hipError_t mlp_infer(hipStream_t st, const __bf16* const* wb, const float* const* p, int members, const long off_b[4],
                      long off_w4, long off_b4, double c, double c_tilde, const double* q, long M, float* y,
@@ -64,8 +72,9 @@ struct qpgf_mlp {
   std::vector<float*> p, m1, m2; // fp32 params and Adam moments [NPARAM]
   std::vector<__bf16*> wb;       // bf16 hidden weights, 4 matrices back to back
   std::vector<long> step;
+  double kappa = HUGE_VAL;       // error-estimate calibration: |L_mean - L| <= kappa * spread; +inf = none
   // work buffers (maxb rows)
-  double* q = nullptr;           // queries [maxb][6] when built internally
+  double* q = nullptr;           // training minibatch queries [maxb][6]
   __bf16 *F = nullptr, *FT = nullptr;
   float* Z[4] = {};              // pre-activations [maxb][H]
   __bf16* A[4] = {};             // activations [maxb][H]
@@ -87,6 +96,8 @@ struct qpgf_mlp {
   size_t qinst_cap = 0;
   double* qall = nullptr;
   size_t qall_cap = 0;
+  uint32_t* perm = nullptr;      // training data order [perm_cap]
+  size_t perm_cap = 0;
 };
 
 namespace {
@@ -262,7 +273,7 @@ void qpgf_mlp_destroy(qpgf_mlp* m) {
   for (auto* v : m->m2) if (v) (void)hipFree(v);
   for (auto* v : m->wb) if (v) (void)hipFree(v);
   void* ptrs[] = {m->q, m->F, m->FT, m->out, m->dA, m->dZf, m->dZ, m->dZT, m->part, m->grad, m->ybuf, m->counts,
-                  m->cursor, m->fidx, m->fx, m->fout, m->qinst, m->qall};
+                  m->cursor, m->fidx, m->fx, m->fout, m->qinst, m->qall, m->perm};
   for (void* v : ptrs)
     if (v) (void)hipFree(v);
   for (int l = 0; l < 4; ++l) {
@@ -457,7 +468,7 @@ qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double
     S_TRY(mlp_infer(m->stream, m->wb.data(), m->p.data(), m->members, B_OFF, OFF_W4, OFF_B4, info.c, info.c_tilde,
                     m->qall + 6 * b0, n, m->ybuf, ystride));
     S_TRY(mlp_combine(m->stream, info.prec, m->qall + 6 * b0, n, m->ybuf, m->members, m->maxb * 2, info.c, info.eps,
-                      tol, wood_tol, rmin, static_cast<char*>(out) + b0 * esz, fell_back + b0));
+                      tol, m->kappa, wood_tol, rmin, static_cast<char*>(out) + b0 * esz, fell_back + b0));
   }
   // fallback: per-instance compaction, the plain method on those targets, scatter back
   std::vector<uint32_t> cnt(n_inst + 1, 0);
@@ -509,3 +520,257 @@ qpgf_status qpgf_surrogate_eval(qpgf_mlp* m, qpgf_plan* plan, double tol, double
   return QPGF_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Training data, training loop, calibration of the error estimate, checkpoints
+// ---------------------------------------------------------------------------
+namespace {
+
+qpgf_status fallback_plan(qpgf_mlp* m, qpgf_plan* plan, qpgf_plan_info& info) {
+  if (qpgf_plan_get_info(plan, &info) != QPGF_OK || info.kind != QPGF_KIND_GD3D)
+    return sfail(QPGF_E_ARG, "the plan must be of kind GD3D");
+  if (info.c != kC || info.c_tilde != kCt)
+    return sfail(QPGF_E_ARG, "the plan must use the surrogate's c = 0.6 and c_tilde = 1");
+  if (qpgf_plan_set_stream(plan, m->stream) != QPGF_OK) return sfail(QPGF_E_ARG, "plan stream");
+  return QPGF_OK;
+}
+
+qpgf_status check_instances(int n_inst, const double* k, const double* a1, const double* a2, const int64_t* t_off) {
+  if (n_inst <= 0 || !k || !a1 || !a2 || !t_off) return sfail(QPGF_E_ARG, "bad instance arguments");
+  if (t_off[0] != 0) return sfail(QPGF_E_ARG, "t_off[0] must be 0");
+  for (int i = 0; i < n_inst; ++i)
+    if (t_off[i + 1] < t_off[i]) return sfail(QPGF_E_ARG, "t_off must be non-decreasing");
+  if (t_off[n_inst] > (int64_t)0x7fffffff) return sfail(QPGF_E_SIZE, "at most 2^31 - 1 targets");
+  return QPGF_OK;
+}
+
+// prepare instance i and write the plain method's smooth part at its targets into L
+qpgf_status smooth_of(qpgf_plan* plan, int i, double k, double a1, double a2, const double* x, int64_t n, void* L) {
+  qpgf_status st = qpgf_prepare(plan, k, a1, a2);
+  if (st == QPGF_OK && n > 0) st = qpgf_evaluate_smooth(plan, x, n, L);
+  if (st != QPGF_OK)
+    return sfail(st, std::string("instance ") + std::to_string(i) + ": " + qpgf_last_error());
+  return QPGF_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+constexpr char kCkptMagic[8] = {'Q', 'P', 'G', 'F', 'M', 'L', 'P', '1'};
+
+}  // namespace
+
+extern "C" {
+
+qpgf_status qpgf_mlp_set_calibration(qpgf_mlp* m, double kappa) {
+  s_err.clear();
+  if (!m) return sfail(QPGF_E_ARG, "model is NULL");
+  if (!(kappa > 0.0)) return sfail(QPGF_E_ARG, "kappa must be positive (+inf: accept nothing)");
+  m->kappa = kappa;
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_mlp_get_calibration(const qpgf_mlp* m, double* kappa) {
+  s_err.clear();
+  if (!m || !kappa) return sfail(QPGF_E_ARG, "model and kappa must be non-NULL");
+  *kappa = m->kappa;
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_surrogate_make_data(qpgf_mlp* m, qpgf_plan* plan, int n_inst, const double* k, const double* a1,
+                                     const double* a2, const int64_t* t_off, const double* x, double* q, float* y) {
+  s_err.clear();
+  if (!m || !plan) return sfail(QPGF_E_ARG, "model and plan must be non-NULL");
+  qpgf_status st = check_instances(n_inst, k, a1, a2, t_off);
+  if (st != QPGF_OK) return st;
+  qpgf_plan_info info;
+  st = fallback_plan(m, plan, info);
+  if (st != QPGF_OK) return st;
+  const int64_t T = t_off[n_inst];
+  if (T == 0) return QPGF_OK;
+  if (!x || !q || !y) return sfail(QPGF_E_ARG, "x, q and y must be non-NULL");
+  int64_t maxn = 0;
+  for (int i = 0; i < n_inst; ++i) maxn = std::max(maxn, t_off[i + 1] - t_off[i]);
+  DevBuf L;
+  S_TRY(hipMalloc(&L.p, (size_t)maxn * 16));
+  for (int i = 0; i < n_inst; ++i) {
+    const int64_t t0 = t_off[i], n = t_off[i + 1] - t0;
+    st = smooth_of(plan, i, k[i], a1[i], a2[i], x + 3 * t0, n, L.p);
+    if (st != QPGF_OK) return st;
+    if (n) S_TRY(mlp_make_rows(m->stream, info.prec, x + 3 * t0, (long)n, k[i], a1[i], a2[i], L.p, q + 6 * t0,
+                               y + 2 * t0));
+  }
+  S_TRY(hipStreamSynchronize(m->stream));   // L is freed on return
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_surrogate_train(qpgf_mlp* m, const double* q, const float* y, int64_t N, const qpgf_train_cfg* cfg,
+                                 float* loss) {
+  s_err.clear();
+  if (!m || !cfg) return sfail(QPGF_E_ARG, "model and cfg must be non-NULL");
+  const int64_t B = cfg->batch;
+  if (B < 64 || B % 64 || B > m->maxb) return sfail(QPGF_E_ARG, "batch must be a multiple of 64 <= max_batch");
+  if (N < B || N > (int64_t)0xffffffff) return sfail(QPGF_E_ARG, "need batch <= N < 2^32 rows");
+  if (!q || !y) return sfail(QPGF_E_ARG, "q and y must be non-NULL");
+  if (cfg->steps < 0) return sfail(QPGF_E_ARG, "steps < 0");
+  if (!(cfg->lr_max > 0.f) || !(cfg->lr_min >= 0.f) || cfg->lr_min > cfg->lr_max)
+    return sfail(QPGF_E_ARG, "need 0 <= lr_min <= lr_max, lr_max > 0");
+  if (cfg->member < -1 || cfg->member >= m->members) return sfail(QPGF_E_ARG, "member out of range");
+  if ((size_t)N > m->perm_cap) {
+    if (m->perm) (void)hipFree(m->perm);
+    m->perm = nullptr;
+    m->perm_cap = 0;
+    S_TRY(dalloc(&m->perm, (size_t)N));
+    m->perm_cap = (size_t)N;
+  }
+  std::vector<uint32_t> order((size_t)N);
+  const int e0 = cfg->member < 0 ? 0 : cfg->member, e1 = cfg->member < 0 ? m->members : cfg->member + 1;
+  for (int e = e0; e < e1; ++e) {
+    uint64_t s = cfg->seed * 0x9E3779B97F4A7C15ull + 1000003ull * (uint64_t)e + 12345ull;
+    for (int64_t i = 0; i < N; ++i) order[i] = (uint32_t)i;
+    int64_t pos = N;
+    for (int64_t t = 0; t < cfg->steps; ++t) {
+      if (pos + B > N) {
+        // a fresh data order each epoch (Fisher-Yates); the previous upload must be complete
+        S_TRY(hipStreamSynchronize(m->stream));
+        for (int64_t i = N - 1; i > 0; --i) std::swap(order[i], order[splitmix(s) % (uint64_t)(i + 1)]);
+        S_TRY(hipMemcpyAsync(m->perm, order.data(), (size_t)N * sizeof(uint32_t), hipMemcpyHostToDevice, m->stream));
+        pos = 0;
+      }
+      S_TRY(mlp_gather_rows(m->stream, q, y, m->perm + pos, (long)B, m->q, m->ybuf));
+      pos += B;
+      const double lr = cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) * (1.0 + cos(M_PI * (double)t / cfg->steps));
+      qpgf_status st = qpgf_mlp_train_step(m, e, m->q, m->ybuf, B, (float)lr, loss ? loss + e : nullptr);
+      if (st != QPGF_OK) return st;
+    }
+  }
+  S_TRY(hipStreamSynchronize(m->stream));   // the host data order is freed on return
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_surrogate_calibrate(qpgf_mlp* m, qpgf_plan* plan, int n_inst, const double* k, const double* a1,
+                                     const double* a2, const int64_t* t_off, const double* x, double quantile,
+                                     double safety, double* kappa) {
+  s_err.clear();
+  if (!m || !plan) return sfail(QPGF_E_ARG, "model and plan must be non-NULL");
+  qpgf_status st = check_instances(n_inst, k, a1, a2, t_off);
+  if (st != QPGF_OK) return st;
+  if (!(quantile > 0.0 && quantile <= 1.0)) return sfail(QPGF_E_ARG, "quantile must be in (0, 1]");
+  if (!(safety >= 1.0) || std::isinf(safety)) return sfail(QPGF_E_ARG, "safety must be finite and >= 1");
+  if (m->members < 2) return sfail(QPGF_E_ARG, "the error estimate needs at least two members");
+  qpgf_plan_info info;
+  st = fallback_plan(m, plan, info);
+  if (st != QPGF_OK) return st;
+  const int64_t T = t_off[n_inst];
+  if (T == 0 || !x) return sfail(QPGF_E_ARG, "no calibration targets");
+  const size_t esz = info.prec == QPGF_C128 ? 16 : 8;
+  DevBuf L, R, Q;
+  S_TRY(hipMalloc(&L.p, (size_t)T * esz));
+  S_TRY(hipMalloc(&R.p, (size_t)T * sizeof(double)));
+  S_TRY(hipMalloc(&Q.p, (size_t)m->maxb * 6 * sizeof(double)));
+  for (int i = 0; i < n_inst; ++i) {
+    const int64_t t0 = t_off[i], n = t_off[i + 1] - t0;
+    st = smooth_of(plan, i, k[i], a1[i], a2[i], x + 3 * t0, n, static_cast<char*>(L.p) + t0 * esz);
+    if (st != QPGF_OK) return st;
+  }
+  // queries chunk by chunk (rows of one instance share (k, alpha)), network, ratio
+  double* q = static_cast<double*>(Q.p);
+  const long ystride = m->maxb * 2;
+  for (int i = 0; i < n_inst; ++i) {
+    for (int64_t b0 = t_off[i]; b0 < t_off[i + 1]; b0 += m->maxb) {
+      const long n = (long)std::min<int64_t>(m->maxb, t_off[i + 1] - b0);
+      S_TRY(mlp_make_rows(m->stream, info.prec, x + 3 * b0, n, k[i], a1[i], a2[i],
+                          static_cast<char*>(L.p) + b0 * esz, q, m->out));
+      S_TRY(mlp_infer(m->stream, m->wb.data(), m->p.data(), m->members, B_OFF, OFF_W4, OFF_B4, kC, kCt, q, n,
+                      m->ybuf, ystride));
+      S_TRY(mlp_calib_ratio(m->stream, info.prec, n, m->ybuf, m->members, ystride,
+                            static_cast<char*>(L.p) + b0 * esz, static_cast<double*>(R.p) + b0));
+    }
+  }
+  std::vector<double> r((size_t)T);
+  S_TRY(hipMemcpyAsync(r.data(), R.p, (size_t)T * sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  S_TRY(hipStreamSynchronize(m->stream));
+  // far targets (NaN) carry no estimate; +inf stays and keeps the model from accepting anything
+  r.erase(std::remove_if(r.begin(), r.end(), [](double v) { return v != v; }), r.end());
+  if (r.empty()) return sfail(QPGF_E_ARG, "no near-region calibration targets (|x3| <= 0.6)");
+  const size_t j = std::min(r.size() - 1, (size_t)std::ceil(quantile * (double)r.size()) - 1);
+  std::nth_element(r.begin(), r.begin() + (long)j, r.end());
+  const double kap = safety * r[j];
+  m->kappa = kap > 0.0 ? kap : HUGE_VAL;
+  if (kappa) *kappa = m->kappa;
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_mlp_save(qpgf_mlp* m, const char* path) {
+  s_err.clear();
+  if (!m || !path) return sfail(QPGF_E_ARG, "model and path must be non-NULL");
+  std::vector<float> buf((size_t)NPARAM * 3);
+  S_TRY(hipStreamSynchronize(m->stream));
+  FILE* f = fopen(path, "wb");
+  if (!f) return sfail(QPGF_E_IO, std::string("cannot open ") + path + " for writing");
+  const int32_t members = m->members;
+  const int64_t np = NPARAM;
+  bool ok = fwrite(kCkptMagic, 1, 8, f) == 8 && fwrite(&members, sizeof members, 1, f) == 1 &&
+            fwrite(&np, sizeof np, 1, f) == 1 && fwrite(&m->kappa, sizeof m->kappa, 1, f) == 1;
+  for (int e = 0; e < m->members && ok; ++e) {
+    const int64_t step = m->step[e];
+    hipError_t r = hipMemcpy(buf.data(), m->p[e], NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+    if (r == hipSuccess) r = hipMemcpy(buf.data() + NPARAM, m->m1[e], NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+    if (r == hipSuccess)
+      r = hipMemcpy(buf.data() + 2 * NPARAM, m->m2[e], NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+    if (r != hipSuccess) {
+      fclose(f);
+      return sfail(QPGF_E_HIP, std::string("checkpoint copy: ") + hipGetErrorString(r));
+    }
+    ok = fwrite(&step, sizeof step, 1, f) == 1 && fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  }
+  ok = (fclose(f) == 0) && ok;
+  if (!ok) return sfail(QPGF_E_IO, std::string("write to ") + path + " failed");
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_mlp_load(qpgf_mlp* m, const char* path) {
+  s_err.clear();
+  if (!m || !path) return sfail(QPGF_E_ARG, "model and path must be non-NULL");
+  FILE* f = fopen(path, "rb");
+  if (!f) return sfail(QPGF_E_IO, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t members = 0;
+  int64_t np = 0;
+  double kap = 0.0;
+  bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0 &&
+            fread(&members, sizeof members, 1, f) == 1 && fread(&np, sizeof np, 1, f) == 1 &&
+            fread(&kap, sizeof kap, 1, f) == 1;
+  if (!ok || members != m->members || np != NPARAM || !(kap > 0.0)) {
+    fclose(f);
+    return sfail(QPGF_E_IO, std::string(path) + " is not a checkpoint of a " + std::to_string(m->members) +
+                                "-member model of this architecture");
+  }
+  std::vector<float> buf((size_t)NPARAM * 3 * members);
+  std::vector<int64_t> steps(members);
+  for (int e = 0; e < members && ok; ++e)
+    ok = fread(&steps[e], sizeof(int64_t), 1, f) == 1 && steps[e] >= 0 &&
+         fread(buf.data() + (size_t)e * 3 * NPARAM, sizeof(float), (size_t)NPARAM * 3, f) == (size_t)NPARAM * 3;
+  ok = ok && fgetc(f) == EOF;
+  fclose(f);
+  if (!ok) return sfail(QPGF_E_IO, std::string(path) + " is truncated or corrupt");
+  // the model changes only once the whole file has been read
+  S_TRY(hipStreamSynchronize(m->stream));
+  for (int e = 0; e < members; ++e) {
+    const float* b = buf.data() + (size_t)e * 3 * NPARAM;
+    S_TRY(hipMemcpy(m->p[e], b, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    S_TRY(hipMemcpy(m->m1[e], b + NPARAM, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    S_TRY(hipMemcpy(m->m2[e], b + 2 * NPARAM, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    m->step[e] = steps[e];
+    S_TRY(refresh(m, e));
+  }
+  m->kappa = kap;
+  S_TRY(hipStreamSynchronize(m->stream));
+  return QPGF_OK;
+}
+
+}  // extern "C"

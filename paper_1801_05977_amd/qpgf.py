@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqpgf.so")
 C128, C64 = 0, 1
 KIND_G2D, KIND_GD3D, KIND_MAXWELL3D, KIND_G2D_GRAD, KIND_G2D_HESS_DIFF = 0, 1, 2, 3, 4
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_WOOD", 3: "E_SPECIAL", 4: "E_SIZE", 5: "E_HIP", 6: "E_NOMEM",
-          7: "E_UNSUPPORTED"}
+          7: "E_UNSUPPORTED", 8: "E_IO"}
 
 
 class QpgfError(RuntimeError):
@@ -44,13 +44,22 @@ class PlanInfo(ctypes.Structure):
                 ("far_points", ctypes.c_int)]
 
 
+class TrainCfg(ctypes.Structure):
+    """qpgf_train_cfg."""
+    _fields_ = [("batch", ctypes.c_int64), ("steps", ctypes.c_int64), ("lr_max", ctypes.c_float),
+                ("lr_min", ctypes.c_float), ("member", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
 EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf_plan_set_stream",
            "qpgf_plan_get_info", "qpgf_prepare", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
            "qpgf_g2d_grad", "qpgf_g2d_hess_diff", "qpgf_prepare_hess_diff", "qpgf_prepare_stage", "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing",
            "qpgf_g2d_batched", "qpgf_plan_autotune", "qpgf_last_error", "qpgf_version", "qpgf_evaluate_smooth",
            "qpgf_mlp_param_count", "qpgf_mlp_create", "qpgf_mlp_destroy", "qpgf_mlp_set_stream",
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
-           "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval"]
+           "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration",
+           "qpgf_mlp_get_calibration", "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate",
+           "qpgf_mlp_save", "qpgf_mlp_load"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch", "bin_place",
           "overflow", "layout", "ring", "gather_far"]
 
@@ -108,12 +117,22 @@ def lib():
     DP = ctypes.POINTER(ctypes.c_double)
     L.qpgf_surrogate_eval.argtypes = [P, P, D, D, D, ctypes.c_int, DP, DP, DP, ctypes.POINTER(ctypes.c_int64), VP,
                                       VP, U8P, ctypes.POINTER(ctypes.c_int64)]
+    L.qpgf_mlp_set_calibration.argtypes = [P, D]
+    L.qpgf_mlp_get_calibration.argtypes = [P, DP]
+    L.qpgf_surrogate_make_data.argtypes = [P, P, ctypes.c_int, DP, DP, DP, ctypes.POINTER(ctypes.c_int64), VP, VP, VP]
+    L.qpgf_surrogate_train.argtypes = [P, VP, VP, I64, ctypes.POINTER(TrainCfg), VP]
+    L.qpgf_surrogate_calibrate.argtypes = [P, P, ctypes.c_int, DP, DP, DP, ctypes.POINTER(ctypes.c_int64), VP, D, D,
+                                           DP]
+    L.qpgf_mlp_save.argtypes = [P, ctypes.c_char_p]
+    L.qpgf_mlp_load.argtypes = [P, ctypes.c_char_p]
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
                  "qpgf_prepare_stage", "qpgf_evaluate", "qpgf_g2d", "qpgf_gd3d", "qpgf_maxwell3d",
                  "qpgf_copy_field", "qpgf_plan_enable_timing", "qpgf_plan_get_timing", "qpgf_g2d_batched",
                  "qpgf_plan_autotune", "qpgf_evaluate_smooth", "qpgf_mlp_create", "qpgf_mlp_set_stream",
                  "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
-                 "qpgf_mlp_train_step", "qpgf_surrogate_eval"):
+                 "qpgf_mlp_train_step", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration", "qpgf_mlp_get_calibration",
+                 "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate", "qpgf_mlp_save",
+                 "qpgf_mlp_load"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -370,3 +389,57 @@ class Mlp:
                                              _ptr(x, torch.float64, "x"), _ptr(out, plan.cdtype, "out"),
                                              _ptr(fell_back, torch.uint8, "fell_back"), ctypes.byref(nf)))
         return out, fell_back, nf.value
+
+    @staticmethod
+    def _inst(k, a1, a2, t_off):
+        arr = lambda ct, v: (ct * len(v))(*v)
+        return (len(k), arr(ctypes.c_double, [float(v) for v in k]), arr(ctypes.c_double, [float(v) for v in a1]),
+                arr(ctypes.c_double, [float(v) for v in a2]), arr(ctypes.c_int64, [int(v) for v in t_off]))
+
+    @property
+    def kappa(self):
+        """Calibration factor of the error estimate (+inf: uncalibrated, accepts nothing)."""
+        v = ctypes.c_double()
+        _check_mlp(lib().qpgf_mlp_get_calibration(self._h, ctypes.byref(v)))
+        return v.value
+
+    @kappa.setter
+    def kappa(self, v):
+        _check_mlp(lib().qpgf_mlp_set_calibration(self._h, float(v)))
+
+    def make_data(self, plan, k, a1, a2, t_off, x):
+        """qpgf_surrogate_make_data: training rows (q [T][6] float64, y [T][2] float32) from the plain method."""
+        T = int(t_off[-1])
+        q = torch.empty((T, 6), dtype=torch.float64, device="cuda")
+        y = torch.empty((T, 2), dtype=torch.float32, device="cuda")
+        self._stream()
+        _check_mlp(lib().qpgf_surrogate_make_data(self._h, plan._h, *self._inst(k, a1, a2, t_off),
+                                                  _ptr(x, torch.float64, "x"), _ptr(q, torch.float64, "q"),
+                                                  _ptr(y, torch.float32, "y")))
+        return q, y
+
+    def train(self, q, y, batch, steps, lr_max, lr_min, seed=0, member=-1):
+        """qpgf_surrogate_train; returns the last minibatch loss of each member (device float32 [members])."""
+        cfg = TrainCfg(batch=batch, steps=steps, lr_max=lr_max, lr_min=lr_min, member=member, reserved=0, seed=seed)
+        loss = torch.full((self.members,), float("nan"), dtype=torch.float32, device="cuda")
+        self._stream()
+        _check_mlp(lib().qpgf_surrogate_train(self._h, _ptr(q, torch.float64, "q"), _ptr(y, torch.float32, "y"),
+                                              q.shape[0], ctypes.byref(cfg), _ptr(loss, torch.float32, "loss")))
+        return loss
+
+    def calibrate(self, plan, k, a1, a2, t_off, x, quantile=1.0, safety=2.0):
+        """qpgf_surrogate_calibrate; returns the fitted kappa."""
+        v = ctypes.c_double()
+        self._stream()
+        _check_mlp(lib().qpgf_surrogate_calibrate(self._h, plan._h, *self._inst(k, a1, a2, t_off),
+                                                  _ptr(x, torch.float64, "x"), float(quantile), float(safety),
+                                                  ctypes.byref(v)))
+        return v.value
+
+    def save(self, path):
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        self._stream()
+        _check_mlp(lib().qpgf_mlp_load(self._h, os.fsencode(path)))

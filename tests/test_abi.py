@@ -38,14 +38,17 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(qpgf_params, lattice_rmin), sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes),"
         " offsetof(qpgf_params, quad_q), offsetof(qpgf_params, sing_order), offsetof(qpgf_params, far_m),"
         " offsetof(qpgf_params, maxwell_trace), offsetof(qpgf_plan_info, far_m1),"
-        " offsetof(qpgf_plan_info, far_points));return 0;}\n")
+        " offsetof(qpgf_plan_info, far_points));"
+        "printf(\"%zu %zu %zu\\n\", sizeof(qpgf_train_cfg), offsetof(qpgf_train_cfg, member),"
+        " offsetof(qpgf_train_cfg, seed));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(qpgf.Params), qpgf.Params.lattice_rmin.offset, ctypes.sizeof(qpgf.PlanInfo),
             qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset, qpgf.Params.sing_order.offset,
             qpgf.Params.far_m.offset, qpgf.Params.maxwell_trace.offset, qpgf.PlanInfo.far_m1.offset,
-            qpgf.PlanInfo.far_points.offset]
+            qpgf.PlanInfo.far_points.offset, ctypes.sizeof(qpgf.TrainCfg), qpgf.TrainCfg.member.offset,
+            qpgf.TrainCfg.seed.offset]
     assert got == want
 
 
@@ -103,3 +106,19 @@ def test_surrogate_entry_points_validate_before_touching_the_device():
     assert L.qpgf_evaluate_smooth(None, None, 0, None) == 1
     assert L.qpgf_surrogate_eval(None, None, 0.0, 0.0, 0.0, 0, None, None, None, None, None, None, None,
                                  None) == 1
+
+
+def test_surrogate_training_and_checkpoint_entry_points_validate():
+    L = qpgf.lib()
+    one = (ctypes.c_double * 1)(1.0)
+    off = (ctypes.c_int64 * 2)(0, 0)
+    cfg = qpgf.TrainCfg(batch=64, steps=1, lr_max=1e-3, lr_min=0.0, member=-1, reserved=0, seed=0)
+    kap = ctypes.c_double()
+    assert L.qpgf_mlp_set_calibration(None, 1.0) == 1
+    assert L.qpgf_mlp_get_calibration(None, ctypes.byref(kap)) == 1
+    assert L.qpgf_surrogate_make_data(None, None, 1, one, one, one, off, None, None, None) == 1
+    assert L.qpgf_surrogate_train(None, None, None, 64, ctypes.byref(cfg), None) == 1
+    assert L.qpgf_surrogate_calibrate(None, None, 1, one, one, one, off, None, 1.0, 2.0, ctypes.byref(kap)) == 1
+    assert L.qpgf_mlp_save(None, b"/nonexistent/x") == 1
+    assert L.qpgf_mlp_load(None, b"/nonexistent/x") == 1
+    assert "NULL" in L.qpgf_mlp_last_error().decode()

@@ -152,6 +152,7 @@ def test_surrogate_eval_with_fallback():
     x, t_off = _targets(3, 3000, 70)
     T = len(x)
     m, ps = model(3, 1024)                   # 1024 rows per pass: several passes and a ragged one
+    m.kappa = 1.0                            # any finite estimate passes tol = 1e30
     P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M, wood_tol=1e-5)
     rmin = 1e-3
     out, fell, nf = m.evaluate(P, k, a1, a2, t_off, dev(x), tol=1e30, wood_tol=1e-3, rmin=rmin)
@@ -184,12 +185,13 @@ def test_surrogate_eval_with_fallback():
 
 
 def test_surrogate_zero_tolerance_is_the_plain_method():
-    """tol = 0: the ensemble spread exceeds it everywhere, every target takes the plain method and the
+    """tol = 0: the error estimate exceeds it everywhere, every target takes the plain method and the
     result equals qpgf_gd3d per instance."""
     M = (32, 32, 16)
     k, a1, a2 = _instances()
     x, t_off = _targets(3, 2000, 80)
     m, _ = model(2, 4096)
+    m.kappa = 1.0
     P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C64, *M, wood_tol=1e-5)
     out, fell, nf = m.evaluate(P, k, a1, a2, t_off, dev(x), tol=0.0, wood_tol=1e-3, rmin=1e-3)
     fell = fell.cpu().numpy()
@@ -230,3 +232,146 @@ def test_training_on_plain_method_data_reduces_the_loss():
     print("loss", hist)
     assert np.all(np.isfinite(hist))
     assert hist[-1] < 0.1 * hist[0]
+
+
+def test_uncalibrated_or_single_member_model_accepts_nothing():
+    """A new model has kappa = +inf; a one-member model has no spread to estimate its error with."""
+    M = (32, 32, 16)
+    k, a1, a2 = _instances()
+    x, t_off = _targets(2, 1500, 85)
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C64, *M, wood_tol=1e-5)
+    m, _ = model(2, 1024)
+    assert m.kappa == math.inf
+    _, fell, nf = m.evaluate(P, k[:2], a1[:2], a2[:2], t_off, dev(x), tol=1e30)
+    assert nf == len(x) and np.all(fell.cpu().numpy() & 4)
+    m1, _ = model(1, 1024)
+    m1.kappa = 1.0
+    _, fell, nf = m1.evaluate(P, k[:2], a1[:2], a2[:2], t_off, dev(x), tol=1e30)
+    assert nf == len(x) and np.all(fell.cpu().numpy() & 4)
+
+
+def _train_instances(n, seed, min_beta=0.3):
+    """(k, alpha1, alpha2) with k ~ U[1,10], alpha ~ U[-1/2,1/2]^2, at least min_beta from a Wood anomaly."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        k, a1, a2 = rng.uniform(1, 10), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5)
+        n1, n2 = np.meshgrid(np.arange(-12, 13), np.arange(-12, 13))
+        if np.min(np.sqrt(np.abs(k * k - (a1 + n1) ** 2 - (a2 + n2) ** 2))) >= min_beta:
+            out.append((k, a1, a2))
+    return np.array(out)
+
+
+def test_make_data_rows_are_the_plain_smooth_part():
+    M = (32, 32, 16)
+    inst = _train_instances(3, 95)
+    per = [700, 0, 1300]
+    x = workloads.targets(sum(per), 3, seed=96, zmax=0.6)
+    t_off = np.concatenate([[0], np.cumsum(per)])
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M)
+    m = qpgf.Mlp(2, 1024, seed=1)
+    q, y = m.make_data(P, inst[:, 0], inst[:, 1], inst[:, 2], t_off, dev(x))
+    q, y = q.cpu().numpy(), y.cpu().numpy()
+    for i in range(3):
+        sl = slice(t_off[i], t_off[i + 1])
+        if per[i] == 0:
+            continue
+        P.prepare(*inst[i])
+        L = P.smooth(dev(x[sl])).cpu().numpy()
+        assert np.array_equal(q[sl, :3], x[sl]) and np.all(q[sl, 3:] == inst[i])
+        assert np.array_equal(y[sl, 0], (10 * L.real).astype(np.float32))
+        assert np.array_equal(y[sl, 1], (10 * L.imag).astype(np.float32))
+
+
+def test_checkpoint_roundtrip_resumes_training_exactly(tmp_path):
+    """Parameters, Adam moments, step counts and kappa survive save/load: training resumed from a
+    checkpoint takes the same steps as uninterrupted training (bit for bit)."""
+    B = 256
+    q = dev(queries(B, 97))
+    y = dev(np.random.default_rng(98).normal(size=(B, 2)).astype(np.float32))
+    a = qpgf.Mlp(2, 1024, seed=11)
+    for e in range(2):
+        for _ in range(3):
+            a.train_step(q, y, 1e-3, member=e)
+    a.kappa = 3.5
+    path = str(tmp_path / "mlp.ckpt")
+    a.save(path)
+    for e in range(2):
+        for _ in range(3):
+            a.train_step(q, y, 1e-3, member=e)
+    b = qpgf.Mlp(2, 1024, seed=12)
+    before = b.params(0).cpu().numpy()
+    b.load(path)
+    assert b.kappa == 3.5
+    for e in range(2):
+        for _ in range(3):
+            b.train_step(q, y, 1e-3, member=e)
+    for e in range(2):
+        assert np.array_equal(a.params(e).cpu().numpy(), b.params(e).cpu().numpy())
+    # a checkpoint of another ensemble size, or a cut file, is refused and changes nothing
+    c = qpgf.Mlp(3, 1024, seed=13)
+    pc = c.params(0).cpu().numpy()
+    with pytest.raises(qpgf.QpgfError) as ei:
+        c.load(path)
+    assert ei.value.status == 8
+    raw = open(path, "rb").read()
+    cut = tmp_path / "cut.ckpt"
+    cut.write_bytes(raw[:len(raw) - 100])
+    with pytest.raises(qpgf.QpgfError):
+        b.load(str(cut))
+    assert np.array_equal(c.params(0).cpu().numpy(), pc)
+    assert not np.array_equal(before, b.params(0).cpu().numpy())
+
+
+def _surrogate(M, members, n_train, per, steps, seed):
+    P = qpgf.Plan(qpgf.KIND_GD3D, qpgf.C128, *M)
+    inst = _train_instances(n_train, seed)
+    x = workloads.targets(n_train * per, 3, seed=seed + 1, zmax=0.6)
+    t_off = np.arange(n_train + 1) * per
+    m = qpgf.Mlp(members, 8192, seed=seed + 2)
+    q, y = m.make_data(P, inst[:, 0], inst[:, 1], inst[:, 2], t_off, dev(x))
+    return P, m, q, y
+
+
+def test_library_training_reduces_the_loss():
+    P, m, q, y = _surrogate((32, 32, 16), 2, 8, 1024, 0, 120)
+    g0 = [m.gradient(q[:4096].contiguous(), y[:4096].contiguous(), member=e)[1].item() for e in range(2)]
+    loss = m.train(q, y, batch=1024, steps=200, lr_max=2e-3, lr_min=1e-5, seed=3).cpu().numpy()
+    g1 = [m.gradient(q[:4096].contiguous(), y[:4096].contiguous(), member=e)[1].item() for e in range(2)]
+    print("loss", g0, g1, loss)
+    assert np.all(np.isfinite(loss))
+    assert all(b < 0.1 * a for a, b in zip(g0, g1))
+
+
+def test_calibrated_gate_holds_on_fresh_instances():
+    """The acceptance contract: after calibration on held-out instances, every value the surrogate
+    accepts at tolerance tol lies within tol of the plain method (relative to |G_d|) on instances it
+    has never seen; the rest fall back to the plain method (the same plan on a subset of the targets:
+    its binning differs, so agreement is to the plan's own bar, not bit for bit)."""
+    M = (32, 32, 16)
+    P, m, q, y = _surrogate(M, 4, 24, 2048, 0, 130)
+    m.train(q, y, batch=2048, steps=600, lr_max=2e-3, lr_min=1e-5, seed=5)
+    cal = _train_instances(12, 131)
+    xc = workloads.targets(12 * 4096, 3, seed=132, zmax=0.6)
+    kap = m.calibrate(P, cal[:, 0], cal[:, 1], cal[:, 2], np.arange(13) * 4096, dev(xc), quantile=1.0, safety=2.0)
+    assert math.isfinite(kap) and kap == m.kappa
+    fresh = _train_instances(10, 133)
+    pq = 4000
+    x = workloads.targets(10 * pq, 3, seed=134)
+    t_off = np.arange(11) * pq
+    plain = np.concatenate([P(*fresh[i], dev(x[i * pq:(i + 1) * pq])).cpu().numpy() for i in range(10)])
+    report = []
+    # The estimate bounds the error by tol |G_d| of the value returned; loose tolerances make sure the
+    # gate is exercised on accepted values at all (this small model is far from 1e-4).
+    for tol in (1e-4, 1e-3, 1e-2, 1e-1, 1.0, 3.0):
+        out, fell, nf = m.evaluate(P, fresh[:, 0], fresh[:, 1], fresh[:, 2], t_off, dev(x), tol, wood_tol=1e-3,
+                                   rmin=1e-3)
+        out, fell = out.cpu().numpy(), fell.cpu().numpy()
+        acc = fell == 0
+        e = np.abs(out[acc] - plain[acc]) / np.abs(out[acc])
+        report.append((tol, int(acc.sum()), float(e.max()) if e.size else 0.0))
+        assert np.all(e <= tol), (tol, e.max())
+        fb = ~acc & np.isfinite(plain)
+        assert parity(out[fb], plain[fb]) <= 1e-10
+    print("kappa", kap, "tol, accepted, max rel err:", report)
+    assert report[-1][1] > 0
