@@ -272,6 +272,35 @@ qpgf_status qpgf_prepare_hess_diff(qpgf_plan* plan, double k1, double k2, double
 qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const double* k, const double* alpha, const int* m1,
                              const int64_t* t_off, const double* x, void* out, uint8_t* flags);
 
+/* Caller-owned workspace.  A plan's bulk device arrays are the near grid (every
+ * field), its node-interleaved copy (2D derivative kinds and the complex64 2D
+ * G), the far slab (its size grows with the wavenumber: see far_m1, far_m2 and
+ * the slab geometry in qpgf_plan_info) and the per-call target scratch (the
+ * binning of 3D targets, the ring mask of 2D ring_interp).  By default the plan
+ * allocates them itself and grows the slab and the scratch on demand.
+ *
+ * qpgf_plan_workspace_bytes: the bytes (in *bytes) of one device buffer that
+ * holds all of them for instances of wavenumber up to kmax (both wavenumbers of
+ * the second-derivative differences) and calls of up to max_targets targets.
+ *
+ * qpgf_plan_set_workspace: the plan frees its own arrays and lays them out in
+ * [ptr, ptr + bytes) (device memory, 256-byte aligned, bytes at least what
+ * qpgf_plan_workspace_bytes returns for the same kmax and max_targets).  From
+ * then on no single-instance call allocates device memory: a prepare, g2d,
+ * gd3d, maxwell3d, ... of a larger wavenumber, or an evaluate of more targets,
+ * returns QPGF_E_SIZE instead.  The caller keeps the buffer alive and leaves it
+ * alone until the plan is destroyed or given another workspace.  ptr = NULL
+ * (bytes 0) returns the plan to allocating its own arrays.  Either way the grids
+ * are lost: prepare again before evaluating.  Synchronises the plan's stream.
+ * Not covered: the plan's constant tables, allocated at creation (quadrature,
+ * twiddles, the 2D singular-part tables, and the 3D H table, sized for
+ * |alpha_i| <= 1: an instance with a larger |alpha_i| grows it), the batched 2D
+ * call's per-batch buffers, and the autotuner's scratch.  Errors: E_ARG (NULL plan or bytes, kmax not finite
+ * or < 0, max_targets outside [0, 2^31 - 1], ptr not aligned), E_SIZE (bytes
+ * too small), E_HIP / E_NOMEM (returning to the plan's own arrays). */
+qpgf_status qpgf_plan_workspace_bytes(const qpgf_plan* plan, double kmax, int64_t max_targets, size_t* bytes);
+qpgf_status qpgf_plan_set_workspace(qpgf_plan* plan, void* ptr, size_t bytes, double kmax, int64_t max_targets);
+
 /* FFT autotuner: for every transform shape the plan uses (and, for 2D plans,
  * every power-of-two x1 length from 16 to params.m1), time the candidate numbers
  * of transforms per block on scratch memory and keep the fastest.  Results are

@@ -91,6 +91,9 @@ void free_batch(Plan& P) {
 
 void free_plan(Plan& P) {
   free_batch(P);
+  if (P.ws) {   // the caller's memory
+    P.grid = P.far = P.gridI = nullptr;
+  }
   if (P.side) (void)hipStreamDestroy(P.side);
   if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
   if (P.ev_join) (void)hipEventDestroy(P.ev_join);
@@ -99,8 +102,9 @@ void free_plan(Plan& P) {
   if (P.b_host) (void)hipHostFree(P.b_host);
   for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI})
     if (q) (void)hipFree(q);
-  void* ptrs[] = {P.grid, P.far, P.xq,   P.wxq, P.wXq, P.cs,   P.rq,          P.wrq,  P.y1q,    P.y2q,    P.tw,
-                  P.twf,  P.F1,  P.F2,   P.D2, P.E2, P.ring_mask, P.htab, P.bin_keyrank, P.bin_rec, P.bin_hist, P.bin_offs, P.bin_cnt, P.bin_ovf, P.bin_novf};
+  free_target_scratch(P.ts);
+  void* ptrs[] = {P.grid, P.far, P.xq, P.wxq, P.wXq, P.cs, P.rq, P.wrq, P.y1q, P.y2q, P.tw, P.twf, P.F1, P.F2, P.D2, P.E2,
+                  P.htab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -196,6 +200,7 @@ hipError_t set_far_geometry(Plan& P, double kmax) {
   const size_t nfar = (size_t)g.Mf1 * g.Mf2 * g.S;
   const size_t bytes = (size_t)P.nfo * nfar * P.esize;
   if (bytes > P.far_cap) {
+    if (P.ws) return hipErrorInvalidValue;   // callers check the workspace's kmax first
     if (P.far) {
       hipError_t e = hipFree(P.far);
       if (e != hipSuccess) return e;
@@ -218,6 +223,30 @@ hipError_t set_far_geometry(Plan& P, double kmax) {
 
 // Wood anomaly: beta_n = 0 for some mode n (Section 1).  Only lattice points with
 // |xi_perp| within 1 of k can come close.
+// Entries of the H table on rho = (m - 4) dh that cover |xi| over the grid's modes.
+int htab_size(const Plan& P, double a1, double a2) {
+  const double e1 = P.M1 / 2 + fabs(a1) + 1.0, e2 = P.M2 / 2 + fabs(a2) + 1.0;
+  const double e3 = (P.M3 / 2 + 1.0) * M_PI / P.p.c_tilde;
+  return (int)(sqrt(e1 * e1 + e2 * e2 + e3 * e3) / P.hd) + 16;
+}
+
+// The far slab for instances up to kmax; a plan on a caller's workspace cannot grow it.
+qpgf_status far_for(Plan& P, double kmax) {
+  if (P.ws && !(kmax <= P.ws_kmax))
+    return fail(QPGF_E_SIZE, "the plan's workspace holds the far slab of wavenumbers up to " +
+                                 std::to_string(P.ws_kmax) + "; set a larger workspace");
+  HIP_TRY(set_far_geometry(P, kmax));
+  return QPGF_OK;
+}
+
+// Calls of more targets than a caller's workspace was sized for are refused.
+qpgf_status targets_fit(const Plan& P, int64_t T) {
+  if (P.ws && T > P.ws_T)
+    return fail(QPGF_E_SIZE, "the plan's workspace holds the scratch of " + std::to_string(P.ws_T) +
+                                 " targets per call; set a larger workspace");
+  return QPGF_OK;
+}
+
 qpgf_status check_instance_m1(const Plan& P, double k, double a1, double a2, int M1);
 qpgf_status check_instance(const Plan& P, double k, double a1, double a2) {
   return check_instance_m1(P, k, a1, a2, P.M1);
@@ -282,13 +311,15 @@ bool has_special(const Plan& P, double k, double a1, double a2, int M1) {
 }
 
 qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, double k2 = 0.0) {
+  if (!P.grid) return fail(QPGF_E_ARG, "the plan has no grid (a failed qpgf_plan_set_workspace): set one again");
   qpgf_status st = check_instance(P, k, a1, a2);
   if (st != QPGF_OK) return st;
   if (P.p.kind == QPGF_KIND_G2D_HESS_DIFF) {
     st = check_instance(P, k2, a1, a2);
     if (st != QPGF_OK) return st;
   }
-  HIP_TRY(set_far_geometry(P, std::max(k, k2)));
+  st = far_for(P, std::max(k, k2));
+  if (st != QPGF_OK) return st;
   P.last_k2 = k2;
   P.spec = has_special(P, k, a1, a2, P.M1) ||
            (P.p.kind == QPGF_KIND_G2D_HESS_DIFF && has_special(P, k2, a1, a2, P.M1));
@@ -297,10 +328,8 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
   P.last_a2 = a2;
   P.prepared = false;
   if (P.dim == 3) {
-    // H table must cover |xi| over the grid's modes
-    const double e1 = P.M1 / 2 + fabs(a1) + 1.0, e2 = P.M2 / 2 + fabs(a2) + 1.0;
-    const double e3 = (P.M3 / 2 + 1.0) * M_PI / P.p.c_tilde;
-    const int need = (int)(sqrt(e1 * e1 + e2 * e2 + e3 * e3) / P.hd) + 16;
+    // H table must cover |xi| over the grid's modes (allocated at creation for |alpha_i| <= 1)
+    const int need = htab_size(P, a1, a2);
     if (need > P.hn) {
       if (P.htab) HIP_TRY(hipFree(P.htab));
       P.htab = nullptr;
@@ -372,7 +401,35 @@ qpgf_status run_evaluate(Plan& P, const double* x, int64_t T, void* out, uint8_t
   if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
   if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
   if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  qpgf_status st = targets_fit(P, T);
+  if (st != QPGF_OK) return st;
   HIP_TRY(launch_gather(P, x, T, out, flags));
+  return QPGF_OK;
+}
+
+// The workspace's parts, each 256-byte aligned: near grid, its interleaved copy, the far slab
+// of the largest instance (kmax), the target scratch of T targets.
+struct WsLayout {
+  size_t grid = 0, gridI = 0, far = 0, scratch = 0, total = 0;
+  int nkeys = 0;
+};
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+WsLayout ws_layout(const Plan& P, double kmax, int64_t T) {
+  WsLayout L;
+  L.grid = al256((size_t)P.nf * P.ncell * P.esize);
+  L.gridI = al256(P.gridI_bytes);
+  const FarGeom g = far_geometry(P, kmax, P.M1);
+  L.far = al256((size_t)P.nfo * g.Mf1 * g.Mf2 * g.S * P.esize);
+  L.nkeys = bin_keys_bound(P, g.Mf1, g.Mf2, g.S, g.P);
+  TargetScratch t;
+  L.scratch = carve_target_scratch(P, nullptr, T, L.nkeys, t);
+  L.total = L.grid + L.gridI + L.far + L.scratch;
+  return L;
+}
+
+qpgf_status check_ws_args(double kmax, int64_t T) {
+  if (!(kmax >= 0.0) || !std::isfinite(kmax)) return fail(QPGF_E_ARG, "kmax must be finite and >= 0");
+  if (T < 0 || T > (int64_t)0x7fffffff) return fail(QPGF_E_ARG, "max_targets must be in [0, 2^31 - 1]");
   return QPGF_OK;
 }
 
@@ -455,13 +512,18 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
 
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
   PLAN_TRY(set_far_geometry(P, 0.0));   // the smallest slab; instances that need more grow it
+  if (P.dim == 3) {
+    P.hn = htab_size(P, 1.0, 1.0);
+    PLAN_TRY(hipMalloc(reinterpret_cast<void**>(&P.htab), (size_t)P.hn * sizeof(double2)));
+  }
   // complex64 G: each node's quad of x1-neighbours (4 values, 32 bytes) while the quads stay about
   // L2-sized (measured: 4.4 MB of quads read 30 % faster than the grid row by row, 8.8 MB slower)
   const bool quads = P.dim == 2 && P.nf == 1 && P.p.prec == QPGF_C64 && 32 * P.ncell <= (5u << 20);
   if (P.dim == 2 && (P.nf > 1 || quads)) {
     // derivative kinds: the near fields interleaved per node; the complex64 G: node quads
     const size_t per = P.nf > 1 ? (size_t)P.nf : 4;
-    PLAN_TRY(hipMalloc(&P.gridI, per * P.ncell * P.esize));
+    P.gridI_bytes = per * P.ncell * P.esize;
+    PLAN_TRY(hipMalloc(&P.gridI, P.gridI_bytes));
   }
 
   const int Q = p->quad_q;
@@ -669,6 +731,8 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
   if (T < 0) return fail(QPGF_E_ARG, "T < 0");
   if (T > 0 && (!x || !out)) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
   if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  st = targets_fit(P, T);
+  if (st != QPGF_OK) return st;
   // The binning of the targets depends on the targets and the grid geometry
   // only: it runs on a second stream while the grids are prepared (fork after
   // the work already on the plan's stream, join before the gather).
@@ -676,7 +740,8 @@ static qpgf_status both(qpgf_plan* plan, int kind, double k, double a1, double a
   if (overlap) {
     // the tile keys of far targets depend on the instance's far slab
     if (!std::isfinite(k) || !std::isfinite(k2)) return fail(QPGF_E_ARG, "need finite k");
-    HIP_TRY(set_far_geometry(P, std::max(k, k2)));
+    st = far_for(P, std::max(k, k2));
+    if (st != QPGF_OK) return st;
     if (!P.side) HIP_TRY(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     if (!P.ev_fork) HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
     if (!P.ev_join) HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
@@ -721,6 +786,70 @@ qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double a1, double a2, const dou
 qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double a1, double a2, const double* x, int64_t T,
                            void* out, uint8_t* flags) {
   return both(plan, QPGF_KIND_MAXWELL3D, k, a1, a2, x, T, out, flags);
+}
+
+qpgf_status qpgf_plan_workspace_bytes(const qpgf_plan* plan, double kmax, int64_t max_targets, size_t* bytes) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, -1);
+  if (st != QPGF_OK) return st;
+  if (!bytes) return fail(QPGF_E_ARG, "bytes is NULL");
+  st = check_ws_args(kmax, max_targets);
+  if (st != QPGF_OK) return st;
+  *bytes = ws_layout(plan->P, kmax, max_targets).total;
+  return QPGF_OK;
+}
+
+qpgf_status qpgf_plan_set_workspace(qpgf_plan* plan, void* ptr, size_t bytes, double kmax, int64_t max_targets) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, -1);
+  if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
+  if (ptr) {
+    st = check_ws_args(kmax, max_targets);
+    if (st != QPGF_OK) return st;
+    if (reinterpret_cast<uintptr_t>(ptr) % 256) return fail(QPGF_E_ARG, "the workspace must be 256-byte aligned");
+  } else if (bytes) {
+    return fail(QPGF_E_ARG, "a NULL workspace must have 0 bytes");
+  }
+  const WsLayout L = ptr ? ws_layout(P, kmax, max_targets) : WsLayout{};
+  if (ptr && bytes < L.total)
+    return fail(QPGF_E_SIZE, "the workspace needs " + std::to_string(L.total) + " bytes (qpgf_plan_workspace_bytes)");
+  // nothing in flight may still use the arrays being replaced
+  HIP_TRY(hipStreamSynchronize(P.stream));
+  if (P.side) HIP_TRY(hipStreamSynchronize(P.side));
+  drain_timers(P);
+  if (!P.ws) {
+    for (void* q : {P.grid, P.gridI, P.far})
+      if (q) HIP_TRY(hipFree(q));
+  }
+  free_target_scratch(P.ts);
+  P.grid = P.gridI = P.far = nullptr;
+  P.far_cap = 0;
+  P.ws = nullptr;
+  P.ws_bytes = 0;
+  P.ws_kmax = 0.0;
+  P.ws_T = 0;
+  P.prepared = false;
+  P.bt_T = -1;
+  P.bt_x = nullptr;
+  if (ptr) {
+    char* b = static_cast<char*>(ptr);
+    P.ws = b;
+    P.ws_bytes = bytes;
+    P.ws_kmax = kmax;
+    P.ws_T = max_targets;
+    P.grid = b;
+    P.gridI = P.gridI_bytes ? b + L.grid : nullptr;
+    P.far = b + L.grid + L.gridI;
+    P.far_cap = L.far;
+    carve_target_scratch(P, b + L.grid + L.gridI + L.far, max_targets, L.nkeys, P.ts);
+  } else {
+    // the plan's own arrays again (the target scratch grows on demand)
+    HIP_TRY(hipMalloc(&P.grid, (size_t)P.nf * P.ncell * P.esize));
+    if (P.gridI_bytes) HIP_TRY(hipMalloc(&P.gridI, P.gridI_bytes));
+  }
+  HIP_TRY(set_far_geometry(P, 0.0));
+  return QPGF_OK;
 }
 
 }  // extern "C"
@@ -1025,6 +1154,8 @@ qpgf_status qpgf_evaluate_smooth(qpgf_plan* plan, const double* x, int64_t T, vo
   if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
   if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
   if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  st = targets_fit(P, T);
+  if (st != QPGF_OK) return st;
   HIP_TRY(launch_gather_smooth(P, x, T, out));
   return QPGF_OK;
 }

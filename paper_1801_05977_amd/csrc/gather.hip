@@ -1592,7 +1592,7 @@ hipError_t gather2d_impl(Plan& P, GArgs& A, const double* x, int64_t T_, void* o
   if (P.p.ring_interp) {
     hipError_t e = ensure_ring_scratch(P, T_);
     if (e != hipSuccess) return e;
-    A.ring_mask = P.ring_mask;
+    A.ring_mask = P.ts.ring_mask;
   }
   {
     KernelTimer t(P, QPGF_T_GATHER);   // the gather alone; the ring pass has its own timer
@@ -1713,34 +1713,34 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     P.bt_x = x;
   }
   B.t = Tl;
-  TRec* rec = reinterpret_cast<TRec*>(P.bin_rec);
+  TRec* rec = reinterpret_cast<TRec*>(P.ts.bin_rec);
   const bool lds_bins = Tl.nkeys <= kBinLdsKeys;
   const long chunk = (T_ + kBinBlocks - 1) / kBinBlocks;
   const hipStream_t bs = bin_stream ? bin_stream : P.stream;
   if (mode != kGatherBinned) {
     {
       KernelTimer t(P, QPGF_T_BIN, bs);
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.bin_novf, 1L);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.ts.bin_novf, 1L);
       if (lds_bins) {
         // LDS histogram sized to the key count (small ones leave LDS to kernels running beside)
         if (Tl.nkeys <= 4096)
           hipLaunchKernelGGL(k_bin_count<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.bin_cnt);
+                             P.ts.bin_cnt);
         else if (Tl.nkeys <= 16384)
           hipLaunchKernelGGL(k_bin_count<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.bin_cnt);
+                             P.ts.bin_cnt);
         else
           hipLaunchKernelGGL(k_bin_count<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.bin_cnt);
-        hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.bin_cnt,
-                           Tl.nkeys, kBinBlocks, P.bin_hist);
+                             P.ts.bin_cnt);
+        hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.ts.bin_cnt,
+                           Tl.nkeys, kBinBlocks, P.ts.bin_hist);
       } else {
         // large key spaces: one global atomic rank per target
-        hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, bs, P.bin_hist,
+        hipLaunchKernelGGL(k_zero_u32, dim3((Tl.nkeys + 255) / 256), dim3(256), 0, bs, P.ts.bin_hist,
                            (long)Tl.nkeys);
-        hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, bs, B, x, (long)T_, P.bin_hist, P.bin_keyrank);
+        hipLaunchKernelGGL(k_bin_key, grid, dim3(256), 0, bs, B, x, (long)T_, P.ts.bin_hist, P.ts.bin_keyrank);
       }
-      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, bs, P.bin_hist, P.bin_offs, Tl.nkeys);
+      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, bs, P.ts.bin_hist, P.ts.bin_offs, Tl.nkeys);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -1748,15 +1748,15 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
       KernelTimer t(P, QPGF_T_BIN_PLACE, bs);
       if (lds_bins && Tl.nkeys <= 4096)
         hipLaunchKernelGGL(k_bin_place<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.bin_cnt, P.bin_offs, rec);
+                           P.ts.bin_cnt, P.ts.bin_offs, rec);
       else if (lds_bins && Tl.nkeys <= 16384)
         hipLaunchKernelGGL(k_bin_place<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.bin_cnt, P.bin_offs, rec);
+                           P.ts.bin_cnt, P.ts.bin_offs, rec);
       else if (lds_bins)
         hipLaunchKernelGGL(k_bin_place<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.bin_cnt, P.bin_offs, rec);
+                           P.ts.bin_cnt, P.ts.bin_offs, rec);
       else
-        hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.bin_keyrank, P.bin_offs, (long)T_, rec);
+        hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.ts.bin_keyrank, P.ts.bin_offs, (long)T_, rec);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -1766,10 +1766,10 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     const dim3 tn(Tl.nnear), tf(Tl.nfar + 1);
 #define QPGF_NEAR(A1_, A2_, A3_, BS_)                                                                             \
   hipLaunchKernelGGL((k_gather3d_near<T, NF, A1_, A2_, A3_, BS_>), tn, dim3(BS_), 0, P.stream, A, Tl, g, rec,     \
-                     P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
+                     P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
 #define QPGF_FAR(A1_, A2_, A3_)                                                                                    \
   hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
-                     P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf)
+                     P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
     // far tiles first (more targets and work each), then the near tiles
     {
       KernelTimer t(P, QPGF_T_GATHER_FAR);
@@ -1781,7 +1781,7 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     if constexpr (NF > 1) {
       if (C.fields)
         hipLaunchKernelGGL((k_gather3d_near_fields<T, NF, 4, 4, 3>), tn, dim3(256), 0, P.stream, A, Tl, g, rec,
-                           P.bin_hist, P.bin_offs, o, flags, P.bin_ovf, P.bin_novf);
+                           P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf);
       else if constexpr (sizeof(T) == 8) QPGF_NEAR(3, 2, 2, 256);
       else QPGF_NEAR(3, 3, 2, 256);
     } else if (C.big) {
@@ -1796,8 +1796,8 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     if (e != hipSuccess) return e;
   }
   KernelTimer t(P, QPGF_T_OVERFLOW);
-  hipLaunchKernelGGL((k_gather3d_overflow<T, NF>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.bin_ovf,
-                     P.bin_novf, o, flags);
+  hipLaunchKernelGGL((k_gather3d_overflow<T, NF>), dim3(64), dim3(256), 0, P.stream, A, g, f, rec, P.ts.bin_ovf,
+                     P.ts.bin_novf, o, flags);
   return hipGetLastError();
 }
 
@@ -1833,48 +1833,112 @@ hipError_t launch_interleave2d(Plan& P) {
 }
 
 hipError_t ensure_ring_scratch(Plan& P, int64_t T_) {
+  TargetScratch& S = P.ts;
   const int64_t words = (T_ + 63) / 64;
-  if (words <= P.ring_words) return hipSuccess;
-  if (P.ring_mask) (void)hipFree(P.ring_mask);
-  P.ring_mask = nullptr;
-  P.ring_words = 0;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&P.ring_mask), (size_t)words * sizeof(unsigned long long));
+  if (words <= S.ring_words) return hipSuccess;
+  if (S.ext) return hipErrorInvalidValue;   // callers check the capacity first
+  if (S.ring_mask) (void)hipFree(S.ring_mask);
+  S.ring_mask = nullptr;
+  S.ring_words = 0;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&S.ring_mask), (size_t)words * sizeof(unsigned long long));
   if (e != hipSuccess) return e;
-  P.ring_words = words;
+  S.ring_words = words;
   return hipSuccess;
 }
 
 hipError_t ensure_bin_scratch(Plan& P, int64_t T_, int nkeys) {
-  if (T_ > P.bin_cap) {
-    for (void* q : {(void*)P.bin_keyrank, (void*)P.bin_rec, (void*)P.bin_ovf})
-      if (q) (void)hipFree(q);
-    P.bin_keyrank = nullptr;
-    P.bin_rec = nullptr;
-    P.bin_ovf = nullptr;
-    P.bin_cap = 0;
-    hipError_t e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_keyrank), (size_t)T_ * sizeof(uint2))) != hipSuccess) return e;
-    if ((e = hipMalloc(&P.bin_rec, (size_t)T_ * sizeof(TRec))) != hipSuccess) return e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_ovf), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
-    P.bin_cap = T_;
+  TargetScratch& S = P.ts;
+  if (S.ext) {
+    const bool fits = T_ <= S.bin_cap && nkeys <= S.bin_keycap && (nkeys > kBinLdsKeys || nkeys <= S.bin_cntkeys);
+    return fits ? hipSuccess : hipErrorInvalidValue;
   }
-  if (nkeys > P.bin_keycap) {
-    for (void* q : {(void*)P.bin_hist, (void*)P.bin_offs, (void*)P.bin_cnt})
+  if (T_ > S.bin_cap) {
+    for (void* q : {(void*)S.bin_keyrank, (void*)S.bin_rec, (void*)S.bin_ovf})
       if (q) (void)hipFree(q);
-    P.bin_hist = nullptr;
-    P.bin_offs = nullptr;
-    P.bin_cnt = nullptr;
-    P.bin_keycap = 0;
+    S.bin_keyrank = nullptr;
+    S.bin_rec = nullptr;
+    S.bin_ovf = nullptr;
+    S.bin_cap = 0;
     hipError_t e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_hist), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_offs), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
-    if (!P.bin_novf && (e = hipMalloc(reinterpret_cast<void**>(&P.bin_novf), sizeof(uint32_t))) != hipSuccess) return e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&P.bin_cnt), (size_t)nkeys * kBinBlocks * sizeof(uint32_t))) !=
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.bin_keyrank), (size_t)T_ * sizeof(uint2))) != hipSuccess) return e;
+    if ((e = hipMalloc(&S.bin_rec, (size_t)T_ * sizeof(TRec))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.bin_ovf), (size_t)T_ * sizeof(uint32_t))) != hipSuccess) return e;
+    S.bin_cap = T_;
+  }
+  if (nkeys > S.bin_keycap) {
+    for (void* q : {(void*)S.bin_hist, (void*)S.bin_offs, (void*)S.bin_cnt})
+      if (q) (void)hipFree(q);
+    S.bin_hist = nullptr;
+    S.bin_offs = nullptr;
+    S.bin_cnt = nullptr;
+    S.bin_keycap = 0;
+    S.bin_cntkeys = 0;
+    hipError_t e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.bin_hist), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.bin_offs), (size_t)nkeys * sizeof(uint32_t))) != hipSuccess) return e;
+    if (!S.bin_novf && (e = hipMalloc(reinterpret_cast<void**>(&S.bin_novf), sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.bin_cnt), (size_t)nkeys * kBinBlocks * sizeof(uint32_t))) !=
         hipSuccess)
       return e;
-    P.bin_keycap = nkeys;
+    S.bin_keycap = nkeys;
+    S.bin_cntkeys = nkeys;
   }
   return hipSuccess;
+}
+
+void free_target_scratch(TargetScratch& S) {
+  if (!S.ext) {
+    for (void* q : {(void*)S.ring_mask, (void*)S.bin_keyrank, S.bin_rec, (void*)S.bin_hist, (void*)S.bin_offs,
+                    (void*)S.bin_cnt, (void*)S.bin_ovf, (void*)S.bin_novf})
+      if (q) (void)hipFree(q);
+  }
+  S = TargetScratch{};
+}
+
+// The tile choices of gather3d_impl, taken at their largest key counts: the near tiles of the
+// kind (Maxwell: the smaller of its two configurations), the 8-node far tiles unless their keys
+// overflow the LDS histograms, else the larger far tiles.  Any slab up to (Mf1, Mf2, S) has at
+// most this many keys: with the small far tiles the keys stay within kBinLdsKeys.
+int bin_keys_bound(const Plan& P, int Mf1, int Mf2, int S, int fp) {
+  if (P.dim != 3) return 0;
+  const bool c64 = P.esize == 8;
+  auto tiles = [](int n, int b) { return std::max(1, n >> b); };
+  long nnear = (long)tiles(P.M1, 4) * tiles(P.M2, 4) * tiles(P.M3, 3);
+  if (P.nf > 1) nnear = std::max(nnear, (long)tiles(P.M1, 3) * tiles(P.M2, c64 ? 3 : 2) * tiles(P.M3, 2));
+  const long fnt3 = ((S - 1 - fp / 2) >> 3) + 1;
+  const long small = (long)tiles(Mf1, 3) * tiles(Mf2, 3) * fnt3;
+  const long big = (long)tiles(Mf1, 4) * tiles(Mf2, c64 ? 4 : 3) * fnt3;
+  const long ks = nnear + small + 1;
+  return (int)(ks <= kBinLdsKeys ? ks : std::max<long>(kBinLdsKeys, nnear + big + 1));
+}
+
+size_t carve_target_scratch(const Plan& P, char* base, int64_t T_, int nkeys, TargetScratch& S) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  TargetScratch t;
+  t.ext = true;
+  if (P.dim == 3) {
+    const int cntkeys = std::min(nkeys, kBinLdsKeys);
+    t.bin_cap = T_;
+    t.bin_keycap = nkeys;
+    t.bin_cntkeys = cntkeys;
+    t.bin_keyrank = reinterpret_cast<uint2*>(take((size_t)T_ * sizeof(uint2)));
+    t.bin_rec = take((size_t)T_ * sizeof(TRec));
+    t.bin_ovf = reinterpret_cast<uint32_t*>(take((size_t)T_ * sizeof(uint32_t)));
+    t.bin_hist = reinterpret_cast<uint32_t*>(take((size_t)nkeys * sizeof(uint32_t)));
+    t.bin_offs = reinterpret_cast<uint32_t*>(take((size_t)nkeys * sizeof(uint32_t)));
+    t.bin_novf = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t)));
+    t.bin_cnt = reinterpret_cast<uint32_t*>(take((size_t)cntkeys * kBinBlocks * sizeof(uint32_t)));
+  } else if (P.p.ring_interp) {
+    t.ring_words = (T_ + 63) / 64;
+    t.ring_mask = reinterpret_cast<unsigned long long*>(take((size_t)t.ring_words * sizeof(unsigned long long)));
+  }
+  if (base) S = t;
+  return off;
 }
 
 void gather_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, long off, long foff, long t0,

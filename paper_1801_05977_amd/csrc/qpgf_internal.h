@@ -114,6 +114,23 @@ struct FftSeg {
 };
 constexpr int kMaxLog2 = 12;   // m <= 4096
 
+// Per-call target scratch of the gathers.
+struct TargetScratch {
+  bool ext = false;                    // not owned by the plan: never grown or freed
+  int64_t bin_cap = 0;                 // targets the per-target arrays hold
+  int bin_keycap = 0;                  // keys hist / offs hold
+  int bin_cntkeys = 0;                 // keys the per-(block, key) counts hold (LDS-histogram binning)
+  uint2* bin_keyrank = nullptr;
+  void* bin_rec = nullptr;             // targets in tile order (32-byte records)
+  uint32_t* bin_hist = nullptr;
+  uint32_t* bin_offs = nullptr;
+  uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
+  uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
+  uint32_t* bin_novf = nullptr;        // their count
+  unsigned long long* ring_mask = nullptr;  // 2D kinds, ring_interp: one bit per target, set for the
+  int64_t ring_words = 0;                   // targets of the cut-off ring (ring_words 64-bit words)
+};
+
 struct Plan {
   qpgf_params p;
   int dim = 2, nf = 1;         // nf: number of near fields (kMxF or kMxT for Maxwell)
@@ -146,6 +163,13 @@ struct Plan {
   int twlog2 = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
+  size_t gridI_bytes = 0;      // its size (0: none)
+  // caller-owned workspace (qpgf_plan_set_workspace): grid, gridI, far and the target scratch
+  // live in it; instances up to ws_kmax and calls of up to ws_T targets fit
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double ws_kmax = 0.0;
+  int64_t ws_T = 0;
   void* gridI = nullptr;       // 2D derivative kinds: the near fields interleaved, [i2][i1][field];
                                // complex64 G: node quads [i2][i1][a] = grid[i2][i1 + a]
   double* E2 = nullptr;        // 2D G with sing_order >= 2: [4][j2'][j1'] real tables of the removed
@@ -160,19 +184,11 @@ struct Plan {
   bool spec = false;           // the prepared instance has a special coefficient (fills take that path)
   bool prepared = false;
 
-  // target binning scratch (3D), grown on demand
+  // target binning scratch (3D) and ring mask (2D ring_interp): grown on demand while the plan
+  // owns it (scratch_ext false); otherwise memory the plan does not own (a caller's workspace, or
+  // the library's fixed scratch during one call), whose capacities are never exceeded
   int64_t bin_min_targets = 1 << 16;   // bin when T >= this; < 0 never
-  int64_t bin_cap = 0;
-  int bin_keycap = 0;
-  uint2* bin_keyrank = nullptr;
-  void* bin_rec = nullptr;             // targets in tile order (32-byte records)
-  uint32_t* bin_hist = nullptr;
-  uint32_t* bin_offs = nullptr;
-  uint32_t* bin_cnt = nullptr;         // per-(block, key) counts / bases
-  unsigned long long* ring_mask = nullptr;  // 2D kinds, ring_interp: one bit per target, set for the
-  int64_t ring_words = 0;                   // targets of the cut-off ring (ring_words 64-bit words)
-  uint32_t* bin_ovf = nullptr;         // sorted positions handed to the overflow kernel
-  uint32_t* bin_novf = nullptr;        // their count
+  TargetScratch ts;
   // tile configuration of the last binning (launch_bin3d), used by launch_gather_binned
   int bt[24] = {};                     // the tile configuration (near and far tiles, key counts)
   int64_t bt_T = -1;
@@ -263,6 +279,12 @@ hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, 
 hipError_t launch_gather(Plan& P, const double* x, int64_t T, void* out, uint8_t* flags);
 hipError_t ensure_bin_scratch(Plan& P, int64_t T, int nkeys);
 hipError_t ensure_ring_scratch(Plan& P, int64_t T);
+// Upper bound of the binning keys of any 3D evaluate on far slabs up to (Mf1, Mf2, S) (0 for 2D).
+int bin_keys_bound(const Plan& P, int Mf1, int Mf2, int S, int fp);
+// Lay out target scratch for T targets and nkeys keys at base (256-byte aligned; NULL: only size
+// it); returns the bytes used.  With base set, ts points into it (ext = true).
+size_t carve_target_scratch(const Plan& P, char* base, int64_t T, int nkeys, TargetScratch& ts);
+void free_target_scratch(TargetScratch& ts);
 hipError_t launch_gather_smooth(Plan& P, const double* x, int64_t T, void* out);
 // The 3D calculation step in two halves: binning of the targets by grid tile
 // (needs only the targets and the plan's geometry, so it may run on another

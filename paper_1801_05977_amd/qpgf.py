@@ -59,7 +59,7 @@ EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
            "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration",
            "qpgf_mlp_get_calibration", "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate",
-           "qpgf_mlp_save", "qpgf_mlp_load"]
+           "qpgf_mlp_save", "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch", "bin_place",
           "overflow", "layout", "ring", "gather_far"]
 
@@ -123,6 +123,8 @@ def lib():
     L.qpgf_surrogate_train.argtypes = [P, VP, VP, I64, ctypes.POINTER(TrainCfg), VP]
     L.qpgf_surrogate_calibrate.argtypes = [P, P, ctypes.c_int, DP, DP, DP, ctypes.POINTER(ctypes.c_int64), VP, D, D,
                                            DP]
+    L.qpgf_plan_workspace_bytes.argtypes = [P, D, I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.qpgf_plan_set_workspace.argtypes = [P, VP, ctypes.c_size_t, D, I64]
     L.qpgf_mlp_save.argtypes = [P, ctypes.c_char_p]
     L.qpgf_mlp_load.argtypes = [P, ctypes.c_char_p]
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
@@ -132,7 +134,7 @@ def lib():
                  "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
                  "qpgf_mlp_train_step", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration", "qpgf_mlp_get_calibration",
                  "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate", "qpgf_mlp_save",
-                 "qpgf_mlp_load"):
+                 "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -196,6 +198,26 @@ class Plan:
 
     def _stream(self):
         _check(lib().qpgf_plan_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def workspace_bytes(self, kmax, max_targets):
+        n = ctypes.c_size_t()
+        _check(lib().qpgf_plan_workspace_bytes(self._h, float(kmax), int(max_targets), ctypes.byref(n)))
+        return n.value
+
+    def use_workspace(self, kmax, max_targets, buf=None):
+        """qpgf_plan_set_workspace on a torch uint8 buffer (allocated here when not given); the plan keeps a
+        reference to it.  use_workspace(None, None) returns the plan to its own arrays."""
+        self._stream()
+        if kmax is None:
+            _check(lib().qpgf_plan_set_workspace(self._h, None, 0, 0.0, 0))
+            self._ws = None
+            return None
+        if buf is None:
+            buf = torch.empty(self.workspace_bytes(kmax, max_targets), dtype=torch.uint8, device="cuda")
+        _check(lib().qpgf_plan_set_workspace(self._h, _ptr(buf, torch.uint8, "workspace"), buf.numel(),
+                                             float(kmax), int(max_targets)))
+        self._ws = buf
+        return buf
 
     def out_tensor(self, T):
         shape = {KIND_MAXWELL3D: (T, 6), KIND_G2D_GRAD: (T, 2), KIND_G2D_HESS_DIFF: (T, 3)}.get(self.kind, (T,))

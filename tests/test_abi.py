@@ -122,3 +122,11 @@ def test_surrogate_training_and_checkpoint_entry_points_validate():
     assert L.qpgf_mlp_save(None, b"/nonexistent/x") == 1
     assert L.qpgf_mlp_load(None, b"/nonexistent/x") == 1
     assert "NULL" in L.qpgf_mlp_last_error().decode()
+
+
+def test_workspace_entry_points_validate():
+    L = qpgf.lib()
+    n = ctypes.c_size_t()
+    assert L.qpgf_plan_workspace_bytes(None, 1.0, 10, ctypes.byref(n)) == 1
+    assert L.qpgf_plan_set_workspace(None, None, 0, 1.0, 10) == 1
+    assert "NULL" in L.qpgf_last_error().decode()
