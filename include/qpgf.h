@@ -205,6 +205,22 @@ qpgf_status qpgf_prepare(qpgf_plan* plan, double k, double a1, double a2);
  * ([T], [T][6] for MAXWELL3D, [T][2] for G2D_GRAD, [T][3] for G2D_HESS_DIFF);
  * flags: device uint8 [T] or NULL.  T = 0 is a no-op. */
 qpgf_status qpgf_evaluate(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qpgf_evaluate with the
+ * same arguments, kernels and results, whose per-call target scratch (the
+ * binning of 3D targets, the ring mask of 2D ring_interp) lives in a fixed
+ * 64 MiB device array of the library instead of memory the plan allocates.
+ * Each GPU the library runs on holds its own copy of that array until the
+ * process ends (the first call on a device looks its address up).  The call
+ * allocates nothing; the plan's grids must exist (a prepare before it, on a
+ * plan that owns its arrays or has a workspace).  Every call on one GPU, from
+ * any plan, shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * The scratch is cleared by the call's own kernels where it must start at
+ * zero.  The plan's device must be current.  Errors: as qpgf_evaluate, and
+ * QPGF_E_SIZE when the scratch of T targets does not fit (the message gives
+ * the most that do for this plan: about 1e6 for a 256 x 256 x 64 GD3D plan). */
+qpgf_status qpgf_evaluate_noalloc(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags);
 
 /* prepare + evaluate: G (kind G2D), G_d (GD3D) and GG (MAXWELL3D) at T targets. */
 qpgf_status qpgf_g2d(qpgf_plan* plan, double k, double alpha,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -410,7 +411,7 @@ qpgf_status run_evaluate(Plan& P, const double* x, int64_t T, void* out, uint8_t
 // The workspace's parts, each 256-byte aligned: near grid, its interleaved copy, the far slab
 // of the largest instance (kmax), the target scratch of T targets.
 struct WsLayout {
-  size_t grid = 0, gridI = 0, far = 0, scratch = 0, total = 0;
+  size_t grid = 0, gridI = 0, far = 0, targets = 0, total = 0;
   int nkeys = 0;
 };
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -422,8 +423,8 @@ WsLayout ws_layout(const Plan& P, double kmax, int64_t T) {
   L.far = al256((size_t)P.nfo * g.Mf1 * g.Mf2 * g.S * P.esize);
   L.nkeys = bin_keys_bound(P, g.Mf1, g.Mf2, g.S, g.P);
   TargetScratch t;
-  L.scratch = carve_target_scratch(P, nullptr, T, L.nkeys, t);
-  L.total = L.grid + L.gridI + L.far + L.scratch;
+  L.targets = carve_target_scratch(P, nullptr, T, L.nkeys, t);
+  L.total = L.grid + L.gridI + L.far + L.targets;
   return L;
 }
 
@@ -444,6 +445,35 @@ void drain_timers(Plan& P) {
     (void)hipEventDestroy(e.b);
   }
   P.pending.clear();
+}
+
+// Fixed target scratch of qpgf_evaluate_noalloc: each GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the name for memory: the per-device address
+// comes from hipGetSymbolAddress (scratch_address).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// The device address of the current GPU's copy of the scratch, looked up on the first call on
+// each device (with that device current) and kept.
+qpgf_status scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(QPGF_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QPGF_E_HIP, "hipGetSymbolAddress returned NULL for the fixed scratch");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return QPGF_OK;
 }
 
 }  // namespace
@@ -510,6 +540,7 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
     if (s_ != QPGF_OK) return bail(s_); \
   } while (0)
 
+  PLAN_TRY(hipGetDevice(&P.device));
   PLAN_TRY(hipMalloc(&P.grid, P.nf * P.ncell * P.esize));
   PLAN_TRY(set_far_geometry(P, 0.0));   // the smallest slab; instances that need more grow it
   if (P.dim == 3) {
@@ -786,6 +817,48 @@ qpgf_status qpgf_gd3d(qpgf_plan* plan, double k, double a1, double a2, const dou
 qpgf_status qpgf_maxwell3d(qpgf_plan* plan, double k, double a1, double a2, const double* x, int64_t T,
                            void* out, uint8_t* flags) {
   return both(plan, QPGF_KIND_MAXWELL3D, k, a1, a2, x, T, out, flags);
+}
+
+qpgf_status qpgf_evaluate_noalloc(qpgf_plan* plan, const double* x, int64_t T, void* out, uint8_t* flags) {
+  g_err.clear();
+  qpgf_status st = check_plan(plan, -1);
+  if (st != QPGF_OK) return st;
+  Plan& P = plan->P;
+  if (T < 0) return fail(QPGF_E_ARG, "T < 0");
+  if (T == 0) return QPGF_OK;
+  if (!x || !out) return fail(QPGF_E_ARG, "x and out must be non-NULL device pointers");
+  if (!P.prepared) return fail(QPGF_E_ARG, "evaluate before a complete prepare");
+  if (T > (int64_t)0x7fffffff) return fail(QPGF_E_SIZE, "at most 2^31 - 1 targets per call");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != P.device) return fail(QPGF_E_ARG, "make the plan's device current");
+  const int nkeys = bin_keys_bound(P, P.Mf1, P.Mf2, P.S, P.fp);
+  TargetScratch mine;
+  if (carve_target_scratch(P, nullptr, T, nkeys, mine) > kNoAllocScratchBytes) {
+    int64_t lo = 0, hi = T;   // the most targets whose scratch fits
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (carve_target_scratch(P, nullptr, mid, nkeys, mine) <= kNoAllocScratchBytes) lo = mid;
+      else hi = mid - 1;
+    }
+    return fail(QPGF_E_SIZE, "qpgf_evaluate_noalloc: at most " + std::to_string(lo) +
+                                 " targets per call fit the fixed scratch of this plan's geometry (64 MiB)");
+  }
+  char* base = nullptr;
+  st = scratch_address(dev, &base);
+  if (st != QPGF_OK) return st;
+  carve_target_scratch(P, base, T, nkeys, mine);
+  // the plan's own scratch is set aside for the call; timers (which create events) are off
+  const bool timing = P.timing;
+  P.timing = false;
+  std::swap(P.ts, mine);
+  const hipError_t e = launch_gather(P, x, T, out, flags);
+  std::swap(P.ts, mine);
+  P.timing = timing;
+  P.bt_T = -1;
+  P.bt_x = nullptr;
+  if (e != hipSuccess) return hip_fail(e, "launch_gather (fixed scratch)");
+  return QPGF_OK;
 }
 
 qpgf_status qpgf_plan_workspace_bytes(const qpgf_plan* plan, double kmax, int64_t max_targets, size_t* bytes) {
@@ -1073,9 +1146,9 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
   }
   size_t need = 0;
   for (const Shape& s : shapes) need = std::max(need, (size_t)s.n * s.batch * P.esize);
-  void* scratch = nullptr;
-  HIP_TRY(hipMalloc(&scratch, need));
-  HIP_TRY(hipMemset(scratch, 0, need));
+  void* tune_buf = nullptr;
+  HIP_TRY(hipMalloc(&tune_buf, need));
+  HIP_TRY(hipMemset(tune_buf, 0, need));
   hipEvent_t a = nullptr, b = nullptr;
   HIP_TRY(hipEventCreate(&a));
   HIP_TRY(hipEventCreate(&b));
@@ -1100,16 +1173,16 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
       const long es = s.rows ? 1 : s.batch;
       const long b_in = s.rows ? 1 : s.batch, s_in = s.rows ? 0 : 1, s_out = s.rows ? s.n : 0;
       hipError_t e = hipSuccess;
-      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_fft(P, scratch, s.n, es, s.batch, b_in, s_in, s_out);
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_fft(P, tune_buf, s.n, es, s.batch, b_in, s_in, s_out);
       if (e == hipSuccess) e = hipEventRecord(a, P.stream);
-      for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_fft(P, scratch, s.n, es, s.batch, b_in, s_in, s_out);
+      for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_fft(P, tune_buf, s.n, es, s.batch, b_in, s_in, s_out);
       if (e == hipSuccess) e = hipEventRecord(b, P.stream);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       if (e != hipSuccess) {
         P.timing = timing;
-        (void)hipFree(scratch);
+        (void)hipFree(tune_buf);
         return hip_fail(e, "autotune");
       }
       const double us = 1000.0 * ms / 5;
@@ -1131,7 +1204,7 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
   P.timing = timing;
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  (void)hipFree(scratch);
+  (void)hipFree(tune_buf);
   free_batch(P);   // a captured batched graph used the old tiles
   if (cache_path && !lines.empty()) {
     if (FILE* f = fopen(cache_path, "a")) {

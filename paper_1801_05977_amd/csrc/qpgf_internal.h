@@ -216,6 +216,7 @@ struct Plan {
   // per-kernel timing (qpgf_plan_enable_timing)
   struct Pending { int id; hipEvent_t a, b; };
   bool timing = false;
+  int device = 0;              // the GPU the plan's arrays live on (current at creation)
   std::vector<Pending> pending;
   double t_ms[QPGF_T_COUNT] = {};
   int64_t t_n[QPGF_T_COUNT] = {};

@@ -59,7 +59,8 @@ EXPORTS = ["qpgf_params_default", "qpgf_plan_create", "qpgf_plan_destroy", "qpgf
            "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
            "qpgf_mlp_train_step", "qpgf_mlp_last_error", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration",
            "qpgf_mlp_get_calibration", "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate",
-           "qpgf_mlp_save", "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace"]
+           "qpgf_mlp_save", "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace",
+           "qpgf_evaluate_noalloc"]
 TIMERS = ["htable", "fill", "fft_t", "fft_2", "fft_1", "far", "far_fft", "gather", "bin", "batch", "bin_place",
           "overflow", "layout", "ring", "gather_far"]
 
@@ -125,6 +126,7 @@ def lib():
                                            DP]
     L.qpgf_plan_workspace_bytes.argtypes = [P, D, I64, ctypes.POINTER(ctypes.c_size_t)]
     L.qpgf_plan_set_workspace.argtypes = [P, VP, ctypes.c_size_t, D, I64]
+    L.qpgf_evaluate_noalloc.argtypes = [P, VP, I64, VP, U8P]
     L.qpgf_mlp_save.argtypes = [P, ctypes.c_char_p]
     L.qpgf_mlp_load.argtypes = [P, ctypes.c_char_p]
     for name in ("qpgf_plan_create", "qpgf_plan_set_stream", "qpgf_plan_get_info", "qpgf_prepare",
@@ -134,7 +136,8 @@ def lib():
                  "qpgf_mlp_get_params", "qpgf_mlp_set_params", "qpgf_mlp_forward", "qpgf_mlp_gradient",
                  "qpgf_mlp_train_step", "qpgf_surrogate_eval", "qpgf_mlp_set_calibration", "qpgf_mlp_get_calibration",
                  "qpgf_surrogate_make_data", "qpgf_surrogate_train", "qpgf_surrogate_calibrate", "qpgf_mlp_save",
-                 "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace"):
+                 "qpgf_mlp_load", "qpgf_plan_workspace_bytes", "qpgf_plan_set_workspace",
+                 "qpgf_evaluate_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
