@@ -583,14 +583,22 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
       }
     PLAN_ST(upload(&P.cs, cs));
   }
-  // radial rule on [eps, 2 eps] with Y', Y'' at the nodes
-  std::vector<double> rq(Q), wrq(Q), y1q(Q), y2q(Q);
+  // radial rule on [eps, 2 eps] with Y', Y'' at the nodes.  Its integrands carry J0(|eta| r),
+  // sin(rho r) up to the grid's largest frequency (2D: |eta| of the corner mode; 3D: the end of the
+  // H table); measured, the rule reaches rounding with about 0.065 |eta| + 16 nodes (80 at |eta| =
+  // 1043, the corner of 2048 x 128), so it takes max(quad_q, 0.07 |eta| + 24) of them.
+  const double eta_max = P.dim == 2 ? std::hypot(P.M1 / 2 + 1.0, (P.M2 / 2) * M_PI / p->c_tilde) : P.hn * P.hd;
+  P.Qr = std::max(Q, 8 * (int)std::ceil((0.07 * eta_max + 24.0) / 8.0));
+  const int Qr = P.Qr;
+  std::vector<long double> rx, rw;
+  gauss_legendre(Qr, rx, rw);
+  std::vector<double> rq(Qr), wrq(Qr), y1q(Qr), y2q(Qr);
   {
     const long double e = p->eps;
-    for (int q = 0; q < Q; ++q) {
-      long double r = e + 0.5L * e * (gx[q] + 1.0L);
+    for (int q = 0; q < Qr; ++q) {
+      long double r = e + 0.5L * e * (rx[q] + 1.0L);
       rq[q] = (double)r;
-      wrq[q] = (double)(0.5L * e * gw[q]);
+      wrq[q] = (double)(0.5L * e * rw[q]);
       y1q[q] = cut_Y1(rq[q], p->eps);
       y2q[q] = cut_Y2(rq[q], p->eps);
     }
@@ -651,9 +659,9 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   }
   if (p->kind == QPGF_KIND_G2D) {
     // Phi_1(r) = (2 + ln r) Y'(r)/r + Y''(r) ln r at the radial nodes, times the weights
-    std::vector<double> wphi(Q);
+    std::vector<double> wphi(Qr);
     long double f1tail = 0.0L;
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < Qr; ++q) {
       long double r = rq[q], lr = logl(r);
       wphi[q] = (double)(wrq[q] * ((2.0L + lr) * y1q[q] / r + y2q[q] * lr));
       f1tail += (long double)wrq[q] * r * lr * cut_Y(rq[q], p->eps);

@@ -34,6 +34,7 @@ struct FillArgs {
                              // the grid sum L_N = sum L-hat_j phi_j another; both are
                              // applied here so the FFTs are plain sums)
   int M1, M2, Mt, Q;
+  int Qr;                    // nodes of the radial rule
   double hd;                 // H table spacing (3D)
   long fstride;              // elements per field
   // special coefficients (a propagating beta within stol of |J|, Sections 2.1 / 3.1)
@@ -142,7 +143,7 @@ __device__ double2 fhat_direct(double k, double rho, const FillArgs& A) {
   // int_0^eps e^{ikr} sin(rho r) dr = (eps / 2i) [E1(i(k + rho) eps) - E1(i(k - rho) eps)]
   const double2 d = csub(e1i((k + rho) * e), e1i((k - rho) * e));
   double2 s = mk(0.5 * e * d.y, -0.5 * e * d.x);
-  for (int q = 0; q < A.Q; ++q) {
+  for (int q = 0; q < A.Qr; ++q) {
     const double r = A.rq[q];
     double sn, cn;
     sincos(k * r, &sn, &cn);
@@ -843,6 +844,7 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
   A.wXq = P.wXq;
   A.rq = P.rq;
   A.wrq = P.wrq;
+  A.Qr = P.Qr;
   A.eps = P.p.eps;
   A.E = P.E2;
   A.sing_order = P.p.sing_order;
@@ -942,7 +944,7 @@ hipError_t launch_sing2d(Plan& P, double f1zero) {
   const long n = (long)P.M1 * P.M2;
   const double A2 = 1.0 / (2.0 * sqrt(kPi * P.p.c_tilde));
   hipLaunchKernelGGL(k_sing2d, dim3((n + 255) / 256), dim3(256), 0, P.stream, P.M1, P.M2, P.p.c_tilde, A2,
-                     P.p.quad_q, P.rq, P.wrq, f1zero, P.F1, P.F2);
+                     P.Qr, P.rq, P.wrq, f1zero, P.F1, P.F2);
   return hipGetLastError();
 }
 
@@ -971,7 +973,7 @@ hipError_t launch_sing2d_hess(Plan& P, int Qg, const double* rg, const double* w
 }
 
 hipError_t launch_htable(Plan& P, double k) {
-  hipLaunchKernelGGL(k_htable, dim3((P.hn + 3) / 4), dim3(256), 0, P.stream, P.hn, P.hd, k, P.p.quad_q, P.rq,
+  hipLaunchKernelGGL(k_htable, dim3((P.hn + 3) / 4), dim3(256), 0, P.stream, P.hn, P.hd, k, P.Qr, P.rq,
                      P.wrq, P.y1q, P.y2q, P.htab);
   return hipGetLastError();
 }
@@ -996,6 +998,7 @@ void fill_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg, 
   I.A.wXq = P.wXq;
   I.A.rq = P.rq;
   I.A.wrq = P.wrq;
+  I.A.Qr = P.Qr;
   I.A.eps = P.p.eps;
   I.A.k2 = 0.0;
   I.A.E = P.E2;

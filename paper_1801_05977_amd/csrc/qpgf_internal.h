@@ -177,6 +177,7 @@ struct Plan {
   double* D2 = nullptr;        // 2D derivative tables: gradient [8][j2'][j1'] (a1 P1 Q1 R1 a2 P2 Q2 R2),
                                // second-derivative differences [6][j2'][j1'] (u11 v11 u12 v12 u22 v22)
   double2* htab = nullptr;     // 3D: H(rho) on rho = (m - 4) dh
+  int Qr = 0;                  // nodes of the radial rule rq, wrq, y1q, y2q
   int hn = 0;
   double hd = 0.05;
   double last_k = 0, last_a1 = 0, last_a2 = 0;

@@ -2,6 +2,7 @@
 and at parity with the CPU oracle; graph replay with new (k, alpha); autotuner."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -71,3 +72,44 @@ def test_batched_rejects_bad_instances():
     with pytest.raises(qpgf.QpgfError) as e:
         P.batched([2.1], [0.3], [512], [0, 10], x)                         # m1 above the plan's
     assert e.value.status == 4
+
+
+@pytest.mark.timeout(900)
+def test_batched_full_size_sampled():
+    """The batched benchmark workload: 64 instances (k ~ U[1,20], alpha ~ U[-1/2,1/2], Wood and
+    special cases redrawn), x1 sizes 256 .. 2048, 128 slices, 1e6 targets each, both precisions.
+
+    The GPU evaluates all 6.4e7 targets in one batched call; the oracle recomputes 200 seeded
+    targets of every instance (with its first and last) from that instance's own coefficients."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    n, per, M2 = 64, 1_000_000, 128
+    k, a = workloads.instances_2d(n, seed=1, k_range=(1.0, 20.0), n2_max=M2 // 2)
+    m1 = [int(256 << v) for v in np.random.default_rng(1).integers(0, 4, n)]
+    assert sorted(set(m1)) == [256, 512, 1024, 2048]
+    t_off = np.arange(n + 1, dtype=np.int64) * per
+    x = workloads.targets(n * per, 2, seed=1)
+    rng = np.random.default_rng(21)
+    picks = [np.unique(np.concatenate([[i * per, (i + 1) * per - 1], i * per + rng.choice(per, 198, replace=False)]))
+             for i in range(n)]
+    idx = np.concatenate(picks)
+    xd = torch.from_numpy(x).cuda()
+    sel = torch.from_numpy(idx).cuda()
+    outs = {}
+    for prec in (qpgf.C128, qpgf.C64):
+        P = qpgf.Plan(qpgf.KIND_G2D, prec, max(m1), M2)
+        outs[prec] = P.batched(k, a, m1, t_off, xd)[sel].cpu().numpy()
+        P.close()
+    del xd
+    # the oracle's instances in worker processes (numpy only; spawned, so they never touch the GPU)
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1), mp_context=mp.get_context("spawn")) as ex:
+        o = list(ex.map(method.eval_g2d, k, a, [x[p] for p in picks], [m // 2 for m in m1], [M2 // 2] * n))
+    for prec in (qpgf.C128, qpgf.C64):
+        off = 0
+        worst = []
+        for i, p in enumerate(picks):
+            g = outs[prec][off:off + len(p)]
+            off += len(p)
+            worst.append(parity(g, o[i]))
+        print("batched full size", "c128" if prec == qpgf.C128 else "c64", max(worst), int(np.argmax(worst)))
+        assert max(worst) <= TOL[prec], (int(np.argmax(worst)), max(worst))

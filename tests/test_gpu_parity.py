@@ -370,3 +370,34 @@ def test_gd3d_full_size_sampled():
     o = method.eval_gd3d(k, a1, a2, x[idx], M1 // 2, M2 // 2, M3 // 2)
     assert parity(outs[qpgf.C128], o) <= TOL[qpgf.C128]
     assert parity(outs[qpgf.C64], o) <= TOL[qpgf.C64]
+
+
+@pytest.mark.timeout(900)
+def test_maxwell3d_full_size_sampled():
+    """The Maxwell tensor at its benchmark size: k = 5.3, alpha = (0.1, 0.4), 512 x 512 modes, 32
+    slices, 1e6 targets, both precisions, every component on its own scale.
+
+    The GPU evaluates all 1e6 targets as the benchmark does; the oracle recomputes 400 of them
+    (seeded, with the first and the last, plus targets inside the cut-off ring of a lattice
+    point) from its own full-size coefficients of the seven fields."""
+    M1, M2, M3, T = 512, 512, 32, 1_000_000
+    k, a1, a2 = 5.3, 0.1, 0.4
+    x = workloads.targets(T, 3, seed=3)
+    rng = np.random.default_rng(12)
+    ring = rng.normal(size=(12, 3))
+    ring *= (rng.uniform(0.02, 0.38, 12) / np.linalg.norm(ring, axis=1))[:, None]
+    x[:12] = ring + 2 * np.pi * rng.integers(-1, 2, (12, 1)) * np.array([1.0, 1.0, 0.0])
+    idx = np.unique(np.concatenate([np.arange(12), [T - 1], rng.choice(T, 388, replace=False)]))
+    xd = dev(x)
+    outs = {}
+    for prec in (qpgf.C128, qpgf.C64):
+        P = qpgf.Plan(qpgf.KIND_MAXWELL3D, prec, M1, M2, M3)
+        outs[prec] = P(k, a1, a2, xd)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        P.close()
+    st = method.prepare_3d(k, a1, a2, M1 // 2, M2 // 2, M3 // 2, maxwell=True)
+    o = method.evaluate_3d(st, x[idx])
+    assert o.shape == (len(idx), 6)
+    for prec in (qpgf.C128, qpgf.C64):
+        errs = [parity(outs[prec][:, j], o[:, j]) for j in range(6)]
+        print("maxwell full size", "c128" if prec == qpgf.C128 else "c64", errs)
+        assert max(errs) <= TOL[prec], errs

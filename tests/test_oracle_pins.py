@@ -371,3 +371,18 @@ def test_paper_table_points_2d_order_of_magnitude():
         g = method.eval_g2d(k, al, x, N, N)
         ours = abs(g[0] - truth.g2d(k, al, x)[0]) / abs(truth.g2d(k, al, x)[0])
         assert ours < 10 * err, (tab, N, p, ours, err)
+
+
+def test_fhat_2d_radial_rule_converged_on_the_largest_tested_grid():
+    # The ring integrals of F-hat (Section 2.2) carry J0(|eta| r), J1(|eta| r) over [eps, 2 eps]: ~33
+    # oscillations at the corner |eta| = 1043 of the widest grid the tests use (2048 x 128).  The
+    # oracle's 160-node rule must already sit at rounding there: doubling it moves no coefficient by
+    # more than 1e-12 of the largest, while a 64-node rule is off by 2e-9 of it.
+    F64 = method.fhat_2d(1024, 64, q=64)
+    F160 = method.fhat_2d(1024, 64, q=160)
+    F320 = method.fhat_2d(1024, 64, q=320)
+    m = np.isfinite(F320[0])
+    s = np.max(np.abs(F320[0][m]))
+    for a, b in zip(F160, F320):
+        assert np.max(np.abs(a[m] - b[m])) <= 1e-12 * s
+    assert np.max(np.abs(F64[0][m] - F320[0][m])) > 1e-9 * s
