@@ -673,6 +673,131 @@ __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const 
   }
 }
 
+constexpr int kFar8Threads = 512;   // 64 targets in flight per block
+
+// DPP moves of a double within rows of 16 lanes (the control is a compile-time constant).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+// Sum over each aligned group of 8 lanes, the total in every lane of the group: lane ^ 1, lane ^ 2
+// (quad permutations), then the mirror within the half row (lane i with 7 - i) joins the quads.
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  return v;
+}
+
+// Complex128 far tiles, 8 lanes per target.  The LDS serves 128 bytes per clock (8 lanes of a
+// 16-byte read); one target's 8-point stencil row is 8 contiguous nodes (128 bytes) of the
+// staged footprint, so each group of 8 lanes reads one row per clock whatever its alignment,
+// where one lane per target (random rows in every group of 8 lanes) waits on bank conflicts.
+// Lane a of a group takes x1 node a of every row of the target's 8 x 8 x 8 stencil; the eight
+// partial sums are joined by DPP moves.  Every lane of a group computes the target's stencil
+// (the same record, so the group branches together).  Keys, footprints, overflow and results
+// as k_gather3d_far; the Maxwell fields are staged one at a time for each pass of BS targets.
+template <int NF, int FB1, int FB2, int FB3, int BS>
+__global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const double2* __restrict__ far,
+                                                       const TRec* __restrict__ rec,
+                                                       const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ offs,
+                                                       double2* __restrict__ out, uint8_t* __restrict__ flags,
+                                                       uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+  constexpr int FP = 8, LO = FP / 2 - 1;
+  constexpr int F1 = (1 << FB1) + FP - 1, F2 = (1 << FB2) + FP - 1, F3 = (1 << FB3) + FP - 1;
+  constexpr int NO = NOut<NF>::v;
+  constexpr int G = BS / 8;                  // targets in flight per block
+  __shared__ double2 lds[F1 * F2 * F3];
+  const int key = B.nnear + (int)blockIdx.x;
+  const uint32_t cnt = hist[key];
+  if (cnt == 0) return;
+  const long start = offs[key];
+  if (key == B.nkeys - 1) {
+    for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
+      const TRec r = rec[j];
+      const bool fin = isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) out[(long)r.i * NO + o] = nan2();
+      if (flags) flags[r.i] = fin ? 6 : 8;
+    }
+    return;
+  }
+  const int kk = key - B.nnear;
+  const int b1 = kk % B.fnt1, b2 = (kk / B.fnt1) % B.fnt2, b3 = kk / (B.fnt1 * B.fnt2);
+  const int o1 = (b1 << FB1) - LO, o2 = (b2 << FB2) - LO, o3 = (b3 << FB3) - LO;
+  const int g = (int)threadIdx.x >> 3, a = (int)threadIdx.x & 7;
+  if (NO == 1) {
+    stage_far<double, F1, F2, F3>(A, far, o1, o2, o3, lds);
+    __syncthreads();
+  }
+  const long passes = NO == 1 ? 1 : ((long)cnt + BS - 1) / BS;
+  for (long p = 0; p < passes; ++p) {
+    const long t0 = NO == 1 ? 0 : p * BS, t1 = NO == 1 ? (long)cnt : std::min((long)cnt, t0 + BS);
+#pragma unroll 1
+    for (int f = 0; f < NO; ++f) {
+      if (NO > 1) {
+        __syncthreads();   // the previous field's reads are done
+        stage_far<double, F1, F2, F3>(A, far + f * A.ffs, o1, o2, o3, lds);
+        __syncthreads();
+      }
+#pragma unroll 1
+      for (long t = t0 + g; t < t1; t += G) {
+        const long j = start + t;
+        const TRec r = rec[j];
+        Far3<double, FP> st;
+        bool miss = !far3_stencil<double, FP>(A, r.x, r.y, r.z, st);
+        const int l1 = (st.p1 - LO - o1) & (A.Mf1 - 1);
+        const int l2 = (st.p2 - LO - o2) & (A.Mf2 - 1);
+        const int l3 = st.s0 - LO - o3;
+        miss = miss || l1 > F1 - FP || l2 > F2 - FP || l3 < 0 || l3 > F3 - FP;
+        if (miss) {
+          if (f == 0 && a == 0) ovf[atomicAdd(novf, 1u)] = (uint32_t)j;
+          continue;
+        }
+        // this lane's x1 weight (a select chain keeps the weights in registers)
+        double w1a = st.w1[0];
+#pragma unroll
+        for (int m = 1; m < FP; ++m) w1a = a == m ? st.w1[m] : w1a;
+        const double2* node = lds + (l3 * F2 + l2) * F1 + l1 + a;
+        double ax = 0.0, ay = 0.0;
+        double w3[FP];
+#pragma unroll
+        for (int m = 0; m < FP; ++m) w3[m] = st.w3[m];
+#pragma unroll 1
+        for (int c = 0; c < FP; ++c) {
+          const double wc = w3[0];
+#pragma unroll
+          for (int m = 0; m < FP - 1; ++m) w3[m] = w3[m + 1];
+          const double2* slice = node + c * (F2 * F1);
+          double px = 0.0, py = 0.0;
+#pragma unroll
+          for (int b = 0; b < FP; ++b) {
+            const double2 v = slice[b * F1];
+            px = fma(st.w2[b], v.x, px);
+            py = fma(st.w2[b], v.y, py);
+          }
+          ax = fma(wc, px, ax);
+          ay = fma(wc, py, ay);
+        }
+        ax = sum8(w1a * ax);
+        ay = sum8(w1a * ay);
+        if (a == 0) {
+          // the phase e^{i alpha.x'}; GG_13, GG_23 carry sgn(x3) (as far3_finish)
+          double ps, pc;
+          sincos(A.a1 * r.x + A.a2 * r.y, &ps, &pc);
+          double2 v = cmul(mk(pc, ps), mk(ax, ay));
+          if (NO == kMxO && f >= 4 && r.z < 0.0) v = cscale(v, -1.0);
+          out[(long)r.i * NO + f] = v;
+          if (flags && f == 0) flags[r.i] = 2;
+        }
+      }
+    }
+  }
+}
+
 // Targets the tiled kernels handed over (stencil outside the tile footprint): evaluated
 // from global memory.  The count is read on the device.
 template <typename T, int NF>
@@ -1770,12 +1895,19 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
 #define QPGF_FAR(A1_, A2_, A3_)                                                                                    \
   hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
                      P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
+#define QPGF_FAR8(A1_, A2_, A3_, BS_)                                                                            \
+  hipLaunchKernelGGL((k_gather3d_far8<NF, A1_, A2_, A3_, BS_>), tf, dim3(BS_), 0, P.stream, A, Tl, f, rec, P.ts.bin_hist, \
+                     P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
     // far tiles first (more targets and work each), then the near tiles
     {
       KernelTimer t(P, QPGF_T_GATHER_FAR);
-      if (!C.far_big) QPGF_FAR(3, 3, 3);
-      else if constexpr (sizeof(T) == 8) QPGF_FAR(4, 3, 3);
-      else QPGF_FAR(4, 4, 3);
+      if constexpr (sizeof(T) == 8) {
+        if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads);
+        else QPGF_FAR8(4, 3, 3, kFar8Threads);
+      } else {
+        if (!C.far_big) QPGF_FAR(3, 3, 3);
+        else QPGF_FAR(4, 4, 3);
+      }
     }
     KernelTimer t(P, QPGF_T_GATHER);
     if constexpr (NF > 1) {
@@ -1792,6 +1924,7 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     }
 #undef QPGF_NEAR
 #undef QPGF_FAR
+#undef QPGF_FAR8
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
