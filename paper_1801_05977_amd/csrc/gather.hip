@@ -1848,15 +1848,14 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, bs, P.ts.bin_novf, 1L);
       if (lds_bins) {
         // LDS histogram sized to the key count (small ones leave LDS to kernels running beside)
-        if (Tl.nkeys <= 4096)
-          hipLaunchKernelGGL(k_bin_count<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.ts.bin_cnt);
-        else if (Tl.nkeys <= 16384)
-          hipLaunchKernelGGL(k_bin_count<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.ts.bin_cnt);
-        else
-          hipLaunchKernelGGL(k_bin_count<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                             P.ts.bin_cnt);
+#define QPGF_BIN_COUNT(K_)                                                                                     \
+  hipLaunchKernelGGL(k_bin_count<K_>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.ts.bin_cnt)
+        if (Tl.nkeys <= 4096) QPGF_BIN_COUNT(4096);
+        else if (Tl.nkeys <= 16384) QPGF_BIN_COUNT(16384);
+        else if (Tl.nkeys <= 20480) QPGF_BIN_COUNT(20480);
+        else if (Tl.nkeys <= 24576) QPGF_BIN_COUNT(24576);
+        else QPGF_BIN_COUNT(kBinLdsKeys);
+#undef QPGF_BIN_COUNT
         hipLaunchKernelGGL(k_bin_colscan, dim3((Tl.nkeys + 63) / 64), dim3(64 * kColGroups), 0, bs, P.ts.bin_cnt,
                            Tl.nkeys, kBinBlocks, P.ts.bin_hist);
       } else {
@@ -1871,17 +1870,19 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
     }
     {
       KernelTimer t(P, QPGF_T_BIN_PLACE, bs);
-      if (lds_bins && Tl.nkeys <= 4096)
-        hipLaunchKernelGGL(k_bin_place<4096>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.ts.bin_cnt, P.ts.bin_offs, rec);
-      else if (lds_bins && Tl.nkeys <= 16384)
-        hipLaunchKernelGGL(k_bin_place<16384>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.ts.bin_cnt, P.ts.bin_offs, rec);
-      else if (lds_bins)
-        hipLaunchKernelGGL(k_bin_place<kBinLdsKeys>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk,
-                           P.ts.bin_cnt, P.ts.bin_offs, rec);
+#define QPGF_BIN_PLACE(K_)                                                                                     \
+  hipLaunchKernelGGL(k_bin_place<K_>, dim3(kBinBlocks), dim3(1024), 0, bs, B, x, (long)T_, chunk, P.ts.bin_cnt, \
+                     P.ts.bin_offs, rec)
+      // the LDS histograms are sized to the key count, so that the binning's blocks leave LDS to the
+      // preparation's kernels running beside them on the plan's stream
+      if (lds_bins && Tl.nkeys <= 4096) QPGF_BIN_PLACE(4096);
+      else if (lds_bins && Tl.nkeys <= 16384) QPGF_BIN_PLACE(16384);
+      else if (lds_bins && Tl.nkeys <= 20480) QPGF_BIN_PLACE(20480);
+      else if (lds_bins && Tl.nkeys <= 24576) QPGF_BIN_PLACE(24576);
+      else if (lds_bins) QPGF_BIN_PLACE(kBinLdsKeys);
       else
         hipLaunchKernelGGL(k_bin_scatter, grid, dim3(256), 0, bs, x, P.ts.bin_keyrank, P.ts.bin_offs, (long)T_, rec);
+#undef QPGF_BIN_PLACE
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
