@@ -239,6 +239,15 @@ def main():
             traffic = rec.get("bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    if dom == "gather_far":
+        # the far gather reads every stencil node from LDS: FP^3 nodes per far target, against the
+        # LDS read rate of 128 bytes per clock per CU (256 CUs, 2.4 GHz)
+        fp = info.far_points
+        lds_bytes = counts[2] * fp ** 3 * (8 if prec == qpgf.C64 else 16)
+        lds_peak = 128 * 256 * 2.4e9 / 1e12
+        lds_ach = lds_bytes / (d["avg_ms"] * 1e-3) / 1e12
+        roofline["lds"] = {"bytes_per_launch": lds_bytes, "achieved": round(lds_ach, 2), "peak": round(lds_peak, 1),
+                           "unit": "TB/s", "frac": round(lds_ach / lds_peak, 3)}
 
     gate = None
     if not args.no_gate:
