@@ -93,7 +93,7 @@ void free_batch(Plan& P) {
 void free_plan(Plan& P) {
   free_batch(P);
   if (P.ws) {   // the caller's memory
-    P.grid = P.far = P.gridI = nullptr;
+    P.grid = P.far = P.gridI = P.farI = nullptr;
   }
   if (P.side) (void)hipStreamDestroy(P.side);
   if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
@@ -104,8 +104,8 @@ void free_plan(Plan& P) {
   for (void* q : {P.b_grid, P.b_far, P.b_desc, P.gridI})
     if (q) (void)hipFree(q);
   free_target_scratch(P.ts);
-  void* ptrs[] = {P.grid, P.far, P.xq, P.wxq, P.wXq, P.cs, P.rq, P.wrq, P.y1q, P.y2q, P.tw, P.twf, P.F1, P.F2, P.D2, P.E2,
-                  P.htab};
+  void* ptrs[] = {P.grid, P.far, P.farI, P.xq, P.wxq, P.wXq, P.cs, P.rq, P.wrq, P.y1q, P.y2q, P.tw, P.twf, P.F1, P.F2,
+                  P.D2, P.E2, P.htab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -160,19 +160,19 @@ qpgf_status validate(const qpgf_params* p) {
 // Far-slab geometry (Algorithm 2.1 / 3.1 / 4.1 step 2b: the series on the slab, interpolated with
 // the P-point Lagrange rule per axis).  The rule's error for a term of wavenumber q along an axis of
 // spacing h is about C_P (q h)^P, C_8 = 1e-3, C_4 = 0.023: with h = 2 pi / Mf and the propagating terms
-// (q <= k), Mf >= 2 pi k / x keeps it near 1e-11 for complex128 (P = 8, x = 0.0977), 1e-7 for
-// complex64 in 2D (P = 8, x = 0.3) and 1e-6 for complex64 in 3D (P = 4, x = 0.081: 64 nodes per target
-// instead of 512).  The evanescent terms the series keeps just below c set the floors: hf <= 1/64, and
-// 512 modes (complex128; 256 leave up to 4e-11 of |G_d| next to |x3| = c at k = 3.7, 512 leave 6e-13)
-// or 256 (complex64 in 2D) or 512 (complex64 in 3D, the 4-point rule: 1.2e-7).  Slices
-// z_s = c - (P/2 - 1) hf + s hf, s < S: a target at |x_t| = z uses slices floor((z - z_0) / hf)
-// - (P/2 - 1) .. + P/2, so S = ceil((zmax - c) / hf) + P covers every z <= zmax.  params.far_m and
-// params.far_h override the modes and the spacing.
+// (q <= k), Mf >= 2 pi k / x keeps it near 1e-11 for complex128 (P = 8, x = 0.0977) and 1e-6 for
+// complex64 (P = 4, x = 0.081: 16 nodes per target in 2D and 64 in 3D instead of 64 and 512).  The
+// evanescent terms the series keeps just below c set the floors: hf <= 1/64, and 512 modes
+// (complex128; 256 leave up to 4e-11 of |G_d| next to |x3| = c at k = 3.7, 512 leave 6e-13), 512 for
+// complex64 in 3D, 256 for complex64 in 2D (3e-7 of the terms' size).  Slices z_s = c - (P/2 - 1) hf
+// + s hf, s < S: a target at |x_t| = z uses slices floor((z - z_0) / hf) - (P/2 - 1) .. + P/2, so
+// S = ceil((zmax - c) / hf) + P covers every z <= zmax.  params.far_m and params.far_h override the
+// modes and the spacing.
 FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
   const bool c128 = P.p.prec == QPGF_C128;
   FarGeom g;
-  g.P = (P.dim == 3 && !c128) ? 4 : 8;
-  const double x = c128 ? 0.0977 : (g.P == 4 ? 0.081 : 0.3);
+  g.P = c128 ? 8 : 4;
+  const double x = c128 ? 0.0977 : 0.081;
   const int floor_m = (c128 || P.dim == 3) ? 512 : 256;
   const double want = 2.0 * M_PI * std::max(kmax, 0.0) / x;
   int mk = floor_m;
@@ -211,6 +211,23 @@ hipError_t set_far_geometry(Plan& P, double kmax) {
     hipError_t e = hipMalloc(&P.far, bytes);
     if (e != hipSuccess) return e;
     P.far_cap = bytes;
+  }
+  if (P.gridI_bytes) {
+    // the far slab's copy in the gather's layout (node quads of the complex64 G, or the fields
+    // interleaved per node)
+    const size_t bi = (size_t)(P.nf > 1 ? P.nfo : 4) * nfar * P.esize;
+    if (bi > P.farI_cap) {
+      if (P.ws) return hipErrorInvalidValue;
+      if (P.farI) {
+        hipError_t e = hipFree(P.farI);
+        if (e != hipSuccess) return e;
+      }
+      P.farI = nullptr;
+      P.farI_cap = 0;
+      hipError_t e = hipMalloc(&P.farI, bi);
+      if (e != hipSuccess) return e;
+      P.farI_cap = bi;
+    }
   }
   P.Mf1 = g.Mf1;
   P.Mf2 = g.Mf2;
@@ -411,7 +428,7 @@ qpgf_status run_evaluate(Plan& P, const double* x, int64_t T, void* out, uint8_t
 // The workspace's parts, each 256-byte aligned: near grid, its interleaved copy, the far slab
 // of the largest instance (kmax), the target scratch of T targets.
 struct WsLayout {
-  size_t grid = 0, gridI = 0, far = 0, targets = 0, total = 0;
+  size_t grid = 0, gridI = 0, far = 0, farI = 0, targets = 0, total = 0;
   int nkeys = 0;
 };
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -420,11 +437,13 @@ WsLayout ws_layout(const Plan& P, double kmax, int64_t T) {
   L.grid = al256((size_t)P.nf * P.ncell * P.esize);
   L.gridI = al256(P.gridI_bytes);
   const FarGeom g = far_geometry(P, kmax, P.M1);
-  L.far = al256((size_t)P.nfo * g.Mf1 * g.Mf2 * g.S * P.esize);
+  const size_t nfar = (size_t)g.Mf1 * g.Mf2 * g.S;
+  L.far = al256((size_t)P.nfo * nfar * P.esize);
+  L.farI = P.gridI_bytes ? al256((size_t)(P.nf > 1 ? P.nfo : 4) * nfar * P.esize) : 0;
   L.nkeys = bin_keys_bound(P, g.Mf1, g.Mf2, g.S, g.P);
   TargetScratch t;
   L.targets = carve_target_scratch(P, nullptr, T, L.nkeys, t);
-  L.total = L.grid + L.gridI + L.far + L.targets;
+  L.total = L.grid + L.gridI + L.far + L.farI + L.targets;
   return L;
 }
 
@@ -900,12 +919,13 @@ qpgf_status qpgf_plan_set_workspace(qpgf_plan* plan, void* ptr, size_t bytes, do
   if (P.side) HIP_TRY(hipStreamSynchronize(P.side));
   drain_timers(P);
   if (!P.ws) {
-    for (void* q : {P.grid, P.gridI, P.far})
+    for (void* q : {P.grid, P.gridI, P.far, P.farI})
       if (q) HIP_TRY(hipFree(q));
   }
   free_target_scratch(P.ts);
-  P.grid = P.gridI = P.far = nullptr;
+  P.grid = P.gridI = P.far = P.farI = nullptr;
   P.far_cap = 0;
+  P.farI_cap = 0;
   P.ws = nullptr;
   P.ws_bytes = 0;
   P.ws_kmax = 0.0;
@@ -923,7 +943,9 @@ qpgf_status qpgf_plan_set_workspace(qpgf_plan* plan, void* ptr, size_t bytes, do
     P.gridI = P.gridI_bytes ? b + L.grid : nullptr;
     P.far = b + L.grid + L.gridI;
     P.far_cap = L.far;
-    carve_target_scratch(P, b + L.grid + L.gridI + L.far, max_targets, L.nkeys, P.ts);
+    P.farI = L.farI ? b + L.grid + L.gridI + L.far : nullptr;
+    P.farI_cap = L.farI;
+    carve_target_scratch(P, b + L.grid + L.gridI + L.far + L.farI, max_targets, L.nkeys, P.ts);
   } else {
     // the plan's own arrays again (the target scratch grows on demand)
     HIP_TRY(hipMalloc(&P.grid, (size_t)P.nf * P.ncell * P.esize));

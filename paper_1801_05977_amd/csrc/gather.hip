@@ -32,6 +32,7 @@ struct GArgs {
   int smooth;              // 1: return the interpolated smooth part L_N only (near branch)
   int sing_order;          // 2D G: degree of the removed Taylor factor of the log singularity (1..3)
   int quad;                // 2D G, complex64: the near grid is node quads (4 x1-neighbours per node)
+  int far_layout;          // 2D far slab: 0 fields apart [f][s][i1], 1 node quads, 2 fields interleaved
   // 2D kinds, ring_interp: bit i of ring_mask marks target i (a near target with
   // ring_lo < r < ring_hi) for the ring pass
   unsigned long long* ring_mask;
@@ -253,15 +254,15 @@ __device__ __forceinline__ void near3_finish(const GArgs& A, double x1, double x
 // ---------------------------------------------------------------------------
 // The far slab holds the series on its own periodic grid (Mf1 x Mf2, spacings 2 pi / Mf)
 // at slices z_s = fz0 + s hf: G_d, or the six tensor entries GG_pq (13 and 23 for x3 > 0).
-// FP = far_points_3d<T>() interpolation points per axis.
-template <typename T, int FP = far_points_3d<T>()>
+// FP = far_points<T>() interpolation points per axis.
+template <typename T, int FP = far_points<T>()>
 struct Far3 {
   int p1, p2, s0;
   T w1[FP], w2[FP], w3[FP];
 };
 
 // false: |x3| beyond the slab
-template <typename T, int FP = far_points_3d<T>()>
+template <typename T, int FP = far_points<T>()>
 __device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T, FP>& s) {
   double s0, f3;
   if (!far_slice(A, fabs(x3), s0, f3)) return false;
@@ -278,7 +279,7 @@ __device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x
 }
 
 // FP^3-point stencil sums of the NFO far fields from global memory.
-template <typename T, int NFO, int FP = far_points_3d<T>()>
+template <typename T, int NFO, int FP = far_points<T>()>
 __device__ __forceinline__ void far3_sum_global(const GArgs& A, const cplx<T>* __restrict__ far,
                                                 const Far3<T, FP>& s, double2 L[NFO]) {
   constexpr int LO = FP / 2 - 1;
@@ -601,7 +602,7 @@ __global__ __launch_bounds__(256) void k_gather3d_near_fields(GArgs A, TileArgs 
 // the last key (non-finite and out-of-slab targets: NaN).  The FP-point footprint of one field is
 // staged at a time: for one field (G_d) once per tile; for the six Maxwell entries field by field
 // for each pass of BS targets, whose sums stay in registers.
-template <typename T, int NF, int FB1, int FB2, int FB3, int BS, int FP = far_points_3d<T>()>
+template <typename T, int NF, int FB1, int FB2, int FB3, int BS, int FP = far_points<T>()>
 __global__ __launch_bounds__(BS) void k_gather3d_far(GArgs A, TileArgs B, const cplx<T>* __restrict__ grid,
                                                       const cplx<T>* __restrict__ far,
                                                       const TRec* __restrict__ rec,
@@ -976,29 +977,48 @@ __device__ __forceinline__ void ring_mark(const GArgs& A, bool take, long i, lon
 }
 
 // Far branch of the 2D kinds (Algorithm 2.1 step 2b, the series (1.2) and its term-wise
-// derivatives): the far slab [field][s][i1] (Mf1 modes, slices fz0 + s hf) interpolated with
-// 8 x 8 nodes.  false when |x2| lies beyond the slab.
+// derivatives): the far slab (Mf1 modes, slices fz0 + s hf) interpolated with FP x FP nodes (8 on
+// the complex128 path, 4 on the complex64 one), read in the plan's layout of it (A.far_layout:
+// fields apart [f][s][i1], node quads, or fields interleaved per node [s][i1][f], as the near
+// grid is read).  false when |x2| lies beyond the slab.
 template <typename T, int NF>
 __device__ __forceinline__ bool far2d_sum(const GArgs& A, const cplx<T>* __restrict__ far, double t, double z,
                                           double2 L[NF]) {
+  constexpr int FP = far_points<T>(), LO = FP / 2 - 1;
   double s0, f2;
   if (!far_slice(A, z, s0, f2)) return false;
-  T w1[8], w2[8];
+  T w1[FP], w2[FP];
   const double u = t * A.ihf1, p = floor(u);
-  lagp<T, 8>((T)(u - p), w1);
-  lagp<T, 8>((T)f2, w2);
-  const int i0 = (int)p - 3;
-  const long r0 = (long)s0 - 3;
+  lagp<T, FP>((T)(u - p), w1);
+  lagp<T, FP>((T)f2, w2);
+  const int i0 = (int)p - LO;
+  const long r0 = (long)s0 - LO;
+  if constexpr (FP == 4) {
+    // complex64: the near grid's row sums (one fixed order for the quads and the row-major slab,
+    // so that single-instance plans and the batched call give the same bits)
+    long rows[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rows[b] = (r0 + b) * A.Mf1;
+    const int j0 = i0 & (A.Mf1 - 1);
+    if constexpr (NF == 1) {
+      L[0] = A.far_layout == 1 ? stencil2d_quad(far, rows, j0, w1, w2) : stencil2d<T>(far, rows, j0, A.Mf1, w1, w2);
+      return true;
+    } else if (A.far_layout == 2) {
+      stencil2d_fields<T, NF>(far, rows, j0, A.Mf1, w1, w2, L);
+      return true;
+    }
+  }
+  const long fstride = A.far_layout == 2 ? 1 : A.ffs, nstride = A.far_layout == 2 ? NF : 1;
   Acc<T> acc[NF];
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < FP; ++b) {
     const long row = (r0 + b) * A.Mf1;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < FP; ++a) {
       const T w = w2[b] * w1[a];
-      const long o = row + ((i0 + a) & (A.Mf1 - 1));
+      const long o = (row + ((i0 + a) & (A.Mf1 - 1))) * nstride;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f].add(w, far[f * A.ffs + o]);
+      for (int f = 0; f < NF; ++f) acc[f].add(w, far[f * fstride + o]);
     }
   }
 #pragma unroll
@@ -1698,6 +1718,7 @@ GArgs make_gargs(const Plan& P, int smooth) {
   A.smooth = smooth;
   A.sing_order = P.p.sing_order;
   A.quad = P.dim == 2 && P.nf == 1 && P.gridI != nullptr;
+  A.far_layout = (P.dim == 2 && P.farI != nullptr) ? (P.nf == 1 ? 1 : 2) : 0;
   A.ring_mask = nullptr;
   // the ring zone r_lo < r < r_hi: r_hi = 2 eps + 2 sqrt(2) h, beyond which every stencil node has
   // Y = 0; r_lo = max(eps, eps/2 + 2 sqrt(2) h) keeps every node at least eps/2 from the lattice point
@@ -1712,6 +1733,7 @@ hipError_t gather2d_impl(Plan& P, GArgs& A, const double* x, int64_t T_, void* o
   const auto* g = static_cast<const cplx<T>*>(P.grid);
   const auto* f = static_cast<const cplx<T>*>(P.far);
   const auto* gi = static_cast<const cplx<T>*>(P.gridI);
+  if (A.far_layout) f = static_cast<const cplx<T>*>(P.farI);
   auto* o = static_cast<cplx<T>*>(out);
   const dim3 grid((unsigned)((T_ + 255) / 256));
   if (P.p.ring_interp) {
@@ -1778,7 +1800,7 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   B.Mf1 = P.Mf1;
   B.Mf2 = P.Mf2;
   B.fp = P.fp;
-  if (P.fp != far_points_3d<T>()) return hipErrorInvalidValue;
+  if (P.fp != far_points<T>()) return hipErrorInvalidValue;
   // Near tiles.  One field: 16 x 16 x 8 nodes (several 256-thread blocks per CU, so one
   // block's staging overlaps the others' interpolation), or, when that leaves fewer than
   // kMinPerTile targets per tile on average (fine grids), 32 x 32 x 8 (complex64, 108 KiB,
@@ -1947,23 +1969,32 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 
 }  // namespace
 
+// The near grid's and the far slab's copies in the gather's layout (rows of M1 and Mf1 nodes).
 hipError_t launch_interleave2d(Plan& P) {
-  if (P.dim != 2 || !P.gridI) return hipErrorInvalidValue;
-  if (P.nf == 1) {
-    // complex64 G: node quads of the near grid
-    if (P.esize != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_quads, dim3((unsigned)((4 * P.ncell + 255) / 256)), dim3(256), 0, P.stream,
-                       static_cast<const float2*>(P.grid), static_cast<float2*>(P.gridI), (long)P.ncell, P.M1);
-    return hipGetLastError();
+  if (P.dim != 2 || !P.gridI || !P.farI) return hipErrorInvalidValue;
+  const void* src[2] = {P.grid, P.far};
+  void* dst[2] = {P.gridI, P.farI};
+  const long n[2] = {(long)P.ncell, (long)P.nfar};
+  const int m1[2] = {P.M1, P.Mf1}, nf[2] = {P.nf, P.nfo};
+  for (int w = 0; w < 2; ++w) {
+    if (P.nf == 1) {
+      // complex64 G: node quads
+      if (P.esize != 8) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_quads, dim3((unsigned)((4 * n[w] + 255) / 256)), dim3(256), 0, P.stream,
+                         static_cast<const float2*>(src[w]), static_cast<float2*>(dst[w]), n[w], m1[w]);
+    } else {
+      const long tot = n[w] * nf[w];
+      if (P.esize == 16)
+        hipLaunchKernelGGL(k_interleave<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
+                           static_cast<const double2*>(src[w]), static_cast<double2*>(dst[w]), n[w], nf[w]);
+      else
+        hipLaunchKernelGGL(k_interleave<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
+                           static_cast<const float2*>(src[w]), static_cast<float2*>(dst[w]), n[w], nf[w]);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  const long tot = (long)P.ncell * P.nf;
-  if (P.esize == 16)
-    hipLaunchKernelGGL(k_interleave<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
-                       static_cast<const double2*>(P.grid), static_cast<double2*>(P.gridI), (long)P.ncell, P.nf);
-  else
-    hipLaunchKernelGGL(k_interleave<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P.stream,
-                       static_cast<const float2*>(P.grid), static_cast<float2*>(P.gridI), (long)P.ncell, P.nf);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t ensure_ring_scratch(Plan& P, int64_t T_) {
@@ -2098,6 +2129,7 @@ void gather_inst_2d(const Plan& P, double k, double a, int M1, const FarGeom& fg
   A.ffs = (long)fg.Mf1 * fg.S;
   A.quad = 0;   // the batched graph keeps the instances' grids row by row (node quads of all
                 // instances cost more than they save: four times the grids no longer stay in L2)
+  A.far_layout = 0;
   A.ring_mask = nullptr;
   A.ring_lo = A.ring_hi = 0.0;
   I.off = off;

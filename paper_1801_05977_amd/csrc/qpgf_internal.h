@@ -26,7 +26,7 @@ constexpr int kMxO = 6;
 // Far branch: the far slab is interpolated with the P-point Lagrange rule per axis (nodes
 // base - (P/2 - 1) .. base + P/2; its first slice lies P/2 - 1 spacings below c): P = 8 in 2D and
 // for complex128 in 3D, P = 4 for complex64 in 3D (on a finer slab).
-template <typename T> constexpr int far_points_3d() { return sizeof(T) == 4 ? 4 : 8; }
+template <typename T> constexpr int far_points() { return sizeof(T) == 4 ? 4 : 8; }
 
 template <typename T> struct C2;
 template <> struct C2<double> { using type = double2; };
@@ -164,6 +164,8 @@ struct Plan {
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
   size_t gridI_bytes = 0;      // its size (0: none)
+  void* farI = nullptr;        // 2D plans with gridI: the far slab in the same layout (node quads or
+  size_t farI_cap = 0;         // fields interleaved per node), grown with the slab
   // caller-owned workspace (qpgf_plan_set_workspace): grid, gridI, far and the target scratch
   // live in it; instances up to ws_kmax and calls of up to ws_T targets fit
   char* ws = nullptr;

@@ -59,6 +59,7 @@ def test_fill2d_and_grid2d_stages(prec):
     assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
     # far slab: at its nodes the series (1.2) itself, on its own grid of far_m1 >= 256 modes
     assert P.info.far_m1 == (512 if prec == qpgf.C128 else 256) and P.info.far_fields == 1
+    assert P.info.far_points == (8 if prec == qpgf.C128 else 4)
     (si, pi), pts = slabcheck.nodes_2d(P.info, 60, seed=1)
     ref_F = truth.g2d(k, al, pts) * np.exp(-1j * al * pts[:, 0])
     assert slabcheck.rel(slabcheck.slab_2d(P)[si, pi], ref_F) <= tol
