@@ -132,7 +132,7 @@ typedef struct {
                               accuracy to the cut-offs' smoothness): the ring's error falls by two to three
                               orders of magnitude.  The gather marks those targets (one bit per target in a
                               plan-owned mask of T/8 bytes, grown on demand) and a second pass corrects them
-                              (in FP64 for complex128, in FP32 for complex64).
+                              in FP64 (both precisions).
                               0 (default): Algorithm 2.1 / Section 2.4 as printed.  Every
                               other kind, and qpgf_g2d_batched, require 0. */
   int far_m;               /* modes per periodic axis of the far slab (a power of two in [16, 4096],

@@ -161,7 +161,8 @@ qpgf_status validate(const qpgf_params* p) {
 // the P-point Lagrange rule per axis).  The rule's error for a term of wavenumber q along an axis of
 // spacing h is about C_P (q h)^P, C_8 = 1e-3, C_4 = 0.023: with h = 2 pi / Mf and the propagating terms
 // (q <= k), Mf >= 2 pi k / x keeps it near 1e-11 for complex128 (P = 8, x = 0.0977) and 1e-6 for
-// complex64 (P = 4, x = 0.081: 16 nodes per target in 2D and 64 in 3D instead of 64 and 512).  The
+// complex64 (P = 4, x = 0.081: 16 nodes per target in 2D and 64 in 3D instead of 64 and 512); the
+// slice spacing follows the same rule with its own x.  The
 // evanescent terms the series keeps just below c set the floors: hf <= 1/64, and 512 modes
 // (complex128; 256 leave up to 4e-11 of |G_d| next to |x3| = c at k = 3.7, 512 leave 6e-13), 512 for
 // complex64 in 3D, 256 for complex64 in 2D (3e-7 of the terms' size).  Slices z_s = c - (P/2 - 1) hf
@@ -183,8 +184,10 @@ FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
   if (P.p.far_h > 0.0) {
     g.hf = P.p.far_h;
   } else {
+    // the slice spacing: k hf <= 0.107 (complex128, 8 points: 1e-11) or 0.11 (complex64, 4 points:
+    // 3e-6 of the series, against the complex64 bar of 1e-5)
     double inv = 64.0;
-    const double need = std::max(kmax, 0.0) / (c128 ? 0.107 : x);
+    const double need = std::max(kmax, 0.0) / (c128 ? 0.107 : 0.11);
     while (inv < need && inv < 4096.0) inv *= 2.0;
     g.hf = 1.0 / inv;
   }

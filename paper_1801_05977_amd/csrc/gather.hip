@@ -1101,8 +1101,8 @@ __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __re
 // nodes replaces f Y at the target, so that the result is the interpolant of K = L + f Y:
 // out += e^{i alpha x1} (sum_ab w_a w_b (f Y)(node_ab) - (f Y)(target)), f the removed singular
 // part of the plan's order and a node's position its offset (p1 h1, p2 h2) from the lattice
-// point.  The complex128 path computes in FP64, the complex64 path in FP32 (the correction is a
-// small part of a result kept to single precision; the phase stays FP64).  Each block takes
+// point.  The correction is computed in FP64 on both paths (singular work next to the lattice
+// point), as is the phase.  Each block takes
 // kRingSpan consecutive targets: its first wave reads their mask words and collects the marked
 // offsets in LDS, then all lanes correct them (kRingSpan targets per block: fewer, fuller blocks
 // measured faster than small ones whose waves stay mostly idle).
@@ -1230,38 +1230,39 @@ __global__ __launch_bounds__(256) void k_ring2d(GArgs A, const double* __restric
     double n1;
     const double t = reduce_cell(x1, n1);
     const double u = t * A.ih1, p = floor(u), u2 = x2 * A.ih2, p2 = floor(u2);
-    T w1[4], w2[4];
-    lag4<T>((T)(u - p), w1);
-    lag4<T>((T)(u2 - p2), w2);
+    // the singular part near the origin in FP64 on both paths (only the grid values are complex64)
+    double w1[4], w2[4];
+    lag4<double>(u - p, w1);
+    lag4<double>(u2 - p2, w2);
     // NF = 1: f Y of the 2D G; NF = 2: the gradient's h1, h2; NF = 3: h_11, h_12, h_22
-    cplx<T> acc[NF], at[NF];
+    double2 acc[NF], at[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = cv<T>(0, 0);
+    for (int f = 0; f < NF; ++f) acc[f] = mk(0.0, 0.0);
     for (int b = 0; b < 4; ++b) {
-      const T zn = (T)((p2 - 1.0 + b) * A.h2);
-      cplx<T> row[NF];
+      const double zn = (p2 - 1.0 + b) * A.h2;
+      double2 row[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) row[f] = cv<T>(0, 0);
+      for (int f = 0; f < NF; ++f) row[f] = mk(0.0, 0.0);
       for (int a = 0; a < 4; ++a) {
-        const T tn = (T)((p - 1.0 + a) * A.h1);
-        cplx<T> v[NF];
-        if constexpr (NF == 1) v[0] = fy_removed<T>(A, tn, zn);
-        else if constexpr (NF == 2) hgrad_at<T>(A, tn, zn, v[0], v[1]);
-        else hhess_at<T>(A, tn, zn, v);
+        const double tn = (p - 1.0 + a) * A.h1;
+        double2 v[NF];
+        if constexpr (NF == 1) v[0] = fy_removed<double>(A, tn, zn);
+        else if constexpr (NF == 2) hgrad_at<double>(A, tn, zn, v[0], v[1]);
+        else hhess_at<double>(A, tn, zn, v);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) row[f] = cv<T>(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
+        for (int f = 0; f < NF; ++f) row[f] = mk(fma(w1[a], v[f].x, row[f].x), fma(w1[a], v[f].y, row[f].y));
       }
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[f] = cv<T>(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
+      for (int f = 0; f < NF; ++f) acc[f] = mk(fma(w2[b], row[f].x, acc[f].x), fma(w2[b], row[f].y, acc[f].y));
     }
-    if constexpr (NF == 1) at[0] = fy_removed<T>(A, (T)t, (T)x2);
-    else if constexpr (NF == 2) hgrad_at<T>(A, (T)t, (T)x2, at[0], at[1]);
-    else hhess_at<T>(A, (T)t, (T)x2, at);
+    if constexpr (NF == 1) at[0] = fy_removed<double>(A, t, x2);
+    else if constexpr (NF == 2) hgrad_at<double>(A, t, x2, at[0], at[1]);
+    else hhess_at<double>(A, t, x2, at);
     double ps, pc;
     sincos(A.a1 * x1, &ps, &pc);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const double2 corr = cmul(mk(pc, ps), mk((double)(acc[f].x - at[f].x), (double)(acc[f].y - at[f].y)));
+      const double2 corr = cmul(mk(pc, ps), mk(acc[f].x - at[f].x, acc[f].y - at[f].y));
       const cplx<T> o = out[i * NF + f];
       store_out<T>(out, i * NF + f, mk((double)o.x + corr.x, (double)o.y + corr.y));
     }
