@@ -50,10 +50,10 @@ def algorithmic_bytes(name, info, counts, esize):
         return ncell * esize * nf
     if name in ("fft_t", "fft_2", "fft_1"):
         return 2 * ncell * esize * nf
-    if name == "far":
+    if name == "far":          # the far slab written once (in 3D with its x2 transform)
         return nfar * esize * nfo
-    if name == "far_fft":      # two passes over the far slab
-        return 4 * nfar * esize * nfo
+    if name == "far_fft":      # the x1 pass over the far slab
+        return 2 * nfar * esize * nfo
     if name == "bin":          # coordinates read once (counts, then scans of the small count table)
         return T * 24
     if name == "bin_place":    # coordinates read, 32-byte tile-ordered record written per target

@@ -393,12 +393,10 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
       HIP_TRY(launch_far(P, k, a1, a2));
     }
     {
-      // the far slab on its own periodic grid Mf1 x Mf2: columns (x2, 3D), then rows (x1)
+      // the far slab on its own periodic grid Mf1 x Mf2: rows (x1; in 3D the far fill above has
+      // already run the x2 columns)
       KernelTimer t(P, QPGF_T_FAR_FFT);
-      const long nfo = P.nfo;
-      if (P.dim == 3)
-        HIP_TRY(launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2));
-      HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * nfo, 1, 0, P.Mf1));
+      HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * P.nfo, 1, 0, P.Mf1));
     }
     if (P.dim == 2 && P.gridI) {
       // the gather reads a stencil row (of all fields) as one contiguous, aligned run

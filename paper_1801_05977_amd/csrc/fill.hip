@@ -655,29 +655,79 @@ __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int
 // (i/8pi^2) beta^-1 e^{i beta z_s} of the Mf1 x Mf2 lowest modes, z_s = z0 + s hf.  NFO = kMxO:
 // the six entries of the Maxwell tensor (1.4) instead, the term times delta_pq - xi_p xi_q / k^2
 // with xi = (alpha1 + j1, alpha2 + j2, beta) (the entries 13 and 23 take sgn(x3) at the target).
-template <typename T, int NFO>
-__global__ void k_far3d(double k, double a1, double a2, int M1, int M2, int S, double z0, double hf, long fstride,
-                        cplx<T>* __restrict__ out) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long n = (long)M1 * M2 * S;
-  if (idx >= n) return;
-  const int j1p = (int)(idx % M1);
-  const int j2p = (int)((idx / M1) % M2);
-  const int s = (int)(idx / ((long)M1 * M2));
+// One far-slab coefficient of the series (1.3) in 3D: (i/8 pi^2) beta^-1 e^{i beta z} at mode
+// (j1, j2) (FFT order) and height z.
+__device__ __forceinline__ double2 far3_coef(double k, double a1, double a2, int M1, int M2, double z, int j1p,
+                                             int j2p) {
   const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
   const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-  const double z = z0 + s * hf;
-  const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
-  if (NFO == 1) {
-    store_c<T>(out, idx, v);
-  } else {
-    const double ik2 = 1.0 / (k * k);
-    const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
-    const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+  return cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
+}
+
+// The Maxwell far slab's coefficients, one thread per (s, j2, j1) writing all six entries (beta and
+// e^{i beta z} formed once for them); the x2 and x1 transforms follow as separate passes.
+template <typename T>
+__global__ void k_far3d_mx(double k, double a1, double a2, int M1, int M2, int S, double z0, double hf, long fstride,
+                           cplx<T>* __restrict__ out) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M1 * M2 * S) return;
+  const int j1p = (int)(idx % M1), j2p = (int)((idx / M1) % M2), s = (int)(idx / ((long)M1 * M2));
+  const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
+  const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
+  const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z0 + s * hf)));
+  const double ik2 = 1.0 / (k * k);
+  const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
+  const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const double2 m = cscale(cmul(cc[P[f]], cc[Qp[f]]), -ik2);
-      store_c<T>(out, f * fstride + idx, cmul(v, mk((f < 3 ? 1.0 : 0.0) + m.x, m.y)));
+  for (int f = 0; f < 6; ++f) {
+    const double2 m = cscale(cmul(cc[P[f]], cc[Qp[f]]), -ik2);
+    store_c<T>(out, f * fstride + idx, cmul(v, mk((f < 3 ? 1.0 : 0.0) + m.x, m.y)));
+  }
+}
+
+// The G_d far slab [s][i2][i1]: its coefficients are generated straight into LDS for a tile of
+// adjacent x1 columns and the inverse DFT along x2 runs there (the first of its two transform
+// passes; the coefficients never go to memory).  Batch b: slice b / M1, column b % M1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double a2, int M1, int M2, int S, double z0,
+                                                    double hf, int log2n, int tile, const cplx<T>* __restrict__ tw,
+                                                    int twlog2, cplx<T>* __restrict__ out) {
+  extern __shared__ char smem_raw[];
+  using V = cplx<T>;
+  const int n = M2, pitch = n + 1;
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  const long nbatch = (long)M1 * S;
+  const long b0 = (long)blockIdx.x * tile;
+  const int ntile = (int)min((long)tile, nbatch - b0);
+  const int total = tile * n;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int e = idx / tile, t = idx - e * tile;
+    if (t < ntile) {
+      const long b = b0 + t;
+      const long s = b / M1;
+      const int j1p = (int)(b - s * M1);
+      const double2 v = far3_coef(k, a1, a2, M1, M2, z0 + s * hf, j1p, e);
+      V c;
+      c.x = (T)v.x;
+      c.y = (T)v.y;
+      buf[t * pitch + e] = c;
+    }
+  }
+  __syncthreads();
+  if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
+    V* twl = buf + tile * pitch;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j << (twlog2 - log2n)];
+    __syncthreads();
+    fftdev::inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, twl, log2n);
+  } else {
+    fftdev::inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, tw, twlog2);
+  }
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int e = idx / tile, t = idx - e * tile;
+    if (t < ntile) {
+      const long b = b0 + t;
+      const long plane = b / M1;
+      out[plane * ((long)M1 * M2) + (long)e * M1 + (b - plane * M1)] = buf[t * pitch + e];
     }
   }
 }
@@ -930,10 +980,22 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
     else
       hipLaunchKernelGGL(k_far2d<T>, g, b, 0, P.stream, k, a1, P.Mf1, P.S, z0, hf, out);
   } else if (P.nfo == kMxO) {
-    hipLaunchKernelGGL((k_far3d<T, kMxO>), g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar,
-                       out);
+    hipLaunchKernelGGL(k_far3d_mx<T>, g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * P.nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2);
   } else {
-    hipLaunchKernelGGL((k_far3d<T, 1>), g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar, out);
+    // coefficients and the x2 transform in one pass (the x1 pass follows in the caller)
+    const int n = P.Mf2, log2n = __builtin_ctz((unsigned)n), pitch = n + 1;
+    const long nbatch = (long)P.Mf1 * P.S;
+    const int tile = fft_tile(P, n, false, nbatch);
+    const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
+                       sizeof(cplx<T>);
+    const cplx<T>* tw = nullptr;
+    if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
+    const dim3 gb((unsigned)((nbatch + tile - 1) / tile));
+    hipLaunchKernelGGL(k_far3d_cols<T>, gb, dim3(256), shm, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, log2n,
+                       tile, tw, P.twlog2, out);
   }
   return hipGetLastError();
 }
