@@ -1808,9 +1808,10 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
   // 1024 threads) or 32 x 16 x 8 (complex128, 117 KiB, 512 threads).  Maxwell: 8 x 8 x 4
   // (complex64) or 8 x 4 x 4 (complex128) with every field staged (47 / 60 KiB for seven
   // fields), or 16 x 16 x 8 staged field by field when the tiles hold few targets.
-  // Far tiles (8-point footprints, one field staged at a time): 8 x 8 x 8 nodes (27 / 53 KiB), or
-  // 16 x 16 x 8 (complex64, 62 KiB) or 16 x 8 x 8 (complex128, 81 KiB) when the 8-node tiles' keys
-  // would not fit the LDS histograms of the binning.
+  // Far tiles (one field staged at a time): complex128 (8-point footprints) 8 x 8 x 8 nodes
+  // (53 KiB), or 16 x 8 x 8 (81 KiB) when the 8-node tiles' keys would not fit the LDS histograms
+  // of the binning; complex64 (4-point footprints) 16 x 16 x 8 (19 x 19 x 11 nodes, 31 KiB: fewer
+  // keys, so longer runs of the binning's record writes, and less halo per owned node).
   // Must match the instantiations below.
   TileCfg C{};
   TileArgs& Tl = C.t;
@@ -1851,8 +1852,9 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
       Tl.nfar = Tl.fnt1 * Tl.fnt2 * Tl.fnt3;
       Tl.nkeys = Tl.nnear + Tl.nfar + 1;
     };
-    // 8-node far tiles (several blocks per CU) unless their keys would overflow the LDS histograms
-    set_far(false);
+    // complex128: 8-node far tiles (two blocks per CU) unless their keys would overflow the LDS
+    // histograms; complex64 (4-point stencils, small footprints): 16 x 16 x 8 far tiles
+    set_far(sizeof(T) == 4);
     if (Tl.nkeys > kBinLdsKeys) set_far(true);
     e = ensure_bin_scratch(P, T_, Tl.nkeys);
     if (e != hipSuccess) return e;
