@@ -352,13 +352,13 @@ def _timed(fn, steps, warmup):
 
 def run_batched2d(args):
     """64 instances k ~ U[1,20], alpha ~ U[-0.5,0.5] (Wood and special cases rejected),
-    x1 sizes 256 * 2^U{0..3}, 128 transverse slices, 1e6 targets each, complex64."""
+    x1 sizes 256 * U{1..8}, 128 transverse slices, 1e6 targets each, complex64."""
     import numpy as np
     import torch
     from paper_1801_05977_amd import qpgf, workloads
     n, per, M2 = 64, 1_000_000, 128
     k, a = workloads.instances_2d(n, seed=1, k_range=(1.0, 20.0), n2_max=M2 // 2)
-    m1 = [int(256 << v) for v in np.random.default_rng(1).integers(0, 4, n)]
+    m1 = workloads.x1_sizes_2d(n, seed=1)
     t_off = np.arange(n + 1, dtype=np.int64) * per
     x = torch.from_numpy(workloads.targets(n * per, 2, seed=1)).cuda()
     prec = qpgf.C64 if args.prec == "c64" else qpgf.C128

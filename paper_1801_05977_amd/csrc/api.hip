@@ -41,6 +41,8 @@ qpgf_status hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 bool pow2_in(int m, int lo, int hi) { return m >= lo && m <= hi && (m & (m - 1)) == 0; }
+// x1 sizes of the 2D grids: m = 2^a r, a >= 1, r in {1, 3, 5, 7} (the transforms' radices)
+bool m1_2d_in(int m, int lo, int hi) { return m >= lo && m <= hi && (m & 1) == 0 && fftdev::fft_length_ok(m); }
 
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n.
 void gauss_legendre(int n, std::vector<long double>& x, std::vector<long double>& w) {
@@ -118,8 +120,9 @@ qpgf_status validate(const qpgf_params* p) {
   if (!p) return fail(QPGF_E_ARG, "params is NULL");
   if (p->kind < 0 || p->kind > 4) return fail(QPGF_E_ARG, "unknown kind");
   if (p->prec != QPGF_C128 && p->prec != QPGF_C64) return fail(QPGF_E_ARG, "unknown precision");
-  if (!pow2_in(p->m1, 16, 4096) || !pow2_in(p->m2, 16, 4096))
-    return fail(QPGF_E_SIZE, "m1 and m2 must be powers of two in [16, 4096]");
+  if (kind_is_2d(p->kind) ? !m1_2d_in(p->m1, 16, 4096) : !pow2_in(p->m1, 16, 4096))
+    return fail(QPGF_E_SIZE, "m1 must be in [16, 4096]: a power of two, or in 2D 2^a r with a >= 1 and r = 3, 5 or 7");
+  if (!pow2_in(p->m2, 16, 4096)) return fail(QPGF_E_SIZE, "m2 must be a power of two in [16, 4096]");
   if (!kind_is_2d(p->kind) && !pow2_in(p->m3, 16, 4096))
     return fail(QPGF_E_SIZE, "m3 must be a power of two in [16, 4096]");
   {
@@ -179,7 +182,10 @@ FarGeom qpgf::far_geometry(const Plan& P, double kmax, int M1) {
   int mk = floor_m;
   while (mk < want && mk < 4096) mk <<= 1;
   const int cap = (P.dim == 3 && c128) ? 2048 : 4096;   // the 3D far slab's x2 axis is a column axis
-  g.Mf1 = P.p.far_m ? P.p.far_m : std::min(std::max(M1, mk), 4096);
+  // at least the near grid's modes along x1, rounded up to a power of two (2D x1 sizes 2^a r)
+  int m1f = 16;
+  while (m1f < M1) m1f <<= 1;
+  g.Mf1 = P.p.far_m ? P.p.far_m : std::min(std::max(m1f, mk), 4096);
   g.Mf2 = P.dim == 3 ? (P.p.far_m ? P.p.far_m : std::min(std::max(P.M2, mk), cap)) : 1;
   if (P.p.far_h > 0.0) {
     g.hf = P.p.far_h;
@@ -629,15 +635,29 @@ qpgf_status qpgf_plan_create(const qpgf_params* p, qpgf_plan** out) {
   }
   // twiddles e^{+2 pi i j / NT}
   {
-    // every transform length up to 4096 (far slabs grow with k) reads this table with a stride
-    const int NT = 1 << kMaxLog2;
-    P.twlog2 = __builtin_ctz((unsigned)NT);
+    // every transform length (far slabs grow with k) divides NT and reads this table with a stride;
+    // one octant is evaluated, the rest follows by symmetry: quadrant turns multiply by i, and
+    // within a quadrant e^{i(pi/2 - t)} swaps cos and sin
+    const int NT = kTwiddles, NQ = NT / 4;
+    P.ntw = NT;
+    std::vector<long double> cb(NQ / 2 + 1), sb(NQ / 2 + 1);
+    for (int q = 0; q <= NQ / 2; ++q) {
+      const long double a = 2.0L * kPiL * q / NT;
+      cb[q] = cosl(a);
+      sb[q] = sinl(a);
+    }
     std::vector<double2> tw(NT);
     std::vector<float2> twf(NT);
     for (int j = 0; j < NT; ++j) {
-      long double a = 2.0L * kPiL * j / NT;
-      tw[j] = make_double2((double)cosl(a), (double)sinl(a));
-      twf[j] = make_float2((float)cosl(a), (float)sinl(a));
+      const int quad = j / NQ, q = j - quad * NQ;
+      long double c = q <= NQ / 2 ? cb[q] : sb[NQ - q], sn = q <= NQ / 2 ? sb[q] : cb[NQ - q];
+      for (int t = 0; t < quad; ++t) {
+        const long double c0 = c;
+        c = -sn;
+        sn = c0;
+      }
+      tw[j] = make_double2((double)c, (double)sn);
+      twf[j] = make_float2((float)c, (float)sn);
     }
     PLAN_ST(upload(&P.tw, tw));
     PLAN_ST(upload(&P.twf, twf));
@@ -995,7 +1015,8 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
   if (n_inst <= 0 || !k || !alpha || !m1 || !t_off) return fail(QPGF_E_ARG, "need n_inst > 0 and host k, alpha, m1, t_off");
   if (t_off[0] != 0) return fail(QPGF_E_ARG, "t_off[0] must be 0");
   for (int i = 0; i < n_inst; ++i) {
-    if (!pow2_in(m1[i], 16, P.M1)) return fail(QPGF_E_SIZE, "m1[i] must be a power of two in [16, params.m1]");
+    if (!m1_2d_in(m1[i], 16, P.M1))
+      return fail(QPGF_E_SIZE, "m1[i] must be in [16, params.m1]: 2^a r with a >= 1 and r = 1, 3, 5 or 7");
     if (t_off[i + 1] < t_off[i]) return fail(QPGF_E_ARG, "t_off must be non-decreasing");
   }
   const int64_t T = t_off[n_inst];
@@ -1055,16 +1076,16 @@ extern "C" qpgf_status qpgf_g2d_batched(qpgf_plan* plan, int n_inst, const doubl
     gather_inst_2d(P, k[i], alpha[i], M, fg[i], (long)goff, (long)foff, (long)t_off[i], (long)t_off[i + 1], gb,
                    h + Lo.gat_off + i * gsz);
     gb += (long)((t_off[i + 1] - t_off[i] + 255) / 256);
-    FftSeg sT{(long)goff, P.M2, __builtin_ctz((unsigned)P.M2), (long)M, (long)M, (long)M, 1, 0,
+    FftSeg sT{(long)goff, P.M2, (long)M, (long)M, (long)M, 1, 0,
               fft_tile(P, P.M2, false, M), tb};
     tb += (sT.nbatch + sT.tile - 1) / sT.tile;
     // column transforms: padded rows; plus the twiddles when they fit
     Lo.lds_T = std::max(Lo.lds_T, (long)sT.tile * (sT.n + 1) +
                                       (fft_twiddles_in_lds(sT.tile, sT.n + 1, sT.n, P.esize) ? sT.n : 0));
-    FftSeg sR{(long)goff, M, __builtin_ctz((unsigned)M), 1, (long)P.M2, 1, 0, (long)M, fft_tile(P, M, true, P.M2), rrb};
+    FftSeg sR{(long)goff, M, 1, (long)P.M2, 1, 0, (long)M, fft_tile(P, M, true, P.M2), rrb};
     rrb += (sR.nbatch + sR.tile - 1) / sR.tile;
     Lo.lds_R = std::max(Lo.lds_R, (long)sR.tile * sR.n + (fft_twiddles_in_lds(sR.tile, sR.n, sR.n, P.esize) ? sR.n : 0));
-    FftSeg sF{(long)foff, MF, __builtin_ctz((unsigned)MF), 1, (long)SF, 1, 0, (long)MF, fft_tile(P, MF, true, SF), frb};
+    FftSeg sF{(long)foff, MF, 1, (long)SF, 1, 0, (long)MF, fft_tile(P, MF, true, SF), frb};
     frb += (sF.nbatch + sF.tile - 1) / sF.tile;
     Lo.lds_F = std::max(Lo.lds_F, (long)sF.tile * sF.n + (fft_twiddles_in_lds(sF.tile, sF.n, sF.n, P.esize) ? sF.n : 0));
     std::memcpy(h + Lo.segT_off + i * sizeof(FftSeg), &sT, sizeof sT);
@@ -1153,6 +1174,7 @@ extern "C" qpgf_status qpgf_plan_autotune(qpgf_plan* plan, const char* cache_pat
   if (P.dim == 2) {
     shapes.push_back({P.M2, false, (long)P.M1 * P.nf});
     for (int n = 16; n <= P.M1; n <<= 1) shapes.push_back({n, true, (long)P.M2 * P.nf});
+    if (P.M1 & (P.M1 - 1)) shapes.push_back({P.M1, true, (long)P.M2 * P.nf});   // 2^a r
     for (int n = 16; n <= P.Mf1; n <<= 1) shapes.push_back({n, true, (long)P.S * P.nfo});
   } else {
     shapes.push_back({P.M3, false, (long)P.M1 * P.M2 * P.nf});

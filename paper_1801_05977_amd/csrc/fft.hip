@@ -20,8 +20,8 @@ namespace {
 using namespace fftdev;
 
 template <typename T>
-__device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch, long b_in,
-                                         long s_in, long s_out, int tile, const cplx<T>* __restrict__ tw, int twlog2,
+__device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, long es, long nbatch, long b_in,
+                                         long s_in, long s_out, int tile, const cplx<T>* __restrict__ tw, int ntw,
                                          long blk, char* smem_raw) {
   using V = cplx<T>;
   const int pitch = n + (es == 1 ? 0 : 1);   // pad column tiles so their LDS writes do not share a bank
@@ -43,11 +43,12 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, int 
   if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
     // the n twiddles of this length, read once into LDS after the block's data
     V* twl = buf + tile * pitch;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j << (twlog2 - log2n)];
+    const int stride = ntw / n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j * stride];
     __syncthreads();
-    inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, twl, log2n);
+    inverse_dft_lds<T>(buf, n, pitch, ntile, twl, n);
   } else {
-    inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, tw, twlog2);
+    inverse_dft_lds<T>(buf, n, pitch, ntile, tw, ntw);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int t, e;
@@ -62,11 +63,11 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, int log2n, long es, long nbatch,
+__global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, long es, long nbatch,
                                              long b_in, long s_in, long s_out, int tile,
-                                             const cplx<T>* __restrict__ tw, int twlog2) {
+                                             const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ char smem_raw[];
-  fft_body<T>(data, n, log2n, es, nbatch, b_in, s_in, s_out, tile, tw, twlog2, blockIdx.x, smem_raw);
+  fft_body<T>(data, n, es, nbatch, b_in, s_in, s_out, tile, tw, ntw, blockIdx.x, smem_raw);
 }
 
 // Several independent batched transforms (segments, e.g. one per instance, of
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, 
 // first block is <= b.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, const FftSeg* __restrict__ segs,
-                                                   int nseg, const cplx<T>* __restrict__ tw, int twlog2) {
+                                                   int nseg, const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ char smem_raw[];
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
@@ -83,14 +84,13 @@ __global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, c
     else hi = mid - 1;
   }
   const FftSeg g = segs[lo];
-  fft_body<T>(base + g.off, g.n, g.log2n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, twlog2,
+  fft_body<T>(base + g.off, g.n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, ntw,
               (long)blockIdx.x - g.blk0, smem_raw);
 }
 
 template <typename T>
 hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   if (n <= 1 || nbatch <= 0) return hipSuccess;
-  const int log2n = __builtin_ctz((unsigned)n);
   int tile = fft_tile(P, n, es == 1, nbatch);
   const int pitch = n + (es == 1 ? 0 : 1);
   const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
@@ -98,8 +98,8 @@ hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in,
   const long nblk = (nbatch + tile - 1) / tile;
   const cplx<T>* tw = nullptr;
   if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
-  hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(256), shm, P.stream, static_cast<cplx<T>*>(data), n, log2n,
-                     es, nbatch, b_in, s_in, s_out, tile, tw, P.twlog2);
+  hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(256), shm, P.stream, static_cast<cplx<T>*>(data), n,
+                     es, nbatch, b_in, s_in, s_out, tile, tw, P.ntw);
   return hipGetLastError();
 }
 
@@ -109,7 +109,7 @@ hipError_t fft_multi_impl(Plan& P, void* base, const FftSeg* dsegs, int nseg, lo
   const cplx<T>* tw = nullptr;
   if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
   hipLaunchKernelGGL(k_fft_multi<T>, dim3((unsigned)nblocks), dim3(256), shm, P.stream, static_cast<cplx<T>*>(base),
-                     dsegs, nseg, tw, P.twlog2);
+                     dsegs, nseg, tw, P.ntw);
   return hipGetLastError();
 }
 

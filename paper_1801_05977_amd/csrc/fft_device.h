@@ -1,8 +1,8 @@
 // Device building blocks of the inverse DFTs (unnormalised, e^{+2 pi i jp/n},
-// power-of-two lengths): radix-8/4/2 butterflies in registers and one
-// in-place Stockham autosort pass over transforms held in LDS.  Shared by the
-// FFT kernels and by the 3D fill, which transforms its pencils along the
-// transverse axis before writing them.
+// lengths n = 2^a r with r in {1, 3, 5, 7}): radix-8/4/2 and radix-3/5/7
+// butterflies in registers and one in-place Stockham autosort pass over
+// transforms held in LDS.  Shared by the FFT kernels and by the 3D fill, which
+// transforms its pencils along the transverse axis before writing them.
 #pragma once
 
 #include "qpgf_internal.h"
@@ -70,24 +70,79 @@ __device__ __forceinline__ void dft2(V v[2]) {
   v[1] = c_sub(a, v[1]);
 }
 
+// cos and sin of 2 pi q / R for the odd radices (q = 1 .. (R - 1)/2)
+__host__ __device__ constexpr double cos_odd(int R, int q) {
+  return R == 3 ? -0.5
+         : R == 5 ? (q == 1 ? 0.30901699437494742410 : -0.80901699437494742410)
+                  : (q == 1 ? 0.62348980185873353053 : q == 2 ? -0.22252093395631440429 : -0.90096886790241912624);
+}
+__host__ __device__ constexpr double sin_odd(int R, int q) {
+  return R == 3 ? 0.86602540378443864676
+         : R == 5 ? (q == 1 ? 0.95105651629515357212 : 0.58778525229247312917)
+                  : (q == 1 ? 0.78183148246802980871 : q == 2 ? 0.97492791218182360702 : 0.43388373911755812048);
+}
+
+// inverse DFT of odd prime length R in registers, y_m = sum_r v_r e^{+2 pi i r m / R}: the inputs
+// r and R - r share cos(2 pi r m / R) and carry opposite sines, so each pair of outputs m, R - m
+// takes (R - 1)/2 cosine and sine sums over a_q = v_q + v_{R-q} and b_q = v_q - v_{R-q}
+template <int R, typename V, typename T>
+__device__ __forceinline__ void dft_odd(V v[R]) {
+  constexpr int H = (R - 1) / 2;
+  V a[H], b[H];
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    a[q - 1] = c_add(v[q], v[R - q]);
+    b[q - 1] = c_sub(v[q], v[R - q]);
+  }
+  V out[R];
+  out[0] = v[0];
+#pragma unroll
+  for (int q = 0; q < H; ++q) out[0] = c_add(out[0], a[q]);
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    V cr = v[0], si;
+    si.x = 0;
+    si.y = 0;
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      const int qm = (q * m) % R;                     // cos(2 pi qm / R) = cos(2 pi id / R)
+      const int id = qm <= H ? qm : R - qm;
+      const T c = (T)cos_odd(R, id);
+      const T sn = (T)(qm <= H ? sin_odd(R, id) : -sin_odd(R, id));
+      cr.x += c * a[q - 1].x;
+      cr.y += c * a[q - 1].y;
+      si.x += sn * b[q - 1].x;
+      si.y += sn * b[q - 1].y;
+    }
+    out[m] = c_addi(cr, si);       // y_m = cr + i si
+    out[R - m] = c_subi(cr, si);   // y_{R-m} = cr - i si
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = out[r];
+}
+
 template <int R, typename V, typename T>
 __device__ __forceinline__ void dftR(V v[R]) {
   if constexpr (R == 8) dft8<V, T>(v);
   else if constexpr (R == 4) dft4<V>(v);
-  else dft2<V>(v);
+  else if constexpr (R == 2) dft2<V>(v);
+  else dft_odd<R, V, T>(v);
 }
 
 // One in-place Stockham pass of radix R over `ntile` transforms of length n
 // held in LDS (row pitch `pitch`): every thread first reads its butterflies'
 // inputs into registers, the block synchronises, then writes the outputs.
-// At most MAXB butterflies per thread (256 threads).
+// Ns (the product of the radices already applied) is a power of two: the odd
+// radix, if any, takes the last pass.  Twiddles e^{2 pi i q / ntw} at stride
+// ntw / (Ns R) from a table of ntw entries.  At most MAXB butterflies per thread
+// (256 threads).
 template <typename T, int R, int MAXB>
-__device__ __forceinline__ void stockham_pass(cplx<T>* buf, int n, int pitch, int ntile, int Ns, int lr,
-                                              const cplx<T>* __restrict__ tw, int twlog2) {
+__device__ __forceinline__ void stockham_pass(cplx<T>* buf, int n, int pitch, int ntile, int Ns,
+                                              const cplx<T>* __restrict__ tw, int ntw) {
   using V = cplx<T>;
   const int nb = n / R;
   const int total = ntile * nb;
-  const int step_log = twlog2 - (__builtin_ctz(Ns) + lr);   // NT / (Ns R)
+  const int step = ntw / (Ns * R);
   V v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
@@ -108,10 +163,10 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, int n, int pitch, in
       const int kk = j & (Ns - 1);
       if (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw[(r * kk) << step_log]);
+        for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw[(r * kk) * step]);
       }
       dftR<R, V, T>(v[q]);
-      V* dst = buf + t * pitch + ((j - kk) << lr) + kk;
+      V* dst = buf + t * pitch + (j - kk) * R + kk;
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
@@ -123,21 +178,33 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, int n, int pitch, in
 template <typename T> constexpr int lds_cap() { return 65536 / (int)sizeof(cplx<T>); }
 
 
-// All passes of inverse DFTs of length n = 2^log2n over `ntile` transforms in
-// LDS (row pitch `pitch`): radix-8 passes, then one radix-4 or radix-2 pass for
-// the remaining factor.  256 threads; ntile * n <= lds_cap<T>().
+// All passes of inverse DFTs of length n = 2^a r (r in {1, 3, 5, 7}) over `ntile` transforms in
+// LDS (row pitch `pitch`): radix-8 passes, one radix-4 or radix-2 pass for the rest of 2^a, then
+// the radix-r pass.  256 threads; ntile * n <= lds_cap<T>(); tw holds ntw twiddles, n | ntw.
 template <typename T>
-__device__ __forceinline__ void inverse_dft_lds(cplx<T>* buf, int n, int log2n, int pitch, int ntile,
-                                                const cplx<T>* __restrict__ tw, int twlog2) {
+__device__ __forceinline__ void inverse_dft_lds(cplx<T>* buf, int n, int pitch, int ntile,
+                                                const cplx<T>* __restrict__ tw, int ntw) {
   constexpr int CAP = lds_cap<T>();
-  int Ns = 1, rem = log2n;
+  const int odd = n >> __builtin_ctz((unsigned)n);
+  int Ns = 1, rem = __builtin_ctz((unsigned)n);
   while (rem >= 3) {
-    stockham_pass<T, 8, CAP / (8 * 256)>(buf, n, pitch, ntile, Ns, 3, tw, twlog2);
+    stockham_pass<T, 8, CAP / (8 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
     Ns <<= 3;
     rem -= 3;
   }
-  if (rem == 2) stockham_pass<T, 4, CAP / (4 * 256)>(buf, n, pitch, ntile, Ns, 2, tw, twlog2);
-  else if (rem == 1) stockham_pass<T, 2, CAP / (2 * 256)>(buf, n, pitch, ntile, Ns, 1, tw, twlog2);
+  if (rem == 2) stockham_pass<T, 4, CAP / (4 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
+  else if (rem == 1) stockham_pass<T, 2, CAP / (2 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
+  Ns <<= rem;
+  if (odd == 3) stockham_pass<T, 3, (CAP + 3 * 256 - 1) / (3 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
+  else if (odd == 5) stockham_pass<T, 5, (CAP + 5 * 256 - 1) / (5 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
+  else if (odd == 7) stockham_pass<T, 7, (CAP + 7 * 256 - 1) / (7 * 256)>(buf, n, pitch, ntile, Ns, tw, ntw);
+}
+
+// Lengths the transforms take: 2^a r, r in {1, 3, 5, 7} (r = 1: powers of two).
+__host__ __device__ inline bool fft_length_ok(int n) {
+  if (n < 2) return false;
+  const int odd = n >> __builtin_ctz((unsigned)n);
+  return odd == 1 || odd == 3 || odd == 5 || odd == 7;
 }
 
 }  // namespace fftdev

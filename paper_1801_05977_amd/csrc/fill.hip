@@ -193,7 +193,7 @@ template <typename T, int NF, bool FUSE, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __restrict__ xq,
                                                 const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                 const double2* __restrict__ htab, cplx<T>* __restrict__ out,
-                                                const cplx<T>* __restrict__ tw, int twlog2) {
+                                                const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ double2 sa[];
   // FUSE: the pencils, [pencil][jt'] with pitch Mt + 1, after the weights
   cplx<T>* pen = reinterpret_cast<cplx<T>*>(sa + TP * A.Q);
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   }
   if constexpr (FUSE) {
     __syncthreads();
-    fftdev::inverse_dft_lds<T>(pen, A.Mt, __builtin_ctz((unsigned)A.Mt), pitch, TP, tw, twlog2);
+    fftdev::inverse_dft_lds<T>(pen, A.Mt, pitch, TP, tw, ntw);
     // grid values [i3][j2'][j1'], TP consecutive j1' per slice
     const int np = min(TP, A.M1 - j1p0);
     for (int idx = threadIdx.x; idx < TP * A.Mt; idx += blockDim.x) {
@@ -285,7 +285,7 @@ __device__ __forceinline__ void fill2d_body(const FillArgs& A, int blk, const do
   if (j1p >= A.M1) return;
   const double2* ap = sa + ip;
   const double lead0 = a * a - A.k * A.k;
-  const int jt_tab = j1 & (M1t - 1);
+  const int jt_tab = j1 < 0 ? j1 + M1t : j1;
   // E-hat = -(alpha^2/2) e_tt - (k^2/4) e_rr - (alpha^3/6) e_ttt - (alpha k^2/4) e_trr (real)
   const double ka = A.k * A.k;
   const double ce0 = -0.5 * A.a1 * A.a1, ce1 = -0.25 * ka;
@@ -690,8 +690,8 @@ __global__ void k_far3d_mx(double k, double a1, double a2, int M1, int M2, int S
 // passes; the coefficients never go to memory).  Batch b: slice b / M1, column b % M1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double a2, int M1, int M2, int S, double z0,
-                                                    double hf, int log2n, int tile, const cplx<T>* __restrict__ tw,
-                                                    int twlog2, cplx<T>* __restrict__ out) {
+                                                    double hf, int tile, const cplx<T>* __restrict__ tw,
+                                                    int ntw, cplx<T>* __restrict__ out) {
   extern __shared__ char smem_raw[];
   using V = cplx<T>;
   const int n = M2, pitch = n + 1;
@@ -716,11 +716,12 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
   __syncthreads();
   if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
     V* twl = buf + tile * pitch;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j << (twlog2 - log2n)];
+    const int stride = ntw / n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j * stride];
     __syncthreads();
-    fftdev::inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, twl, log2n);
+    fftdev::inverse_dft_lds<T>(buf, n, pitch, ntile, twl, n);
   } else {
-    fftdev::inverse_dft_lds<T>(buf, n, log2n, pitch, ntile, tw, twlog2);
+    fftdev::inverse_dft_lds<T>(buf, n, pitch, ntile, tw, ntw);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int e = idx / tile, t = idx - e * tile;
@@ -936,31 +937,31 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
     if (P.nf == kMxF) {
       if (spec)
         hipLaunchKernelGGL((k_fill3d<T, kMxF, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
       else
         hipLaunchKernelGGL((k_fill3d<T, kMxF, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
     } else if (P.nf == kMxT) {
       if (spec)
         hipLaunchKernelGGL((k_fill3d<T, kMxT, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
       else
         hipLaunchKernelGGL((k_fill3d<T, kMxT, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
     } else if (fuse) {
       if (spec)
         hipLaunchKernelGGL((k_fill3d<T, 1, true, true>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
       else
         hipLaunchKernelGGL((k_fill3d<T, 1, true, false>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
     } else {
       if (spec)
         hipLaunchKernelGGL((k_fill3d<T, 1, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
       else
         hipLaunchKernelGGL((k_fill3d<T, 1, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.twlog2);
+                           P.htab, out, tw, P.ntw);
     }
   }
   return hipGetLastError();
@@ -986,7 +987,7 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
     return launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * P.nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2);
   } else {
     // coefficients and the x2 transform in one pass (the x1 pass follows in the caller)
-    const int n = P.Mf2, log2n = __builtin_ctz((unsigned)n), pitch = n + 1;
+    const int n = P.Mf2, pitch = n + 1;
     const long nbatch = (long)P.Mf1 * P.S;
     const int tile = fft_tile(P, n, false, nbatch);
     const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
@@ -994,8 +995,8 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
     const cplx<T>* tw = nullptr;
     if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
     const dim3 gb((unsigned)((nbatch + tile - 1) / tile));
-    hipLaunchKernelGGL(k_far3d_cols<T>, gb, dim3(256), shm, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, log2n,
-                       tile, tw, P.twlog2, out);
+    hipLaunchKernelGGL(k_far3d_cols<T>, gb, dim3(256), shm, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf,
+                       tile, tw, P.ntw, out);
   }
   return hipGetLastError();
 }

@@ -823,6 +823,10 @@ __global__ __launch_bounds__(256) void k_gather3d_overflow(GArgs A, const cplx<T
 }
 
 // 2D: G (Algorithm 2.1).
+// i mod M for i in [-M, 2M): x1 node indices of the 2D grids, whose length M1 = 2^a r need not be a
+// power of two
+__device__ __forceinline__ int wrap_m(int i, int M) { return i < 0 ? i + M : (i >= M ? i - M : i); }
+
 // 4 x 4 stencil sum of a 2D grid: rows[b] is the first element of stencil row b, i0 the
 // first x1 node (periodic in x1).
 template <typename T>
@@ -832,7 +836,7 @@ __device__ __forceinline__ double2 stencil2d_scalar(const cplx<T>* __restrict__ 
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc.add(w2[b] * w1[a], g[rows[b] + ((i0 + a) & (M1 - 1))]);
+    for (int a = 0; a < 4; ++a) acc.add(w2[b] * w1[a], g[rows[b] + wrap_m(i0 + a, M1)]);
   return acc.get();
 }
 template <typename T>
@@ -874,8 +878,8 @@ __device__ __forceinline__ double2 stencil2d<float>(const float2* __restrict__ g
     // the row wraps in x1: four single loads, the same sums
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      rs[b] = row4v(g[rows[b] + i0], g[rows[b] + ((i0 + 1) & (M1 - 1))], g[rows[b] + ((i0 + 2) & (M1 - 1))],
-                    g[rows[b] + ((i0 + 3) & (M1 - 1))], w1);
+      rs[b] = row4v(g[rows[b] + i0], g[rows[b] + wrap_m(i0 + 1, M1)], g[rows[b] + wrap_m(i0 + 2, M1)],
+                    g[rows[b] + wrap_m(i0 + 3, M1)], w1);
   } else {
 #pragma unroll
     for (int b = 0; b < 4; ++b) rs[b] = row4(g + rows[b] + i0, w1);
@@ -914,7 +918,7 @@ __device__ __forceinline__ void stencil2d_multi(const cplx<T>* __restrict__ g, c
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const cplx<T>* q = g + (rows[b] + ((i0 + a) & (M1 - 1))) * NF;
+      const cplx<T>* q = g + (rows[b] + wrap_m(i0 + a, M1)) * NF;
 #pragma unroll
       for (int f = 0; f < NF; ++f) acc[f].add(w2[b] * w1[a], q[f]);
     }
@@ -1049,7 +1053,7 @@ __device__ __forceinline__ bool gather2d_one(const GArgs& A, const cplx<T>* __re
       T w1[4], w2[4];
       const double u = t * A.ih1, p = floor(u);
       lag4<T>((T)(u - p), w1);
-      const int i0 = ((int)p - 1) & (A.M1 - 1);
+      const int i0 = wrap_m((int)p - 1, A.M1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
       long rows[4];
@@ -1306,7 +1310,7 @@ __device__ __forceinline__ bool gather2d_grad_one(const GArgs& A, const cplx<T>*
       T w1[4], w2[4];
       const double u = t * A.ih1, p = floor(u);
       lag4<T>((T)(u - p), w1);
-      const int i0 = ((int)p - 1) & (A.M1 - 1);
+      const int i0 = wrap_m((int)p - 1, A.M1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
       long rows[4];
@@ -1383,7 +1387,7 @@ __device__ __forceinline__ bool gather2d_hess_one(const GArgs& A, const cplx<T>*
       T w1[4], w2[4];
       const double u = t * A.ih1, p = floor(u);
       lag4<T>((T)(u - p), w1);
-      const int i0 = ((int)p - 1) & (A.M1 - 1);
+      const int i0 = wrap_m((int)p - 1, A.M1);
       const double u2 = x2 * A.ih2, p2 = floor(u2);
       lag4<T>((T)(u2 - p2), w2);
       long rows[4];
@@ -1675,7 +1679,7 @@ __global__ __launch_bounds__(256) void k_quads(const float2* __restrict__ in, fl
   const int a = (int)(v & 3);
   const long row = e / M1;
   const int i1 = (int)(e - row * M1);
-  q[v] = in[row * M1 + ((i1 + a) & (M1 - 1))];
+  q[v] = in[row * M1 + wrap_m(i1 + a, M1)];
 }
 
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };

@@ -102,17 +102,19 @@ __host__ __device__ inline double cut_Y2(double r, double eps) { return -smooth_
 // plan
 // ---------------------------------------------------------------------------
 // One batched inverse-FFT segment (see k_fft_multi): `nbatch` transforms of
-// length n = 2^log2n starting at element `off`; transform b starts at
+// length n starting at element `off`; transform b starts at
 // (b / b_in) * s_out + (b % b_in) * s_in, elements `es` apart; `tile` transforms
 // per block; the segment's first block is blk0.
 struct FftSeg {
   long off;
-  int n, log2n;
+  int n;
   long es, nbatch, b_in, s_in, s_out;
   int tile;
   long blk0;
 };
 constexpr int kMaxLog2 = 12;   // m <= 4096
+// Twiddle table length: every transform length n = 2^a r (a <= 12, r in {1, 3, 5, 7}) divides it.
+constexpr int kTwiddles = (1 << kMaxLog2) * 3 * 5 * 7;
 
 // Per-call target scratch of the gathers.
 struct TargetScratch {
@@ -158,9 +160,9 @@ struct Plan {
   double* wrq = nullptr;       // weights
   double* y1q = nullptr;       // Y'(rq)
   double* y2q = nullptr;       // Y''(rq)
-  double2* tw = nullptr;       // twiddles e^{2 pi i j / NT}, double
+  double2* tw = nullptr;       // twiddles e^{2 pi i j / ntw}, double
   float2* twf = nullptr;       // same, float
-  int twlog2 = 0;
+  int ntw = 0;
   double2* F1 = nullptr;       // 2D singular tables (FFT order [j2'][j1'])
   double2* F2 = nullptr;
   size_t gridI_bytes = 0;      // its size (0: none)

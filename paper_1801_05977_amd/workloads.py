@@ -60,3 +60,10 @@ def instances_2d(n, seed, k_range=(1.0, 20.0), a_range=(-0.5, 0.5), min_beta=1e-
         ks.append(k)
         als.append(a)
     return np.array(ks), np.array(als)
+
+
+def x1_sizes_2d(n, seed, unit=256, most=8):
+    """n x1 grid sizes unit * U{1..most} (with unit = 256: 256 .. 2048, the odd multiples taking the
+    transforms' radix-3, -5 and -7 passes)."""
+    rng = np.random.default_rng(seed)
+    return [int(unit * v) for v in rng.integers(1, most + 1, n)]

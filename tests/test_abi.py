@@ -82,6 +82,26 @@ def test_plan_create_rejects_bad_params(field, value, status):
     assert L.qpgf_last_error().decode()
 
 
+@pytest.mark.parametrize("kind", [qpgf.KIND_G2D, qpgf.KIND_G2D_GRAD, qpgf.KIND_G2D_HESS_DIFF, qpgf.KIND_GD3D])
+@pytest.mark.parametrize("m1", [15, 18, 36, 90, 100, 4104, 8192])
+def test_plan_create_rejects_x1_sizes_outside_the_transform_lengths(kind, m1):
+    """x1 sizes are 2^a r with a >= 1 and r in {1, 3, 5, 7} in 2D (powers of two in 3D), 16 .. 4096."""
+    L = qpgf.lib()
+    p = qpgf.default_params(kind, qpgf.C128, m1, 32, 32)
+    h = ctypes.c_void_p()
+    assert L.qpgf_plan_create(ctypes.byref(p), ctypes.byref(h)) == 4
+    assert not h.value and "m1" in L.qpgf_last_error().decode()
+
+
+@pytest.mark.parametrize("m1", [24, 96, 768, 1280, 1792])
+def test_plan_create_rejects_mixed_radix_x1_in_3d(m1):
+    L = qpgf.lib()
+    p = qpgf.default_params(qpgf.KIND_GD3D, qpgf.C128, m1, 32, 32)
+    h = ctypes.c_void_p()
+    assert L.qpgf_plan_create(ctypes.byref(p), ctypes.byref(h)) == 4
+    assert not h.value
+
+
 def test_null_arguments():
     L = qpgf.lib()
     assert L.qpgf_plan_create(None, None) == 1

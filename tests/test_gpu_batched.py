@@ -29,8 +29,11 @@ def _instances(n, seed):
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
 def test_batched_equals_single_instance_plans(prec, tmp_path):
     M2 = 64
-    m1 = [256, 512, 64, 1024, 128, 256]
-    counts = [3000, 1500, 0, 4000, 2500, 777]
+    # 2^a r x1 sizes beside the powers of two, the largest (the plan's) 3 * 256; every plan here takes
+    # the same radial rule for its singular tables (it grows with the grid's largest mode), so the
+    # batched and the single-instance results agree bit for bit
+    m1 = [256, 512, 64, 768, 128, 256, 640, 80, 112]
+    counts = [3000, 1500, 0, 4000, 2500, 777, 2000, 901, 1200]
     t_off = np.concatenate([[0], np.cumsum(counts)])
     k, a = _instances(len(m1), seed=1)
     x = workloads.targets(int(t_off[-1]), 2, seed=4)
@@ -52,7 +55,7 @@ def test_batched_equals_single_instance_plans(prec, tmp_path):
             np.testing.assert_array_equal(g[sl], gi)
             np.testing.assert_array_equal(f[sl], fi.cpu().numpy())
             Pi.close()
-        for i in (0, 3):
+        for i in (0, 3, 6, 8):
             sl = slice(int(t_off[i]), int(t_off[i + 1]))
             o = method.eval_g2d(k[i], a[i], x[sl], m1[i] // 2, M2 // 2)
             assert parity(g[sl], o) <= TOL[prec], (rep, i)
@@ -72,12 +75,15 @@ def test_batched_rejects_bad_instances():
     with pytest.raises(qpgf.QpgfError) as e:
         P.batched([2.1], [0.3], [512], [0, 10], x)                         # m1 above the plan's
     assert e.value.status == 4
+    with pytest.raises(qpgf.QpgfError) as e:
+        P.batched([2.1], [0.3], [144], [0, 10], x)                         # 16 * 9: not 2^a r
+    assert e.value.status == 4
 
 
 @pytest.mark.timeout(900)
 def test_batched_full_size_sampled():
     """The batched benchmark workload: 64 instances (k ~ U[1,20], alpha ~ U[-1/2,1/2], Wood and
-    special cases redrawn), x1 sizes 256 .. 2048, 128 slices, 1e6 targets each, both precisions.
+    special cases redrawn), x1 sizes 256 * U{1..8}, 128 slices, 1e6 targets each, both precisions.
 
     The GPU evaluates all 6.4e7 targets in one batched call; the oracle recomputes 200 seeded
     targets of every instance (with its first and last) from that instance's own coefficients."""
@@ -85,8 +91,8 @@ def test_batched_full_size_sampled():
     from concurrent.futures import ProcessPoolExecutor
     n, per, M2 = 64, 1_000_000, 128
     k, a = workloads.instances_2d(n, seed=1, k_range=(1.0, 20.0), n2_max=M2 // 2)
-    m1 = [int(256 << v) for v in np.random.default_rng(1).integers(0, 4, n)]
-    assert sorted(set(m1)) == [256, 512, 1024, 2048]
+    m1 = workloads.x1_sizes_2d(n, seed=1)
+    assert sorted(set(m1)) == [256 * v for v in range(1, 9)]
     t_off = np.arange(n + 1, dtype=np.int64) * per
     x = workloads.targets(n * per, 2, seed=1)
     rng = np.random.default_rng(21)

@@ -68,7 +68,7 @@ def _edge_targets():
 
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
-@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001)])
+@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001), ((80, 32), 1_003)])
 def test_hess2d_end_to_end(prec, shape, T):
     """Seeded uniform targets (ragged count) plus edge cases; flags exact, values to the parity bar."""
     M1, M2 = shape

@@ -74,7 +74,7 @@ def _edge_targets():
 
 @pytest.mark.parametrize("order", [2, 3])
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
-@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001)])
+@pytest.mark.parametrize("shape,T", [((64, 32), 1_000), ((256, 64), 10_001), ((112, 32), 1_003)])
 def test_ho_end_to_end(prec, order, shape, T):
     M1, M2 = shape
     x = np.vstack([workloads.targets(T, 2, seed=7), _edge_targets()])

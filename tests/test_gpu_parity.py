@@ -126,6 +126,44 @@ def test_g2d_large_grid_row_major_path():
 
 
 @pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("M1", [24, 80, 112, 96])
+def test_g2d_mixed_radix_stages(prec, M1):
+    """x1 sizes 2^a r (r = 3, 5, 7): coefficients and grid element by element; the far slab keeps a
+    power-of-two mode count at least M1."""
+    M2 = 32
+    k, al = 2.1, 0.3
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
+    ref_L = A2 * method.lhat_2d(k, al, M1 // 2, M2 // 2)
+    P.prepare(k, al, 0.0, stage=2)
+    g = cen(P.field().cpu().numpy().reshape(M2, M1).T, (0, 1))
+    ref_G = method.grid_2d(ref_L / A2)
+    tol = 1e-12 if prec == qpgf.C128 else 2e-6
+    assert np.abs(g - ref_G).max() <= tol * np.abs(ref_G).max()
+    assert P.info.far_m1 == (512 if prec == qpgf.C128 else 256)
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
+@pytest.mark.parametrize("M1", [768, 1280, 1792])
+def test_g2d_mixed_radix_x1_sizes(prec, M1):
+    """G on grids of 3, 5 and 7 times 256 x-nodes: seeded targets plus targets whose stencils wrap in x1,
+    against the oracle; the far slab takes the next power of two of modes."""
+    M2, T = 64, 20_001
+    k, al = 2.1, 0.3
+    x = workloads.targets(T, 2, seed=21)
+    P = qpgf.Plan(qpgf.KIND_G2D, prec, M1, M2)
+    g = P(k, al, 0.0, dev(x)).cpu().numpy()
+    m = 1 << (M1 - 1).bit_length()
+    assert P.info.far_m1 == m
+    t = x[:, 0] - 2 * math.pi * np.floor((x[:, 0] + math.pi) / (2 * math.pi))
+    wrap = np.nonzero((t > math.pi - 2 * (2 * math.pi / M1)) | (t < -math.pi + 2 * math.pi / M1))[0]
+    rng = np.random.default_rng(5)
+    pick = np.unique(np.concatenate([wrap[:40], rng.choice(len(x), 400, replace=False)]))
+    assert len(wrap) >= 10
+    o = method.eval_g2d(k, al, x[pick], M1 // 2, M2 // 2)
+    assert parity(g[pick], o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [qpgf.C128, qpgf.C64])
 @pytest.mark.parametrize("shape", [(64, 64, 32), (32, 128, 64)])
 def test_gd3d_small(prec, shape):
     M1, M2, M3 = shape
