@@ -366,7 +366,7 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
     KernelTimer t(P, QPGF_T_HTABLE);
     HIP_TRY(launch_htable(P, k));
   }
-  // from stage 1 on, the 3D single-field fill also runs the transverse transform
+  // from stage 1 on, the 3D fill also runs the transverse transform when its pencils fit in LDS
   const bool fused = stage >= 1 && fill_fuses_transverse(P);
   {
     KernelTimer t(P, QPGF_T_FILL);

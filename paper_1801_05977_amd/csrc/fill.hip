@@ -185,17 +185,18 @@ __device__ __forceinline__ double2 h_interp(const double2* __restrict__ tab, dou
 // L-hat_dj = A3 [ I-terms + H(|xi|) / (|xi|^2 - k^2) ], i.e. K-hat_dj of (3.3)
 // minus F-hat_j of (3.5) with the common 1/(|xi|^2-k^2) cancelled exactly.
 //
-// FUSE: the block also runs the transverse inverse DFT of its TP pencils
-// (Algorithm 3.1 step 1c) in LDS and writes grid values instead of
-// coefficients, saving one pass over the grid (one field only; the transform
-// is the same sequence of passes and twiddles as the separate FFT kernel).
+// FUSE: the block also runs the transverse inverse DFT of its TP pencils of
+// every field (Algorithm 3.1 step 1c; the NF fields of the Maxwell kinds) in
+// LDS and writes grid values instead of coefficients, saving one pass over the
+// grid (the transform is the same sequence of passes and twiddles as the
+// separate FFT kernel).
 template <typename T, int NF, bool FUSE, bool SPEC>
 __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __restrict__ xq,
                                                 const double* __restrict__ wxq, const double2* __restrict__ cs,
                                                 const double2* __restrict__ htab, cplx<T>* __restrict__ out,
                                                 const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ double2 sa[];
-  // FUSE: the pencils, [pencil][jt'] with pitch Mt + 1, after the weights
+  // FUSE: the pencils, [field][pencil][jt'] with pitch Mt + 1, after the weights
   cplx<T>* pen = reinterpret_cast<cplx<T>*>(sa + TP * A.Q);
   const int pitch = A.Mt + 1;
   const int ip = threadIdx.x % TP, lane = threadIdx.x / TP;
@@ -213,22 +214,22 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   const double k2 = A.k * A.k;
   // coefficient jt' of this pencil: into the LDS pencil (FUSE) or the near grid (and the Maxwell fields)
   auto put = [&](int jtp, double J, double2 L) {
-    if constexpr (FUSE) {
-      store_c<T>(pen, (size_t)ip * pitch + jtp, L);
-    } else {
-      const size_t o = ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p;
-      store_c<T>(out, o, L);
-      if (NF == kMxF || NF == kMxT) {
-        // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~) (Algorithm 4.1 step 1c),
-        // pq = 11 22 33 12 13 23 (without 33 for the trace variant)
-        const double cc[3] = {xi1, xi2, J};
-        constexpr int NP = NF - 1;
-        const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+    // field g of coefficient jt': the LDS pencil (FUSE) or the near grid
+    auto put1 = [&](int g, double2 v) {
+      if constexpr (FUSE) store_c<T>(pen, ((size_t)g * TP + ip) * pitch + jtp, v);
+      else store_c<T>(out, g * A.fstride + ((size_t)jtp * A.M2 + j2p) * A.M1 + j1p, v);
+    };
+    put1(0, L);
+    if constexpr (NF == kMxF || NF == kMxT) {
+      // L-hat^{pq} = -c^p c^q L-hat with c = (alpha1 + j1, alpha2 + j2, j3 pi / c~) (Algorithm 4.1 step 1c),
+      // pq = 11 22 33 12 13 23 (without 33 for the trace variant)
+      const double cc[3] = {xi1, xi2, J};
+      constexpr int NP = NF - 1;
+      const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-        for (int f = 0, g = 0; f < 6; ++f) {
-          if (NP == 5 && f == 2) continue;
-          store_c<T>(out, (++g) * A.fstride + o, cscale(L, -cc[P[f]] * cc[Qp[f]]));
-        }
+      for (int f = 0, g = 0; f < 6; ++f) {
+        if (NP == 5 && f == 2) continue;
+        put1(++g, cscale(L, -cc[P[f]] * cc[Qp[f]]));
       }
     }
   };
@@ -255,12 +256,12 @@ __global__ __launch_bounds__(256) void k_fill3d(FillArgs A, const double* __rest
   }
   if constexpr (FUSE) {
     __syncthreads();
-    fftdev::inverse_dft_lds<T>(pen, A.Mt, pitch, TP, tw, ntw);
-    // grid values [i3][j2'][j1'], TP consecutive j1' per slice
+    fftdev::inverse_dft_lds<T>(pen, A.Mt, pitch, TP * NF, tw, ntw);
+    // grid values [field][i3][j2'][j1'], TP consecutive j1' per slice
     const int np = min(TP, A.M1 - j1p0);
-    for (int idx = threadIdx.x; idx < TP * A.Mt; idx += blockDim.x) {
-      const int p = idx % TP, i3 = idx / TP;
-      if (p < np) out[((size_t)i3 * A.M2 + j2p) * A.M1 + j1p0 + p] = pen[p * pitch + i3];
+    for (int idx = threadIdx.x; idx < NF * TP * A.Mt; idx += blockDim.x) {
+      const int p = idx % TP, r = idx / TP, i3 = r % A.Mt, g = r / A.Mt;
+      if (p < np) out[g * A.fstride + ((size_t)i3 * A.M2 + j2p) * A.M1 + j1p0 + p] = pen[(g * TP + p) * pitch + i3];
     }
   }
 }
@@ -933,36 +934,28 @@ hipError_t fill_impl(Plan& P, double k, double a1, double a2, bool fuse, bool sp
     dim3 grid((P.M1 + TP - 1) / TP, P.M2);
     const cplx<T>* tw = nullptr;
     if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
-    const size_t shf = shm + (size_t)TP * (P.Mt + 1) * sizeof(cplx<T>);
+    const size_t shf = shm + (size_t)P.nf * TP * (P.Mt + 1) * sizeof(cplx<T>);
+#define QPGF_FILL3D(NF_, FUSE_, SHM_)                                                                              \
+  do {                                                                                                              \
+    if (spec)                                                                                                       \
+      hipLaunchKernelGGL((k_fill3d<T, NF_, FUSE_, true>), grid, dim3(TP * TL), SHM_, P.stream, A, P.xq, P.wxq, P.cs, \
+                         P.htab, out, tw, P.ntw);                                                                   \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_fill3d<T, NF_, FUSE_, false>), grid, dim3(TP * TL), SHM_, P.stream, A, P.xq, P.wxq,      \
+                         P.cs, P.htab, out, tw, P.ntw);                                                             \
+  } while (0)
     if (P.nf == kMxF) {
-      if (spec)
-        hipLaunchKernelGGL((k_fill3d<T, kMxF, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
-      else
-        hipLaunchKernelGGL((k_fill3d<T, kMxF, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
+      if (fuse) QPGF_FILL3D(kMxF, true, shf);
+      else QPGF_FILL3D(kMxF, false, shm);
     } else if (P.nf == kMxT) {
-      if (spec)
-        hipLaunchKernelGGL((k_fill3d<T, kMxT, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
-      else
-        hipLaunchKernelGGL((k_fill3d<T, kMxT, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
+      if (fuse) QPGF_FILL3D(kMxT, true, shf);
+      else QPGF_FILL3D(kMxT, false, shm);
     } else if (fuse) {
-      if (spec)
-        hipLaunchKernelGGL((k_fill3d<T, 1, true, true>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
-      else
-        hipLaunchKernelGGL((k_fill3d<T, 1, true, false>), grid, dim3(TP * TL), shf, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
+      QPGF_FILL3D(1, true, shf);
     } else {
-      if (spec)
-        hipLaunchKernelGGL((k_fill3d<T, 1, false, true>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
-      else
-        hipLaunchKernelGGL((k_fill3d<T, 1, false, false>), grid, dim3(TP * TL), shm, P.stream, A, P.xq, P.wxq, P.cs,
-                           P.htab, out, tw, P.ntw);
+      QPGF_FILL3D(1, false, shm);
     }
+#undef QPGF_FILL3D
   }
   return hipGetLastError();
 }
@@ -1112,11 +1105,12 @@ hipError_t launch_far2d_multi(Plan& P, const void* dinst, int n_inst, long nbloc
   return hipGetLastError();
 }
 
-// The fill can take the transverse transform over for one 3D field when its TP
-// pencils and the pencil weights fit together in 64 KiB of LDS.
+// The 3D fill takes the transverse transform over when the TP pencils of all its fields and the
+// pencil weights fit together in 64 KiB of LDS (G_d up to long transverse axes; the Maxwell
+// fields at complex64 with up to 32 slices).
 bool fill_fuses_transverse(const Plan& P) {
-  const size_t lds = (size_t)TP * P.p.quad_q * sizeof(double2) + (size_t)TP * (P.Mt + 1) * P.esize;
-  return P.dim == 3 && P.nf == 1 && P.Mt > 1 && lds <= 65536;
+  const size_t lds = (size_t)TP * P.p.quad_q * sizeof(double2) + (size_t)P.nf * TP * (P.Mt + 1) * P.esize;
+  return P.dim == 3 && P.Mt > 1 && lds <= 65536;
 }
 
 hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse) {
