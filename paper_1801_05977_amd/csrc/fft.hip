@@ -1,13 +1,18 @@
 // Batched inverse DFTs (unnormalised, e^{+2 pi i jp/n}) along one axis of a
 // strided array: the grid synthesis of Algorithms 2.1 / 3.1 / 4.1 (steps 1c-1d),
 // L_N(x_p) = sum_j L-hat_j e^{i pi j p / N}, with coefficients and grid points
-// both stored mod n.  Power-of-two lengths, radix-4 (plus one radix-2) Stockham
-// autosort passes staged in LDS.
+// both stored mod n.  Lengths 2^a r (r = 1, 3, 5, 7): radix-8/4/2 Stockham
+// autosort passes and one radix-r pass, staged in LDS.
 //
 // Batch b of a launch starts at element (b / b_in) * s_out + (b % b_in) * s_in
 // and its elements are elem_stride apart.  A block takes `tile` consecutive
 // batches: for rows (elem_stride 1) each batch is one contiguous run, for
 // columns (s_in 1) the tile's batches are adjacent, so both load coalesced.
+// Every thread issues its loads (and stores) 64 bytes at a time before it
+// touches LDS, so a block keeps that many bytes per thread in flight instead of
+// one value; consecutive tiles go to the same XCD (blocks are dealt to the eight
+// XCDs in turn), so the halves of a 128-byte line that two column tiles share
+// meet in one L2.
 #include <algorithm>
 
 #include "fft_device.h"
@@ -19,25 +24,64 @@ namespace {
 
 using namespace fftdev;
 
+// global transfers per thread in flight: 64 bytes (8 complex64 or 4 complex128 values, which
+// stay in registers; larger arrays of complex128 are placed in scratch memory by the compiler)
+template <typename T> constexpr int ld_unroll() { return 64 / (int)sizeof(cplx<T>); }
+
+// Logical block of hardware block b of nblk: the hardware deals blocks to the 8 XCDs in turn,
+// so block b runs on XCD b % 8; logical blocks [x per, (x + 1) per) all run on XCD x.
+__device__ __forceinline__ long xcd_block(long b, long nblk) {
+  const long per = nblk >> 3;
+  return b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
+}
+
 template <typename T>
 __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, long es, long nbatch, long b_in,
                                          long s_in, long s_out, int tile, const cplx<T>* __restrict__ tw, int ntw,
                                          long blk, char* smem_raw) {
   using V = cplx<T>;
-  const int pitch = n + (es == 1 ? 0 : 1);   // pad column tiles so their LDS writes do not share a bank
+  constexpr int kLdU = ld_unroll<T>();
+  const bool rows = es == 1;
+  const int pitch = n + (rows ? 0 : 1);   // pad column tiles so their LDS writes do not share a bank
   V* buf = reinterpret_cast<V*>(smem_raw);
   const long b0 = blk * tile;
   const int ntile = (int)min((long)tile, nbatch - b0);
   const int total = tile * n;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int t, e;
-    if (es == 1) { t = idx / n; e = idx - t * n; }
-    else { e = idx / tile; t = idx - e * tile; }
-    if (t < ntile) {
-      const long b = b0 + t;
-      const long base = (b / b_in) * s_out + (b % b_in) * s_in;
-      buf[t * pitch + e] = data[base + (long)e * es];
+  // element idx of the block's tile: transform t, element e (rows: e fastest; columns: t fastest);
+  // 32-bit quotients (the host keeps batches below 2^31)
+  // (the global offset, and the LDS offset or -1 beyond the block's transforms)
+  const unsigned un = (unsigned)n, ut = (unsigned)tile, ubin = (unsigned)b_in;
+  struct Loc {
+    long g;
+    int l;
+  };
+  auto locate = [&](int idx) -> Loc {
+    unsigned t, e;
+    if (rows) {
+      t = (unsigned)idx / un;
+      e = (unsigned)idx - t * un;
+    } else {
+      e = (unsigned)idx / ut;
+      t = (unsigned)idx - e * ut;
     }
+    if (idx >= total || (int)t >= ntile) return Loc{0, -1};
+    const unsigned b = (unsigned)b0 + t, q = b / ubin;
+    return Loc{(long)q * s_out + (long)(b - q * ubin) * s_in + (long)e * es, (int)(t * (unsigned)pitch + e)};
+  };
+  // (every lane loads, those beyond the block's transforms from element 0, so no load sits in a
+  // branch whose join would wait for it)
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    int o[kLdU];
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      const Loc L = locate(i0 + u * 256 + (int)threadIdx.x);
+      o[u] = L.l;
+      v[u] = data[L.g];
+    }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u)
+      if (o[u] >= 0) buf[o[u]] = v[u];
   }
   __syncthreads();
   if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
@@ -50,15 +94,17 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, long
   } else {
     inverse_dft_lds<T>(buf, n, pitch, ntile, tw, ntw);
   }
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int t, e;
-    if (es == 1) { t = idx / n; e = idx - t * n; }
-    else { e = idx / tile; t = idx - e * tile; }
-    if (t < ntile) {
-      const long b = b0 + t;
-      const long base = (b / b_in) * s_out + (b % b_in) * s_in;
-      data[base + (long)e * es] = buf[t * pitch + e];
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    Loc L[kLdU];
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      L[u] = locate(i0 + u * 256 + (int)threadIdx.x);
+      v[u] = buf[L[u].l >= 0 ? L[u].l : 0];
     }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u)
+      if (L[u].l >= 0) data[L[u].g] = v[u];
   }
 }
 
@@ -67,7 +113,7 @@ __global__ __launch_bounds__(256) void k_fft(cplx<T>* __restrict__ data, int n, 
                                              long b_in, long s_in, long s_out, int tile,
                                              const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ char smem_raw[];
-  fft_body<T>(data, n, es, nbatch, b_in, s_in, s_out, tile, tw, ntw, blockIdx.x, smem_raw);
+  fft_body<T>(data, n, es, nbatch, b_in, s_in, s_out, tile, tw, ntw, xcd_block(blockIdx.x, gridDim.x), smem_raw);
 }
 
 // Several independent batched transforms (segments, e.g. one per instance, of
@@ -77,20 +123,21 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, const FftSeg* __restrict__ segs,
                                                    int nseg, const cplx<T>* __restrict__ tw, int ntw) {
   extern __shared__ char smem_raw[];
+  const long blk = xcd_block(blockIdx.x, gridDim.x);
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (segs[mid].blk0 <= (long)blockIdx.x) lo = mid;
+    if (segs[mid].blk0 <= blk) lo = mid;
     else hi = mid - 1;
   }
   const FftSeg g = segs[lo];
-  fft_body<T>(base + g.off, g.n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, ntw,
-              (long)blockIdx.x - g.blk0, smem_raw);
+  fft_body<T>(base + g.off, g.n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, ntw, blk - g.blk0, smem_raw);
 }
 
 template <typename T>
 hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   if (n <= 1 || nbatch <= 0) return hipSuccess;
+  if (nbatch + 64 >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit batch indices in the kernel
   int tile = fft_tile(P, n, es == 1, nbatch);
   const int pitch = n + (es == 1 ? 0 : 1);
   const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
@@ -115,7 +162,7 @@ hipError_t fft_multi_impl(Plan& P, void* base, const FftSeg* dsegs, int nseg, lo
 
 }  // namespace
 
-// Transforms per block: about 2048 elements, at most 64 transforms and never
+// Transforms per block: about 32 KiB of data, at most 64 transforms and never
 // more than fit 64 KiB of LDS (the passes hold at most 64 KiB / (R * 256)
 // butterflies per thread in registers), unless the autotuner has recorded a
 // faster choice for this length and axis.
@@ -127,12 +174,12 @@ int fft_tile(const Plan& P, int n, bool rows, long nbatch) {
   auto it = P.fft_tiles.find(key);
   if (it != P.fft_tiles.end()) tile = it->second;
   if (tile <= 0 || tile > cap) {
-    // about 2048 elements per block (16 KiB complex64): several blocks per CU,
-    // so one block's LDS passes overlap the others' global loads and stores
-    // (the autotuner's choices on gfx950 cluster there)
+    // about 32 KiB per block (4096 complex64 or 2048 complex128 elements): several blocks per
+    // CU, so one block's LDS passes overlap the others' global loads and stores (measured on
+    // gfx950: length-512 rows of complex64 move 3.5 TB/s at 8 per block, 2.8 TB/s at 4)
     // column groups of at least 64 bytes so the loads stay coalesced
     const int min_tile = rows ? 1 : std::max(1, (int)(64 / P.esize));
-    tile = std::max(1, std::min(cap, std::max(2048 / n, min_tile)));
+    tile = std::max(1, std::min(cap, std::max((int)(32768 / P.esize) / n, min_tile)));
     if (tile > 64) tile = 64;
     // columns: whole aligned groups of adjacent columns
     if (!rows) tile = 1 << (31 - __builtin_clz((unsigned)tile));
