@@ -463,16 +463,30 @@ __device__ __forceinline__ double2 lds_sump(const cplx<T>* base, const T a1[FP],
   return mk((double)accx, (double)accy);
 }
 
+// Footprint staging: each thread issues its loads 64 bytes at a time before writing LDS (lanes
+// past the footprint load its first node again), so a block keeps several loads per thread in
+// flight instead of waiting on each.
+template <typename T> constexpr int stage_unroll() { return 64 / (int)sizeof(cplx<T>); }
+
 // Stage field f's near footprint of a tile, (F1 x F2 x F3 nodes from (o1, o2, o3), periodic).
 template <typename T, int F1, int F2, int F3>
 __device__ __forceinline__ void stage_near(const GArgs& A, const cplx<T>* __restrict__ grid, int o1, int o2, int o3,
                                            int nfield, cplx<T>* lds) {
-  constexpr int FSZ = F1 * F2 * F3;
-  for (int idx = threadIdx.x; idx < nfield * FSZ; idx += blockDim.x) {
-    const int f = idx / FSZ, r = idx - f * FSZ;
-    const int z = r / (F1 * F2), y = (r / F1) % F2, xx = r % F1;
-    const int g1 = (o1 + xx) & (A.M1 - 1), g2 = (o2 + y) & (A.M2 - 1), g3 = (o3 + z) & (A.M3 - 1);
-    lds[idx] = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+  constexpr int FSZ = F1 * F2 * F3, U = stage_unroll<T>();
+  const int n = nfield * FSZ, nt = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * nt) {
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * nt < n ? i0 + u * nt : 0;
+      const int f = idx / FSZ, r = idx - f * FSZ;
+      const int z = r / (F1 * F2), y = (r / F1) % F2, xx = r % F1;
+      const int g1 = (o1 + xx) & (A.M1 - 1), g2 = (o2 + y) & (A.M2 - 1), g3 = (o3 + z) & (A.M3 - 1);
+      v[u] = grid[f * A.fs + ((long)g3 * A.M2 + g2) * A.M1 + g1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * nt < n) lds[i0 + u * nt] = v[u];
   }
 }
 
@@ -481,12 +495,21 @@ __device__ __forceinline__ void stage_near(const GArgs& A, const cplx<T>* __rest
 template <typename T, int F1, int F2, int F3>
 __device__ __forceinline__ void stage_far(const GArgs& A, const cplx<T>* __restrict__ far, int o1, int o2, int o3,
                                           cplx<T>* lds) {
-  constexpr int FSZ = F1 * F2 * F3;
-  for (int idx = threadIdx.x; idx < FSZ; idx += blockDim.x) {
-    const int z = idx / (F1 * F2), y = (idx / F1) % F2, xx = idx % F1;
-    const int g1 = (o1 + xx) & (A.Mf1 - 1), g2 = (o2 + y) & (A.Mf2 - 1);
-    const int g3 = min(max(o3 + z, 0), A.S - 1);
-    lds[idx] = far[((long)g3 * A.Mf2 + g2) * A.Mf1 + g1];
+  constexpr int FSZ = F1 * F2 * F3, U = stage_unroll<T>();
+  const int nt = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < FSZ; i0 += U * nt) {
+    cplx<T> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * nt < FSZ ? i0 + u * nt : 0;
+      const int z = idx / (F1 * F2), y = (idx / F1) % F2, xx = idx % F1;
+      const int g1 = (o1 + xx) & (A.Mf1 - 1), g2 = (o2 + y) & (A.Mf2 - 1);
+      const int g3 = min(max(o3 + z, 0), A.S - 1);
+      v[u] = far[((long)g3 * A.Mf2 + g2) * A.Mf1 + g1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * nt < FSZ) lds[i0 + u * nt] = v[u];
   }
 }
 
