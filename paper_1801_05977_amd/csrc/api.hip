@@ -400,9 +400,12 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
     }
     {
       // the far slab on its own periodic grid Mf1 x Mf2: rows (x1; in 3D the far fill above has
-      // already run the x2 columns)
+      // already run the x2 columns), or the x2 columns where the Maxwell far fill ran the rows
       KernelTimer t(P, QPGF_T_FAR_FFT);
-      HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * P.nfo, 1, 0, P.Mf1));
+      if (far_rows_in_fill(P))
+        HIP_TRY(launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * P.nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2));
+      else
+        HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * P.nfo, 1, 0, P.Mf1));
     }
     if (P.dim == 2 && P.gridI) {
       // the gather reads a stencil row (of all fields) as one contiguous, aligned run

@@ -686,6 +686,56 @@ __global__ void k_far3d_mx(double k, double a1, double a2, int M1, int M2, int S
   }
 }
 
+// The same six entries generated straight into LDS for `tile` rows (s, j2) of x1 coefficients,
+// the inverse DFT along x1 run there on all 6 tile rows, and the rows written out (the x2
+// transform follows as a column pass): one write of the slab instead of a write, then a read and
+// a write by the x1 row pass.  LDS: [entry][row][j1'], then the twiddles when they fit.
+template <typename T>
+__global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, double a2, int M1, int M2, int S,
+                                                       double z0, double hf, int tile, long fstride,
+                                                       const cplx<T>* __restrict__ tw, int ntw,
+                                                       cplx<T>* __restrict__ out) {
+  extern __shared__ char smem_raw[];
+  using V = cplx<T>;
+  const int n = M1;
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  const long nrows = (long)M2 * S, r0 = (long)blockIdx.x * tile;
+  const int ntile = (int)min((long)tile, nrows - r0);
+  const double ik2 = 1.0 / (k * k);
+  const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+  for (int idx = threadIdx.x; idx < tile * n; idx += blockDim.x) {
+    const int t = idx / n, j1p = idx - t * n;
+    if (t < ntile) {
+      const long r = r0 + t;
+      const int s = (int)(r / M2), j2p = (int)(r - (long)s * M2);
+      const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
+      const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
+      const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z0 + s * hf)));
+      const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const double2 m = cscale(cmul(cc[P[f]], cc[Qp[f]]), -ik2);
+        store_c<T>(buf, (size_t)(f * tile + t) * n + j1p, cmul(v, mk((f < 3 ? 1.0 : 0.0) + m.x, m.y)));
+      }
+    }
+  }
+  __syncthreads();
+  // rows of the last block beyond the slab hold stale LDS: transformed, never written
+  if (fft_twiddles_in_lds(6 * tile, n, n, sizeof(V))) {
+    V* twl = buf + 6 * tile * n;
+    const int stride = ntw / n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j * stride];
+    __syncthreads();
+    fftdev::inverse_dft_lds<T>(buf, n, n, 6 * tile, twl, n);
+  } else {
+    fftdev::inverse_dft_lds<T>(buf, n, n, 6 * tile, tw, ntw);
+  }
+  for (int idx = threadIdx.x; idx < 6 * tile * n; idx += blockDim.x) {
+    const int fr = idx / n, i1 = idx - fr * n, f = fr / tile, t = fr - f * tile;
+    if (t < ntile) out[f * fstride + (r0 + t) * n + i1] = buf[idx];
+  }
+}
+
 // The G_d far slab [s][i2][i1]: its coefficients are generated straight into LDS for a tile of
 // adjacent x1 columns and the inverse DFT along x2 runs there (the first of its two transform
 // passes; the coefficients never go to memory).  Batch b: slice b / M1, column b % M1.
@@ -973,6 +1023,16 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
       hipLaunchKernelGGL(k_far2d_hess<T>, g, b, 0, P.stream, k, P.last_k2, a1, P.Mf1, P.S, z0, hf, (long)P.nfar, out);
     else
       hipLaunchKernelGGL(k_far2d<T>, g, b, 0, P.stream, k, a1, P.Mf1, P.S, z0, hf, out);
+  } else if (P.nfo == kMxO && far_rows_in_fill(P)) {
+    // coefficients and the x1 transform in one pass (the x2 pass follows in the caller)
+    const int n = P.Mf1, tile = std::max(1, std::min(fftdev::lds_cap<T>() / (6 * n), 4));
+    const size_t shm = ((size_t)6 * tile * n + (fft_twiddles_in_lds(6 * tile, n, n, sizeof(cplx<T>)) ? n : 0)) *
+                       sizeof(cplx<T>);
+    const cplx<T>* tw = nullptr;
+    if constexpr (sizeof(T) == 8) tw = P.tw; else tw = P.twf;
+    const long nrows = (long)P.Mf2 * P.S;
+    hipLaunchKernelGGL(k_far3d_mx_rows<T>, dim3((unsigned)((nrows + tile - 1) / tile)), dim3(256), shm, P.stream, k,
+                       a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, tile, (long)P.nfar, tw, P.ntw, out);
   } else if (P.nfo == kMxO) {
     hipLaunchKernelGGL(k_far3d_mx<T>, g, b, 0, P.stream, k, a1, a2, P.Mf1, P.Mf2, P.S, z0, hf, (long)P.nfar, out);
     hipError_t e = hipGetLastError();
@@ -1118,6 +1178,12 @@ hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse) {
   const bool spec = P.spec;
   return P.p.prec == QPGF_C128 ? fill_impl<double>(P, k, a1, a2, fuse, spec)
                                : fill_impl<float>(P, k, a1, a2, fuse, spec);
+}
+
+// The Maxwell far slab's six entries of an x1 row (6 Mf1 values) fit one block's LDS: the far
+// fill then runs the x1 transform, and the caller's second pass is the x2 columns.
+bool far_rows_in_fill(const Plan& P) {
+  return P.dim == 3 && P.nfo == kMxO && 6L * P.Mf1 * (long)P.esize <= 65536 - (long)P.Mf1 * (long)P.esize;
 }
 
 hipError_t launch_far(Plan& P, double k, double a1, double a2) {
