@@ -89,11 +89,13 @@ __host__ __device__ constexpr double lag_inv_den(int m) {
     if (n != m) d *= (double)(m - n);
   return 1.0 / d;
 }
-template <typename W, int P>
+// (node m at offset m - LOW from the base node; LOW = P/2 - 1 centres an even rule on the
+// target's cell)
+template <typename W, int P, int LOW = P / 2 - 1>
 __device__ __forceinline__ void lagp(W f, W w[P]) {
   W g[P], pre[P], suf[P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) g[m] = f + W(P / 2 - 1 - m);
+  for (int m = 0; m < P; ++m) g[m] = f + W(LOW - m);
   pre[0] = W(1);
 #pragma unroll
   for (int m = 1; m < P; ++m) pre[m] = pre[m - 1] * g[m - 1];
@@ -255,23 +257,24 @@ __device__ __forceinline__ void near3_finish(const GArgs& A, double x1, double x
 // The far slab holds the series on its own periodic grid (Mf1 x Mf2, spacings 2 pi / Mf)
 // at slices z_s = fz0 + s hf: G_d, or the six tensor entries GG_pq (13 and 23 for x3 > 0).
 // FP = far_points<T>() interpolation points per axis.
-template <typename T, int FP = far_points<T>()>
+template <typename T, int FP = far_points<T>(), int FPT = FP>
 struct Far3 {
   int p1, p2, s0;
-  T w1[FP], w2[FP], w3[FP];
+  T w1[FP], w2[FPT], w3[FPT];
 };
 
-// false: |x3| beyond the slab
-template <typename T, int FP = far_points<T>()>
-__device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T, FP>& s) {
+// false: |x3| beyond the slab.  FPT points along x2 and x3 (FPT = FP - 1: the first FPT nodes of
+// the FP-point rows, nodes -(FP/2 - 1) .. FPT - FP/2)
+template <typename T, int FP = far_points<T>(), int FPT = FP>
+__device__ __forceinline__ bool far3_stencil(const GArgs& A, double x1, double x2, double x3, Far3<T, FP, FPT>& s) {
   double s0, f3;
   if (!far_slice(A, fabs(x3), s0, f3)) return false;
   double n;
   const double u1 = reduce_cell(x1, n) * A.ihf1, q1 = floor(u1);
   const double u2 = reduce_cell(x2, n) * A.ihf2, q2 = floor(u2);
   lagp<T, FP>((T)(u1 - q1), s.w1);
-  lagp<T, FP>((T)(u2 - q2), s.w2);
-  lagp<T, FP>((T)f3, s.w3);
+  lagp<T, FPT, FP / 2 - 1>((T)(u2 - q2), s.w2);
+  lagp<T, FPT, FP / 2 - 1>((T)f3, s.w3);
   s.p1 = (int)q1;
   s.p2 = (int)q2;
   s.s0 = (int)s0;
@@ -723,7 +726,9 @@ __device__ __forceinline__ double sum8(double v) {
 // partial sums are joined by DPP moves.  Every lane of a group computes the target's stencil
 // (the same record, so the group branches together).  Keys, footprints, overflow and results
 // as k_gather3d_far; the Maxwell fields are staged one at a time for each pass of BS targets.
-template <int NF, int FB1, int FB2, int FB3, int BS>
+// PT = 7: a 7-point rule along x2 and x3 (the rows' first 7 nodes), 49 rows per target instead of
+// 64, where the slab's spacing is fine enough for it (far7_ok).
+template <int NF, int FB1, int FB2, int FB3, int BS, int PT>
 __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const double2* __restrict__ far,
                                                        const TRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ hist,
@@ -771,8 +776,8 @@ __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const
       for (long t = t0 + g; t < t1; t += G) {
         const long j = start + t;
         const TRec r = rec[j];
-        Far3<double, FP> st;
-        bool miss = !far3_stencil<double, FP>(A, r.x, r.y, r.z, st);
+        Far3<double, FP, PT> st;
+        bool miss = !far3_stencil<double, FP, PT>(A, r.x, r.y, r.z, st);
         const int l1 = (st.p1 - LO - o1) & (A.Mf1 - 1);
         const int l2 = (st.p2 - LO - o2) & (A.Mf2 - 1);
         const int l3 = st.s0 - LO - o3;
@@ -787,18 +792,18 @@ __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const
         for (int m = 1; m < FP; ++m) w1a = a == m ? st.w1[m] : w1a;
         const double2* node = lds + (l3 * F2 + l2) * F1 + l1 + a;
         double ax = 0.0, ay = 0.0;
-        double w3[FP];
+        double w3[PT];
 #pragma unroll
-        for (int m = 0; m < FP; ++m) w3[m] = st.w3[m];
+        for (int m = 0; m < PT; ++m) w3[m] = st.w3[m];
 #pragma unroll 1
-        for (int c = 0; c < FP; ++c) {
+        for (int c = 0; c < PT; ++c) {
           const double wc = w3[0];
 #pragma unroll
-          for (int m = 0; m < FP - 1; ++m) w3[m] = w3[m + 1];
+          for (int m = 0; m < PT - 1; ++m) w3[m] = w3[m + 1];
           const double2* slice = node + c * (F2 * F1);
           double px = 0.0, py = 0.0;
 #pragma unroll
-          for (int b = 0; b < FP; ++b) {
+          for (int b = 0; b < PT; ++b) {
             const double2 v = slice[b * F1];
             px = fma(st.w2[b], v.x, px);
             py = fma(st.w2[b], v.y, py);
@@ -1705,6 +1710,17 @@ __global__ __launch_bounds__(256) void k_quads(const float2* __restrict__ in, fl
   q[v] = in[row * M1 + wrap_m(i1 + a, M1)];
 }
 
+// The complex128 G_d far gather may take 7 points along x2 and x3 (the 8-point rule's error
+// constant 1.1e-3 against 2.4e-3 for 7 points, at one power of the spacing less): propagating
+// terms (q <= k) then leave 2.4e-3 (k h)^7 <= 2e-11 for k h <= 0.07 along x2 (h = 2 pi / Mf2) and
+// along x3 (h = hf), and the evanescent terms that reach c leave about 1e-11 at the geometry's
+// floors (512 modes, hf <= 1/64).  Only on the automatic geometry (no far_m / far_h override).
+bool far7_ok(const Plan& P) {
+  if (P.p.far_m != 0 || P.p.far_h != 0.0 || P.dim != 3) return false;
+  const double k = std::max(P.last_k, P.last_k2);
+  return k * P.hf <= 0.07 && k * (2.0 * kPi / P.Mf2) <= 0.07;
+}
+
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
 
 template <typename T>
@@ -1948,15 +1964,20 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
 #define QPGF_FAR(A1_, A2_, A3_)                                                                                    \
   hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
                      P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
-#define QPGF_FAR8(A1_, A2_, A3_, BS_)                                                                            \
-  hipLaunchKernelGGL((k_gather3d_far8<NF, A1_, A2_, A3_, BS_>), tf, dim3(BS_), 0, P.stream, A, Tl, f, rec, P.ts.bin_hist, \
-                     P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
+#define QPGF_FAR8(A1_, A2_, A3_, BS_, PT_)                                                                        \
+  hipLaunchKernelGGL((k_gather3d_far8<NF, A1_, A2_, A3_, BS_, PT_>), tf, dim3(BS_), 0, P.stream, A, Tl, f, rec,      \
+                     P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
     // far tiles first (more targets and work each), then the near tiles
     {
       KernelTimer t(P, QPGF_T_GATHER_FAR);
       if constexpr (sizeof(T) == 8) {
-        if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads);
-        else QPGF_FAR8(4, 3, 3, kFar8Threads);
+        if (NF == 1 && far7_ok(P)) {
+          if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads, 7);
+          else QPGF_FAR8(4, 3, 3, kFar8Threads, 7);
+        } else {
+          if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads, 8);
+          else QPGF_FAR8(4, 3, 3, kFar8Threads, 8);
+        }
       } else {
         if (!C.far_big) QPGF_FAR(3, 3, 3);
         else QPGF_FAR(4, 4, 3);

@@ -384,6 +384,33 @@ def test_edge_targets_and_status_codes():
     assert e.value.status == 1
 
 
+@pytest.mark.parametrize("k", [3.7, 7.3])
+def test_gd3d_far_branch_next_to_c(k):
+    """The far branch where it is hardest for the slab rule: |x3| just beyond c, where the
+    evanescent terms of the series are largest, in the binned launch (7e4 targets).  At k = 3.7
+    the complex128 far gather takes 7 points along x2 and x3, at k = 7.3 the slab's spacing is
+    too coarse for that and it keeps 8.  The oracle sums the series (1.3) itself."""
+    M1, M2, M3, T = 64, 64, 32, 70_000
+    a1, a2 = 0.2, 0.35
+    rng = np.random.default_rng(31)
+    x = np.empty((T, 3))
+    x[:, 0] = rng.uniform(0.0, 2 * math.pi, T)
+    x[:, 1] = rng.uniform(0.0, 2 * math.pi, T)
+    x[:, 2] = rng.choice([-1.0, 1.0], T) * rng.uniform(0.6 + 1e-9, 0.63, T)
+    pick = rng.choice(T, 300, replace=False)
+    o = truth.gd3d(k, a1, a2, x[pick])
+    for prec in (qpgf.C128, qpgf.C64):
+        P = qpgf.Plan(qpgf.KIND_GD3D, prec, M1, M2, M3)
+        flags = torch.empty(T, dtype=torch.uint8, device="cuda")
+        g = P(k, a1, a2, dev(x), flags=flags).cpu().numpy()
+        assert np.all(flags.cpu().numpy() == 2)
+        err = parity(g[pick], o)
+        print("far next to c", k, "c128" if prec == qpgf.C128 else "c64", err)
+        # the slab's design error: about 1e-11 (complex128) and 1e-6 (complex64) of the series
+        assert err <= (5e-11 if prec == qpgf.C128 else 5e-6)
+        P.close()
+
+
 # ----------------------------------------------------------------------------- full size, sampled
 
 @pytest.mark.timeout(900)
