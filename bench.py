@@ -240,10 +240,11 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
     if dom == "gather_far":
-        # the far gather reads every stencil node from LDS: FP^3 nodes per far target, against the
-        # LDS read rate of 128 bytes per clock per CU (256 CUs, 2.4 GHz)
-        fp = info.far_points
-        lds_bytes = counts[2] * fp ** 3 * (8 if prec == qpgf.C64 else 16)
+        # the far gather reads every stencil node from LDS (far_points along x1, far_points_t along
+        # x2 and x3 per far target), against the LDS read rate of 128 bytes per clock per CU
+        # (256 CUs, 2.4 GHz)
+        nodes = info.far_points * info.far_points_t ** 2
+        lds_bytes = counts[2] * nodes * (8 if prec == qpgf.C64 else 16)
         lds_peak = 128 * 256 * 2.4e9 / 1e12
         lds_ach = lds_bytes / (d["avg_ms"] * 1e-3) / 1e12
         roofline["lds"] = {"bytes_per_launch": lds_bytes, "achieved": round(lds_ach, 2), "peak": round(lds_peak, 1),

@@ -170,6 +170,10 @@ typedef struct {
                               GG_pq of the series (11 22 33 12 13 23; 13 and 23 for x3 > 0) */
   int far_points;          /* interpolation points per axis on the far slab: 8, or 4 for complex64
                               in 3D; slice s lies at |x_t| = c - (far_points/2 - 1) h_f + s h_f */
+  int far_points_t;        /* points along x2 and x3 of the binned far gather for the last prepared
+                              instance: 7 for the complex128 G_d where the slab's spacing h gives
+                              k h <= 0.07 on both axes (the first 7 nodes of each 8-point row),
+                              else far_points */
 } qpgf_plan_info;
 
 /* Fill *p with the defaults above for the given kind, precision and sizes. */

@@ -767,6 +767,7 @@ qpgf_status qpgf_plan_get_info(const qpgf_plan* plan, qpgf_plan_info* info) {
   info->far_m2 = P.Mf2;
   info->far_fields = P.nfo;
   info->far_points = P.fp;
+  info->far_points_t = (P.dim == 3 && P.p.prec == QPGF_C128 && P.nf == 1 && far7_ok(P)) ? 7 : P.fp;
   return QPGF_OK;
 }
 

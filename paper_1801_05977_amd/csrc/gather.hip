@@ -1710,17 +1710,6 @@ __global__ __launch_bounds__(256) void k_quads(const float2* __restrict__ in, fl
   q[v] = in[row * M1 + wrap_m(i1 + a, M1)];
 }
 
-// The complex128 G_d far gather may take 7 points along x2 and x3 (the 8-point rule's error
-// constant 1.1e-3 against 2.4e-3 for 7 points, at one power of the spacing less): propagating
-// terms (q <= k) then leave 2.4e-3 (k h)^7 <= 2e-11 for k h <= 0.07 along x2 (h = 2 pi / Mf2) and
-// along x3 (h = hf), and the evanescent terms that reach c leave about 1e-11 at the geometry's
-// floors (512 modes, hf <= 1/64).  Only on the automatic geometry (no far_m / far_h override).
-bool far7_ok(const Plan& P) {
-  if (P.p.far_m != 0 || P.p.far_h != 0.0 || P.dim != 3) return false;
-  const double k = std::max(P.last_k, P.last_k2);
-  return k * P.hf <= 0.07 && k * (2.0 * kPi / P.Mf2) <= 0.07;
-}
-
 enum GatherMode { kGatherAll = 0, kBinOnly = 1, kGatherBinned = 2 };
 
 template <typename T>
@@ -2019,6 +2008,17 @@ hipError_t gather_impl(Plan& P, const double* x, int64_t T_, void* out, uint8_t*
 }
 
 }  // namespace
+
+// The complex128 G_d far gather may take 7 points along x2 and x3 (the 8-point rule's error
+// constant 1.1e-3 against 2.4e-3 for 7 points, at one power of the spacing less): propagating
+// terms (q <= k) then leave 2.4e-3 (k h)^7 <= 2e-11 for k h <= 0.07 along x2 (h = 2 pi / Mf2) and
+// along x3 (h = hf), and the evanescent terms that reach c leave about 1e-11 at the geometry's
+// floors (512 modes, hf <= 1/64).  Only on the automatic geometry (no far_m / far_h override).
+bool far7_ok(const Plan& P) {
+  if (P.p.far_m != 0 || P.p.far_h != 0.0 || P.dim != 3) return false;
+  const double k = std::max(P.last_k, P.last_k2);
+  return k * P.hf <= 0.07 && k * (2.0 * kPi / P.Mf2) <= 0.07;
+}
 
 // The near grid's and the far slab's copies in the gather's layout (rows of M1 and Mf1 nodes).
 hipError_t launch_interleave2d(Plan& P) {

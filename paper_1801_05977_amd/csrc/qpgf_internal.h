@@ -267,6 +267,7 @@ hipError_t launch_htable(Plan& P, double k);
 hipError_t launch_fill(Plan& P, double k, double a1, double a2, bool fuse_transverse);
 bool fill_fuses_transverse(const Plan& P);
 bool far_rows_in_fill(const Plan& P);
+bool far7_ok(const Plan& P);
 hipError_t launch_far(Plan& P, double k, double a1, double a2);
 hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
                       long s_out);

@@ -41,7 +41,7 @@ class PlanInfo(ctypes.Structure):
                 ("c", ctypes.c_double), ("c_tilde", ctypes.c_double), ("eps", ctypes.c_double),
                 ("n_fields", ctypes.c_int), ("grid_bytes", ctypes.c_size_t), ("far_grid_bytes", ctypes.c_size_t),
                 ("far_m1", ctypes.c_int), ("far_m2", ctypes.c_int), ("far_fields", ctypes.c_int),
-                ("far_points", ctypes.c_int)]
+                ("far_points", ctypes.c_int), ("far_points_t", ctypes.c_int)]
 
 
 class TrainCfg(ctypes.Structure):

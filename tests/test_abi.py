@@ -34,11 +34,11 @@ def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qpgf.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qpgf_params),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qpgf_params),"
         " offsetof(qpgf_params, lattice_rmin), sizeof(qpgf_plan_info), offsetof(qpgf_plan_info, far_grid_bytes),"
         " offsetof(qpgf_params, quad_q), offsetof(qpgf_params, sing_order), offsetof(qpgf_params, far_m),"
         " offsetof(qpgf_params, maxwell_trace), offsetof(qpgf_plan_info, far_m1),"
-        " offsetof(qpgf_plan_info, far_points));"
+        " offsetof(qpgf_plan_info, far_points), offsetof(qpgf_plan_info, far_points_t));"
         "printf(\"%zu %zu %zu\\n\", sizeof(qpgf_train_cfg), offsetof(qpgf_train_cfg, member),"
         " offsetof(qpgf_train_cfg, seed));return 0;}\n")
     exe = tmp_path / "sz"
@@ -47,7 +47,7 @@ def test_struct_layout_matches_header(tmp_path):
     want = [ctypes.sizeof(qpgf.Params), qpgf.Params.lattice_rmin.offset, ctypes.sizeof(qpgf.PlanInfo),
             qpgf.PlanInfo.far_grid_bytes.offset, qpgf.Params.quad_q.offset, qpgf.Params.sing_order.offset,
             qpgf.Params.far_m.offset, qpgf.Params.maxwell_trace.offset, qpgf.PlanInfo.far_m1.offset,
-            qpgf.PlanInfo.far_points.offset, ctypes.sizeof(qpgf.TrainCfg), qpgf.TrainCfg.member.offset,
+            qpgf.PlanInfo.far_points.offset, qpgf.PlanInfo.far_points_t.offset, ctypes.sizeof(qpgf.TrainCfg), qpgf.TrainCfg.member.offset,
             qpgf.TrainCfg.seed.offset]
     assert got == want
 

@@ -404,6 +404,7 @@ def test_gd3d_far_branch_next_to_c(k):
         flags = torch.empty(T, dtype=torch.uint8, device="cuda")
         g = P(k, a1, a2, dev(x), flags=flags).cpu().numpy()
         assert np.all(flags.cpu().numpy() == 2)
+        assert P.info.far_points_t == (4 if prec == qpgf.C64 else (7 if k < 5 else 8))
         err = parity(g[pick], o)
         print("far next to c", k, "c128" if prec == qpgf.C128 else "c64", err)
         # the slab's design error: about 1e-11 (complex128) and 1e-6 (complex64) of the series
