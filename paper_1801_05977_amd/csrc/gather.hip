@@ -795,7 +795,9 @@ __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const
         double w3[PT];
 #pragma unroll
         for (int m = 0; m < PT; ++m) w3[m] = st.w3[m];
-#pragma unroll 1
+        // all PT x PT rows unrolled: a wave has the reads of several slices in flight (measured
+        // 0.71 -> 0.58 ms against a rolled slice loop; no spills at 512 threads per block)
+#pragma unroll
         for (int c = 0; c < PT; ++c) {
           const double wc = w3[0];
 #pragma unroll
