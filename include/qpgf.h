@@ -172,8 +172,8 @@ typedef struct {
                               in 3D; slice s lies at |x_t| = c - (far_points/2 - 1) h_f + s h_f */
   int far_points_t;        /* points along x2 and x3 of the binned far gather for the last prepared
                               instance: 7 for the complex128 G_d where the slab's spacing h gives
-                              k h <= 0.07 on both axes (the first 7 nodes of each 8-point row),
-                              else far_points */
+                              k h <= 0.07 on both axes (the first 7 nodes of each 8-point row;
+                              far tiles within 0.8 of a lattice point keep 8), else far_points */
 } qpgf_plan_info;
 
 /* Fill *p with the defaults above for the given kind, precision and sizes. */

@@ -727,24 +727,37 @@ __device__ __forceinline__ double sum8(double v) {
 // (the same record, so the group branches together).  Keys, footprints, overflow and results
 // as k_gather3d_far; the Maxwell fields are staged one at a time for each pass of BS targets.
 // PT = 7: a 7-point rule along x2 and x3 (the rows' first 7 nodes), 49 rows per target instead of
-// 64, where the slab's spacing is fine enough for it (far7_ok).
+// 64, where the slab's spacing is fine enough for it (far7_ok).  Its error grows towards the
+// lattice points, where the series' high modes matter most: sel = 1 takes only the tiles whose
+// targets all lie at least kFar7Rmin from every lattice point (and the key of the targets outside
+// the slab), sel = 2 only the others, on a grid of 2 c1 x 2 c2 x c3 blocks covering the c1 (c2)
+// tiles next to x1 (x2) = 0 on either side and the first c3 slice tiles; sel = 0 every tile.
+constexpr double kFar7Rmin = 0.8;
 template <int NF, int FB1, int FB2, int FB3, int BS, int PT>
 __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const double2* __restrict__ far,
                                                        const TRec* __restrict__ rec,
                                                        const uint32_t* __restrict__ hist,
                                                        const uint32_t* __restrict__ offs,
                                                        double2* __restrict__ out, uint8_t* __restrict__ flags,
-                                                       uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf) {
+                                                       uint32_t* __restrict__ ovf, uint32_t* __restrict__ novf,
+                                                       int sel, int c1, int c2) {
   constexpr int FP = 8, LO = FP / 2 - 1;
   constexpr int F1 = (1 << FB1) + FP - 1, F2 = (1 << FB2) + FP - 1, F3 = (1 << FB3) + FP - 1;
   constexpr int NO = NOut<NF>::v;
   constexpr int G = BS / 8;                  // targets in flight per block
   __shared__ double2 lds[F1 * F2 * F3];
-  const int key = B.nnear + (int)blockIdx.x;
+  int key = B.nnear + (int)blockIdx.x;
+  if (sel == 2) {
+    const int i1 = (int)blockIdx.x % (2 * c1), i2 = ((int)blockIdx.x / (2 * c1)) % (2 * c2);
+    const int i3 = (int)blockIdx.x / (4 * c1 * c2);
+    const int t1 = i1 < c1 ? i1 : B.fnt1 - 2 * c1 + i1, t2 = i2 < c2 ? i2 : B.fnt2 - 2 * c2 + i2;
+    key = B.nnear + (i3 * B.fnt2 + t2) * B.fnt1 + t1;
+  }
   const uint32_t cnt = hist[key];
   if (cnt == 0) return;
   const long start = offs[key];
   if (key == B.nkeys - 1) {
+    if (sel == 2) return;
     for (long j = start + threadIdx.x; j < start + (long)cnt; j += blockDim.x) {
       const TRec r = rec[j];
       const bool fin = isfinite(r.x) && isfinite(r.y) && isfinite(r.z);
@@ -756,6 +769,16 @@ __global__ __launch_bounds__(BS) void k_gather3d_far8(GArgs A, TileArgs B, const
   }
   const int kk = key - B.nnear;
   const int b1 = kk % B.fnt1, b2 = (kk / B.fnt1) % B.fnt2, b3 = kk / (B.fnt1 * B.fnt2);
+  if (sel != 0) {
+    // the tile's targets: base nodes [lo, lo + 2^FB) per periodic axis (node i at x = i 2 pi / Mf,
+    // periodic), base slices from b3 2^FB3 (|x3| >= c); their distance to the nearest lattice point
+    const int lo1 = b1 << FB1, lo2 = b2 << FB2;
+    const double d1 = min(lo1, A.Mf1 - lo1 - (1 << FB1)) * (2.0 * kPi / A.Mf1);
+    const double d2 = min(lo2, A.Mf2 - lo2 - (1 << FB2)) * (2.0 * kPi / A.Mf2);
+    const double z = fmax(A.c, A.fz0 + (double)(b3 << FB3) * A.hf);
+    const bool close = d1 * d1 + d2 * d2 + z * z < kFar7Rmin * kFar7Rmin;
+    if (close != (sel == 2)) return;
+  }
   const int o1 = (b1 << FB1) - LO, o2 = (b2 << FB2) - LO, o3 = (b3 << FB3) - LO;
   const int g = (int)threadIdx.x >> 3, a = (int)threadIdx.x & 7;
   if (NO == 1) {
@@ -1955,19 +1978,33 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
 #define QPGF_FAR(A1_, A2_, A3_)                                                                                    \
   hipLaunchKernelGGL((k_gather3d_far<T, NF, A1_, A2_, A3_, 256>), tf, dim3(256), 0, P.stream, A, Tl, g, f, rec,    \
                      P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
-#define QPGF_FAR8(A1_, A2_, A3_, BS_, PT_)                                                                        \
-  hipLaunchKernelGGL((k_gather3d_far8<NF, A1_, A2_, A3_, BS_, PT_>), tf, dim3(BS_), 0, P.stream, A, Tl, f, rec,      \
-                     P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf)
+#define QPGF_FAR8G(A1_, A2_, A3_, BS_, PT_, SEL_, G_, C1_, C2_)                                                  \
+  hipLaunchKernelGGL((k_gather3d_far8<NF, A1_, A2_, A3_, BS_, PT_>), G_, dim3(BS_), 0, P.stream, A, Tl, f, rec,      \
+                     P.ts.bin_hist, P.ts.bin_offs, o, flags, P.ts.bin_ovf, P.ts.bin_novf, SEL_, C1_, C2_)
+#define QPGF_FAR8(A1_, A2_, A3_, BS_, PT_, SEL_) QPGF_FAR8G(A1_, A2_, A3_, BS_, PT_, SEL_, tf, 0, 0)
     // far tiles first (more targets and work each), then the near tiles
     {
       KernelTimer t(P, QPGF_T_GATHER_FAR);
       if constexpr (sizeof(T) == 8) {
         if (NF == 1 && far7_ok(P)) {
-          if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads, 7);
-          else QPGF_FAR8(4, 3, 3, kFar8Threads, 7);
+          // 7 points along x2 and x3 away from the lattice points; 8 in the few tiles next to them,
+          // on a grid of those tiles only (c1, c2 tiles on either side of x = 0, c3 slice tiles)
+          const int fb1 = C.far_big ? 4 : 3;
+          const double h1 = 2.0 * kPi / P.Mf1, h2 = 2.0 * kPi / P.Mf2;
+          const int c1 = std::min((int)std::ceil(kFar7Rmin / (h1 * (1 << fb1))), Tl.fnt1 / 2);
+          const int c2 = std::min((int)std::ceil(kFar7Rmin / (h2 * 8)), Tl.fnt2 / 2);
+          const int c3 = std::min((int)std::ceil((kFar7Rmin - P.fz0) / (P.hf * 8)) + 1, Tl.fnt3);
+          const dim3 t8((unsigned)std::max(1, 4 * c1 * c2 * c3));
+          if (!C.far_big) {
+            QPGF_FAR8(3, 3, 3, kFar8Threads, 7, 1);
+            if (c1 > 0 && c2 > 0 && c3 > 0) QPGF_FAR8G(3, 3, 3, kFar8Threads, 8, 2, t8, c1, c2);
+          } else {
+            QPGF_FAR8(4, 3, 3, kFar8Threads, 7, 1);
+            if (c1 > 0 && c2 > 0 && c3 > 0) QPGF_FAR8G(4, 3, 3, kFar8Threads, 8, 2, t8, c1, c2);
+          }
         } else {
-          if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads, 8);
-          else QPGF_FAR8(4, 3, 3, kFar8Threads, 8);
+          if (!C.far_big) QPGF_FAR8(3, 3, 3, kFar8Threads, 8, 0);
+          else QPGF_FAR8(4, 3, 3, kFar8Threads, 8, 0);
         }
       } else {
         if (!C.far_big) QPGF_FAR(3, 3, 3);
@@ -1990,6 +2027,7 @@ hipError_t gather3d_impl(Plan& P, const GArgs& A, const double* x, int64_t T_, v
 #undef QPGF_NEAR
 #undef QPGF_FAR
 #undef QPGF_FAR8
+#undef QPGF_FAR8G
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
