@@ -49,12 +49,15 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, long
   const int total = tile * n;
   // element idx of the block's tile: transform t, element e (rows: e fastest; columns: t fastest);
   // 32-bit quotients (the host keeps batches below 2^31)
-  // (the global offset, and the LDS offset or -1 beyond the block's transforms)
+  // (the global offset, and the LDS offset or -1 beyond the block's transforms, where the global
+  // offset is the block's own first element: a lane past the end reloads it, and no other block
+  // writes it)
   const unsigned un = (unsigned)n, ut = (unsigned)tile, ubin = (unsigned)b_in;
   struct Loc {
     long g;
     int l;
   };
+  const long g0 = (b0 / b_in) * s_out + (b0 % b_in) * s_in;
   auto locate = [&](int idx) -> Loc {
     unsigned t, e;
     if (rows) {
@@ -64,12 +67,11 @@ __device__ __forceinline__ void fft_body(cplx<T>* __restrict__ data, int n, long
       e = (unsigned)idx / ut;
       t = (unsigned)idx - e * ut;
     }
-    if (idx >= total || (int)t >= ntile) return Loc{0, -1};
+    if (idx >= total || (int)t >= ntile) return Loc{g0, -1};
     const unsigned b = (unsigned)b0 + t, q = b / ubin;
     return Loc{(long)q * s_out + (long)(b - q * ubin) * s_in + (long)e * es, (int)(t * (unsigned)pitch + e)};
   };
-  // (every lane loads, those beyond the block's transforms from element 0, so no load sits in a
-  // branch whose join would wait for it)
+  // (every lane loads, so no load sits in a branch whose join would wait for it)
   for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
     V v[kLdU];
     int o[kLdU];
