@@ -87,7 +87,9 @@ typedef enum {
 /* Method parameters.  Grid sizes follow Sections 2.1 / 3.1 with an independent
  * size per axis: m1 = 2 N1 modes in x1; 2D: m2 = 2 N2 transverse (x2) modes;
  * 3D: m2 = 2 N2 modes in x2 and m3 = 2 N3 transverse (x3) modes.  Each must be
- * a power of two in [16, 4096] (m3 unused in 2D); with complex128 the axes
+ * a power of two in [16, 4096] (m3 unused in 2D), except m1 of the 2D kinds:
+ * 2^a r with a >= 1 and r in {1, 3, 5, 7} (the transforms' radix-3, -5 and -7
+ * passes follow the power-of-two ones), in [16, 4096]; with complex128 the axes
  * transformed as columns (2D: m2; 3D: m2, m3) at most 2048.  Grid spacing: pi/N1, pi/N2
  * (3D) and c_tilde/N_t in the transverse direction.
  * Defaults (qpgf_params_default): c = 0.6, c_tilde = 1 (the values of Section 6),
@@ -110,7 +112,8 @@ typedef struct {
   double c_tilde;          /* periodisation half-length in the transverse axis, c_tilde > c */
   double eps;              /* singular cut-off Y_eps: 1 on [0, eps], 0 beyond 2 eps; 2 eps <= c_tilde */
   int quad_q;              /* Gauss-Legendre nodes for the X'- and radial integrals, 16..256 */
-  double far_h;            /* far-slab slice spacing h_f; 0: automatic, the largest 2^-j <= min(1/64, x/k) */
+  double far_h;            /* far-slab slice spacing h_f; 0: automatic, the largest 2^-j <= min(1/64, x/k),
+                              x = 0.107 for complex128 and 0.11 for complex64 */
   double far_zmax;         /* largest |x_t| the far slab must cover */
   double wood_tol;
   double special_tol;
@@ -137,9 +140,10 @@ typedef struct {
                               other kind, and qpgf_g2d_batched, require 0. */
   int far_m;               /* modes per periodic axis of the far slab (a power of two in [16, 4096],
                               complex128 x2 axis <= 2048); 0: automatic per prepared instance, the
-                              largest of m1 (3D: m2), a floor, and the smallest power of two >= 2 pi k / x,
-                              x = 0.0977 for complex128 and 0.3 for complex64 (k: the instance's largest
-                              wavenumber).  The floor is 512 modes for complex128 and 256 for complex64.
+                              largest of m1 rounded up to a power of two (3D x2: m2), a floor, and the
+                              smallest power of two >= 2 pi k / x, x = 0.0977 for complex128 and 0.081
+                              for complex64 (k: the instance's largest wavenumber).  The floor is 512
+                              modes, 256 for complex64 in 2D.
                               The far slab holds the terms of the series with
                               |j| < far_m / 2; the 8-point rule interpolates a term of wavenumber q to
                               about (q h)^8 / 1000, h = 2 pi / far_m or h_f, which the automatic choice keeps
@@ -277,8 +281,8 @@ qpgf_status qpgf_g2d_hess_diff(qpgf_plan* plan, double k1, double k2, double alp
 qpgf_status qpgf_prepare_hess_diff(qpgf_plan* plan, double k1, double k2, double alpha, int stage);
 
 /* Batched form of Algorithm 2.1: n_inst independent instances in one call.
- * Instance i has wavenumber k[i], alpha[i] and x1 size m1[i] (a power of two,
- * 16 <= m1[i] <= params.m1; every instance uses the plan's transverse size m2
+ * Instance i has wavenumber k[i], alpha[i] and x1 size m1[i] (2^a r with a >= 1
+ * and r in {1, 3, 5, 7}, 16 <= m1[i] <= params.m1; every instance uses the plan's transverse size m2
  * and method parameters) and owns targets t_off[i] .. t_off[i+1]-1 of the
  * concatenated device array x [t_off[n_inst]][2]; its results go to the same
  * positions of out (and flags).  k, alpha, m1 and t_off are HOST arrays, read
@@ -322,7 +326,7 @@ qpgf_status qpgf_plan_workspace_bytes(const qpgf_plan* plan, double kmax, int64_
 qpgf_status qpgf_plan_set_workspace(qpgf_plan* plan, void* ptr, size_t bytes, double kmax, int64_t max_targets);
 
 /* FFT autotuner: for every transform shape the plan uses (and, for 2D plans,
- * every power-of-two x1 length from 16 to params.m1), time the candidate numbers
+ * every power-of-two x1 length from 16 to params.m1, and params.m1), time the candidate numbers
  * of transforms per block on scratch memory and keep the fastest.  Results are
  * cached in the text file cache_path (NULL: no file), one line per shape:
  * "<arch> <prec> <n> <rows|cols> <batch> <tile> <us>"; shapes found there are not
