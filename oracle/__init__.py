@@ -12,12 +12,12 @@ Two oracles live here:
 * ``truth``  -- the exact Green's functions G (eq. 1.2), G_d (eq. 1.3) and the
   Maxwell tensor (eq. 1.4), summed directly from the eigenfunction expansions
   with explicit tail bounds, plus the image expansions (1.1) for complex k.
-  This judges *accuracy*.
+  It measures *accuracy*.
 * ``method`` -- the same discrete approximation the library computes
   (Algorithms 2.1, 3.1 and 4.1 with the frozen parameter set), evaluated
   plainly: closed-form coefficients with converged quadrature, grid values by
   direct (non-FFT) DFT sums, tensor-product cubic Lagrange interpolation and
-  the exact singular add-back.  This judges *parity*.
+  the exact singular add-back.  It measures *parity*.
 
 * ``grad2d`` -- the same for the first derivatives of the 2D G (Section
   2.4.1): differentiated coefficients, the singular parts h1, h2 and their
