@@ -238,19 +238,24 @@ __device__ __forceinline__ void features_row(const double* __restrict__ Q, doubl
   const double t1 = x1 - 2.0 * kPi * floor((x1 + kPi) * (0.5 / kPi));
   const double t2 = x2 - 2.0 * kPi * floor((x2 + kPi) * (0.5 / kPi));
   int o = 0;
-  for (int h = 1; h <= 8; ++h) {
-    f[o++] = (float)cos(h * t1);
-    f[o++] = (float)sin(h * t1);
-  }
-  for (int h = 1; h <= 8; ++h) {
-    f[o++] = (float)cos(h * t2);
-    f[o++] = (float)sin(h * t2);
-  }
+  // harmonics h = 1 .. nh of an angle: one sine and cosine, then rotations by it (FP64, so the
+  // recurrence's rounding stays far below the features' bf16 precision)
+  auto harmonics = [&](double th, int nh) {
+    double s1, c1;
+    sincos(th, &s1, &c1);
+    double cs = c1, sn = s1;
+    for (int h = 1; h <= nh; ++h) {
+      f[o++] = (float)cs;
+      f[o++] = (float)sn;
+      const double cn = cs * c1 - sn * s1;
+      sn = sn * c1 + cs * s1;
+      cs = cn;
+    }
+  };
+  harmonics(t1, 8);
+  harmonics(t2, 8);
   const double z = kPi * x3 / c_tilde;
-  for (int h = 1; h <= 6; ++h) {
-    f[o++] = (float)cos(h * z);
-    f[o++] = (float)sin(h * z);
-  }
+  harmonics(z, 6);
   const double r = sqrt(t1 * t1 + t2 * t2 + x3 * x3);
   f[o++] = (float)(x3 / c);
   f[o++] = (float)((k - 5.5) / 4.5);
@@ -258,8 +263,10 @@ __device__ __forceinline__ void features_row(const double* __restrict__ Q, doubl
   f[o++] = (float)(2.0 * a2);
   const double args[8] = {k * t1, k * t2, k * x3, k * r, a1 * t1, a2 * t2, 2.0 * kPi * a1, 2.0 * kPi * a2};
   for (int h = 0; h < 8; ++h) {
-    f[o++] = (float)cos(args[h]);
-    f[o++] = (float)sin(args[h]);
+    double sn, cs;
+    sincos(args[h], &sn, &cs);
+    f[o++] = (float)cs;
+    f[o++] = (float)sn;
   }
 }
 
