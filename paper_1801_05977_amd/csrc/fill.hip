@@ -656,13 +656,25 @@ __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int
 // (i/8pi^2) beta^-1 e^{i beta z_s} of the Mf1 x Mf2 lowest modes, z_s = z0 + s hf.  NFO = kMxO:
 // the six entries of the Maxwell tensor (1.4) instead, the term times delta_pq - xi_p xi_q / k^2
 // with xi = (alpha1 + j1, alpha2 + j2, beta) (the entries 13 and 23 take sgn(x3) at the target).
+// i c beta^-1 e^{i beta z} (c and z real, beta from beta_of, so one of its parts is zero).  An
+// evanescent mode (beta = i q) gives the real (c/q) e^{-qz}, a propagating one (beta = p)
+// (c/p)(-sin pz, cos pz): one exponential or one sine-cosine pair, and one division.  The complex
+// quotient and product written out in full take the same roundings, their other terms being exact
+// zeros (up to the sign of a zero part); beta = 0, a Wood anomaly, is refused before any fill.
+__device__ __forceinline__ double2 ibeta_exp(double c, double2 b, double z) {
+  if (b.x == 0.0) return mk(c / b.y * exp(-(b.y * z)), 0.0);
+  double s, co;
+  sincos(b.x * z, &s, &co);
+  const double w = c / b.x;
+  return mk(-(w * s), w * co);
+}
+
 // One far-slab coefficient of the series (1.3) in 3D: (i/8 pi^2) beta^-1 e^{i beta z} at mode
 // (j1, j2) (FFT order) and height z.
 __device__ __forceinline__ double2 far3_coef(double k, double a1, double a2, int M1, int M2, double z, int j1p,
                                              int j2p) {
   const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
-  const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-  return cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z)));
+  return ibeta_exp(1.0 / (8.0 * kPi * kPi), beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2)), z);
 }
 
 // The Maxwell far slab's coefficients, one thread per (s, j2, j1) writing all six entries (beta and
@@ -675,7 +687,7 @@ __global__ void k_far3d_mx(double k, double a1, double a2, int M1, int M2, int S
   const int j1p = (int)(idx % M1), j2p = (int)((idx / M1) % M2), s = (int)(idx / ((long)M1 * M2));
   const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
   const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-  const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z0 + s * hf)));
+  const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z0 + s * hf);
   const double ik2 = 1.0 / (k * k);
   const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
   const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
@@ -710,7 +722,7 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
       const int s = (int)(r / M2), j2p = (int)(r - (long)s * M2);
       const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
       const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-      const double2 v = cmul(cdiv(mk(0.0, 1.0 / (8.0 * kPi * kPi)), b), cexpi(cscale(b, z0 + s * hf)));
+      const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z0 + s * hf);
       const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
@@ -872,7 +884,7 @@ __global__ void k_far2d(double k, double a, int M1, int S, double z0, double hf,
   const int j1p = (int)(idx % M1), s = (int)(idx / M1);
   const double2 b = beta_of(k, fabs(a + centered(j1p, M1)));
   const double z = z0 + s * hf;
-  store_c<T>(out, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
+  store_c<T>(out, idx, ibeta_exp(1.0 / (4.0 * kPi), b, z));
 }
 
 // Far slab of the 2D gradient: the coefficients of the series (1.2) differentiated,
@@ -925,7 +937,7 @@ __global__ void k_far2d_multi(const FillInst* __restrict__ inst, int n_inst, cpl
   const int j1p = (int)(idx % I.Mf1), s = (int)(idx / I.Mf1);
   const double2 b = beta_of(I.A.k, fabs(I.A.a1 + centered(j1p, I.Mf1)));
   const double z = I.z0 + s * I.hf;
-  store_c<T>(base + I.foff, idx, cmul(cdiv(mk(0.0, 1.0 / (4.0 * kPi)), b), cexpi(cscale(b, z))));
+  store_c<T>(base + I.foff, idx, ibeta_exp(1.0 / (4.0 * kPi), b, z));
 }
 
 template <typename T>
