@@ -656,17 +656,31 @@ __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int
 // (i/8pi^2) beta^-1 e^{i beta z_s} of the Mf1 x Mf2 lowest modes, z_s = z0 + s hf.  NFO = kMxO:
 // the six entries of the Maxwell tensor (1.4) instead, the term times delta_pq - xi_p xi_q / k^2
 // with xi = (alpha1 + j1, alpha2 + j2, beta) (the entries 13 and 23 take sgn(x3) at the target).
-// i c beta^-1 e^{i beta z} (c and z real, beta from beta_of, so one of its parts is zero).  An
+// i c beta^-1 e^{i beta z} (c real, z >= 0, beta from beta_of, so one of its parts is zero).  An
 // evanescent mode (beta = i q) gives the real (c/q) e^{-qz}, a propagating one (beta = p)
 // (c/p)(-sin pz, cos pz): one exponential or one sine-cosine pair, and one division.  The complex
 // quotient and product written out in full take the same roundings, their other terms being exact
 // zeros (up to the sign of a zero part); beta = 0, a Wood anomaly, is refused before any fill.
+// Terms with qz > kFarNegligibleQz are taken as zero.  The modes lie one per unit area of the
+// (xi1, xi2) plane, so the dropped terms sum to about 2 pi c e^{-50} / z (about 1e-21 c / z),
+// against the propagating terms' c/p >= c/k: far below the FP64 rounding of the slab's values.
+// The Maxwell entries carry at most 1 + |xi|^2/k^2 more, so theirs sum to about 3e-18 c/(k^2 z^3).
+constexpr double kFarNegligibleQz = 50.0;
 __device__ __forceinline__ double2 ibeta_exp(double c, double2 b, double z) {
-  if (b.x == 0.0) return mk(c / b.y * exp(-(b.y * z)), 0.0);
+  if (b.x == 0.0) {
+    const double qz = b.y * z;
+    return mk(qz > kFarNegligibleQz ? 0.0 : c / b.y * exp(-qz), 0.0);
+  }
   double s, co;
   sincos(b.x * z, &s, &co);
   const double w = c / b.x;
   return mk(-(w * s), w * co);
+}
+
+// The same cut decided from |xi|^2 = r2 before any square root: q z > kFarNegligibleQz with
+// q^2 = r2 - k^2 (the slab's modes are mostly past it).
+__device__ __forceinline__ bool far_negligible(double r2, double k, double z) {
+  return (r2 - k * k) * (z * z) > kFarNegligibleQz * kFarNegligibleQz;
 }
 
 // One far-slab coefficient of the series (1.3) in 3D: (i/8 pi^2) beta^-1 e^{i beta z} at mode
@@ -674,7 +688,9 @@ __device__ __forceinline__ double2 ibeta_exp(double c, double2 b, double z) {
 __device__ __forceinline__ double2 far3_coef(double k, double a1, double a2, int M1, int M2, double z, int j1p,
                                              int j2p) {
   const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
-  return ibeta_exp(1.0 / (8.0 * kPi * kPi), beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2)), z);
+  const double r2 = xi1 * xi1 + xi2 * xi2;
+  if (far_negligible(r2, k, z)) return mk(0.0, 0.0);
+  return ibeta_exp(1.0 / (8.0 * kPi * kPi), beta_of(k, sqrt(r2)), z);
 }
 
 // The Maxwell far slab's coefficients, one thread per (s, j2, j1) writing all six entries (beta and
@@ -686,8 +702,14 @@ __global__ void k_far3d_mx(double k, double a1, double a2, int M1, int M2, int S
   if (idx >= (long)M1 * M2 * S) return;
   const int j1p = (int)(idx % M1), j2p = (int)((idx / M1) % M2), s = (int)(idx / ((long)M1 * M2));
   const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
-  const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-  const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z0 + s * hf);
+  const double r2 = xi1 * xi1 + xi2 * xi2, z = z0 + s * hf;
+  if (far_negligible(r2, k, z)) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) store_c<T>(out, f * fstride + idx, mk(0.0, 0.0));
+    return;
+  }
+  const double2 b = beta_of(k, sqrt(r2));
+  const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z);
   const double ik2 = 1.0 / (k * k);
   const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
   const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
@@ -721,8 +743,14 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
       const long r = r0 + t;
       const int s = (int)(r / M2), j2p = (int)(r - (long)s * M2);
       const double xi1 = a1 + centered(j1p, M1), xi2 = a2 + centered(j2p, M2);
-      const double2 b = beta_of(k, sqrt(xi1 * xi1 + xi2 * xi2));
-      const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z0 + s * hf);
+      const double r2 = xi1 * xi1 + xi2 * xi2, z = z0 + s * hf;
+      if (far_negligible(r2, k, z)) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) store_c<T>(buf, (size_t)(f * tile + t) * n + j1p, mk(0.0, 0.0));
+        continue;
+      }
+      const double2 b = beta_of(k, sqrt(r2));
+      const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z);
       const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
@@ -763,6 +791,7 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
   const long b0 = (long)blockIdx.x * tile;
   const int ntile = (int)min((long)tile, nbatch - b0);
   const int total = tile * n;
+  bool nz = false;
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int e = idx / tile, t = idx - e * tile;
     if (t < ntile) {
@@ -770,13 +799,31 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
       const long s = b / M1;
       const int j1p = (int)(b - s * M1);
       const double2 v = far3_coef(k, a1, a2, M1, M2, z0 + s * hf, j1p, e);
+      nz |= v.x != 0.0 || v.y != 0.0;
       V c;
       c.x = (T)v.x;
       c.y = (T)v.y;
       buf[t * pitch + e] = c;
     }
   }
-  __syncthreads();
+  // Columns whose every term is past the cut (|alpha1 + j1| beyond about 50/z) transform to zeros,
+  // written at once when a wave's stores span at most 16 rows (tile >= 4; on gfx950 a stream of
+  // stores over 32 rows of 32 bytes each, complex128 in 2-column tiles, ran slower than the
+  // transforms it would replace).
+  if (!__syncthreads_or(nz) && tile >= 4) {
+    V zero;
+    zero.x = (T)0;
+    zero.y = (T)0;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int e = idx / tile, t = idx - e * tile;
+      if (t < ntile) {
+        const long b = b0 + t;
+        const long plane = b / M1;
+        out[plane * ((long)M1 * M2) + (long)e * M1 + (b - plane * M1)] = zero;
+      }
+    }
+    return;
+  }
   if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
     V* twl = buf + tile * pitch;
     const int stride = ntw / n;
