@@ -737,6 +737,7 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
   const int ntile = (int)min((long)tile, nrows - r0);
   const double ik2 = 1.0 / (k * k);
   const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+  bool nz = false;
   for (int idx = threadIdx.x; idx < tile * n; idx += blockDim.x) {
     const int t = idx / n, j1p = idx - t * n;
     if (t < ntile) {
@@ -749,6 +750,7 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
         for (int f = 0; f < 6; ++f) store_c<T>(buf, (size_t)(f * tile + t) * n + j1p, mk(0.0, 0.0));
         continue;
       }
+      nz = true;
       const double2 b = beta_of(k, sqrt(r2));
       const double2 v = ibeta_exp(1.0 / (8.0 * kPi * kPi), b, z);
       const double2 cc[3] = {mk(xi1, 0.0), mk(xi2, 0.0), b};
@@ -759,7 +761,17 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
       }
     }
   }
-  __syncthreads();
+  // rows (s, j2) with every term past the cut (|alpha2 + j2| beyond about 50/z) transform to zeros
+  if (!__syncthreads_or(nz)) {
+    V zero;
+    zero.x = (T)0;
+    zero.y = (T)0;
+    for (int idx = threadIdx.x; idx < 6 * tile * n; idx += blockDim.x) {
+      const int fr = idx / n, i1 = idx - fr * n, f = fr / tile, t = fr - f * tile;
+      if (t < ntile) out[f * fstride + (r0 + t) * n + i1] = zero;
+    }
+    return;
+  }
   // rows of the last block beyond the slab hold stale LDS: transformed, never written
   if (fft_twiddles_in_lds(6 * tile, n, n, sizeof(V))) {
     V* twl = buf + 6 * tile * n;
