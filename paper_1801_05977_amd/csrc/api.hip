@@ -404,6 +404,8 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
       KernelTimer t(P, QPGF_T_FAR_FFT);
       if (far_rows_in_fill(P))
         HIP_TRY(launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * P.nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2));
+      else if (P.dim == 3 && P.nfo == 1)
+        HIP_TRY(launch_fft_far_rows(P, k, a1));
       else
         HIP_TRY(launch_fft(P, P.far, P.Mf1, 1, (long)P.Mf2 * P.S * P.nfo, 1, 0, P.Mf1));
     }

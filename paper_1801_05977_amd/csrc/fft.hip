@@ -136,6 +136,72 @@ __global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, c
   fft_body<T>(base + g.off, g.n, g.es, g.nbatch, g.b_in, g.s_in, g.s_out, g.tile, tw, ntw, blk - g.blk0, smem_raw);
 }
 
+// x1 rows of the 3D G_d far slab [s][i2][i1] after its x2 pass.  Row b = s M2 + i2 is zero in every
+// column j1 whose terms all fell past the cut at z_s = z0 + s hf (far_negligible with
+// |xi|^2 = (alpha1 + j1)^2): those inputs are taken as zero without being read (their lanes load the
+// block's first element, so every lane still loads and no load waits at a branch join).  The
+// transform's input is that of the whole row, but for terms at the cut itself.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_far_rows(cplx<T>* __restrict__ data, int n, long nrows, int M2, int tile,
+                                                      double k, double a1, double z0, double hf,
+                                                      const cplx<T>* __restrict__ tw, int ntw) {
+  extern __shared__ char smem_raw[];
+  using V = cplx<T>;
+  constexpr int kLdU = ld_unroll<T>();
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  const long b0 = xcd_block(blockIdx.x, gridDim.x) * tile;
+  const int ntile = (int)min((long)tile, nrows - b0);
+  const int total = tile * n;
+  const unsigned un = (unsigned)n, um2 = (unsigned)M2;
+  const long g0 = b0 * n;
+  V zero;
+  zero.x = (T)0;
+  zero.y = (T)0;
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    int o[kLdU];   // LDS offset of a value read; -2 - offset for a zero; -1 past the block's rows
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      const unsigned t = (unsigned)idx / un, e = (unsigned)idx - t * un;
+      const bool in = idx < total && (int)t < ntile;
+      const unsigned b = (unsigned)b0 + t, s = b / um2;
+      const double xi = a1 + (double)((int)e < (n >> 1) ? (int)e : (int)e - n);
+      const bool keep = in && !far_negligible(xi * xi, k, z0 + (long)s * hf);
+      o[u] = keep ? idx : in ? -2 - idx : -1;
+      v[u] = data[keep ? b0 * n + idx : g0];
+    }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      if (o[u] >= 0) buf[o[u]] = v[u];
+      else if (o[u] <= -2) buf[-2 - o[u]] = zero;
+    }
+  }
+  __syncthreads();
+  if (fft_twiddles_in_lds(tile, n, n, sizeof(V))) {
+    V* twl = buf + tile * n;
+    const int stride = ntw / n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j * stride];
+    __syncthreads();
+    inverse_dft_lds<T>(buf, n, n, ntile, twl, n);
+  } else {
+    inverse_dft_lds<T>(buf, n, n, ntile, tw, ntw);
+  }
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    int o[kLdU];
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      o[u] = idx < ntile * n ? idx : -1;
+      v[u] = buf[o[u] >= 0 ? o[u] : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u)
+      if (o[u] >= 0) data[g0 + o[u]] = v[u];
+  }
+}
+
 template <typename T>
 hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   if (n <= 1 || nbatch <= 0) return hipSuccess;
@@ -201,6 +267,25 @@ hipError_t launch_fft_multi(Plan& P, void* base, const FftSeg* dsegs, int nseg, 
 hipError_t launch_fft(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   return P.p.prec == QPGF_C128 ? fft_impl<double>(P, data, n, es, nbatch, b_in, s_in, s_out)
                                : fft_impl<float>(P, data, n, es, nbatch, b_in, s_in, s_out);
+}
+
+hipError_t launch_fft_far_rows(Plan& P, double k, double a1) {
+  const int n = P.Mf1;
+  const long nrows = (long)P.Mf2 * P.S;
+  if (n <= 1 || nrows <= 0) return hipSuccess;
+  if (nrows + 64 >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit row indices in the kernel
+  const int tile = fft_tile(P, n, true, nrows);
+  const long nblk = (nrows + tile - 1) / tile;
+  if (P.p.prec == QPGF_C128) {
+    const size_t shm = ((size_t)tile * n + (fft_twiddles_in_lds(tile, n, n, sizeof(double2)) ? n : 0)) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_far_rows<double>, dim3((unsigned)nblk), dim3(256), shm, P.stream,
+                       static_cast<double2*>(P.far), n, nrows, P.Mf2, tile, k, a1, P.fz0, P.hf, P.tw, P.ntw);
+  } else {
+    const size_t shm = ((size_t)tile * n + (fft_twiddles_in_lds(tile, n, n, sizeof(float2)) ? n : 0)) * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_far_rows<float>, dim3((unsigned)nblk), dim3(256), shm, P.stream,
+                       static_cast<float2*>(P.far), n, nrows, P.Mf2, tile, k, a1, P.fz0, P.hf, P.twf, P.ntw);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace qpgf

@@ -656,16 +656,13 @@ __global__ __launch_bounds__(256) void k_htable(int hn, double hd, double k, int
 // (i/8pi^2) beta^-1 e^{i beta z_s} of the Mf1 x Mf2 lowest modes, z_s = z0 + s hf.  NFO = kMxO:
 // the six entries of the Maxwell tensor (1.4) instead, the term times delta_pq - xi_p xi_q / k^2
 // with xi = (alpha1 + j1, alpha2 + j2, beta) (the entries 13 and 23 take sgn(x3) at the target).
+
 // i c beta^-1 e^{i beta z} (c real, z >= 0, beta from beta_of, so one of its parts is zero).  An
 // evanescent mode (beta = i q) gives the real (c/q) e^{-qz}, a propagating one (beta = p)
 // (c/p)(-sin pz, cos pz): one exponential or one sine-cosine pair, and one division.  The complex
 // quotient and product written out in full take the same roundings, their other terms being exact
 // zeros (up to the sign of a zero part); beta = 0, a Wood anomaly, is refused before any fill.
-// Terms with qz > kFarNegligibleQz are taken as zero.  The modes lie one per unit area of the
-// (xi1, xi2) plane, so the dropped terms sum to about 2 pi c e^{-50} / z (about 1e-21 c / z),
-// against the propagating terms' c/p >= c/k: far below the FP64 rounding of the slab's values.
-// The Maxwell entries carry at most 1 + |xi|^2/k^2 more, so theirs sum to about 3e-18 c/(k^2 z^3).
-constexpr double kFarNegligibleQz = 50.0;
+// Terms past the cut of far_negligible are taken as zero.
 __device__ __forceinline__ double2 ibeta_exp(double c, double2 b, double z) {
   if (b.x == 0.0) {
     const double qz = b.y * z;
@@ -675,12 +672,6 @@ __device__ __forceinline__ double2 ibeta_exp(double c, double2 b, double z) {
   sincos(b.x * z, &s, &co);
   const double w = c / b.x;
   return mk(-(w * s), w * co);
-}
-
-// The same cut decided from |xi|^2 = r2 before any square root: q z > kFarNegligibleQz with
-// q^2 = r2 - k^2 (the slab's modes are mostly past it).
-__device__ __forceinline__ bool far_negligible(double r2, double k, double z) {
-  return (r2 - k * k) * (z * z) > kFarNegligibleQz * kFarNegligibleQz;
 }
 
 // One far-slab coefficient of the series (1.3) in 3D: (i/8 pi^2) beta^-1 e^{i beta z} at mode

@@ -63,6 +63,18 @@ __host__ __device__ inline double2 beta_of(double k, double rho) {
   return d >= 0.0 ? mk(sqrt(d), 0.0) : mk(0.0, sqrt(-d));
 }
 
+// The far slab's evanescent terms (c/q) e^{-qz} with q z > kFarNegligibleQz are taken as zero.  The
+// modes lie one per unit area of the (xi1, xi2) plane, so the dropped terms sum to about
+// 2 pi c e^{-50} / z (about 1e-21 c / z), against the propagating terms' c/p >= c/k: far below the
+// FP64 rounding of the slab's values.  The Maxwell entries carry at most 1 + |xi|^2/k^2 more, so
+// theirs sum to about 3e-18 c/(k^2 z^3).  The test takes |xi|^2 = r2, before any square root
+// (q^2 = r2 - k^2).  Rounding is monotone, so a column j1 that passes it with r2 = (alpha1 + j1)^2
+// has every term of that column (any j2) past it too.
+constexpr double kFarNegligibleQz = 50.0;
+__host__ __device__ inline bool far_negligible(double r2, double k, double z) {
+  return (r2 - k * k) * (z * z) > kFarNegligibleQz * kFarNegligibleQz;
+}
+
 // ---------------------------------------------------------------------------
 // C^8 cut-off transition S(u) = I_u(9,9) (Bernstein form), S', S''
 // ---------------------------------------------------------------------------
@@ -269,6 +281,8 @@ bool fill_fuses_transverse(const Plan& P);
 bool far_rows_in_fill(const Plan& P);
 bool far7_ok(const Plan& P);
 hipError_t launch_far(Plan& P, double k, double a1, double a2);
+// x1 rows of the 3D G_d far slab after its x2 pass, reading only the columns that hold terms
+hipError_t launch_fft_far_rows(Plan& P, double k, double a1);
 hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
                       long s_out);
 int fft_tile(const Plan& P, int n, bool rows, long nbatch);
