@@ -403,7 +403,7 @@ qpgf_status run_prepare(Plan& P, double k, double a1, double a2, int stage, doub
       // already run the x2 columns), or the x2 columns where the Maxwell far fill ran the rows
       KernelTimer t(P, QPGF_T_FAR_FFT);
       if (far_rows_in_fill(P))
-        HIP_TRY(launch_fft(P, P.far, P.Mf2, P.Mf1, (long)P.Mf1 * P.S * P.nfo, P.Mf1, 1, (long)P.Mf1 * P.Mf2));
+        HIP_TRY(launch_fft_far_cols(P, k, a2));
       else if (P.dim == 3 && P.nfo == 1)
         HIP_TRY(launch_fft_far_rows(P, k, a1));
       else

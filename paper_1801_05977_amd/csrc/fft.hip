@@ -202,6 +202,82 @@ __global__ __launch_bounds__(256) void k_fft_far_rows(cplx<T>* __restrict__ data
   }
 }
 
+// x2 columns of the Maxwell far slab [f][s][i2][i1] after its x1 pass, `tile` adjacent columns per
+// block.  Column (f, s, i1) is zero at every j2 whose terms all fell past the cut at z_s = z0 + s hf
+// (far_negligible with |xi|^2 = (alpha2 + j2)^2): those inputs are taken as zero without being read,
+// as in k_fft_far_rows.  Batch b: plane q = b / M1 (field q / S, slice q % S), column b % M1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_far_cols(cplx<T>* __restrict__ data, int n, int M1, int S, long nbatch,
+                                                      int tile, double k, double a2, double z0, double hf,
+                                                      const cplx<T>* __restrict__ tw, int ntw) {
+  extern __shared__ char smem_raw[];
+  using V = cplx<T>;
+  constexpr int kLdU = ld_unroll<T>();
+  const int pitch = n + 1;
+  V* buf = reinterpret_cast<V*>(smem_raw);
+  const long b0 = xcd_block(blockIdx.x, gridDim.x) * tile;
+  const int ntile = (int)min((long)tile, nbatch - b0);
+  const int total = tile * n;
+  const unsigned ut = (unsigned)tile, um1 = (unsigned)M1, us = (unsigned)S;
+  const long plane = (long)M1 * n;
+  const long g0 = (b0 / M1) * plane + (b0 % M1);
+  auto gofs = [&](unsigned t, unsigned e) -> long {
+    const unsigned b = (unsigned)b0 + t, q = b / um1;
+    return (long)q * plane + (long)e * M1 + (b - q * um1);
+  };
+  V zero;
+  zero.x = (T)0;
+  zero.y = (T)0;
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    int o[kLdU];   // LDS offset of a value read; -2 - offset for a zero; -1 past the block's columns
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      const unsigned e = (unsigned)idx / ut, t = (unsigned)idx - e * ut;
+      const bool in = idx < total && (int)t < ntile;
+      const unsigned s = (((unsigned)b0 + t) / um1) % us;
+      const double xi = a2 + (double)((int)e < (n >> 1) ? (int)e : (int)e - n);
+      const bool keep = in && !far_negligible(xi * xi, k, z0 + (long)s * hf);
+      const int l = (int)(t * (unsigned)pitch + e);
+      o[u] = keep ? l : in ? -2 - l : -1;
+      v[u] = data[keep ? gofs(t, e) : g0];
+    }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      if (o[u] >= 0) buf[o[u]] = v[u];
+      else if (o[u] <= -2) buf[-2 - o[u]] = zero;
+    }
+  }
+  __syncthreads();
+  if (fft_twiddles_in_lds(tile, pitch, n, sizeof(V))) {
+    V* twl = buf + tile * pitch;
+    const int stride = ntw / n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) twl[j] = tw[(long)j * stride];
+    __syncthreads();
+    inverse_dft_lds<T>(buf, n, pitch, ntile, twl, n);
+  } else {
+    inverse_dft_lds<T>(buf, n, pitch, ntile, tw, ntw);
+  }
+  for (int i0 = 0; i0 < total; i0 += kLdU * 256) {
+    V v[kLdU];
+    long g[kLdU];
+    int o[kLdU];
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u) {
+      const int idx = i0 + u * 256 + (int)threadIdx.x;
+      const unsigned e = (unsigned)idx / ut, t = (unsigned)idx - e * ut;
+      const bool in = idx < total && (int)t < ntile;
+      o[u] = in ? (int)(t * (unsigned)pitch + e) : -1;
+      g[u] = in ? gofs(t, e) : g0;
+      v[u] = buf[o[u] >= 0 ? o[u] : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kLdU; ++u)
+      if (o[u] >= 0) data[g[u]] = v[u];
+  }
+}
+
 template <typename T>
 hipError_t fft_impl(Plan& P, void* data, int n, long es, long nbatch, long b_in, long s_in, long s_out) {
   if (n <= 1 || nbatch <= 0) return hipSuccess;
@@ -284,6 +360,27 @@ hipError_t launch_fft_far_rows(Plan& P, double k, double a1) {
     const size_t shm = ((size_t)tile * n + (fft_twiddles_in_lds(tile, n, n, sizeof(float2)) ? n : 0)) * sizeof(float2);
     hipLaunchKernelGGL(k_fft_far_rows<float>, dim3((unsigned)nblk), dim3(256), shm, P.stream,
                        static_cast<float2*>(P.far), n, nrows, P.Mf2, tile, k, a1, P.fz0, P.hf, P.twf, P.ntw);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_far_cols(Plan& P, double k, double a2) {
+  const int n = P.Mf2;
+  const long nbatch = (long)P.Mf1 * P.S * P.nfo;
+  if (n <= 1 || nbatch <= 0) return hipSuccess;
+  if (nbatch + 64 >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit batch indices in the kernel
+  const int tile = fft_tile(P, n, false, nbatch), pitch = n + 1;
+  const long nblk = (nbatch + tile - 1) / tile;
+  if (P.p.prec == QPGF_C128) {
+    const size_t shm =
+        ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(double2)) ? n : 0)) * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_far_cols<double>, dim3((unsigned)nblk), dim3(256), shm, P.stream,
+                       static_cast<double2*>(P.far), n, P.Mf1, P.S, nbatch, tile, k, a2, P.fz0, P.hf, P.tw, P.ntw);
+  } else {
+    const size_t shm =
+        ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(float2)) ? n : 0)) * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_far_cols<float>, dim3((unsigned)nblk), dim3(256), shm, P.stream,
+                       static_cast<float2*>(P.far), n, P.Mf1, P.S, nbatch, tile, k, a2, P.fz0, P.hf, P.twf, P.ntw);
   }
   return hipGetLastError();
 }

@@ -283,6 +283,8 @@ bool far7_ok(const Plan& P);
 hipError_t launch_far(Plan& P, double k, double a1, double a2);
 // x1 rows of the 3D G_d far slab after its x2 pass, reading only the columns that hold terms
 hipError_t launch_fft_far_rows(Plan& P, double k, double a1);
+// x2 columns of the Maxwell far slab after its x1 pass, reading only the rows that hold terms
+hipError_t launch_fft_far_cols(Plan& P, double k, double a2);
 hipError_t launch_fft(Plan& P, void* data, int n, long elem_stride, long nbatch, long b_in, long s_in,
                       long s_out);
 int fft_tile(const Plan& P, int n, bool rows, long nbatch);
