@@ -137,10 +137,9 @@ __global__ __launch_bounds__(256) void k_fft_multi(cplx<T>* __restrict__ base, c
 }
 
 // x1 rows of the 3D G_d far slab [s][i2][i1] after its x2 pass.  Row b = s M2 + i2 is zero in every
-// column j1 whose terms all fell past the cut at z_s = z0 + s hf (far_negligible with
-// |xi|^2 = (alpha1 + j1)^2): those inputs are taken as zero without being read (their lanes load the
-// block's first element, so every lane still loads and no load waits at a branch join).  The
-// transform's input is that of the whole row, but for terms at the cut itself.
+// column j1 whose terms all fell past the cut at z_s = z0 + s hf (far_band_empty): the x2 pass
+// leaves those columns unwritten and here they are taken as zero without being read (their lanes
+// load the block's first element, so every lane still loads and no load waits at a branch join).
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_far_rows(cplx<T>* __restrict__ data, int n, long nrows, int M2, int tile,
                                                       double k, double a1, double z0, double hf,
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(256) void k_fft_far_rows(cplx<T>* __restrict__ data
       const bool in = idx < total && (int)t < ntile;
       const unsigned b = (unsigned)b0 + t, s = b / um2;
       const double xi = a1 + (double)((int)e < (n >> 1) ? (int)e : (int)e - n);
-      const bool keep = in && !far_negligible(xi * xi, k, z0 + (long)s * hf);
+      const bool keep = in && !far_band_empty(xi, k, z0, hf, (long)s);
       o[u] = keep ? idx : in ? -2 - idx : -1;
       v[u] = data[keep ? b0 * n + idx : g0];
     }
@@ -204,8 +203,8 @@ __global__ __launch_bounds__(256) void k_fft_far_rows(cplx<T>* __restrict__ data
 
 // x2 columns of the Maxwell far slab [f][s][i2][i1] after its x1 pass, `tile` adjacent columns per
 // block.  Column (f, s, i1) is zero at every j2 whose terms all fell past the cut at z_s = z0 + s hf
-// (far_negligible with |xi|^2 = (alpha2 + j2)^2): those inputs are taken as zero without being read,
-// as in k_fft_far_rows.  Batch b: plane q = b / M1 (field q / S, slice q % S), column b % M1.
+// (far_band_empty): the x1 pass leaves those rows unwritten and here they are taken as zero without
+// being read, as in k_fft_far_rows.  Batch b: plane q = b / M1 (field q / S, slice q % S), column b % M1.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_far_cols(cplx<T>* __restrict__ data, int n, int M1, int S, long nbatch,
                                                       int tile, double k, double a2, double z0, double hf,
@@ -238,7 +237,7 @@ __global__ __launch_bounds__(256) void k_fft_far_cols(cplx<T>* __restrict__ data
       const bool in = idx < total && (int)t < ntile;
       const unsigned s = (((unsigned)b0 + t) / um1) % us;
       const double xi = a2 + (double)((int)e < (n >> 1) ? (int)e : (int)e - n);
-      const bool keep = in && !far_negligible(xi * xi, k, z0 + (long)s * hf);
+      const bool keep = in && !far_band_empty(xi, k, z0, hf, (long)s);
       const int l = (int)(t * (unsigned)pitch + e);
       o[u] = keep ? l : in ? -2 - l : -1;
       v[u] = data[keep ? gofs(t, e) : g0];

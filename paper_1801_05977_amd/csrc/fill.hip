@@ -728,6 +728,14 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
   const int ntile = (int)min((long)tile, nrows - r0);
   const double ik2 = 1.0 / (k * k);
   const int P[6] = {0, 1, 2, 0, 0, 1}, Qp[6] = {0, 1, 2, 1, 2, 2};
+  // rows (s, j2) of far_band_empty are left unwritten: the x2 pass takes them as zero unread
+  __shared__ unsigned char wr[64];
+  if ((int)threadIdx.x < tile) {
+    const int t = threadIdx.x;
+    const long r = r0 + t;
+    const int s = (int)(r / M2);
+    wr[t] = t < ntile && !far_band_empty(a2 + centered((int)(r - (long)s * M2), M2), k, z0, hf, s);
+  }
   bool nz = false;
   for (int idx = threadIdx.x; idx < tile * n; idx += blockDim.x) {
     const int t = idx / n, j1p = idx - t * n;
@@ -752,14 +760,14 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
       }
     }
   }
-  // rows (s, j2) with every term past the cut (|alpha2 + j2| beyond about 50/z) transform to zeros
+  // tiles whose every term is past the cut transform to zeros, written at once
   if (!__syncthreads_or(nz)) {
     V zero;
     zero.x = (T)0;
     zero.y = (T)0;
     for (int idx = threadIdx.x; idx < 6 * tile * n; idx += blockDim.x) {
       const int fr = idx / n, i1 = idx - fr * n, f = fr / tile, t = fr - f * tile;
-      if (t < ntile) out[f * fstride + (r0 + t) * n + i1] = zero;
+      if (wr[t]) out[f * fstride + (r0 + t) * n + i1] = zero;
     }
     return;
   }
@@ -775,7 +783,7 @@ __global__ __launch_bounds__(256) void k_far3d_mx_rows(double k, double a1, doub
   }
   for (int idx = threadIdx.x; idx < 6 * tile * n; idx += blockDim.x) {
     const int fr = idx / n, i1 = idx - fr * n, f = fr / tile, t = fr - f * tile;
-    if (t < ntile) out[f * fstride + (r0 + t) * n + i1] = buf[idx];
+    if (wr[t]) out[f * fstride + (r0 + t) * n + i1] = buf[idx];
   }
 }
 
@@ -794,6 +802,14 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
   const long b0 = (long)blockIdx.x * tile;
   const int ntile = (int)min((long)tile, nbatch - b0);
   const int total = tile * n;
+  // columns of far_band_empty are left unwritten: the x1 pass takes them as zero unread
+  __shared__ unsigned char wr[64];
+  if ((int)threadIdx.x < tile) {
+    const int t = threadIdx.x;
+    const long b = b0 + t;
+    const long s = b / M1;
+    wr[t] = t < ntile && !far_band_empty(a1 + centered((int)(b - s * M1), M1), k, z0, hf, s);
+  }
   bool nz = false;
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int e = idx / tile, t = idx - e * tile;
@@ -809,17 +825,14 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
       buf[t * pitch + e] = c;
     }
   }
-  // Columns whose every term is past the cut (|alpha1 + j1| beyond about 50/z) transform to zeros,
-  // written at once when a wave's stores span at most 16 rows (tile >= 4; on gfx950 a stream of
-  // stores over 32 rows of 32 bytes each, complex128 in 2-column tiles, ran slower than the
-  // transforms it would replace).
-  if (!__syncthreads_or(nz) && tile >= 4) {
+  // tiles whose every term is past the cut transform to zeros, written at once
+  if (!__syncthreads_or(nz)) {
     V zero;
     zero.x = (T)0;
     zero.y = (T)0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
       const int e = idx / tile, t = idx - e * tile;
-      if (t < ntile) {
+      if (wr[t]) {
         const long b = b0 + t;
         const long plane = b / M1;
         out[plane * ((long)M1 * M2) + (long)e * M1 + (b - plane * M1)] = zero;
@@ -838,7 +851,7 @@ __global__ __launch_bounds__(256) void k_far3d_cols(double k, double a1, double 
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int e = idx / tile, t = idx - e * tile;
-    if (t < ntile) {
+    if (wr[t]) {
       const long b = b0 + t;
       const long plane = b / M1;
       out[plane * ((long)M1 * M2) + (long)e * M1 + (b - plane * M1)] = buf[t * pitch + e];
@@ -1104,7 +1117,7 @@ hipError_t far_impl(Plan& P, double k, double a1, double a2) {
     // coefficients and the x2 transform in one pass (the x1 pass follows in the caller)
     const int n = P.Mf2, pitch = n + 1;
     const long nbatch = (long)P.Mf1 * P.S;
-    const int tile = fft_tile(P, n, false, nbatch);
+    const int tile = std::min(fft_tile(P, n, false, nbatch), 64);   // the kernel's column flags hold 64
     const size_t shm = ((size_t)tile * pitch + (fft_twiddles_in_lds(tile, pitch, n, sizeof(cplx<T>)) ? n : 0)) *
                        sizeof(cplx<T>);
     const cplx<T>* tw = nullptr;

@@ -68,11 +68,20 @@ __host__ __device__ inline double2 beta_of(double k, double rho) {
 // 2 pi c e^{-50} / z (about 1e-21 c / z), against the propagating terms' c/p >= c/k: far below the
 // FP64 rounding of the slab's values.  The Maxwell entries carry at most 1 + |xi|^2/k^2 more, so
 // theirs sum to about 3e-18 c/(k^2 z^3).  The test takes |xi|^2 = r2, before any square root
-// (q^2 = r2 - k^2).  Rounding is monotone, so a column j1 that passes it with r2 = (alpha1 + j1)^2
-// has every term of that column (any j2) past it too.
+// (q^2 = r2 - k^2).  A column j1 past it with r2 = (alpha1 + j1)^2 has every term (any j2) past it
+// too, up to the rounding of terms at the cut itself.
 constexpr double kFarNegligibleQz = 50.0;
 __host__ __device__ inline bool far_negligible(double r2, double k, double z) {
   return (r2 - k * k) * (z * z) > kFarNegligibleQz * kFarNegligibleQz;
+}
+// Whether the far slab's column j1 (xi = alpha1 + j1), or Maxwell row j2 (xi = alpha2 + j2), at
+// slice s holds only terms past the cut: far_negligible with |xi|^2 = xi^2 at z = z0 + s hf.  It
+// decides which values the first transform writes and the second reads, so it is evaluated without
+// contraction: every kernel that calls it takes the same decision, bit for bit.
+__host__ __device__ inline bool far_band_empty(double xi, double k, double z0, double hf, long s) {
+#pragma clang fp contract(off)
+  const double z = z0 + (double)s * hf;
+  return (xi * xi - k * k) * (z * z) > kFarNegligibleQz * kFarNegligibleQz;
 }
 
 // ---------------------------------------------------------------------------

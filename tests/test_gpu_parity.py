@@ -412,6 +412,34 @@ def test_gd3d_far_branch_next_to_c(k):
         P.close()
 
 
+@pytest.mark.parametrize("kind,prec", [(qpgf.KIND_GD3D, qpgf.C128), (qpgf.KIND_GD3D, qpgf.C64),
+                                       (qpgf.KIND_MAXWELL3D, qpgf.C64)])
+def test_far_slab_reuse_bitwise(kind, prec):
+    """The far slab's first transform leaves the bands that hold only terms past the cut unwritten
+    and the second takes them as zero without reading them.  A plan whose slab still holds a
+    wider band from a previous instance (same slab geometry: k 6.1 then 2.3) gives bitwise the
+    slab and the values of a fresh plan."""
+    M1, M2, M3, T = 64, 64, 32, 40_000
+    rng = np.random.default_rng(47)
+    x = np.empty((T, 3))
+    x[:, 0] = rng.uniform(0.0, 2 * math.pi, T)
+    x[:, 1] = rng.uniform(0.0, 2 * math.pi, T)
+    x[:, 2] = rng.choice([-1.0, 1.0], T) * rng.uniform(0.6 + 1e-9, 1.0, T)
+    xd = dev(x)
+    used, fresh = qpgf.Plan(kind, prec, M1, M2, M3), qpgf.Plan(kind, prec, M1, M2, M3)
+    used(6.1, 0.45, -0.3, xd)
+    geom = (used.info.far_m1, used.info.far_m2, used.info.far_slices)
+    g = used(2.3, 0.1, 0.2, xd).cpu().numpy()
+    assert (used.info.far_m1, used.info.far_m2, used.info.far_slices) == geom
+    ref = fresh(2.3, 0.1, 0.2, xd).cpu().numpy()
+    assert np.array_equal(g.view(np.uint8), ref.view(np.uint8))
+    for f in range(6 if kind == qpgf.KIND_MAXWELL3D else 1):
+        a, b = used.field(1, f).cpu().numpy(), fresh.field(1, f).cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    used.close()
+    fresh.close()
+
+
 # ----------------------------------------------------------------------------- full size, sampled
 
 @pytest.mark.timeout(900)
