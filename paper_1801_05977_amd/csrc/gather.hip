@@ -1564,11 +1564,55 @@ __global__ __launch_bounds__(256) void k_bin_key(BinArgs B, const double* __rest
   keyrank[i] = make_uint2(key, r);
 }
 
-// exclusive scan of hist[0..n) into offs[0..n) with one block of 1024 threads
+// exclusive scan of hist[0..n) into offs[0..n) with one block of 1024 threads.  Up to 32 x 1024 keys:
+// thread t reads keys t + 1024 j (coalesced, all loads issued first) and the block scans one row of
+// 1024 keys at a time (64-lane shuffle scans, then the 16 wave totals), carrying the running total
+// from row to row.  More keys: each thread sums a contiguous segment, the block scans the segment
+// sums and each thread writes its segment's prefixes.
+constexpr int kScanRows = 32;
 __global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
                                                    int n) {
   __shared__ uint32_t part[1024];
-  const int t = threadIdx.x, per = (n + 1023) / 1024;
+  const int t = threadIdx.x;
+  if (n <= kScanRows * 1024) {
+    const int lane = t & 63, w = t >> 6, rows = (n + 1023) / 1024;
+    uint32_t v[kScanRows];
+#pragma unroll
+    for (int j = 0; j < kScanRows; ++j) {
+      const int i = t + j * 1024;
+      v[j] = j < rows && i < n ? hist[i] : 0u;
+    }
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < kScanRows; ++j) {
+      if (j < rows) {   // uniform over the block
+        uint32_t x = v[j];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(x, d, 64);
+          if (lane >= d) x += y;
+        }
+        if (lane == 63) part[w] = x;   // wave totals
+        __syncthreads();
+        if (w == 0) {
+          uint32_t q = lane < 16 ? part[lane] : 0u;
+#pragma unroll
+          for (int d = 1; d < 16; d <<= 1) {
+            const uint32_t y = __shfl_up(q, d, 64);
+            if (lane >= d) q += y;
+          }
+          if (lane < 16) part[lane] = q;   // inclusive prefixes of the wave totals
+        }
+        __syncthreads();
+        const int i = t + j * 1024;
+        if (i < n) offs[i] = carry + (w > 0 ? part[w - 1] : 0u) + x - v[j];
+        carry += part[15];
+        __syncthreads();
+      }
+    }
+    return;
+  }
+  const int per = (n + 1023) / 1024;
   const int lo = min(n, t * per), hi = min(n, lo + per);
   uint32_t s = 0;
   for (int i = lo; i < hi; ++i) s += hist[i];
