@@ -1658,7 +1658,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ 
 constexpr int kBinBlocks = 256;
 constexpr int kMinPerTile = 1500;   // targets per tile below which the larger tiles are used
 constexpr int kMaxPerFieldTile = 512;   // Maxwell: targets per 16 x 16 x 8 tile below which fields are staged one by one
-constexpr int kBinUnroll = 4;
+constexpr int kBinUnroll = 8;
 constexpr int kBinLdsKeys = 32768;   // 128 KiB of LDS: one 1024-thread block per CU
 
 template <int KEYS>
