@@ -412,6 +412,31 @@ def test_gd3d_far_branch_next_to_c(k):
         P.close()
 
 
+@pytest.mark.parametrize("kind,prec,far_m", [
+    (qpgf.KIND_GD3D, qpgf.C128, 256), (qpgf.KIND_GD3D, qpgf.C128, 2048),
+    (qpgf.KIND_GD3D, qpgf.C64, 256), (qpgf.KIND_GD3D, qpgf.C64, 2048),
+    (qpgf.KIND_MAXWELL3D, qpgf.C64, 256), (qpgf.KIND_MAXWELL3D, qpgf.C64, 2048)])
+def test_far_slab_nodes_at_far_m(kind, prec, far_m):
+    """The far slab at caller-set sizes: column tiles from 16 columns down to one, and at 2048 modes
+    the Maxwell slab's unfused passes.  At sampled nodes it is the series (1.3) itself, the bands of
+    dropped terms included (256 modes truncate the series at about e^-70 at these heights)."""
+    k, a1, a2 = 3.7, 0.2, 0.35
+    P = qpgf.Plan(kind, prec, 32, 32, 16, far_m=far_m)
+    P.prepare(k, a1, a2, stage=2)
+    assert (P.info.far_m1, P.info.far_m2) == (far_m, far_m)
+    idx, pts = slabcheck.nodes_3d(P.info, 30 if kind == qpgf.KIND_GD3D else 12, seed=11)
+    ph = np.exp(-1j * (a1 * pts[:, 0] + a2 * pts[:, 1]))
+    tol = 1e-12 if prec == qpgf.C128 else 2e-6
+    if kind == qpgf.KIND_GD3D:
+        ref = truth.gd3d(k, a1, a2, pts) * ph
+        assert slabcheck.rel(slabcheck.slab_3d(P)[idx], ref) <= tol
+    else:
+        ref = truth.maxwell3d(k, a1, a2, pts) * ph[:, None]
+        for f in range(6):
+            assert slabcheck.rel(slabcheck.slab_3d(P, f)[idx], ref[:, f]) <= tol, f
+    P.close()
+
+
 @pytest.mark.parametrize("kind,prec", [(qpgf.KIND_GD3D, qpgf.C128), (qpgf.KIND_GD3D, qpgf.C64),
                                        (qpgf.KIND_MAXWELL3D, qpgf.C64)])
 def test_far_slab_reuse_bitwise(kind, prec):
